@@ -1,0 +1,155 @@
+/*
+ * orc.h -- the plain FP64 CPU oracle of the chromatic Metropolis-Hastings
+ * sampler (Song & Moore, "Parallel Chromatic MCMC with Spatial Partitioning").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this code: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or constant with the
+ * GPU library; the only thing the two sides have in common is the published
+ * definition of the Philox4x32-10 counter-based generator, which each side
+ * implements on its own.
+ *
+ * Everything is IEEE double precision, single-threaded, compiled with
+ * -ffp-contract=off so that every integer decided by floating point (region
+ * of an event, detection test, first sample of an arrival window) is
+ * reproducible bit for bit.
+ *
+ * Model (Section 3, "Generative Model of Seismic Signals"), in the 2-D,
+ * attenuating form that Section 4.1 names as the natural case for a spatial
+ * partition:
+ *   - stations on an nsx x nsy grid, cell-centred, spacing ds;
+ *     domain D = [0, nsx*ds) x [0, nsy*ds);
+ *   - events e = (x, y, t, m): uniform location, uniform onset time t in
+ *     [0, N) samples, magnitude m with m - mmin ~ Exp(mrate); their number
+ *     is Poisson with mean lambda (the event prior of Section 3);
+ *   - distance d to a station; detected only if d < rc; arrival
+ *     a = t + d / vel (the arrival model of Section 3 with zero jitter);
+ *   - the event's signal at a detecting station is zero-mean Gaussian with
+ *     standard deviation A * phi(n - a) on n in [ceil(a), ceil(a) + ts),
+ *     A = m * exp(-d / atten), phi(tau) = exp(-tau / decay);
+ *   - signal likelihood: zero-mean diagonal Gaussian whose variance at each
+ *     sample is the noise variance sigma^2 plus the variances of all
+ *     arriving signals (Section 3, the paragraph after the joint density).
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nsx, nsy;   /* station grid */
+    double  ds;         /* station spacing */
+    int64_t N;          /* samples per trace */
+    double  sigma;      /* background noise standard deviation */
+    double  atten;      /* attenuation length of the amplitude */
+    double  vel;        /* wave speed, domain units per sample */
+    double  decay;      /* decay of the amplitude envelope, samples */
+    int32_t ts;         /* signal duration, samples */
+    int32_t _pad0;
+    double  rc;         /* detection cutoff distance (strict d < rc) */
+    double  lambda;     /* Poisson mean number of events in the domain */
+    double  mmin;       /* magnitude lower bound */
+    double  mrate;      /* rate of the exponential magnitude prior */
+} orc_model;
+
+enum { ORC_BIRTH = 0, ORC_DEATH = 1, ORC_LOC = 2, ORC_TIME = 3, ORC_MAG = 4 };
+enum { ORC_SCHED_CHROMATIC = 0, ORC_SCHED_NAIVE = 1 };
+
+typedef struct {
+    int32_t gx, gy;       /* regions per axis of the unshifted grid */
+    int32_t dynamic;      /* 0 static partition, 1 offset redrawn every sweep */
+    int32_t period;       /* colour period p (0: derive it) */
+    int32_t k;            /* moves per region per colour phase */
+    int32_t cap;          /* per-region event capacity */
+    double  pb, pd, ploc, pt, pm;  /* move-type probabilities */
+    double  sxy, st, sm;  /* random-walk step sizes */
+    int32_t prior_only;   /* 1: likelihood switched off */
+    int32_t schedule;     /* ORC_SCHED_* */
+    /* lattice mode (tests only): events live on a finite site set */
+    int32_t lattice;
+    int32_t kx, ky, kt, km;   /* sites per axis */
+    int32_t _pad1;
+    double  hm;               /* magnitude site spacing */
+} orc_sampler;
+
+typedef struct {
+    double   x, y, t, m;
+    uint64_t id;
+    int32_t  region;
+    int32_t  _pad;
+} orc_event;
+
+/* ---- Philox4x32-10 and the conversions built on it ------------------- */
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u01(uint32_t w0, uint32_t w1);
+void   orc_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                      uint32_t j, double out[8]);
+void   orc_offset(uint32_t seed, uint32_t chain, uint32_t sweep, double wx, double wy,
+                  double *dx, double *dy);
+
+/* ---- geometry --------------------------------------------------------- */
+double orc_station_x(const orc_model *m, int32_t ix);
+double orc_station_y(const orc_model *m, int32_t iy);
+int32_t orc_region_axis(double x, double off, double w, int32_t g);
+int32_t orc_partition_and_color(const orc_model *m, int32_t gx, int32_t gy,
+                                double offx, double offy, int32_t dynamic,
+                                int32_t *nrx, int32_t *nry, int32_t *period,
+                                int32_t *ncolors, int32_t *color_of_region);
+int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
+                                double offx, double offy, int32_t period);
+
+/* ---- likelihood ------------------------------------------------------- */
+typedef struct {
+    double  d, a, amp;   /* distance, arrival time, amplitude */
+    int64_t n0, n1;      /* affected samples [n0, n1); empty when not detected */
+    int32_t in;          /* detected: d < rc */
+    int32_t _pad;
+} orc_arrival_t;
+double orc_arrival_time(double x, double y, double t, double sx, double sy, double vel,
+                        double *d_out);
+void   orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
+                   orc_arrival_t *out);
+double orc_arrival_variance(const orc_model *m, const orc_arrival_t *ar, int64_t n);
+void   orc_event_variance(const orc_model *m, const orc_event *ev, int64_t nev, double *E);
+double orc_loglik(const orc_model *m, const double *s, const orc_event *ev, int64_t nev);
+double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev);
+double orc_single_term(double sigma, double s, double e);
+
+/* ---- forward simulator ------------------------------------------------ */
+void   orc_simulate(const orc_model *m, const orc_event *truth, int64_t nev,
+                    uint32_t seed, double *s_out);
+
+/* ---- the sampler (serial, chromatic static/dynamic, naive) ----------- */
+typedef struct orc_chain orc_chain;
+orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double *s,
+                         uint32_t seed, uint32_t chain);
+void    orc_chain_free(orc_chain *c);
+int32_t orc_chain_begin_sweep(orc_chain *c, int64_t sweep);
+int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color,
+                        const double *feed, double *log);
+int32_t orc_chain_sweep(orc_chain *c, int64_t sweep, const double *feed, double *log);
+int64_t orc_chain_count(const orc_chain *c);
+int64_t orc_chain_events(const orc_chain *c, orc_event *out, int64_t cap);
+int32_t orc_chain_set_events(orc_chain *c, const orc_event *ev, int64_t nev);
+void    orc_chain_layout(const orc_chain *c, int32_t *nrx, int32_t *nry, int32_t *period,
+                         int32_t *ncolors, double *offx, double *offy);
+int64_t orc_chain_overflows(const orc_chain *c);
+double  orc_chain_delta(orc_chain *c, int32_t region, int32_t type, int64_t idx,
+                        const orc_event *proposed);
+
+/* ---- lattice mode: brute-force enumeration of the posterior ---------- */
+int64_t orc_lattice_nsites(const orc_model *m, const orc_sampler *sp);
+void    orc_lattice_site(const orc_model *m, const orc_sampler *sp, int64_t site,
+                         orc_event *out);
+int64_t orc_enumerate(const orc_model *m, const orc_sampler *sp, const double *s,
+                      int32_t nmax, int32_t *sites_out, double *logw_out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

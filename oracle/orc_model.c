@@ -1,0 +1,385 @@
+/*
+ * orc_model.c -- oracle: random numbers, geometry, partition and colouring,
+ * likelihood and forward simulator.  TEST INFRASTRUCTURE ONLY (see orc.h).
+ *
+ * Plain FP64, no blocking, no fusion: each function states the definition it
+ * follows and computes it directly.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10, as defined by Salmon, Moraes, Dror and Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3" (SC'11): a 10-round Feistel-like
+ * bijection of a 128-bit counter under a 64-bit key.  Each round multiplies
+ * counter words 0 and 2 by the two Philox multipliers, exchanges and XORs the
+ * halves with the other words and the round key; the key is bumped by the two
+ * Weyl constants between rounds.
+ * ---------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on the open interval (0, 1) from two 32-bit words: the top 26 bits
+ * of each word form a 52-bit integer k, and u = (2k + 1) / 2^53, the centre
+ * of the k-th of 2^52 equal cells.  2k + 1 < 2^53 is exactly representable,
+ * so the conversion is exact on any IEEE machine and never yields 0 or 1. */
+double orc_u01(uint32_t w0, uint32_t w1)
+{
+    uint64_t k = ((uint64_t)(w0 >> 6) << 26) | (uint64_t)(w1 >> 6);
+    return (double)(2u * k + 1u) * 0x1p-53;
+}
+
+/* Key of a sampler chain: (seed, chain).  Counter of a move's draws:
+ * (sweep, region, move, block).  Four blocks per move give the record
+ *   [0] uniform choosing the move type     [1] uniform a (index / birth x)
+ *   [2] uniform b (birth y / direction)    [3] uniform c (birth onset time)
+ *   [4] Exp(1) draw (birth magnitude)      [5],[6] two standard normals
+ *   [7] log of the acceptance uniform
+ * Normals use the Box-Muller transform. */
+void orc_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                    uint32_t j, double out[8])
+{
+    uint32_t key[2] = {seed, chain};
+    uint32_t w[4];
+    uint32_t ctr[4] = {sweep, region, j, 0u};
+
+    orc_philox4x32_10(ctr, key, w);
+    out[0] = orc_u01(w[0], w[1]);
+    out[1] = orc_u01(w[2], w[3]);
+
+    ctr[3] = 1u;
+    orc_philox4x32_10(ctr, key, w);
+    out[2] = orc_u01(w[0], w[1]);
+    out[3] = orc_u01(w[2], w[3]);
+
+    ctr[3] = 2u;
+    orc_philox4x32_10(ctr, key, w);
+    out[4] = -log(orc_u01(w[0], w[1]));
+    out[7] = log(orc_u01(w[2], w[3]));
+
+    ctr[3] = 3u;
+    orc_philox4x32_10(ctr, key, w);
+    double u1 = orc_u01(w[0], w[1]);
+    double u2 = orc_u01(w[2], w[3]);
+    double r = sqrt(-2.0 * log(u1));
+    out[5] = r * cos(2.0 * M_PI * u2);
+    out[6] = r * sin(2.0 * M_PI * u2);
+}
+
+/* Dynamic colouring (Section 4.3.2): after every full round the region
+ * boundaries are shifted by an offset drawn uniformly; here one offset per
+ * axis, uniform on [0, w), drawn from counter (sweep, 0xFFFFFFFF, 0, 0). */
+void orc_offset(uint32_t seed, uint32_t chain, uint32_t sweep, double wx, double wy,
+                double *dx, double *dy)
+{
+    uint32_t key[2] = {seed, chain};
+    uint32_t ctr[4] = {sweep, 0xFFFFFFFFu, 0u, 0u};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    *dx = orc_u01(w[0], w[1]) * wx;
+    *dy = orc_u01(w[2], w[3]) * wy;
+}
+
+/* ------------------------------------------------------------------------
+ * Geometry.  Stations sit at the centres of an nsx x nsy grid of cells of
+ * side ds.
+ * ---------------------------------------------------------------------- */
+double orc_station_x(const orc_model *m, int32_t ix) { return ((double)ix + 0.5) * m->ds; }
+double orc_station_y(const orc_model *m, int32_t iy) { return ((double)iy + 0.5) * m->ds; }
+
+/* Region index along one axis (Section 4.1 partitions the latent space into
+ * intervals of length l; Section 4.3.2 shifts all boundaries by an offset).
+ * Region i covers [off + (i-1) w, off + i w) clipped to the domain, so an
+ * offset in [0, w) gives regions 0..g. */
+int32_t orc_region_axis(double x, double off, double w, int32_t g)
+{
+    double f = floor((x - off) / w);
+    int32_t i = (int32_t)f + 1;
+    if (i < 0) i = 0;
+    if (i > g) i = g;
+    return i;
+}
+
+static void region_bounds(double off, double w, double L, int32_t i, double *lo, double *hi)
+{
+    double a = off + (double)(i - 1) * w;
+    double b = off + (double)i * w;
+    *lo = a > 0.0 ? a : 0.0;
+    *hi = b < L ? b : L;
+}
+
+/* Distance from a point to the closure of a rectangle. */
+static double rect_dist(double px, double py, double x0, double x1, double y0, double y1)
+{
+    double dx = 0.0, dy = 0.0;
+    if (px < x0) dx = x0 - px; else if (px > x1) dx = px - x1;
+    if (py < y0) dy = y0 - py; else if (py > y1) dy = py - y1;
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* Number of (station, pair of same-coloured regions) conflicts: two regions
+ * of one colour must not both lie within the detection cutoff of a common
+ * station, otherwise their events could explain the same signal and the
+ * regions would not be conditionally independent (the Markov-blanket
+ * argument of Section 4.1, with the blanket given by shared stations). */
+int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
+                                double offx, double offy, int32_t period)
+{
+    double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    double wx = Lx / (double)gx, wy = Ly / (double)gy;
+    int32_t nrx = gx + 1;
+    int64_t bad = 0;
+    int32_t cap = (gx + 1) * (gy + 1);
+    int32_t *near = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    for (int32_t sy = 0; sy < m->nsy; ++sy) {
+        for (int32_t sx = 0; sx < m->nsx; ++sx) {
+            double px = orc_station_x(m, sx), py = orc_station_y(m, sy);
+            int32_t nn = 0;
+            for (int32_t k = 0; k <= gy; ++k) {
+                double y0, y1;
+                region_bounds(offy, wy, Ly, k, &y0, &y1);
+                if (!(y1 > y0)) continue;
+                for (int32_t i = 0; i <= gx; ++i) {
+                    double x0, x1;
+                    region_bounds(offx, wx, Lx, i, &x0, &x1);
+                    if (!(x1 > x0)) continue;
+                    if (rect_dist(px, py, x0, x1, y0, y1) < m->rc) near[nn++] = k * nrx + i;
+                }
+            }
+            for (int32_t a = 0; a < nn; ++a) {
+                for (int32_t b = a + 1; b < nn; ++b) {
+                    int32_t ia = near[a] % nrx, ka = near[a] / nrx;
+                    int32_t ib = near[b] % nrx, kb = near[b] / nrx;
+                    int32_t ca = (ia % period) + period * (ka % period);
+                    int32_t cb = (ib % period) + period * (kb % period);
+                    if (ca == cb) ++bad;
+                }
+            }
+        }
+    }
+    free(near);
+    return bad;
+}
+
+/* Partition and colouring.  Colour of region (i, k) is (i mod p) + p (k mod p).
+ * Static partitions (Section 4.3.1) use the smallest period whose colouring
+ * passes the exact station check at the given offset; dynamic partitions
+ * (Section 4.3.2) need a period that holds for every offset: same-coloured
+ * regions are then at least (p - 1) w apart, which exceeds 2 rc when
+ * p = ceil(2 rc / w) + 1.  Returns 0, or -4 when no valid colouring exists. */
+int32_t orc_partition_and_color(const orc_model *m, int32_t gx, int32_t gy,
+                                double offx, double offy, int32_t dynamic,
+                                int32_t *nrx, int32_t *nry, int32_t *period,
+                                int32_t *ncolors, int32_t *color_of_region)
+{
+    double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    double wx = Lx / (double)gx, wy = Ly / (double)gy;
+    double w = wx < wy ? wx : wy;
+    int32_t p;
+    if (dynamic) {
+        p = (int32_t)ceil(2.0 * m->rc / w) + 1;
+        if (orc_coloring_violations(m, gx, gy, offx, offy, p) != 0) return -4;
+    } else {
+        int32_t pmax = (gx > gy ? gx : gy) + 1;
+        for (p = 1; p <= pmax; ++p)
+            if (orc_coloring_violations(m, gx, gy, offx, offy, p) == 0) break;
+        if (p > pmax) return -4;
+    }
+    *nrx = gx + 1;
+    *nry = gy + 1;
+    *period = p;
+    *ncolors = p * p;
+    if (color_of_region) {
+        for (int32_t k = 0; k <= gy; ++k)
+            for (int32_t i = 0; i <= gx; ++i)
+                color_of_region[k * (gx + 1) + i] = (i % p) + p * (k % p);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Signal model (Section 3).
+ * ---------------------------------------------------------------------- */
+
+/* Arrival time of an event at a station: onset plus distance over wave speed
+ * (the mean of the arrival model in Section 3; this model has no jitter). */
+double orc_arrival_time(double x, double y, double t, double sx, double sy, double vel,
+                        double *d_out)
+{
+    double dx = x - sx, dy = y - sy;
+    double d = sqrt(dx * dx + dy * dy);
+    if (d_out) *d_out = d;
+    return t + d / vel;
+}
+
+/* Arrival of one event at station (ix, iy): distance d, detection d < rc,
+ * arrival a = t + d / vel, amplitude A = m exp(-d / atten), and the samples
+ * [n0, n1) = [ceil(a), ceil(a) + ts) clipped to the trace. */
+void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
+                 orc_arrival_t *out)
+{
+    out->a = orc_arrival_time(e->x, e->y, e->t, orc_station_x(m, ix), orc_station_y(m, iy),
+                              m->vel, &out->d);
+    out->in = out->d < m->rc;
+    out->amp = e->m * exp(-out->d / m->atten);
+    int64_t n0 = (int64_t)ceil(out->a);
+    int64_t n1 = n0 + m->ts;
+    if (n0 < 0) n0 = 0;
+    if (n1 > m->N) n1 = m->N;
+    if (!out->in || n0 >= n1) { n0 = 0; n1 = 0; }
+    out->n0 = n0;
+    out->n1 = n1;
+}
+
+/* Variance the event adds at sample n: its signal is zero-mean Gaussian with
+ * standard deviation A phi(n - a), phi(tau) = exp(-tau / decay), during the
+ * signal duration, and absent otherwise. */
+double orc_arrival_variance(const orc_model *m, const orc_arrival_t *ar, int64_t n)
+{
+    if (n < ar->n0 || n >= ar->n1) return 0.0;
+    double env = exp(-((double)n - ar->a) / m->decay);
+    double sd = ar->amp * env;
+    return sd * sd;
+}
+
+/* Events whose signal reaches station (ix, iy) at all. */
+static int64_t events_at_station(const orc_model *m, const orc_event *ev, int64_t nev,
+                                 int32_t ix, int32_t iy, int64_t *idx)
+{
+    int64_t k = 0;
+    double sx = orc_station_x(m, ix), sy = orc_station_y(m, iy);
+    for (int64_t i = 0; i < nev; ++i) {
+        double dx = ev[i].x - sx, dy = ev[i].y - sy;
+        if (sqrt(dx * dx + dy * dy) < m->rc) idx[k++] = i;
+    }
+    return k;
+}
+
+/* One station's summed event variance: row[n] = sum over the listed events,
+ * in list order, of the variance each adds at sample n. */
+static void station_row(const orc_model *m, const orc_event *ev, const int64_t *idx,
+                        int64_t k, int32_t ix, int32_t iy, double *row)
+{
+    for (int64_t n = 0; n < m->N; ++n) row[n] = 0.0;
+    for (int64_t q = 0; q < k; ++q) {
+        orc_arrival_t ar;
+        orc_arrival(m, &ev[idx[q]], ix, iy, &ar);
+        for (int64_t n = ar.n0; n < ar.n1; ++n) row[n] += orc_arrival_variance(m, &ar, n);
+    }
+}
+
+/* E[j][n] = sum over events of the variance each adds (no noise term).
+ * Station j = iy * nsx + ix, samples contiguous. */
+void orc_event_variance(const orc_model *m, const orc_event *ev, int64_t nev, double *E)
+{
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
+    for (int32_t iy = 0; iy < m->nsy; ++iy) {
+        for (int32_t ix = 0; ix < m->nsx; ++ix) {
+            double *row = E + ((int64_t)iy * m->nsx + ix) * m->N;
+            int64_t k = events_at_station(m, ev, nev, ix, iy, idx);
+            station_row(m, ev, idx, k, ix, iy, row);
+        }
+    }
+    free(idx);
+}
+
+/* Log density of one sample: zero-mean Gaussian with variance sigma^2 + e. */
+double orc_single_term(double sigma, double s, double e)
+{
+    double v = sigma * sigma + e;
+    return -0.5 * (log(2.0 * M_PI) + log(v) + s * s / v);
+}
+
+/* Signal log-likelihood log P(s | e) summed over every station and sample. */
+double orc_loglik(const orc_model *m, const double *s, const orc_event *ev, int64_t nev)
+{
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
+    double *row = (double *)malloc(sizeof(double) * (size_t)m->N);
+    double total = 0.0;
+    for (int32_t iy = 0; iy < m->nsy; ++iy) {
+        for (int32_t ix = 0; ix < m->nsx; ++ix) {
+            const double *sr = s + ((int64_t)iy * m->nsx + ix) * m->N;
+            int64_t k = events_at_station(m, ev, nev, ix, iy, idx);
+            station_row(m, ev, idx, k, ix, iy, row);
+            for (int64_t n = 0; n < m->N; ++n) total += orc_single_term(m->sigma, sr[n], row[n]);
+        }
+    }
+    free(row);
+    free(idx);
+    return total;
+}
+
+/* Log of the event prior (Section 3) as a set density: Poisson count with
+ * mean lambda, uniform location over the domain, uniform onset over [0, N),
+ * exponential magnitude above mmin. */
+double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev)
+{
+    double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    double total = -m->lambda;
+    for (int64_t i = 0; i < nev; ++i) {
+        total += log(m->lambda) - log(Lx * Ly) - log((double)m->N) + log(m->mrate)
+                 - m->mrate * (ev[i].m - m->mmin);
+    }
+    return total;
+}
+
+/* Forward simulator (Section 5 evaluates on worlds sampled from the model):
+ * given the true events, each sample is Gaussian with the model's variance,
+ * s = sqrt(sigma^2 + E) z.  The standard normal z for station j and sample n
+ * comes from Philox under key (seed, 0x80000001), counter (n / 2, j, 0, 0),
+ * by Box-Muller: even n take the cosine branch, odd n the sine branch. */
+void orc_simulate(const orc_model *m, const orc_event *truth, int64_t nev,
+                  uint32_t seed, double *s_out)
+{
+    uint32_t key[2] = {seed, 0x80000001u};
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
+    double *row = (double *)malloc(sizeof(double) * (size_t)m->N);
+    for (int32_t iy = 0; iy < m->nsy; ++iy) {
+        for (int32_t ix = 0; ix < m->nsx; ++ix) {
+            int64_t j = (int64_t)iy * m->nsx + ix;
+            double *out = s_out + j * m->N;
+            int64_t k = events_at_station(m, truth, nev, ix, iy, idx);
+            station_row(m, truth, idx, k, ix, iy, row);
+            for (int64_t n = 0; n < m->N; ++n) {
+                uint32_t ctr[4] = {(uint32_t)(n >> 1), (uint32_t)j, 0u, 0u};
+                uint32_t w[4];
+                orc_philox4x32_10(ctr, key, w);
+                double u1 = orc_u01(w[0], w[1]);
+                double u2 = orc_u01(w[2], w[3]);
+                double r = sqrt(-2.0 * log(u1));
+                double z = (n & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
+                out[n] = sqrt(m->sigma * m->sigma + row[n]) * z;
+            }
+        }
+    }
+    free(row);
+    free(idx);
+}

@@ -1,0 +1,611 @@
+/*
+ * orc_sampler.c -- oracle: the Metropolis-Hastings sampler over the event
+ * set, run region by region in colour phases.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Follows Section 4: the latent space is partitioned into regions
+ * (Section 4.1), regions are coloured so that regions of one colour are
+ * conditionally independent, and Algorithm 4 runs k MH moves inside every
+ * region of one colour while the other regions are held at their values from
+ * the start of the phase.  Section 4.3.2 (dynamic colouring) redraws the
+ * partition offset after every full round of colours.  Algorithm 3 (naive
+ * parallel MH) is the same phase with every region in one colour; it is kept
+ * only as a negative control.
+ *
+ * The log-likelihood change of a move is evaluated directly: for every sample
+ * the move can affect, the model variance is summed from scratch over the
+ * events present before and after the move, and the two Gaussian log
+ * densities are differenced.  No incremental state is kept.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    orc_event *e;
+    int64_t n, capa;
+} evlist;
+
+static void ev_push(evlist *l, const orc_event *e)
+{
+    if (l->n == l->capa) {
+        l->capa = l->capa ? 2 * l->capa : 8;
+        l->e = (orc_event *)realloc(l->e, sizeof(orc_event) * (size_t)l->capa);
+    }
+    l->e[l->n++] = *e;
+}
+
+/* Removal keeps the remaining events in their order. */
+static void ev_remove(evlist *l, int64_t i)
+{
+    for (int64_t q = i; q + 1 < l->n; ++q) l->e[q] = l->e[q + 1];
+    l->n--;
+}
+
+static int cmp_id(const void *a, const void *b)
+{
+    uint64_t x = ((const orc_event *)a)->id, y = ((const orc_event *)b)->id;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+struct orc_chain {
+    orc_model m;
+    orc_sampler sp;
+    const double *s;
+    uint32_t seed, chain;
+    double Lx, Ly, wx, wy;
+    int32_t nrx, nry, period, ncolors;
+    double offx, offy;
+    int32_t *color;
+    int64_t nreg;
+    evlist *reg;        /* per region, sorted by id */
+    evlist *snap;       /* per station: copies of the events that reach it */
+    int64_t nsta;
+    int64_t overflows;
+    int32_t laid_out;
+};
+
+/* ---------------------------------------------------------------- lattice */
+static double lat_hx(const orc_chain *c) { return c->Lx / (double)c->sp.kx; }
+static double lat_hy(const orc_chain *c) { return c->Ly / (double)c->sp.ky; }
+static double lat_ht(const orc_chain *c) { return (double)c->m.N / (double)c->sp.kt; }
+
+static void lat_coords(const orc_chain *c, int32_t ix, int32_t iy, int32_t it, int32_t im,
+                       orc_event *e)
+{
+    e->x = ((double)ix + 0.5) * lat_hx(c);
+    e->y = ((double)iy + 0.5) * lat_hy(c);
+    e->t = ((double)it + 0.5) * lat_ht(c);
+    e->m = c->m.mmin + ((double)im + 0.5) * c->sp.hm;
+}
+
+static void lat_index(const orc_chain *c, const orc_event *e, int32_t *ix, int32_t *iy,
+                      int32_t *it, int32_t *im)
+{
+    *ix = (int32_t)floor(e->x / lat_hx(c));
+    *iy = (int32_t)floor(e->y / lat_hy(c));
+    *it = (int32_t)floor(e->t / lat_ht(c));
+    *im = (int32_t)floor((e->m - c->m.mmin) / c->sp.hm);
+}
+
+/* ------------------------------------------------------------- partition */
+static int32_t region_of(const orc_chain *c, double x, double y)
+{
+    int32_t i = orc_region_axis(x, c->offx, c->wx, c->sp.gx);
+    int32_t k = orc_region_axis(y, c->offy, c->wy, c->sp.gy);
+    return k * c->nrx + i;
+}
+
+static void region_rect(const orc_chain *c, int32_t r, double *x0, double *x1, double *y0,
+                        double *y1)
+{
+    int32_t i = r % c->nrx, k = r / c->nrx;
+    double a = c->offx + (double)(i - 1) * c->wx, b = c->offx + (double)i * c->wx;
+    *x0 = a > 0.0 ? a : 0.0;
+    *x1 = b < c->Lx ? b : c->Lx;
+    a = c->offy + (double)(k - 1) * c->wy;
+    b = c->offy + (double)k * c->wy;
+    *y0 = a > 0.0 ? a : 0.0;
+    *y1 = b < c->Ly ? b : c->Ly;
+}
+
+/* Lattice sites (x, y part) inside region r, in row-major order. */
+static int64_t lat_region_sites(const orc_chain *c, int32_t r, int64_t want, int32_t *ix,
+                                int32_t *iy)
+{
+    int64_t cnt = 0;
+    for (int32_t b = 0; b < c->sp.ky; ++b) {
+        for (int32_t a = 0; a < c->sp.kx; ++a) {
+            orc_event e;
+            lat_coords(c, a, b, 0, 0, &e);
+            if (region_of(c, e.x, e.y) != r) continue;
+            if (cnt == want) { *ix = a; *iy = b; }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double *s,
+                         uint32_t seed, uint32_t chain)
+{
+    orc_chain *c = (orc_chain *)calloc(1, sizeof(orc_chain));
+    c->m = *m;
+    c->sp = *sp;
+    c->s = s;
+    c->seed = seed;
+    c->chain = chain;
+    c->Lx = (double)m->nsx * m->ds;
+    c->Ly = (double)m->nsy * m->ds;
+    c->wx = c->Lx / (double)sp->gx;
+    c->wy = c->Ly / (double)sp->gy;
+    c->nrx = sp->gx + 1;
+    c->nry = sp->gy + 1;
+    c->nreg = (int64_t)c->nrx * c->nry;
+    c->color = (int32_t *)calloc((size_t)c->nreg, sizeof(int32_t));
+    c->reg = (evlist *)calloc((size_t)c->nreg, sizeof(evlist));
+    c->nsta = (int64_t)m->nsx * m->nsy;
+    c->snap = (evlist *)calloc((size_t)c->nsta, sizeof(evlist));
+    return c;
+}
+
+void orc_chain_free(orc_chain *c)
+{
+    if (!c) return;
+    for (int64_t r = 0; r < c->nreg; ++r) free(c->reg[r].e);
+    for (int64_t j = 0; j < c->nsta; ++j) free(c->snap[j].e);
+    free(c->reg);
+    free(c->snap);
+    free(c->color);
+    free(c);
+}
+
+/* Lay out the partition for this sweep and move every event into the list
+ * of its region, each list sorted by event id.  Returns 0, -3 when a region
+ * would exceed its capacity, -4 when the colouring check fails. */
+static int32_t relayout(orc_chain *c, double offx, double offy)
+{
+    c->offx = offx;
+    c->offy = offy;
+    if (!c->laid_out || c->sp.dynamic) {
+        int32_t nrx, nry, p, nc;
+        int32_t rc = orc_partition_and_color(&c->m, c->sp.gx, c->sp.gy, offx, offy,
+                                             c->sp.dynamic, &nrx, &nry, &p, &nc, c->color);
+        if (rc != 0) return rc;
+        if (c->sp.period > 0) {
+            if (orc_coloring_violations(&c->m, c->sp.gx, c->sp.gy, offx, offy, c->sp.period) != 0)
+                return -4;
+            p = c->sp.period;
+            nc = p * p;
+            for (int32_t k = 0; k < nry; ++k)
+                for (int32_t i = 0; i < nrx; ++i) c->color[k * nrx + i] = (i % p) + p * (k % p);
+        }
+        c->period = p;
+        c->ncolors = nc;
+        c->laid_out = 1;
+    }
+    evlist all = {0, 0, 0};
+    for (int64_t r = 0; r < c->nreg; ++r) {
+        for (int64_t q = 0; q < c->reg[r].n; ++q) ev_push(&all, &c->reg[r].e[q]);
+        c->reg[r].n = 0;
+    }
+    int32_t status = 0;
+    for (int64_t q = 0; q < all.n; ++q) {
+        orc_event e = all.e[q];
+        e.region = region_of(c, e.x, e.y);
+        if (c->reg[e.region].n >= c->sp.cap) status = -3;
+        ev_push(&c->reg[e.region], &e);
+    }
+    for (int64_t r = 0; r < c->nreg; ++r)
+        qsort(c->reg[r].e, (size_t)c->reg[r].n, sizeof(orc_event), cmp_id);
+    free(all.e);
+    return status;
+}
+
+int32_t orc_chain_begin_sweep(orc_chain *c, int64_t sweep)
+{
+    double ox = 0.0, oy = 0.0;
+    if (c->sp.dynamic) orc_offset(c->seed, c->chain, (uint32_t)sweep, c->wx, c->wy, &ox, &oy);
+    return relayout(c, ox, oy);
+}
+
+int32_t orc_chain_set_events(orc_chain *c, const orc_event *ev, int64_t nev)
+{
+    for (int64_t r = 0; r < c->nreg; ++r) c->reg[r].n = 0;
+    for (int64_t q = 0; q < nev; ++q) ev_push(&c->reg[0], &ev[q]);
+    return relayout(c, c->offx, c->offy);
+}
+
+void orc_chain_layout(const orc_chain *c, int32_t *nrx, int32_t *nry, int32_t *period,
+                      int32_t *ncolors, double *offx, double *offy)
+{
+    *nrx = c->nrx; *nry = c->nry; *period = c->period; *ncolors = c->ncolors;
+    *offx = c->offx; *offy = c->offy;
+}
+
+int64_t orc_chain_count(const orc_chain *c)
+{
+    int64_t n = 0;
+    for (int64_t r = 0; r < c->nreg; ++r) n += c->reg[r].n;
+    return n;
+}
+
+/* Events in region order, each region's list in id order. */
+int64_t orc_chain_events(const orc_chain *c, orc_event *out, int64_t cap)
+{
+    int64_t n = 0;
+    for (int64_t r = 0; r < c->nreg; ++r)
+        for (int64_t q = 0; q < c->reg[r].n; ++q) {
+            if (n < cap) out[n] = c->reg[r].e[q];
+            ++n;
+        }
+    return n;
+}
+
+int64_t orc_chain_overflows(const orc_chain *c) { return c->overflows; }
+
+/* ----------------------------------------------------------- likelihood */
+
+/* Snapshot of the event set at the start of a colour phase, indexed by the
+ * stations each event reaches (Algorithm 4 holds the other regions at these
+ * values for the whole phase). */
+static void build_snapshot(orc_chain *c)
+{
+    for (int64_t j = 0; j < c->nsta; ++j) c->snap[j].n = 0;
+    int32_t reach = (int32_t)ceil(c->m.rc / c->m.ds) + 1;
+    for (int64_t r = 0; r < c->nreg; ++r) {
+        for (int64_t q = 0; q < c->reg[r].n; ++q) {
+            const orc_event *e = &c->reg[r].e[q];
+            int32_t cx = (int32_t)floor(e->x / c->m.ds), cy = (int32_t)floor(e->y / c->m.ds);
+            for (int32_t iy = cy - reach; iy <= cy + reach; ++iy) {
+                if (iy < 0 || iy >= c->m.nsy) continue;
+                for (int32_t ix = cx - reach; ix <= cx + reach; ++ix) {
+                    if (ix < 0 || ix >= c->m.nsx) continue;
+                    orc_arrival_t ar;
+                    orc_arrival(&c->m, e, ix, iy, &ar);
+                    if (ar.in) ev_push(&c->snap[(int64_t)iy * c->m.nsx + ix], e);
+                }
+            }
+        }
+    }
+}
+
+static double gauss_logpdf(double s, double v)
+{
+    return -0.5 * (log(2.0 * M_PI) + log(v) + s * s / v);
+}
+
+/* Change of log P(s | e) when, in region r, the event at index idx of the
+ * region's list is removed (death), replaced by *nw (location, time and
+ * magnitude moves), or *nw is added (birth).  Every other region contributes
+ * its snapshot events.  Sums run over the union of the samples where the old
+ * or the new event has signal; elsewhere nothing changes. */
+static double move_delta(orc_chain *c, int32_t r, int32_t type, int64_t idx,
+                         const orc_event *nw)
+{
+    const orc_model *m = &c->m;
+    const evlist *own = &c->reg[r];
+    const orc_event *old = (type == ORC_BIRTH) ? NULL : &own->e[idx];
+    const orc_event *neu = (type == ORC_DEATH) ? NULL : nw;
+    int32_t reach = (int32_t)ceil(m->rc / m->ds) + 1;
+    int32_t lo_x = m->nsx, hi_x = -1, lo_y = m->nsy, hi_y = -1;
+    const orc_event *pts[2] = {old, neu};
+    for (int q = 0; q < 2; ++q) {
+        if (!pts[q]) continue;
+        int32_t cx = (int32_t)floor(pts[q]->x / m->ds), cy = (int32_t)floor(pts[q]->y / m->ds);
+        if (cx - reach < lo_x) lo_x = cx - reach;
+        if (cx + reach > hi_x) hi_x = cx + reach;
+        if (cy - reach < lo_y) lo_y = cy - reach;
+        if (cy + reach > hi_y) hi_y = cy + reach;
+    }
+    if (lo_x < 0) lo_x = 0;
+    if (lo_y < 0) lo_y = 0;
+    if (hi_x >= m->nsx) hi_x = m->nsx - 1;
+    if (hi_y >= m->nsy) hi_y = m->nsy - 1;
+
+    double delta = 0.0;
+    orc_arrival_t *others = NULL;
+    int64_t others_cap = 0;
+    for (int32_t iy = lo_y; iy <= hi_y; ++iy) {
+        for (int32_t ix = lo_x; ix <= hi_x; ++ix) {
+            orc_arrival_t ao, an;
+            memset(&ao, 0, sizeof ao);
+            memset(&an, 0, sizeof an);
+            if (old) orc_arrival(m, old, ix, iy, &ao);
+            if (neu) orc_arrival(m, neu, ix, iy, &an);
+            if (!ao.in && !an.in) continue;
+            int64_t lo = m->N, hi = 0;
+            if (ao.n1 > ao.n0) { lo = ao.n0; hi = ao.n1; }
+            if (an.n1 > an.n0) {
+                if (an.n0 < lo) lo = an.n0;
+                if (an.n1 > hi) hi = an.n1;
+            }
+            if (hi <= lo) continue;
+            int64_t j = (int64_t)iy * m->nsx + ix;
+            /* every other event reaching this station */
+            int64_t need = c->snap[j].n + own->n;
+            if (need > others_cap) {
+                others_cap = need;
+                others = (orc_arrival_t *)realloc(others, sizeof(orc_arrival_t) * (size_t)need);
+            }
+            int64_t no = 0;
+            for (int64_t q = 0; q < c->snap[j].n; ++q) {
+                if (c->snap[j].e[q].region == r) continue;
+                orc_arrival(m, &c->snap[j].e[q], ix, iy, &others[no]);
+                if (others[no].in) ++no;
+            }
+            for (int64_t q = 0; q < own->n; ++q) {
+                if (old && q == idx) continue;
+                orc_arrival(m, &own->e[q], ix, iy, &others[no]);
+                if (others[no].in) ++no;
+            }
+            const double *srow = c->s + j * m->N;
+            for (int64_t n = lo; n < hi; ++n) {
+                double base = m->sigma * m->sigma;
+                for (int64_t q = 0; q < no; ++q) base += orc_arrival_variance(m, &others[q], n);
+                double v_old = base + (old ? orc_arrival_variance(m, &ao, n) : 0.0);
+                double v_new = base + (neu ? orc_arrival_variance(m, &an, n) : 0.0);
+                delta += gauss_logpdf(srow[n], v_new) - gauss_logpdf(srow[n], v_old);
+            }
+        }
+    }
+    free(others);
+    return delta;
+}
+
+double orc_chain_delta(orc_chain *c, int32_t region, int32_t type, int64_t idx,
+                       const orc_event *proposed)
+{
+    build_snapshot(c);
+    return move_delta(c, region, type, idx, proposed);
+}
+
+/* --------------------------------------------------------------- moves */
+
+/* One MH move inside region r (Algorithm 2's step, confined to the region
+ * as in Algorithm 4).  Move types (Section 3): birth from the region's prior
+ * and death of a uniformly chosen event (Geyer-Moller birth-death for a
+ * Poisson process restricted to the region), a Gaussian location offset, a
+ * Gaussian time offset and a Gaussian magnitude offset.  A proposal that
+ * leaves the region, the trace or the magnitude support is rejected without
+ * evaluating the likelihood.  log entry: type, status (0 invalid,
+ * 1 rejected, 2 accepted), delta, log alpha. */
+static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const double *d,
+                     double lam_r, double *logentry)
+{
+    const orc_model *m = &c->m;
+    const orc_sampler *sp = &c->sp;
+    evlist *own = &c->reg[r];
+    int64_t n = own->n;
+    double c1 = sp->pb, c2 = c1 + sp->pd, c3 = c2 + sp->ploc, c4 = c3 + sp->pt;
+    int32_t type = d[0] < c1 ? ORC_BIRTH
+                 : d[0] < c2 ? ORC_DEATH
+                 : d[0] < c3 ? ORC_LOC
+                 : d[0] < c4 ? ORC_TIME : ORC_MAG;
+    int valid = 1;
+    int64_t idx = -1;
+    orc_event nw;
+    memset(&nw, 0, sizeof nw);
+
+    if (type == ORC_BIRTH) {
+        if (n >= sp->cap) {
+            valid = 0;
+            c->overflows++;
+        } else if (sp->lattice) {
+            int32_t ix = 0, iy = 0;
+            int64_t nr = lat_region_sites(c, r, -1, &ix, &iy);
+            int64_t pick = (int64_t)floor(d[1] * (double)nr);
+            if (pick >= nr) pick = nr - 1;
+            lat_region_sites(c, r, pick, &ix, &iy);
+            int32_t it = (int32_t)floor(d[2] * (double)sp->kt);
+            int32_t im = (int32_t)floor(d[3] * (double)sp->km);
+            if (it >= sp->kt) it = sp->kt - 1;
+            if (im >= sp->km) im = sp->km - 1;
+            lat_coords(c, ix, iy, it, im, &nw);
+        } else {
+            double x0, x1, y0, y1;
+            region_rect(c, r, &x0, &x1, &y0, &y1);
+            nw.x = x0 + d[1] * (x1 - x0);
+            nw.y = y0 + d[2] * (y1 - y0);
+            nw.t = d[3] * (double)m->N;
+            nw.m = m->mmin + d[4] / m->mrate;
+            valid = nw.x >= 0.0 && nw.x < c->Lx && nw.y >= 0.0 && nw.y < c->Ly &&
+                    nw.t < (double)m->N && region_of(c, nw.x, nw.y) == r;
+        }
+        nw.id = ((uint64_t)sweep << 32) | ((uint64_t)(uint32_t)r << 12) | (uint64_t)j;
+        nw.region = r;
+    } else {
+        if (n == 0) {
+            valid = 0;
+        } else {
+            idx = (int64_t)floor(d[1] * (double)n);
+            if (idx >= n) idx = n - 1;
+            nw = own->e[idx];
+            if (sp->lattice) {
+                int32_t ix, iy, it, im;
+                lat_index(c, &nw, &ix, &iy, &it, &im);
+                if (type == ORC_LOC) {
+                    int32_t dir = (int32_t)floor(d[2] * 4.0);
+                    if (dir == 0) ix -= 1; else if (dir == 1) ix += 1;
+                    else if (dir == 2) iy -= 1; else iy += 1;
+                } else if (type == ORC_TIME) {
+                    it += d[2] < 0.5 ? -1 : 1;
+                } else if (type == ORC_MAG) {
+                    im += d[2] < 0.5 ? -1 : 1;
+                }
+                if (type != ORC_DEATH) {
+                    valid = ix >= 0 && ix < sp->kx && iy >= 0 && iy < sp->ky && it >= 0 &&
+                            it < sp->kt && im >= 0 && im < sp->km;
+                    if (valid) {
+                        lat_coords(c, ix, iy, it, im, &nw);
+                        valid = region_of(c, nw.x, nw.y) == r;
+                    }
+                }
+            } else if (type == ORC_LOC) {
+                nw.x = nw.x + sp->sxy * d[5];
+                nw.y = nw.y + sp->sxy * d[6];
+                valid = nw.x >= 0.0 && nw.x < c->Lx && nw.y >= 0.0 && nw.y < c->Ly &&
+                        region_of(c, nw.x, nw.y) == r;
+            } else if (type == ORC_TIME) {
+                nw.t = nw.t + sp->st * d[5];
+                valid = nw.t >= 0.0 && nw.t < (double)m->N;
+            } else if (type == ORC_MAG) {
+                nw.m = nw.m + sp->sm * d[5];
+                valid = nw.m >= m->mmin;
+            }
+        }
+    }
+
+    double delta = 0.0, la = 0.0;
+    int32_t status = 0;
+    if (valid) {
+        if (!sp->prior_only) delta = move_delta(c, r, type, idx, &nw);
+        if (type == ORC_BIRTH) {
+            la = delta + log(lam_r) + log(sp->pd) - log((double)(n + 1)) - log(sp->pb);
+        } else if (type == ORC_DEATH) {
+            la = delta + log((double)n) + log(sp->pb) - log(lam_r) - log(sp->pd);
+        } else if (type == ORC_MAG && !sp->lattice) {
+            la = delta - m->mrate * (nw.m - own->e[idx].m);
+        } else {
+            la = delta;
+        }
+        if (d[7] < la) {
+            status = 2;
+            if (type == ORC_BIRTH) ev_push(own, &nw);
+            else if (type == ORC_DEATH) ev_remove(own, idx);
+            else own->e[idx] = nw;
+        } else {
+            status = 1;
+        }
+    }
+    if (logentry) {
+        logentry[0] = (double)type;
+        logentry[1] = (double)status;
+        logentry[2] = delta;
+        logentry[3] = la;
+    }
+}
+
+/* One colour phase of Algorithm 4: every region of the colour runs k moves;
+ * the other regions are held at the phase-start snapshot.  With the naive
+ * schedule (Algorithm 3) every region belongs to the phase.
+ * feed (optional): draws [region][k][8]; log (optional): [region][k][4]. */
+int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double *feed,
+                        double *log_out)
+{
+    build_snapshot(c);
+    for (int64_t r = 0; r < c->nreg; ++r) {
+        if (c->sp.schedule == ORC_SCHED_CHROMATIC && c->color[r] != color) continue;
+        double x0, x1, y0, y1;
+        region_rect(c, (int32_t)r, &x0, &x1, &y0, &y1);
+        double area = (x1 - x0) * (y1 - y0);
+        if (!(area > 0.0)) continue;
+        double lam_r;
+        if (c->sp.lattice) {
+            int32_t a, b;
+            int64_t nr = lat_region_sites(c, (int32_t)r, -1, &a, &b);
+            if (nr == 0) continue;
+            lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.ky);
+        } else {
+            lam_r = c->m.lambda * area / (c->Lx * c->Ly);
+        }
+        for (int32_t j = 0; j < c->sp.k; ++j) {
+            double d[8];
+            const double *dp;
+            if (feed) {
+                dp = feed + ((r * c->sp.k) + j) * 8;
+            } else {
+                orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+                dp = d;
+            }
+            run_move(c, (int32_t)r, (uint32_t)sweep, (uint32_t)j, dp, lam_r,
+                     log_out ? log_out + ((r * c->sp.k) + j) * 4 : NULL);
+        }
+    }
+    return 0;
+}
+
+/* One full sweep: lay out the partition (a fresh offset when dynamic), then
+ * the colours in ascending order. */
+int32_t orc_chain_sweep(orc_chain *c, int64_t sweep, const double *feed, double *log_out)
+{
+    int32_t rc = orc_chain_begin_sweep(c, sweep);
+    if (rc != 0) return rc;
+    int32_t nphase = c->sp.schedule == ORC_SCHED_NAIVE ? 1 : c->ncolors;
+    for (int32_t col = 0; col < nphase; ++col) {
+        rc = orc_chain_phase(c, sweep, col, feed, log_out);
+        if (rc != 0) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ enumeration */
+
+int64_t orc_lattice_nsites(const orc_model *m, const orc_sampler *sp)
+{
+    (void)m;
+    return (int64_t)sp->kx * sp->ky * sp->kt * sp->km;
+}
+
+void orc_lattice_site(const orc_model *m, const orc_sampler *sp, int64_t site, orc_event *out)
+{
+    int32_t im = (int32_t)(site % sp->km);
+    int64_t rest = site / sp->km;
+    int32_t it = (int32_t)(rest % sp->kt);
+    rest /= sp->kt;
+    int32_t iy = (int32_t)(rest % sp->ky);
+    int32_t ix = (int32_t)(rest / sp->ky);
+    double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    memset(out, 0, sizeof *out);
+    out->x = ((double)ix + 0.5) * (Lx / (double)sp->kx);
+    out->y = ((double)iy + 0.5) * (Ly / (double)sp->ky);
+    out->t = ((double)it + 0.5) * ((double)m->N / (double)sp->kt);
+    out->m = m->mmin + ((double)im + 0.5) * sp->hm;
+}
+
+/* Every multiset of at most nmax sites, with its unnormalised log posterior:
+ * the lattice Poisson prior (independent Poisson(lambda / S) counts on the S
+ * sites, so a multiset with counts k_s has weight prod mu^k_s / k_s!) times
+ * the signal likelihood.  sites_out: [count][nmax], ascending, padded -1. */
+int64_t orc_enumerate(const orc_model *m, const orc_sampler *sp, const double *s,
+                      int32_t nmax, int32_t *sites_out, double *logw_out, int64_t cap)
+{
+    int64_t S = orc_lattice_nsites(m, sp);
+    double mu = m->lambda / (double)S;
+    int64_t count = 0;
+    int32_t *cur = (int32_t *)calloc((size_t)(nmax > 0 ? nmax : 1), sizeof(int32_t));
+    orc_event *ev = (orc_event *)calloc((size_t)(nmax > 0 ? nmax : 1), sizeof(orc_event));
+    for (int32_t n = 0; n <= nmax; ++n) {
+        for (int32_t q = 0; q < n; ++q) cur[q] = 0;
+        for (;;) {
+            double lw = -m->lambda + (double)n * log(mu);
+            int32_t run = 1;
+            for (int32_t q = 0; q < n; ++q) {
+                if (q > 0 && cur[q] == cur[q - 1]) {
+                    ++run;
+                    lw -= log((double)run);
+                } else {
+                    run = 1;
+                }
+                orc_lattice_site(m, sp, cur[q], &ev[q]);
+            }
+            if (!sp->prior_only) lw += orc_loglik(m, s, ev, n);
+            if (count < cap) {
+                for (int32_t q = 0; q < nmax; ++q)
+                    sites_out[count * nmax + q] = q < n ? cur[q] : -1;
+                logw_out[count] = lw;
+            }
+            ++count;
+            /* next non-decreasing sequence */
+            int32_t pos = n - 1;
+            while (pos >= 0 && cur[pos] == S - 1) --pos;
+            if (pos < 0) break;
+            cur[pos]++;
+            for (int32_t q = pos + 1; q < n; ++q) cur[q] = cur[pos];
+        }
+    }
+    free(cur);
+    free(ev);
+    return count;
+}

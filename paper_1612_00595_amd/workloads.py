@@ -1,0 +1,177 @@
+"""Workload definitions and seeded input generators.
+
+This module is the only one that both the GPU path and the CPU oracle draw
+their inputs from.  It holds workload constants and numpy random generators
+and none of the method's arithmetic: no likelihood, no proposal rule, no
+acceptance ratio.
+
+Workloads follow the paper's toy seismic model (Section 3) in the 2-D,
+attenuating form Section 4.1 names as the natural case for spatial
+partitioning; the paper evaluates only on synthetic worlds sampled from its
+own model (Section 5), so every input here is synthetic by construction.
+
+Physical constants shared by every workload: stations on a cell-centred grid
+of spacing 0.2, amplitude m exp(-d / 0.2), onset-delayed exponential envelope
+of decay 20 samples, arrival t + d / 0.05, noise sigma 0.1, detection cutoff
+0.19, signal duration 128 samples, magnitude 2 + Exp(1).  Larger workloads
+keep the station spacing and grow the domain, so that an event still reaches
+at most four stations.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BIRTH, DEATH, LOC, TIME, MAG = range(5)
+
+
+@dataclass(frozen=True)
+class ModelSpec:
+    nsx: int = 5
+    nsy: int = 5
+    ds: float = 0.2
+    N: int = 1000
+    sigma: float = 0.1
+    atten: float = 0.2
+    vel: float = 0.05
+    decay: float = 20.0
+    ts: int = 128
+    rc: float = 0.19
+    lam: float = 20.0
+    mmin: float = 2.0
+    mrate: float = 1.0
+
+    @property
+    def Lx(self) -> float:
+        return self.nsx * self.ds
+
+    @property
+    def Ly(self) -> float:
+        return self.nsy * self.ds
+
+    @property
+    def nsta(self) -> int:
+        return self.nsx * self.nsy
+
+    def asdict(self) -> dict:
+        return dataclasses.asdict(self)
+
+
+@dataclass(frozen=True)
+class SamplerSpec:
+    gx: int = 4
+    gy: int = 4
+    dynamic: int = 0
+    period: int = 0
+    k: int = 16
+    cap: int = 64
+    pb: float = 0.2
+    pd: float = 0.2
+    ploc: float = 0.2
+    pt: float = 0.2
+    pm: float = 0.2
+    sxy: float = 0.02
+    st: float = 1.0
+    sm: float = 0.2
+    prior_only: int = 0
+    schedule: int = 0
+    lattice: int = 0
+    kx: int = 0
+    ky: int = 0
+    kt: int = 0
+    km: int = 0
+    hm: float = 0.0
+
+    @property
+    def nreg(self) -> int:
+        return (self.gx + 1) * (self.gy + 1)
+
+    def asdict(self) -> dict:
+        return dataclasses.asdict(self)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    model: ModelSpec
+    sampler: SamplerSpec
+    trace_dtype: str          # "f64" or "f32"
+    chains: int = 1
+    sweeps: int = 100
+    seed: int = 0
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+# 5x5 stations on [0,1]^2, 1000-sample fp64 traces, Poisson mean 20 events,
+# 4x4 static regions (2x2 colour pattern), 2000 sweeps, seed 0.
+SMALL = Workload(
+    name="s5x5-n1000-static4x4-f64",
+    model=ModelSpec(nsx=5, nsy=5, N=1000, lam=20.0),
+    sampler=SamplerSpec(gx=4, gy=4, dynamic=0),
+    trace_dtype="f64", chains=1, sweeps=2000, seed=0)
+
+# 64x64 stations, 144000-sample fp32 traces (2.36 GB), Poisson mean 20000,
+# 64x64 regions whose offset is redrawn every sweep, 500 sweeps, one chain.
+LARGE = Workload(
+    name="s64x64-n144000-dyn64x64-f32",
+    model=ModelSpec(nsx=64, nsy=64, N=144000, lam=20000.0),
+    sampler=SamplerSpec(gx=64, gy=64, dynamic=1),
+    trace_dtype="f32", chains=1, sweeps=500, seed=1)
+
+# 32 independent chains of one 32x32-station instance, 36000-sample fp32
+# traces, Poisson mean 5000, dynamic 32x32 regions, all chains in one launch.
+CHAINS32 = Workload(
+    name="s32x32-n36000-dyn32x32-f32-c32",
+    model=ModelSpec(nsx=32, nsy=32, N=36000, lam=5000.0),
+    sampler=SamplerSpec(gx=32, gy=32, dynamic=1),
+    trace_dtype="f32", chains=32, sweeps=500, seed=2)
+
+WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32)}
+
+
+def scaled(w: Workload, *, side: int, N: int, lam: float, name: str | None = None,
+           **sampler_kw) -> Workload:
+    """Same physics on a smaller station grid (used by tests)."""
+    model = dataclasses.replace(w.model, nsx=side, nsy=side, N=N, lam=lam)
+    sampler = dataclasses.replace(w.sampler, gx=side, gy=side, **sampler_kw) \
+        if w.sampler.dynamic else dataclasses.replace(w.sampler, **sampler_kw)
+    return dataclasses.replace(w, name=name or f"{w.name}-scaled{side}", model=model,
+                               sampler=sampler)
+
+
+# ------------------------------------------------------------------ inputs
+
+def truth_events(model: ModelSpec, seed: int, n: int | None = None):
+    """Events from the prior: Poisson(lam) count, uniform location and onset,
+    magnitude mmin + Exp(mrate).  Returns a dict of float64 arrays and ids."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if n is None:
+        n = int(rng.poisson(model.lam))
+    x = np.minimum(rng.random(n) * model.Lx, np.nextafter(model.Lx, 0.0))
+    y = np.minimum(rng.random(n) * model.Ly, np.nextafter(model.Ly, 0.0))
+    t = np.minimum(rng.random(n) * model.N, np.nextafter(float(model.N), 0.0))
+    m = model.mmin + rng.standard_exponential(n) / model.mrate
+    return dict(x=x, y=y, t=t, m=m, id=np.arange(n, dtype=np.uint64))
+
+
+def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int) -> np.ndarray:
+    """Per-move random draws for replay runs, shape [nsweeps, regions, k, 8]:
+    [0..3] uniforms on [0,1), [4] Exp(1), [5],[6] standard normals, [7] log of
+    a uniform on (0,1].  Both the GPU path and the oracle consume the same
+    array, so their proposals coincide bit for bit."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (nsweeps, sampler.nreg, sampler.k)
+    out = np.empty(shape + (8,), dtype=np.float64)
+    out[..., 0:4] = rng.random(shape + (4,))
+    out[..., 4] = rng.standard_exponential(shape)
+    out[..., 5:7] = rng.standard_normal(shape + (2,))
+    out[..., 7] = np.log1p(-rng.random(shape))
+    return out
+
+
+def random_state(model: ModelSpec, seed: int, n: int):
+    """An arbitrary event set (for likelihood-difference tests)."""
+    return truth_events(model, seed, n=n)
