@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the chromatic MH region sweep on one MI355X.
+
+A step is one full sweep (the partition re-layout plus every colour phase)
+of the sampler over the synthetic instance of the 64x64-station,
+144000-sample fp32 workload with Poisson mean 20000 events and shifted 64x64
+regions.  The instance lives in HBM before timing starts (the trace is
+generated on the device by the library's forward simulator).
+
+Prints one JSON line: proposals/s (attempted MH moves per second) with a
+roofline block for the sweep kernel (algorithmic bytes per launch over its
+average HIP-event-timed duration) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MH proposals/s + event-location ESS/s per GPU, learned vs plain at equal F1"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--block", type=int, default=0, help="sweep workgroup size, 0 = autotune")
+    ap.add_argument("--profile-sweeps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, warmup: int, budget_s: float):
+    """The oracle as it stands, single-threaded, on the same workload: its own
+    synthetic trace of the same shape (seeded normals scaled by the model
+    variance), sweeps 0 .. warmup-1 untimed, then sweeps until budget_s."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1612_00595_amd import workloads as W
+
+    m = O.make_model(**w.model.asdict())
+    sp = O.make_sampler(**w.sampler.asdict())
+    tr = W.truth_events(w.model, w.seed)
+    truth = O.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
+    rng = np.random.Generator(np.random.PCG64(10_000 + w.seed))
+    z = rng.standard_normal((w.model.nsta, w.model.N), dtype=np.float32)
+    s = O.trace_from_noise_f32(m, truth, z)
+    del z
+    ch = O.Chain(m, sp, s, seed=w.seed)
+    for sw in range(warmup):
+        ch.sweep(sw)
+    R, k = w.sampler.nreg, w.sampler.k
+    logbuf = np.full((R, k, 4), -1.0)
+    moves, sweeps, t0 = 0, 0, time.perf_counter()
+    while True:
+        logbuf[...] = -1.0
+        ch.sweep(warmup + sweeps, log=logbuf)
+        moves += int(np.sum(logbuf[..., 1] >= 0))
+        sweeps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=moves / el, unit="proposals/s", cores=1, kind="oracle",
+                sample=f"{w.name}: oracle sweeps {warmup}..{warmup + sweeps - 1} "
+                       f"({sweeps} sweeps, {moves} proposals, {el:.1f} s) on its own "
+                       f"instance of the same shape, single thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sampler's "
+              "multi-GPU sharding is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1612_00595_amd import chromh, workloads as W
+
+    w = W.WORKLOADS[args.workload] if args.workload else W.LARGE
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    tr = W.truth_events(w.model, w.seed)
+    truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
+    log(f"[bench] simulating {w.name}: {w.model.nsta} stations x {w.model.N} samples, "
+        f"{len(truth)} true events")
+    trace = chromh.simulate(w.model, truth, 1000 + w.seed, w.trace_dtype, dev)
+    smp = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=w.chains, seed=w.seed,
+                                  block=args.block)
+    if args.block == 0:
+        smp.autotune(0, 3)
+    log(f"[bench] sweep workgroup size {smp.block}, {smp.ncolors} colours")
+
+    smp.run_sweeps(0, args.warmup)
+    torch.cuda.synchronize()
+    c0 = sum(smp.read_counters(c) for c in range(w.chains))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.run_sweeps(args.warmup, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = sum(smp.read_counters(c) for c in range(w.chains))
+    el = t1 - t0
+    proposals = int((c1 - c0)[:15].reshape(5, 3)[:, 0].sum())
+    value = proposals / el
+    log(f"[bench] {args.steps} sweeps in {el * 1e3:.1f} ms: {value:.4g} proposals/s")
+
+    # live per-launch timing of the sweep kernel (HIP events on this stream)
+    first = args.warmup + args.steps
+    P = args.profile_sweeps
+    c2 = sum(smp.read_counters(c) for c in range(w.chains))
+    ms = smp.time_phases(first, P, stream)
+    c3 = sum(smp.read_counters(c) for c in range(w.chains))
+    launches = P * smp.ncolors
+    avg_ms = float(ms[:smp.ncolors].sum()) / launches
+    tb = 4 if w.trace_dtype == "f32" else 8
+    samp_read = int(c3[15] - c2[15])
+    samp_written = int(c3[16] - c2[16])
+    bytes_per_launch = (samp_read * (tb + 8) + samp_written * 8) / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    log(f"[bench] sweep kernel: {avg_ms * 1e3:.1f} us/launch, "
+        f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s")
+
+    nev = len(smp.read_events(0))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "stations": w.model.nsta,
+            "samples": w.model.N,
+            "trace_dtype": w.trace_dtype,
+            "regions": f"{w.sampler.gx + 1}x{w.sampler.gy + 1}",
+            "dynamic_offsets": bool(w.sampler.dynamic),
+            "colours": smp.ncolors,
+            "moves_per_region": w.sampler.k,
+            "chains": w.chains,
+            "poisson_mean_events": w.model.lam,
+            "events_after_run": nev,
+            "block": smp.block,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_sweep_color",
+            "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    smp.close()
+    del trace
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(w, args.warmup, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * chromh.h -- C-ABI of the chromatic Metropolis-Hastings region sweep on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library infers the set of seismic events that explains a set of
+ * station traces (the inference problem of Section 3 of Song & Moore,
+ * "Parallel Chromatic MCMC with Spatial Partitioning"), by MH over the event
+ * set, run region by region in colour phases (Section 4, Algorithm 4) with
+ * the partition offset redrawn between sweeps (Section 4.3.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int32_t status: CMH_OK (0) or a negative
+ *     CMH_E* code; it never throws.  cmh_last_error() returns a message for
+ *     the last failure on the calling thread.
+ *   - Pointers named *_dev are device pointers (HIP device memory on the
+ *     current device), *_host are host pointers.  The caller owns every
+ *     buffer: traces, workspace, feed and log arrays must outlive the state.
+ *     The library never allocates device memory; it owns only the small host
+ *     handle freed by cmh_destroy.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Sweep calls only enqueue work.  Calls that return data to the host
+ *     synchronise that stream first.  Errors raised on the device (event
+ *     capacity, NaN) are latched in a device word and reported by the next
+ *     synchronising call; the state then answers CMH_ESTATE until destroyed.
+ *   - Arguments are validated before any device work.
+ *
+ * Model (Section 3, in the 2-D attenuating form Section 4.1 names as the
+ * natural case for a spatial partition):
+ *   stations on an nsx x nsy grid, cell-centred with spacing ds; domain
+ *   [0, nsx ds) x [0, nsy ds); events (x, y, t, m) with Poisson(lambda) count,
+ *   uniform location and onset t in [0, n_samples), m - mag_min ~
+ *   Exp(mag_rate); an event reaches a station at distance d < r_c with
+ *   arrival a = t + d / velocity and adds a zero-mean Gaussian signal of
+ *   standard deviation m exp(-d / atten) exp(-(n - a) / env_decay) on samples
+ *   n in [ceil(a), ceil(a) + t_s); the trace is Gaussian with variance
+ *   sigma^2 plus the variances of all arriving signals.
+ *
+ * Trace layout: [station][sample], station j = iy * nsx + ix, samples
+ * contiguous; dtype CMH_F32 or CMH_F64.
+ */
+#ifndef CHROMH_H
+#define CHROMH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CMH_OK      0
+#define CMH_EINVAL (-1)   /* invalid argument */
+#define CMH_EHIP   (-2)   /* a HIP runtime call failed */
+#define CMH_ECAP   (-3)   /* a region's event capacity was exceeded */
+#define CMH_ECOLOR (-4)   /* no colouring satisfies the independence check */
+#define CMH_ENAN   (-5)   /* NaN/Inf met in a likelihood evaluation */
+#define CMH_ESTATE (-6)   /* state poisoned by an earlier device error */
+
+#define CMH_F32 0
+#define CMH_F64 1
+
+#define CMH_BIRTH 0
+#define CMH_DEATH 1
+#define CMH_LOC   2
+#define CMH_TIME  3
+#define CMH_MAG   4
+
+typedef struct {
+    int32_t nsx, nsy;     /* station grid */
+    double  ds;           /* station spacing */
+    int64_t n_samples;    /* samples per trace */
+    double  sigma;        /* noise standard deviation */
+    double  atten;        /* amplitude attenuation length */
+    double  velocity;     /* domain units per sample */
+    double  env_decay;    /* amplitude envelope decay, samples */
+    int32_t t_s;          /* signal duration, samples (1..128) */
+    int32_t _pad0;
+    double  r_c;          /* detection cutoff, 0 < r_c < ds */
+    double  lambda;       /* Poisson mean number of events */
+    double  mag_min;      /* magnitude lower bound */
+    double  mag_rate;     /* rate of the exponential magnitude prior */
+} cmh_model;
+
+typedef struct {
+    int32_t grid_x, grid_y;     /* regions per axis of the unshifted grid */
+    int32_t dynamic;            /* 1: offset redrawn every sweep */
+    int32_t period;             /* colour period p, 0 = derive */
+    int32_t moves_per_region;   /* k, MH moves per region per colour phase */
+    int32_t region_capacity;    /* events per region, 1..64 */
+    double  p_birth, p_death, p_loc, p_time, p_mag;   /* sum to 1 */
+    double  step_xy, step_t, step_m;                  /* random-walk steps */
+    int32_t prior_only;         /* 1: likelihood switched off */
+    int32_t block;              /* threads per workgroup: 64, 128, 256; 0 = tune */
+} cmh_sampler;
+
+typedef struct {
+    double   x, y, t, m;
+    uint64_t id;       /* (sweep << 32) | (region << 12) | move, or caller's */
+    int32_t  region;   /* linear region index k * (grid_x + 1) + i */
+    int32_t  _pad;
+} cmh_event;
+
+typedef struct cmh_state cmh_state;
+
+const char *cmh_last_error(void);
+
+/* Partition and colouring (Sections 4.1 and 4.3).  Region i along x covers
+ * [off_x + (i - 1) w, off_x + i w) clipped to the domain, w = domain / grid,
+ * i in 0..grid_x; the offset is in [0, w).  Colour of region (i, k) is
+ * (i mod p) + p (k mod p).  Static partitions use the smallest p whose
+ * colouring passes the exact check (no station within r_c of two regions of
+ * one colour); dynamic ones use p = ceil(2 r_c / w) + 1, which holds for
+ * every offset.  color_of_region: caller array of (grid_x+1)*(grid_y+1)
+ * int32, may be NULL.  Pure host function.  CMH_ECOLOR if no p works. */
+int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t grid_y,
+                                double off_x, double off_y, int32_t dynamic,
+                                int32_t *n_reg_x, int32_t *n_reg_y, int32_t *period,
+                                int32_t *n_colors, int32_t *color_of_region);
+
+/* Workspace bytes for n_chains chains: the per-chain event-variance
+ * accumulator (n_stations x n_samples doubles), two event tables of
+ * region_capacity slots per region, offsets, statistics and flags. */
+int32_t cmh_state_bytes(const cmh_model *model, const cmh_sampler *sampler,
+                        int32_t n_chains, size_t *bytes);
+
+/* Initialise n_chains chains on one trace (Algorithm 4's input: an empty
+ * world, zero event variance).  trace_dev: [station][sample] of trace_dtype,
+ * shared by all chains, read only.  Chain c draws from Philox4x32-10 under
+ * key (seed, c).  Enqueues the workspace set-up on hip_stream. */
+int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler,
+                       const void *trace_dev, int32_t trace_dtype, int32_t n_chains,
+                       uint32_t seed, void *workspace_dev, size_t workspace_bytes,
+                       void *hip_stream, cmh_state **out);
+
+/* One colour phase of sweep `sweep` on every chain (Algorithm 4's inner
+ * parallel loop): every region of colour `color` runs k MH moves at once,
+ * one workgroup per region.  color == 0 first lays out the sweep's partition
+ * (a fresh offset when dynamic) and moves every event into the list of its
+ * region.  Phases must be called in colour order. */
+int32_t cmh_sweep_color(cmh_state *st, int64_t sweep, int32_t color, void *hip_stream);
+
+/* Sweeps first_sweep .. first_sweep + n_sweeps - 1, every colour in order
+ * (Algorithm 4's outer loop with Section 4.3.2's offset draw).  Replayed
+ * from captured HIP graphs when no feed or log is attached. */
+int32_t cmh_run_sweeps(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream);
+
+/* Current events of one chain, in region order and by id within a region.
+ * Synchronises.  If more than cap events exist, *n_out is set and
+ * CMH_EINVAL returned. */
+int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64_t cap,
+                        int64_t *n_out);
+
+/* Replace one chain's events (host array, ids kept) and recompute its event
+ * variance exactly.  Synchronises. */
+int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host, int64_t n);
+
+/* Replay mode.  feed_dev: doubles [n_sweeps][regions][k][8] holding, per
+ * move, the draws the sampler would otherwise take from Philox: [0] uniform
+ * for the move type, [1] uniform a (index or birth x), [2] uniform b (birth
+ * y), [3] uniform c (birth onset), [4] Exp(1) (birth magnitude), [5], [6]
+ * standard normals, [7] log of the acceptance uniform.  Chain 0 only.
+ * NULL detaches. */
+int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
+                     int64_t n_sweeps);
+
+/* Move log.  log_dev: doubles [n_sweeps][regions][k][4] = move type,
+ * status (0 rejected before the likelihood, 1 rejected, 2 accepted),
+ * log-likelihood change, log acceptance ratio.  Chain 0 only.  NULL
+ * detaches. */
+int32_t cmh_set_log(cmh_state *st, double *log_dev, int64_t first_sweep, int64_t n_sweeps);
+
+/* Exact recomputation of every chain's event variance from its events and,
+ * when out_host is not NULL, each chain's signal log-likelihood
+ * log P(s | e) (Section 3) into out_host[n_chains].  write_variance = 0 only
+ * evaluates the log-likelihood.  Synchronises when out_host is given. */
+int32_t cmh_refresh(cmh_state *st, int32_t write_variance, double *out_host, void *hip_stream);
+
+/* Copy one chain's event variance for stations [station0, station0 + nsta)
+ * into out_host (nsta x n_samples doubles).  Synchronises. */
+int32_t cmh_read_variance(cmh_state *st, int32_t chain, int64_t station0, int64_t nsta,
+                          double *out_host);
+
+/* Per-chain move statistics since init, out_host[17]: [3 t + 0], [3 t + 1],
+ * [3 t + 2] = attempted, evaluated (valid proposals) and accepted moves of
+ * type t (CMH_BIRTH .. CMH_MAG); [15] footprint samples evaluated; [16]
+ * footprint samples rewritten on acceptance.  Synchronises. */
+int32_t cmh_read_stats(cmh_state *st, int32_t chain, uint64_t *out_host);
+
+/* Threads per workgroup of the sweep kernel in use (after tuning). */
+int32_t cmh_get_block(cmh_state *st, int32_t *block);
+
+/* Times each sweep-kernel workgroup size on n_trial sweeps starting at
+ * first_sweep, keeps the fastest, then restores the chains' events and
+ * recomputes their event variance.  Results are cached per problem shape.
+ * Synchronises. */
+int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream);
+
+/* Runs sweeps first_sweep .. first_sweep + n_sweeps - 1 like cmh_run_sweeps
+ * but launched one kernel at a time, with HIP events recorded on hip_stream
+ * around each; ms_out[c] receives the summed milliseconds of colour c's
+ * phases and ms_out[n_colors] those of the sweeps' re-layouts.  Synchronises.
+ * Used for measurement. */
+int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream,
+                        float *ms_out);
+
+int32_t cmh_destroy(cmh_state *st);
+
+/* Forward simulator (synthetic worlds sampled from the model, Section 5):
+ * trace[j][n] = sqrt(sigma^2 + E_j[n]) z_jn with E from the given events and
+ * z standard normal from Philox4x32-10 under key (seed, 0x80000001),
+ * counter (n / 2, j, 0, 0), Box-Muller (even n cosine, odd n sine).
+ * truth_host: n_events events (host).  workspace_dev must hold
+ * cmh_simulate_bytes() bytes.  Enqueues on hip_stream and synchronises
+ * before returning (the staged events live in the workspace). */
+int32_t cmh_simulate_bytes(const cmh_model *model, const cmh_event *truth_host,
+                           int64_t n_events, size_t *bytes);
+int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_t n_events,
+                     uint32_t seed, void *trace_dev, int32_t trace_dtype,
+                     void *workspace_dev, size_t workspace_bytes, void *hip_stream);
+
+/* Draw records [count][8] that chain `chain` takes for moves j0 .. j0+count-1
+ * of region `region` in sweep `sweep` (the same layout as the feed), computed
+ * on the device into out_dev.  Enqueues on hip_stream. */
+int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                       uint32_t j0, int32_t count, double *out_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

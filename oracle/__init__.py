@@ -87,6 +87,7 @@ def lib():
         L.orc_arrival_time.argtypes = [C.c_double] * 6 + [P]
         L.orc_arrival_time.restype = C.c_double
         L.orc_event_variance.argtypes = [P, P, C.c_int64, P]
+        L.orc_event_variance_rows.argtypes = [P, P, C.c_int64, C.c_int64, C.c_int64, P]
         L.orc_loglik.argtypes = [P, P, P, C.c_int64]
         L.orc_loglik.restype = C.c_double
         L.orc_logprior.argtypes = [P, P, C.c_int64]
@@ -94,8 +95,12 @@ def lib():
         L.orc_single_term.argtypes = [C.c_double] * 3
         L.orc_single_term.restype = C.c_double
         L.orc_simulate.argtypes = [P, P, C.c_int64, C.c_uint32, P]
+        L.orc_simulate_rows.argtypes = [P, P, C.c_int64, C.c_uint32, C.c_int64, C.c_int64, P]
+        L.orc_trace_from_noise_f32.argtypes = [P, P, C.c_int64, P, P]
         L.orc_chain_new.argtypes = [P, P, P, C.c_uint32, C.c_uint32]
         L.orc_chain_new.restype = P
+        L.orc_chain_new_f32.argtypes = [P, P, P, C.c_uint32, C.c_uint32]
+        L.orc_chain_new_f32.restype = P
         L.orc_chain_free.argtypes = [P]
         L.orc_chain_begin_sweep.argtypes = [P, C.c_int64]
         L.orc_chain_begin_sweep.restype = C.c_int32
@@ -211,6 +216,13 @@ def event_variance(model: Model, ev: np.ndarray) -> np.ndarray:
     return E
 
 
+def event_variance_rows(model: Model, ev: np.ndarray, j0: int, nrows: int) -> np.ndarray:
+    ev = np.ascontiguousarray(ev, dtype=EVENT_DTYPE)
+    E = np.zeros((nrows, model.N))
+    lib().orc_event_variance_rows(C.byref(model), _ptr(ev), len(ev), j0, nrows, _ptr(E))
+    return E
+
+
 def loglik(model: Model, s: np.ndarray, ev: np.ndarray) -> float:
     s = np.ascontiguousarray(s, dtype=np.float64)
     ev = np.ascontiguousarray(ev, dtype=EVENT_DTYPE)
@@ -233,13 +245,36 @@ def simulate(model: Model, truth: np.ndarray, seed: int) -> np.ndarray:
     return s
 
 
+def simulate_rows(model: Model, truth: np.ndarray, seed: int, j0: int, nrows: int) -> np.ndarray:
+    truth = np.ascontiguousarray(truth, dtype=EVENT_DTYPE)
+    s = np.zeros((nrows, model.N))
+    lib().orc_simulate_rows(C.byref(model), _ptr(truth), len(truth), seed, j0, nrows, _ptr(s))
+    return s
+
+
+def trace_from_noise_f32(model: Model, truth: np.ndarray, z: np.ndarray) -> np.ndarray:
+    truth = np.ascontiguousarray(truth, dtype=EVENT_DTYPE)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    assert z.size == model.nsx * model.nsy * model.N
+    out = np.empty_like(z)
+    lib().orc_trace_from_noise_f32(C.byref(model), _ptr(truth), len(truth), _ptr(z), _ptr(out))
+    return out
+
+
 class Chain:
-    """One oracle chain.  The trace array is kept alive by the object."""
+    """One oracle chain.  The trace array is kept alive by the object; a
+    float32 trace is read as is (each sample widened to binary64)."""
 
     def __init__(self, model: Model, sampler: Sampler, s: np.ndarray, seed: int, chain: int = 0):
         self.model, self.sampler = model, sampler
-        self.s = np.ascontiguousarray(s, dtype=np.float64)
-        self._h = lib().orc_chain_new(C.byref(model), C.byref(sampler), _ptr(self.s), seed, chain)
+        if s.dtype == np.float32:
+            self.s = np.ascontiguousarray(s)
+            self._h = lib().orc_chain_new_f32(C.byref(model), C.byref(sampler), _ptr(self.s),
+                                              seed, chain)
+        else:
+            self.s = np.ascontiguousarray(s, dtype=np.float64)
+            self._h = lib().orc_chain_new(C.byref(model), C.byref(sampler), _ptr(self.s), seed,
+                                          chain)
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -116,6 +116,8 @@ void   orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t i
                    orc_arrival_t *out);
 double orc_arrival_variance(const orc_model *m, const orc_arrival_t *ar, int64_t n);
 void   orc_event_variance(const orc_model *m, const orc_event *ev, int64_t nev, double *E);
+void   orc_event_variance_rows(const orc_model *m, const orc_event *ev, int64_t nev, int64_t j0,
+                               int64_t nrows, double *E);
 double orc_loglik(const orc_model *m, const double *s, const orc_event *ev, int64_t nev);
 double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev);
 double orc_single_term(double sigma, double s, double e);
@@ -123,11 +125,17 @@ double orc_single_term(double sigma, double s, double e);
 /* ---- forward simulator ------------------------------------------------ */
 void   orc_simulate(const orc_model *m, const orc_event *truth, int64_t nev,
                     uint32_t seed, double *s_out);
+void   orc_simulate_rows(const orc_model *m, const orc_event *truth, int64_t nev, uint32_t seed,
+                         int64_t j0, int64_t nrows, double *s_out);
+void   orc_trace_from_noise_f32(const orc_model *m, const orc_event *truth, int64_t nev,
+                                const float *z, float *s_out);
 
 /* ---- the sampler (serial, chromatic static/dynamic, naive) ----------- */
 typedef struct orc_chain orc_chain;
 orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double *s,
                          uint32_t seed, uint32_t chain);
+orc_chain *orc_chain_new_f32(const orc_model *m, const orc_sampler *sp, const float *s,
+                             uint32_t seed, uint32_t chain);
 void    orc_chain_free(orc_chain *c);
 int32_t orc_chain_begin_sweep(orc_chain *c, int64_t sweep);
 int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color,

@@ -311,6 +311,19 @@ void orc_event_variance(const orc_model *m, const orc_event *ev, int64_t nev, do
     free(idx);
 }
 
+/* The same for stations [j0, j0 + nrows) only. */
+void orc_event_variance_rows(const orc_model *m, const orc_event *ev, int64_t nev, int64_t j0,
+                             int64_t nrows, double *E)
+{
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
+    for (int64_t j = j0; j < j0 + nrows; ++j) {
+        int32_t ix = (int32_t)(j % m->nsx), iy = (int32_t)(j / m->nsx);
+        int64_t k = events_at_station(m, ev, nev, ix, iy, idx);
+        station_row(m, ev, idx, k, ix, iy, E + (j - j0) * m->N);
+    }
+    free(idx);
+}
+
 /* Log density of one sample: zero-mean Gaussian with variance sigma^2 + e. */
 double orc_single_term(double sigma, double s, double e)
 {
@@ -359,25 +372,51 @@ double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev)
 void orc_simulate(const orc_model *m, const orc_event *truth, int64_t nev,
                   uint32_t seed, double *s_out)
 {
+    orc_simulate_rows(m, truth, nev, seed, 0, (int64_t)m->nsx * m->nsy, s_out);
+}
+
+/* The same simulator restricted to stations [j0, j0 + nrows). */
+void orc_simulate_rows(const orc_model *m, const orc_event *truth, int64_t nev, uint32_t seed,
+                       int64_t j0, int64_t nrows, double *s_out)
+{
     uint32_t key[2] = {seed, 0x80000001u};
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
+    double *row = (double *)malloc(sizeof(double) * (size_t)m->N);
+    for (int64_t j = j0; j < j0 + nrows; ++j) {
+        int32_t ix = (int32_t)(j % m->nsx), iy = (int32_t)(j / m->nsx);
+        double *out = s_out + (j - j0) * m->N;
+        int64_t k = events_at_station(m, truth, nev, ix, iy, idx);
+        station_row(m, truth, idx, k, ix, iy, row);
+        for (int64_t n = 0; n < m->N; ++n) {
+            uint32_t ctr[4] = {(uint32_t)(n >> 1), (uint32_t)j, 0u, 0u};
+            uint32_t w[4];
+            orc_philox4x32_10(ctr, key, w);
+            double u1 = orc_u01(w[0], w[1]);
+            double u2 = orc_u01(w[2], w[3]);
+            double r = sqrt(-2.0 * log(u1));
+            double z = (n & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
+            out[n] = sqrt(m->sigma * m->sigma + row[n]) * z;
+        }
+    }
+    free(row);
+    free(idx);
+}
+
+/* The simulator with the standard normals supplied by the caller:
+ * s = sqrt(sigma^2 + E) z, rounded to binary32. */
+void orc_trace_from_noise_f32(const orc_model *m, const orc_event *truth, int64_t nev,
+                              const float *z, float *s_out)
+{
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nev > 0 ? nev : 1));
     double *row = (double *)malloc(sizeof(double) * (size_t)m->N);
     for (int32_t iy = 0; iy < m->nsy; ++iy) {
         for (int32_t ix = 0; ix < m->nsx; ++ix) {
             int64_t j = (int64_t)iy * m->nsx + ix;
-            double *out = s_out + j * m->N;
             int64_t k = events_at_station(m, truth, nev, ix, iy, idx);
             station_row(m, truth, idx, k, ix, iy, row);
-            for (int64_t n = 0; n < m->N; ++n) {
-                uint32_t ctr[4] = {(uint32_t)(n >> 1), (uint32_t)j, 0u, 0u};
-                uint32_t w[4];
-                orc_philox4x32_10(ctr, key, w);
-                double u1 = orc_u01(w[0], w[1]);
-                double u2 = orc_u01(w[2], w[3]);
-                double r = sqrt(-2.0 * log(u1));
-                double z = (n & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
-                out[n] = sqrt(m->sigma * m->sigma + row[n]) * z;
-            }
+            for (int64_t n = 0; n < m->N; ++n)
+                s_out[j * m->N + n] =
+                    (float)(sqrt(m->sigma * m->sigma + row[n]) * (double)z[j * m->N + n]);
         }
     }
     free(row);

@@ -52,7 +52,8 @@ static int cmp_id(const void *a, const void *b)
 struct orc_chain {
     orc_model m;
     orc_sampler sp;
-    const double *s;
+    const double *s;      /* trace, binary64 ... */
+    const float *s32;     /* ... or binary32 */
     uint32_t seed, chain;
     double Lx, Ly, wx, wy;
     int32_t nrx, nry, period, ncolors;
@@ -125,6 +126,19 @@ static int64_t lat_region_sites(const orc_chain *c, int32_t r, int64_t want, int
         }
     }
     return cnt;
+}
+
+static double trace_at(const orc_chain *c, int64_t j, int64_t n)
+{
+    return c->s ? c->s[j * c->m.N + n] : (double)c->s32[j * c->m.N + n];
+}
+
+orc_chain *orc_chain_new_f32(const orc_model *m, const orc_sampler *sp, const float *s,
+                             uint32_t seed, uint32_t chain)
+{
+    orc_chain *c = orc_chain_new(m, sp, NULL, seed, chain);
+    c->s32 = s;
+    return c;
 }
 
 orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double *s,
@@ -340,13 +354,13 @@ static double move_delta(orc_chain *c, int32_t r, int32_t type, int64_t idx,
                 orc_arrival(m, &own->e[q], ix, iy, &others[no]);
                 if (others[no].in) ++no;
             }
-            const double *srow = c->s + j * m->N;
             for (int64_t n = lo; n < hi; ++n) {
+                double sv = trace_at(c, j, n);
                 double base = m->sigma * m->sigma;
                 for (int64_t q = 0; q < no; ++q) base += orc_arrival_variance(m, &others[q], n);
                 double v_old = base + (old ? orc_arrival_variance(m, &ao, n) : 0.0);
                 double v_new = base + (neu ? orc_arrival_variance(m, &an, n) : 0.0);
-                delta += gauss_logpdf(srow[n], v_new) - gauss_logpdf(srow[n], v_old);
+                delta += gauss_logpdf(sv, v_new) - gauss_logpdf(sv, v_old);
             }
         }
     }

@@ -1,0 +1,306 @@
+"""Python binding of libchromh.so (include/chromh.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP
+library.  PyTorch provides device memory (traces, workspaces, feed and log
+arrays) and the stream.  If the library is missing the import of a function
+here raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .workloads import ModelSpec, SamplerSpec
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchromh.so")
+
+CMH_F32, CMH_F64 = 0, 1
+ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ECAP", -4: "ECOLOR", -5: "ENAN", -6: "ESTATE"}
+
+EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("t", "<f8"), ("m", "<f8"),
+                        ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4")])
+
+
+class CmhModel(C.Structure):
+    _fields_ = [("nsx", C.c_int32), ("nsy", C.c_int32), ("ds", C.c_double),
+                ("n_samples", C.c_int64), ("sigma", C.c_double), ("atten", C.c_double),
+                ("velocity", C.c_double), ("env_decay", C.c_double), ("t_s", C.c_int32),
+                ("_pad0", C.c_int32), ("r_c", C.c_double), ("lam", C.c_double),
+                ("mag_min", C.c_double), ("mag_rate", C.c_double)]
+
+
+class CmhSampler(C.Structure):
+    _fields_ = [("grid_x", C.c_int32), ("grid_y", C.c_int32), ("dynamic", C.c_int32),
+                ("period", C.c_int32), ("moves_per_region", C.c_int32),
+                ("region_capacity", C.c_int32), ("p_birth", C.c_double),
+                ("p_death", C.c_double), ("p_loc", C.c_double), ("p_time", C.c_double),
+                ("p_mag", C.c_double), ("step_xy", C.c_double), ("step_t", C.c_double),
+                ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32)]
+
+
+class CmhError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_init_state",
+           "cmh_sweep_color", "cmh_run_sweeps", "cmh_read_events", "cmh_write_events",
+           "cmh_set_feed", "cmh_set_log", "cmh_refresh", "cmh_read_variance", "cmh_read_stats",
+           "cmh_get_block", "cmh_autotune", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
+           "cmh_move_draws"]
+
+_lib = None
+
+
+def lib():
+    """Loads libchromh.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1612_00595_amd.build` (HIP, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U32, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+    sig = {
+        "cmh_last_error": ([], C.c_char_p),
+        "cmh_partition_and_color": ([P, I32, I32, D, D, I32, P, P, P, P, P], I32),
+        "cmh_state_bytes": ([P, P, I32, P], I32),
+        "cmh_init_state": ([P, P, P, I32, I32, U32, P, C.c_size_t, P, P], I32),
+        "cmh_sweep_color": ([P, I64, I32, P], I32),
+        "cmh_run_sweeps": ([P, I64, I64, P], I32),
+        "cmh_read_events": ([P, I32, P, I64, P], I32),
+        "cmh_write_events": ([P, I32, P, I64], I32),
+        "cmh_set_feed": ([P, P, I64, I64], I32),
+        "cmh_set_log": ([P, P, I64, I64], I32),
+        "cmh_refresh": ([P, I32, P, P], I32),
+        "cmh_read_variance": ([P, I32, I64, I64, P], I32),
+        "cmh_read_stats": ([P, I32, P], I32),
+        "cmh_get_block": ([P, P], I32),
+        "cmh_autotune": ([P, I64, I32, P], I32),
+        "cmh_time_phases": ([P, I64, I64, P, P], I32),
+        "cmh_destroy": ([P], I32),
+        "cmh_simulate_bytes": ([P, P, I64, P], I32),
+        "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
+        "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, P, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != 0:
+        raise CmhError(rc, lib().cmh_last_error().decode())
+
+
+def model_struct(spec: ModelSpec) -> CmhModel:
+    m = CmhModel()
+    m.nsx, m.nsy, m.ds, m.n_samples = spec.nsx, spec.nsy, spec.ds, spec.N
+    m.sigma, m.atten, m.velocity, m.env_decay = spec.sigma, spec.atten, spec.vel, spec.decay
+    m.t_s, m.r_c, m.lam = spec.ts, spec.rc, spec.lam
+    m.mag_min, m.mag_rate = spec.mmin, spec.mrate
+    return m
+
+
+def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
+    s = CmhSampler()
+    s.grid_x, s.grid_y, s.dynamic, s.period = spec.gx, spec.gy, spec.dynamic, spec.period
+    s.moves_per_region, s.region_capacity = spec.k, spec.cap
+    s.p_birth, s.p_death, s.p_loc, s.p_time, s.p_mag = spec.pb, spec.pd, spec.ploc, spec.pt, spec.pm
+    s.step_xy, s.step_t, s.step_m = spec.sxy, spec.st, spec.sm
+    s.prior_only, s.block = spec.prior_only, block
+    return s
+
+
+def _ptr(a) -> C.c_void_p:
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream=None) -> C.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def as_events(x, y, t, m, ids=None) -> np.ndarray:
+    ev = np.zeros(len(x), dtype=EVENT_DTYPE)
+    ev["x"], ev["y"], ev["t"], ev["m"] = x, y, t, m
+    ev["id"] = np.arange(len(x), dtype=np.uint64) if ids is None else ids
+    return ev
+
+
+def partition_and_color(model: ModelSpec, gx: int, gy: int, offx: float, offy: float,
+                        dynamic: int):
+    nrx, nry, p, nc = (C.c_int32() for _ in range(4))
+    colors = np.zeros((gx + 1) * (gy + 1), dtype=np.int32)
+    m = model_struct(model)
+    check(lib().cmh_partition_and_color(C.byref(m), gx, gy, offx, offy, dynamic, C.byref(nrx),
+                                        C.byref(nry), C.byref(p), C.byref(nc), _ptr(colors)))
+    return nrx.value, nry.value, p.value, nc.value, colors
+
+
+def simulate(model: ModelSpec, truth: np.ndarray, seed: int, dtype: str = "f32",
+             device="cuda", stream=None):
+    """Trace [stations, N] on the device, sampled from the model given truth."""
+    import torch
+    truth = np.ascontiguousarray(truth, dtype=EVENT_DTYPE)
+    m = model_struct(model)
+    nbytes = C.c_size_t()
+    check(lib().cmh_simulate_bytes(C.byref(m), _ptr(truth), len(truth), C.byref(nbytes)))
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    trace = torch.empty((model.nsta, model.N), dtype=tdt, device=device)
+    check(lib().cmh_simulate(C.byref(m), _ptr(truth), len(truth), seed, _ptr(trace),
+                             CMH_F32 if dtype == "f32" else CMH_F64, _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    del ws
+    return trace
+
+
+def move_draws(seed: int, chain: int, sweep: int, region: int, j0: int, count: int,
+               device="cuda") -> np.ndarray:
+    import torch
+    out = torch.empty((count, 8), dtype=torch.float64, device=device)
+    check(lib().cmh_move_draws(seed, chain, sweep, region, j0, count, _ptr(out), _stream()))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+class ChromaticSampler:
+    """Chains of the chromatic MH sampler sharing one device trace."""
+
+    def __init__(self, model: ModelSpec, sampler: SamplerSpec, trace, chains: int = 1,
+                 seed: int = 0, block: int = 0, stream=None):
+        import torch
+        if not (trace.is_cuda and trace.dim() == 2 and trace.is_contiguous()):
+            raise ValueError("trace must be a contiguous 2-D device tensor [stations, samples]")
+        if trace.dtype not in (torch.float32, torch.float64):
+            raise ValueError("trace must be float32 or float64")
+        self.model, self.sampler, self.chains = model, sampler, chains
+        self.trace = trace
+        self._m = model_struct(model)
+        self._s = sampler_struct(sampler, block)
+        nbytes = C.c_size_t()
+        check(lib().cmh_state_bytes(C.byref(self._m), C.byref(self._s), chains, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=trace.device)
+        h = C.c_void_p()
+        check(lib().cmh_init_state(C.byref(self._m), C.byref(self._s), _ptr(trace),
+                                   CMH_F64 if trace.dtype == torch.float64 else CMH_F32, chains,
+                                   seed, _ptr(self.workspace), self.workspace.numel(),
+                                   _stream(stream), C.byref(h)))
+        self._h = h
+        _, _, self.period, self.ncolors, _ = partition_and_color(
+            model, sampler.gx, sampler.gy, 0.0, 0.0, sampler.dynamic) \
+            if sampler.period == 0 else (0, 0, sampler.period, sampler.period ** 2, None)
+        self._feed = None
+        self._log = None
+
+    # -- sweeps --------------------------------------------------------
+    def sweep_color(self, sweep: int, color: int, stream=None):
+        check(lib().cmh_sweep_color(self._h, sweep, color, _stream(stream)))
+
+    def run_sweeps(self, first: int, n: int, stream=None):
+        check(lib().cmh_run_sweeps(self._h, first, n, _stream(stream)))
+
+    def autotune(self, first: int, n_trial: int = 3, stream=None) -> int:
+        check(lib().cmh_autotune(self._h, first, n_trial, _stream(stream)))
+        return self.block
+
+    @property
+    def block(self) -> int:
+        b = C.c_int32()
+        check(lib().cmh_get_block(self._h, C.byref(b)))
+        return b.value
+
+    # -- replay --------------------------------------------------------
+    def _check_buffer(self, t, last: int, name: str):
+        import torch
+        want = (self.sampler.nreg, self.sampler.k, last)
+        if (t.dim() != 4 or tuple(t.shape[1:]) != want or t.dtype != torch.float64
+                or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 device tensor "
+                             f"[n_sweeps, {want[0]}, {want[1]}, {want[2]}]")
+
+    def set_feed(self, feed, first: int):
+        """feed: float64 device tensor [n_sweeps, regions, k, 8] (or None)."""
+        if feed is not None:
+            self._check_buffer(feed, 8, "feed")
+        self._feed = feed
+        if feed is None:
+            check(lib().cmh_set_feed(self._h, None, 0, 0))
+        else:
+            check(lib().cmh_set_feed(self._h, _ptr(feed), first, feed.shape[0]))
+
+    def set_log(self, log, first: int):
+        """log: float64 device tensor [n_sweeps, regions, k, 4] (or None)."""
+        if log is not None:
+            self._check_buffer(log, 4, "log")
+        self._log = log
+        if log is None:
+            check(lib().cmh_set_log(self._h, None, 0, 0))
+        else:
+            check(lib().cmh_set_log(self._h, _ptr(log), first, log.shape[0]))
+
+    # -- state ---------------------------------------------------------
+    def read_events(self, chain: int = 0) -> np.ndarray:
+        n = C.c_int64()
+        rc = lib().cmh_read_events(self._h, chain, None, 0, C.byref(n))
+        if rc not in (0, -1):
+            check(rc)
+        out = np.zeros(n.value, dtype=EVENT_DTYPE)
+        check(lib().cmh_read_events(self._h, chain, _ptr(out), len(out), C.byref(n)))
+        return out
+
+    def write_events(self, chain: int, ev: np.ndarray):
+        ev = np.ascontiguousarray(ev, dtype=EVENT_DTYPE)
+        check(lib().cmh_write_events(self._h, chain, _ptr(ev), len(ev)))
+
+    def refresh(self, write_variance: bool = True, loglik: bool = True, stream=None):
+        out = np.zeros(self.chains) if loglik else None
+        check(lib().cmh_refresh(self._h, 1 if write_variance else 0,
+                                None if out is None else _ptr(out), _stream(stream)))
+        return out
+
+    def read_variance(self, chain: int = 0, station0: int = 0, nsta: int | None = None):
+        nsta = self.model.nsta - station0 if nsta is None else nsta
+        out = np.zeros((nsta, self.model.N))
+        check(lib().cmh_read_variance(self._h, chain, station0, nsta, _ptr(out)))
+        return out
+
+    def read_stats(self, chain: int = 0) -> np.ndarray:
+        """[5, 3] attempted / evaluated / accepted moves per move type."""
+        return self.read_counters(chain)[:15].reshape(5, 3)
+
+    def read_counters(self, chain: int = 0) -> np.ndarray:
+        """All 17 counters: the move table, then footprint samples evaluated
+        and footprint samples rewritten."""
+        out = np.zeros(17, dtype=np.uint64)
+        check(lib().cmh_read_stats(self._h, chain, _ptr(out)))
+        return out
+
+    def time_phases(self, first: int, n: int, stream=None) -> np.ndarray:
+        """Milliseconds per colour phase (summed over n sweeps), then re-layout."""
+        out = np.zeros(self.ncolors + 1, dtype=np.float32)
+        check(lib().cmh_time_phases(self._h, first, n, _stream(stream), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cmh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

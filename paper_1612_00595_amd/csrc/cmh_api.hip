@@ -1,0 +1,927 @@
+// cmh_api.hip -- the C-ABI of the chromatic MH library (include/chromh.h):
+// argument validation, partition and colouring, workspace layout inside the
+// caller's device buffer, eager and graph-replayed sweeps, host transfers,
+// the workgroup-size autotuner and the forward simulator's staging.
+#include "chromh.h"
+#include "cmh_common.hpp"
+#include "cmh_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using cmh::Events;
+using cmh::Geo;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(CMH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------- validation
+int32_t check_model(const cmh_model *m)
+{
+    if (!m) return fail(CMH_EINVAL, "model is NULL");
+    if (m->nsx < 1 || m->nsy < 1) return fail(CMH_EINVAL, "station grid must be at least 1x1");
+    if ((long long)m->nsx * m->nsy > (1LL << 22)) return fail(CMH_EINVAL, "too many stations");
+    if (!(m->ds > 0.0)) return fail(CMH_EINVAL, "ds must be positive");
+    if (m->n_samples < 1) return fail(CMH_EINVAL, "n_samples must be positive");
+    if ((long long)m->nsx * m->nsy * m->n_samples >= (1LL << 31))
+        return fail(CMH_EINVAL, "stations x samples must stay below 2^31");
+    if (!(m->sigma > 0.0)) return fail(CMH_EINVAL, "sigma must be positive");
+    if (!(m->atten > 0.0)) return fail(CMH_EINVAL, "atten must be positive");
+    if (!(m->velocity > 0.0)) return fail(CMH_EINVAL, "velocity must be positive");
+    if (!(m->env_decay > 0.0)) return fail(CMH_EINVAL, "env_decay must be positive");
+    if (m->t_s < 1 || m->t_s > cmh::kMaxTs) return fail(CMH_EINVAL, "t_s must be in 1..128");
+    if (!(m->r_c > 0.0) || !(m->r_c < m->ds))
+        return fail(CMH_EINVAL, "r_c must satisfy 0 < r_c < ds");
+    if (!(m->lambda > 0.0)) return fail(CMH_EINVAL, "lambda must be positive");
+    if (!(m->mag_rate > 0.0)) return fail(CMH_EINVAL, "mag_rate must be positive");
+    if (!std::isfinite(m->mag_min)) return fail(CMH_EINVAL, "mag_min must be finite");
+    return CMH_OK;
+}
+
+int32_t check_grid(int32_t gx, int32_t gy)
+{
+    if (gx < 1 || gy < 1) return fail(CMH_EINVAL, "grid must be at least 1x1");
+    if ((long long)(gx + 1) * (gy + 1) >= (1LL << 20))
+        return fail(CMH_EINVAL, "at most 2^20 regions");
+    return CMH_OK;
+}
+
+// Rectangle distance from a station to the closure of a region.
+double rect_distance(double px, double py, double x0, double x1, double y0, double y1)
+{
+    const double dx = px < x0 ? x0 - px : (px > x1 ? px - x1 : 0.0);
+    const double dy = py < y0 ? y0 - py : (py > y1 ? py - y1 : 0.0);
+    return std::sqrt(dx * dx + dy * dy);
+}
+
+// Number of (station, same-coloured region pair) conflicts for period p.
+long long colour_conflicts(const cmh_model *m, int gx, int gy, double offx, double offy, int p)
+{
+    const double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    const double wx = Lx / (double)gx, wy = Ly / (double)gy;
+    std::vector<double> xlo(gx + 1), xhi(gx + 1), ylo(gy + 1), yhi(gy + 1);
+    for (int i = 0; i <= gx; ++i) cmh::region_span(offx, wx, Lx, i, &xlo[i], &xhi[i]);
+    for (int k = 0; k <= gy; ++k) cmh::region_span(offy, wy, Ly, k, &ylo[k], &yhi[k]);
+    long long bad = 0;
+    std::vector<int> hit;
+    for (int sy = 0; sy < m->nsy; ++sy) {
+        const double py = cmh::station_pos(sy, m->ds);
+        for (int sx = 0; sx < m->nsx; ++sx) {
+            const double px = cmh::station_pos(sx, m->ds);
+            hit.clear();
+            for (int k = 0; k <= gy; ++k) {
+                if (!(yhi[k] > ylo[k])) continue;
+                if (py < ylo[k] - m->r_c || py > yhi[k] + m->r_c) continue;
+                for (int i = 0; i <= gx; ++i) {
+                    if (!(xhi[i] > xlo[i])) continue;
+                    if (rect_distance(px, py, xlo[i], xhi[i], ylo[k], yhi[k]) < m->r_c)
+                        hit.push_back((i % p) + p * (k % p));
+                }
+            }
+            std::sort(hit.begin(), hit.end());
+            for (size_t q = 1; q < hit.size(); ++q) bad += hit[q] == hit[q - 1];
+        }
+    }
+    return bad;
+}
+
+int32_t choose_period(const cmh_model *m, int gx, int gy, double offx, double offy, int dynamic,
+                      int requested, int *period)
+{
+    const double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    const double w = std::min(Lx / (double)gx, Ly / (double)gy);
+    int p;
+    if (dynamic) {
+        p = (int)std::ceil(2.0 * m->r_c / w) + 1;
+        if (requested > 0) {
+            if (requested < p)
+                return fail(CMH_ECOLOR, "requested period too small for shifted partitions");
+            p = requested;
+        }
+        if (colour_conflicts(m, gx, gy, offx, offy, p) != 0)
+            return fail(CMH_ECOLOR, "colouring check failed");
+    } else if (requested > 0) {
+        p = requested;
+        if (colour_conflicts(m, gx, gy, offx, offy, p) != 0)
+            return fail(CMH_ECOLOR, "requested period gives dependent regions of one colour");
+    } else {
+        const int pmax = std::max(gx, gy) + 1;
+        for (p = 1; p <= pmax; ++p)
+            if (colour_conflicts(m, gx, gy, offx, offy, p) == 0) break;
+        if (p > pmax) return fail(CMH_ECOLOR, "no colouring separates the regions");
+    }
+    *period = p;
+    return CMH_OK;
+}
+
+int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
+{
+    int32_t rc = check_model(m);
+    if (rc) return rc;
+    if (!s) return fail(CMH_EINVAL, "sampler is NULL");
+    rc = check_grid(s->grid_x, s->grid_y);
+    if (rc) return rc;
+    if (s->moves_per_region < 1 || s->moves_per_region > 4095)
+        return fail(CMH_EINVAL, "moves_per_region must be in 1..4095");
+    if (s->region_capacity < 1 || s->region_capacity > cmh::kMaxCap)
+        return fail(CMH_EINVAL, "region_capacity must be in 1..64");
+    const double ps[5] = {s->p_birth, s->p_death, s->p_loc, s->p_time, s->p_mag};
+    double sum = 0.0;
+    for (double v : ps) {
+        if (!(v >= 0.0)) return fail(CMH_EINVAL, "move probabilities must be non-negative");
+        sum += v;
+    }
+    if (!(s->p_birth > 0.0) || !(s->p_death > 0.0))
+        return fail(CMH_EINVAL, "birth and death probabilities must be positive");
+    if (std::fabs(sum - 1.0) > 1e-9) return fail(CMH_EINVAL, "move probabilities must sum to 1");
+    if (!(s->step_xy >= 0.0) || !(s->step_t >= 0.0) || !(s->step_m >= 0.0))
+        return fail(CMH_EINVAL, "step sizes must be non-negative");
+    if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256)
+        return fail(CMH_EINVAL, "block must be 0, 64, 128 or 256");
+    if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
+    if (s->prior_only != 0 && s->prior_only != 1)
+        return fail(CMH_EINVAL, "prior_only must be 0 or 1");
+    int p = 0;
+    rc = choose_period(m, s->grid_x, s->grid_y, 0.0, 0.0, s->dynamic, s->period, &p);
+    if (rc) return rc;
+
+    std::memset(g, 0, sizeof *g);
+    g->nsx = m->nsx; g->nsy = m->nsy; g->nsta = m->nsx * m->nsy; g->ts = m->t_s;
+    g->N = (int)m->n_samples;
+    g->gx = s->grid_x; g->gy = s->grid_y; g->nrx = s->grid_x + 1; g->nry = s->grid_y + 1;
+    g->R = g->nrx * g->nry;
+    g->period = p; g->ncolors = p * p; g->dynamic = s->dynamic;
+    g->k = s->moves_per_region; g->cap = s->region_capacity; g->prior_only = s->prior_only;
+    g->ds = m->ds; g->sigma2 = m->sigma * m->sigma; g->atten = m->atten; g->vel = m->velocity;
+    g->decay = m->env_decay; g->rc = m->r_c; g->lambda = m->lambda; g->mmin = m->mag_min;
+    g->mrate = m->mag_rate;
+    g->Lx = (double)m->nsx * m->ds; g->Ly = (double)m->nsy * m->ds;
+    g->wx = g->Lx / (double)s->grid_x; g->wy = g->Ly / (double)s->grid_y;
+    g->pb = s->p_birth; g->pd = s->p_death; g->ploc = s->p_loc; g->pt = s->p_time;
+    g->pm = s->p_mag;
+    g->sxy = s->step_xy; g->st = s->step_t; g->sm = s->step_m;
+    g->c1 = g->pb;
+    g->c2 = g->c1 + g->pd;
+    g->c3 = g->c2 + g->ploc;
+    g->c4 = g->c3 + g->pt;
+    return CMH_OK;
+}
+
+// Workspace carving.  When st is NULL only the size is computed.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        const size_t o = align_up(off);
+        off = o + count * sizeof(T);
+        return base ? (T *)(base + o) : nullptr;
+    }
+};
+
+void carve_events(Carver &c, const Geo &g, int chains, Events *ev)
+{
+    const size_t slots = (size_t)chains * g.R * g.cap;
+    ev->x = c.take<double>(slots);
+    ev->y = c.take<double>(slots);
+    ev->t = c.take<double>(slots);
+    ev->m = c.take<double>(slots);
+    ev->id = c.take<unsigned long long>(slots);
+    ev->cnt = c.take<int>((size_t)chains * g.R);
+    ev->off = c.take<double>((size_t)chains * 2);
+}
+
+}  // namespace
+
+struct cmh_state {
+    Geo g;
+    int chains = 0;
+    int f64 = 0;
+    const void *trace = nullptr;
+    double *E = nullptr;
+    Events ev[2];
+    Events snap;
+    int cur = 0;
+    long long *sweep_ctr = nullptr;
+    int *err = nullptr;
+    unsigned long long *stats = nullptr;
+    unsigned long long *stats_snap = nullptr;
+    double *partials = nullptr;
+    double *llout = nullptr;
+    int block = 256;
+    const double *feed = nullptr;
+    long long feed_first = 0, feed_n = 0;
+    double *logp = nullptr;
+    long long log_first = 0, log_n = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_block = 0;
+    hipStream_t cap_stream = nullptr;
+    int poisoned = 0;
+};
+
+namespace {
+
+size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
+{
+    Carver c{base};
+    double *E = c.take<double>((size_t)chains * g.nsta * (size_t)g.N);
+    Events ev0, ev1, snap;
+    carve_events(c, g, chains, &ev0);
+    carve_events(c, g, chains, &ev1);
+    carve_events(c, g, chains, &snap);
+    long long *sweep = c.take<long long>(1);
+    int *err = c.take<int>(1);
+    unsigned long long *stats = c.take<unsigned long long>((size_t)chains * cmh::kStats);
+    unsigned long long *stats_snap = c.take<unsigned long long>((size_t)chains * cmh::kStats);
+    double *partials = c.take<double>((size_t)chains * cmh::refresh_blocks(g));
+    double *llout = c.take<double>((size_t)chains);
+    if (st) {
+        st->E = E;
+        st->ev[0] = ev0;
+        st->ev[1] = ev1;
+        st->snap = snap;
+        st->sweep_ctr = sweep;
+        st->err = err;
+        st->stats = stats;
+        st->stats_snap = stats_snap;
+        st->partials = partials;
+        st->llout = llout;
+    }
+    return align_up(c.off);
+}
+
+int32_t check_state(cmh_state *st)
+{
+    if (!st) return fail(CMH_EINVAL, "state is NULL");
+    if (st->poisoned) return fail(CMH_ESTATE, "state poisoned by an earlier device error");
+    return CMH_OK;
+}
+
+// Synchronises the device and turns a latched device flag into a status.
+int32_t sync_and_check(cmh_state *st)
+{
+    HIPCHK(hipDeviceSynchronize());
+    int flags = 0;
+    HIPCHK(hipMemcpy(&flags, st->err, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) {
+        st->poisoned = 1;
+        if (flags & cmh::kFlagCap) return fail(CMH_ECAP, "a region exceeded its event capacity");
+        if (flags & cmh::kFlagNan) return fail(CMH_ENAN, "NaN or Inf in a likelihood change");
+        return fail(CMH_ESTATE, "footprint or tile capacity exceeded");
+    }
+    return CMH_OK;
+}
+
+hipError_t copy_events(const Events &dst, const Events &src, const Geo &g, int chains,
+                       hipStream_t s)
+{
+    const size_t slots = (size_t)chains * g.R * g.cap;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dst.x, src.x, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if ((e = hipMemcpyAsync(dst.y, src.y, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if ((e = hipMemcpyAsync(dst.t, src.t, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if ((e = hipMemcpyAsync(dst.m, src.m, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if ((e = hipMemcpyAsync(dst.id, src.id, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if ((e = hipMemcpyAsync(dst.cnt, src.cnt, (size_t)chains * g.R * 4, hipMemcpyDeviceToDevice,
+                            s)))
+        return e;
+    return hipMemcpyAsync(dst.off, src.off, (size_t)chains * 16, hipMemcpyDeviceToDevice, s);
+}
+
+// Enqueue one colour phase (and, for colour 0 of a shifted partition, the
+// sweep's re-layout) reading the sweep index from the device counter.
+hipError_t enqueue_phase(cmh_state *st, int color, bool relayout, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (relayout && st->g.dynamic) {
+        e = cmh::launch_rebin(st->g, st->ev[st->cur], st->ev[st->cur ^ 1], st->sweep_ctr, st->err,
+                              st->chains, s);
+        if (e) return e;
+        st->cur ^= 1;
+    }
+    return cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
+                             st->sweep_ctr, st->feed, st->feed_first, st->logp, st->log_first,
+                             st->log_n, st->stats, st->err, st->block, st->chains, s);
+}
+
+void drop_graphs(cmh_state *st)
+{
+    for (auto &gr : st->graph) {
+        if (gr) (void)hipGraphExecDestroy(gr);
+        gr = nullptr;
+    }
+    st->graph_block = 0;
+}
+
+// One graph per layout parity: [re-layout], every colour, advance counter.
+int32_t build_graphs(cmh_state *st)
+{
+    drop_graphs(st);
+    const int saved = st->cur;
+    const int nparity = st->g.dynamic ? 2 : 1;
+    for (int par = 0; par < nparity; ++par) {
+        st->cur = par;
+        HIPCHK(hipStreamBeginCapture(st->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < st->g.ncolors && e == hipSuccess; ++c)
+            e = enqueue_phase(st, c, c == 0, st->cap_stream);
+        if (e == hipSuccess) e = cmh::advance_sweep(st->sweep_ctr, st->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(st->cap_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            st->cur = saved;
+            drop_graphs(st);
+            return fail(CMH_EHIP, std::string("graph capture failed: ") +
+                                      hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&st->graph[par], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            st->cur = saved;
+            drop_graphs(st);
+            return fail(CMH_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+    }
+    st->cur = saved;
+    st->graph_block = st->block;
+    return CMH_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, int> g_tune_cache;
+
+}  // namespace
+
+extern "C" {
+
+const char *cmh_last_error(void) { return g_err.c_str(); }
+
+int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t grid_y,
+                                double off_x, double off_y, int32_t dynamic, int32_t *n_reg_x,
+                                int32_t *n_reg_y, int32_t *period, int32_t *n_colors,
+                                int32_t *color_of_region)
+{
+    int32_t rc = check_model(model);
+    if (rc) return rc;
+    rc = check_grid(grid_x, grid_y);
+    if (rc) return rc;
+    if (!n_reg_x || !n_reg_y || !period || !n_colors) return fail(CMH_EINVAL, "NULL output");
+    const double Lx = (double)model->nsx * model->ds, Ly = (double)model->nsy * model->ds;
+    const double wx = Lx / grid_x, wy = Ly / grid_y;
+    if (!(off_x >= 0.0 && off_x < wx && off_y >= 0.0 && off_y < wy))
+        return fail(CMH_EINVAL, "offsets must lie in [0, w)");
+    int p = 0;
+    rc = choose_period(model, grid_x, grid_y, off_x, off_y, dynamic ? 1 : 0, 0, &p);
+    if (rc) return rc;
+    *n_reg_x = grid_x + 1;
+    *n_reg_y = grid_y + 1;
+    *period = p;
+    *n_colors = p * p;
+    if (color_of_region)
+        for (int k = 0; k <= grid_y; ++k)
+            for (int i = 0; i <= grid_x; ++i)
+                color_of_region[k * (grid_x + 1) + i] = (i % p) + p * (k % p);
+    return CMH_OK;
+}
+
+int32_t cmh_state_bytes(const cmh_model *model, const cmh_sampler *sampler, int32_t n_chains,
+                        size_t *bytes)
+{
+    Geo g;
+    int32_t rc = make_geo(model, sampler, &g);
+    if (rc) return rc;
+    if (n_chains < 1 || n_chains > 65535) return fail(CMH_EINVAL, "n_chains must be in 1..65535");
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = carve_state(g, n_chains, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const void *trace_dev,
+                       int32_t trace_dtype, int32_t n_chains, uint32_t seed, void *workspace_dev,
+                       size_t workspace_bytes, void *hip_stream, cmh_state **out)
+{
+    if (!out) return fail(CMH_EINVAL, "out is NULL");
+    *out = nullptr;
+    Geo g;
+    int32_t rc = make_geo(model, sampler, &g);
+    if (rc) return rc;
+    if (n_chains < 1 || n_chains > 65535) return fail(CMH_EINVAL, "n_chains must be in 1..65535");
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    if (!trace_dev) return fail(CMH_EINVAL, "trace_dev is NULL");
+    if (!workspace_dev) return fail(CMH_EINVAL, "workspace_dev is NULL");
+    const size_t need = carve_state(g, n_chains, nullptr, nullptr);
+    if (workspace_bytes < need)
+        return fail(CMH_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    g.seed = seed;
+
+    cmh_state *st = new cmh_state();
+    st->g = g;
+    st->chains = n_chains;
+    st->f64 = trace_dtype == CMH_F64;
+    st->trace = trace_dev;
+    st->block = sampler->block ? sampler->block : 256;
+    carve_state(g, n_chains, (char *)workspace_dev, st);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
+    const long long nE = (long long)n_chains * g.nsta * (long long)g.N;
+    const long long nR = (long long)n_chains * g.R;
+    if (!e) e = cmh::fill_f64(st->E, nE, 0.0, s);
+    for (int b = 0; b < 2 && !e; ++b) {
+        e = cmh::fill_i32(st->ev[b].cnt, nR, 0, s);
+        if (!e) e = cmh::fill_f64(st->ev[b].off, 2LL * n_chains, 0.0, s);
+    }
+    if (!e) e = cmh::fill_i32(st->err, 1, 0, s);
+    if (!e) e = cmh::fill_u64(st->stats, (long long)cmh::kStats * n_chains, s);
+    if (!e) e = cmh::set_sweep(st->sweep_ctr, 0, s);
+    if (e) {
+        if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
+        delete st;
+        return fail(CMH_EHIP, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = st;
+    return CMH_OK;
+}
+
+int32_t cmh_sweep_color(cmh_state *st, int64_t sweep, int32_t color, void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (color < 0 || color >= st->g.ncolors) return fail(CMH_EINVAL, "colour out of range");
+    if (sweep < 0 || sweep >= (1LL << 32)) return fail(CMH_EINVAL, "sweep out of range");
+    if (st->feed && (sweep < st->feed_first || sweep >= st->feed_first + st->feed_n))
+        return fail(CMH_EINVAL, "sweep outside the attached feed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(cmh::set_sweep(st->sweep_ctr, sweep, s));
+    HIPCHK(enqueue_phase(st, color, color == 0, s));
+    return CMH_OK;
+}
+
+int32_t cmh_run_sweeps(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (n_sweeps < 0 || first_sweep < 0 || first_sweep + n_sweeps > (1LL << 32))
+        return fail(CMH_EINVAL, "sweep range out of bounds");
+    if (st->feed || st->logp) {
+        for (int64_t s = first_sweep; s < first_sweep + n_sweeps; ++s)
+            for (int c = 0; c < st->g.ncolors; ++c) {
+                rc = cmh_sweep_color(st, s, c, hip_stream);
+                if (rc) return rc;
+            }
+        return CMH_OK;
+    }
+    if (n_sweeps == 0) return CMH_OK;
+    if (st->graph_block != st->block || !st->graph[0]) {
+        rc = build_graphs(st);
+        if (rc) return rc;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(cmh::set_sweep(st->sweep_ctr, first_sweep, s));
+    for (int64_t q = 0; q < n_sweeps; ++q) {
+        HIPCHK(hipGraphLaunch(st->graph[st->g.dynamic ? st->cur : 0], s));
+        if (st->g.dynamic) st->cur ^= 1;
+    }
+    return CMH_OK;
+}
+
+int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64_t cap,
+                        int64_t *n_out)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
+    if (!n_out) return fail(CMH_EINVAL, "n_out is NULL");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    const Geo &g = st->g;
+    const Events &ev = st->ev[st->cur];
+    const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
+    std::vector<int> cnt(g.R);
+    std::vector<double> x(slots), y(slots), t(slots), m(slots);
+    std::vector<unsigned long long> id(slots);
+    HIPCHK(hipMemcpy(cnt.data(), ev.cnt + (size_t)chain * g.R, g.R * sizeof(int),
+                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(x.data(), ev.x + o, slots * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(y.data(), ev.y + o, slots * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(t.data(), ev.t + o, slots * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(m.data(), ev.m + o, slots * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(id.data(), ev.id + o, slots * 8, hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (int r = 0; r < g.R; ++r) n += cnt[r];
+    *n_out = n;
+    if (n > cap) return fail(CMH_EINVAL, "output capacity too small");
+    if (n > 0 && !out_host) return fail(CMH_EINVAL, "out_host is NULL");
+    int64_t q = 0;
+    for (int r = 0; r < g.R; ++r)
+        for (int s = 0; s < cnt[r]; ++s) {
+            const size_t a = (size_t)r * g.cap + s;
+            cmh_event &e = out_host[q++];
+            e.x = x[a]; e.y = y[a]; e.t = t[a]; e.m = m[a]; e.id = id[a];
+            e.region = r; e._pad = 0;
+        }
+    return CMH_OK;
+}
+
+int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host, int64_t n)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
+    if (n < 0 || (n > 0 && !ev_host)) return fail(CMH_EINVAL, "bad event array");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    const Geo &g = st->g;
+    const Events &ev = st->ev[st->cur];
+    double off[2];
+    HIPCHK(hipMemcpy(off, ev.off + 2 * chain, 16, hipMemcpyDeviceToHost));
+    std::vector<std::vector<cmh_event>> reg(g.R);
+    for (int64_t q = 0; q < n; ++q) {
+        const cmh_event &e = ev_host[q];
+        if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
+              e.t < (double)g.N && e.m >= g.mmin))
+            return fail(CMH_EINVAL, "event outside the model's support");
+        const int i = cmh::region_axis(e.x, off[0], g.wx, g.gx);
+        const int k = cmh::region_axis(e.y, off[1], g.wy, g.gy);
+        reg[k * g.nrx + i].push_back(e);
+    }
+    const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
+    std::vector<int> cnt(g.R, 0);
+    std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0);
+    std::vector<unsigned long long> id(slots, 0);
+    for (int r = 0; r < g.R; ++r) {
+        auto &L = reg[r];
+        if ((int)L.size() > g.cap) return fail(CMH_ECAP, "a region exceeds its capacity");
+        std::sort(L.begin(), L.end(),
+                  [](const cmh_event &a, const cmh_event &b) { return a.id < b.id; });
+        cnt[r] = (int)L.size();
+        for (size_t s = 0; s < L.size(); ++s) {
+            const size_t a = (size_t)r * g.cap + s;
+            x[a] = L[s].x; y[a] = L[s].y; t[a] = L[s].t; m[a] = L[s].m; id[a] = L[s].id;
+        }
+    }
+    HIPCHK(hipMemcpy(ev.cnt + (size_t)chain * g.R, cnt.data(), g.R * sizeof(int),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.x + o, x.data(), slots * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.y + o, y.data(), slots * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.t + o, t.data(), slots * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.m + o, m.data(), slots * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.id + o, id.data(), slots * 8, hipMemcpyHostToDevice));
+    HIPCHK(cmh::launch_refresh(g, ev, st->trace, st->f64, st->E, 1, st->partials, nullptr, chain,
+                               1, st->err, nullptr));
+    return sync_and_check(st);
+}
+
+int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep, int64_t n_sweeps)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (feed_dev && (first_sweep < 0 || n_sweeps < 1))
+        return fail(CMH_EINVAL, "feed needs first_sweep >= 0 and n_sweeps >= 1");
+    st->feed = feed_dev;
+    st->feed_first = feed_dev ? first_sweep : 0;
+    st->feed_n = feed_dev ? n_sweeps : 0;
+    return CMH_OK;
+}
+
+int32_t cmh_set_log(cmh_state *st, double *log_dev, int64_t first_sweep, int64_t n_sweeps)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (log_dev && (first_sweep < 0 || n_sweeps < 1))
+        return fail(CMH_EINVAL, "log needs first_sweep >= 0 and n_sweeps >= 1");
+    st->logp = log_dev;
+    st->log_first = log_dev ? first_sweep : 0;
+    st->log_n = log_dev ? n_sweeps : 0;
+    return CMH_OK;
+}
+
+int32_t cmh_refresh(cmh_state *st, int32_t write_variance, double *out_host, void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(cmh::launch_refresh(st->g, st->ev[st->cur], st->trace, st->f64, st->E,
+                               write_variance ? 1 : 0, st->partials,
+                               out_host ? st->llout : nullptr, 0, st->chains, st->err, s));
+    if (!out_host) return CMH_OK;
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(out_host, st->llout, (size_t)st->chains * 8, hipMemcpyDeviceToHost));
+    return CMH_OK;
+}
+
+int32_t cmh_read_variance(cmh_state *st, int32_t chain, int64_t station0, int64_t nsta,
+                          double *out_host)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
+    if (station0 < 0 || nsta < 0 || station0 + nsta > st->g.nsta || (nsta > 0 && !out_host))
+        return fail(CMH_EINVAL, "station range out of bounds");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    const size_t N = (size_t)st->g.N;
+    const double *src = st->E + ((size_t)chain * st->g.nsta + (size_t)station0) * N;
+    HIPCHK(hipMemcpy(out_host, src, (size_t)nsta * N * 8, hipMemcpyDeviceToHost));
+    return CMH_OK;
+}
+
+int32_t cmh_read_stats(cmh_state *st, int32_t chain, uint64_t *out_host)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (chain < 0 || chain >= st->chains || !out_host) return fail(CMH_EINVAL, "bad arguments");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(out_host, st->stats + (size_t)chain * cmh::kStats, cmh::kStats * 8,
+                     hipMemcpyDeviceToHost));
+    return CMH_OK;
+}
+
+int32_t cmh_get_block(cmh_state *st, int32_t *block)
+{
+    if (!st || !block) return fail(CMH_EINVAL, "NULL argument");
+    *block = st->block;
+    return CMH_OK;
+}
+
+int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
+    if (st->feed || st->logp) return fail(CMH_EINVAL, "detach feed and log before tuning");
+    const Geo &g = st->g;
+    const auto key = std::make_tuple(g.nsx, g.nsy, g.N, g.gx, g.gy, g.k, g.cap, st->chains,
+                                     st->f64, g.dynamic);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            st->block = it->second;
+            return CMH_OK;
+        }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    const int saved_cur = st->cur;
+    HIPCHK(copy_events(st->snap, st->ev[saved_cur], g, st->chains, s));
+    HIPCHK(hipMemcpyAsync(st->stats_snap, st->stats, (size_t)st->chains * cmh::kStats * 8,
+                          hipMemcpyDeviceToDevice, s));
+    auto restore = [&]() -> int32_t {
+        st->cur = saved_cur;
+        HIPCHK(copy_events(st->ev[saved_cur], st->snap, g, st->chains, s));
+        HIPCHK(cmh::launch_refresh(g, st->ev[saved_cur], st->trace, st->f64, st->E, 1,
+                                   st->partials, nullptr, 0, st->chains, st->err, s));
+        HIPCHK(hipMemcpyAsync(st->stats, st->stats_snap, (size_t)st->chains * cmh::kStats * 8,
+                              hipMemcpyDeviceToDevice, s));
+        return CMH_OK;
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int cands[3] = {64, 128, 256};
+    int best = st->block;
+    float best_ms = 1e30f;
+    for (int b : cands) {
+        st->block = b;
+        rc = cmh_run_sweeps(st, first_sweep, 1, hip_stream);  // warm-up, builds graphs
+        if (!rc) rc = restore();
+        if (!rc) {
+            (void)hipEventRecord(e0, s);
+            rc = cmh_run_sweeps(st, first_sweep, n_trial, hip_stream);
+            (void)hipEventRecord(e1, s);
+        }
+        if (!rc) rc = sync_and_check(st);
+        float ms = 0.f;
+        if (!rc) (void)hipEventElapsedTime(&ms, e0, e1);
+        const int32_t rc2 = restore();
+        if (rc || rc2) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc ? rc : rc2;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st->block = best;
+    drop_graphs(st);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    return sync_and_check(st);
+}
+
+int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream,
+                        float *ms_out)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!ms_out || n_sweeps < 1 || first_sweep < 0 || first_sweep + n_sweeps > (1LL << 32))
+        return fail(CMH_EINVAL, "bad arguments");
+    if (st->feed && (first_sweep < st->feed_first ||
+                     first_sweep + n_sweeps > st->feed_first + st->feed_n))
+        return fail(CMH_EINVAL, "sweeps outside the attached feed");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nc = st->g.ncolors;
+    std::vector<hipEvent_t> ev((size_t)n_sweeps * (nc + 2));
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    hipError_t e = hipSuccess;
+    for (int64_t q = 0; q < n_sweeps && e == hipSuccess; ++q) {
+        hipEvent_t *E = &ev[(size_t)q * (nc + 2)];
+        e = cmh::set_sweep(st->sweep_ctr, first_sweep + q, s);
+        if (!e) e = hipEventRecord(E[0], s);
+        if (!e && st->g.dynamic) {
+            e = cmh::launch_rebin(st->g, st->ev[st->cur], st->ev[st->cur ^ 1], st->sweep_ctr,
+                                  st->err, st->chains, s);
+            st->cur ^= 1;
+        }
+        if (!e) e = hipEventRecord(E[1], s);
+        for (int c = 0; c < nc && !e; ++c) {
+            e = enqueue_phase(st, c, false, s);
+            if (!e) e = hipEventRecord(E[2 + c], s);
+        }
+    }
+    if (!e) e = hipStreamSynchronize(s);
+    for (int c = 0; c <= nc; ++c) ms_out[c] = 0.f;
+    for (int64_t q = 0; q < n_sweeps && !e; ++q) {
+        hipEvent_t *E = &ev[(size_t)q * (nc + 2)];
+        float ms = 0.f;
+        if (!e) e = hipEventElapsedTime(&ms, E[0], E[1]);
+        ms_out[nc] += ms;
+        for (int c = 0; c < nc && !e; ++c) {
+            e = hipEventElapsedTime(&ms, E[1 + c], E[2 + c]);
+            ms_out[c] += ms;
+        }
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e) return fail(CMH_EHIP, std::string("phase timing: ") + hipGetErrorString(e));
+    return sync_and_check(st);
+}
+
+int32_t cmh_destroy(cmh_state *st)
+{
+    if (!st) return CMH_OK;
+    drop_graphs(st);
+    if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
+    delete st;
+    return CMH_OK;
+}
+
+// ---------------------------------------------------------------- simulator
+namespace {
+
+struct TruthLayout {
+    Geo g;
+    std::vector<std::vector<cmh_event>> cells;
+    int cap = 1;
+};
+
+int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, TruthLayout *L)
+{
+    int32_t rc = check_model(model);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !truth)) return fail(CMH_EINVAL, "bad truth array");
+    Geo &g = L->g;
+    std::memset(&g, 0, sizeof g);
+    g.nsx = model->nsx; g.nsy = model->nsy; g.nsta = g.nsx * g.nsy; g.ts = model->t_s;
+    g.N = (int)model->n_samples;
+    g.gx = model->nsx; g.gy = model->nsy; g.nrx = g.gx + 1; g.nry = g.gy + 1;
+    g.R = g.nrx * g.nry;
+    g.ds = model->ds; g.sigma2 = model->sigma * model->sigma; g.atten = model->atten;
+    g.vel = model->velocity; g.decay = model->env_decay; g.rc = model->r_c;
+    g.Lx = (double)model->nsx * model->ds; g.Ly = (double)model->nsy * model->ds;
+    g.wx = g.Lx / (double)g.gx; g.wy = g.Ly / (double)g.gy;
+    L->cells.assign(g.R, {});
+    for (int64_t q = 0; q < n; ++q) {
+        const cmh_event &e = truth[q];
+        if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
+              e.t < (double)g.N && std::isfinite(e.m)))
+            return fail(CMH_EINVAL, "truth event outside the domain");
+        const int i = cmh::region_axis(e.x, 0.0, g.wx, g.gx);
+        const int k = cmh::region_axis(e.y, 0.0, g.wy, g.gy);
+        L->cells[k * g.nrx + i].push_back(e);
+    }
+    L->cap = 1;
+    for (auto &c : L->cells) {
+        std::sort(c.begin(), c.end(),
+                  [](const cmh_event &a, const cmh_event &b) { return a.id < b.id; });
+        L->cap = std::max(L->cap, (int)c.size());
+    }
+    if (L->cap > cmh::kMaxTileEvents / 9)
+        return fail(CMH_EINVAL, "too many truth events in one station cell");
+    g.cap = L->cap;
+    return CMH_OK;
+}
+
+size_t carve_truth(const Geo &g, char *base, Events *ev, int **err)
+{
+    Carver c{base};
+    Events e;
+    carve_events(c, g, 1, &e);
+    int *f = c.take<int>(1);
+    if (ev) *ev = e;
+    if (err) *err = f;
+    return align_up(c.off);
+}
+
+}  // namespace
+
+int32_t cmh_simulate_bytes(const cmh_model *model, const cmh_event *truth_host, int64_t n_events,
+                           size_t *bytes)
+{
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    TruthLayout L;
+    int32_t rc = truth_layout(model, truth_host, n_events, &L);
+    if (rc) return rc;
+    *bytes = carve_truth(L.g, nullptr, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_t n_events,
+                     uint32_t seed, void *trace_dev, int32_t trace_dtype, void *workspace_dev,
+                     size_t workspace_bytes, void *hip_stream)
+{
+    TruthLayout L;
+    int32_t rc = truth_layout(model, truth_host, n_events, &L);
+    if (rc) return rc;
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    if (!trace_dev || !workspace_dev) return fail(CMH_EINVAL, "NULL device buffer");
+    const Geo &g = L.g;
+    const size_t need = carve_truth(g, nullptr, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(CMH_EINVAL, "simulator workspace too small");
+    Events ev;
+    int *err = nullptr;
+    carve_truth(g, (char *)workspace_dev, &ev, &err);
+    const size_t slots = (size_t)g.R * g.cap;
+    std::vector<int> cnt(g.R, 0);
+    std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0), off(2, 0.0);
+    std::vector<unsigned long long> id(slots, 0);
+    for (int r = 0; r < g.R; ++r) {
+        cnt[r] = (int)L.cells[r].size();
+        for (size_t s = 0; s < L.cells[r].size(); ++s) {
+            const size_t a = (size_t)r * g.cap + s;
+            const cmh_event &e = L.cells[r][s];
+            x[a] = e.x; y[a] = e.y; t[a] = e.t; m[a] = e.m; id[a] = e.id;
+        }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(hipMemcpyAsync(ev.cnt, cnt.data(), g.R * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.x, x.data(), slots * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.y, y.data(), slots * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.t, t.data(), slots * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.m, m.data(), slots * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.id, id.data(), slots * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ev.off, off.data(), 16, hipMemcpyHostToDevice, s));
+    HIPCHK(cmh::fill_i32(err, 1, 0, s));
+    HIPCHK(cmh::launch_simulate(g, ev, seed, trace_dev, trace_dtype == CMH_F64, err, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int flags = 0;
+    HIPCHK(hipMemcpy(&flags, err, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags) return fail(CMH_ESTATE, "simulator tile capacity exceeded");
+    return CMH_OK;
+}
+
+int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region, uint32_t j0,
+                       int32_t count, double *out_dev, void *hip_stream)
+{
+    if (count < 0 || (count > 0 && !out_dev)) return fail(CMH_EINVAL, "bad arguments");
+    if (count == 0) return CMH_OK;
+    HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, out_dev,
+                             (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// cmh_common.hpp -- shared definitions of the chromatic MH library: the
+// by-value parameter block every kernel receives, the event-table layout, and
+// the small pieces of arithmetic that must give the same bits on the host and
+// the device (Philox4x32-10, uniform conversion, region binning, arrival
+// geometry).  Compiled with -ffp-contract=off so that no product is fused
+// into an add where the result decides an integer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmh {
+
+constexpr int kMaxCap = 64;          // events per region
+constexpr int kMaxSeg = 32;          // footprint segments per move
+constexpr int kMaxTs = 128;          // signal duration, samples
+constexpr int kMaxFootprint = 2048;  // samples touched by one move (16 * kMaxTs)
+constexpr int kDrawChunk = 64;       // moves whose draws are staged at once
+constexpr int kTile = 2048;          // samples per workgroup in streaming kernels
+constexpr int kMaxTileEvents = 640;  // events reaching one station tile
+
+enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8 };
+
+// Per-chain statistics: [3 t + 0..2] attempted / evaluated / accepted moves of
+// type t, [15] footprint samples evaluated, [16] footprint samples rewritten.
+constexpr int kStats = 17;
+
+// Model, partition and sampler constants (by value in every kernel).
+struct Geo {
+    int nsx, nsy, nsta, ts;
+    int N;
+    int gx, gy, nrx, nry, R;
+    int period, ncolors, dynamic;
+    int k, cap, prior_only;
+    uint32_t seed;
+    double ds, sigma2, atten, vel, decay, rc, lambda, mmin, mrate, Lx, Ly;
+    double wx, wy;
+    double pb, pd, ploc, pt, pm, sxy, st, sm;
+    double c1, c2, c3, c4;  // cumulative move-type thresholds
+};
+
+// Region-slot event table for all chains.  Slot s of region r of chain c is
+// element ((c * R) + r) * cap + s of each array; cnt[c * R + r] slots are
+// live, ordered by id.  off[2c], off[2c+1]: the partition offset the table
+// is laid out for.
+struct Events {
+    double *x, *y, *t, *m;
+    unsigned long long *id;
+    int *cnt;
+    double *off;
+};
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds, each multiplying counter
+// words 0 and 2 by the Philox multipliers and mixing the high halves with the
+// other words and the round key; the key advances by the Weyl constants.
+__host__ __device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t a = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t b = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t x0 = (uint32_t)(b >> 32) ^ c[1] ^ k0;
+        const uint32_t x2 = (uint32_t)(a >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)b;
+        c[3] = (uint32_t)a;
+        c[0] = x0;
+        c[2] = x2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Open-interval uniform: centre of cell k of 2^52, k from the top 26 bits of
+// two words.  Exact in binary64.
+__host__ __device__ inline double unit_open(uint32_t hi, uint32_t lo)
+{
+    const uint64_t cell = ((uint64_t)(hi >> 6) << 26) | (uint64_t)(lo >> 6);
+    return (double)(cell * 2u + 1u) * 0x1p-53;
+}
+
+// Partition offset of sweep `sweep` for chain `chain`: counter
+// (sweep, 0xFFFFFFFF, 0, 0) under key (seed, chain).
+__host__ __device__ inline void sweep_offset(uint32_t seed, uint32_t chain, uint32_t sweep,
+                                             double wx, double wy, double *ox, double *oy)
+{
+    uint32_t c[4] = {sweep, 0xFFFFFFFFu, 0u, 0u};
+    philox10(c, seed, chain);
+    *ox = unit_open(c[0], c[1]) * wx;
+    *oy = unit_open(c[2], c[3]) * wy;
+}
+
+// Region index along one axis: floor((x - off) / w) + 1 clamped to [0, g].
+__host__ __device__ inline int region_axis(double x, double off, double w, int g)
+{
+    const double f = floor((x - off) / w);
+    int i = (int)f + 1;
+    i = i < 0 ? 0 : i;
+    return i > g ? g : i;
+}
+
+// Rectangle of region index i along one axis, clipped to [0, L).
+__host__ __device__ inline void region_span(double off, double w, double L, int i, double *lo,
+                                            double *hi)
+{
+    const double a = off + (double)(i - 1) * w;
+    const double b = off + (double)i * w;
+    *lo = a > 0.0 ? a : 0.0;
+    *hi = b < L ? b : L;
+}
+
+// Station position on the cell-centred grid.
+__host__ __device__ inline double station_pos(int i, double ds) { return ((double)i + 0.5) * ds; }
+
+// Arrival of an event at a station: distance, arrival time, first sample and
+// the variance scale B = A^2 exp(-2 (n0 - a) / decay), so that the variance
+// the event adds at sample n0 + q is B exp(-2 q / decay).
+struct Arrival {
+    int in;       // d < rc and the window meets the trace
+    int n0, n1;   // [n0, n1): affected samples; n0 = ceil(a)
+    double B;
+};
+
+__device__ inline Arrival arrive(const Geo &g, double x, double y, double t, double m, int ix,
+                                 int iy)
+{
+    Arrival ar;
+    const double dx = x - station_pos(ix, g.ds);
+    const double dy = y - station_pos(iy, g.ds);
+    const double d = sqrt(dx * dx + dy * dy);
+    const double a = t + d / g.vel;
+    const double c = ceil(a);
+    ar.in = 0;
+    ar.n0 = 0;
+    ar.n1 = 0;
+    ar.B = 0.0;
+    if (d < g.rc && c < (double)g.N) {
+        ar.n0 = (int)c;
+        ar.n1 = ar.n0 + g.ts < g.N ? ar.n0 + g.ts : g.N;
+        const double amp = m * exp(-d / g.atten);
+        ar.B = amp * amp * exp(-2.0 * (c - a) / g.decay);
+        ar.in = 1;
+    }
+    return ar;
+}
+
+}  // namespace cmh

@@ -1,0 +1,823 @@
+// cmh_kernels.hip -- device kernels of the chromatic MH region sweep.
+//
+//   k_sweep_color   one colour phase (Algorithm 4's parallel loop): one
+//                   workgroup per region of the colour, k MH moves each
+//   k_rebin         the sweep's partition (Section 4.3.2 offset) and the
+//                   move of every event into its region's id-ordered list
+//   k_refresh       exact event variance and signal log-likelihood (Section 3)
+//   k_simulate      forward simulator (synthetic worlds, Section 5)
+//   k_draws         the per-move draw records, for inspection
+#include "cmh_common.hpp"
+#include "cmh_kernels.hpp"
+
+#include <math.h>
+
+namespace cmh {
+
+// ------------------------------------------------------------------ draws
+// Per-move draw record under key (seed, chain), counter (sweep, region,
+// move, block): [0] move-type uniform, [1] uniform a, [2] uniform b,
+// [3] uniform c, [4] Exp(1), [5] [6] standard normals (Box-Muller),
+// [7] log of the acceptance uniform.
+__device__ inline void move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                                  uint32_t j, double out[8])
+{
+    uint32_t c[4];
+    c[0] = sweep; c[1] = region; c[2] = j; c[3] = 0u;
+    philox10(c, seed, chain);
+    out[0] = unit_open(c[0], c[1]);
+    out[1] = unit_open(c[2], c[3]);
+    c[0] = sweep; c[1] = region; c[2] = j; c[3] = 1u;
+    philox10(c, seed, chain);
+    out[2] = unit_open(c[0], c[1]);
+    out[3] = unit_open(c[2], c[3]);
+    c[0] = sweep; c[1] = region; c[2] = j; c[3] = 2u;
+    philox10(c, seed, chain);
+    out[4] = -log(unit_open(c[0], c[1]));
+    out[7] = log(unit_open(c[2], c[3]));
+    c[0] = sweep; c[1] = region; c[2] = j; c[3] = 3u;
+    philox10(c, seed, chain);
+    const double u1 = unit_open(c[0], c[1]);
+    const double u2 = unit_open(c[2], c[3]);
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 2.0 * M_PI * u2;
+    out[5] = rad * cos(ang);
+    out[6] = rad * sin(ang);
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One run of affected samples at one station: samples [lo, lo + len),
+// flat positions [pre, pre + len); the old event's window [o0, o1) with
+// scale Bo and the new event's window [w0, w1) with scale Bn.
+struct Seg {
+    int j, lo, len, pre;
+    int o0, o1, w0, w1;
+    double Bo, Bn;
+};
+
+struct MoveHdr {
+    int valid, type, n, nseg, S, pad;
+    double dm;  // magnitude change (magnitude move)
+};
+
+// Footprint of a move, computed by the 64 lanes of wave 0: every station
+// within the detection cutoff of the old or the new event, with the union of
+// their sample windows.  Lanes scan a box of candidate stations (the cells
+// around both events); a wave prefix sum places each lane's segments.
+__device__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
+                          double om, bool has_new, double nx, double ny, double nt, double nm,
+                          Seg *segs, int *nseg_out, int *S_out, int *flags)
+{
+    int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
+    if (has_old) {
+        const int cx = (int)floor(ox / g.ds), cy = (int)floor(oy / g.ds);
+        cx0 = min(cx0, cx); cx1 = max(cx1, cx); cy0 = min(cy0, cy); cy1 = max(cy1, cy);
+    }
+    if (has_new) {
+        const int cx = (int)floor(nx / g.ds), cy = (int)floor(ny / g.ds);
+        cx0 = min(cx0, cx); cx1 = max(cx1, cx); cy0 = min(cy0, cy); cy1 = max(cy1, cy);
+    }
+    cx0 = max(cx0 - 1, 0); cy0 = max(cy0 - 1, 0);
+    cx1 = min(cx1 + 1, g.nsx - 1); cy1 = min(cy1 + 1, g.nsy - 1);
+    const int bw = cx1 - cx0 + 1;
+    const int nbox = bw * (cy1 - cy0 + 1);
+    int seg_base = 0, samp_base = 0;
+    for (int c0 = 0; c0 < nbox; c0 += 64) {
+        const int cidx = c0 + lane;
+        int ns = 0, nsamp = 0;
+        Seg a, b;
+        if (cidx < nbox) {
+            const int ix = cx0 + cidx % bw, iy = cy0 + cidx / bw;
+            Arrival ao, an;
+            ao.in = 0; ao.n0 = 0; ao.n1 = 0; ao.B = 0.0;
+            an = ao;
+            if (has_old) ao = arrive(g, ox, oy, ot, om, ix, iy);
+            if (has_new) an = arrive(g, nx, ny, nt, nm, ix, iy);
+            const int j = iy * g.nsx + ix;
+            a.j = j; b.j = j;
+            a.o0 = ao.in ? ao.n0 : 0; a.o1 = ao.in ? ao.n1 : 0;
+            a.w0 = an.in ? an.n0 : 0; a.w1 = an.in ? an.n1 : 0;
+            a.Bo = ao.B; a.Bn = an.B;
+            b = a;
+            if (ao.in && an.in) {
+                const int lo = max(ao.n0, an.n0), hi = min(ao.n1, an.n1);
+                if (lo <= hi) {  // overlapping or touching windows: one run
+                    a.lo = min(ao.n0, an.n0);
+                    a.len = max(ao.n1, an.n1) - a.lo;
+                    ns = 1;
+                } else {         // disjoint windows: two runs, in sample order
+                    a.lo = min(ao.n0, an.n0);
+                    a.len = (ao.n0 < an.n0 ? ao.n1 : an.n1) - a.lo;
+                    b.lo = max(ao.n0, an.n0);
+                    b.len = (ao.n0 < an.n0 ? an.n1 : ao.n1) - b.lo;
+                    ns = 2;
+                }
+            } else if (ao.in) {
+                a.lo = ao.n0; a.len = ao.n1 - ao.n0; ns = 1;
+            } else if (an.in) {
+                a.lo = an.n0; a.len = an.n1 - an.n0; ns = 1;
+            }
+            nsamp = (ns >= 1 ? a.len : 0) + (ns == 2 ? b.len : 0);
+        }
+        int cs = ns, css = nsamp;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t1 = __shfl_up(cs, o, 64);
+            const int t2 = __shfl_up(css, o, 64);
+            if (lane >= o) { cs += t1; css += t2; }
+        }
+        const int sbase = seg_base + cs - ns;
+        const int pbase = samp_base + css - nsamp;
+        if (ns >= 1) {
+            if (sbase + ns <= kMaxSeg) {
+                a.pre = pbase;
+                segs[sbase] = a;
+                if (ns == 2) {
+                    b.pre = pbase + a.len;
+                    segs[sbase + 1] = b;
+                }
+            } else {
+                *flags |= kFlagSeg;
+            }
+        }
+        seg_base += __shfl(cs, 63, 64);
+        samp_base += __shfl(css, 63, 64);
+    }
+    *nseg_out = seg_base;
+    *S_out = samp_base;
+}
+
+// ------------------------------------------------------------ sweep colour
+// One workgroup per region of colour `color` (blockIdx.x) and chain
+// (blockIdx.y).  The region's events are staged in LDS; wave 0 lane 0 draws
+// and builds each proposal, wave 0 finds its footprint, every thread
+// evaluates the log-likelihood change on a strided share of the footprint
+// samples, and on acceptance writes the updated event variance in place.
+// The event variance E of other regions is read but never written: the
+// colouring guarantees that no station is reached from two regions of one
+// colour (Section 4.1's Markov-blanket argument).
+template <typename TraceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E,
+              int color, const long long *__restrict__ sweep_ptr, const double *__restrict__ feed,
+              long long feed_first, double *__restrict__ logp, long long log_first,
+              long long log_n, unsigned long long *__restrict__ stats, int *__restrict__ err)
+{
+    constexpr int W = BLOCK / 64;
+    constexpr int MAXQ = kMaxFootprint / BLOCK;
+    __shared__ double s_draw[kDrawChunk][8];
+    __shared__ double s_T[kMaxTs];
+    __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
+    __shared__ unsigned long long s_id[kMaxCap];
+    __shared__ Seg s_seg[2][kMaxSeg];
+    __shared__ MoveHdr s_hdr[2];
+    __shared__ double s_part[2][W];
+    __shared__ int s_n;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int p = g.period;
+    const int ci = color % p, ck = color / p;
+    const int ni = (g.nrx - ci + p - 1) / p;
+    const int i = ci + p * ((int)blockIdx.x % ni);
+    const int kk = ck + p * ((int)blockIdx.x / ni);
+    if (i >= g.nrx || kk >= g.nry) return;
+    const int r = kk * g.nrx + i;
+    const int chain = blockIdx.y;
+    const long long sweep = *sweep_ptr;
+
+    const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
+    double x0, x1, y0, y1;
+    region_span(offx, g.wx, g.Lx, i, &x0, &x1);
+    region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
+    const double area = (x1 - x0) * (y1 - y0);
+    if (!(area > 0.0)) return;
+    const double lamR = g.lambda * area / (g.Lx * g.Ly);
+    const double log_lamR = log(lamR), log_pb = log(g.pb), log_pd = log(g.pd);
+
+    const long long base = ((long long)chain * g.R + r) * g.cap;
+    const long long ebase = (long long)chain * g.nsta * (long long)g.N;
+    int n = ev.cnt[chain * g.R + r];
+    for (int s = tid; s < n; s += BLOCK) {
+        s_ex[s] = ev.x[base + s]; s_ey[s] = ev.y[base + s];
+        s_et[s] = ev.t[base + s]; s_em[s] = ev.m[base + s];
+        s_id[s] = ev.id[base + s];
+    }
+    for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-2.0 * (double)q / g.decay);
+
+    const bool use_feed = feed != nullptr && chain == 0;
+    const bool use_log = logp != nullptr && chain == 0 && sweep >= log_first &&
+                         sweep < log_first + log_n;
+    unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
+                 cnt_acc[5] = {0, 0, 0, 0, 0};
+    unsigned long long samp_read = 0, samp_written = 0;
+    int flags = 0;
+
+    for (int j = 0; j < g.k; ++j) {
+        const int buf = j & 1;
+        const int slot = j % kDrawChunk;
+        if (slot == 0) {
+            __syncthreads();
+            for (int q = tid; q < kDrawChunk && j + q < g.k; q += BLOCK) {
+                if (use_feed) {
+                    const double *row = feed + (((sweep - feed_first) * g.R + r) * g.k + (j + q)) * 8;
+                    for (int c = 0; c < 8; ++c) s_draw[q][c] = row[c];
+                } else {
+                    double d[8];
+                    move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r,
+                               (uint32_t)(j + q), d);
+                    for (int c = 0; c < 8; ++c) s_draw[q][c] = d[c];
+                }
+            }
+            __syncthreads();
+        }
+
+        if (wave == 0) {
+            int type = 0, valid = 0, idx = -1;
+            double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0;
+            if (lane == 0) {
+                const double *d = s_draw[slot];
+                const double u = d[0];
+                type = u < g.c1 ? 0 : u < g.c2 ? 1 : u < g.c3 ? 2 : u < g.c4 ? 3 : 4;
+                if (type == 0) {
+                    if (n >= g.cap) {
+                        flags |= kFlagCap;
+                    } else {
+                        nx = x0 + d[1] * (x1 - x0);
+                        ny = y0 + d[2] * (y1 - y0);
+                        nt = d[3] * (double)g.N;
+                        nm = g.mmin + d[4] / g.mrate;
+                        valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
+                                nt < (double)g.N && region_axis(nx, offx, g.wx, g.gx) == i &&
+                                region_axis(ny, offy, g.wy, g.gy) == kk;
+                    }
+                } else if (n > 0) {
+                    idx = (int)floor(d[1] * (double)n);
+                    if (idx >= n) idx = n - 1;
+                    ox = s_ex[idx]; oy = s_ey[idx]; ot = s_et[idx]; om = s_em[idx];
+                    nx = ox; ny = oy; nt = ot; nm = om;
+                    valid = 1;
+                    if (type == 2) {
+                        nx = ox + g.sxy * d[5];
+                        ny = oy + g.sxy * d[6];
+                        valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
+                                region_axis(nx, offx, g.wx, g.gx) == i &&
+                                region_axis(ny, offy, g.wy, g.gy) == kk;
+                    } else if (type == 3) {
+                        nt = ot + g.st * d[5];
+                        valid = nt >= 0.0 && nt < (double)g.N;
+                    } else if (type == 4) {
+                        nm = om + g.sm * d[5];
+                        valid = nm >= g.mmin;
+                    }
+                }
+            }
+            type = __shfl(type, 0, 64);
+            valid = __shfl(valid, 0, 64);
+            int nseg = 0, S = 0;
+            if (valid && !g.prior_only) {
+                ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
+                ot = __shfl(ot, 0, 64); om = __shfl(om, 0, 64);
+                nx = __shfl(nx, 0, 64); ny = __shfl(ny, 0, 64);
+                nt = __shfl(nt, 0, 64); nm = __shfl(nm, 0, 64);
+                int fl = 0;
+                footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm,
+                          s_seg[buf], &nseg, &S, &fl);
+                const bool bad = __ballot(fl != 0) != 0ull || S > MAXQ * BLOCK;
+                if (bad) {
+                    valid = 0;
+                    if (lane == 0) flags |= kFlagSeg;
+                }
+            }
+            if (lane == 0) {
+                MoveHdr h;
+                h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.pad = 0;
+                h.dm = nm - om;
+                s_hdr[buf] = h;
+                // remember the proposal for the update
+                s_draw[slot][0] = nx; s_draw[slot][1] = ny; s_draw[slot][2] = nt;
+                s_draw[slot][3] = nm; s_draw[slot][4] = (double)idx;
+            }
+        }
+        __syncthreads();
+        const MoveHdr h = s_hdr[buf];
+        const double lnu = s_draw[slot][7];
+        if (!h.valid) {
+            if (tid == 0) {
+                cnt_att[h.type]++;
+                if (use_log) {
+                    double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
+                    lg[0] = (double)h.type; lg[1] = 0.0; lg[2] = 0.0; lg[3] = 0.0;
+                }
+            }
+            continue;
+        }
+
+        double delta = 0.0;
+        double enew[MAXQ];
+        int eidx[MAXQ];  // station * N + sample, or -1
+        if (!g.prior_only) {
+            const Seg *sg = s_seg[buf];
+            double part = 0.0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                const int f = tid + q * BLOCK;
+                eidx[q] = -1;
+                enew[q] = 0.0;
+                if (f < h.S) {
+                    int s = 0;
+                    while (s + 1 < h.nseg && sg[s + 1].pre <= f) ++s;
+                    const Seg &a = sg[s];
+                    const int nn = a.lo + (f - a.pre);
+                    const long long gi = (long long)a.j * g.N + nn;
+                    const double eo = E[ebase + gi];
+                    const double sv = (double)trace[gi];
+                    const double qv = sv * sv;
+                    const double co = (nn >= a.o0 && nn < a.o1) ? a.Bo * s_T[nn - a.o0] : 0.0;
+                    const double cn = (nn >= a.w0 && nn < a.w1) ? a.Bn * s_T[nn - a.w0] : 0.0;
+                    double en = (eo - co) + cn;
+                    en = en > 0.0 ? en : 0.0;
+                    const double de = en - eo;
+                    if (de != 0.0) {
+                        const double v = g.sigma2 + eo;
+                        const double vp = g.sigma2 + en;
+                        part += -0.5 * (log1p(de / v) - qv * de / (v * vp));
+                    }
+                    enew[q] = en;
+                    eidx[q] = (int)gi;
+                }
+            }
+            part = wave_sum(part);
+            if (lane == 0) s_part[buf][wave] = part;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < W; ++w) delta += s_part[buf][w];
+        }
+
+        double la;
+        if (h.type == 0)
+            la = delta + log_lamR + log_pd - log((double)(h.n + 1)) - log_pb;
+        else if (h.type == 1)
+            la = delta + log((double)h.n) + log_pb - log_lamR - log_pd;
+        else if (h.type == 4)
+            la = delta - g.mrate * h.dm;
+        else
+            la = delta;
+        bool accept = lnu < la;
+        if (!(delta == delta) || delta - delta != 0.0) {  // NaN or Inf
+            accept = false;
+            if (tid == 0) flags |= kFlagNan;
+        }
+        if (accept && !g.prior_only) {
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q)
+                if (eidx[q] >= 0) E[ebase + eidx[q]] = enew[q];
+        }
+        if (tid == 0) {
+            cnt_att[h.type]++;
+            cnt_val[h.type]++;
+            samp_read += (unsigned long long)h.S;
+            const double *pr = s_draw[slot];
+            if (accept) {
+                cnt_acc[h.type]++;
+                samp_written += (unsigned long long)h.S;
+                if (h.type == 0) {
+                    s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
+                    s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
+                              ((unsigned long long)r << 12) | (unsigned long long)j;
+                    ++n;
+                } else if (h.type == 1) {
+                    const int idx = (int)pr[4];
+                    for (int q = idx; q + 1 < n; ++q) {
+                        s_ex[q] = s_ex[q + 1]; s_ey[q] = s_ey[q + 1];
+                        s_et[q] = s_et[q + 1]; s_em[q] = s_em[q + 1];
+                        s_id[q] = s_id[q + 1];
+                    }
+                    --n;
+                } else {
+                    const int idx = (int)pr[4];
+                    s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
+                }
+            }
+            if (use_log) {
+                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
+                lg[0] = (double)h.type; lg[1] = accept ? 2.0 : 1.0; lg[2] = delta; lg[3] = la;
+            }
+        }
+    }
+
+    if (tid == 0) s_n = n;
+    __syncthreads();
+    const int nf = s_n;
+    for (int s = tid; s < nf; s += BLOCK) {
+        ev.x[base + s] = s_ex[s]; ev.y[base + s] = s_ey[s];
+        ev.t[base + s] = s_et[s]; ev.m[base + s] = s_em[s];
+        ev.id[base + s] = s_id[s];
+    }
+    if (tid == 0) {
+        ev.cnt[chain * g.R + r] = nf;
+        unsigned long long *st = stats + (long long)chain * kStats;
+        for (int t = 0; t < 5; ++t) {
+            if (cnt_att[t]) atomicAdd(&st[3 * t + 0], (unsigned long long)cnt_att[t]);
+            if (cnt_val[t]) atomicAdd(&st[3 * t + 1], (unsigned long long)cnt_val[t]);
+            if (cnt_acc[t]) atomicAdd(&st[3 * t + 2], (unsigned long long)cnt_acc[t]);
+        }
+        if (samp_read) atomicAdd(&st[15], samp_read);
+        if (samp_written) atomicAdd(&st[16], samp_written);
+        if (flags) atomicOr(err, flags);
+    }
+}
+
+// ------------------------------------------------------------------ rebin
+// Dynamic partition (Section 4.3.2): the sweep's offset comes from Philox;
+// each thread owns one region of the new layout and collects, in id order,
+// the events of the old layout that fall into it.  With both offsets in
+// [0, w) an event's region index moves by at most one per axis, so a 5x5
+// window of old regions is always enough.
+__global__ void k_rebin(Geo g, Events src, Events dst, const long long *__restrict__ sweep_ptr,
+                        int *__restrict__ err)
+{
+    const int chain = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= g.R) return;
+    const long long sweep = *sweep_ptr;
+    double offx, offy;
+    sweep_offset(g.seed, (uint32_t)chain, (uint32_t)sweep, g.wx, g.wy, &offx, &offy);
+    if (r == 0) {
+        dst.off[2 * chain] = offx;
+        dst.off[2 * chain + 1] = offy;
+    }
+    const int i = r % g.nrx, k = r / g.nrx;
+    const long long dbase = ((long long)chain * g.R + r) * g.cap;
+    int n = 0;
+    for (int ko = max(k - 2, 0); ko <= min(k + 2, g.gy); ++ko) {
+        for (int io = max(i - 2, 0); io <= min(i + 2, g.gx); ++io) {
+            const int ro = ko * g.nrx + io;
+            const long long sbase = ((long long)chain * g.R + ro) * g.cap;
+            const int no = src.cnt[chain * g.R + ro];
+            for (int s = 0; s < no; ++s) {
+                const double x = src.x[sbase + s], y = src.y[sbase + s];
+                if (region_axis(x, offx, g.wx, g.gx) != i || region_axis(y, offy, g.wy, g.gy) != k)
+                    continue;
+                if (n >= g.cap) {
+                    atomicOr(err, kFlagCap);
+                    continue;
+                }
+                const unsigned long long id = src.id[sbase + s];
+                int pos = n;
+                while (pos > 0 && dst.id[dbase + pos - 1] > id) {
+                    dst.x[dbase + pos] = dst.x[dbase + pos - 1];
+                    dst.y[dbase + pos] = dst.y[dbase + pos - 1];
+                    dst.t[dbase + pos] = dst.t[dbase + pos - 1];
+                    dst.m[dbase + pos] = dst.m[dbase + pos - 1];
+                    dst.id[dbase + pos] = dst.id[dbase + pos - 1];
+                    --pos;
+                }
+                dst.x[dbase + pos] = x;
+                dst.y[dbase + pos] = y;
+                dst.t[dbase + pos] = src.t[sbase + s];
+                dst.m[dbase + pos] = src.m[sbase + s];
+                dst.id[dbase + pos] = id;
+                ++n;
+            }
+        }
+    }
+    dst.cnt[chain * g.R + r] = n;
+}
+
+// ------------------------------------------------------- refresh / loglik
+// Gathers, for one station and one tile of kTile samples, every event of the
+// table that reaches the station with a window meeting the tile (regions in
+// index order, slots in id order), into LDS as (first sample, scale).
+__device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int n_lo, int n_hi,
+                           int *s_n0, double *s_B, int *s_cnt, int *flags)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid == 0) *s_cnt = 0;
+    __syncthreads();
+    if (tid < 64) {
+        const int ix = j % g.nsx, iy = j / g.nsx;
+        const double sx = station_pos(ix, g.ds), sy = station_pos(iy, g.ds);
+        const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
+        const int i0 = region_axis(sx - g.rc, offx, g.wx, g.gx);
+        const int i1 = region_axis(sx + g.rc, offx, g.wx, g.gx);
+        const int k0 = region_axis(sy - g.rc, offy, g.wy, g.gy);
+        const int k1 = region_axis(sy + g.rc, offy, g.wy, g.gy);
+        int count = 0;
+        for (int kk = k0; kk <= k1; ++kk) {
+            for (int ii = i0; ii <= i1; ++ii) {
+                const int r = kk * g.nrx + ii;
+                const int nr = ev.cnt[chain * g.R + r];
+                const long long base = ((long long)chain * g.R + r) * g.cap;
+                for (int s0 = 0; s0 < nr; s0 += 64) {
+                    const int s = s0 + lane;
+                    bool take = false;
+                    Arrival ar;
+                    ar.in = 0;
+                    if (s < nr) {
+                        ar = arrive(g, ev.x[base + s], ev.y[base + s], ev.t[base + s],
+                                    ev.m[base + s], ix, iy);
+                        take = ar.in && ar.n0 < n_hi && ar.n1 > n_lo;
+                    }
+                    const unsigned long long mask = __ballot(take);
+                    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                    if (take) {
+                        const int pos = count + before;
+                        if (pos < kMaxTileEvents) {
+                            s_n0[pos] = ar.n0;
+                            s_B[pos] = ar.B;
+                        } else {
+                            *flags |= kFlagTile;
+                        }
+                    }
+                    count += __popcll(mask);
+                }
+            }
+        }
+        if (lane == 0) *s_cnt = count < kMaxTileEvents ? count : kMaxTileEvents;
+    }
+    __syncthreads();
+    return *s_cnt;
+}
+
+// Exact event variance for every chain, station and sample, optionally
+// written to E, and per-workgroup partial sums of the signal log-likelihood
+// (Section 3: zero-mean Gaussian with variance sigma^2 plus the arriving
+// signals' variances).  One workgroup per (station, tile), blockIdx.y chain.
+template <typename TraceT>
+__global__ void __launch_bounds__(256)
+k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E, int write,
+          double *__restrict__ partials, int chain0, int *__restrict__ err)
+{
+    __shared__ int s_n0[kMaxTileEvents];
+    __shared__ double s_B[kMaxTileEvents];
+    __shared__ double s_T[kMaxTs];
+    __shared__ double s_part[4];
+    __shared__ int s_cnt;
+    const int tiles = (g.N + kTile - 1) / kTile;
+    const int j = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const int chain = chain0 + blockIdx.y;
+    const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
+    const int tid = threadIdx.x;
+    int flags = 0;
+    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    const int ne = gather_tile(g, ev, chain, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
+    const double l2pi = log(2.0 * M_PI);
+    const double null_c = -0.5 * (l2pi + log(g.sigma2));
+    const double null_q = -0.5 / g.sigma2;
+    const long long row = (long long)j * g.N;
+    double *Erow = E + (long long)chain * g.nsta * (long long)g.N + row;
+    double acc = 0.0;
+    for (int nn = n_lo + tid; nn < n_hi; nn += 256) {
+        double e = 0.0;
+        for (int q = 0; q < ne; ++q) {
+            const int d = nn - s_n0[q];
+            if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+        }
+        const double sv = (double)trace[row + nn];
+        const double qv = sv * sv;
+        if (e > 0.0) {
+            const double v = g.sigma2 + e;
+            acc += -0.5 * (l2pi + log(v) + qv / v);
+        } else {
+            acc += null_c + null_q * qv;
+        }
+        if (write) Erow[nn] = e;
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) s_part[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        partials[(long long)blockIdx.y * gridDim.x + blockIdx.x] =
+            ((s_part[0] + s_part[1]) + s_part[2]) + s_part[3];
+        if (flags) atomicOr(err, flags);
+    }
+}
+
+// Sums each chain's partials in a fixed order (deterministic result).
+__global__ void __launch_bounds__(256)
+k_sum_partials(const double *__restrict__ partials, int per_chain, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    const double *p = partials + (long long)blockIdx.x * per_chain;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < per_chain; q += 256) acc += p[q];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+// ----------------------------------------------------------------- simulate
+// trace[j][n] = sqrt(sigma^2 + E_j[n]) z_jn, z from Philox under key
+// (seed, 0x80000001), counter (n / 2, j, 0, 0), Box-Muller (even n cosine,
+// odd n sine).  E gathered from the truth events binned like an event table.
+template <typename TraceT>
+__global__ void __launch_bounds__(256)
+k_simulate(Geo g, Events ev, uint32_t seed, TraceT *__restrict__ trace, int *__restrict__ err)
+{
+    __shared__ int s_n0[kMaxTileEvents];
+    __shared__ double s_B[kMaxTileEvents];
+    __shared__ double s_T[kMaxTs];
+    __shared__ int s_cnt;
+    const int tiles = (g.N + kTile - 1) / kTile;
+    const int j = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
+    const int tid = threadIdx.x;
+    int flags = 0;
+    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    const int ne = gather_tile(g, ev, 0, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
+    const long long row = (long long)j * g.N;
+    for (int n2 = n_lo + 2 * tid; n2 < n_hi; n2 += 512) {
+        uint32_t c[4] = {(uint32_t)(n2 >> 1), (uint32_t)j, 0u, 0u};
+        philox10(c, seed, 0x80000001u);
+        const double u1 = unit_open(c[0], c[1]);
+        const double u2 = unit_open(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double ang = 2.0 * M_PI * u2;
+        const double z[2] = {rad * cos(ang), rad * sin(ang)};
+        for (int h = 0; h < 2; ++h) {
+            const int nn = n2 + h;
+            if (nn >= n_hi) break;
+            double e = 0.0;
+            for (int q = 0; q < ne; ++q) {
+                const int d = nn - s_n0[q];
+                if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+            }
+            trace[row + nn] = (TraceT)(sqrt(g.sigma2 + e) * z[h]);
+        }
+    }
+    if (tid == 0 && flags) atomicOr(err, flags);
+}
+
+// --------------------------------------------------------------- utilities
+__global__ void k_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                        uint32_t j0, int count, double *__restrict__ out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    double d[8];
+    move_draws(seed, chain, sweep, region, j0 + (uint32_t)q, d);
+    for (int c = 0; c < 8; ++c) out[(long long)q * 8 + c] = d[c];
+}
+
+__global__ void k_fill_f64(double *__restrict__ p, long long n, double v)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+__global__ void k_fill_i32(int *__restrict__ p, long long n, int v)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *__restrict__ p, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = 0ull;
+}
+
+__global__ void k_set_sweep(long long *p, long long v) { *p = v; }
+__global__ void k_advance_sweep(long long *p) { *p += 1; }
+
+// ------------------------------------------------------------- launchers
+template <typename TraceT>
+static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *trace, double *E,
+                                 int color, const long long *sweep_ptr, const double *feed,
+                                 long long feed_first, double *logp, long long log_first,
+                                 long long log_n, unsigned long long *stats, int *err, int block,
+                                 int chains, hipStream_t s)
+{
+    const int p = g.period;
+    const int ci = color % p, ck = color / p;
+    const int ni = (g.nrx - ci + p - 1) / p, nk = (g.nry - ck + p - 1) / p;
+    const dim3 grid(ni * nk, chains);
+    const TraceT *tr = (const TraceT *)trace;
+    switch (block) {
+    case 64:
+        k_sweep_color<TraceT, 64><<<grid, 64, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
+                                                       feed_first, logp, log_first, log_n,
+                                                       stats, err);
+        break;
+    case 128:
+        k_sweep_color<TraceT, 128><<<grid, 128, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
+                                                         feed_first, logp, log_first, log_n,
+                                                         stats, err);
+        break;
+    default:
+        k_sweep_color<TraceT, 256><<<grid, 256, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
+                                                         feed_first, logp, log_first, log_n,
+                                                         stats, err);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
+                        int color, const long long *sweep_ptr, const double *feed,
+                        long long feed_first, double *logp, long long log_first, long long log_n,
+                        unsigned long long *stats, int *err, int block, int chains, hipStream_t s)
+{
+    if (f64)
+        return launch_sweep_t<double>(g, ev, trace, E, color, sweep_ptr, feed, feed_first, logp,
+                                      log_first, log_n, stats, err, block, chains, s);
+    return launch_sweep_t<float>(g, ev, trace, E, color, sweep_ptr, feed, feed_first, logp,
+                                 log_first, log_n, stats, err, block, chains, s);
+}
+
+hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
+                        const long long *sweep_ptr, int *err, int chains, hipStream_t s)
+{
+    const dim3 grid((g.R + 127) / 128, chains);
+    k_rebin<<<grid, 128, 0, s>>>(g, src, dst, sweep_ptr, err);
+    return hipGetLastError();
+}
+
+int refresh_blocks(const Geo &g) { return g.nsta * ((g.N + kTile - 1) / kTile); }
+
+hipError_t launch_refresh(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
+                          int write, double *partials, double *out, int chain0, int nchains,
+                          int *err, hipStream_t s)
+{
+    const int per = refresh_blocks(g);
+    const dim3 grid(per, nchains);
+    if (f64)
+        k_refresh<double><<<grid, 256, 0, s>>>(g, ev, (const double *)trace, E, write, partials,
+                                               chain0, err);
+    else
+        k_refresh<float><<<grid, 256, 0, s>>>(g, ev, (const float *)trace, E, write, partials,
+                                              chain0, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || out == nullptr) return e;
+    k_sum_partials<<<nchains, 256, 0, s>>>(partials, per, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_simulate(const Geo &g, const Events &ev, uint32_t seed, void *trace, int f64,
+                           int *err, hipStream_t s)
+{
+    const int per = refresh_blocks(g);
+    if (f64)
+        k_simulate<double><<<per, 256, 0, s>>>(g, ev, seed, (double *)trace, err);
+    else
+        k_simulate<float><<<per, 256, 0, s>>>(g, ev, seed, (float *)trace, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                        uint32_t j0, int count, double *out, hipStream_t s)
+{
+    k_draws<<<(count + 127) / 128, 128, 0, s>>>(seed, chain, sweep, region, j0, count, out);
+    return hipGetLastError();
+}
+
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    k_fill_f64<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    k_fill_i32<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t fill_u64(unsigned long long *p, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    k_fill_u64<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t set_sweep(long long *p, long long v, hipStream_t s)
+{
+    k_set_sweep<<<1, 1, 0, s>>>(p, v);
+    return hipGetLastError();
+}
+
+hipError_t advance_sweep(long long *p, hipStream_t s)
+{
+    k_advance_sweep<<<1, 1, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+}  // namespace cmh

@@ -1,0 +1,28 @@
+// cmh_kernels.hpp -- host-side launchers of the device kernels.
+#pragma once
+
+#include "cmh_common.hpp"
+
+namespace cmh {
+
+hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
+                        int color, const long long *sweep_ptr, const double *feed,
+                        long long feed_first, double *logp, long long log_first, long long log_n,
+                        unsigned long long *stats, int *err, int block, int chains, hipStream_t s);
+hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
+                        const long long *sweep_ptr, int *err, int chains, hipStream_t s);
+int refresh_blocks(const Geo &g);
+hipError_t launch_refresh(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
+                          int write, double *partials, double *out, int chain0, int nchains,
+                          int *err, hipStream_t s);
+hipError_t launch_simulate(const Geo &g, const Events &ev, uint32_t seed, void *trace, int f64,
+                           int *err, hipStream_t s);
+hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                        uint32_t j0, int count, double *out, hipStream_t s);
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t s);
+hipError_t fill_u64(unsigned long long *p, long long n, hipStream_t s);
+hipError_t set_sweep(long long *p, long long v, hipStream_t s);
+hipError_t advance_sweep(long long *p, hipStream_t s);
+
+}  // namespace cmh

@@ -1,0 +1,80 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the
+header declares, validates arguments on the host, and its partition and
+colouring (a pure host function) agree bit for bit with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1612_00595_amd import chromh, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "chromh.h")).read()
+    return sorted(set(re.findall(r"\b(cmh_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for core in ("cmh_partition_and_color", "cmh_init_state", "cmh_sweep_color",
+                 "cmh_run_sweeps", "cmh_read_events"):
+        assert core in names
+    assert set(names) == set(chromh.EXPORTS)
+
+
+def test_library_loads_and_exports_every_symbol():
+    L = chromh.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_host_validation_errors():
+    L = chromh.lib()
+    m = chromh.model_struct(W.SMALL.model)
+    s = chromh.sampler_struct(W.SMALL.sampler)
+    nbytes = C.c_size_t()
+    assert L.cmh_state_bytes(C.byref(m), C.byref(s), 1, C.byref(nbytes)) == 0
+    assert nbytes.value > 25 * 1000 * 8
+    bad = chromh.model_struct(W.SMALL.model)
+    bad.r_c = 0.25  # must stay below the station spacing
+    assert L.cmh_state_bytes(C.byref(bad), C.byref(s), 1, C.byref(nbytes)) == -1
+    assert b"r_c" in L.cmh_last_error()
+    bad = chromh.sampler_struct(W.SMALL.sampler)
+    bad.p_mag = 0.5  # probabilities no longer sum to one
+    assert L.cmh_state_bytes(C.byref(m), C.byref(bad), 1, C.byref(nbytes)) == -1
+    bad = chromh.sampler_struct(W.SMALL.sampler)
+    bad.region_capacity = 65
+    assert L.cmh_state_bytes(C.byref(m), C.byref(bad), 1, C.byref(nbytes)) == -1
+    bad = chromh.sampler_struct(W.SMALL.sampler)
+    bad.block = 96
+    assert L.cmh_state_bytes(C.byref(m), C.byref(bad), 1, C.byref(nbytes)) == -1
+    assert L.cmh_state_bytes(C.byref(m), C.byref(s), 0, C.byref(nbytes)) == -1
+    # a static period that leaves dependent regions in one colour
+    bad = chromh.sampler_struct(W.SMALL.sampler)
+    bad.period = 1
+    assert L.cmh_state_bytes(C.byref(m), C.byref(bad), 1, C.byref(nbytes)) == -4
+    h = C.c_void_p()
+    assert L.cmh_init_state(C.byref(m), C.byref(s), None, 0, 1, 0, None, 0, None,
+                            C.byref(h)) == -1
+    assert L.cmh_destroy(None) == 0
+
+
+@pytest.mark.parametrize("side,grid,dynamic", [(5, 4, 0), (5, 5, 1), (12, 12, 1), (8, 3, 0),
+                                               (16, 16, 1)])
+def test_partition_matches_oracle(orc, side, grid, dynamic):
+    spec = W.ModelSpec(nsx=side, nsy=side, N=100)
+    om = orc.make_model(**spec.asdict())
+    rng = np.random.default_rng(side * 100 + grid)
+    L = side * 0.2
+    w = L / grid
+    offs = [(0.0, 0.0)] + ([tuple(rng.random(2) * w) for _ in range(25)] if dynamic else [])
+    for ox, oy in offs:
+        got = chromh.partition_and_color(spec, grid, grid, ox, oy, dynamic)
+        rc, *want = orc.partition_and_color(om, grid, grid, ox, oy, dynamic)
+        assert rc == 0
+        assert got[:4] == tuple(want[:4])
+        assert np.array_equal(got[4], want[4])
