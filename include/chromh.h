@@ -90,7 +90,7 @@ typedef struct {
     double  p_birth, p_death, p_loc, p_time, p_mag;   /* sum to 1 */
     double  step_xy, step_t, step_m;                  /* random-walk steps */
     int32_t prior_only;         /* 1: likelihood switched off */
-    int32_t block;              /* threads per workgroup: 64, 128, 256; 0 = tune */
+    int32_t block;              /* threads per workgroup: 128, 256, 512; 0 = default 256 */
 } cmh_sampler;
 
 typedef struct {
@@ -119,7 +119,8 @@ int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t 
 
 /* Workspace bytes for n_chains chains: the per-chain event-variance
  * accumulator (n_stations x n_samples doubles), two event tables of
- * region_capacity slots per region, offsets, statistics and flags. */
+ * region_capacity slots per region, offsets, the sweep's per-move draw
+ * records, statistics and flags. */
 int32_t cmh_state_bytes(const cmh_model *model, const cmh_sampler *sampler,
                         int32_t n_chains, size_t *bytes);
 
@@ -198,7 +199,8 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
 /* Runs sweeps first_sweep .. first_sweep + n_sweeps - 1 like cmh_run_sweeps
  * but launched one kernel at a time, with HIP events recorded on hip_stream
  * around each; ms_out[c] receives the summed milliseconds of colour c's
- * phases and ms_out[n_colors] those of the sweeps' re-layouts.  Synchronises.
+ * phases and ms_out[n_colors] those of the sweeps' starts (re-layout and the
+ * sweep's draw records).  Synchronises.
  * Used for measurement. */
 int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream,
                         float *ms_out);

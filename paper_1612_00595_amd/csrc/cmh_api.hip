@@ -158,8 +158,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (std::fabs(sum - 1.0) > 1e-9) return fail(CMH_EINVAL, "move probabilities must sum to 1");
     if (!(s->step_xy >= 0.0) || !(s->step_t >= 0.0) || !(s->step_m >= 0.0))
         return fail(CMH_EINVAL, "step sizes must be non-negative");
-    if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256)
-        return fail(CMH_EINVAL, "block must be 0, 64, 128 or 256");
+    if (s->block != 0 && s->block != 128 && s->block != 256 && s->block != 512)
+        return fail(CMH_EINVAL, "block must be 0, 128, 256 or 512");
     if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
@@ -186,6 +186,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     g->c2 = g->c1 + g->pd;
     g->c3 = g->c2 + g->ploc;
     g->c4 = g->c3 + g->pt;
+    g->att2 = 2.0 / g->atten;
+    g->dec2 = 2.0 / g->decay;
     return CMH_OK;
 }
 
@@ -231,6 +233,7 @@ struct cmh_state {
     unsigned long long *stats_snap = nullptr;
     double *partials = nullptr;
     double *llout = nullptr;
+    double *draws = nullptr;  // [chain][region][move][8] for the current sweep
     int block = 256;
     const double *feed = nullptr;
     long long feed_first = 0, feed_n = 0;
@@ -258,7 +261,9 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     unsigned long long *stats_snap = c.take<unsigned long long>((size_t)chains * cmh::kStats);
     double *partials = c.take<double>((size_t)chains * cmh::refresh_blocks(g));
     double *llout = c.take<double>((size_t)chains);
+    double *draws = c.take<double>((size_t)chains * g.R * (size_t)g.k * 8);
     if (st) {
+        st->draws = draws;
         st->E = E;
         st->ev[0] = ev0;
         st->ev[1] = ev1;
@@ -311,20 +316,32 @@ hipError_t copy_events(const Events &dst, const Events &src, const Geo &g, int c
     return hipMemcpyAsync(dst.off, src.off, (size_t)chains * 16, hipMemcpyDeviceToDevice, s);
 }
 
-// Enqueue one colour phase (and, for colour 0 of a shifted partition, the
-// sweep's re-layout) reading the sweep index from the device counter.
-hipError_t enqueue_phase(cmh_state *st, int color, bool relayout, hipStream_t s)
+// Enqueue the start of a sweep: the re-layout of a shifted partition and
+// the draw records of every move of the sweep.
+hipError_t enqueue_sweep_start(cmh_state *st, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    if (relayout && st->g.dynamic) {
+    if (st->g.dynamic) {
         e = cmh::launch_rebin(st->g, st->ev[st->cur], st->ev[st->cur ^ 1], st->sweep_ctr, st->err,
                               st->chains, s);
         if (e) return e;
         st->cur ^= 1;
     }
+    return cmh::launch_sweep_draws(st->g, st->sweep_ctr, st->feed, st->feed_first, st->draws,
+                                   st->chains, s);
+}
+
+// Enqueue one colour phase (colour 0 first starts the sweep), reading the
+// sweep index from the device counter.
+hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
+{
+    if (start) {
+        hipError_t e = enqueue_sweep_start(st, s);
+        if (e) return e;
+    }
     return cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
-                             st->sweep_ctr, st->feed, st->feed_first, st->logp, st->log_first,
-                             st->log_n, st->stats, st->err, st->block, st->chains, s);
+                             st->sweep_ctr, st->draws, st->logp, st->log_first, st->log_n,
+                             st->stats, st->err, st->block, st->chains, s);
 }
 
 void drop_graphs(cmh_state *st)
@@ -706,7 +723,7 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const int cands[3] = {64, 128, 256};
+    const int cands[3] = {128, 256, 512};
     int best = st->block;
     float best_ms = 1e30f;
     for (int b : cands) {
@@ -762,11 +779,7 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
         hipEvent_t *E = &ev[(size_t)q * (nc + 2)];
         e = cmh::set_sweep(st->sweep_ctr, first_sweep + q, s);
         if (!e) e = hipEventRecord(E[0], s);
-        if (!e && st->g.dynamic) {
-            e = cmh::launch_rebin(st->g, st->ev[st->cur], st->ev[st->cur ^ 1], st->sweep_ctr,
-                                  st->err, st->chains, s);
-            st->cur ^= 1;
-        }
+        if (!e) e = enqueue_sweep_start(st, s);
         if (!e) e = hipEventRecord(E[1], s);
         for (int c = 0; c < nc && !e; ++c) {
             e = enqueue_phase(st, c, false, s);
@@ -821,6 +834,7 @@ int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, 
     g.R = g.nrx * g.nry;
     g.ds = model->ds; g.sigma2 = model->sigma * model->sigma; g.atten = model->atten;
     g.vel = model->velocity; g.decay = model->env_decay; g.rc = model->r_c;
+    g.att2 = 2.0 / g.atten; g.dec2 = 2.0 / g.decay;
     g.Lx = (double)model->nsx * model->ds; g.Ly = (double)model->nsy * model->ds;
     g.wx = g.Lx / (double)g.gx; g.wy = g.Ly / (double)g.gy;
     L->cells.assign(g.R, {});

@@ -37,6 +37,7 @@ struct Geo {
     double wx, wy;
     double pb, pd, ploc, pt, pm, sxy, st, sm;
     double c1, c2, c3, c4;  // cumulative move-type thresholds
+    double att2, dec2;      // 2 / atten, 2 / decay
 };
 
 // Region-slot event table for all chains.  Slot s of region r of chain c is
@@ -136,8 +137,8 @@ __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, dou
     if (d < g.rc && c < (double)g.N) {
         ar.n0 = (int)c;
         ar.n1 = ar.n0 + g.ts < g.N ? ar.n0 + g.ts : g.N;
-        const double amp = m * exp(-d / g.atten);
-        ar.B = amp * amp * exp(-2.0 * (c - a) / g.decay);
+        // A^2 exp(-2 (c - a) / decay) with A = m exp(-d / atten), one exponential
+        ar.B = m * m * exp(-(g.att2 * d + g.dec2 * (c - a)));
         ar.in = 1;
     }
     return ar;

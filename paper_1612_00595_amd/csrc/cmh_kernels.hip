@@ -52,27 +52,42 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// One run of affected samples at one station: samples [lo, lo + len),
-// flat positions [pre, pre + len); the old event's window [o0, o1) with
-// scale Bo and the new event's window [w0, w1) with scale Bn.
+// One run of affected samples at one station: samples [lo, lo + len); the
+// old event's window [o0, o1) with scale Bo and the new event's window
+// [w0, w1) with scale Bn.  Runs are laid end to end in flat positions in
+// their order in the table.
 struct Seg {
-    int j, lo, len, pre;
+    int j, lo, len, pad;
     int o0, o1, w0, w1;
     double Bo, Bn;
 };
 
 struct MoveHdr {
-    int valid, type, n, nseg, S, pad;
+    int valid, type, n, nseg;
     double dm;  // magnitude change (magnitude move)
 };
 
+// x lies in region index `want` of one axis.  Points further than 1e-9 w
+// from both edges of the region's interval are decided by comparison (the
+// floor in region_axis cannot differ there); the rest by region_axis itself.
+__device__ inline bool in_region_axis(double x, double lo, double hi, double off, double w, int g,
+                                      int want)
+{
+    const double eps = 1e-9 * w;
+    if (x > lo + eps && x < hi - eps) return true;
+    return region_axis(x, off, w, g) == want;
+}
+
 // Footprint of a move, computed by the 64 lanes of wave 0: every station
 // within the detection cutoff of the old or the new event, with the union of
-// their sample windows.  Lanes scan a box of candidate stations (the cells
-// around both events); a wave prefix sum places each lane's segments.
+// their sample windows.  Candidate stations are the cells around both events;
+// lanes 0-31 evaluate the old event's arrival at candidate `lane`, lanes
+// 32-63 the new event's at candidate `lane - 32`, so the two arrival
+// computations run side by side.  A wave prefix sum then places each
+// candidate's one or two sample runs.
 __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
                           double om, bool has_new, double nx, double ny, double nt, double nm,
-                          Seg *segs, int *nseg_out, int *S_out, int *flags)
+                          Seg *segs, int *nseg_out, int *flags)
 {
     int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
     if (has_old) {
@@ -87,92 +102,98 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
     cx1 = min(cx1 + 1, g.nsx - 1); cy1 = min(cy1 + 1, g.nsy - 1);
     const int bw = cx1 - cx0 + 1;
     const int nbox = bw * (cy1 - cy0 + 1);
+    const int half = lane >> 5, hl = lane & 31;
+    const bool mine = half == 0 ? has_old : has_new;
+    const double ex = half ? nx : ox, ey = half ? ny : oy, et = half ? nt : ot,
+                 em = half ? nm : om;
     int seg_base = 0, samp_base = 0;
-    for (int c0 = 0; c0 < nbox; c0 += 64) {
-        const int cidx = c0 + lane;
-        int ns = 0, nsamp = 0;
-        Seg a, b;
+    (void)samp_base;
+    for (int c0 = 0; c0 < nbox; c0 += 32) {
+        const int cidx = c0 + hl;
+        Arrival ar;
+        ar.in = 0; ar.n0 = 0; ar.n1 = 0; ar.B = 0.0;
+        int ix = 0, iy = 0;
         if (cidx < nbox) {
-            const int ix = cx0 + cidx % bw, iy = cy0 + cidx / bw;
-            Arrival ao, an;
-            ao.in = 0; ao.n0 = 0; ao.n1 = 0; ao.B = 0.0;
-            an = ao;
-            if (has_old) ao = arrive(g, ox, oy, ot, om, ix, iy);
-            if (has_new) an = arrive(g, nx, ny, nt, nm, ix, iy);
+            ix = cx0 + cidx % bw;
+            iy = cy0 + cidx / bw;
+            if (mine) ar = arrive(g, ex, ey, et, em, ix, iy);
+        }
+        // lanes 0-31 take the new event's arrival from their partner lane
+        Arrival an;
+        an.in = __shfl(ar.in, hl + 32, 64);
+        an.n0 = __shfl(ar.n0, hl + 32, 64);
+        an.n1 = __shfl(ar.n1, hl + 32, 64);
+        an.B = __shfl(ar.B, hl + 32, 64);
+        const Arrival ao = ar;
+        int ns = 0, nsamp = 0;
+        Seg sa, sb;
+        if (half == 0 && cidx < nbox && (ao.in || an.in)) {
             const int j = iy * g.nsx + ix;
-            a.j = j; b.j = j;
-            a.o0 = ao.in ? ao.n0 : 0; a.o1 = ao.in ? ao.n1 : 0;
-            a.w0 = an.in ? an.n0 : 0; a.w1 = an.in ? an.n1 : 0;
-            a.Bo = ao.B; a.Bn = an.B;
-            b = a;
+            sa.j = j;
+            sa.o0 = ao.in ? ao.n0 : 0; sa.o1 = ao.in ? ao.n1 : 0;
+            sa.w0 = an.in ? an.n0 : 0; sa.w1 = an.in ? an.n1 : 0;
+            sa.Bo = ao.B; sa.Bn = an.B;
+            sb = sa;
             if (ao.in && an.in) {
-                const int lo = max(ao.n0, an.n0), hi = min(ao.n1, an.n1);
-                if (lo <= hi) {  // overlapping or touching windows: one run
-                    a.lo = min(ao.n0, an.n0);
-                    a.len = max(ao.n1, an.n1) - a.lo;
+                if (max(ao.n0, an.n0) <= min(ao.n1, an.n1)) {  // overlapping or touching
+                    sa.lo = min(ao.n0, an.n0);
+                    sa.len = max(ao.n1, an.n1) - sa.lo;
                     ns = 1;
-                } else {         // disjoint windows: two runs, in sample order
-                    a.lo = min(ao.n0, an.n0);
-                    a.len = (ao.n0 < an.n0 ? ao.n1 : an.n1) - a.lo;
-                    b.lo = max(ao.n0, an.n0);
-                    b.len = (ao.n0 < an.n0 ? an.n1 : ao.n1) - b.lo;
+                } else {                                         // disjoint, sample order
+                    sa.lo = min(ao.n0, an.n0);
+                    sa.len = (ao.n0 < an.n0 ? ao.n1 : an.n1) - sa.lo;
+                    sb.lo = max(ao.n0, an.n0);
+                    sb.len = (ao.n0 < an.n0 ? an.n1 : ao.n1) - sb.lo;
                     ns = 2;
                 }
             } else if (ao.in) {
-                a.lo = ao.n0; a.len = ao.n1 - ao.n0; ns = 1;
-            } else if (an.in) {
-                a.lo = an.n0; a.len = an.n1 - an.n0; ns = 1;
+                sa.lo = ao.n0; sa.len = ao.n1 - ao.n0; ns = 1;
+            } else {
+                sa.lo = an.n0; sa.len = an.n1 - an.n0; ns = 1;
             }
-            nsamp = (ns >= 1 ? a.len : 0) + (ns == 2 ? b.len : 0);
+            nsamp = sa.len + (ns == 2 ? sb.len : 0);
         }
-        int cs = ns, css = nsamp;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t1 = __shfl_up(cs, o, 64);
-            const int t2 = __shfl_up(css, o, 64);
-            if (lane >= o) { cs += t1; css += t2; }
-        }
-        const int sbase = seg_base + cs - ns;
-        const int pbase = samp_base + css - nsamp;
+        const unsigned long long m1 = __ballot(ns >= 1), m2 = __ballot(ns == 2);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int sbase = seg_base + __popcll(m1 & below) + __popcll(m2 & below);
         if (ns >= 1) {
             if (sbase + ns <= kMaxSeg) {
-                a.pre = pbase;
-                segs[sbase] = a;
-                if (ns == 2) {
-                    b.pre = pbase + a.len;
-                    segs[sbase + 1] = b;
-                }
+                segs[sbase] = sa;
+                if (ns == 2) segs[sbase + 1] = sb;
             } else {
                 *flags |= kFlagSeg;
             }
         }
-        seg_base += __shfl(cs, 63, 64);
-        samp_base += __shfl(css, 63, 64);
+        seg_base += __popcll(m1) + __popcll(m2);
+        samp_base += 0;
+        (void)nsamp;
     }
     *nseg_out = seg_base;
-    *S_out = samp_base;
 }
 
 // ------------------------------------------------------------ sweep colour
 // One workgroup per region of colour `color` (blockIdx.x) and chain
-// (blockIdx.y).  The region's events are staged in LDS; wave 0 lane 0 draws
-// and builds each proposal, wave 0 finds its footprint, every thread
-// evaluates the log-likelihood change on a strided share of the footprint
-// samples, and on acceptance writes the updated event variance in place.
-// The event variance E of other regions is read but never written: the
+// (blockIdx.y).  The region's events and the k moves' draws are staged in
+// LDS; wave 0 lane 0 builds each proposal, wave 0 finds its footprint, and
+// every thread evaluates the log-likelihood change on a strided share of the
+// footprint samples (all loads issued before any arithmetic; one division per
+// sample and one logarithm per thread, of the product of the variance
+// ratios).  On acceptance the threads write the updated event variance in
+// place.  The event variance of other regions is read but never written: the
 // colouring guarantees that no station is reached from two regions of one
-// colour (Section 4.1's Markov-blanket argument).
+// colour (the Markov-blanket argument of Section 4.1).
 template <typename TraceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E,
-              int color, const long long *__restrict__ sweep_ptr, const double *__restrict__ feed,
-              long long feed_first, double *__restrict__ logp, long long log_first,
-              long long log_n, unsigned long long *__restrict__ stats, int *__restrict__ err)
+              int color, const long long *__restrict__ sweep_ptr, const double *__restrict__ draws,
+              double *__restrict__ logp, long long log_first, long long log_n,
+              unsigned long long *__restrict__ stats, int *__restrict__ err)
 {
     constexpr int W = BLOCK / 64;
     constexpr int MAXQ = kMaxFootprint / BLOCK;
     __shared__ double s_draw[kDrawChunk][8];
     __shared__ double s_T[kMaxTs];
+    __shared__ double s_log[kMaxCap + 2];  // s_log[q] = log(q)
     __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
     __shared__ unsigned long long s_id[kMaxCap];
     __shared__ Seg s_seg[2][kMaxSeg];
@@ -202,6 +223,7 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
 
     const long long base = ((long long)chain * g.R + r) * g.cap;
     const long long ebase = (long long)chain * g.nsta * (long long)g.N;
+    const double *dsrc = draws + ((long long)chain * g.R + r) * (long long)g.k * 8;
     int n = ev.cnt[chain * g.R + r];
     for (int s = tid; s < n; s += BLOCK) {
         s_ex[s] = ev.x[base + s]; s_ey[s] = ev.y[base + s];
@@ -209,8 +231,8 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         s_id[s] = ev.id[base + s];
     }
     for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
 
-    const bool use_feed = feed != nullptr && chain == 0;
     const bool use_log = logp != nullptr && chain == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
     unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
@@ -223,17 +245,8 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         const int slot = j % kDrawChunk;
         if (slot == 0) {
             __syncthreads();
-            for (int q = tid; q < kDrawChunk && j + q < g.k; q += BLOCK) {
-                if (use_feed) {
-                    const double *row = feed + (((sweep - feed_first) * g.R + r) * g.k + (j + q)) * 8;
-                    for (int c = 0; c < 8; ++c) s_draw[q][c] = row[c];
-                } else {
-                    double d[8];
-                    move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r,
-                               (uint32_t)(j + q), d);
-                    for (int c = 0; c < 8; ++c) s_draw[q][c] = d[c];
-                }
-            }
+            const int m = min(kDrawChunk, g.k - j) * 8;
+            for (int q = tid; q < m; q += BLOCK) s_draw[q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
             __syncthreads();
         }
 
@@ -253,8 +266,9 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                         nt = d[3] * (double)g.N;
                         nm = g.mmin + d[4] / g.mrate;
                         valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
-                                nt < (double)g.N && region_axis(nx, offx, g.wx, g.gx) == i &&
-                                region_axis(ny, offy, g.wy, g.gy) == kk;
+                                nt < (double)g.N &&
+                                in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
+                                in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
                     }
                 } else if (n > 0) {
                     idx = (int)floor(d[1] * (double)n);
@@ -266,8 +280,8 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                         nx = ox + g.sxy * d[5];
                         ny = oy + g.sxy * d[6];
                         valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
-                                region_axis(nx, offx, g.wx, g.gx) == i &&
-                                region_axis(ny, offy, g.wy, g.gy) == kk;
+                                in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
+                                in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
                     } else if (type == 3) {
                         nt = ot + g.st * d[5];
                         valid = nt >= 0.0 && nt < (double)g.N;
@@ -279,7 +293,7 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             }
             type = __shfl(type, 0, 64);
             valid = __shfl(valid, 0, 64);
-            int nseg = 0, S = 0;
+            int nseg = 0;
             if (valid && !g.prior_only) {
                 ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
                 ot = __shfl(ot, 0, 64); om = __shfl(om, 0, 64);
@@ -287,19 +301,18 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                 nt = __shfl(nt, 0, 64); nm = __shfl(nm, 0, 64);
                 int fl = 0;
                 footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm,
-                          s_seg[buf], &nseg, &S, &fl);
-                const bool bad = __ballot(fl != 0) != 0ull || S > MAXQ * BLOCK;
-                if (bad) {
+                          s_seg[buf], &nseg, &fl);
+                if (__ballot(fl != 0) != 0ull) {
                     valid = 0;
                     if (lane == 0) flags |= kFlagSeg;
                 }
             }
             if (lane == 0) {
                 MoveHdr h;
-                h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.pad = 0;
+                h.valid = valid; h.type = type; h.n = n; h.nseg = nseg;
                 h.dm = nm - om;
                 s_hdr[buf] = h;
-                // remember the proposal for the update
+                // keep the proposal for the update
                 s_draw[slot][0] = nx; s_draw[slot][1] = ny; s_draw[slot][2] = nt;
                 s_draw[slot][3] = nm; s_draw[slot][4] = (double)idx;
             }
@@ -307,7 +320,32 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         __syncthreads();
         const MoveHdr h = s_hdr[buf];
         const double lnu = s_draw[slot][7];
-        if (!h.valid) {
+
+        double delta = 0.0;
+        double enew[MAXQ];
+        int gidx[MAXQ];  // station * N + sample of this thread's samples, or -1
+        int S = 0;
+        bool valid = h.valid != 0;
+        int sidx[MAXQ], sbeg[MAXQ];  // run holding flat position f, and its start
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) { sidx[q] = 0; sbeg[q] = 0; }
+        if (valid && !g.prior_only) {
+            const Seg *sg = s_seg[buf];
+            for (int t = 0; t < h.nseg; ++t) {
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q) {
+                    const bool here = tid + q * BLOCK >= S;
+                    sidx[q] = here ? t : sidx[q];
+                    sbeg[q] = here ? S : sbeg[q];
+                }
+                S += sg[t].len;
+            }
+            if (S > MAXQ * BLOCK) {  // cannot happen for t_s <= kMaxTs; kept as a guard
+                valid = false;
+                if (tid == 0) flags |= kFlagSeg;
+            }
+        }
+        if (!valid) {
             if (tid == 0) {
                 cnt_att[h.type]++;
                 if (use_log) {
@@ -317,41 +355,56 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             }
             continue;
         }
-
-        double delta = 0.0;
-        double enew[MAXQ];
-        int eidx[MAXQ];  // station * N + sample, or -1
         if (!g.prior_only) {
             const Seg *sg = s_seg[buf];
-            double part = 0.0;
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
                 const int f = tid + q * BLOCK;
-                eidx[q] = -1;
-                enew[q] = 0.0;
-                if (f < h.S) {
-                    int s = 0;
-                    while (s + 1 < h.nseg && sg[s + 1].pre <= f) ++s;
-                    const Seg &a = sg[s];
-                    const int nn = a.lo + (f - a.pre);
-                    const long long gi = (long long)a.j * g.N + nn;
-                    const double eo = E[ebase + gi];
-                    const double sv = (double)trace[gi];
-                    const double qv = sv * sv;
-                    const double co = (nn >= a.o0 && nn < a.o1) ? a.Bo * s_T[nn - a.o0] : 0.0;
-                    const double cn = (nn >= a.w0 && nn < a.w1) ? a.Bn * s_T[nn - a.w0] : 0.0;
-                    double en = (eo - co) + cn;
-                    en = en > 0.0 ? en : 0.0;
-                    const double de = en - eo;
-                    if (de != 0.0) {
-                        const double v = g.sigma2 + eo;
-                        const double vp = g.sigma2 + en;
-                        part += -0.5 * (log1p(de / v) - qv * de / (v * vp));
-                    }
-                    enew[q] = en;
-                    eidx[q] = (int)gi;
+                gidx[q] = -1;
+                if (f < S) {
+                    const Seg &a = sg[sidx[q]];
+                    gidx[q] = a.j * g.N + a.lo + (f - sbeg[q]);
                 }
             }
+            // load: every sample's variance and trace value in flight at once.
+            // Loads are unconditional (idle slots read element 0) so that no
+            // branch or select separates a load from its issue.
+            double eo[MAXQ], sv[MAXQ];
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                const int gi = gidx[q] >= 0 ? gidx[q] : 0;
+                eo[q] = E[ebase + gi];
+                sv[q] = (double)trace[gi];
+            }
+            // compute: sum of -1/2 [log(v'/v) + s^2 (1/v' - 1/v)], v = sigma^2 + E,
+            // as -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')]; slots beyond the
+            // footprint are skipped by a block-uniform bound
+            double prod = 1.0, lin = 0.0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) {
+                enew[q] = eo[q];
+                if (q * BLOCK < S) {
+                    const bool ok = gidx[q] >= 0;
+                    const Seg &a = sg[sidx[q]];
+                    const int nn = gidx[q] - a.j * g.N;
+                    const bool io = ok && nn >= a.o0 && nn < a.o1;
+                    const bool iw = ok && nn >= a.w0 && nn < a.w1;
+                    const double to = s_T[io ? nn - a.o0 : 0], tw = s_T[iw ? nn - a.w0 : 0];
+                    const double e0 = ok ? eo[q] : 0.0;
+                    const double co = io ? a.Bo * to : 0.0;
+                    const double cn = iw ? a.Bn * tw : 0.0;
+                    double en = (e0 - co) + cn;
+                    en = en > 0.0 ? en : 0.0;
+                    const double de = en - e0;
+                    const double v = g.sigma2 + e0;
+                    const double vp = g.sigma2 + en;
+                    const double inv = 1.0 / (v * vp);
+                    prod *= de != 0.0 ? vp * vp * inv : 1.0;
+                    lin += (ok ? sv[q] * sv[q] : 0.0) * de * inv;
+                    enew[q] = en;
+                }
+            }
+            double part = -0.5 * (log(prod) - lin);
             part = wave_sum(part);
             if (lane == 0) s_part[buf][wave] = part;
             __syncthreads();
@@ -361,9 +414,9 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
 
         double la;
         if (h.type == 0)
-            la = delta + log_lamR + log_pd - log((double)(h.n + 1)) - log_pb;
+            la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb;
         else if (h.type == 1)
-            la = delta + log((double)h.n) + log_pb - log_lamR - log_pd;
+            la = delta + s_log[h.n] + log_pb - log_lamR - log_pd;
         else if (h.type == 4)
             la = delta - g.mrate * h.dm;
         else
@@ -376,16 +429,16 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         if (accept && !g.prior_only) {
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q)
-                if (eidx[q] >= 0) E[ebase + eidx[q]] = enew[q];
+                if (gidx[q] >= 0) E[ebase + gidx[q]] = enew[q];
         }
         if (tid == 0) {
             cnt_att[h.type]++;
             cnt_val[h.type]++;
-            samp_read += (unsigned long long)h.S;
+            samp_read += (unsigned long long)S;
             const double *pr = s_draw[slot];
             if (accept) {
                 cnt_acc[h.type]++;
-                samp_written += (unsigned long long)h.S;
+                samp_written += (unsigned long long)S;
                 if (h.type == 0) {
                     s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
                     s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
@@ -430,6 +483,29 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         if (samp_read) atomicAdd(&st[15], samp_read);
         if (samp_written) atomicAdd(&st[16], samp_written);
         if (flags) atomicOr(err, flags);
+    }
+}
+
+// Every move's draw record for one sweep: [chain][region][move][8], from
+// Philox (or, for chain 0 in replay mode, copied from the caller's feed).
+__global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
+                              const double *__restrict__ feed, long long feed_first,
+                              double *__restrict__ draws)
+{
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int chain = blockIdx.y;
+    const long long per = (long long)g.R * g.k;
+    if (q >= per) return;
+    const long long sweep = *sweep_ptr;
+    double *out = draws + ((long long)chain * per + q) * 8;
+    if (feed != nullptr && chain == 0) {
+        const double *row = feed + ((sweep - feed_first) * per + q) * 8;
+        for (int c = 0; c < 8; ++c) out[c] = row[c];
+    } else {
+        double d[8];
+        move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)(q / g.k),
+                   (uint32_t)(q % g.k), d);
+        for (int c = 0; c < 8; ++c) out[c] = d[c];
     }
 }
 
@@ -696,10 +772,10 @@ __global__ void k_advance_sweep(long long *p) { *p += 1; }
 // ------------------------------------------------------------- launchers
 template <typename TraceT>
 static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *trace, double *E,
-                                 int color, const long long *sweep_ptr, const double *feed,
-                                 long long feed_first, double *logp, long long log_first,
-                                 long long log_n, unsigned long long *stats, int *err, int block,
-                                 int chains, hipStream_t s)
+                                 int color, const long long *sweep_ptr, const double *draws,
+                                 double *logp, long long log_first, long long log_n,
+                                 unsigned long long *stats, int *err, int block, int chains,
+                                 hipStream_t s)
 {
     const int p = g.period;
     const int ci = color % p, ck = color / p;
@@ -707,35 +783,41 @@ static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *tra
     const dim3 grid(ni * nk, chains);
     const TraceT *tr = (const TraceT *)trace;
     switch (block) {
-    case 64:
-        k_sweep_color<TraceT, 64><<<grid, 64, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
-                                                       feed_first, logp, log_first, log_n,
-                                                       stats, err);
+    case 512:
+        k_sweep_color<TraceT, 512><<<grid, 512, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
+                                                         logp, log_first, log_n, stats, err);
         break;
     case 128:
-        k_sweep_color<TraceT, 128><<<grid, 128, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
-                                                         feed_first, logp, log_first, log_n,
-                                                         stats, err);
+        k_sweep_color<TraceT, 128><<<grid, 128, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
+                                                         logp, log_first, log_n, stats, err);
         break;
     default:
-        k_sweep_color<TraceT, 256><<<grid, 256, 0, s>>>(g, ev, tr, E, color, sweep_ptr, feed,
-                                                         feed_first, logp, log_first, log_n,
-                                                         stats, err);
+        k_sweep_color<TraceT, 256><<<grid, 256, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
+                                                         logp, log_first, log_n, stats, err);
         break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
-                        int color, const long long *sweep_ptr, const double *feed,
-                        long long feed_first, double *logp, long long log_first, long long log_n,
-                        unsigned long long *stats, int *err, int block, int chains, hipStream_t s)
+                        int color, const long long *sweep_ptr, const double *draws, double *logp,
+                        long long log_first, long long log_n, unsigned long long *stats, int *err,
+                        int block, int chains, hipStream_t s)
 {
     if (f64)
-        return launch_sweep_t<double>(g, ev, trace, E, color, sweep_ptr, feed, feed_first, logp,
-                                      log_first, log_n, stats, err, block, chains, s);
-    return launch_sweep_t<float>(g, ev, trace, E, color, sweep_ptr, feed, feed_first, logp,
-                                 log_first, log_n, stats, err, block, chains, s);
+        return launch_sweep_t<double>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
+                                      log_n, stats, err, block, chains, s);
+    return launch_sweep_t<float>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
+                                 log_n, stats, err, block, chains, s);
+}
+
+hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
+                              long long feed_first, double *draws, int chains, hipStream_t s)
+{
+    const long long per = (long long)g.R * g.k;
+    const dim3 grid((unsigned)((per + 255) / 256), chains);
+    k_sweep_draws<<<grid, 256, 0, s>>>(g, sweep_ptr, feed, feed_first, draws);
+    return hipGetLastError();
 }
 
 hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,

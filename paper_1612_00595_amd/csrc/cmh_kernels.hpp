@@ -6,9 +6,11 @@
 namespace cmh {
 
 hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
-                        int color, const long long *sweep_ptr, const double *feed,
-                        long long feed_first, double *logp, long long log_first, long long log_n,
-                        unsigned long long *stats, int *err, int block, int chains, hipStream_t s);
+                        int color, const long long *sweep_ptr, const double *draws, double *logp,
+                        long long log_first, long long log_n, unsigned long long *stats, int *err,
+                        int block, int chains, hipStream_t s);
+hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
+                              long long feed_first, double *draws, int chains, hipStream_t s);
 hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
                         const long long *sweep_ptr, int *err, int chains, hipStream_t s);
 int refresh_blocks(const Geo &g);

@@ -99,7 +99,7 @@ def _replay(w, nsw, block, feed_seed=77, compare_each_phase=True):
     return gpu, ref, m, s, acc
 
 
-@pytest.mark.parametrize("block", [64, 128, 256])
+@pytest.mark.parametrize("block", [128, 256, 512])
 def test_replay_parity_small_static(block):
     say("replay", W.SMALL.name, "block", block)
     gpu, ref, m, s, acc = _replay(W.SMALL, 12, block)
@@ -140,7 +140,7 @@ def test_replay_parity_full_size_large():
     fd = torch.from_numpy(feed).to(DEV)
     rows = np.random.default_rng(1).choice(w.model.nsta, 48, replace=False)
     Er = {int(j): O.event_variance_rows(m, rev, int(j), 1)[0] for j in rows}
-    for block in (64, 128, 256):
+    for block in (128, 256, 512):
         say("gpu sweep block", block)
         gpu = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3, block=block)
         gpu.set_feed(fd, 0)
@@ -264,7 +264,7 @@ def test_prior_only_gpu_chain_samples_the_prior():
     assert stats.kstest(np.concatenate(xs) / w.model.Lx, "uniform").pvalue > 1e-3
     assert stats.kstest(np.concatenate(ms) - 2.0, "expon").pvalue > 1e-3
     st = gpu.read_stats(0)
-    assert st[:, 0].sum() == 700 * 16 * spec.k
+    assert st[:, 0].sum() == (100 + 600 * 5) * 16 * spec.k
 
 
 # ------------------------------------------------------------ error paths
