@@ -63,7 +63,8 @@ struct Seg {
 };
 
 struct MoveHdr {
-    int valid, type, n, nseg;
+    int valid, type, n, nseg, S;
+    int flags;  // error flags, raised only when the move is consumed
     double dm;  // magnitude change (magnitude move)
 };
 
@@ -87,7 +88,7 @@ __device__ inline bool in_region_axis(double x, double lo, double hi, double off
 // candidate's one or two sample runs.
 __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
                           double om, bool has_new, double nx, double ny, double nt, double nm,
-                          Seg *segs, int *nseg_out, int *flags)
+                          Seg *segs, int *nseg_out, int *S_out, int *flags)
 {
     int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
     if (has_old) {
@@ -107,7 +108,6 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
     const double ex = half ? nx : ox, ey = half ? ny : oy, et = half ? nt : ot,
                  em = half ? nm : om;
     int seg_base = 0, samp_base = 0;
-    (void)samp_base;
     for (int c0 = 0; c0 < nbox; c0 += 32) {
         const int cidx = c0 + hl;
         Arrival ar;
@@ -165,21 +165,105 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
             }
         }
         seg_base += __popcll(m1) + __popcll(m2);
-        samp_base += 0;
-        (void)nsamp;
+        int tot = nsamp;
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+        samp_base += __shfl(tot, 0, 64);
     }
     *nseg_out = seg_base;
+    *S_out = samp_base;
 }
 
 // ------------------------------------------------------------ sweep colour
+// Wave 0 of a sweep workgroup ("scout"): builds move jj's proposal from its
+// draws and the region's current events, and its footprint, into buffer
+// `buf`.  Lane 0 owns the event table; the other lanes help with the
+// footprint.
+__device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i, int kk,
+                                  double offx, double offy, double x0, double x1, double y0,
+                                  double y1, int n, const double (*drw)[kDrawChunk][8],
+                                  const double *s_ex, const double *s_ey, const double *s_et,
+                                  const double *s_em, Seg (*s_seg)[kMaxSeg], MoveHdr *s_hdr,
+                                  double (*s_prop)[5], int max_samples)
+{
+    int type = 0, valid = 0, idx = -1, mflags = 0;
+    double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0;
+    if (lane == 0) {
+        const double *d = drw[(jj >> 6) & 1][jj & 63];
+        const double u = d[0];
+        type = u < g.c1 ? 0 : u < g.c2 ? 1 : u < g.c3 ? 2 : u < g.c4 ? 3 : 4;
+        if (type == 0) {
+            if (n >= g.cap) {
+                mflags |= kFlagCap;
+            } else {
+                nx = x0 + d[1] * (x1 - x0);
+                ny = y0 + d[2] * (y1 - y0);
+                nt = d[3] * (double)g.N;
+                nm = g.mmin + d[4] / g.mrate;
+                valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly && nt < (double)g.N &&
+                        in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
+                        in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
+            }
+        } else if (n > 0) {
+            idx = (int)floor(d[1] * (double)n);
+            if (idx >= n) idx = n - 1;
+            ox = s_ex[idx]; oy = s_ey[idx]; ot = s_et[idx]; om = s_em[idx];
+            nx = ox; ny = oy; nt = ot; nm = om;
+            valid = 1;
+            if (type == 2) {
+                nx = ox + g.sxy * d[5];
+                ny = oy + g.sxy * d[6];
+                valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
+                        in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
+                        in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
+            } else if (type == 3) {
+                nt = ot + g.st * d[5];
+                valid = nt >= 0.0 && nt < (double)g.N;
+            } else if (type == 4) {
+                nm = om + g.sm * d[5];
+                valid = nm >= g.mmin;
+            }
+        }
+    }
+    type = __shfl(type, 0, 64);
+    valid = __shfl(valid, 0, 64);
+    int nseg = 0, S = 0;
+    if (valid && !g.prior_only) {
+        ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
+        ot = __shfl(ot, 0, 64); om = __shfl(om, 0, 64);
+        nx = __shfl(nx, 0, 64); ny = __shfl(ny, 0, 64);
+        nt = __shfl(nt, 0, 64); nm = __shfl(nm, 0, 64);
+        int fl = 0;
+        footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
+                  &nseg, &S, &fl);
+        if (__ballot(fl != 0) != 0ull || S > max_samples) {
+            valid = 0;
+            mflags |= kFlagSeg;
+        }
+    }
+    if (lane == 0) {
+        MoveHdr h;
+        h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.flags = mflags;
+        h.dm = nm - om;
+        s_hdr[buf] = h;
+        s_prop[buf][0] = nx; s_prop[buf][1] = ny; s_prop[buf][2] = nt; s_prop[buf][3] = nm;
+        s_prop[buf][4] = (double)idx;
+    }
+}
+
 // One workgroup per region of colour `color` (blockIdx.x) and chain
-// (blockIdx.y).  The region's events and the k moves' draws are staged in
-// LDS; wave 0 lane 0 builds each proposal, wave 0 finds its footprint, and
-// every thread evaluates the log-likelihood change on a strided share of the
-// footprint samples (all loads issued before any arithmetic; one division per
-// sample and one logarithm per thread, of the product of the variance
-// ratios).  On acceptance the threads write the updated event variance in
-// place.  The event variance of other regions is read but never written: the
+// (blockIdx.y); k MH moves in sequence (Algorithm 4's inner loop).
+//   Wave 0 (scout) builds each move's proposal and footprint.  While the
+//   other waves evaluate move j it already builds move j + 1 on the
+//   assumption that move j is rejected (the state is then unchanged); after
+//   an acceptance it rebuilds move j + 1 from the updated events.  The chain
+//   of states is exactly the sequential one.
+//   Waves 1.. (evaluators) evaluate the log-likelihood change on a strided
+//   share of the footprint samples: every load issued before any arithmetic,
+//   one division per sample and one logarithm per thread (of the product of
+//   the variance ratios); on acceptance they write the new event variance in
+//   place.
+// The event variance of other regions is read but never written: the
 // colouring guarantees that no station is reached from two regions of one
 // colour (the Markov-blanket argument of Section 4.1).
 template <typename TraceT, int BLOCK>
@@ -189,15 +273,18 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
               double *__restrict__ logp, long long log_first, long long log_n,
               unsigned long long *__restrict__ stats, int *__restrict__ err)
 {
+    static_assert(BLOCK >= 128 && BLOCK % 64 == 0, "one scout wave and at least one evaluator");
     constexpr int W = BLOCK / 64;
-    constexpr int MAXQ = kMaxFootprint / BLOCK;
-    __shared__ double s_draw[kDrawChunk][8];
+    constexpr int EV = BLOCK - 64;
+    constexpr int MAXQ = (kMaxFootprint + EV - 1) / EV;
+    __shared__ double s_draw[2][kDrawChunk][8];
     __shared__ double s_T[kMaxTs];
     __shared__ double s_log[kMaxCap + 2];  // s_log[q] = log(q)
     __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
     __shared__ unsigned long long s_id[kMaxCap];
     __shared__ Seg s_seg[2][kMaxSeg];
     __shared__ MoveHdr s_hdr[2];
+    __shared__ double s_prop[2][5];
     __shared__ double s_part[2][W];
     __shared__ int s_n;
 
@@ -232,6 +319,10 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     }
     for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-2.0 * (double)q / g.decay);
     for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
+    for (int c = 0; c < 2 && 64 * c < g.k; ++c) {
+        const int m = min(kDrawChunk, g.k - 64 * c) * 8;
+        for (int q = tid; q < m; q += BLOCK) s_draw[c][q >> 3][q & 7] = dsrc[64LL * 8 * c + q];
+    }
 
     const bool use_log = logp != nullptr && chain == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
@@ -239,136 +330,60 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                  cnt_acc[5] = {0, 0, 0, 0, 0};
     unsigned long long samp_read = 0, samp_written = 0;
     int flags = 0;
+    __syncthreads();
+    if (wave == 0)
+        scout_move(g, lane, 0, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw, s_ex, s_ey, s_et,
+                   s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+    __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
         const int buf = j & 1;
-        const int slot = j % kDrawChunk;
-        if (slot == 0) {
-            __syncthreads();
-            const int m = min(kDrawChunk, g.k - j) * 8;
-            for (int q = tid; q < m; q += BLOCK) s_draw[q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
+        // moves 128, 192, ... start a chunk whose buffer held moves 128 earlier
+        if (((j + 1) & 63) == 0 && j + 1 < g.k && j + 1 >= 128) {
+            const int c = (j + 1) >> 6;
+            const int m = min(kDrawChunk, g.k - (j + 1)) * 8;
+            for (int q = tid; q < m; q += BLOCK)
+                s_draw[c & 1][q >> 3][q & 7] = dsrc[(long long)(j + 1) * 8 + q];
             __syncthreads();
         }
-
-        if (wave == 0) {
-            int type = 0, valid = 0, idx = -1;
-            double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0;
-            if (lane == 0) {
-                const double *d = s_draw[slot];
-                const double u = d[0];
-                type = u < g.c1 ? 0 : u < g.c2 ? 1 : u < g.c3 ? 2 : u < g.c4 ? 3 : 4;
-                if (type == 0) {
-                    if (n >= g.cap) {
-                        flags |= kFlagCap;
-                    } else {
-                        nx = x0 + d[1] * (x1 - x0);
-                        ny = y0 + d[2] * (y1 - y0);
-                        nt = d[3] * (double)g.N;
-                        nm = g.mmin + d[4] / g.mrate;
-                        valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
-                                nt < (double)g.N &&
-                                in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
-                                in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
-                    }
-                } else if (n > 0) {
-                    idx = (int)floor(d[1] * (double)n);
-                    if (idx >= n) idx = n - 1;
-                    ox = s_ex[idx]; oy = s_ey[idx]; ot = s_et[idx]; om = s_em[idx];
-                    nx = ox; ny = oy; nt = ot; nm = om;
-                    valid = 1;
-                    if (type == 2) {
-                        nx = ox + g.sxy * d[5];
-                        ny = oy + g.sxy * d[6];
-                        valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
-                                in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
-                                in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
-                    } else if (type == 3) {
-                        nt = ot + g.st * d[5];
-                        valid = nt >= 0.0 && nt < (double)g.N;
-                    } else if (type == 4) {
-                        nm = om + g.sm * d[5];
-                        valid = nm >= g.mmin;
-                    }
-                }
-            }
-            type = __shfl(type, 0, 64);
-            valid = __shfl(valid, 0, 64);
-            int nseg = 0;
-            if (valid && !g.prior_only) {
-                ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
-                ot = __shfl(ot, 0, 64); om = __shfl(om, 0, 64);
-                nx = __shfl(nx, 0, 64); ny = __shfl(ny, 0, 64);
-                nt = __shfl(nt, 0, 64); nm = __shfl(nm, 0, 64);
-                int fl = 0;
-                footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm,
-                          s_seg[buf], &nseg, &fl);
-                if (__ballot(fl != 0) != 0ull) {
-                    valid = 0;
-                    if (lane == 0) flags |= kFlagSeg;
-                }
-            }
-            if (lane == 0) {
-                MoveHdr h;
-                h.valid = valid; h.type = type; h.n = n; h.nseg = nseg;
-                h.dm = nm - om;
-                s_hdr[buf] = h;
-                // keep the proposal for the update
-                s_draw[slot][0] = nx; s_draw[slot][1] = ny; s_draw[slot][2] = nt;
-                s_draw[slot][3] = nm; s_draw[slot][4] = (double)idx;
-            }
-        }
-        __syncthreads();
         const MoveHdr h = s_hdr[buf];
-        const double lnu = s_draw[slot][7];
+        const double lnu = s_draw[(j >> 6) & 1][j & 63][7];
+        const bool evaluate = h.valid && !g.prior_only;
 
-        double delta = 0.0;
         double enew[MAXQ];
         int gidx[MAXQ];  // station * N + sample of this thread's samples, or -1
-        int S = 0;
-        bool valid = h.valid != 0;
-        int sidx[MAXQ], sbeg[MAXQ];  // run holding flat position f, and its start
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) { sidx[q] = 0; sbeg[q] = 0; }
-        if (valid && !g.prior_only) {
+        for (int q = 0; q < MAXQ; ++q) { gidx[q] = -1; enew[q] = 0.0; }
+        if (wave == 0) {
+            if (j + 1 < g.k)  // speculative: the state as if move j is rejected
+                scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+        } else if (evaluate) {
+            const int et = tid - 64;
             const Seg *sg = s_seg[buf];
+            int sidx[MAXQ], sbeg[MAXQ];  // run holding flat position f, and its start
+            int S = 0;
+#pragma unroll
+            for (int q = 0; q < MAXQ; ++q) { sidx[q] = 0; sbeg[q] = 0; }
             for (int t = 0; t < h.nseg; ++t) {
 #pragma unroll
                 for (int q = 0; q < MAXQ; ++q) {
-                    const bool here = tid + q * BLOCK >= S;
+                    const bool here = et + q * EV >= S;
                     sidx[q] = here ? t : sidx[q];
                     sbeg[q] = here ? S : sbeg[q];
                 }
                 S += sg[t].len;
             }
-            if (S > MAXQ * BLOCK) {  // cannot happen for t_s <= kMaxTs; kept as a guard
-                valid = false;
-                if (tid == 0) flags |= kFlagSeg;
-            }
-        }
-        if (!valid) {
-            if (tid == 0) {
-                cnt_att[h.type]++;
-                if (use_log) {
-                    double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
-                    lg[0] = (double)h.type; lg[1] = 0.0; lg[2] = 0.0; lg[3] = 0.0;
-                }
-            }
-            continue;
-        }
-        if (!g.prior_only) {
-            const Seg *sg = s_seg[buf];
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
-                const int f = tid + q * BLOCK;
-                gidx[q] = -1;
+                const int f = et + q * EV;
                 if (f < S) {
                     const Seg &a = sg[sidx[q]];
                     gidx[q] = a.j * g.N + a.lo + (f - sbeg[q]);
                 }
             }
-            // load: every sample's variance and trace value in flight at once.
-            // Loads are unconditional (idle slots read element 0) so that no
-            // branch or select separates a load from its issue.
+            // load: every sample's variance and trace value in flight at once;
+            // idle slots read element 0 so that no branch separates the loads
             double eo[MAXQ], sv[MAXQ];
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
@@ -376,14 +391,12 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                 eo[q] = E[ebase + gi];
                 sv[q] = (double)trace[gi];
             }
-            // compute: sum of -1/2 [log(v'/v) + s^2 (1/v' - 1/v)], v = sigma^2 + E,
-            // as -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')]; slots beyond the
-            // footprint are skipped by a block-uniform bound
+            // sum of -1/2 [log(v'/v) + s^2 (1/v' - 1/v)], v = sigma^2 + E, as
+            // -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')]
             double prod = 1.0, lin = 0.0;
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
-                enew[q] = eo[q];
-                if (q * BLOCK < S) {
+                if (q * EV < S) {
                     const bool ok = gidx[q] >= 0;
                     const Seg &a = sg[sidx[q]];
                     const int nn = gidx[q] - a.j * g.N;
@@ -407,11 +420,14 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             double part = -0.5 * (log(prod) - lin);
             part = wave_sum(part);
             if (lane == 0) s_part[buf][wave] = part;
-            __syncthreads();
-#pragma unroll
-            for (int w = 0; w < W; ++w) delta += s_part[buf][w];
         }
+        __syncthreads();
 
+        double delta = 0.0;
+        if (evaluate) {
+#pragma unroll
+            for (int w = 1; w < W; ++w) delta += s_part[buf][w];
+        }
         double la;
         if (h.type == 0)
             la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb;
@@ -421,24 +437,36 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             la = delta - g.mrate * h.dm;
         else
             la = delta;
-        bool accept = lnu < la;
+        bool accept = h.valid && lnu < la;
         if (!(delta == delta) || delta - delta != 0.0) {  // NaN or Inf
             accept = false;
             if (tid == 0) flags |= kFlagNan;
         }
-        if (accept && !g.prior_only) {
-#pragma unroll
-            for (int q = 0; q < MAXQ; ++q)
-                if (gidx[q] >= 0) E[ebase + gidx[q]] = enew[q];
-        }
         if (tid == 0) {
+            flags |= h.flags;
             cnt_att[h.type]++;
-            cnt_val[h.type]++;
-            samp_read += (unsigned long long)S;
-            const double *pr = s_draw[slot];
-            if (accept) {
+            if (h.valid) {
+                cnt_val[h.type]++;
+                samp_read += (unsigned long long)h.S;
+            }
+            if (use_log) {
+                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
+                lg[0] = (double)h.type;
+                lg[1] = h.valid ? (accept ? 2.0 : 1.0) : 0.0;
+                lg[2] = h.valid ? delta : 0.0;
+                lg[3] = h.valid ? la : 0.0;
+            }
+        }
+        if (accept) {
+            if (wave > 0 && !g.prior_only) {
+#pragma unroll
+                for (int q = 0; q < MAXQ; ++q)
+                    if (gidx[q] >= 0) E[ebase + gidx[q]] = enew[q];
+            }
+            if (tid == 0) {
                 cnt_acc[h.type]++;
-                samp_written += (unsigned long long)S;
+                samp_written += (unsigned long long)h.S;
+                const double *pr = s_prop[buf];
                 if (h.type == 0) {
                     s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
                     s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
@@ -457,10 +485,12 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                     s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
                 }
             }
-            if (use_log) {
-                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
-                lg[0] = (double)h.type; lg[1] = accept ? 2.0 : 1.0; lg[2] = delta; lg[3] = la;
-            }
+            n = __shfl(n, 0, 64);
+            __syncthreads();  // the new events and variance are visible
+            if (wave == 0 && j + 1 < g.k)
+                scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+            __syncthreads();
         }
     }
 
