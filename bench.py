@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic", default=None,
                     help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic for calibrating hardware byte counters)")
     return ap.parse_args()
 
 
@@ -101,6 +104,12 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tr = W.truth_events(w.model, w.seed)
     truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
     log(f"[bench] simulating {w.name}: {w.model.nsta} stations x {w.model.N} samples, "
