@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic", default=None,
                     help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 32-chain workload measured next to the main one")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating hardware byte counters)")
@@ -87,6 +89,36 @@ def cpu_baseline(w, warmup: int, budget_s: float):
                        f"instance of the same shape, single thread")
 
 
+def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
+    """Proposals/s over `steps` graph-replayed sweeps after `warmup`, and the
+    sweep kernel's HIP-event-timed launch duration and algorithmic bytes."""
+    import torch
+    smp.run_sweeps(0, warmup)
+    torch.cuda.synchronize()
+    c0 = sum(smp.read_counters(c) for c in range(w.chains))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.run_sweeps(warmup, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = sum(smp.read_counters(c) for c in range(w.chains))
+    el = t1 - t0
+    proposals = int((c1 - c0)[:15].reshape(5, 3)[:, 0].sum())
+    first = warmup + steps
+    ms = smp.time_phases(first, profile_sweeps, stream)
+    c3 = sum(smp.read_counters(c) for c in range(w.chains))
+    launches = profile_sweeps * smp.ncolors
+    avg_ms = float(ms[:smp.ncolors].sum()) / launches
+    tb = 4 if w.trace_dtype == "f32" else 8
+    samp_read = int(c3[15] - c1[15])
+    samp_written = int(c3[16] - c1[16])
+    bytes_per_launch = (samp_read * (tb + 8) + samp_written * 8) / launches
+    return dict(elapsed=el, proposals=proposals, value=proposals / el, avg_ms=avg_ms,
+                bytes_per_launch=bytes_per_launch,
+                achieved=bytes_per_launch / (avg_ms * 1e-3) / 1e9,
+                start_ms=float(ms[smp.ncolors]) / profile_sweeps)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -121,33 +153,10 @@ def main():
         smp.autotune(0, 3)
     log(f"[bench] sweep workgroup size {smp.block}, {smp.ncolors} colours")
 
-    smp.run_sweeps(0, args.warmup)
-    torch.cuda.synchronize()
-    c0 = sum(smp.read_counters(c) for c in range(w.chains))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    smp.run_sweeps(args.warmup, args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    c1 = sum(smp.read_counters(c) for c in range(w.chains))
-    el = t1 - t0
-    proposals = int((c1 - c0)[:15].reshape(5, 3)[:, 0].sum())
-    value = proposals / el
+    res = measure(smp, w, args.warmup, args.steps, args.profile_sweeps, stream)
+    el, value = res["elapsed"], res["value"]
+    avg_ms, bytes_per_launch, achieved = res["avg_ms"], res["bytes_per_launch"], res["achieved"]
     log(f"[bench] {args.steps} sweeps in {el * 1e3:.1f} ms: {value:.4g} proposals/s")
-
-    # live per-launch timing of the sweep kernel (HIP events on this stream)
-    first = args.warmup + args.steps
-    P = args.profile_sweeps
-    c2 = sum(smp.read_counters(c) for c in range(w.chains))
-    ms = smp.time_phases(first, P, stream)
-    c3 = sum(smp.read_counters(c) for c in range(w.chains))
-    launches = P * smp.ncolors
-    avg_ms = float(ms[:smp.ncolors].sum()) / launches
-    tb = 4 if w.trace_dtype == "f32" else 8
-    samp_read = int(c3[15] - c2[15])
-    samp_written = int(c3[16] - c2[16])
-    bytes_per_launch = (samp_read * (tb + 8) + samp_written * 8) / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         traffic = json.load(open(args.traffic)).get("bytes_per_launch")
@@ -194,9 +203,30 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
     }
+    block = smp.block
     smp.close()
     del trace
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        wb = W.CHAINS32
+        trb = W.truth_events(wb.model, wb.seed)
+        truthb = chromh.as_events(trb["x"], trb["y"], trb["t"], trb["m"], trb["id"])
+        traceb = chromh.simulate(wb.model, truthb, 1000 + wb.seed, wb.trace_dtype, dev)
+        sb = chromh.ChromaticSampler(wb.model, wb.sampler, traceb, chains=wb.chains,
+                                     seed=wb.seed, block=block)
+        rb = measure(sb, wb, args.warmup, max(args.steps // 5, 5), 2, stream)
+        log(f"[bench] {wb.name}: {rb['value']:.4g} proposals/s, sweep kernel "
+            f"{rb['avg_ms'] * 1e3:.1f} us/launch, {rb['achieved']:.1f} GB/s algorithmic")
+        out["batched"] = {
+            "workload": wb.name, "chains": wb.chains, "value": rb["value"],
+            "unit": "proposals/s", "ms_per_step": rb["elapsed"] * 1e3 / max(args.steps // 5, 5),
+            "sweep_kernel_us": rb["avg_ms"] * 1e3,
+            "algorithmic_bytes_per_launch": rb["bytes_per_launch"],
+            "achieved_GBps": rb["achieved"], "frac": rb["achieved"] / HBM_PEAK_GBS,
+        }
+        sb.close()
+        del traceb
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.warmup, args.cpu_seconds)
