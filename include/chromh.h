@@ -226,6 +226,84 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
 int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
                        uint32_t j0, int32_t count, double *out_dev, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned birth proposal: a mixture-density network (MDN).
+ *
+ * Input: 576 BF16 features = the 3x3 block of stations around a centre
+ * station (row-major) x 64 log-envelope values e[n] = ln(sigma^2 +
+ * mean(s[n..n+3]^2)) - ln(sigma^2) from a window start (rounded to binary32,
+ * then BF16).  Layers 576 -> 256 -> 256 -> 256 (GELU, erf form) -> 64 (56
+ * live): 8 components x (logit, mean x, y, t, log sd x, y, t) over the
+ * event's offset from the centre station in units of ds and from the window
+ * start in units of 32 samples; log sds clamped to sd_xy in [0.025, 1.5],
+ * sd_t in [1/64, 1].  BF16 operands on MFMA, FP32 accumulation.
+ *
+ * Parameter blob (caller-owned device memory, cmh_mdn_param_bytes): FP32
+ * master weights and biases of the four layers (weights [out][in]) in order
+ * W1 b1 W2 b2 W3 b3 W4 b4 (n_params floats), the Adam moments, then BF16
+ * copies of the weights.  Work buffers hold a row batch's activations.
+ * ---------------------------------------------------------------------- */
+#define CMH_MDN_IN 576
+#define CMH_MDN_OUT 64
+
+int32_t cmh_mdn_sizes(int64_t *n_params, int64_t *n_weights_bf16);
+int32_t cmh_mdn_param_bytes(size_t *bytes);
+
+/* Glorot-uniform weights from Philox4x32-10 under key (seed, 0x80000004),
+ * counter (parameter index, 0, 0, 0); zero biases and Adam moments. */
+int32_t cmh_mdn_init(void *params_dev, uint32_t seed, void *hip_stream);
+
+/* Replace / read the FP32 master parameters (host arrays of n_params floats);
+ * setting zeroes the Adam moments and refreshes the BF16 copies.
+ * Synchronises. */
+int32_t cmh_mdn_set_params(void *params_dev, const float *host, void *hip_stream);
+int32_t cmh_mdn_get_params(const void *params_dev, float *host);
+
+int32_t cmh_mdn_work_bytes(int32_t rows, size_t *bytes);
+
+/* Head outputs out_dev[rows][64] (FP32) for BF16 features x_dev[rows][576]. */
+int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
+                        void *work_dev, size_t work_bytes, void *hip_stream);
+
+/* Mean mixture negative log-likelihood of targets z_dev[rows][3] and its
+ * gradient w.r.t. every FP32 parameter (grad_dev[n_params]); per-row losses
+ * into loss_dev[rows] when not NULL.  Mixture components are untruncated
+ * Gaussians in the training loss. */
+int32_t cmh_mdn_gradients(const void *params_dev, const void *x_dev, const float *z_dev,
+                          int32_t rows, float *grad_dev, float *loss_dev, void *work_dev,
+                          size_t work_bytes, void *hip_stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected at `step`, from
+ * 1) on the gradients of cmh_mdn_gradients. */
+int32_t cmh_mdn_train_step(void *params_dev, const void *x_dev, const float *z_dev, int32_t rows,
+                           int32_t step, float lr, float *loss_dev, void *work_dev,
+                           size_t work_bytes, void *hip_stream);
+
+/* Training pairs from the forward simulator (synthetic local worlds, as the
+ * paper's evaluation samples worlds from the model): pair p is a 3x3 block of
+ * stations around a centre at the origin, a target event uniform in
+ * [-ds, ds)^2 with onset uniform in [-16, 64) samples of the window, and 3
+ * background events uniform in [-(1.5 ds + r_c), 1.5 ds + r_c)^2 with onsets
+ * in [-(t_s + 8), 64 + 8), magnitudes from the prior, traces over the
+ * window's first 67 samples.  Draws: Philox under key (seed, 0x80000003):
+ * counter (p mod 2^32, p div 2^32, 0, c) for the events (c = 0: target x, y;
+ * 1: target t, m; 2 + b and 5 + b: background b's x, y and t, m), counter
+ * (p mod 2^32, p div 2^32, 1 + station, n / 2) for the noise (Box-Muller,
+ * even n cosine, odd n sine).  Writes x_dev[count]
+ * [576] BF16 and the target offsets z_dev[count][3] = (x / ds, y / ds, t / 32). */
+int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair, int32_t count,
+                      void *x_dev, float *z_dev, void *hip_stream);
+
+/* Anchors of an instance: centre station c over the interior stations
+ * (1 <= ix <= nsx - 2, 1 <= iy <= nsy - 2, row-major) times window starts
+ * tau = 32 i (tau + 67 <= n_samples); anchor index = c * n_tau + i. */
+int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_tau);
+
+/* Every anchor's 576 BF16 features (x_dev[n_anchors][576]) and weight
+ * w_dev[n_anchors] = 1e-3 + mean over its features of max(0, f - 1). */
+int32_t cmh_anchor_features(const cmh_model *model, const void *trace_dev, int32_t trace_dtype,
+                            void *x_dev, double *w_dev, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

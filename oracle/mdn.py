@@ -1,0 +1,176 @@
+"""FP64 reference of the learned proposal's network (numpy).  TEST
+INFRASTRUCTURE ONLY, like the rest of `oracle/`.
+
+A mixture-density network: 576 features -> three GELU layers of 256 -> 56
+outputs = 8 components x (logit, mean x, y, t, log sd x, y, t), log sds
+clamped per axis; loss = mean negative log-likelihood of the target under
+the mixture of untruncated Gaussians.  With ``bf16=True`` the reference
+rounds to BF16 exactly where the GPU stores BF16 (features, weight copies,
+hidden activations, the loss gradient and the backpropagated GELU
+gradients) and otherwise computes in FP64; with ``bf16=False`` it is plain
+FP64 throughout (pinned by finite differences).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+from scipy.special import erf
+
+from . import EVENT_DTYPE, Model, _ptr, lib  # noqa: F401
+
+N_IN, N_HID, N_K, N_OUT_PAD = 576, 256, 8, 64
+SLO = np.array([np.log(0.025), np.log(0.025), np.log(0.5 / 32)])
+SHI = np.array([np.log(1.5), np.log(1.5), 0.0])
+LAYERS = [(N_IN, N_HID), (N_HID, N_HID), (N_HID, N_HID), (N_HID, N_OUT_PAD)]
+
+
+def to_f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def to_bf16(x) -> np.ndarray:
+    """Round to BF16 (round to nearest, ties to even) through binary32."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def param_layout():
+    """(name, shape, offset) of the flat FP32 parameter vector."""
+    out, o = [], 0
+    for l, (fi, fo) in enumerate(LAYERS):
+        out.append((f"W{l + 1}", (fo, fi), o))
+        o += fi * fo
+        out.append((f"b{l + 1}", (fo,), o))
+        o += fo
+    return out, o
+
+
+def unflatten(flat: np.ndarray) -> dict:
+    lay, n = param_layout()
+    assert flat.size == n
+    return {name: np.asarray(flat[o:o + int(np.prod(sh))], dtype=np.float64).reshape(sh)
+            for name, sh, o in lay}
+
+
+def flatten(P: dict) -> np.ndarray:
+    lay, n = param_layout()
+    out = np.zeros(n)
+    for name, sh, o in lay:
+        out[o:o + int(np.prod(sh))] = P[name].ravel()
+    return out
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + erf(z / np.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)
+
+
+def forward(P: dict, X: np.ndarray, bf16: bool = True):
+    r = to_bf16 if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    W = [r(P[f"W{l + 1}"]) for l in range(4)]
+    a = r(X)
+    Zs, As = [], [a]
+    for l in range(3):
+        z = a @ W[l].T + P[f"b{l + 1}"]
+        Zs.append(z)
+        a = r(gelu(z))
+        As.append(a)
+    o = a @ W[3].T + P["b4"]
+    return o, Zs, As, W
+
+
+def mixture_nll(o: np.ndarray, z: np.ndarray):
+    """Per-row loss and d loss / d output (not yet divided by the batch)."""
+    M = o.shape[0]
+    K = N_K
+    logit = o[:, 0:7 * K:7]
+    mu = np.stack([o[:, 1 + d:7 * K:7] for d in range(3)], axis=-1)      # M x K x 3
+    sraw = np.stack([o[:, 4 + d:7 * K:7] for d in range(3)], axis=-1)
+    s = np.clip(sraw, SLO, SHI)
+    lse = np.log(np.sum(np.exp(logit - logit.max(1, keepdims=True)), 1)) + logit.max(1)
+    u = (z[:, None, :] - mu) * np.exp(-s)
+    ell = (logit - lse[:, None]) + np.sum(-0.5 * u * u - s - 0.5 * np.log(2 * np.pi), axis=-1)
+    best = ell.max(1)
+    logp = best + np.log(np.sum(np.exp(ell - best[:, None]), 1))
+    gam = np.exp(ell - logp[:, None])
+    pik = np.exp(logit - lse[:, None])
+    g = np.zeros((M, N_OUT_PAD))
+    g[:, 0:7 * K:7] = pik - gam
+    free = (sraw > SLO) & (sraw < SHI)
+    for d in range(3):
+        g[:, 1 + d:7 * K:7] = -gam * u[..., d] * np.exp(-s[..., d])
+        g[:, 4 + d:7 * K:7] = np.where(free[..., d], -gam * (u[..., d] ** 2 - 1.0), 0.0)
+    return -logp, g
+
+
+def loss_and_grads(P: dict, X: np.ndarray, Z: np.ndarray, bf16: bool = True):
+    """Mean loss and gradients of every parameter (dict like P)."""
+    r = to_bf16 if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    o, Zs, As, W = forward(P, X, bf16)
+    M = X.shape[0]
+    per_row, g = mixture_nll(o, Z)
+    dO = r(g / M)
+    G = {"W4": dO.T @ As[3], "b4": dO.sum(0)}
+    dnext = dO
+    for l in (2, 1, 0):
+        dA = dnext @ W[l + 1]
+        dH = r(dA * gelu_grad(Zs[l]))
+        G[f"W{l + 1}"] = dH.T @ As[l]
+        G[f"b{l + 1}"] = dH.sum(0)
+        dnext = dH
+    return float(per_row.mean()), per_row, G
+
+
+def mixture_table(o: np.ndarray, centres: np.ndarray, taus: np.ndarray, ds: float) -> np.ndarray:
+    """Per-row mixture in absolute units: [rows][8][7] = (log pi, mu x, mu y,
+    mu t, sd x, sd y, sd t)."""
+    K = N_K
+    logit = o[:, 0:7 * K:7]
+    lse = np.log(np.sum(np.exp(logit - logit.max(1, keepdims=True)), 1)) + logit.max(1)
+    out = np.zeros((o.shape[0], K, 7))
+    out[..., 0] = logit - lse[:, None]
+    scale = np.array([ds, ds, 32.0])
+    for d in range(3):
+        s = np.clip(o[:, 4 + d:7 * K:7], SLO[d], SHI[d])
+        base = centres[:, d][:, None] if d < 2 else taus[:, None]
+        out[..., 1 + d] = base + scale[d] * o[:, 1 + d:7 * K:7]
+        out[..., 4 + d] = scale[d] * np.exp(s)
+    return out
+
+
+# ------------------------------------------------------------- features
+
+def pair(model: Model, seed: int, p: int):
+    L = lib()
+    L.orc_mdn_pair.argtypes = [C.c_void_p, C.c_uint32, C.c_int64, C.c_void_p, C.c_void_p]
+    f = np.zeros(N_IN)
+    t = np.zeros(3)
+    L.orc_mdn_pair(C.byref(model), seed, p, _ptr(f), _ptr(t))
+    return f, t
+
+
+def pairs(model: Model, seed: int, first: int, count: int):
+    F = np.zeros((count, N_IN))
+    T = np.zeros((count, 3))
+    for q in range(count):
+        F[q], T[q] = pair(model, seed, first + q)
+    return F, T
+
+
+def anchor_features(model: Model, s: np.ndarray, n_tau: int, a: int) -> np.ndarray:
+    L = lib()
+    L.orc_anchor_features.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    f = np.zeros(N_IN)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    L.orc_anchor_features(C.byref(model), _ptr(s), n_tau, a, _ptr(f))
+    return f
+
+
+def anchor_weight(feat_rounded: np.ndarray) -> float:
+    return 1e-3 + float(np.mean(np.maximum(0.0, feat_rounded - 1.0)))

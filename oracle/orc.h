@@ -130,6 +130,11 @@ void   orc_simulate_rows(const orc_model *m, const orc_event *truth, int64_t nev
 void   orc_trace_from_noise_f32(const orc_model *m, const orc_event *truth, int64_t nev,
                                 const float *z, float *s_out);
 
+/* ---- learned proposal: training pairs and anchor features -------------- */
+void   orc_mdn_pair(const orc_model *m, uint32_t seed, int64_t p, double *feat, double *target);
+void   orc_anchor_features(const orc_model *m, const double *s, int32_t n_tau, int32_t a,
+                           double *feat);
+
 /* ---- the sampler (serial, chromatic static/dynamic, naive) ----------- */
 typedef struct orc_chain orc_chain;
 orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double *s,

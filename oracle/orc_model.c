@@ -422,3 +422,105 @@ void orc_trace_from_noise_f32(const orc_model *m, const orc_event *truth, int64_
     free(row);
     free(idx);
 }
+
+/* ------------------------------------------------------------------------
+ * Learned birth proposal: training pairs and anchor window features.  The
+ * network and its proposal density are an addition of this implementation
+ * (an independence proposal corrected inside MH, so the posterior is
+ * unchanged); the pair generator samples local worlds from the model of
+ * Section 3, as the paper's evaluation samples worlds (Section 5).
+ * ---------------------------------------------------------------------- */
+
+/* Log envelope of one station over 64 samples from q = s^2 over 67 samples:
+ * f[n] = ln(sigma^2 + (q[n] + q[n+1] + q[n+2] + q[n+3]) / 4) - ln(sigma^2). */
+static void log_envelope(double sigma, const double *q, double *f)
+{
+    double s2 = sigma * sigma;
+    for (int n = 0; n < 64; ++n)
+        f[n] = log(s2 + (q[n] + q[n + 1] + q[n + 2] + q[n + 3]) * 0.25) - log(s2);
+}
+
+/* Training pair p: a 3x3 block of stations (spacing ds) around a centre at
+ * the origin, one target event and three background events drawn from
+ * Philox under key (seed, 0x80000003), the block's traces over the window's
+ * first 67 samples, features[9][64] and the target offset (x/ds, y/ds, t/32). */
+void orc_mdn_pair(const orc_model *m, uint32_t seed, int64_t p, double *feat, double *target)
+{
+    uint32_t key[2] = {seed, 0x80000003u};
+    double ev[4][4];
+    for (int e = 0; e < 4; ++e) {
+        uint32_t c0[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), 0u,
+                          (uint32_t)(e == 0 ? 0 : 2 + (e - 1))};
+        uint32_t c1[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), 0u,
+                          (uint32_t)(e == 0 ? 1 : 5 + (e - 1))};
+        uint32_t w0[4], w1[4];
+        orc_philox4x32_10(c0, key, w0);
+        orc_philox4x32_10(c1, key, w1);
+        double ux = orc_u01(w0[0], w0[1]), uy = orc_u01(w0[2], w0[3]);
+        double ut = orc_u01(w1[0], w1[1]), um = orc_u01(w1[2], w1[3]);
+        if (e == 0) {
+            ev[e][0] = (2.0 * ux - 1.0) * m->ds;
+            ev[e][1] = (2.0 * uy - 1.0) * m->ds;
+            ev[e][2] = -16.0 + ut * 80.0;
+        } else {
+            double half = 1.5 * m->ds + m->rc;
+            ev[e][0] = (2.0 * ux - 1.0) * half;
+            ev[e][1] = (2.0 * uy - 1.0) * half;
+            ev[e][2] = -(double)(m->ts + 8) + ut * (double)(64 + m->ts + 16);
+        }
+        ev[e][3] = m->mmin - log(um) / m->mrate;
+    }
+    for (int b = 0; b < 9; ++b) {
+        double sx = (double)(b % 3 - 1) * m->ds, sy = (double)(b / 3 - 1) * m->ds;
+        double q[67];
+        for (int n = 0; n < 67; ++n) {
+            double E = 0.0;
+            for (int e = 0; e < 4; ++e) {
+                double dx = ev[e][0] - sx, dy = ev[e][1] - sy;
+                double d = sqrt(dx * dx + dy * dy);
+                if (!(d < m->rc)) continue;
+                double a = ev[e][2] + d / m->vel;
+                double n0 = ceil(a);
+                if ((double)n < n0 || (double)n >= n0 + m->ts) continue;
+                double amp = ev[e][3] * exp(-d / m->atten);
+                double env = exp(-((double)n - a) / m->decay);
+                E += (amp * env) * (amp * env);
+            }
+            uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), (uint32_t)(1 + b),
+                             (uint32_t)(n >> 1)};
+            uint32_t w[4];
+            orc_philox4x32_10(c, key, w);
+            double u1 = orc_u01(w[0], w[1]), u2 = orc_u01(w[2], w[3]);
+            double r = sqrt(-2.0 * log(u1));
+            double z = (n & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
+            double s = sqrt(m->sigma * m->sigma + E) * z;
+            q[n] = s * s;
+        }
+        log_envelope(m->sigma, q, feat + b * 64);
+    }
+    target[0] = ev[0][0] / m->ds;
+    target[1] = ev[0][1] / m->ds;
+    target[2] = ev[0][2] / 32.0;
+}
+
+/* Anchor a of an instance: centre station (1 + c mod (nsx-2), 1 + c div
+ * (nsx-2)) with c = a div n_tau, window start 32 (a mod n_tau); features
+ * from the trace and weight 1e-3 + mean(max(0, f - 1)) over the features
+ * after rounding them to binary32 and BF16 (as given in feat_rounded). */
+void orc_anchor_features(const orc_model *m, const double *s, int32_t n_tau, int32_t a,
+                         double *feat)
+{
+    int32_t icx = m->nsx - 2;
+    int32_t c = a / n_tau, ti = a % n_tau;
+    int32_t cx = 1 + c % icx, cy = 1 + c / icx;
+    int64_t tau = 32 * (int64_t)ti;
+    for (int b = 0; b < 9; ++b) {
+        int64_t j = (int64_t)(cy + b / 3 - 1) * m->nsx + (cx + b % 3 - 1);
+        double q[67];
+        for (int n = 0; n < 67; ++n) {
+            double v = s[j * m->N + tau + n];
+            q[n] = v * v;
+        }
+        log_envelope(m->sigma, q, feat + b * 64);
+    }
+}

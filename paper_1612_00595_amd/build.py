@@ -13,8 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libchromh.so")
-SOURCES = ["cmh_kernels.hip", "cmh_api.hip"]
-HEADERS = ["cmh_common.hpp", "cmh_kernels.hpp"]
+SOURCES = ["cmh_kernels.hip", "cmh_mdn.hip", "cmh_api.hip"]
+HEADERS = ["cmh_common.hpp", "cmh_kernels.hpp", "cmh_mdn.hpp"]
 ARCH = "gfx950"
 
 

@@ -51,7 +51,10 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_sweep_color", "cmh_run_sweeps", "cmh_read_events", "cmh_write_events",
            "cmh_set_feed", "cmh_set_log", "cmh_refresh", "cmh_read_variance", "cmh_read_stats",
            "cmh_get_block", "cmh_autotune", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
-           "cmh_move_draws"]
+           "cmh_move_draws", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
+           "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
+           "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
+           "cmh_anchor_features"]
 
 _lib = None
 
@@ -87,6 +90,18 @@ def lib():
         "cmh_simulate_bytes": ([P, P, I64, P], I32),
         "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
         "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, P, P], I32),
+        "cmh_mdn_sizes": ([P, P], I32),
+        "cmh_mdn_param_bytes": ([P], I32),
+        "cmh_mdn_init": ([P, U32, P], I32),
+        "cmh_mdn_set_params": ([P, P, P], I32),
+        "cmh_mdn_get_params": ([P, P], I32),
+        "cmh_mdn_work_bytes": ([I32, P], I32),
+        "cmh_mdn_forward": ([P, P, I32, P, P, C.c_size_t, P], I32),
+        "cmh_mdn_gradients": ([P, P, P, I32, P, P, P, C.c_size_t, P], I32),
+        "cmh_mdn_train_step": ([P, P, P, I32, I32, C.c_float, P, P, C.c_size_t, P], I32),
+        "cmh_mdn_pairs": ([P, U32, I64, I32, P, P, P], I32),
+        "cmh_anchor_count": ([P, P, P], I32),
+        "cmh_anchor_features": ([P, P, I32, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -304,3 +319,100 @@ class ChromaticSampler:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- learned proposal
+
+class MDN:
+    """The mixture-density network of the learned birth proposal, with its
+    parameters (FP32 master + Adam moments + BF16 copies) in device memory."""
+
+    def __init__(self, device="cuda", seed: int | None = 0):
+        import torch
+        n, nh = C.c_int64(), C.c_int64()
+        check(lib().cmh_mdn_sizes(C.byref(n), C.byref(nh)))
+        self.n_params = n.value
+        nb = C.c_size_t()
+        check(lib().cmh_mdn_param_bytes(C.byref(nb)))
+        self.device = device
+        self.params = torch.zeros(nb.value, dtype=torch.uint8, device=device)
+        self._work = None
+        self._rows = 0
+        if seed is not None:
+            check(lib().cmh_mdn_init(_ptr(self.params), seed, _stream()))
+
+    def work(self, rows: int):
+        import torch
+        if self._work is None or rows > self._rows:
+            nb = C.c_size_t()
+            check(lib().cmh_mdn_work_bytes(rows, C.byref(nb)))
+            self._work = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            self._rows = rows
+        return self._work
+
+    def set_params(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.n_params
+        check(lib().cmh_mdn_set_params(_ptr(self.params), _ptr(flat), _stream()))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().cmh_mdn_get_params(_ptr(self.params), _ptr(out)))
+        return out
+
+    def forward(self, X):
+        """X: bfloat16 device tensor [rows, 576] -> float32 [rows, 64]."""
+        import torch
+        rows = X.shape[0]
+        out = torch.empty((rows, 64), dtype=torch.float32, device=self.device)
+        w = self.work(rows)
+        check(lib().cmh_mdn_forward(_ptr(self.params), _ptr(X), rows, _ptr(out), _ptr(w),
+                                    w.numel(), _stream()))
+        return out
+
+    def gradients(self, X, Z):
+        import torch
+        rows = X.shape[0]
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        loss = torch.empty(rows, dtype=torch.float32, device=self.device)
+        w = self.work(rows)
+        check(lib().cmh_mdn_gradients(_ptr(self.params), _ptr(X), _ptr(Z), rows, _ptr(grad),
+                                      _ptr(loss), _ptr(w), w.numel(), _stream()))
+        return loss, grad
+
+    def train_step(self, X, Z, step: int, lr: float, loss=None):
+        rows = X.shape[0]
+        w = self.work(rows)
+        check(lib().cmh_mdn_train_step(_ptr(self.params), _ptr(X), _ptr(Z), rows, step, lr,
+                                       None if loss is None else _ptr(loss), _ptr(w), w.numel(),
+                                       _stream()))
+
+
+def mdn_pairs(model: ModelSpec, seed: int, first: int, count: int, device="cuda"):
+    """Training pairs from the forward simulator: (bf16 [count, 576], f32 [count, 3])."""
+    import torch
+    X = torch.empty((count, 576), dtype=torch.bfloat16, device=device)
+    Z = torch.empty((count, 3), dtype=torch.float32, device=device)
+    m = model_struct(model)
+    check(lib().cmh_mdn_pairs(C.byref(m), seed, first, count, _ptr(X), _ptr(Z), _stream()))
+    return X, Z
+
+
+def anchor_count(model: ModelSpec):
+    na, nt = C.c_int32(), C.c_int32()
+    m = model_struct(model)
+    check(lib().cmh_anchor_count(C.byref(m), C.byref(na), C.byref(nt)))
+    return na.value, nt.value
+
+
+def anchor_features(model: ModelSpec, trace):
+    """(bf16 [anchors, 576], f64 [anchors]) features and weights of a device trace."""
+    import torch
+    na, _ = anchor_count(model)
+    X = torch.empty((na, 576), dtype=torch.bfloat16, device=trace.device)
+    wts = torch.empty(na, dtype=torch.float64, device=trace.device)
+    m = model_struct(model)
+    check(lib().cmh_anchor_features(C.byref(m), _ptr(trace),
+                                    CMH_F64 if trace.dtype == torch.float64 else CMH_F32,
+                                    _ptr(X), _ptr(wts), _stream()))
+    return X, wts

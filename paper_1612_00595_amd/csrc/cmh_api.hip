@@ -5,6 +5,7 @@
 #include "chromh.h"
 #include "cmh_common.hpp"
 #include "cmh_kernels.hpp"
+#include "cmh_mdn.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -935,6 +936,222 @@ int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t r
     if (count == 0) return CMH_OK;
     HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, out_dev,
                              (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- learned proposal
+namespace {
+
+void model_geo(const cmh_model *m, Geo *g)
+{
+    std::memset(g, 0, sizeof *g);
+    g->nsx = m->nsx; g->nsy = m->nsy; g->nsta = m->nsx * m->nsy; g->ts = m->t_s;
+    g->N = (int)m->n_samples;
+    g->ds = m->ds; g->sigma2 = m->sigma * m->sigma; g->atten = m->atten; g->vel = m->velocity;
+    g->decay = m->env_decay; g->rc = m->r_c; g->lambda = m->lambda; g->mmin = m->mag_min;
+    g->mrate = m->mag_rate;
+    g->att2 = 2.0 / g->atten; g->dec2 = 2.0 / g->decay;
+    g->Lx = (double)m->nsx * m->ds; g->Ly = (double)m->nsy * m->ds;
+}
+
+struct MdnBlob {
+    float *params;
+    __bf16 *hcopy;
+};
+
+size_t mdn_param_bytes()
+{
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    return align_up((size_t)3 * L.np * 4) + align_up((size_t)L.nh * 2);
+}
+
+MdnBlob mdn_blob(const void *p)
+{
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    MdnBlob b;
+    b.params = (float *)p;
+    b.hcopy = (__bf16 *)((char *)p + align_up((size_t)3 * L.np * 4));
+    return b;
+}
+
+size_t carve_mdn_work(int M, char *base, cmh::MdnBuffers *B, float **grad)
+{
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    Carver c{base};
+    cmh::MdnBuffers b;
+    const size_t mh = (size_t)M * cmh::kMdnHid, mo = (size_t)M * cmh::kMdnOutPad;
+    for (int l = 0; l < 3; ++l) b.Z[l] = c.take<float>(mh);
+    for (int l = 0; l < 3; ++l) b.A[l] = c.take<__bf16>(mh);
+    b.O = c.take<float>(mo);
+    b.dO = c.take<__bf16>(mo);
+    b.dA = c.take<float>(mh);
+    b.dH[0] = c.take<__bf16>(mh);
+    b.dH[1] = c.take<__bf16>(mh);
+    b.loss = c.take<float>((size_t)M);
+    float *gr = c.take<float>((size_t)L.np);
+    if (B) *B = b;
+    if (grad) *grad = gr;
+    return align_up(c.off);
+}
+
+int32_t check_rows(int32_t rows) { return rows >= 1 && rows <= (1 << 20) ? CMH_OK : fail(CMH_EINVAL, "rows must be in 1..2^20"); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t cmh_mdn_sizes(int64_t *n_params, int64_t *n_weights_bf16)
+{
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    if (n_params) *n_params = L.np;
+    if (n_weights_bf16) *n_weights_bf16 = L.nh;
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_param_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = mdn_param_bytes();
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_init(void *params_dev, uint32_t seed, void *hip_stream)
+{
+    if (!params_dev) return fail(CMH_EINVAL, "params_dev is NULL");
+    const MdnBlob b = mdn_blob(params_dev);
+    HIPCHK(cmh::mdn_init(b.params, b.hcopy, seed, (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_set_params(void *params_dev, const float *host, void *hip_stream)
+{
+    if (!params_dev || !host) return fail(CMH_EINVAL, "NULL argument");
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    const MdnBlob b = mdn_blob(params_dev);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(hipMemcpyAsync(b.params, host, (size_t)L.np * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(b.params + L.np, 0, (size_t)2 * L.np * 4, s));
+    HIPCHK(cmh::mdn_refresh_copies(b.params, b.hcopy, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_get_params(const void *params_dev, float *host)
+{
+    if (!params_dev || !host) return fail(CMH_EINVAL, "NULL argument");
+    const cmh::MdnLayout L = cmh::mdn_layout();
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(host, params_dev, (size_t)L.np * 4, hipMemcpyDeviceToHost));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_work_bytes(int32_t rows, size_t *bytes)
+{
+    int32_t rc = check_rows(rows);
+    if (rc) return rc;
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = carve_mdn_work(rows, nullptr, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
+                        void *work_dev, size_t work_bytes, void *hip_stream)
+{
+    int32_t rc = check_rows(rows);
+    if (rc) return rc;
+    if (!params_dev || !x_dev || !out_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "work buffer too small");
+    cmh::MdnBuffers B;
+    carve_mdn_work(rows, (char *)work_dev, &B, nullptr);
+    B.O = out_dev;
+    const MdnBlob b = mdn_blob(params_dev);
+    HIPCHK(cmh::mdn_forward(b.params, b.hcopy, (const __bf16 *)x_dev, rows, B,
+                            (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_gradients(const void *params_dev, const void *x_dev, const float *z_dev,
+                          int32_t rows, float *grad_dev, float *loss_dev, void *work_dev,
+                          size_t work_bytes, void *hip_stream)
+{
+    int32_t rc = check_rows(rows);
+    if (rc) return rc;
+    if (!params_dev || !x_dev || !z_dev || !grad_dev || !work_dev)
+        return fail(CMH_EINVAL, "NULL argument");
+    if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "work buffer too small");
+    cmh::MdnBuffers B;
+    carve_mdn_work(rows, (char *)work_dev, &B, nullptr);
+    if (loss_dev) B.loss = loss_dev;
+    const MdnBlob b = mdn_blob(params_dev);
+    HIPCHK(cmh::mdn_backward(b.params, b.hcopy, (const __bf16 *)x_dev, z_dev, rows, B, grad_dev,
+                             (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_train_step(void *params_dev, const void *x_dev, const float *z_dev, int32_t rows,
+                           int32_t step, float lr, float *loss_dev, void *work_dev,
+                           size_t work_bytes, void *hip_stream)
+{
+    int32_t rc = check_rows(rows);
+    if (rc) return rc;
+    if (step < 1) return fail(CMH_EINVAL, "Adam steps count from 1");
+    if (!params_dev || !x_dev || !z_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "work buffer too small");
+    cmh::MdnBuffers B;
+    float *grad = nullptr;
+    carve_mdn_work(rows, (char *)work_dev, &B, &grad);
+    if (loss_dev) B.loss = loss_dev;
+    const MdnBlob b = mdn_blob(params_dev);
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(cmh::mdn_backward(b.params, b.hcopy, (const __bf16 *)x_dev, z_dev, rows, B, grad, s));
+    HIPCHK(cmh::mdn_adam(b.params, b.hcopy, grad, step, lr, s));
+    return CMH_OK;
+}
+
+int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair, int32_t count,
+                      void *x_dev, float *z_dev, void *hip_stream)
+{
+    int32_t rc = check_model(model);
+    if (rc) return rc;
+    if (count < 0 || first_pair < 0 || (count > 0 && (!x_dev || !z_dev)))
+        return fail(CMH_EINVAL, "bad arguments");
+    Geo g;
+    model_geo(model, &g);
+    HIPCHK(cmh::mdn_pairs(g, seed, first_pair, count, (__bf16 *)x_dev, z_dev,
+                          (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_tau)
+{
+    int32_t rc = check_model(model);
+    if (rc) return rc;
+    if (model->nsx < 3 || model->nsy < 3 || model->n_samples < cmh::kMdnWin + 3)
+        return fail(CMH_EINVAL, "anchors need a 3x3 station grid and 67 samples");
+    const int ntau = (int)((model->n_samples - (cmh::kMdnWin + 3)) / cmh::kMdnTScale) + 1;
+    if (n_tau) *n_tau = ntau;
+    if (n_anchors) *n_anchors = (model->nsx - 2) * (model->nsy - 2) * ntau;
+    return CMH_OK;
+}
+
+int32_t cmh_anchor_features(const cmh_model *model, const void *trace_dev, int32_t trace_dtype,
+                            void *x_dev, double *w_dev, void *hip_stream)
+{
+    int32_t na = 0, ntau = 0;
+    int32_t rc = cmh_anchor_count(model, &na, &ntau);
+    if (rc) return rc;
+    if (!trace_dev || !x_dev || !w_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    Geo g;
+    model_geo(model, &g);
+    HIPCHK(cmh::anchor_features(g, trace_dev, trace_dtype == CMH_F64, ntau, (__bf16 *)x_dev, w_dev,
+                                (hipStream_t)hip_stream));
     return CMH_OK;
 }
 

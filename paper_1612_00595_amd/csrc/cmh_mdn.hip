@@ -1,0 +1,500 @@
+// cmh_mdn.hip -- the learned birth proposal's network: a mixture-density
+// MLP (576 -> 256 -> 256 -> 256 -> 8 Gaussian components over (x, y, t)),
+// its training pairs and its input features.
+//
+//   k_gemm          C = op(A) op(B), BF16 operands on 16x16x32 MFMA tiles with
+//                   FP32 accumulation, fused bias / GELU epilogues
+//   k_mdn_loss      mixture negative log-likelihood and its gradient
+//   k_gelu_back     dH = dA * GELU'(H), rounded to BF16
+//   k_bias_grad     column sums
+//   k_adam          Adam on FP32 master weights, BF16 copies refreshed
+//   k_sim_pairs     simulator-generated (window features, event) pairs
+//   k_anchor_feat   window features and weights of an instance's anchors
+//   k_mdn_init      Glorot-uniform initial weights from Philox
+//
+// Feature definition (both for pairs and anchors): for the 3x3 block of
+// stations around a centre station (row-major), the log envelope
+// e[n] = ln(sigma^2 + mean(s[n..n+3]^2)) - ln(sigma^2) over 64 samples from
+// the window start, rounded to binary32 and then to BF16.
+#include "cmh_common.hpp"
+#include "cmh_mdn.hpp"
+
+#include <math.h>
+
+namespace cmh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double gelu_d(double z) { return 0.5 * z * (1.0 + erf(z * M_SQRT1_2)); }
+__device__ inline float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * (float)M_SQRT1_2)); }
+__device__ inline float gelu_grad_f(float z)
+{
+    return 0.5f * (1.0f + erff(z * (float)M_SQRT1_2)) +
+           z * expf(-0.5f * z * z) * (float)(0.5 * M_2_SQRTPI * M_SQRT1_2);
+}
+
+// -------------------------------------------------------------------- GEMM
+// C[M][N] = sum_k op(A)[m][k] op(B)[k][n].  op(A)[m][k] = TA ? A[k*lda + m]
+// : A[m*lda + k]; op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64x64 tile
+// per workgroup, four waves of 32x32, k-steps of 32 staged through LDS.
+// EPI 0: C (fp32).  EPI 1: Z = C + bias (fp32) and GELU(Z) as BF16 into Cb.
+// EPI 2: C + bias (fp32).
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256)
+k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
+       int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
+       __bf16 *__restrict__ Cb, int ldcb)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sA[64][40];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[64][40];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const __bf16 zero = (__bf16)0.0f;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        for (int e = tid; e < 2048; e += 256) {
+            const int r = TA ? (e & 63) : (e >> 5), c = TA ? (e >> 6) : (e & 31);
+            const int gi = i0 + r, gk = k0 + c;
+            sA[r][c] = (gi < M && gk < K) ? (TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk])
+                                          : zero;
+        }
+        for (int e = tid; e < 2048; e += 256) {
+            const int r = TB ? (e >> 5) : (e & 63), c = TB ? (e & 31) : (e >> 6);
+            const int gj = j0 + r, gk = k0 + c;
+            sB[r][c] = (gj < N && gk < K) ? (TB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj])
+                                          : zero;
+        }
+        __syncthreads();
+        const int kk = 8 * (lane >> 4);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const bf16x8 fa = *(const bf16x8 *)&sA[wi + 16 * a + (lane & 15)][kk];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const bf16x8 fb = *(const bf16x8 *)&sB[wj + 16 * b + (lane & 15)][kk];
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[a][b], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wi + 16 * a + 4 * (lane >> 4) + v;
+                const int j = j0 + wj + 16 * b + (lane & 15);
+                if (i >= M || j >= N) continue;
+                float z = acc[a][b][v];
+                if (EPI != 0) z += bias[j];
+                C[(long)i * ldc + j] = z;
+                if (EPI == 1) Cb[(long)i * ldcb + j] = (__bf16)gelu_f(z);
+            }
+}
+
+// dH = dA * GELU'(Z), BF16.
+__global__ void k_gelu_back(long n, const float *__restrict__ dA, const float *__restrict__ Z,
+                            __bf16 *__restrict__ dH)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        dH[q] = (__bf16)(dA[q] * gelu_grad_f(Z[q]));
+}
+
+// db[j] = sum_m D[m][j] for BF16 or FP32 D (one thread per column, fixed order).
+template <typename T>
+__global__ void k_bias_grad(int M, int N, const T *__restrict__ D, int ldd, float *__restrict__ db)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += (float)D[(long)m * ldd + j];
+    db[j] = s;
+}
+
+// Mixture negative log-likelihood of the targets and its gradient w.r.t. the
+// head outputs, per sample (one thread each).  Head layout, component k:
+// [7k] logit, [7k+1..3] means, [7k+4..6] log standard deviations, clamped to
+// [slo_d, shi_d].  Gradients are divided by M (mean loss).
+__global__ void k_mdn_loss(int M, const float *__restrict__ O, int ldo,
+                           const float *__restrict__ Zt, float *__restrict__ loss,
+                           __bf16 *__restrict__ dO, int lddo)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const float *o = O + (long)m * ldo;
+    const float z[3] = {Zt[3 * m], Zt[3 * m + 1], Zt[3 * m + 2]};
+    const float slo[3] = {kMdnSloXY, kMdnSloXY, kMdnSloT}, shi[3] = {kMdnShiXY, kMdnShiXY, kMdnShiT};
+    float lmax = -1e30f;
+    for (int k = 0; k < kMdnK; ++k) lmax = fmaxf(lmax, o[7 * k]);
+    float lse = 0.f;
+    for (int k = 0; k < kMdnK; ++k) lse += expf(o[7 * k] - lmax);
+    lse = lmax + logf(lse);
+    float ell[kMdnK], best = -1e30f;
+    for (int k = 0; k < kMdnK; ++k) {
+        float l = o[7 * k] - lse;
+        for (int d = 0; d < 3; ++d) {
+            const float s = fminf(fmaxf(o[7 * k + 4 + d], slo[d]), shi[d]);
+            const float u = (z[d] - o[7 * k + 1 + d]) * expf(-s);
+            l += -0.5f * u * u - s - 0.9189385332046727f;
+        }
+        ell[k] = l;
+        best = fmaxf(best, l);
+    }
+    float tot = 0.f;
+    for (int k = 0; k < kMdnK; ++k) tot += expf(ell[k] - best);
+    const float logp = best + logf(tot);
+    loss[m] = -logp;
+    const float inv = 1.0f / (float)M;
+    __bf16 *g = dO + (long)m * lddo;
+    for (int k = 0; k < kMdnK; ++k) {
+        const float gam = expf(ell[k] - logp);
+        const float pik = expf(o[7 * k] - lse);
+        g[7 * k] = (__bf16)((pik - gam) * inv);
+        for (int d = 0; d < 3; ++d) {
+            const float sr = o[7 * k + 4 + d];
+            const float s = fminf(fmaxf(sr, slo[d]), shi[d]);
+            const float is = expf(-s);
+            const float u = (z[d] - o[7 * k + 1 + d]) * is;
+            g[7 * k + 1 + d] = (__bf16)(-gam * u * is * inv);
+            const bool free = sr > slo[d] && sr < shi[d];
+            g[7 * k + 4 + d] = (__bf16)(free ? -gam * (u * u - 1.0f) * inv : 0.0f);
+        }
+    }
+    for (int c = 7 * kMdnK; c < lddo; ++c) g[c] = (__bf16)0.0f;
+}
+
+// Adam (Kingma & Ba) with bias correction on FP32 master weights; the BF16
+// copy of a weight matrix is refreshed in the same pass (wb may be null).
+__global__ void k_adam(long n, float *__restrict__ w, float *__restrict__ mo, float *__restrict__ ve,
+                       const float *__restrict__ g, __bf16 *__restrict__ wb, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x) {
+        const float gq = g[q];
+        const float m = b1 * mo[q] + (1.f - b1) * gq;
+        const float v = b2 * ve[q] + (1.f - b2) * gq * gq;
+        mo[q] = m;
+        ve[q] = v;
+        const float wn = w[q] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+        w[q] = wn;
+        if (wb) wb[q] = (__bf16)wn;
+    }
+}
+
+__global__ void k_to_bf16(long n, const float *__restrict__ w, __bf16 *__restrict__ wb)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        wb[q] = (__bf16)w[q];
+}
+
+// Glorot-uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)), from
+// Philox under key (seed, 0x80000004), counter (parameter index, 0, 0, 0);
+// biases zero; padded head rows zero.
+__global__ void k_mdn_init(float *__restrict__ W, long n, int fan_in, int fan_out, int rows_live,
+                           long offset, uint32_t seed)
+{
+    const double a = sqrt(6.0 / (double)(fan_in + fan_out));
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x) {
+        if (q / fan_in >= rows_live) {
+            W[q] = 0.f;
+            continue;
+        }
+        uint32_t c[4] = {(uint32_t)(offset + q), (uint32_t)((offset + q) >> 32), 0u, 0u};
+        philox10(c, seed, 0x80000004u);
+        W[q] = (float)((2.0 * unit_open(c[0], c[1]) - 1.0) * a);
+    }
+}
+
+// --------------------------------------------------------------- features
+// Rounds a binary64 feature to binary32 and then to BF16.
+__device__ inline __bf16 feat_bf16(double v) { return (__bf16)(float)v; }
+
+// One training pair per wave: a local world around a centre station at the
+// origin (3x3 block of stations at spacing ds), one target event and
+// kMdnBg background events, the block's traces over samples [0, 67) of the
+// window, and the 576 window features.  Draws: key (seed, 0x80000003);
+// counter (pair, 0, 0, c) for the events (c = 0 target x, y; c = 1 target t,
+// magnitude; c = 2 + b background event b x, y; c = 2 + kMdnBg + b its t,
+// magnitude); counter (pair, 1 + station, n / 2, 0) for the noise.
+__global__ void __launch_bounds__(64)
+k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__restrict__ Zt)
+{
+    __shared__ double s_ev[kMdnBg + 1][4];
+    __shared__ double s_q[9][kMdnWin + 4];
+    const long p = first + blockIdx.x;
+    const int lane = threadIdx.x;
+    if (lane <= kMdnBg) {
+        uint32_t c0[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, (uint32_t)(lane == 0 ? 0 : 2 + (lane - 1))};
+        uint32_t c1[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u,
+                          (uint32_t)(lane == 0 ? 1 : 2 + kMdnBg + (lane - 1))};
+        philox10(c0, seed, 0x80000003u);
+        philox10(c1, seed, 0x80000003u);
+        const double ux = unit_open(c0[0], c0[1]), uy = unit_open(c0[2], c0[3]);
+        const double ut = unit_open(c1[0], c1[1]), um = unit_open(c1[2], c1[3]);
+        double x, y, t;
+        if (lane == 0) {
+            x = (2.0 * ux - 1.0) * g.ds;
+            y = (2.0 * uy - 1.0) * g.ds;
+            t = -16.0 + ut * 80.0;
+        } else {
+            const double half = 1.5 * g.ds + g.rc;
+            x = (2.0 * ux - 1.0) * half;
+            y = (2.0 * uy - 1.0) * half;
+            t = -(double)(g.ts + 8) + ut * (double)(kMdnWin + g.ts + 16);
+        }
+        s_ev[lane][0] = x;
+        s_ev[lane][1] = y;
+        s_ev[lane][2] = t;
+        s_ev[lane][3] = g.mmin - log(um) / g.mrate;
+    }
+    __syncthreads();
+    const int nsamp = kMdnWin + 3;
+    for (int e = lane; e < 9 * nsamp; e += 64) {
+        const int b = e / nsamp, n = e % nsamp;
+        const double sx = (double)(b % 3 - 1) * g.ds, sy = (double)(b / 3 - 1) * g.ds;
+        double E = 0.0;
+        for (int q = 0; q <= kMdnBg; ++q) {
+            const double dx = s_ev[q][0] - sx, dy = s_ev[q][1] - sy;
+            const double d = sqrt(dx * dx + dy * dy);
+            if (!(d < g.rc)) continue;
+            const double a = s_ev[q][2] + d / g.vel;
+            const double n0 = ceil(a);
+            if ((double)n < n0 || (double)n >= n0 + g.ts) continue;
+            const double amp = s_ev[q][3] * exp(-d / g.atten);
+            const double env = exp(-((double)n - a) / g.decay);
+            E += (amp * env) * (amp * env);
+        }
+        uint32_t c[4] = {(uint32_t)p, (uint32_t)(p >> 32), (uint32_t)(1 + b), (uint32_t)(n >> 1)};
+        philox10(c, seed, 0x80000003u);
+        const double u1 = unit_open(c[0], c[1]), u2 = unit_open(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double zz = (n & 1) ? rad * sin(2.0 * M_PI * u2) : rad * cos(2.0 * M_PI * u2);
+        const double sv = sqrt(g.sigma2 + E) * zz;
+        s_q[b][n] = sv * sv;
+    }
+    __syncthreads();
+    const double ls2 = log(g.sigma2);
+    __bf16 *xo = X + (long)blockIdx.x * kMdnIn;
+    for (int e = lane; e < kMdnIn; e += 64) {
+        const int b = e / kMdnWin, n = e % kMdnWin;
+        const double m4 = (s_q[b][n] + s_q[b][n + 1] + s_q[b][n + 2] + s_q[b][n + 3]) * 0.25;
+        xo[e] = feat_bf16(log(g.sigma2 + m4) - ls2);
+    }
+    if (lane == 0) {
+        Zt[3 * (long)blockIdx.x + 0] = (float)(s_ev[0][0] / g.ds);
+        Zt[3 * (long)blockIdx.x + 1] = (float)(s_ev[0][1] / g.ds);
+        Zt[3 * (long)blockIdx.x + 2] = (float)(s_ev[0][2] / (double)kMdnTScale);
+    }
+}
+
+// Window features and weight of every anchor of an instance: anchor a =
+// (centre station c, window start tau), c over the interior stations in
+// row-major order, tau = 32 i for tau + 67 <= N.  Weight:
+// 1e-3 + mean over the 576 features of max(0, f - 1).
+template <typename TraceT>
+__global__ void __launch_bounds__(64)
+k_anchor_feat(Geo g, const TraceT *__restrict__ trace, int ntau, __bf16 *__restrict__ X,
+              double *__restrict__ wout)
+{
+    __shared__ double s_f[kMdnIn];
+    const int a = blockIdx.x, lane = threadIdx.x;
+    const int c = a / ntau, ti = a % ntau;
+    const int icx = g.nsx - 2;
+    const int cx = 1 + c % icx, cy = 1 + c / icx;
+    const int tau = kMdnTScale * ti;
+    const double ls2 = log(g.sigma2);
+    for (int e = lane; e < kMdnIn; e += 64) {
+        const int b = e / kMdnWin, n = e % kMdnWin;
+        const int j = (cy + b / 3 - 1) * g.nsx + (cx + b % 3 - 1);
+        const TraceT *row = trace + (long)j * g.N + tau + n;
+        double acc = 0.0;
+        for (int u = 0; u < 4; ++u) {
+            const double v = (double)row[u];
+            acc += v * v;
+        }
+        const double f = log(g.sigma2 + acc * 0.25) - ls2;
+        const __bf16 fb = feat_bf16(f);
+        X[(long)a * kMdnIn + e] = fb;
+        s_f[e] = (double)(float)fb;
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int e = lane; e < kMdnIn; e += 64) s += s_f[e] > 1.0 ? s_f[e] - 1.0 : 0.0;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) wout[a] = 1e-3 + s / (double)kMdnIn;
+}
+
+// ------------------------------------------------------------- launchers
+template <bool TA, bool TB, int EPI>
+static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
+                       float *C, int ldc, const float *bias, __bf16 *Cb, int ldcb, hipStream_t s)
+{
+    const dim3 grid((N + 63) / 64, (M + 63) / 64);
+    k_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Cb, ldcb);
+    return hipGetLastError();
+}
+
+static unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
+
+MdnLayout mdn_layout()
+{
+    MdnLayout L;
+    long o = 0;
+    const int fin[4] = {kMdnIn, kMdnHid, kMdnHid, kMdnHid};
+    const int fout[4] = {kMdnHid, kMdnHid, kMdnHid, kMdnOutPad};
+    for (int l = 0; l < 4; ++l) {
+        L.W[l] = o; L.fin[l] = fin[l]; L.fout[l] = fout[l];
+        o += (long)fin[l] * fout[l];
+        L.b[l] = o;
+        o += fout[l];
+    }
+    L.np = o;
+    long h = 0;
+    for (int l = 0; l < 4; ++l) {
+        L.Wh[l] = h;
+        h += (long)L.fin[l] * L.fout[l];
+    }
+    L.nh = h;
+    return L;
+}
+
+hipError_t mdn_init(float *params, __bf16 *hcopy, uint32_t seed, hipStream_t s)
+{
+    const MdnLayout L = mdn_layout();
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < 4 && !e; ++l) {
+        const long n = (long)L.fin[l] * L.fout[l];
+        const int live = l == 3 ? 7 * kMdnK : L.fout[l];
+        k_mdn_init<<<grid_for(n), 256, 0, s>>>(params + L.W[l], n, L.fin[l],
+                                              l == 3 ? 7 * kMdnK : L.fout[l], live, L.W[l], seed);
+        e = hipGetLastError();
+        if (!e) e = hipMemsetAsync(params + L.b[l], 0, sizeof(float) * L.fout[l], s);
+    }
+    // Adam moments
+    if (!e) e = hipMemsetAsync(params + L.np, 0, sizeof(float) * 2 * L.np, s);
+    if (!e) e = mdn_refresh_copies(params, hcopy, s);
+    return e;
+}
+
+hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s)
+{
+    const MdnLayout L = mdn_layout();
+    for (int l = 0; l < 4; ++l) {
+        const long n = (long)L.fin[l] * L.fout[l];
+        k_to_bf16<<<grid_for(n), 256, 0, s>>>(n, params + L.W[l], hcopy + L.Wh[l]);
+        hipError_t e = hipGetLastError();
+        if (e) return e;
+    }
+    return hipSuccess;
+}
+
+// Forward pass for M rows of features.  Buffers: Z[l] fp32 pre-activations
+// and A[l] BF16 activations of the three hidden layers, O fp32 head output.
+hipError_t mdn_forward(const float *params, const __bf16 *hcopy, const __bf16 *X, int M,
+                       const MdnBuffers &B, hipStream_t s)
+{
+    const MdnLayout L = mdn_layout();
+    hipError_t e;
+    const __bf16 *in = X;
+    int kin = kMdnIn;
+    for (int l = 0; l < 3; ++l) {
+        e = gemm<false, true, 1>(M, kMdnHid, kin, in, kin, hcopy + L.Wh[l], kin, B.Z[l], kMdnHid,
+                                 params + L.b[l], B.A[l], kMdnHid, s);
+        if (e) return e;
+        in = B.A[l];
+        kin = kMdnHid;
+    }
+    return gemm<false, true, 2>(M, kMdnOutPad, kMdnHid, in, kMdnHid, hcopy + L.Wh[3], kMdnHid,
+                                B.O, kMdnOutPad, params + L.b[3], nullptr, 0, s);
+}
+
+// Loss and gradients of the mean mixture NLL w.r.t. every parameter (into
+// grad, laid out like the FP32 parameters).
+hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *X, const float *Zt,
+                        int M, const MdnBuffers &B, float *grad, hipStream_t s)
+{
+    const MdnLayout L = mdn_layout();
+    hipError_t e = mdn_forward(params, hcopy, X, M, B, s);
+    if (e) return e;
+    k_mdn_loss<<<(M + 127) / 128, 128, 0, s>>>(M, B.O, kMdnOutPad, Zt, B.loss, B.dO, kMdnOutPad);
+    if ((e = hipGetLastError())) return e;
+    // head: dW4 = dO^T A3, db4 = sum dO, dA3 = dO W4
+    e = gemm<true, false, 0>(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid,
+                             grad + L.W[3], kMdnHid, nullptr, nullptr, 0, s);
+    if (e) return e;
+    k_bias_grad<__bf16><<<1, 64, 0, s>>>(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3]);
+    if ((e = hipGetLastError())) return e;
+    const __bf16 *dnext = B.dO;
+    int nout = kMdnOutPad;
+    for (int l = 2; l >= 0; --l) {
+        // dA_l = dOut W_{l+1}; dH_l = dA_l * GELU'(Z_l)
+        e = gemm<false, false, 0>(M, kMdnHid, nout, dnext, nout, hcopy + L.Wh[l + 1], kMdnHid,
+                                  B.dA, kMdnHid, nullptr, nullptr, 0, s);
+        if (e) return e;
+        const long n = (long)M * kMdnHid;
+        k_gelu_back<<<grid_for(n), 256, 0, s>>>(n, B.dA, B.Z[l], B.dH[l & 1]);
+        if ((e = hipGetLastError())) return e;
+        const __bf16 *in = l == 0 ? X : B.A[l - 1];
+        const int kin = l == 0 ? kMdnIn : kMdnHid;
+        e = gemm<true, false, 0>(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l],
+                                 kin, nullptr, nullptr, 0, s);
+        if (e) return e;
+        k_bias_grad<__bf16><<<(kMdnHid + 63) / 64, 64, 0, s>>>(M, kMdnHid, B.dH[l & 1], kMdnHid,
+                                                               grad + L.b[l]);
+        if ((e = hipGetLastError())) return e;
+        dnext = B.dH[l & 1];
+        nout = kMdnHid;
+    }
+    return hipSuccess;
+}
+
+hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, float lr,
+                    hipStream_t s)
+{
+    const MdnLayout L = mdn_layout();
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    float *mo = params + L.np, *ve = params + 2 * L.np;
+    for (int l = 0; l < 4; ++l) {
+        const long nw = (long)L.fin[l] * L.fout[l];
+        k_adam<<<grid_for(nw), 256, 0, s>>>(nw, params + L.W[l], mo + L.W[l], ve + L.W[l],
+                                           grad + L.W[l], hcopy + L.Wh[l], lr, b1, b2, eps, c1, c2);
+        hipError_t e = hipGetLastError();
+        if (e) return e;
+        k_adam<<<1, 256, 0, s>>>(L.fout[l], params + L.b[l], mo + L.b[l], ve + L.b[l],
+                                 grad + L.b[l], nullptr, lr, b1, b2, eps, c1, c2);
+        if ((e = hipGetLastError())) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t mdn_pairs(const Geo &g, uint32_t seed, long first, int count, __bf16 *X, float *Zt,
+                     hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    k_sim_pairs<<<count, 64, 0, s>>>(g, seed, first, X, Zt);
+    return hipGetLastError();
+}
+
+hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, __bf16 *X, double *w,
+                           hipStream_t s)
+{
+    const int na = (g.nsx - 2) * (g.nsy - 2) * ntau;
+    if (na <= 0) return hipSuccess;
+    if (f64)
+        k_anchor_feat<double><<<na, 64, 0, s>>>(g, (const double *)trace, ntau, X, w);
+    else
+        k_anchor_feat<float><<<na, 64, 0, s>>>(g, (const float *)trace, ntau, X, w);
+    return hipGetLastError();
+}
+
+}  // namespace cmh

@@ -1,0 +1,59 @@
+// cmh_mdn.hpp -- constants, parameter layout and launchers of the
+// mixture-density network used by the learned birth proposal.
+#pragma once
+
+#include <algorithm>
+
+#include "cmh_common.hpp"
+
+namespace cmh {
+
+constexpr int kMdnWin = 64;             // envelope samples per station
+constexpr int kMdnIn = 9 * kMdnWin;     // 3x3 stations x 64 = 576 features
+constexpr int kMdnHid = 256;            // hidden width
+constexpr int kMdnK = 8;                // mixture components
+constexpr int kMdnOutPad = 64;          // 8 x 7 outputs padded to 64
+constexpr int kMdnBg = 3;               // background events per training pair
+constexpr int kMdnTScale = 32;          // window step and time unit, samples
+// clamps of the log standard deviations (x, y in units of ds; t in units of
+// 32 samples): sigma_xy in [0.025, 1.5] ds, sigma_t in [0.5, 32] samples
+constexpr float kMdnSloXY = -3.6888794541139363f;
+constexpr float kMdnShiXY = 0.4054651081081644f;
+constexpr float kMdnSloT = -4.1588830833596715f;
+constexpr float kMdnShiT = 0.0f;
+
+// FP32 parameter blob: for layer l, W[l] (fout x fin, row-major, the
+// layer's output index first) then b[l]; np floats.  The blob is followed by
+// the Adam first and second moments (np floats each).  BF16 copies of the
+// four weight matrices live in a separate array (offsets Wh[l], nh values).
+struct MdnLayout {
+    long W[4], b[4], Wh[4];
+    int fin[4], fout[4];
+    long np, nh;
+};
+MdnLayout mdn_layout();
+
+struct MdnBuffers {
+    float *Z[3];      // pre-activations, M x 256
+    __bf16 *A[3];     // GELU activations, M x 256
+    float *O;         // head output, M x 64
+    __bf16 *dO;       // d loss / d head output, M x 64
+    float *dA;        // M x 256
+    __bf16 *dH[2];    // M x 256
+    float *loss;      // M
+};
+
+hipError_t mdn_init(float *params, __bf16 *hcopy, uint32_t seed, hipStream_t s);
+hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s);
+hipError_t mdn_forward(const float *params, const __bf16 *hcopy, const __bf16 *X, int M,
+                       const MdnBuffers &B, hipStream_t s);
+hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *X, const float *Zt,
+                        int M, const MdnBuffers &B, float *grad, hipStream_t s);
+hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, float lr,
+                    hipStream_t s);
+hipError_t mdn_pairs(const Geo &g, uint32_t seed, long first, int count, __bf16 *X, float *Zt,
+                     hipStream_t s);
+hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, __bf16 *X, double *w,
+                           hipStream_t s);
+
+}  // namespace cmh
