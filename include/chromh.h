@@ -159,10 +159,14 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
  * move, the draws the sampler would otherwise take from Philox: [0] uniform
  * for the move type, [1] uniform a (index or birth x), [2] uniform b (birth
  * y), [3] uniform c (birth onset), [4] Exp(1) (birth magnitude), [5], [6]
- * standard normals, [7] log of the acceptance uniform.  Chain 0 only.
- * NULL detaches. */
+ * standard normals, [7] log of the acceptance uniform.  With learned births
+ * (cmh_set_learned) the records are [16]: the same 8, then [8] mixture
+ * uniform, [9] anchor uniform, [10] component uniform, [11..13] standard
+ * normals truncated to [-4, 4], [14], [15] unused.  width (8 or 16) states
+ * the record size; a sweep whose mode needs the other size fails with
+ * CMH_EINVAL before any launch.  Chain 0 only.  NULL detaches. */
 int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
-                     int64_t n_sweeps);
+                     int64_t n_sweeps, int32_t width);
 
 /* Move log.  log_dev: doubles [n_sweeps][regions][k][4] = move type,
  * status (0 rejected before the likelihood, 1 rejected, 2 accepted),
@@ -205,6 +209,32 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
 int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream,
                         float *ms_out);
 
+/* Learned birth proposal (the independence proposal of Section 3's MH
+ * ratio, its density entering the birth and death ratios).  A birth in a
+ * region R that holds at least one station draws, with probability
+ * p_learned, from q_R: an anchor a (station s in R, window i) with
+ * probability w_a / W_R, W_R the total weight of R's anchors, then component
+ * k of the anchor's mixture with probability pi_k, then (x, y, t) = mean +
+ * sd * (independent standard normals truncated to [-4, 4]), magnitude from
+ * the prior; otherwise it draws from the prior on R.  The birth and death
+ * ratios carry log(b / p_R) = log((1 - p_learned) + p_learned q_R(x, y, t)
+ * area(R) n_samples) at the born or dying event; the posterior is unchanged.
+ *   table_dev: [n_stations * n_tau][8][8] binary64, anchor a = station *
+ *     n_tau + window, per component (mean x, y, t, sd x, y, t, log pi_k,
+ *     pi_1 + ... + pi_k), as cmh_mixture_table writes it;
+ *   weights_dev: [n_stations * n_tau] positive anchor weights;
+ *   work_dev: cmh_learned_bytes(st, n_tau) bytes for the library's derived
+ *     arrays (weight running sums, component normalisers, the table's time
+ *     reach, per-sweep birth proposals).
+ * All three are caller-owned and must outlive their use.  p_learned in
+ * [0, 1).  table_dev NULL returns to plain births.  Regions may hold at most
+ * 16 stations (a larger one raises CMH_ESTATE at the next check).  Drops
+ * captured sweep graphs; enqueues the preparation on hip_stream. */
+int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes);
+int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *weights_dev,
+                        int32_t n_tau, double p_learned, void *work_dev, size_t work_bytes,
+                        void *hip_stream);
+
 int32_t cmh_destroy(cmh_state *st);
 
 /* Forward simulator (synthetic worlds sampled from the model, Section 5):
@@ -220,11 +250,13 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
                      uint32_t seed, void *trace_dev, int32_t trace_dtype,
                      void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
-/* Draw records [count][8] that chain `chain` takes for moves j0 .. j0+count-1
- * of region `region` in sweep `sweep` (the same layout as the feed), computed
- * on the device into out_dev.  Enqueues on hip_stream. */
+/* Draw records [count][width] (width 8, or 16 for learned births) that
+ * chain `chain` takes for moves j0 .. j0+count-1 of region `region` in sweep
+ * `sweep` (the same layout as the feed), computed on the device into
+ * out_dev.  Enqueues on hip_stream. */
 int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
-                       uint32_t j0, int32_t count, double *out_dev, void *hip_stream);
+                       uint32_t j0, int32_t count, int32_t width, double *out_dev,
+                       void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Learned birth proposal: a mixture-density network (MDN).
@@ -281,28 +313,46 @@ int32_t cmh_mdn_train_step(void *params_dev, const void *x_dev, const float *z_d
 
 /* Training pairs from the forward simulator (synthetic local worlds, as the
  * paper's evaluation samples worlds from the model): pair p is a 3x3 block of
- * stations around a centre at the origin, a target event uniform in
- * [-ds, ds)^2 with onset uniform in [-16, 64) samples of the window, and 3
- * background events uniform in [-(1.5 ds + r_c), 1.5 ds + r_c)^2 with onsets
- * in [-(t_s + 8), 64 + 8), magnitudes from the prior, traces over the
- * window's first 67 samples.  Draws: Philox under key (seed, 0x80000003):
- * counter (p mod 2^32, p div 2^32, 0, c) for the events (c = 0: target x, y;
- * 1: target t, m; 2 + b and 5 + b: background b's x, y and t, m), counter
- * (p mod 2^32, p div 2^32, 1 + station, n / 2) for the noise (Box-Muller,
- * even n cosine, odd n sine).  Writes x_dev[count]
- * [576] BF16 and the target offsets z_dev[count][3] = (x / ds, y / ds, t / 32). */
+ * stations around a centre at the origin.  An edge class drawn from counter
+ * c = 8 keeps all nine stations with probability 1/2, else (1/16 each) drops
+ * the block's column and/or row beyond a domain edge that lies half a
+ * spacing from the centre on that side.  A target event is uniform within
+ * one spacing of the centre inside the domain with onset uniform in [-16,
+ * 64) samples of the window; 3 background events are uniform within 1.5 ds +
+ * r_c of the centre inside the domain, onsets in [-(t_s + 8), 64 + 8);
+ * magnitudes from the prior; traces over the window's first 67 samples.
+ * Draws: Philox under key (seed, 0x80000003): counter (p mod 2^32, p div
+ * 2^32, 0, c) for the events (c = 0: target x, y; 1: target t, m; 2 + b and
+ * 5 + b: background b's x, y and t, m), counter (p mod 2^32, p div 2^32, 1 +
+ * station, n / 2) for the noise (Box-Muller, even n cosine, odd n sine).
+ * Writes x_dev[count][576] BF16 (0 for a dropped station) and the target
+ * offsets z_dev[count][3] = (x / ds, y / ds, t / 32). */
 int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair, int32_t count,
                       void *x_dev, float *z_dev, void *hip_stream);
 
-/* Anchors of an instance: centre station c over the interior stations
- * (1 <= ix <= nsx - 2, 1 <= iy <= nsy - 2, row-major) times window starts
- * tau = 32 i (tau + 67 <= n_samples); anchor index = c * n_tau + i. */
+/* Anchors of an instance: every station c (row-major) times window starts
+ * tau = 32 i (tau + 67 <= n_samples); anchor index = c * n_tau + i.
+ * CMH_EINVAL below 67 samples. */
 int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_tau);
 
-/* Every anchor's 576 BF16 features (x_dev[n_anchors][576]) and weight
- * w_dev[n_anchors] = 1e-3 + mean over its features of max(0, f - 1). */
+/* Anchors first .. first + count - 1: their 576 BF16 features (x_dev[count]
+ * [576]: the log envelopes of the 3x3 block of stations around the anchor's
+ * station over the window's 64 samples, 0 for block stations beyond the
+ * grid) and weights w_dev[count] = 1e-3 + mean over the features of
+ * max(0, f - 1), which rank windows by how far their envelopes rise above
+ * the noise.  The trace is device memory [nsta][n_samples]. */
 int32_t cmh_anchor_features(const cmh_model *model, const void *trace_dev, int32_t trace_dtype,
-                            void *x_dev, double *w_dev, void *hip_stream);
+                            int64_t first, int32_t count, void *x_dev, double *w_dev,
+                            void *hip_stream);
+
+/* Mixture table of anchors first .. first + rows - 1 from the network's head
+ * outputs head_dev[rows][64] (cmh_mdn_forward): table_dev[rows][8][8] in
+ * binary64, per component (mean x, mean y, mean t, sd x, sd y, sd t, log
+ * weight, cumulative weight), absolute units.  Means are clamped to within
+ * 2 spacings of the anchor's station and to [tau - 32, tau + 96]; sds to
+ * [0.025, 1.5] spacings and [0.5, 32] samples. */
+int32_t cmh_mixture_table(const cmh_model *model, const float *head_dev, int64_t first,
+                          int32_t rows, double *table_dev, void *hip_stream);
 
 #ifdef __cplusplus
 }

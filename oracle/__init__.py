@@ -119,6 +119,13 @@ def lib():
         L.orc_chain_overflows.restype = C.c_int64
         L.orc_chain_delta.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, P]
         L.orc_chain_delta.restype = C.c_double
+        L.orc_chain_set_learned.argtypes = [P, P, P, C.c_int32, C.c_double]
+        L.orc_chain_set_learned.restype = C.c_int32
+        L.orc_move_draws16.argtypes = [C.c_uint32] * 5 + [P]
+        L.orc_chain_learned_q.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_double]
+        L.orc_chain_learned_q.restype = C.c_double
+        L.orc_chain_learned_draw.argtypes = [P, C.c_int32, P, P]
+        L.orc_chain_learned_draw.restype = C.c_int32
         L.orc_lattice_nsites.argtypes = [P, P]
         L.orc_lattice_nsites.restype = C.c_int64
         L.orc_lattice_site.argtypes = [P, P, C.c_int64, P]
@@ -179,6 +186,12 @@ def u01(w0: int, w1: int) -> float:
 def move_draws(seed, chain, sweep, region, j) -> np.ndarray:
     out = np.zeros(8)
     lib().orc_move_draws(seed, chain, sweep, region, j, _ptr(out))
+    return out
+
+
+def move_draws16(seed, chain, sweep, region, j) -> np.ndarray:
+    out = np.zeros(16)
+    lib().orc_move_draws16(seed, chain, sweep, region, j, _ptr(out))
     return out
 
 
@@ -316,6 +329,27 @@ class Chain:
 
     def overflows(self) -> int:
         return lib().orc_chain_overflows(self._h)
+
+    def set_learned(self, table, weights, n_tau: int, p_learned: float = 0.5) -> int:
+        """Learned births from a mixture table [nsta * n_tau][8][8] and anchor
+        weights [nsta * n_tau] (both kept alive here); table None: off."""
+        if table is None:
+            self._ltab = self._lw = None
+            return lib().orc_chain_set_learned(self._h, None, None, 0, 0.0)
+        self._ltab = np.ascontiguousarray(table, dtype=np.float64)
+        self._lw = np.ascontiguousarray(weights, dtype=np.float64)
+        return lib().orc_chain_set_learned(self._h, _ptr(self._ltab), _ptr(self._lw), n_tau,
+                                           p_learned)
+
+    def learned_q(self, region, x, y, t) -> float:
+        return lib().orc_chain_learned_q(self._h, region, x, y, t)
+
+    def learned_draw(self, region, d16) -> np.ndarray:
+        d = np.ascontiguousarray(d16, dtype=np.float64)
+        out = np.zeros(3)
+        rc = lib().orc_chain_learned_draw(self._h, region, _ptr(d), _ptr(out))
+        assert rc == 0
+        return out
 
     def delta(self, region, mtype, idx, proposed) -> float:
         p = np.ascontiguousarray(proposed, dtype=EVENT_DTYPE).reshape(1)

@@ -127,21 +127,39 @@ def loss_and_grads(P: dict, X: np.ndarray, Z: np.ndarray, bf16: bool = True):
     return float(per_row.mean()), per_row, G
 
 
-def mixture_table(o: np.ndarray, centres: np.ndarray, taus: np.ndarray, ds: float) -> np.ndarray:
-    """Per-row mixture in absolute units: [rows][8][7] = (log pi, mu x, mu y,
-    mu t, sd x, sd y, sd t)."""
+MU_XY, MU_T_LO, MU_T_HI = 2.0, -1.0, 3.0
+
+
+def mixture_table(o: np.ndarray, nsx: int, ds: float, n_tau: int, first: int = 0) -> np.ndarray:
+    """Mixture table of anchors first .. first + rows - 1 (anchor a: station
+    a // n_tau in row-major order, window start 32 (a % n_tau)) from head
+    outputs: [rows][8][8] = (mean x, y, t, sd x, y, t, log weight,
+    cumulative weight) in absolute units, means clamped to +-2 spacings of
+    the station and to [tau - 32, tau + 96], log sds to the training clamps."""
+    o = np.asarray(o, dtype=np.float64)
+    rows = o.shape[0]
+    a = first + np.arange(rows)
+    c = a // n_tau
+    sx = ((c % nsx) + 0.5) * ds
+    sy = ((c // nsx) + 0.5) * ds
+    tau = 32.0 * (a % n_tau)
     K = N_K
     logit = o[:, 0:7 * K:7]
-    lse = np.log(np.sum(np.exp(logit - logit.max(1, keepdims=True)), 1)) + logit.max(1)
-    out = np.zeros((o.shape[0], K, 7))
-    out[..., 0] = logit - lse[:, None]
-    scale = np.array([ds, ds, 32.0])
+    lmax = logit.max(1, keepdims=True)
+    lse = lmax[:, 0] + np.log(np.sum(np.exp(logit - lmax), 1))
+    T = np.zeros((rows, K, 8))
+    T[..., 0] = sx[:, None] + ds * np.clip(o[:, 1:7 * K:7], -MU_XY, MU_XY)
+    T[..., 1] = sy[:, None] + ds * np.clip(o[:, 2:7 * K:7], -MU_XY, MU_XY)
+    T[..., 2] = tau[:, None] + 32.0 * np.clip(o[:, 3:7 * K:7], MU_T_LO, MU_T_HI)
+    scale = (ds, ds, 32.0)
     for d in range(3):
-        s = np.clip(o[:, 4 + d:7 * K:7], SLO[d], SHI[d])
-        base = centres[:, d][:, None] if d < 2 else taus[:, None]
-        out[..., 1 + d] = base + scale[d] * o[:, 1 + d:7 * K:7]
-        out[..., 4 + d] = scale[d] * np.exp(s)
-    return out
+        T[..., 3 + d] = scale[d] * np.exp(np.clip(o[:, 4 + d:7 * K:7], SLO[d], SHI[d]))
+    T[..., 6] = logit - lse[:, None]
+    cum = np.zeros(rows)
+    for k in range(K):                 # sequential running sum, as specified
+        cum = cum + np.exp(T[:, k, 6])
+        T[:, k, 7] = cum
+    return T
 
 
 # ------------------------------------------------------------- features

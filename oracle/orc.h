@@ -147,6 +147,15 @@ int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color,
                         const double *feed, double *log);
 int32_t orc_chain_sweep(orc_chain *c, int64_t sweep, const double *feed, double *log);
 int64_t orc_chain_count(const orc_chain *c);
+/* learned birth proposal: table [nsta * n_tau][8][8] of (mean x, y, t, sd x,
+ * y, t, log weight, cumulative weight) and anchor weights [nsta * n_tau],
+ * both kept by the caller; NULL table switches it off. */
+int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *weights,
+                              int32_t n_tau, double p_learned);
+void    orc_move_draws16(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                         uint32_t j, double out[16]);
+double  orc_chain_learned_q(orc_chain *c, int32_t region, double x, double y, double t);
+int32_t orc_chain_learned_draw(orc_chain *c, int32_t region, const double *d, double *out);
 int64_t orc_chain_events(const orc_chain *c, orc_event *out, int64_t cap);
 int32_t orc_chain_set_events(orc_chain *c, const orc_event *ev, int64_t nev);
 void    orc_chain_layout(const orc_chain *c, int32_t *nrx, int32_t *nry, int32_t *period,

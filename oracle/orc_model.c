@@ -440,44 +440,76 @@ static void log_envelope(double sigma, const double *q, double *f)
         f[n] = log(s2 + (q[n] + q[n + 1] + q[n + 2] + q[n + 3]) * 0.25) - log(s2);
 }
 
+/* Edge classes of a training pair: class 0 has all nine stations of the 3x3
+ * block; classes 1..8 drop the column (ex = -1 left, +1 right) and/or the row
+ * (ey) beyond the domain edge, which lies half a spacing from the centre on
+ * that side, in the order (-1,-1) (0,-1) (1,-1) (-1,0) (1,0) (-1,1) (0,1)
+ * (1,1).  A uniform u gives class 0 when 16u < 8, else class 16u - 7. */
+static void edge_class(double u, int *ex, int *ey)
+{
+    static const int tx[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+    static const int ty[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+    int k = (int)floor(u * 16.0);
+    if (k > 15) k = 15;
+    if (k < 8) {
+        *ex = 0;
+        *ey = 0;
+    } else {
+        *ex = tx[k - 8];
+        *ey = ty[k - 8];
+    }
+}
+
 /* Training pair p: a 3x3 block of stations (spacing ds) around a centre at
- * the origin, one target event and three background events drawn from
- * Philox under key (seed, 0x80000003), the block's traces over the window's
- * first 67 samples, features[9][64] and the target offset (x/ds, y/ds, t/32). */
+ * the origin, with the edge class drawn under counter (p, 0, 8); one target
+ * event uniform within one spacing of the centre (inside the domain) and
+ * with onset in [-16, 64); three background events anywhere that reaches the
+ * block; all magnitudes from the prior.  Draws from Philox under key (seed,
+ * 0x80000003): counter (p mod 2^32, p div 2^32, 0, c) for the events and the
+ * class, (.., .., 1 + station, n / 2) for the noise of sample n.  Features
+ * [9][64]: each present station's log envelope over the window's first 67
+ * samples; 0 for a missing station.  Target: offset (x/ds, y/ds, t/32). */
 void orc_mdn_pair(const orc_model *m, uint32_t seed, int64_t p, double *feat, double *target)
 {
     uint32_t key[2] = {seed, 0x80000003u};
+    uint32_t plo = (uint32_t)p, phi = (uint32_t)((uint64_t)p >> 32);
+    uint32_t cm[4] = {plo, phi, 0u, 8u}, wm[4];
+    orc_philox4x32_10(cm, key, wm);
+    int ex, ey;
+    edge_class(orc_u01(wm[0], wm[1]), &ex, &ey);
     double ev[4][4];
     for (int e = 0; e < 4; ++e) {
-        uint32_t c0[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), 0u,
-                          (uint32_t)(e == 0 ? 0 : 2 + (e - 1))};
-        uint32_t c1[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), 0u,
-                          (uint32_t)(e == 0 ? 1 : 5 + (e - 1))};
+        uint32_t c0[4] = {plo, phi, 0u, (uint32_t)(e == 0 ? 0 : 2 + (e - 1))};
+        uint32_t c1[4] = {plo, phi, 0u, (uint32_t)(e == 0 ? 1 : 5 + (e - 1))};
         uint32_t w0[4], w1[4];
         orc_philox4x32_10(c0, key, w0);
         orc_philox4x32_10(c1, key, w1);
         double ux = orc_u01(w0[0], w0[1]), uy = orc_u01(w0[2], w0[3]);
         double ut = orc_u01(w1[0], w1[1]), um = orc_u01(w1[2], w1[3]);
-        if (e == 0) {
-            ev[e][0] = (2.0 * ux - 1.0) * m->ds;
-            ev[e][1] = (2.0 * uy - 1.0) * m->ds;
+        double reach = e == 0 ? m->ds : 1.5 * m->ds + m->rc;
+        double xlo = ex < 0 ? -0.5 * m->ds : -reach, xhi = ex > 0 ? 0.5 * m->ds : reach;
+        double ylo = ey < 0 ? -0.5 * m->ds : -reach, yhi = ey > 0 ? 0.5 * m->ds : reach;
+        ev[e][0] = xlo + ux * (xhi - xlo);
+        ev[e][1] = ylo + uy * (yhi - ylo);
+        if (e == 0)
             ev[e][2] = -16.0 + ut * 80.0;
-        } else {
-            double half = 1.5 * m->ds + m->rc;
-            ev[e][0] = (2.0 * ux - 1.0) * half;
-            ev[e][1] = (2.0 * uy - 1.0) * half;
+        else
             ev[e][2] = -(double)(m->ts + 8) + ut * (double)(64 + m->ts + 16);
-        }
         ev[e][3] = m->mmin - log(um) / m->mrate;
     }
     for (int b = 0; b < 9; ++b) {
-        double sx = (double)(b % 3 - 1) * m->ds, sy = (double)(b / 3 - 1) * m->ds;
+        int dx = b % 3 - 1, dy = b / 3 - 1;
+        if ((ex != 0 && dx == ex) || (ey != 0 && dy == ey)) {
+            for (int n = 0; n < 64; ++n) feat[b * 64 + n] = 0.0;
+            continue;
+        }
+        double sx = (double)dx * m->ds, sy = (double)dy * m->ds;
         double q[67];
         for (int n = 0; n < 67; ++n) {
             double E = 0.0;
             for (int e = 0; e < 4; ++e) {
-                double dx = ev[e][0] - sx, dy = ev[e][1] - sy;
-                double d = sqrt(dx * dx + dy * dy);
+                double ddx = ev[e][0] - sx, ddy = ev[e][1] - sy;
+                double d = sqrt(ddx * ddx + ddy * ddy);
                 if (!(d < m->rc)) continue;
                 double a = ev[e][2] + d / m->vel;
                 double n0 = ceil(a);
@@ -486,8 +518,7 @@ void orc_mdn_pair(const orc_model *m, uint32_t seed, int64_t p, double *feat, do
                 double env = exp(-((double)n - a) / m->decay);
                 E += (amp * env) * (amp * env);
             }
-            uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), (uint32_t)(1 + b),
-                             (uint32_t)(n >> 1)};
+            uint32_t c[4] = {plo, phi, (uint32_t)(1 + b), (uint32_t)(n >> 1)};
             uint32_t w[4];
             orc_philox4x32_10(c, key, w);
             double u1 = orc_u01(w[0], w[1]), u2 = orc_u01(w[2], w[3]);
@@ -503,19 +534,22 @@ void orc_mdn_pair(const orc_model *m, uint32_t seed, int64_t p, double *feat, do
     target[2] = ev[0][2] / 32.0;
 }
 
-/* Anchor a of an instance: centre station (1 + c mod (nsx-2), 1 + c div
- * (nsx-2)) with c = a div n_tau, window start 32 (a mod n_tau); features
- * from the trace and weight 1e-3 + mean(max(0, f - 1)) over the features
- * after rounding them to binary32 and BF16 (as given in feat_rounded). */
+/* Anchor a of an instance: centre station c = a div n_tau (any station,
+ * row-major), window start 32 (a mod n_tau); features of the 3x3 block
+ * around it from the trace, 0 for block stations off the grid. */
 void orc_anchor_features(const orc_model *m, const double *s, int32_t n_tau, int32_t a,
                          double *feat)
 {
-    int32_t icx = m->nsx - 2;
     int32_t c = a / n_tau, ti = a % n_tau;
-    int32_t cx = 1 + c % icx, cy = 1 + c / icx;
+    int32_t cx = c % m->nsx, cy = c / m->nsx;
     int64_t tau = 32 * (int64_t)ti;
     for (int b = 0; b < 9; ++b) {
-        int64_t j = (int64_t)(cy + b / 3 - 1) * m->nsx + (cx + b % 3 - 1);
+        int32_t ix = cx + b % 3 - 1, iy = cy + b / 3 - 1;
+        if (ix < 0 || ix >= m->nsx || iy < 0 || iy >= m->nsy) {
+            for (int n = 0; n < 64; ++n) feat[b * 64 + n] = 0.0;
+            continue;
+        }
+        int64_t j = (int64_t)iy * m->nsx + ix;
         double q[67];
         for (int n = 0; n < 67; ++n) {
             double v = s[j * m->N + tau + n];

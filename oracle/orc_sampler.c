@@ -65,6 +65,12 @@ struct orc_chain {
     int64_t nsta;
     int64_t overflows;
     int32_t laid_out;
+    /* learned birth proposal (off when ltab is NULL) */
+    const double *ltab;   /* [nsta * ntau][8 components][8] */
+    const double *lw;     /* anchor weights [nsta * ntau] */
+    double *lcum;         /* per station: running sums of its anchors' weights */
+    int32_t ntau;
+    double plearn;
 };
 
 /* ---------------------------------------------------------------- lattice */
@@ -166,6 +172,7 @@ orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double
 
 void orc_chain_free(orc_chain *c)
 {
+    if (c) free(c->lcum);
     if (!c) return;
     for (int64_t r = 0; r < c->nreg; ++r) free(c->reg[r].e);
     for (int64_t j = 0; j < c->nsta; ++j) free(c->snap[j].e);
@@ -385,13 +392,193 @@ double orc_chain_delta(orc_chain *c, int32_t region, int32_t type, int64_t idx,
  * leaves the region, the trace or the magnitude support is rejected without
  * evaluating the likelihood.  log entry: type, status (0 invalid,
  * 1 rejected, 2 accepted), delta, log alpha. */
+/* ------------------------------------------------------ learned births */
+/* Draw record of 16 for the learned birth proposal: the 8 of
+ * orc_move_draws, then [8] mixture uniform, [9] anchor uniform, [10]
+ * component uniform (counter blocks 4 and 5), [11..13] three standard
+ * normals truncated to [-4, 4]: Box-Muller pairs from blocks 6, 7, ...
+ * (cosine then sine), taking the first three of absolute value at most 4;
+ * after 16 blocks any still missing are 0.  [14], [15] are 0. */
+void orc_move_draws16(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region, uint32_t j,
+                      double out[16])
+{
+    orc_move_draws(seed, chain, sweep, region, j, out);
+    uint32_t key[2] = {seed, chain}, w[4];
+    uint32_t c4[4] = {sweep, region, j, 4u}, c5[4] = {sweep, region, j, 5u};
+    orc_philox4x32_10(c4, key, w);
+    out[8] = orc_u01(w[0], w[1]);
+    out[9] = orc_u01(w[2], w[3]);
+    orc_philox4x32_10(c5, key, w);
+    out[10] = orc_u01(w[0], w[1]);
+    int got = 0;
+    for (uint32_t blk = 6; blk < 22 && got < 3; ++blk) {
+        uint32_t cb[4] = {sweep, region, j, blk};
+        orc_philox4x32_10(cb, key, w);
+        double u1 = orc_u01(w[0], w[1]), u2 = orc_u01(w[2], w[3]);
+        double r = sqrt(-2.0 * log(u1));
+        double z[2] = {r * cos(2.0 * M_PI * u2), r * sin(2.0 * M_PI * u2)};
+        for (int h = 0; h < 2 && got < 3; ++h)
+            if (fabs(z[h]) <= 4.0) out[11 + got++] = z[h];
+    }
+    while (got < 3) out[11 + got++] = 0.0;
+    out[14] = 0.0;
+    out[15] = 0.0;
+}
+
+int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *weights,
+                              int32_t n_tau, double p_learned)
+{
+    free(c->lcum);
+    c->lcum = NULL;
+    c->ltab = NULL;
+    if (!table) return 0;
+    if (n_tau < 1 || !weights || !(p_learned >= 0.0 && p_learned <= 1.0)) return -1;
+    c->lcum = (double *)malloc(sizeof(double) * (size_t)(c->nsta * n_tau));
+    for (int64_t st = 0; st < c->nsta; ++st) {
+        double acc = 0.0;
+        for (int32_t i = 0; i < n_tau; ++i) {
+            acc = acc + weights[st * n_tau + i];
+            c->lcum[st * n_tau + i] = acc;
+        }
+    }
+    c->ltab = table;
+    c->lw = weights;
+    c->ntau = n_tau;
+    c->plearn = p_learned;
+    return 0;
+}
+
+/* Stations whose position lies in region r, ascending; returns the count. */
+static int32_t region_stations(const orc_chain *c, int32_t r, int32_t *out, int32_t cap)
+{
+    int32_t cnt = 0;
+    for (int32_t st = 0; st < (int32_t)c->nsta; ++st) {
+        double sx = orc_station_x(&c->m, st % c->m.nsx), sy = orc_station_y(&c->m, st / c->m.nsx);
+        if (region_of(c, sx, sy) != r) continue;
+        if (cnt < cap) out[cnt] = st;
+        ++cnt;
+    }
+    return cnt;
+}
+
+/* Total anchor weight W_R of region r (stations ascending, anchors in
+ * window order); 0 when no station lies in r. */
+static double region_weight(const orc_chain *c, const int32_t *sta, int32_t ns)
+{
+    double W = 0.0;
+    for (int32_t q = 0; q < ns; ++q) W = W + c->lcum[(int64_t)sta[q] * c->ntau + c->ntau - 1];
+    return W;
+}
+
+/* Density at (x, y, t) of one mixture component truncated at 4 standard
+ * deviations per axis (Gaussian of independent axes, each renormalised by
+ * the mass erf(4 / sqrt 2) inside the truncation). */
+static double component_density(const double *T, double x, double y, double t)
+{
+    double ux = (x - T[0]) / T[3], uy = (y - T[1]) / T[4], ut = (t - T[2]) / T[5];
+    if (!(fabs(ux) <= 4.0 && fabs(uy) <= 4.0 && fabs(ut) <= 4.0)) return 0.0;
+    double lz = log(sqrt(2.0 * M_PI) * erf(4.0 / sqrt(2.0)));
+    return exp(T[6] - log(T[3]) - log(T[4]) - log(T[5]) - 3.0 * lz -
+               0.5 * (ux * ux + uy * uy + ut * ut));
+}
+
+/* q_R(x, y, t): the mixture over the anchors of the stations in R, anchor a
+ * weighted w_a / W_R, each anchor a mixture of 8 truncated Gaussians. */
+static double learned_density(const orc_chain *c, const int32_t *sta, int32_t ns, double W,
+                              double x, double y, double t)
+{
+    double S = 0.0;
+    for (int32_t q = 0; q < ns; ++q) {
+        for (int32_t i = 0; i < c->ntau; ++i) {
+            int64_t a = (int64_t)sta[q] * c->ntau + i;
+            double qa = 0.0;
+            for (int k = 0; k < 8; ++k) qa += component_density(c->ltab + (a * 8 + k) * 8, x, y, t);
+            S += c->lw[a] * qa;
+        }
+    }
+    return S / W;
+}
+
+/* The learned branch of a birth: anchor by u_anchor * W_R against the
+ * running weight sums (stations ascending, then windows), component by
+ * u_comp against the cumulative mixture weights, then the component's mean
+ * plus its standard deviations times the truncated normals. */
+static void learned_draw(const orc_chain *c, const int32_t *sta, int32_t ns, double W,
+                         const double *d, double *x, double *y, double *t)
+{
+    double target = d[9] * W, acc = 0.0, rem = 0.0;
+    int32_t pick = -1;
+    for (int32_t q = 0; q < ns; ++q) {
+        double Ws = c->lcum[(int64_t)sta[q] * c->ntau + c->ntau - 1];
+        double nxt = acc + Ws;
+        if (target < nxt) {
+            pick = sta[q];
+            rem = target - acc;
+            break;
+        }
+        acc = nxt;
+    }
+    if (pick < 0) {
+        pick = sta[ns - 1];
+        rem = c->lcum[(int64_t)pick * c->ntau + c->ntau - 1];
+    }
+    int32_t i = c->ntau - 1;
+    for (int32_t q = 0; q < c->ntau; ++q)
+        if (rem < c->lcum[(int64_t)pick * c->ntau + q]) { i = q; break; }
+    int64_t a = (int64_t)pick * c->ntau + i;
+    int k = 7;
+    for (int q = 0; q < 8; ++q)
+        if (d[10] < c->ltab[(a * 8 + q) * 8 + 7]) { k = q; break; }
+    const double *T = c->ltab + (a * 8 + k) * 8;
+    *x = T[0] + T[3] * d[11];
+    *y = T[1] + T[4] * d[12];
+    *t = T[2] + T[5] * d[13];
+}
+
+/* log(b / p_R) at (x, y, t) for the mixture b = (1 - p_L) p_R + p_L q_R. */
+static double learned_log_ratio(const orc_chain *c, const int32_t *sta, int32_t ns, double W,
+                                double pl, double area, double x, double y, double t)
+{
+    double q = learned_density(c, sta, ns, W, x, y, t);
+    return log((1.0 - pl) + pl * q * area * (double)c->m.N);
+}
+
+double orc_chain_learned_q(orc_chain *c, int32_t region, double x, double y, double t)
+{
+    int32_t sta[64];
+    int32_t ns = region_stations(c, region, sta, 64);
+    if (!c->ltab || ns == 0 || ns > 64) return 0.0;
+    return learned_density(c, sta, ns, region_weight(c, sta, ns), x, y, t);
+}
+
+int32_t orc_chain_learned_draw(orc_chain *c, int32_t region, const double *d, double *out)
+{
+    int32_t sta[64];
+    int32_t ns = region_stations(c, region, sta, 64);
+    if (!c->ltab || ns == 0 || ns > 64) return -1;
+    learned_draw(c, sta, ns, region_weight(c, sta, ns), d, out, out + 1, out + 2);
+    return 0;
+}
+
 static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const double *d,
-                     double lam_r, double *logentry)
+                     double lam_r, double area, double *logentry)
 {
     const orc_model *m = &c->m;
     const orc_sampler *sp = &c->sp;
     evlist *own = &c->reg[r];
     int64_t n = own->n;
+    /* learned births: stations of the region, their weight, the mixing
+     * probability (0 for a region without stations) */
+    int32_t sta[64], ns = 0;
+    double W = 0.0, pl = 0.0;
+    if (c->ltab && !sp->lattice) {
+        ns = region_stations(c, r, sta, 64);
+        if (ns > 64) ns = 0;
+        if (ns > 0) {
+            W = region_weight(c, sta, ns);
+            pl = c->plearn;
+        }
+    }
     double c1 = sp->pb, c2 = c1 + sp->pd, c3 = c2 + sp->ploc, c4 = c3 + sp->pt;
     int32_t type = d[0] < c1 ? ORC_BIRTH
                  : d[0] < c2 ? ORC_DEATH
@@ -420,12 +607,16 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
         } else {
             double x0, x1, y0, y1;
             region_rect(c, r, &x0, &x1, &y0, &y1);
-            nw.x = x0 + d[1] * (x1 - x0);
-            nw.y = y0 + d[2] * (y1 - y0);
-            nw.t = d[3] * (double)m->N;
+            if (pl > 0.0 && d[8] < pl) {
+                learned_draw(c, sta, ns, W, d, &nw.x, &nw.y, &nw.t);
+            } else {
+                nw.x = x0 + d[1] * (x1 - x0);
+                nw.y = y0 + d[2] * (y1 - y0);
+                nw.t = d[3] * (double)m->N;
+            }
             nw.m = m->mmin + d[4] / m->mrate;
             valid = nw.x >= 0.0 && nw.x < c->Lx && nw.y >= 0.0 && nw.y < c->Ly &&
-                    nw.t < (double)m->N && region_of(c, nw.x, nw.y) == r;
+                    nw.t >= 0.0 && nw.t < (double)m->N && region_of(c, nw.x, nw.y) == r;
         }
         nw.id = ((uint64_t)sweep << 32) | ((uint64_t)(uint32_t)r << 12) | (uint64_t)j;
         nw.region = r;
@@ -477,8 +668,10 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
         if (!sp->prior_only) delta = move_delta(c, r, type, idx, &nw);
         if (type == ORC_BIRTH) {
             la = delta + log(lam_r) + log(sp->pd) - log((double)(n + 1)) - log(sp->pb);
+            if (pl > 0.0) la -= learned_log_ratio(c, sta, ns, W, pl, area, nw.x, nw.y, nw.t);
         } else if (type == ORC_DEATH) {
             la = delta + log((double)n) + log(sp->pb) - log(lam_r) - log(sp->pd);
+            if (pl > 0.0) la += learned_log_ratio(c, sta, ns, W, pl, area, nw.x, nw.y, nw.t);
         } else if (type == ORC_MAG && !sp->lattice) {
             la = delta - m->mrate * (nw.m - own->e[idx].m);
         } else {
@@ -504,7 +697,8 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
 /* One colour phase of Algorithm 4: every region of the colour runs k moves;
  * the other regions are held at the phase-start snapshot.  With the naive
  * schedule (Algorithm 3) every region belongs to the phase.
- * feed (optional): draws [region][k][8]; log (optional): [region][k][4]. */
+ * feed (optional): draws [region][k][8] ([16] with learned births); log
+ * (optional): [region][k][4]. */
 int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double *feed,
                         double *log_out)
 {
@@ -524,16 +718,20 @@ int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double
         } else {
             lam_r = c->m.lambda * area / (c->Lx * c->Ly);
         }
+        const int64_t stride = c->ltab ? 16 : 8;
         for (int32_t j = 0; j < c->sp.k; ++j) {
-            double d[8];
+            double d[16];
             const double *dp;
             if (feed) {
-                dp = feed + ((r * c->sp.k) + j) * 8;
+                dp = feed + ((r * c->sp.k) + j) * stride;
             } else {
-                orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+                if (c->ltab)
+                    orc_move_draws16(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+                else
+                    orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
                 dp = d;
             }
-            run_move(c, (int32_t)r, (uint32_t)sweep, (uint32_t)j, dp, lam_r,
+            run_move(c, (int32_t)r, (uint32_t)sweep, (uint32_t)j, dp, lam_r, area,
                      log_out ? log_out + ((r * c->sp.k) + j) * 4 : NULL);
         }
     }

@@ -54,7 +54,8 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_move_draws", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
-           "cmh_anchor_features"]
+           "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
+           "cmh_set_learned"]
 
 _lib = None
 
@@ -78,7 +79,7 @@ def lib():
         "cmh_run_sweeps": ([P, I64, I64, P], I32),
         "cmh_read_events": ([P, I32, P, I64, P], I32),
         "cmh_write_events": ([P, I32, P, I64], I32),
-        "cmh_set_feed": ([P, P, I64, I64], I32),
+        "cmh_set_feed": ([P, P, I64, I64, I32], I32),
         "cmh_set_log": ([P, P, I64, I64], I32),
         "cmh_refresh": ([P, I32, P, P], I32),
         "cmh_read_variance": ([P, I32, I64, I64, P], I32),
@@ -89,7 +90,9 @@ def lib():
         "cmh_destroy": ([P], I32),
         "cmh_simulate_bytes": ([P, P, I64, P], I32),
         "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
-        "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, P, P], I32),
+        "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, I32, P, P], I32),
+        "cmh_learned_bytes": ([P, I32, P], I32),
+        "cmh_set_learned": ([P, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_mdn_sizes": ([P, P], I32),
         "cmh_mdn_param_bytes": ([P], I32),
         "cmh_mdn_init": ([P, U32, P], I32),
@@ -101,7 +104,8 @@ def lib():
         "cmh_mdn_train_step": ([P, P, P, I32, I32, C.c_float, P, P, C.c_size_t, P], I32),
         "cmh_mdn_pairs": ([P, U32, I64, I32, P, P, P], I32),
         "cmh_anchor_count": ([P, P, P], I32),
-        "cmh_anchor_features": ([P, P, I32, P, P, P], I32),
+        "cmh_anchor_features": ([P, P, I32, I64, I32, P, P, P], I32),
+        "cmh_mixture_table": ([P, P, I64, I32, P, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -183,10 +187,11 @@ def simulate(model: ModelSpec, truth: np.ndarray, seed: int, dtype: str = "f32",
 
 
 def move_draws(seed: int, chain: int, sweep: int, region: int, j0: int, count: int,
-               device="cuda") -> np.ndarray:
+               device="cuda", width: int = 8) -> np.ndarray:
     import torch
-    out = torch.empty((count, 8), dtype=torch.float64, device=device)
-    check(lib().cmh_move_draws(seed, chain, sweep, region, j0, count, _ptr(out), _stream()))
+    out = torch.empty((count, width), dtype=torch.float64, device=device)
+    check(lib().cmh_move_draws(seed, chain, sweep, region, j0, count, width, _ptr(out),
+                               _stream()))
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -247,14 +252,39 @@ class ChromaticSampler:
                              f"[n_sweeps, {want[0]}, {want[1]}, {want[2]}]")
 
     def set_feed(self, feed, first: int):
-        """feed: float64 device tensor [n_sweeps, regions, k, 8] (or None)."""
+        """feed: float64 device tensor [n_sweeps, regions, k, 8] ([.., 16]
+        with learned births), or None."""
         if feed is not None:
-            self._check_buffer(feed, 8, "feed")
+            self._check_buffer(feed, feed.shape[-1] if feed.dim() == 4 else 8, "feed")
+            if feed.shape[-1] not in (8, 16):
+                raise ValueError("feed records are 8 or 16 wide")
         self._feed = feed
         if feed is None:
-            check(lib().cmh_set_feed(self._h, None, 0, 0))
+            check(lib().cmh_set_feed(self._h, None, 0, 0, 8))
         else:
-            check(lib().cmh_set_feed(self._h, _ptr(feed), first, feed.shape[0]))
+            check(lib().cmh_set_feed(self._h, _ptr(feed), first, feed.shape[0], feed.shape[-1]))
+
+    def set_learned(self, table, weights, n_tau: int, p_learned: float = 0.5, stream=None):
+        """Learned births from a float64 device table [n_stations * n_tau, 8, 8]
+        and anchor weights [n_stations * n_tau] (kept alive here); None: off."""
+        import torch
+        if table is None:
+            check(lib().cmh_set_learned(self._h, None, None, 0, 0.0, None, 0, _stream(stream)))
+            self._learned = None
+            return
+        na = self.model.nsta * n_tau
+        if (tuple(table.shape) != (na, 8, 8) or table.dtype != torch.float64 or not table.is_cuda
+                or not table.is_contiguous()):
+            raise ValueError(f"table must be a contiguous float64 device tensor [{na}, 8, 8]")
+        if (tuple(weights.shape) != (na,) or weights.dtype != torch.float64 or not weights.is_cuda
+                or not weights.is_contiguous()):
+            raise ValueError(f"weights must be a contiguous float64 device tensor [{na}]")
+        nb = C.c_size_t()
+        check(lib().cmh_learned_bytes(self._h, n_tau, C.byref(nb)))
+        work = torch.empty(nb.value, dtype=torch.uint8, device=self.trace.device)
+        check(lib().cmh_set_learned(self._h, _ptr(table), _ptr(weights), n_tau, p_learned,
+                                    _ptr(work), work.numel(), _stream(stream)))
+        self._learned = (table, weights, work)
 
     def set_log(self, log, first: int):
         """log: float64 device tensor [n_sweeps, regions, k, 4] (or None)."""
@@ -405,14 +435,27 @@ def anchor_count(model: ModelSpec):
     return na.value, nt.value
 
 
-def anchor_features(model: ModelSpec, trace):
-    """(bf16 [anchors, 576], f64 [anchors]) features and weights of a device trace."""
+def anchor_features(model: ModelSpec, trace, first: int = 0, count: int | None = None):
+    """(bf16 [count, 576], f64 [count]) features and weights of anchors
+    first .. first + count - 1 of a device trace (all anchors by default)."""
     import torch
     na, _ = anchor_count(model)
-    X = torch.empty((na, 576), dtype=torch.bfloat16, device=trace.device)
-    wts = torch.empty(na, dtype=torch.float64, device=trace.device)
+    count = na - first if count is None else count
+    X = torch.empty((count, 576), dtype=torch.bfloat16, device=trace.device)
+    wts = torch.empty(count, dtype=torch.float64, device=trace.device)
     m = model_struct(model)
     check(lib().cmh_anchor_features(C.byref(m), _ptr(trace),
                                     CMH_F64 if trace.dtype == torch.float64 else CMH_F32,
-                                    _ptr(X), _ptr(wts), _stream()))
+                                    first, count, _ptr(X), _ptr(wts), _stream()))
     return X, wts
+
+
+def mixture_table(model: ModelSpec, head, first: int = 0):
+    """Binary64 mixture table [rows, 8, 8] of anchors first .. from head
+    outputs [rows, 64] (device float32)."""
+    import torch
+    rows = head.shape[0]
+    T = torch.empty((rows, 8, 8), dtype=torch.float64, device=head.device)
+    m = model_struct(model)
+    check(lib().cmh_mixture_table(C.byref(m), _ptr(head), first, rows, _ptr(T), _stream()))
+    return T

@@ -238,12 +238,14 @@ struct cmh_state {
     int block = 256;
     const double *feed = nullptr;
     long long feed_first = 0, feed_n = 0;
+    int feed_width = 8;
     double *logp = nullptr;
     long long log_first = 0, log_n = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_block = 0;
     hipStream_t cap_stream = nullptr;
     int poisoned = 0;
+    cmh::Learned learned{};  // tab == nullptr: plain births
 };
 
 namespace {
@@ -296,6 +298,8 @@ int32_t sync_and_check(cmh_state *st)
         st->poisoned = 1;
         if (flags & cmh::kFlagCap) return fail(CMH_ECAP, "a region exceeded its event capacity");
         if (flags & cmh::kFlagNan) return fail(CMH_ENAN, "NaN or Inf in a likelihood change");
+        if (flags & cmh::kFlagSta)
+            return fail(CMH_ESTATE, "a region holds more stations than learned births allow");
         return fail(CMH_ESTATE, "footprint or tile capacity exceeded");
     }
     return CMH_OK;
@@ -329,7 +333,7 @@ hipError_t enqueue_sweep_start(cmh_state *st, hipStream_t s)
         st->cur ^= 1;
     }
     return cmh::launch_sweep_draws(st->g, st->sweep_ctr, st->feed, st->feed_first, st->draws,
-                                   st->chains, s);
+                                   st->ev[st->cur].off, st->learned, st->err, st->chains, s);
 }
 
 // Enqueue one colour phase (colour 0 first starts the sweep), reading the
@@ -342,7 +346,7 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
     }
     return cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
                              st->sweep_ctr, st->draws, st->logp, st->log_first, st->log_n,
-                             st->stats, st->err, st->block, st->chains, s);
+                             st->stats, st->err, st->learned, st->block, st->chains, s);
 }
 
 void drop_graphs(cmh_state *st)
@@ -493,6 +497,8 @@ int32_t cmh_sweep_color(cmh_state *st, int64_t sweep, int32_t color, void *hip_s
     if (sweep < 0 || sweep >= (1LL << 32)) return fail(CMH_EINVAL, "sweep out of range");
     if (st->feed && (sweep < st->feed_first || sweep >= st->feed_first + st->feed_n))
         return fail(CMH_EINVAL, "sweep outside the attached feed");
+    if (st->feed && st->feed_width != (st->learned.tab ? 16 : 8))
+        return fail(CMH_EINVAL, "feed records must be 16 wide with learned births, else 8");
     hipStream_t s = (hipStream_t)hip_stream;
     HIPCHK(cmh::set_sweep(st->sweep_ctr, sweep, s));
     HIPCHK(enqueue_phase(st, color, color == 0, s));
@@ -614,12 +620,15 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
     return sync_and_check(st);
 }
 
-int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep, int64_t n_sweeps)
+int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep, int64_t n_sweeps,
+                     int32_t width)
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
     if (feed_dev && (first_sweep < 0 || n_sweeps < 1))
         return fail(CMH_EINVAL, "feed needs first_sweep >= 0 and n_sweeps >= 1");
+    if (feed_dev && width != 8 && width != 16) return fail(CMH_EINVAL, "width must be 8 or 16");
+    st->feed_width = width;
     st->feed = feed_dev;
     st->feed_first = feed_dev ? first_sweep : 0;
     st->feed_n = feed_dev ? n_sweeps : 0;
@@ -771,6 +780,8 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
     if (st->feed && (first_sweep < st->feed_first ||
                      first_sweep + n_sweeps > st->feed_first + st->feed_n))
         return fail(CMH_EINVAL, "sweeps outside the attached feed");
+    if (st->feed && st->feed_width != (st->learned.tab ? 16 : 8))
+        return fail(CMH_EINVAL, "feed records must be 16 wide with learned births, else 8");
     hipStream_t s = (hipStream_t)hip_stream;
     const int nc = st->g.ncolors;
     std::vector<hipEvent_t> ev((size_t)n_sweeps * (nc + 2));
@@ -802,6 +813,70 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
     for (auto &x : ev) (void)hipEventDestroy(x);
     if (e) return fail(CMH_EHIP, std::string("phase timing: ") + hipGetErrorString(e));
     return sync_and_check(st);
+}
+
+namespace {
+size_t carve_learned(const cmh_state *st, int ntau, char *base, cmh::Learned *L, double **part)
+{
+    const cmh::Geo &g = st->g;
+    Carver c{base};
+    const size_t na = (size_t)g.nsta * ntau;
+    double *cum = c.take<double>(na);
+    double *norm = c.take<double>(na * 8);
+    double *reach = c.take<double>(2);
+    double *pp = c.take<double>((size_t)2 * cmh::learned_norm_blocks((long long)na * 8));
+    double *birth = c.take<double>((size_t)st->chains * g.R * g.k * 4);
+    if (L) {
+        L->cum = cum;
+        L->norm = norm;
+        L->reach = reach;
+        L->birth = birth;
+    }
+    if (part) *part = pp;
+    return align_up(c.off);
+}
+}  // namespace
+
+int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = carve_learned(st, n_tau, nullptr, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *weights_dev,
+                        int32_t n_tau, double p_learned, void *work_dev, size_t work_bytes,
+                        void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    drop_graphs(st);
+    if (!table_dev) {
+        st->learned = cmh::Learned{};
+        return CMH_OK;
+    }
+    if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
+    if (!(p_learned >= 0.0 && p_learned < 1.0))
+        return fail(CMH_EINVAL, "p_learned must lie in [0, 1)");
+    if (!weights_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (work_bytes < carve_learned(st, n_tau, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "learned workspace too small");
+    cmh::Learned L{};
+    double *part = nullptr;
+    carve_learned(st, n_tau, (char *)work_dev, &L, &part);
+    L.tab = table_dev;
+    L.w = weights_dev;
+    L.ntau = n_tau;
+    L.pl = p_learned;
+    const double lz3 = 3.0 * log(sqrt(2.0 * M_PI) * erf(4.0 / sqrt(2.0)));
+    HIPCHK(cmh::launch_learned_prep(weights_dev, table_dev, n_tau, st->g.nsta, lz3,
+                                    (double *)L.cum, (double *)L.norm, part, (double *)L.reach,
+                                    (hipStream_t)hip_stream));
+    st->learned = L;
+    return CMH_OK;
 }
 
 int32_t cmh_destroy(cmh_state *st)
@@ -930,11 +1005,12 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
 }
 
 int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region, uint32_t j0,
-                       int32_t count, double *out_dev, void *hip_stream)
+                       int32_t count, int32_t width, double *out_dev, void *hip_stream)
 {
     if (count < 0 || (count > 0 && !out_dev)) return fail(CMH_EINVAL, "bad arguments");
+    if (width != 8 && width != 16) return fail(CMH_EINVAL, "width must be 8 or 16");
     if (count == 0) return CMH_OK;
-    HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, out_dev,
+    HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, width, out_dev,
                              (hipStream_t)hip_stream));
     return CMH_OK;
 }
@@ -1131,27 +1207,47 @@ int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
-    if (model->nsx < 3 || model->nsy < 3 || model->n_samples < cmh::kMdnWin + 3)
-        return fail(CMH_EINVAL, "anchors need a 3x3 station grid and 67 samples");
-    const int ntau = (int)((model->n_samples - (cmh::kMdnWin + 3)) / cmh::kMdnTScale) + 1;
-    if (n_tau) *n_tau = ntau;
-    if (n_anchors) *n_anchors = (model->nsx - 2) * (model->nsy - 2) * ntau;
+    if (model->n_samples < cmh::kMdnWin + 3)
+        return fail(CMH_EINVAL, "anchors need at least 67 samples");
+    const long ntau = (long)((model->n_samples - (cmh::kMdnWin + 3)) / cmh::kMdnTScale) + 1;
+    const long na = (long)model->nsx * model->nsy * ntau;
+    if (na > INT32_MAX) return fail(CMH_EINVAL, "more than 2^31 - 1 anchors");
+    if (n_tau) *n_tau = (int32_t)ntau;
+    if (n_anchors) *n_anchors = (int32_t)na;
     return CMH_OK;
 }
 
 int32_t cmh_anchor_features(const cmh_model *model, const void *trace_dev, int32_t trace_dtype,
-                            void *x_dev, double *w_dev, void *hip_stream)
+                            int64_t first, int32_t count, void *x_dev, double *w_dev,
+                            void *hip_stream)
 {
     int32_t na = 0, ntau = 0;
     int32_t rc = cmh_anchor_count(model, &na, &ntau);
     if (rc) return rc;
-    if (!trace_dev || !x_dev || !w_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (first < 0 || count < 0 || first + count > na)
+        return fail(CMH_EINVAL, "anchor range outside 0 .. n_anchors");
+    if (count > 0 && (!trace_dev || !x_dev || !w_dev)) return fail(CMH_EINVAL, "NULL argument");
     if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
         return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
     Geo g;
     model_geo(model, &g);
-    HIPCHK(cmh::anchor_features(g, trace_dev, trace_dtype == CMH_F64, ntau, (__bf16 *)x_dev, w_dev,
-                                (hipStream_t)hip_stream));
+    HIPCHK(cmh::anchor_features(g, trace_dev, trace_dtype == CMH_F64, ntau, first, count,
+                                (__bf16 *)x_dev, w_dev, (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_mixture_table(const cmh_model *model, const float *head_dev, int64_t first,
+                          int32_t rows, double *table_dev, void *hip_stream)
+{
+    int32_t na = 0, ntau = 0;
+    int32_t rc = cmh_anchor_count(model, &na, &ntau);
+    if (rc) return rc;
+    if (first < 0 || rows < 0 || first + rows > na)
+        return fail(CMH_EINVAL, "anchor range outside 0 .. n_anchors");
+    if (rows > 0 && (!head_dev || !table_dev)) return fail(CMH_EINVAL, "NULL argument");
+    Geo g;
+    model_geo(model, &g);
+    HIPCHK(cmh::mixture_table(g, ntau, first, rows, head_dev, table_dev, (hipStream_t)hip_stream));
     return CMH_OK;
 }
 

@@ -18,8 +18,9 @@ constexpr int kMaxFootprint = 2048;  // samples touched by one move (16 * kMaxTs
 constexpr int kDrawChunk = 64;       // moves whose draws are staged at once
 constexpr int kTile = 2048;          // samples per workgroup in streaming kernels
 constexpr int kMaxTileEvents = 640;  // events reaching one station tile
+constexpr int kMaxRegSta = 16;       // stations of one region, learned births
 
-enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8 };
+enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16 };
 
 // Per-chain statistics: [3 t + 0..2] attempted / evaluated / accepted moves of
 // type t, [15] footprint samples evaluated, [16] footprint samples rewritten.
@@ -38,6 +39,20 @@ struct Geo {
     double pb, pd, ploc, pt, pm, sxy, st, sm;
     double c1, c2, c3, c4;  // cumulative move-type thresholds
     double att2, dec2;      // 2 / atten, 2 / decay
+};
+
+// Learned birth proposal: a mixture over the anchors (station, window) of
+// the stations in a region, mixed with the prior birth with probability pl.
+// tab and w belong to the caller; the rest is derived by the library.
+struct Learned {
+    const double *tab;    // [nsta * ntau][8][8]: mean x, y, t, sd x, y, t, log w, cum w
+    const double *w;      // anchor weights [nsta * ntau]
+    const double *cum;    // per station: running sums of its anchors' weights
+    const double *norm;   // [nsta * ntau][8]: log weight minus log normaliser
+    const double *reach;  // min and max over the table of mean t -/+ 4 sd t - tau
+    double *birth;        // [chain][region][move][4]: birth proposal x, y, t, log b/p
+    int ntau;
+    double pl;
 };
 
 // Region-slot event table for all chains.  Slot s of region r of chain c is

@@ -52,6 +52,107 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// Draw record of 16 for learned births: the 8 above, then [8] mixture
+// uniform, [9] anchor uniform (counter block 4), [10] component uniform
+// (block 5), [11..13] standard normals truncated to [-4, 4]: Box-Muller
+// pairs from blocks 6, 7, ... (cosine, then sine), the first three of
+// absolute value at most 4; after 16 blocks missing ones are 0.  [14], [15]
+// are 0.
+__device__ inline void move_draws16(uint32_t seed, uint32_t chain, uint32_t sweep,
+                                    uint32_t region, uint32_t j, double out[16])
+{
+    move_draws(seed, chain, sweep, region, j, out);
+    uint32_t c[4] = {sweep, region, j, 4u};
+    philox10(c, seed, chain);
+    out[8] = unit_open(c[0], c[1]);
+    out[9] = unit_open(c[2], c[3]);
+    c[0] = sweep; c[1] = region; c[2] = j; c[3] = 5u;
+    philox10(c, seed, chain);
+    out[10] = unit_open(c[0], c[1]);
+    double z[3] = {0.0, 0.0, 0.0};
+    int got = 0;
+    for (uint32_t blk = 6; blk < 22 && got < 3; ++blk) {
+        c[0] = sweep; c[1] = region; c[2] = j; c[3] = blk;
+        philox10(c, seed, chain);
+        const double u1 = unit_open(c[0], c[1]), u2 = unit_open(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double zc = rad * cos(2.0 * M_PI * u2), zs = rad * sin(2.0 * M_PI * u2);
+        if (fabs(zc) <= 4.0) z[got++] = zc;
+        if (got < 3 && fabs(zs) <= 4.0) z[got++] = zs;
+    }
+    out[11] = z[0]; out[12] = z[1]; out[13] = z[2];
+    out[14] = 0.0; out[15] = 0.0;
+}
+
+// Stations whose position falls in region (i, kk) of a partition with
+// offsets (offx, offy), in ascending index; returns their number (only the
+// first `cap` are stored).  Candidates are the cells around the region's
+// span; membership is decided by the region binning itself.
+__device__ inline int region_stations(const Geo &g, double offx, double offy, int i, int kk,
+                                      double x0, double x1, double y0, double y1, int *sta,
+                                      int cap)
+{
+    const int ix0 = max((int)floor(x0 / g.ds - 0.5) - 1, 0);
+    const int ix1 = min((int)ceil(x1 / g.ds - 0.5) + 1, g.nsx - 1);
+    const int iy0 = max((int)floor(y0 / g.ds - 0.5) - 1, 0);
+    const int iy1 = min((int)ceil(y1 / g.ds - 0.5) + 1, g.nsy - 1);
+    int cnt = 0;
+    for (int iy = iy0; iy <= iy1; ++iy) {
+        if (region_axis(station_pos(iy, g.ds), offy, g.wy, g.gy) != kk) continue;
+        for (int ix = ix0; ix <= ix1; ++ix) {
+            if (region_axis(station_pos(ix, g.ds), offx, g.wx, g.gx) != i) continue;
+            if (cnt < cap) sta[cnt] = iy * g.nsx + ix;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+// Windows i whose anchors can put mass at time t: tau_i + reach[0] <= t <=
+// tau_i + reach[1], widened by one window each side.
+__device__ inline void learned_windows(const Learned &L, double t, int *ilo, int *ihi)
+{
+    const double a = floor((t - L.reach[1]) / 32.0) - 1.0;
+    const double b = ceil((t - L.reach[0]) / 32.0) + 1.0;
+    *ilo = (int)fmax(a, 0.0);
+    *ihi = (int)fmin(b, (double)(L.ntau - 1));
+}
+
+// Part of sum over anchors a of the stations sta[0..ns) and windows
+// [ilo, ihi] of w_a sum_k pi_k TN_k(x, y, t): (station, window) pairs
+// first, first + stride, ...  TN_k is the component's Gaussian truncated at
+// 4 sd per axis and renormalised.
+__device__ inline double learned_part(const Learned &L, const int *sta, int ns, int ilo, int ihi,
+                                      double x, double y, double t, int first, int stride)
+{
+    const int nw = ihi - ilo + 1;
+    double S = 0.0;
+    if (nw <= 0) return S;
+    for (int p = first; p < ns * nw; p += stride) {
+        const int q = p / nw;
+        const long long a = (long long)sta[q] * L.ntau + ilo + (p - q * nw);
+        const double *T = L.tab + a * 64;
+        const double *nr = L.norm + a * 8;
+        double qa = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const double ux = (x - T[8 * k + 0]) / T[8 * k + 3];
+            const double uy = (y - T[8 * k + 1]) / T[8 * k + 4];
+            const double ut = (t - T[8 * k + 2]) / T[8 * k + 5];
+            if (fabs(ux) <= 4.0 && fabs(uy) <= 4.0 && fabs(ut) <= 4.0)
+                qa += exp(nr[k] - 0.5 * (ux * ux + uy * uy + ut * ut));
+        }
+        S += L.w[a] * qa;
+    }
+    return S;
+}
+
+// log(b / p_R) for the birth density b = (1 - pl) p_R + pl q_R, given the
+// anchor sum S and the region's total anchor weight W.
+__device__ inline double learned_log_ratio(double pl, double S, double W, double area, int N)
+{
+    return log((1.0 - pl) + pl * (S / W) * area * (double)N);
+}
+
 // One run of affected samples at one station: samples [lo, lo + len); the
 // old event's window [o0, o1) with scale Bo and the new event's window
 // [w0, w1) with scale Bn.  Runs are laid end to end in flat positions in
@@ -66,6 +167,14 @@ struct MoveHdr {
     int valid, type, n, nseg, S;
     int flags;  // error flags, raised only when the move is consumed
     double dm;  // magnitude change (magnitude move)
+    double lr;  // learned births: log(b / p_R) at the born or dying event
+};
+
+// A region's learned-birth constants, staged in LDS by the sweep workgroup.
+struct RegionLearned {
+    int ns;          // stations in the region (at most kMaxRegSta)
+    double W, pl;    // their total anchor weight; mixing probability (0: plain)
+    double area;
 };
 
 // x lies in region index `want` of one axis.  Points further than 1e-9 w
@@ -184,10 +293,12 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
                                   double y1, int n, const double (*drw)[kDrawChunk][8],
                                   const double *s_ex, const double *s_ey, const double *s_et,
                                   const double *s_em, Seg (*s_seg)[kMaxSeg], MoveHdr *s_hdr,
-                                  double (*s_prop)[5], int max_samples)
+                                  double (*s_prop)[5], int max_samples, const Learned &L,
+                                  const double (*lbs)[kDrawChunk][4], const int *lsta,
+                                  const RegionLearned &rl)
 {
     int type = 0, valid = 0, idx = -1, mflags = 0;
-    double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0;
+    double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0, lr = 0;
     if (lane == 0) {
         const double *d = drw[(jj >> 6) & 1][jj & 63];
         const double u = d[0];
@@ -196,12 +307,17 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
             if (n >= g.cap) {
                 mflags |= kFlagCap;
             } else {
-                nx = x0 + d[1] * (x1 - x0);
-                ny = y0 + d[2] * (y1 - y0);
-                nt = d[3] * (double)g.N;
+                if (L.tab != nullptr) {  // derived for the sweep by the draw kernel
+                    const double *lb = lbs[(jj >> 6) & 1][jj & 63];
+                    nx = lb[0]; ny = lb[1]; nt = lb[2]; lr = lb[3];
+                } else {
+                    nx = x0 + d[1] * (x1 - x0);
+                    ny = y0 + d[2] * (y1 - y0);
+                    nt = d[3] * (double)g.N;
+                }
                 nm = g.mmin + d[4] / g.mrate;
-                valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly && nt < (double)g.N &&
-                        in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
+                valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly && nt >= 0.0 &&
+                        nt < (double)g.N && in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
                         in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
             }
         } else if (n > 0) {
@@ -227,6 +343,15 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
     }
     type = __shfl(type, 0, 64);
     valid = __shfl(valid, 0, 64);
+    if (type == 1 && valid && rl.pl > 0.0) {
+        // death under learned births: the birth density at the dying event,
+        // (station, window) pairs spread over the lanes
+        const double ex = __shfl(ox, 0, 64), ey = __shfl(oy, 0, 64), et = __shfl(ot, 0, 64);
+        int ilo, ihi;
+        learned_windows(L, et, &ilo, &ihi);
+        const double S = wave_sum(learned_part(L, lsta, rl.ns, ilo, ihi, ex, ey, et, lane, 64));
+        lr = learned_log_ratio(rl.pl, S, rl.W, rl.area, g.N);
+    }
     int nseg = 0, S = 0;
     if (valid && !g.prior_only) {
         ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
@@ -245,6 +370,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
         MoveHdr h;
         h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.flags = mflags;
         h.dm = nm - om;
+        h.lr = lr;
         s_hdr[buf] = h;
         s_prop[buf][0] = nx; s_prop[buf][1] = ny; s_prop[buf][2] = nt; s_prop[buf][3] = nm;
         s_prop[buf][4] = (double)idx;
@@ -271,13 +397,16 @@ __global__ void __launch_bounds__(BLOCK)
 k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E,
               int color, const long long *__restrict__ sweep_ptr, const double *__restrict__ draws,
               double *__restrict__ logp, long long log_first, long long log_n,
-              unsigned long long *__restrict__ stats, int *__restrict__ err)
+              unsigned long long *__restrict__ stats, int *__restrict__ err, Learned L)
 {
     static_assert(BLOCK >= 128 && BLOCK % 64 == 0, "one scout wave and at least one evaluator");
     constexpr int W = BLOCK / 64;
     constexpr int EV = BLOCK - 64;
     constexpr int MAXQ = (kMaxFootprint + EV - 1) / EV;
     __shared__ double s_draw[2][kDrawChunk][8];
+    __shared__ double s_lb[2][kDrawChunk][4];
+    __shared__ int s_lsta[kMaxRegSta];
+    __shared__ RegionLearned s_rl;
     __shared__ double s_T[kMaxTs];
     __shared__ double s_log[kMaxCap + 2];  // s_log[q] = log(q)
     __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
@@ -311,6 +440,8 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     const long long base = ((long long)chain * g.R + r) * g.cap;
     const long long ebase = (long long)chain * g.nsta * (long long)g.N;
     const double *dsrc = draws + ((long long)chain * g.R + r) * (long long)g.k * 8;
+    const double *lsrc =
+        L.tab != nullptr ? L.birth + ((long long)chain * g.R + r) * (long long)g.k * 4 : nullptr;
     int n = ev.cnt[chain * g.R + r];
     for (int s = tid; s < n; s += BLOCK) {
         s_ex[s] = ev.x[base + s]; s_ey[s] = ev.y[base + s];
@@ -322,6 +453,27 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     for (int c = 0; c < 2 && 64 * c < g.k; ++c) {
         const int m = min(kDrawChunk, g.k - 64 * c) * 8;
         for (int q = tid; q < m; q += BLOCK) s_draw[c][q >> 3][q & 7] = dsrc[64LL * 8 * c + q];
+        if (lsrc != nullptr)
+            for (int q = tid; q < m / 2; q += BLOCK)
+                s_lb[c][q >> 2][q & 3] = lsrc[64LL * 4 * c + q];
+    }
+    int flags = 0;
+    if (tid == 0) {
+        RegionLearned rl;
+        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
+        if (L.tab != nullptr) {
+            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta,
+                                           kMaxRegSta);
+            if (ns > kMaxRegSta) {
+                flags |= kFlagSta;
+            } else if (ns > 0) {
+                double W = 0.0;
+                for (int q = 0; q < ns; ++q)
+                    W = W + L.cum[(long long)s_lsta[q] * L.ntau + L.ntau - 1];
+                rl.ns = ns; rl.W = W; rl.pl = L.pl;
+            }
+        }
+        s_rl = rl;
     }
 
     const bool use_log = logp != nullptr && chain == 0 && sweep >= log_first &&
@@ -329,11 +481,11 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
                  cnt_acc[5] = {0, 0, 0, 0, 0};
     unsigned long long samp_read = 0, samp_written = 0;
-    int flags = 0;
     __syncthreads();
+    const RegionLearned rl = s_rl;
     if (wave == 0)
         scout_move(g, lane, 0, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw, s_ex, s_ey, s_et,
-                   s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+                   s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -344,6 +496,9 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             const int m = min(kDrawChunk, g.k - (j + 1)) * 8;
             for (int q = tid; q < m; q += BLOCK)
                 s_draw[c & 1][q >> 3][q & 7] = dsrc[(long long)(j + 1) * 8 + q];
+            if (lsrc != nullptr)
+                for (int q = tid; q < m / 2; q += BLOCK)
+                    s_lb[c & 1][q >> 2][q & 3] = lsrc[(long long)(j + 1) * 4 + q];
             __syncthreads();
         }
         const MoveHdr h = s_hdr[buf];
@@ -357,7 +512,7 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         if (wave == 0) {
             if (j + 1 < g.k)  // speculative: the state as if move j is rejected
                 scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
@@ -430,9 +585,9 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         }
         double la;
         if (h.type == 0)
-            la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb;
+            la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
         else if (h.type == 1)
-            la = delta + s_log[h.n] + log_pb - log_lamR - log_pd;
+            la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
         else if (h.type == 4)
             la = delta - g.mrate * h.dm;
         else
@@ -489,7 +644,7 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
             __syncthreads();  // the new events and variance are visible
             if (wave == 0 && j + 1 < g.k)
                 scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV);
+                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
             __syncthreads();
         }
     }
@@ -517,26 +672,164 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
 }
 
 // Every move's draw record for one sweep: [chain][region][move][8], from
-// Philox (or, for chain 0 in replay mode, copied from the caller's feed).
+// Philox (or, for chain 0 in replay mode, copied from the caller's feed,
+// records of 8, or of 16 with learned births).  With learned births each
+// birth move's proposal is derived here, since it depends only on the draws
+// and on the sweep's partition: with probability pl (regions holding a
+// station) the anchor is picked by u_anchor W_R against the running weight
+// sums (stations ascending, then windows), the component by u_comp against
+// the cumulative mixture weights, and (x, y, t) = mean + sd * (truncated
+// normals); otherwise (x, y, t) come from the prior on the region.  Either
+// way log(b / p_R) at the proposal goes with it into `birth`.
 __global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
                               const double *__restrict__ feed, long long feed_first,
-                              double *__restrict__ draws)
+                              double *__restrict__ draws, const double *__restrict__ offs,
+                              Learned L, int *__restrict__ err)
 {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int chain = blockIdx.y;
     const long long per = (long long)g.R * g.k;
     if (q >= per) return;
     const long long sweep = *sweep_ptr;
-    double *out = draws + ((long long)chain * per + q) * 8;
+    const bool learned = L.tab != nullptr;
+    const int width = learned ? 16 : 8;
+    const int r = (int)(q / g.k);
+    double d[16];
     if (feed != nullptr && chain == 0) {
-        const double *row = feed + ((sweep - feed_first) * per + q) * 8;
-        for (int c = 0; c < 8; ++c) out[c] = row[c];
+        const double *row = feed + ((sweep - feed_first) * per + q) * width;
+        for (int c = 0; c < width; ++c) d[c] = row[c];
+    } else if (learned) {
+        move_draws16(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)(q % g.k), d);
     } else {
-        double d[8];
-        move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)(q / g.k),
-                   (uint32_t)(q % g.k), d);
-        for (int c = 0; c < 8; ++c) out[c] = d[c];
+        move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)(q % g.k), d);
     }
+    double *out = draws + ((long long)chain * per + q) * 8;
+    for (int c = 0; c < 8; ++c) out[c] = d[c];
+    if (!learned) return;
+    double *lb = L.birth + ((long long)chain * per + q) * 4;
+    if (!(d[0] < g.c1)) {
+        lb[0] = 0.0; lb[1] = 0.0; lb[2] = 0.0; lb[3] = 0.0;
+        return;
+    }
+    const int i = r % g.nrx, kk = r / g.nrx;
+    const double offx = offs[2 * chain], offy = offs[2 * chain + 1];
+    double x0, x1, y0, y1;
+    region_span(offx, g.wx, g.Lx, i, &x0, &x1);
+    region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
+    int sta[kMaxRegSta];
+    const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, sta, kMaxRegSta);
+    if (ns > kMaxRegSta) atomicOr(err, kFlagSta);
+    double W = 0.0, pl = 0.0;
+    if (ns > 0 && ns <= kMaxRegSta) {
+        for (int s = 0; s < ns; ++s) W = W + L.cum[(long long)sta[s] * L.ntau + L.ntau - 1];
+        pl = L.pl;
+    }
+    double x, y, t;
+    if (pl > 0.0 && d[8] < pl) {
+        const double target = d[9] * W;
+        double acc = 0.0, rem = 0.0;
+        int pick = -1;
+        for (int s = 0; s < ns; ++s) {
+            const double nxt = acc + L.cum[(long long)sta[s] * L.ntau + L.ntau - 1];
+            if (target < nxt) {
+                pick = sta[s];
+                rem = target - acc;
+                break;
+            }
+            acc = nxt;
+        }
+        if (pick < 0) {
+            pick = sta[ns - 1];
+            rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
+        }
+        // smallest window i with rem < cum[i] (the last one if none)
+        const double *cum = L.cum + (long long)pick * L.ntau;
+        int lo = 0, hi = L.ntau - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rem < cum[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
+        int k = 7;
+        for (int c = 0; c < 8; ++c)
+            if (d[10] < T[8 * c + 7]) { k = c; break; }
+        x = T[8 * k + 0] + T[8 * k + 3] * d[11];
+        y = T[8 * k + 1] + T[8 * k + 4] * d[12];
+        t = T[8 * k + 2] + T[8 * k + 5] * d[13];
+    } else {
+        x = x0 + d[1] * (x1 - x0);
+        y = y0 + d[2] * (y1 - y0);
+        t = d[3] * (double)g.N;
+    }
+    double lr = 0.0;
+    if (pl > 0.0) {
+        int ilo, ihi;
+        learned_windows(L, t, &ilo, &ihi);
+        const double S = learned_part(L, sta, ns, ilo, ihi, x, y, t, 0, 1);
+        lr = learned_log_ratio(pl, S, W, (x1 - x0) * (y1 - y0), g.N);
+    }
+    lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
+}
+
+// Running sums of every station's anchor weights (one thread per station,
+// windows in order).
+__global__ void k_learned_cum(const double *__restrict__ w, int ntau, int nsta,
+                              double *__restrict__ cum)
+{
+    const int st = blockIdx.x * blockDim.x + threadIdx.x;
+    if (st >= nsta) return;
+    double acc = 0.0;
+    for (int i = 0; i < ntau; ++i) {
+        acc = acc + w[(long long)st * ntau + i];
+        cum[(long long)st * ntau + i] = acc;
+    }
+}
+
+// Per component: log weight minus the log of its normaliser (product of the
+// sds times (sqrt(2 pi) erf(4 / sqrt 2))^3), given lz3 = 3 log(sqrt(2 pi)
+// erf(4 / sqrt 2)); and per block the min / max over components of mean t
+// -/+ 4 sd t minus the anchor's window start.
+__global__ void __launch_bounds__(256)
+k_learned_norm(const double *__restrict__ tab, long long ncomp, int ntau, double lz3,
+               double *__restrict__ norm, double *__restrict__ part)
+{
+    __shared__ double s_lo[256], s_hi[256];
+    double lo = 1e300, hi = -1e300;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ncomp;
+         q += (long long)gridDim.x * blockDim.x) {
+        const double *T = tab + q * 8;
+        norm[q] = T[6] - log(T[3]) - log(T[4]) - log(T[5]) - lz3;
+        const double tau = 32.0 * (double)((q / 8) % ntau);
+        lo = fmin(lo, T[2] - 4.0 * T[5] - tau);
+        hi = fmax(hi, T[2] + 4.0 * T[5] - tau);
+    }
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s_lo[threadIdx.x] = fmin(s_lo[threadIdx.x], s_lo[threadIdx.x + o]);
+            s_hi[threadIdx.x] = fmax(s_hi[threadIdx.x], s_hi[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s_lo[0];
+        part[2 * blockIdx.x + 1] = s_hi[0];
+    }
+}
+
+__global__ void k_learned_reach(const double *__restrict__ part, int nblocks,
+                                double *__restrict__ reach)
+{
+    double lo = 1e300, hi = -1e300;
+    for (int b = 0; b < nblocks; ++b) {
+        lo = fmin(lo, part[2 * b]);
+        hi = fmax(hi, part[2 * b + 1]);
+    }
+    reach[0] = lo;
+    reach[1] = hi;
 }
 
 // ------------------------------------------------------------------ rebin
@@ -766,13 +1059,16 @@ k_simulate(Geo g, Events ev, uint32_t seed, TraceT *__restrict__ trace, int *__r
 
 // --------------------------------------------------------------- utilities
 __global__ void k_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
-                        uint32_t j0, int count, double *__restrict__ out)
+                        uint32_t j0, int count, int width, double *__restrict__ out)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= count) return;
-    double d[8];
-    move_draws(seed, chain, sweep, region, j0 + (uint32_t)q, d);
-    for (int c = 0; c < 8; ++c) out[(long long)q * 8 + c] = d[c];
+    double d[16];
+    if (width == 16)
+        move_draws16(seed, chain, sweep, region, j0 + (uint32_t)q, d);
+    else
+        move_draws(seed, chain, sweep, region, j0 + (uint32_t)q, d);
+    for (int c = 0; c < width; ++c) out[(long long)q * width + c] = d[c];
 }
 
 __global__ void k_fill_f64(double *__restrict__ p, long long n, double v)
@@ -804,8 +1100,8 @@ template <typename TraceT>
 static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *trace, double *E,
                                  int color, const long long *sweep_ptr, const double *draws,
                                  double *logp, long long log_first, long long log_n,
-                                 unsigned long long *stats, int *err, int block, int chains,
-                                 hipStream_t s)
+                                 unsigned long long *stats, int *err, const Learned &L, int block,
+                                 int chains, hipStream_t s)
 {
     const int p = g.period;
     const int ci = color % p, ck = color / p;
@@ -815,15 +1111,15 @@ static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *tra
     switch (block) {
     case 512:
         k_sweep_color<TraceT, 512><<<grid, 512, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err);
+                                                         logp, log_first, log_n, stats, err, L);
         break;
     case 128:
         k_sweep_color<TraceT, 128><<<grid, 128, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err);
+                                                         logp, log_first, log_n, stats, err, L);
         break;
     default:
         k_sweep_color<TraceT, 256><<<grid, 256, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err);
+                                                         logp, log_first, log_n, stats, err, L);
         break;
     }
     return hipGetLastError();
@@ -832,21 +1128,43 @@ static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *tra
 hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
                         int color, const long long *sweep_ptr, const double *draws, double *logp,
                         long long log_first, long long log_n, unsigned long long *stats, int *err,
-                        int block, int chains, hipStream_t s)
+                        const Learned &L, int block, int chains, hipStream_t s)
 {
     if (f64)
         return launch_sweep_t<double>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
-                                      log_n, stats, err, block, chains, s);
+                                      log_n, stats, err, L, block, chains, s);
     return launch_sweep_t<float>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
-                                 log_n, stats, err, block, chains, s);
+                                 log_n, stats, err, L, block, chains, s);
 }
 
 hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
-                              long long feed_first, double *draws, int chains, hipStream_t s)
+                              long long feed_first, double *draws, const double *offs,
+                              const Learned &L, int *err, int chains, hipStream_t s)
 {
     const long long per = (long long)g.R * g.k;
-    const dim3 grid((unsigned)((per + 255) / 256), chains);
-    k_sweep_draws<<<grid, 256, 0, s>>>(g, sweep_ptr, feed, feed_first, draws);
+    const dim3 grid((unsigned)((per + 127) / 128), chains);
+    k_sweep_draws<<<grid, 128, 0, s>>>(g, sweep_ptr, feed, feed_first, draws, offs, L, err);
+    return hipGetLastError();
+}
+
+int learned_norm_blocks(long long ncomp)
+{
+    const long long b = (ncomp + 255) / 256;
+    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int nsta, double lz3,
+                               double *cum, double *norm, double *part, double *reach,
+                               hipStream_t s)
+{
+    k_learned_cum<<<(nsta + 127) / 128, 128, 0, s>>>(w, ntau, nsta, cum);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    const long long ncomp = (long long)nsta * ntau * 8;
+    const int nb = learned_norm_blocks(ncomp);
+    k_learned_norm<<<nb, 256, 0, s>>>(tab, ncomp, ntau, lz3, norm, part);
+    if ((e = hipGetLastError())) return e;
+    k_learned_reach<<<1, 1, 0, s>>>(part, nb, reach);
     return hipGetLastError();
 }
 
@@ -890,9 +1208,9 @@ hipError_t launch_simulate(const Geo &g, const Events &ev, uint32_t seed, void *
 }
 
 hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
-                        uint32_t j0, int count, double *out, hipStream_t s)
+                        uint32_t j0, int count, int width, double *out, hipStream_t s)
 {
-    k_draws<<<(count + 127) / 128, 128, 0, s>>>(seed, chain, sweep, region, j0, count, out);
+    k_draws<<<(count + 127) / 128, 128, 0, s>>>(seed, chain, sweep, region, j0, count, width, out);
     return hipGetLastError();
 }
 

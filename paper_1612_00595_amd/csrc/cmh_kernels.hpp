@@ -8,9 +8,14 @@ namespace cmh {
 hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
                         int color, const long long *sweep_ptr, const double *draws, double *logp,
                         long long log_first, long long log_n, unsigned long long *stats, int *err,
-                        int block, int chains, hipStream_t s);
+                        const Learned &L, int block, int chains, hipStream_t s);
 hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
-                              long long feed_first, double *draws, int chains, hipStream_t s);
+                              long long feed_first, double *draws, const double *offs,
+                              const Learned &L, int *err, int chains, hipStream_t s);
+int learned_norm_blocks(long long ncomp);
+hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int nsta, double lz3,
+                               double *cum, double *norm, double *part, double *reach,
+                               hipStream_t s);
 hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
                         const long long *sweep_ptr, int *err, int chains, hipStream_t s);
 int refresh_blocks(const Geo &g);
@@ -20,7 +25,7 @@ hipError_t launch_refresh(const Geo &g, const Events &ev, const void *trace, int
 hipError_t launch_simulate(const Geo &g, const Events &ev, uint32_t seed, void *trace, int f64,
                            int *err, hipStream_t s);
 hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
-                        uint32_t j0, int count, double *out, hipStream_t s);
+                        uint32_t j0, int count, int width, double *out, hipStream_t s);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t s);
 hipError_t fill_u64(unsigned long long *p, long long n, hipStream_t s);

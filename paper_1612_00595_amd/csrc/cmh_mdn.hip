@@ -218,13 +218,36 @@ __global__ void k_mdn_init(float *__restrict__ W, long n, int fan_in, int fan_ou
 // Rounds a binary64 feature to binary32 and then to BF16.
 __device__ inline __bf16 feat_bf16(double v) { return (__bf16)(float)v; }
 
+// Edge class of a training pair from a uniform u: class 0 (all nine block
+// stations) when 16u < 8, else 16u - 7 in the order (ex, ey) = (-1,-1)
+// (0,-1) (1,-1) (-1,0) (1,0) (-1,1) (0,1) (1,1); ex = -1 drops the block's
+// left column and puts the domain edge half a spacing left of the centre.
+__device__ inline void edge_class(double u, int *ex, int *ey)
+{
+    int k = (int)floor(u * 16.0);
+    k = k > 15 ? 15 : k;
+    if (k < 8) {
+        *ex = 0;
+        *ey = 0;
+        return;
+    }
+    k -= 8;
+    const int tx[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+    const int ty[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+    *ex = tx[k];
+    *ey = ty[k];
+}
+
 // One training pair per wave: a local world around a centre station at the
-// origin (3x3 block of stations at spacing ds), one target event and
-// kMdnBg background events, the block's traces over samples [0, 67) of the
-// window, and the 576 window features.  Draws: key (seed, 0x80000003);
-// counter (pair, 0, 0, c) for the events (c = 0 target x, y; c = 1 target t,
-// magnitude; c = 2 + b background event b x, y; c = 2 + kMdnBg + b its t,
-// magnitude); counter (pair, 1 + station, n / 2, 0) for the noise.
+// origin (3x3 block of stations at spacing ds, minus the row / column beyond
+// the domain edge of its edge class), one target event within one spacing
+// of the centre and kMdnBg background events anywhere that reaches the
+// block, the present stations' traces over samples [0, 67) of the window,
+// and the 576 window features (0 for a missing station).  Draws: key (seed,
+// 0x80000003); counter (pair, 0, 0, c) for the events (c = 0 target x, y;
+// c = 1 target t, magnitude; c = 2 + b background event b x, y; c = 2 +
+// kMdnBg + b its t, magnitude; c = 8 the edge class); counter (pair, 1 +
+// station, n / 2, 0) for the noise.
 __global__ void __launch_bounds__(64)
 k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__restrict__ Zt)
 {
@@ -232,6 +255,10 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
     __shared__ double s_q[9][kMdnWin + 4];
     const long p = first + blockIdx.x;
     const int lane = threadIdx.x;
+    uint32_t cm[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, 8u};
+    philox10(cm, seed, 0x80000003u);
+    int ex, ey;
+    edge_class(unit_open(cm[0], cm[1]), &ex, &ey);
     if (lane <= kMdnBg) {
         uint32_t c0[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, (uint32_t)(lane == 0 ? 0 : 2 + (lane - 1))};
         uint32_t c1[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u,
@@ -240,31 +267,26 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
         philox10(c1, seed, 0x80000003u);
         const double ux = unit_open(c0[0], c0[1]), uy = unit_open(c0[2], c0[3]);
         const double ut = unit_open(c1[0], c1[1]), um = unit_open(c1[2], c1[3]);
-        double x, y, t;
-        if (lane == 0) {
-            x = (2.0 * ux - 1.0) * g.ds;
-            y = (2.0 * uy - 1.0) * g.ds;
-            t = -16.0 + ut * 80.0;
-        } else {
-            const double half = 1.5 * g.ds + g.rc;
-            x = (2.0 * ux - 1.0) * half;
-            y = (2.0 * uy - 1.0) * half;
-            t = -(double)(g.ts + 8) + ut * (double)(kMdnWin + g.ts + 16);
-        }
-        s_ev[lane][0] = x;
-        s_ev[lane][1] = y;
-        s_ev[lane][2] = t;
+        const double reach = lane == 0 ? g.ds : 1.5 * g.ds + g.rc;
+        const double xlo = ex < 0 ? -0.5 * g.ds : -reach, xhi = ex > 0 ? 0.5 * g.ds : reach;
+        const double ylo = ey < 0 ? -0.5 * g.ds : -reach, yhi = ey > 0 ? 0.5 * g.ds : reach;
+        s_ev[lane][0] = xlo + ux * (xhi - xlo);
+        s_ev[lane][1] = ylo + uy * (yhi - ylo);
+        s_ev[lane][2] = lane == 0 ? -16.0 + ut * 80.0
+                                  : -(double)(g.ts + 8) + ut * (double)(kMdnWin + g.ts + 16);
         s_ev[lane][3] = g.mmin - log(um) / g.mrate;
     }
     __syncthreads();
     const int nsamp = kMdnWin + 3;
     for (int e = lane; e < 9 * nsamp; e += 64) {
         const int b = e / nsamp, n = e % nsamp;
-        const double sx = (double)(b % 3 - 1) * g.ds, sy = (double)(b / 3 - 1) * g.ds;
+        const int dx = b % 3 - 1, dy = b / 3 - 1;
+        if ((ex != 0 && dx == ex) || (ey != 0 && dy == ey)) continue;
+        const double sx = (double)dx * g.ds, sy = (double)dy * g.ds;
         double E = 0.0;
         for (int q = 0; q <= kMdnBg; ++q) {
-            const double dx = s_ev[q][0] - sx, dy = s_ev[q][1] - sy;
-            const double d = sqrt(dx * dx + dy * dy);
+            const double ddx = s_ev[q][0] - sx, ddy = s_ev[q][1] - sy;
+            const double d = sqrt(ddx * ddx + ddy * ddy);
             if (!(d < g.rc)) continue;
             const double a = s_ev[q][2] + d / g.vel;
             const double n0 = ceil(a);
@@ -286,6 +308,11 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
     __bf16 *xo = X + (long)blockIdx.x * kMdnIn;
     for (int e = lane; e < kMdnIn; e += 64) {
         const int b = e / kMdnWin, n = e % kMdnWin;
+        const int dx = b % 3 - 1, dy = b / 3 - 1;
+        if ((ex != 0 && dx == ex) || (ey != 0 && dy == ey)) {
+            xo[e] = (__bf16)0.0f;
+            continue;
+        }
         const double m4 = (s_q[b][n] + s_q[b][n + 1] + s_q[b][n + 2] + s_q[b][n + 3]) * 0.25;
         xo[e] = feat_bf16(log(g.sigma2 + m4) - ls2);
     }
@@ -296,41 +323,86 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
     }
 }
 
-// Window features and weight of every anchor of an instance: anchor a =
-// (centre station c, window start tau), c over the interior stations in
-// row-major order, tau = 32 i for tau + 67 <= N.  Weight:
-// 1e-3 + mean over the 576 features of max(0, f - 1).
+// Window features and weight of anchors first .. first + count - 1 of an
+// instance: anchor a = (station c = a / ntau, any station in row-major
+// order; window start tau = 32 (a mod ntau)).  Block stations off the grid
+// give 0.  Weight: 1e-3 + mean over the 576 features of max(0, f - 1).
 template <typename TraceT>
 __global__ void __launch_bounds__(64)
-k_anchor_feat(Geo g, const TraceT *__restrict__ trace, int ntau, __bf16 *__restrict__ X,
-              double *__restrict__ wout)
+k_anchor_feat(Geo g, const TraceT *__restrict__ trace, int ntau, long first,
+              __bf16 *__restrict__ X, double *__restrict__ wout)
 {
     __shared__ double s_f[kMdnIn];
-    const int a = blockIdx.x, lane = threadIdx.x;
-    const int c = a / ntau, ti = a % ntau;
-    const int icx = g.nsx - 2;
-    const int cx = 1 + c % icx, cy = 1 + c / icx;
-    const int tau = kMdnTScale * ti;
+    const long a = first + blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = (int)(a / ntau), ti = (int)(a % ntau);
+    const int cx = c % g.nsx, cy = c / g.nsx;
+    const long tau = (long)kMdnTScale * ti;
     const double ls2 = log(g.sigma2);
     for (int e = lane; e < kMdnIn; e += 64) {
         const int b = e / kMdnWin, n = e % kMdnWin;
-        const int j = (cy + b / 3 - 1) * g.nsx + (cx + b % 3 - 1);
-        const TraceT *row = trace + (long)j * g.N + tau + n;
-        double acc = 0.0;
-        for (int u = 0; u < 4; ++u) {
-            const double v = (double)row[u];
-            acc += v * v;
+        const int ix = cx + b % 3 - 1, iy = cy + b / 3 - 1;
+        double f = 0.0;
+        if (ix >= 0 && ix < g.nsx && iy >= 0 && iy < g.nsy) {
+            const TraceT *row = trace + ((long)iy * g.nsx + ix) * g.N + tau + n;
+            double acc = 0.0;
+            for (int u = 0; u < 4; ++u) {
+                const double v = (double)row[u];
+                acc += v * v;
+            }
+            f = log(g.sigma2 + acc * 0.25) - ls2;
         }
-        const double f = log(g.sigma2 + acc * 0.25) - ls2;
         const __bf16 fb = feat_bf16(f);
-        X[(long)a * kMdnIn + e] = fb;
+        X[(long)blockIdx.x * kMdnIn + e] = fb;
         s_f[e] = (double)(float)fb;
     }
     __syncthreads();
     double s = 0.0;
     for (int e = lane; e < kMdnIn; e += 64) s += s_f[e] > 1.0 ? s_f[e] - 1.0 : 0.0;
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) wout[a] = 1e-3 + s / (double)kMdnIn;
+    if (lane == 0) wout[blockIdx.x] = 1e-3 + s / (double)kMdnIn;
+}
+
+// Mixture table rows of anchors first .. first + rows - 1 from the head
+// outputs O[rows][64]: per component k, (mean x, y, t, sd x, y, t, log
+// weight, cumulative weight) in absolute units.  Means are clamped to the
+// anchor's station +- kMdnMuXY spacings and to [tau + 32 kMdnMuTLo, tau + 32
+// kMdnMuTHi]; log sds to their training clamps.
+__global__ void k_mixture_table(Geo g, int ntau, long first, int rows, const float *__restrict__ O,
+                                double *__restrict__ T)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const long a = first + r;
+    const int c = (int)(a / ntau);
+    const double sx = station_pos(c % g.nsx, g.ds), sy = station_pos(c / g.nsx, g.ds);
+    const double tau = (double)kMdnTScale * (double)(a % ntau);
+    const float *o = O + (long)r * kMdnOutPad;
+    double lmax = -1e300;
+    for (int k = 0; k < kMdnK; ++k) lmax = fmax(lmax, (double)o[7 * k]);
+    double se = 0.0;
+    for (int k = 0; k < kMdnK; ++k) se += exp((double)o[7 * k] - lmax);
+    const double lse = lmax + log(se);
+    const double slo[3] = {log(kMdnSdLoXY), log(kMdnSdLoXY), log(kMdnSdLoT)};
+    const double shi[3] = {log(kMdnSdHiXY), log(kMdnSdHiXY), log(kMdnSdHiT)};
+    double *out = T + (long)r * kMdnK * 8;
+    double cum = 0.0;
+    for (int k = 0; k < kMdnK; ++k) {
+        const double mx = fmin(fmax((double)o[7 * k + 1], -kMdnMuXY), kMdnMuXY);
+        const double my = fmin(fmax((double)o[7 * k + 2], -kMdnMuXY), kMdnMuXY);
+        const double mt = fmin(fmax((double)o[7 * k + 3], kMdnMuTLo), kMdnMuTHi);
+        out[8 * k + 0] = sx + g.ds * mx;
+        out[8 * k + 1] = sy + g.ds * my;
+        out[8 * k + 2] = tau + (double)kMdnTScale * mt;
+        for (int d = 0; d < 3; ++d) {
+            const double ls = fmin(fmax((double)o[7 * k + 4 + d], slo[d]), shi[d]);
+            out[8 * k + 3 + d] = (d < 2 ? g.ds : (double)kMdnTScale) * exp(ls);
+        }
+        const double lp = (double)o[7 * k] - lse;
+        cum = cum + exp(lp);
+        out[8 * k + 6] = lp;
+        out[8 * k + 7] = cum;
+    }
 }
 
 // ------------------------------------------------------------- launchers
@@ -485,15 +557,22 @@ hipError_t mdn_pairs(const Geo &g, uint32_t seed, long first, int count, __bf16 
     return hipGetLastError();
 }
 
-hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, __bf16 *X, double *w,
-                           hipStream_t s)
+hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, long first, int count,
+                           __bf16 *X, double *w, hipStream_t s)
 {
-    const int na = (g.nsx - 2) * (g.nsy - 2) * ntau;
-    if (na <= 0) return hipSuccess;
+    if (count <= 0) return hipSuccess;
     if (f64)
-        k_anchor_feat<double><<<na, 64, 0, s>>>(g, (const double *)trace, ntau, X, w);
+        k_anchor_feat<double><<<count, 64, 0, s>>>(g, (const double *)trace, ntau, first, X, w);
     else
-        k_anchor_feat<float><<<na, 64, 0, s>>>(g, (const float *)trace, ntau, X, w);
+        k_anchor_feat<float><<<count, 64, 0, s>>>(g, (const float *)trace, ntau, first, X, w);
+    return hipGetLastError();
+}
+
+hipError_t mixture_table(const Geo &g, int ntau, long first, int rows, const float *O, double *T,
+                         hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    k_mixture_table<<<(rows + 127) / 128, 128, 0, s>>>(g, ntau, first, rows, O, T);
     return hipGetLastError();
 }
 

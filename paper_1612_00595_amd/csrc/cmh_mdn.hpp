@@ -21,6 +21,12 @@ constexpr float kMdnSloXY = -3.6888794541139363f;
 constexpr float kMdnShiXY = 0.4054651081081644f;
 constexpr float kMdnSloT = -4.1588830833596715f;
 constexpr float kMdnShiT = 0.0f;
+// the same sd clamps as plain ratios for the binary64 mixture table, and the
+// table's clamps of the means: x, y within kMdnMuXY spacings of the anchor's
+// station, t in [tau + 32 kMdnMuTLo, tau + 32 kMdnMuTHi]
+constexpr double kMdnSdLoXY = 0.025, kMdnSdHiXY = 1.5;
+constexpr double kMdnSdLoT = 0.5 / 32.0, kMdnSdHiT = 1.0;
+constexpr double kMdnMuXY = 2.0, kMdnMuTLo = -1.0, kMdnMuTHi = 3.0;
 
 // FP32 parameter blob: for layer l, W[l] (fout x fin, row-major, the
 // layer's output index first) then b[l]; np floats.  The blob is followed by
@@ -53,7 +59,9 @@ hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, f
                     hipStream_t s);
 hipError_t mdn_pairs(const Geo &g, uint32_t seed, long first, int count, __bf16 *X, float *Zt,
                      hipStream_t s);
-hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, __bf16 *X, double *w,
-                           hipStream_t s);
+hipError_t anchor_features(const Geo &g, const void *trace, int f64, int ntau, long first, int count,
+                           __bf16 *X, double *w, hipStream_t s);
+hipError_t mixture_table(const Geo &g, int ntau, long first, int rows, const float *O, double *T,
+                         hipStream_t s);
 
 }  // namespace cmh

@@ -157,19 +157,74 @@ def truth_events(model: ModelSpec, seed: int, n: int | None = None):
     return dict(x=x, y=y, t=t, m=m, id=np.arange(n, dtype=np.uint64))
 
 
-def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int) -> np.ndarray:
+def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int, learned: bool = False) -> np.ndarray:
     """Per-move random draws for replay runs, shape [nsweeps, regions, k, 8]:
     [0..3] uniforms on [0,1), [4] Exp(1), [5],[6] standard normals, [7] log of
-    a uniform on (0,1].  Both the GPU path and the oracle consume the same
+    a uniform on (0,1].  With learned births the records are 16 wide: [8..10]
+    uniforms on [0,1), [11..13] standard normals truncated to [-4, 4],
+    [14], [15] zero.  Both the GPU path and the oracle consume the same
     array, so their proposals coincide bit for bit."""
     rng = np.random.Generator(np.random.PCG64(seed))
     shape = (nsweeps, sampler.nreg, sampler.k)
-    out = np.empty(shape + (8,), dtype=np.float64)
+    out = np.zeros(shape + ((16,) if learned else (8,)), dtype=np.float64)
     out[..., 0:4] = rng.random(shape + (4,))
     out[..., 4] = rng.standard_exponential(shape)
     out[..., 5:7] = rng.standard_normal(shape + (2,))
     out[..., 7] = np.log1p(-rng.random(shape))
+    if learned:
+        out[..., 8:11] = rng.random(shape + (3,))
+        z = rng.standard_normal(shape + (3,))
+        bad = np.abs(z) > 4.0
+        while bad.any():
+            z[bad] = rng.standard_normal(int(bad.sum()))
+            bad = np.abs(z) > 4.0
+        out[..., 11:14] = z
     return out
+
+
+def random_mixture_table(model: ModelSpec, seed: int, sd_scale: float = 1.0, near=None):
+    """An arbitrary learned-proposal table for every anchor (station s,
+    window i; anchor index s * n_tau + i): ([anchors][8][8] with rows (mean
+    x, y, t, sd x, y, t, log weight, cumulative weight), weights
+    [anchors], n_tau).  Means lie near the anchor's station and window; sds
+    are log-uniform over the network's clamp ranges times sd_scale.  With
+    `near` (events with fields x, y, t), component 0 of every anchor whose
+    station lies within 1.5 spacings of an event and whose window starts at
+    most 64 samples before it is moved onto that event with small sds, and
+    the anchor's weight raised, so that such proposals often land."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_tau = (model.N - 67) // 32 + 1
+    na = model.nsta * n_tau
+    st = np.repeat(np.arange(model.nsta), n_tau)
+    tau = 32.0 * np.tile(np.arange(n_tau), model.nsta)
+    sx = ((st % model.nsx) + 0.5) * model.ds
+    sy = ((st // model.nsx) + 0.5) * model.ds
+    T = np.zeros((na, 8, 8))
+    T[..., 0] = sx[:, None] + model.ds * rng.uniform(-1.5, 1.5, (na, 8))
+    T[..., 1] = sy[:, None] + model.ds * rng.uniform(-1.5, 1.5, (na, 8))
+    T[..., 2] = tau[:, None] + rng.uniform(-32.0, 96.0, (na, 8))
+    T[..., 3] = sd_scale * np.exp(rng.uniform(np.log(0.005), np.log(0.3), (na, 8)))
+    T[..., 4] = sd_scale * np.exp(rng.uniform(np.log(0.005), np.log(0.3), (na, 8)))
+    T[..., 5] = sd_scale * np.exp(rng.uniform(np.log(0.5), np.log(32.0), (na, 8)))
+    pi = rng.dirichlet(np.ones(8), na)
+    T[..., 6] = np.log(pi)
+    T[..., 7] = np.cumsum(pi, axis=1)
+    w = 1e-3 + rng.exponential(1.0, na)
+    if near is not None:
+        for e in near:
+            ix, iy = int(e["x"] // model.ds), int(e["y"] // model.ds)
+            for jy in range(max(iy - 1, 0), min(iy + 2, model.nsy)):
+                for jx in range(max(ix - 1, 0), min(ix + 2, model.nsx)):
+                    if np.hypot((jx + 0.5) * model.ds - e["x"],
+                                (jy + 0.5) * model.ds - e["y"]) > 1.5 * model.ds:
+                        continue
+                    for i in range(max(int(np.ceil((e["t"] - 64.0) / 32.0)), 0),
+                                   min(int(e["t"] // 32.0), n_tau - 1) + 1):
+                        a = (jy * model.nsx + jx) * n_tau + i
+                        T[a, 0, 0:3] = [e["x"], e["y"], e["t"]] + rng.normal(0, [0.01, 0.01, 1.0])
+                        T[a, 0, 3:6] = [0.02, 0.02, 2.0]
+                        w[a] += 20.0
+    return T, w, n_tau
 
 
 def random_state(model: ModelSpec, seed: int, n: int):

@@ -78,6 +78,9 @@ def compare_logs(g: np.ndarray, r: np.ndarray, feed: np.ndarray, acc: LogCheck, 
     rel = np.abs(dg - dr) / np.maximum(np.abs(dr), 1.0)
     acc.max_rel = max(acc.max_rel, float(rel.max()))
     assert rel.max() <= 1e-4, f"{where}: delta relative error {rel.max()}"
+    ag, ar = g[..., 3][live], r[..., 3][live]
+    rel_a = np.abs(ag - ar) / np.maximum(np.abs(ar), 1.0)
+    assert rel_a.max() <= 1e-4, f"{where}: log alpha relative error {rel_a.max()}"
     lnu = feed[..., 7][live]
     la = r[..., 3][live]
     tie = np.abs(lnu - la) <= 1e-6

@@ -165,7 +165,7 @@ def test_anchor_features_match_oracle(torch_dev, which):
     say(f"[mdn] anchors {w.name}")
     m, _, _, s = instance(w)
     na, ntau = chromh.anchor_count(w.model)
-    assert ntau == (w.model.N - 67) // 32 + 1 and na == (w.model.nsx - 2) * (w.model.nsy - 2) * ntau
+    assert ntau == (w.model.N - 67) // 32 + 1 and na == w.model.nsx * w.model.nsy * ntau
     dt = torch.float64 if w.trace_dtype == "f64" else torch.float32
     trace = torch.from_numpy(np.ascontiguousarray(s)).to(dt).cuda()
     X, wts = chromh.anchor_features(w.model, trace)

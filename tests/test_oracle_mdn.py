@@ -75,36 +75,60 @@ def test_envelope_features_closed_forms(orc):
     spec = W.ModelSpec(nsx=3, nsy=3, N=100)
     m = orc.make_model(**spec.asdict())
     s = np.full((9, 100), 0.3)
-    f = D.anchor_features(m, s, 2, 0)
+    f = D.anchor_features(m, s, 2, 4 * 2 + 0).reshape(9, 64)     # centre station
     assert np.allclose(f, np.log(0.01 + 0.09) - np.log(0.01), rtol=1e-14)
+    # corner station 0: the block's row and column beyond the grid are 0
+    f = D.anchor_features(m, s, 2, 0).reshape(3, 3, 64)
+    assert np.all(f[0, :, :] == 0) and np.all(f[:, 0, :] == 0)
+    assert np.allclose(f[1:, 1:], np.log(0.01 + 0.09) - np.log(0.01), rtol=1e-14)
     s = np.zeros((9, 100))
     s[4, 40] = 2.0                       # centre station, window of tau = 32
-    f = D.anchor_features(m, s, 2, 1).reshape(9, 64)
+    f = D.anchor_features(m, s, 2, 4 * 2 + 1).reshape(9, 64)
     spike = np.log(0.01 + 4.0 / 4) - np.log(0.01)
     assert np.allclose(f[4, 5:9], spike) and np.allclose(f[4, :5], 0) and np.allclose(f[4, 9:], 0)
     assert np.allclose(np.delete(f, 4, axis=0), 0)
 
 
-def test_training_pair_targets_and_noise_envelope(orc):
+def edge_class_of(F):
+    """(ex, ey) of pairs from which block rows / columns are all zero."""
+    z = np.all(F.reshape(-1, 3, 3, 64) == 0, axis=3)         # [pair, row, col]
+    ex = np.where(z[:, :, 0].all(1), -1, np.where(z[:, :, 2].all(1), 1, 0))
+    ey = np.where(z[:, 0, :].all(1), -1, np.where(z[:, 2, :].all(1), 1, 0))
+    return ex, ey
+
+
+def test_training_pair_targets_and_edge_classes(orc):
     m = orc.make_model(**W.SMALL.model.asdict())
-    F, T = D.pairs(m, 9, 0, 400)
-    assert stats.kstest((T[:, 0] + 1) / 2, "uniform").pvalue > 1e-3
-    assert stats.kstest((T[:, 1] + 1) / 2, "uniform").pvalue > 1e-3
+    F, T = D.pairs(m, 9, 0, 1600)
+    ex, ey = edge_class_of(F)
+    # class 0 with probability 1/2, each of the 8 edge classes 1/16
+    cls = (ey + 1) * 3 + (ex + 1)
+    obs = np.bincount(cls, minlength=9)
+    expect = np.full(9, 1600 / 16)
+    expect[4] = 800
+    assert stats.chisquare(obs, expect).pvalue > 1e-3
+    # targets: uniform over the part of the +-1 spacing box inside the domain
+    for axis, e in ((0, ex), (1, ey)):
+        for side, lo, hi in ((0, -1.0, 1.0), (-1, -0.5, 1.0), (1, -1.0, 0.5)):
+            v = T[e == side, axis]
+            assert stats.kstest((v - lo) / (hi - lo), "uniform").pvalue > 1e-3
     assert stats.kstest((T[:, 2] * 32 + 16) / 80, "uniform").pvalue > 1e-3
     # a target that arrives well inside the window (t < 48) leaves the
     # strongest station envelope far above the noise level
     inside = T[:, 2] * 32 < 48
-    assert inside.sum() > 200 and np.all(F[inside].max(1) > np.log(1 + 30))
+    assert inside.sum() > 800 and np.all(F[inside].max(1) > np.log(1 + 30))
 
 
 def test_training_pair_noise_is_chi_square(orc):
-    # with vanishing magnitudes a feature sample is pure noise: the mean of
-    # four squared N(0, sigma^2) draws, so 4 (exp(f) - 1) ~ chi2 with 4 dof;
-    # the first sample of each station is independent of every other one
+    # with vanishing magnitudes a feature sample of a present station is pure
+    # noise: the mean of four squared N(0, sigma^2) draws, so 4 (exp(f) - 1)
+    # ~ chi2 with 4 dof; the first sample of each station is independent of
+    # every other one
     spec = W.ModelSpec(nsx=5, nsy=5, N=1000, mmin=1e-7, mrate=1e7)
     m = orc.make_model(**spec.asdict())
     F, _ = D.pairs(m, 3, 100, 300)
-    x = 4 * (np.exp(F[:, ::64].ravel()) - 1)
-    assert stats.kstest(x, stats.chi2(4).cdf).pvalue > 1e-3
-    y = 4 * (np.exp(F[:, 1::64].ravel()) - 1)
-    assert stats.kstest(y, stats.chi2(4).cdf).pvalue > 1e-3
+    G = F.reshape(-1, 64)
+    G = G[~np.all(G == 0, axis=1)]
+    for col in (0, 1):
+        x = 4 * (np.exp(G[:, col]) - 1)
+        assert stats.kstest(x, stats.chi2(4).cdf).pvalue > 1e-3
