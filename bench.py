@@ -42,6 +42,12 @@ def parse():
                     help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 32-chain workload measured next to the main one")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain study on the 5x5-station worlds")
+    ap.add_argument("--learned-worlds", type=int, default=8)
+    ap.add_argument("--learned-sweeps", type=int, default=2000)
+    ap.add_argument("--learned-chains", type=int, default=16)
+    ap.add_argument("--learned-pairs", type=int, default=10_000_000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating hardware byte counters)")
@@ -87,6 +93,120 @@ def cpu_baseline(w, warmup: int, budget_s: float):
                 sample=f"{w.name}: oracle sweeps {warmup}..{warmup + sweeps - 1} "
                        f"({sweeps} sweeps, {moves} proposals, {el:.1f} s) on its own "
                        f"instance of the same shape, single thread")
+
+
+# network FLOPs per row: forward 2 (576*256 + 2*256*256 + 256*64) multiply-adds
+# (the head padded to 64), training about three times that (forward, input
+# gradients, weight gradients)
+MDN_FWD_FLOP = 2 * (576 * 256 + 2 * 256 * 256 + 256 * 64)
+MDN_TRAIN_FLOP = 3 * MDN_FWD_FLOP
+BF16_PEAK_TFLOPS = 2500.0
+ESS_CHAINS = 8
+F1_EVERY = 50
+
+
+def learned_study(args, dev):
+    """The learned birth proposal against the plain sampler on 5x5-station,
+    1000-sample worlds (seeds 100, 101, ...): the network trained on fresh
+    simulator pairs, then per world the same chains with and without
+    learned births, sweeps timed with device-side recording of every
+    state, F1 of the final states and event-location ESS after a quarter of
+    burn-in."""
+    import numpy as np
+    import torch
+
+    from paper_1612_00595_amd import chromh, learned, metrics as M, workloads as W
+    w = W.SMALL
+    log(f"[bench] training the proposal network on {args.learned_pairs} simulator pairs")
+    tr = learned.train(w.model, pairs=args.learned_pairs, batch=8192, lr=1e-3, seed=0)
+    train_tflops = tr.pairs * MDN_TRAIN_FLOP / tr.seconds / 1e12
+    out = {"workload": w.name + " worlds", "worlds": args.learned_worlds,
+           "chains": args.learned_chains, "sweeps": args.learned_sweeps,
+           "train": {"pairs": tr.pairs, "batch": 8192, "seconds": tr.seconds,
+                     "held_out_nll": tr.held_out, "achieved_TFLOPs": train_tflops,
+                     "mfma_frac": train_tflops / BF16_PEAK_TFLOPS}}
+    per = {"plain": [], "learned": []}
+    infer_s = 0.0
+    for wi in range(args.learned_worlds):
+        seed = 100 + wi
+        tr_ev = W.truth_events(w.model, seed)
+        truth = chromh.as_events(tr_ev["x"], tr_ev["y"], tr_ev["t"], tr_ev["m"])
+        trace = chromh.simulate(w.model, truth, 1000 + seed, w.trace_dtype, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, wt, ntau = learned.anchor_table(tr.net, w.model, trace)
+        torch.cuda.synchronize()
+        infer_s += time.perf_counter() - t0
+        for mode in ("plain", "learned"):
+            smp = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=args.learned_chains,
+                                          seed=seed)
+            if mode == "learned":
+                smp.set_learned(T, wt, ntau, 0.5)
+            rec = smp.set_record(0, args.learned_sweeps + 1, 256)
+            smp.run_sweeps(0, 1)            # graphs built outside the timed region
+            torch.cuda.synchronize()
+            c0 = sum(smp.read_counters(c) for c in range(args.learned_chains))
+            t0 = time.perf_counter()
+            smp.run_sweeps(1, args.learned_sweeps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            st = sum(smp.read_counters(c) for c in range(args.learned_chains)) - c0
+            f1, ess = [], []
+            curve = np.zeros(len(range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY)))
+            for c in range(args.learned_chains):
+                states = chromh.ChromaticSampler.recorded_states(rec[1:], c)
+                f1.append(M.match(tr_ev, states[-1]).f1)
+                curve += [M.match(tr_ev, states[q]).f1
+                          for q in range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY)]
+                if c < ESS_CHAINS:          # ESS per chain from a subset of the chains
+                    e, k = M.location_ess(states, tr_ev)
+                    ess.append(e if k else np.nan)
+            tab = st[:15].reshape(5, 3).astype(float)
+            per[mode].append(dict(seconds=el, f1=f1, ess=ess, curve=curve / args.learned_chains,
+                                  proposals=float(tab[:, 0].sum()),
+                                  acc=(tab[:, 2] / np.maximum(tab[:, 0], 1)).tolist()))
+            smp.close()
+        del trace, T, wt
+    for mode in ("plain", "learned"):
+        rs = per[mode]
+        f1 = np.concatenate([r["f1"] for r in rs])
+        mean, lo, hi = M.bootstrap_ci(f1)
+        # ESS/s per GPU: mean ESS per chain times the chains that run together
+        ess_s = [np.nanmean(r["ess"]) * args.learned_chains / r["seconds"] for r in rs]
+        out[mode] = {"f1": mean, "f1_ci95": [lo, hi],
+                     "ess_per_s": float(np.mean(ess_s)),
+                     "ess_per_sweep_chain": float(np.nanmean([np.nanmean(r["ess"]) for r in rs]))
+                     / args.learned_sweeps,
+                     "proposals_per_s": float(np.mean([r["proposals"] / r["seconds"] for r in rs])),
+                     "ms_per_sweep": float(np.mean([r["seconds"] for r in rs]))
+                     * 1e3 / args.learned_sweeps,
+                     "acceptance_birth_death_loc_time_mag": np.mean([r["acc"] for r in rs],
+                                                                    axis=0).round(4).tolist()}
+    pl, le = out["plain"], out["learned"]
+    out["ess_per_s_ratio"] = le["ess_per_s"] / pl["ess_per_s"]
+    # F1 against wall time (mean over worlds and chains, every F1_EVERY
+    # sweeps): when the learned chains first reach the plain chains' final F1
+    cp = np.mean([r["curve"] for r in per["plain"]], axis=0)
+    cl = np.mean([r["curve"] for r in per["learned"]], axis=0)
+    sw = np.arange(F1_EVERY, args.learned_sweeps + 1, F1_EVERY)
+    hit = np.nonzero(cl >= cp[-1])[0]
+    out["f1_curve"] = {"sweeps": sw.tolist(), "plain": cp.round(4).tolist(),
+                       "learned": cl.round(4).tolist()}
+    if len(hit):
+        t_l = sw[hit[0]] * le["ms_per_sweep"]
+        t_p = args.learned_sweeps * pl["ms_per_sweep"]
+        out["time_to_plain_final_f1"] = {"learned_ms": float(t_l), "plain_ms": float(t_p),
+                                         "speedup": float(t_p / t_l)}
+    out["equal_f1"] = bool(abs(le["f1"] - pl["f1"]) <= 0.02 or
+                           (le["f1_ci95"][0] <= pl["f1_ci95"][1]
+                            and pl["f1_ci95"][0] <= le["f1_ci95"][1]))
+    na = w.model.nsta * ((w.model.N - 67) // 32 + 1)
+    out["inference"] = {"anchors_per_world": na,
+                        "seconds_per_world": infer_s / args.learned_worlds}
+    log(f"[bench] learned study: F1 plain {pl['f1']:.3f} learned {le['f1']:.3f}; ESS/s plain "
+        f"{pl['ess_per_s']:.4g} learned {le['ess_per_s']:.4g}; training {tr.seconds:.2f} s "
+        f"({train_tflops:.1f} TFLOP/s)")
+    return out
 
 
 def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
@@ -226,6 +346,9 @@ def main():
         }
         sb.close()
         del traceb
+        torch.cuda.empty_cache()
+    if not args.no_learned:
+        out["learned"] = learned_study(args, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

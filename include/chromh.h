@@ -168,6 +168,17 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
 int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
                      int64_t n_sweeps, int32_t width);
 
+/* Sample recording (the record of Algorithm 4's output states).  After the
+ * last colour phase of every sweep s in [first_sweep, first_sweep +
+ * n_sweeps), each chain c's state is written to rec_dev[s - first_sweep][c]
+ * [1 + 4 max_events] (binary64): [0] its event count, then (x, y, t, m) of
+ * its first max_events events (regions in index order, each region's events
+ * in id order); events beyond max_events are counted but not written.  Runs
+ * inside captured sweep graphs (the sweep index is read on the device).
+ * NULL detaches.  Drops captured graphs. */
+int32_t cmh_set_record(cmh_state *st, double *rec_dev, int64_t first_sweep, int64_t n_sweeps,
+                       int32_t max_events);
+
 /* Move log.  log_dev: doubles [n_sweeps][regions][k][4] = move type,
  * status (0 rejected before the likelihood, 1 rejected, 2 accepted),
  * log-likelihood change, log acceptance ratio.  Chain 0 only.  NULL
@@ -293,7 +304,9 @@ int32_t cmh_mdn_get_params(const void *params_dev, float *host);
 
 int32_t cmh_mdn_work_bytes(int32_t rows, size_t *bytes);
 
-/* Head outputs out_dev[rows][64] (FP32) for BF16 features x_dev[rows][576]. */
+/* Head outputs out_dev[rows][64] (FP32) for BF16 features x_dev[rows][576].
+ * x_dev and work_dev must be 16-byte aligned (CMH_EINVAL otherwise), here
+ * and in cmh_mdn_gradients / cmh_mdn_train_step. */
 int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
                         void *work_dev, size_t work_bytes, void *hip_stream);
 

@@ -55,7 +55,7 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
-           "cmh_set_learned"]
+           "cmh_set_learned", "cmh_set_record"]
 
 _lib = None
 
@@ -92,6 +92,7 @@ def lib():
         "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
         "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, I32, P, P], I32),
         "cmh_learned_bytes": ([P, I32, P], I32),
+        "cmh_set_record": ([P, P, I64, I64, I32], I32),
         "cmh_set_learned": ([P, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_mdn_sizes": ([P, P], I32),
         "cmh_mdn_param_bytes": ([P], I32),
@@ -285,6 +286,34 @@ class ChromaticSampler:
         check(lib().cmh_set_learned(self._h, _ptr(table), _ptr(weights), n_tau, p_learned,
                                     _ptr(work), work.numel(), _stream(stream)))
         self._learned = (table, weights, work)
+
+    def set_record(self, first: int, n: int, max_events: int, stream=None):
+        """Record every chain's state after sweeps first .. first + n - 1 into
+        a device buffer [n, chains, 1 + 4 max_events] (returned); n = 0 stops."""
+        import torch
+        if n == 0:
+            check(lib().cmh_set_record(self._h, None, 0, 0, 0))
+            self._rec = None
+            return None
+        rec = torch.zeros((n, self.chains, 1 + 4 * max_events), dtype=torch.float64,
+                          device=self.trace.device)
+        check(lib().cmh_set_record(self._h, _ptr(rec), first, n, max_events))
+        self._rec = rec
+        return rec
+
+    @staticmethod
+    def recorded_states(rec, chain: int) -> list:
+        """Event arrays (fields x, y, t, m) of one chain from a record buffer."""
+        r = rec[:, chain].cpu().numpy() if hasattr(rec, "cpu") else rec[:, chain]
+        maxe = (r.shape[1] - 1) // 4
+        out = []
+        for row in r:
+            n = min(int(row[0]), maxe)
+            ev = np.zeros(n, dtype=EVENT_DTYPE)
+            v = row[1:1 + 4 * n].reshape(n, 4)
+            ev["x"], ev["y"], ev["t"], ev["m"] = v[:, 0], v[:, 1], v[:, 2], v[:, 3]
+            out.append(ev)
+        return out
 
     def set_log(self, log, first: int):
         """log: float64 device tensor [n_sweeps, regions, k, 4] (or None)."""

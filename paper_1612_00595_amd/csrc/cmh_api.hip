@@ -246,6 +246,9 @@ struct cmh_state {
     hipStream_t cap_stream = nullptr;
     int poisoned = 0;
     cmh::Learned learned{};  // tab == nullptr: plain births
+    double *rec = nullptr;   // sample recording (NULL: off)
+    long long rec_first = 0, rec_n = 0;
+    int rec_max = 0;
 };
 
 namespace {
@@ -344,9 +347,13 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
         hipError_t e = enqueue_sweep_start(st, s);
         if (e) return e;
     }
-    return cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
-                             st->sweep_ctr, st->draws, st->logp, st->log_first, st->log_n,
-                             st->stats, st->err, st->learned, st->block, st->chains, s);
+    hipError_t e = cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
+                                     st->sweep_ctr, st->draws, st->logp, st->log_first,
+                                     st->log_n, st->stats, st->err, st->learned, st->block,
+                                     st->chains, s);
+    if (e || st->rec == nullptr || color != st->g.ncolors - 1) return e;
+    return cmh::launch_record(st->g, st->ev[st->cur], st->sweep_ctr, st->rec, st->rec_first,
+                              st->rec_n, st->rec_max, st->chains, s);
 }
 
 void drop_graphs(cmh_state *st)
@@ -635,6 +642,21 @@ int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
     return CMH_OK;
 }
 
+int32_t cmh_set_record(cmh_state *st, double *rec_dev, int64_t first_sweep, int64_t n_sweeps,
+                       int32_t max_events)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (rec_dev && (first_sweep < 0 || n_sweeps < 1 || max_events < 0))
+        return fail(CMH_EINVAL, "record needs first_sweep >= 0, n_sweeps >= 1, max_events >= 0");
+    drop_graphs(st);
+    st->rec = rec_dev;
+    st->rec_first = rec_dev ? first_sweep : 0;
+    st->rec_n = rec_dev ? n_sweeps : 0;
+    st->rec_max = rec_dev ? max_events : 0;
+    return CMH_OK;
+}
+
 int32_t cmh_set_log(cmh_state *st, double *log_dev, int64_t first_sweep, int64_t n_sweeps)
 {
     int32_t rc = check_state(st);
@@ -826,11 +848,13 @@ size_t carve_learned(const cmh_state *st, int ntau, char *base, cmh::Learned *L,
     double *reach = c.take<double>(2);
     double *pp = c.take<double>((size_t)2 * cmh::learned_norm_blocks((long long)na * 8));
     double *birth = c.take<double>((size_t)st->chains * g.R * g.k * 4);
+    double *raw = c.take<double>((size_t)st->chains * g.R * g.k * 8);
     if (L) {
         L->cum = cum;
         L->norm = norm;
         L->reach = reach;
         L->birth = birth;
+        L->raw = raw;
     }
     if (part) *part = pp;
     return align_up(c.off);
@@ -1066,6 +1090,7 @@ size_t carve_mdn_work(int M, char *base, cmh::MdnBuffers *B, float **grad)
     b.dH[0] = c.take<__bf16>(mh);
     b.dH[1] = c.take<__bf16>(mh);
     b.loss = c.take<float>((size_t)M);
+    b.part = c.take<float>((size_t)cmh::kMdnMaxSplits * cmh::kMdnHid * cmh::kMdnIn);
     float *gr = c.take<float>((size_t)L.np);
     if (B) *B = b;
     if (grad) *grad = gr;
@@ -1073,6 +1098,12 @@ size_t carve_mdn_work(int M, char *base, cmh::MdnBuffers *B, float **grad)
 }
 
 int32_t check_rows(int32_t rows) { return rows >= 1 && rows <= (1 << 20) ? CMH_OK : fail(CMH_EINVAL, "rows must be in 1..2^20"); }
+
+int32_t check_aligned(const void *p, const char *what)
+{
+    return ((uintptr_t)p & 15u) == 0 ? CMH_OK
+                                     : fail(CMH_EINVAL, std::string(what) + " must be 16-byte aligned");
+}
 
 }  // namespace
 
@@ -1138,6 +1169,8 @@ int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows,
     int32_t rc = check_rows(rows);
     if (rc) return rc;
     if (!params_dev || !x_dev || !out_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if ((rc = check_aligned(x_dev, "x_dev")) || (rc = check_aligned(work_dev, "work_dev")))
+        return rc;
     if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
         return fail(CMH_EINVAL, "work buffer too small");
     cmh::MdnBuffers B;
@@ -1157,6 +1190,8 @@ int32_t cmh_mdn_gradients(const void *params_dev, const void *x_dev, const float
     if (rc) return rc;
     if (!params_dev || !x_dev || !z_dev || !grad_dev || !work_dev)
         return fail(CMH_EINVAL, "NULL argument");
+    if ((rc = check_aligned(x_dev, "x_dev")) || (rc = check_aligned(work_dev, "work_dev")))
+        return rc;
     if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
         return fail(CMH_EINVAL, "work buffer too small");
     cmh::MdnBuffers B;
@@ -1176,6 +1211,8 @@ int32_t cmh_mdn_train_step(void *params_dev, const void *x_dev, const float *z_d
     if (rc) return rc;
     if (step < 1) return fail(CMH_EINVAL, "Adam steps count from 1");
     if (!params_dev || !x_dev || !z_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if ((rc = check_aligned(x_dev, "x_dev")) || (rc = check_aligned(work_dev, "work_dev")))
+        return rc;
     if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
         return fail(CMH_EINVAL, "work buffer too small");
     cmh::MdnBuffers B;

@@ -51,6 +51,7 @@ struct Learned {
     const double *norm;   // [nsta * ntau][8]: log weight minus log normaliser
     const double *reach;  // min and max over the table of mean t -/+ 4 sd t - tau
     double *birth;        // [chain][region][move][4]: birth proposal x, y, t, log b/p
+    double *raw;          // [chain][region][move][8]: draws 8..15 of each record
     int ntau;
     double pl;
 };

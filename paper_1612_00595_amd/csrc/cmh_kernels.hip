@@ -673,18 +673,11 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
 
 // Every move's draw record for one sweep: [chain][region][move][8], from
 // Philox (or, for chain 0 in replay mode, copied from the caller's feed,
-// records of 8, or of 16 with learned births).  With learned births each
-// birth move's proposal is derived here, since it depends only on the draws
-// and on the sweep's partition: with probability pl (regions holding a
-// station) the anchor is picked by u_anchor W_R against the running weight
-// sums (stations ascending, then windows), the component by u_comp against
-// the cumulative mixture weights, and (x, y, t) = mean + sd * (truncated
-// normals); otherwise (x, y, t) come from the prior on the region.  Either
-// way log(b / p_R) at the proposal goes with it into `birth`.
+// records of 8, or of 16 with learned births, whose draws 8..15 go to
+// L.raw for k_learned_births).
 __global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
                               const double *__restrict__ feed, long long feed_first,
-                              double *__restrict__ draws, const double *__restrict__ offs,
-                              Learned L, int *__restrict__ err)
+                              double *__restrict__ draws, Learned L)
 {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const int chain = blockIdx.y;
@@ -705,71 +698,161 @@ __global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
     }
     double *out = draws + ((long long)chain * per + q) * 8;
     for (int c = 0; c < 8; ++c) out[c] = d[c];
-    if (!learned) return;
-    double *lb = L.birth + ((long long)chain * per + q) * 4;
-    if (!(d[0] < g.c1)) {
-        lb[0] = 0.0; lb[1] = 0.0; lb[2] = 0.0; lb[3] = 0.0;
-        return;
+    if (learned) {
+        double *raw = L.raw + ((long long)chain * per + q) * 8;
+        for (int c = 0; c < 8; ++c) raw[c] = d[8 + c];
     }
+}
+
+// Learned births of one sweep, one wave per (region, chain): each birth
+// move's proposal depends only on its draws and the sweep's partition, so
+// it is derived here, off the sweep's dependent chain of moves.  With
+// probability pl (regions holding a station) the anchor is picked by
+// u_anchor W_R against the running weight sums (stations ascending, then
+// windows), the component by u_comp against the cumulative mixture weights,
+// and (x, y, t) = mean + sd * (truncated normals); otherwise (x, y, t) come
+// from the prior on the region.  Either way log(b / p_R) at the proposal,
+// summed over (station, window) pairs across the lanes, goes with it.
+__global__ void __launch_bounds__(64)
+k_learned_births(Geo g, const double *__restrict__ draws, const double *__restrict__ offs,
+                 Learned L, int *__restrict__ err)
+{
+    __shared__ int s_sta[kMaxRegSta];
+    __shared__ int s_ns;
+    __shared__ double s_W;
+    const int r = blockIdx.x, chain = blockIdx.y, lane = threadIdx.x;
+    const long long per = (long long)g.R * g.k;
     const int i = r % g.nrx, kk = r / g.nrx;
     const double offx = offs[2 * chain], offy = offs[2 * chain + 1];
     double x0, x1, y0, y1;
     region_span(offx, g.wx, g.Lx, i, &x0, &x1);
     region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
-    int sta[kMaxRegSta];
-    const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, sta, kMaxRegSta);
-    if (ns > kMaxRegSta) atomicOr(err, kFlagSta);
-    double W = 0.0, pl = 0.0;
-    if (ns > 0 && ns <= kMaxRegSta) {
-        for (int s = 0; s < ns; ++s) W = W + L.cum[(long long)sta[s] * L.ntau + L.ntau - 1];
-        pl = L.pl;
+    if (lane == 0) {
+        int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_sta, kMaxRegSta);
+        if (ns > kMaxRegSta) {
+            atomicOr(err, kFlagSta);
+            ns = 0;
+        }
+        double W = 0.0;
+        for (int s = 0; s < ns; ++s) W = W + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
+        s_ns = ns;
+        s_W = W;
     }
-    double x, y, t;
-    if (pl > 0.0 && d[8] < pl) {
-        const double target = d[9] * W;
-        double acc = 0.0, rem = 0.0;
-        int pick = -1;
-        for (int s = 0; s < ns; ++s) {
-            const double nxt = acc + L.cum[(long long)sta[s] * L.ntau + L.ntau - 1];
-            if (target < nxt) {
-                pick = sta[s];
-                rem = target - acc;
-                break;
+    __syncthreads();
+    const int ns = s_ns;
+    const double W = s_W, pl = ns > 0 ? L.pl : 0.0;
+    const double area = (x1 - x0) * (y1 - y0);
+    for (int j = 0; j < g.k; ++j) {
+        const long long q = (long long)chain * per + (long long)r * g.k + j;
+        const double *d = draws + q * 8;
+        double *lb = L.birth + q * 4;
+        if (!(d[0] < g.c1)) {
+            if (lane < 4) lb[lane] = 0.0;
+            continue;
+        }
+        const double *e = L.raw + q * 8;  // draws 8..15
+        double x, y, t;
+        if (pl > 0.0 && e[0] < pl) {
+            // lane 0 walks the running sums; the choice is broadcast
+            double px = 0.0, py = 0.0, pt = 0.0;
+            if (lane == 0) {
+                const double target = e[1] * W;
+                double acc = 0.0, rem = 0.0;
+                int pick = -1;
+                for (int s = 0; s < ns; ++s) {
+                    const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
+                    if (target < nxt) {
+                        pick = s_sta[s];
+                        rem = target - acc;
+                        break;
+                    }
+                    acc = nxt;
+                }
+                if (pick < 0) {
+                    pick = s_sta[ns - 1];
+                    rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
+                }
+                // smallest window with rem < cum (the last one if none)
+                const double *cum = L.cum + (long long)pick * L.ntau;
+                int lo = 0, hi = L.ntau - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (rem < cum[mid]) hi = mid;
+                    else lo = mid + 1;
+                }
+                const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
+                int k = 7;
+                for (int c = 0; c < 8; ++c)
+                    if (e[2] < T[8 * c + 7]) { k = c; break; }
+                px = T[8 * k + 0] + T[8 * k + 3] * e[3];
+                py = T[8 * k + 1] + T[8 * k + 4] * e[4];
+                pt = T[8 * k + 2] + T[8 * k + 5] * e[5];
             }
-            acc = nxt;
+            x = __shfl(px, 0, 64);
+            y = __shfl(py, 0, 64);
+            t = __shfl(pt, 0, 64);
+        } else {
+            x = x0 + d[1] * (x1 - x0);
+            y = y0 + d[2] * (y1 - y0);
+            t = d[3] * (double)g.N;
         }
-        if (pick < 0) {
-            pick = sta[ns - 1];
-            rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
+        double lr = 0.0;
+        if (pl > 0.0) {
+            int ilo, ihi;
+            learned_windows(L, t, &ilo, &ihi);
+            const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, x, y, t, lane, 64));
+            lr = learned_log_ratio(pl, S, W, area, g.N);
         }
-        // smallest window i with rem < cum[i] (the last one if none)
-        const double *cum = L.cum + (long long)pick * L.ntau;
-        int lo = 0, hi = L.ntau - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (rem < cum[mid]) hi = mid;
-            else lo = mid + 1;
+        if (lane == 0) {
+            lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
         }
-        const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
-        int k = 7;
-        for (int c = 0; c < 8; ++c)
-            if (d[10] < T[8 * c + 7]) { k = c; break; }
-        x = T[8 * k + 0] + T[8 * k + 3] * d[11];
-        y = T[8 * k + 1] + T[8 * k + 4] * d[12];
-        t = T[8 * k + 2] + T[8 * k + 5] * d[13];
-    } else {
-        x = x0 + d[1] * (x1 - x0);
-        y = y0 + d[2] * (y1 - y0);
-        t = d[3] * (double)g.N;
     }
-    double lr = 0.0;
-    if (pl > 0.0) {
-        int ilo, ihi;
-        learned_windows(L, t, &ilo, &ihi);
-        const double S = learned_part(L, sta, ns, ilo, ihi, x, y, t, 0, 1);
-        lr = learned_log_ratio(pl, S, W, (x1 - x0) * (y1 - y0), g.N);
+}
+
+// Sample recording: after a sweep in [first, first + n), every chain's
+// events (regions in order, each region's list in id order) are appended to
+// rec[sweep - first][chain]: [0] the count, then (x, y, t, m) of the first
+// max_events of them.  One workgroup per chain.
+__global__ void __launch_bounds__(256)
+k_record(Geo g, Events ev, const long long *__restrict__ sweep_ptr, double *__restrict__ rec,
+         long long first, long long n, int max_events)
+{
+    __shared__ int s_base[256];
+    const long long sweep = *sweep_ptr;
+    if (sweep < first || sweep >= first + n) return;
+    const int chain = blockIdx.x, tid = threadIdx.x;
+    const long long stride = 1 + 4LL * max_events;
+    double *out = rec + ((sweep - first) * gridDim.x + chain) * stride;
+    int base = 0;
+    // regions in chunks of 256: a block prefix sum of their counts places
+    // each region's events
+    for (int r0 = 0; r0 < g.R; r0 += 256) {
+        const int r = r0 + tid;
+        const int c = r < g.R ? ev.cnt[chain * g.R + r] : 0;
+        s_base[tid] = c;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int v = tid >= o ? s_base[tid - o] : 0;
+            __syncthreads();
+            s_base[tid] += v;
+            __syncthreads();
+        }
+        const int excl = base + s_base[tid] - c;
+        if (r < g.R) {
+            const long long src = ((long long)chain * g.R + r) * g.cap;
+            for (int s = 0; s < c; ++s) {
+                const int o = excl + s;
+                if (o >= max_events) break;
+                out[1 + 4 * o + 0] = ev.x[src + s];
+                out[1 + 4 * o + 1] = ev.y[src + s];
+                out[1 + 4 * o + 2] = ev.t[src + s];
+                out[1 + 4 * o + 3] = ev.m[src + s];
+            }
+        }
+        base += s_base[255];
+        __syncthreads();
     }
-    lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
+    if (tid == 0) out[0] = (double)base;
 }
 
 // Running sums of every station's anchor weights (one thread per station,
@@ -1143,7 +1226,17 @@ hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const do
 {
     const long long per = (long long)g.R * g.k;
     const dim3 grid((unsigned)((per + 127) / 128), chains);
-    k_sweep_draws<<<grid, 128, 0, s>>>(g, sweep_ptr, feed, feed_first, draws, offs, L, err);
+    k_sweep_draws<<<grid, 128, 0, s>>>(g, sweep_ptr, feed, feed_first, draws, L);
+    hipError_t e = hipGetLastError();
+    if (e || L.tab == nullptr) return e;
+    k_learned_births<<<dim3(g.R, chains), 64, 0, s>>>(g, draws, offs, L, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const Geo &g, const Events &ev, const long long *sweep_ptr, double *rec,
+                         long long first, long long n, int max_events, int chains, hipStream_t s)
+{
+    k_record<<<chains, 256, 0, s>>>(g, ev, sweep_ptr, rec, first, n, max_events);
     return hipGetLastError();
 }
 

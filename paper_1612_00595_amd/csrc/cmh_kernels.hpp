@@ -12,6 +12,8 @@ hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f
 hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
                               long long feed_first, double *draws, const double *offs,
                               const Learned &L, int *err, int chains, hipStream_t s);
+hipError_t launch_record(const Geo &g, const Events &ev, const long long *sweep_ptr, double *rec,
+                         long long first, long long n, int max_events, int chains, hipStream_t s);
 int learned_norm_blocks(long long ncomp);
 hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int nsta, double lz3,
                                double *cum, double *norm, double *part, double *reach,

@@ -38,13 +38,16 @@ __device__ inline float gelu_grad_f(float z)
 // C[M][N] = sum_k op(A)[m][k] op(B)[k][n].  op(A)[m][k] = TA ? A[k*lda + m]
 // : A[m*lda + k]; op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64x64 tile
 // per workgroup, four waves of 32x32, k-steps of 32 staged through LDS.
+// Vector loads need the contiguous extents (M for TA, K otherwise, and N
+// for !TB) and the leading dimensions to be multiples of 8 elements.
 // EPI 0: C (fp32).  EPI 1: Z = C + bias (fp32) and GELU(Z) as BF16 into Cb.
-// EPI 2: C + bias (fp32).
+// EPI 2: C + bias (fp32).  Split K: workgroup z sums k in [z kper, (z + 1)
+// kper) and writes its partial product to C + z M ldc (EPI 0 only).
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
        int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
-       __bf16 *__restrict__ Cb, int ldcb)
+       __bf16 *__restrict__ Cb, int ldcb, int kper)
 {
     __shared__ __attribute__((aligned(16))) __bf16 sA[64][40];
     __shared__ __attribute__((aligned(16))) __bf16 sB[64][40];
@@ -55,18 +58,41 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const __bf16 zero = (__bf16)0.0f;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        for (int e = tid; e < 2048; e += 256) {
-            const int r = TA ? (e & 63) : (e >> 5), c = TA ? (e >> 6) : (e & 31);
-            const int gi = i0 + r, gk = k0 + c;
-            sA[r][c] = (gi < M && gk < K) ? (TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk])
-                                          : zero;
+    const int kbeg = blockIdx.z * kper;
+    const int kend = min(K, kbeg + kper);
+    C += (long)blockIdx.z * M * ldc;
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+        // one 16-byte load per thread and operand: 8 consecutive elements
+        // along the operand's contiguous dimension
+        {
+            bf16x8 v = {zero, zero, zero, zero, zero, zero, zero, zero};
+            if (TA) {  // A[k][m]: 8 m's at one k
+                const int kq = tid >> 3, m8 = 8 * (tid & 7);
+                const int gk = k0 + kq, gi = i0 + m8;
+                if (gk < kend && gi < M) v = *(const bf16x8 *)&A[(long)gk * lda + gi];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sA[m8 + u][kq] = v[u];
+            } else {   // A[m][k]: 8 k's of one row
+                const int r = tid >> 2, k8 = 8 * (tid & 3);
+                const int gi = i0 + r, gk = k0 + k8;
+                if (gi < M && gk < kend) v = *(const bf16x8 *)&A[(long)gi * lda + gk];
+                *(bf16x8 *)&sA[r][k8] = v;
+            }
         }
-        for (int e = tid; e < 2048; e += 256) {
-            const int r = TB ? (e >> 5) : (e & 63), c = TB ? (e & 31) : (e >> 6);
-            const int gj = j0 + r, gk = k0 + c;
-            sB[r][c] = (gj < N && gk < K) ? (TB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj])
-                                          : zero;
+        {
+            bf16x8 v = {zero, zero, zero, zero, zero, zero, zero, zero};
+            if (TB) {  // B[n][k]: 8 k's of one row
+                const int r = tid >> 2, k8 = 8 * (tid & 3);
+                const int gj = j0 + r, gk = k0 + k8;
+                if (gj < N && gk < kend) v = *(const bf16x8 *)&B[(long)gj * ldb + gk];
+                *(bf16x8 *)&sB[r][k8] = v;
+            } else {   // B[k][n]: 8 n's at one k
+                const int kq = tid >> 3, n8 = 8 * (tid & 7);
+                const int gk = k0 + kq, gj = j0 + n8;
+                if (gk < kend && gj < N) v = *(const bf16x8 *)&B[(long)gk * ldb + gj];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sB[n8 + u][kq] = v[u];
+            }
         }
         __syncthreads();
         const int kk = 8 * (lane >> 4);
@@ -106,15 +132,35 @@ __global__ void k_gelu_back(long n, const float *__restrict__ dA, const float *_
         dH[q] = (__bf16)(dA[q] * gelu_grad_f(Z[q]));
 }
 
-// db[j] = sum_m D[m][j] for BF16 or FP32 D (one thread per column, fixed order).
-template <typename T>
-__global__ void k_bias_grad(int M, int N, const T *__restrict__ D, int ldd, float *__restrict__ db)
+// Column sums of a BF16 matrix D[M][N] over rows [z mper, (z + 1) mper)
+// into part[z][N]: 64 columns per workgroup, four row phases per column
+// summed in a fixed order.
+__global__ void __launch_bounds__(256)
+k_col_partial(int M, int N, const __bf16 *__restrict__ D, int ldd, int mper,
+              float *__restrict__ part)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+    __shared__ float s_p[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int m0 = blockIdx.y * mper, m1 = min(M, m0 + mper);
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += (float)D[(long)m * ldd + j];
-    db[j] = s;
+    if (j < N)
+        for (int m = m0 + ph; m < m1; m += 4) s += (float)D[(long)m * ldd + j];
+    s_p[ph][c] = s;
+    __syncthreads();
+    if (ph == 0 && j < N)
+        part[(long)blockIdx.y * N + j] = ((s_p[0][c] + s_p[1][c]) + s_p[2][c]) + s_p[3][c];
+}
+
+// out[q] = sum over z of part[z][q] (z ascending).
+__global__ void k_sum_splits(long n, int nz, const float *__restrict__ part, float *__restrict__ out)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int z = 0; z < nz; ++z) s += part[(long)z * n + q];
+        out[q] = s;
+    }
 }
 
 // Mixture negative log-likelihood of the targets and its gradient w.r.t. the
@@ -410,12 +456,54 @@ template <bool TA, bool TB, int EPI>
 static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
                        float *C, int ldc, const float *bias, __bf16 *Cb, int ldcb, hipStream_t s)
 {
-    const dim3 grid((N + 63) / 64, (M + 63) / 64);
-    k_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Cb, ldcb);
+    const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+    k_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Cb, ldcb, K);
     return hipGetLastError();
 }
 
 static unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
+
+// Row splits of a batch reduction: chunks of at least kMdnSplitRows rows (a
+// multiple of 32), at most kMdnMaxSplits of them.
+int mdn_splits(int M, int *per)
+{
+    int z = (M + kMdnSplitRows - 1) / kMdnSplitRows;
+    z = std::max(1, std::min(z, kMdnMaxSplits));
+    int p = (M + z - 1) / z;
+    p = (p + 31) / 32 * 32;
+    *per = p;
+    return (M + p - 1) / p;
+}
+
+// Weight gradient C[Mo][N] = sum over the batch of op(A)^T B, split over the
+// batch into partial products (part) and summed in a fixed order.
+static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, const __bf16 *B,
+                              int ldb, float *C, float *part, hipStream_t s)
+{
+    int per = 0;
+    const int nz = mdn_splits(Mb, &per);
+    const dim3 grid((N + 63) / 64, (Mo + 63) / 64, nz);
+    k_gemm<true, false, 0><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb, nz > 1 ? part : C, N,
+                                                nullptr, nullptr, 0, per);
+    hipError_t e = hipGetLastError();
+    if (e || nz == 1) return e;
+    const long n = (long)Mo * N;
+    k_sum_splits<<<grid_for(n), 256, 0, s>>>(n, nz, part, C);
+    return hipGetLastError();
+}
+
+// Bias gradient db[N] = column sums of D[Mb][N], split like weight_grad.
+static hipError_t bias_grad(int Mb, int N, const __bf16 *D, int ldd, float *db, float *part,
+                            hipStream_t s)
+{
+    int per = 0;
+    const int nz = mdn_splits(Mb, &per);
+    k_col_partial<<<dim3((N + 63) / 64, nz), 256, 0, s>>>(Mb, N, D, ldd, per, part);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    k_sum_splits<<<grid_for(N), 256, 0, s>>>(N, nz, part, db);
+    return hipGetLastError();
+}
 
 MdnLayout mdn_layout()
 {
@@ -500,11 +588,10 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     k_mdn_loss<<<(M + 127) / 128, 128, 0, s>>>(M, B.O, kMdnOutPad, Zt, B.loss, B.dO, kMdnOutPad);
     if ((e = hipGetLastError())) return e;
     // head: dW4 = dO^T A3, db4 = sum dO, dA3 = dO W4
-    e = gemm<true, false, 0>(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid,
-                             grad + L.W[3], kMdnHid, nullptr, nullptr, 0, s);
+    e = weight_grad(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid, grad + L.W[3],
+                    B.part, s);
     if (e) return e;
-    k_bias_grad<__bf16><<<1, 64, 0, s>>>(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3]);
-    if ((e = hipGetLastError())) return e;
+    if ((e = bias_grad(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3], B.part, s))) return e;
     const __bf16 *dnext = B.dO;
     int nout = kMdnOutPad;
     for (int l = 2; l >= 0; --l) {
@@ -517,12 +604,9 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
         if ((e = hipGetLastError())) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
-        e = gemm<true, false, 0>(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l],
-                                 kin, nullptr, nullptr, 0, s);
+        e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l], B.part, s);
         if (e) return e;
-        k_bias_grad<__bf16><<<(kMdnHid + 63) / 64, 64, 0, s>>>(M, kMdnHid, B.dH[l & 1], kMdnHid,
-                                                               grad + L.b[l]);
-        if ((e = hipGetLastError())) return e;
+        if ((e = bias_grad(M, kMdnHid, B.dH[l & 1], kMdnHid, grad + L.b[l], B.part, s))) return e;
         dnext = B.dH[l & 1];
         nout = kMdnHid;
     }

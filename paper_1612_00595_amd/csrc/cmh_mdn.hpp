@@ -15,6 +15,8 @@ constexpr int kMdnK = 8;                // mixture components
 constexpr int kMdnOutPad = 64;          // 8 x 7 outputs padded to 64
 constexpr int kMdnBg = 3;               // background events per training pair
 constexpr int kMdnTScale = 32;          // window step and time unit, samples
+constexpr int kMdnSplitRows = 512;      // batch rows per split of a gradient reduction
+constexpr int kMdnMaxSplits = 32;       // splits at most
 // clamps of the log standard deviations (x, y in units of ds; t in units of
 // 32 samples): sigma_xy in [0.025, 1.5] ds, sigma_t in [0.5, 32] samples
 constexpr float kMdnSloXY = -3.6888794541139363f;
@@ -47,7 +49,9 @@ struct MdnBuffers {
     float *dA;        // M x 256
     __bf16 *dH[2];    // M x 256
     float *loss;      // M
+    float *part;      // split partial sums: kMdnMaxSplits x 256 x 576
 };
+int mdn_splits(int M, int *per);
 
 hipError_t mdn_init(float *params, __bf16 *hcopy, uint32_t seed, hipStream_t s);
 hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s);

@@ -40,20 +40,20 @@ def match(true_ev, inf_ev, dist_thresh: float = DIST_THRESH,
     tx, ty, tt = (np.asarray(true_ev[f], dtype=np.float64) for f in ("x", "y", "t"))
     ix, iy, it = (np.asarray(inf_ev[f], dtype=np.float64) for f in ("x", "y", "t"))
     nt, ni = len(tx), len(ix)
-    free = np.ones(ni, dtype=bool)
     pairs, dists = [], []
-    for a in np.lexsort((np.arange(nt), tt)):  # by onset time, then index
-        if not free.any():
-            break
-        cand = np.nonzero(free)[0]
-        d = np.hypot(ix[cand] - tx[a], iy[cand] - ty[a])
-        dt = np.abs(it[cand] - tt[a])
-        score = np.maximum(d / dist_thresh, dt / time_thresh)
-        b = int(np.argmin(score))
-        if d[b] < dist_thresh and dt[b] < time_thresh:
-            pairs.append((int(a), int(cand[b])))
-            dists.append(float(d[b]))
-            free[cand[b]] = False
+    if nt and ni:
+        # all pairwise separations at once; taken inferred events get +inf
+        D = np.hypot(ix[None, :] - tx[:, None], iy[None, :] - ty[:, None])
+        T = np.abs(it[None, :] - tt[:, None])
+        S = np.maximum(D / dist_thresh, T / time_thresh)
+        for a in np.lexsort((np.arange(nt), tt)):  # by onset time, then index
+            b = int(np.argmin(S[a]))
+            if not np.isfinite(S[a, b]):
+                break                               # no inferred event left
+            if D[a, b] < dist_thresh and T[a, b] < time_thresh:
+                pairs.append((int(a), b))
+                dists.append(float(D[a, b]))
+                S[:, b] = np.inf
     m = len(pairs)
     precision = m / ni if ni else 1.0
     recall = m / nt if nt else 1.0
