@@ -45,11 +45,51 @@ __device__ inline void move_draws(uint32_t seed, uint32_t chain, uint32_t sweep,
     out[6] = rad * sin(ang);
 }
 
+// Cross-lane moves within a row of 16 lanes (DPP): a double travels as two
+// 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double lane_f64(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane: quad swaps, then the
+// half-row and row mirrors leave each row's sum in all its lanes; the four
+// row sums are read out and added in a fixed order.
 __device__ inline double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// Lanes 0-31 receive the value of lanes 32-63 (v_permlane32_swap exchanges
+// lanes 32-63 of its first operand with lanes 0-31 of its second).
+__device__ inline int upper_half(int v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)r[1];
+}
+
+__device__ inline int wave_sum_i32(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 // Draw record of 16 for learned births: the 8 above, then [8] mixture
@@ -228,11 +268,12 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
             if (mine) ar = arrive(g, ex, ey, et, em, ix, iy);
         }
         // lanes 0-31 take the new event's arrival from their partner lane
+        // (the two halves of the wave swapped in registers)
         Arrival an;
-        an.in = __shfl(ar.in, hl + 32, 64);
-        an.n0 = __shfl(ar.n0, hl + 32, 64);
-        an.n1 = __shfl(ar.n1, hl + 32, 64);
-        an.B = __shfl(ar.B, hl + 32, 64);
+        an.in = upper_half(ar.in);
+        an.n0 = upper_half(ar.n0);
+        an.n1 = upper_half(ar.n1);
+        an.B = __hiloint2double(upper_half(__double2hiint(ar.B)), upper_half(__double2loint(ar.B)));
         const Arrival ao = ar;
         int ns = 0, nsamp = 0;
         Seg sa, sb;
@@ -274,10 +315,7 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
             }
         }
         seg_base += __popcll(m1) + __popcll(m2);
-        int tot = nsamp;
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
-        samp_base += __shfl(tot, 0, 64);
+        samp_base += wave_sum_i32(nsamp);
     }
     *nseg_out = seg_base;
     *S_out = samp_base;
@@ -341,12 +379,12 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
             }
         }
     }
-    type = __shfl(type, 0, 64);
-    valid = __shfl(valid, 0, 64);
+    type = __builtin_amdgcn_readlane(type, 0);
+    valid = __builtin_amdgcn_readlane(valid, 0);
     if (type == 1 && valid && rl.pl > 0.0) {
         // death under learned births: the birth density at the dying event,
         // (station, window) pairs spread over the lanes
-        const double ex = __shfl(ox, 0, 64), ey = __shfl(oy, 0, 64), et = __shfl(ot, 0, 64);
+        const double ex = lane_f64(ox, 0), ey = lane_f64(oy, 0), et = lane_f64(ot, 0);
         int ilo, ihi;
         learned_windows(L, et, &ilo, &ihi);
         const double S = wave_sum(learned_part(L, lsta, rl.ns, ilo, ihi, ex, ey, et, lane, 64));
@@ -354,10 +392,10 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
     }
     int nseg = 0, S = 0;
     if (valid && !g.prior_only) {
-        ox = __shfl(ox, 0, 64); oy = __shfl(oy, 0, 64);
-        ot = __shfl(ot, 0, 64); om = __shfl(om, 0, 64);
-        nx = __shfl(nx, 0, 64); ny = __shfl(ny, 0, 64);
-        nt = __shfl(nt, 0, 64); nm = __shfl(nm, 0, 64);
+        ox = lane_f64(ox, 0); oy = lane_f64(oy, 0);
+        ot = lane_f64(ot, 0); om = lane_f64(om, 0);
+        nx = lane_f64(nx, 0); ny = lane_f64(ny, 0);
+        nt = lane_f64(nt, 0); nm = lane_f64(nm, 0);
         int fl = 0;
         footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
                   &nseg, &S, &fl);
@@ -538,13 +576,18 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                 }
             }
             // load: every sample's variance and trace value in flight at once;
-            // idle slots read element 0 so that no branch separates the loads
+            // slots past the footprint are skipped by a block-uniform test,
+            // idle lanes of a used slot read element 0 (no per-lane branch)
             double eo[MAXQ], sv[MAXQ];
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
-                const int gi = gidx[q] >= 0 ? gidx[q] : 0;
-                eo[q] = E[ebase + gi];
-                sv[q] = (double)trace[gi];
+                eo[q] = 0.0;
+                sv[q] = 0.0;
+                if (q * EV < S) {
+                    const int gi = gidx[q] >= 0 ? gidx[q] : 0;
+                    eo[q] = E[ebase + gi];
+                    sv[q] = (double)trace[gi];
+                }
             }
             // sum of -1/2 [log(v'/v) + s^2 (1/v' - 1/v)], v = sigma^2 + E, as
             // -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')]
@@ -640,12 +683,21 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                     s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
                 }
             }
-            n = __shfl(n, 0, 64);
+            n = __builtin_amdgcn_readlane(n, 0);
             __syncthreads();  // the new events and variance are visible
-            if (wave == 0 && j + 1 < g.k)
-                scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
-            __syncthreads();
+            // The speculative move j + 1 assumed move j rejected.  After an
+            // accepted change of one event (n unchanged) it still holds
+            // unless it proposes to change that same event; a birth or
+            // death changes the list, so move j + 1 is built again.
+            const bool rebuild = h.type <= 1 || (s_hdr[buf ^ 1].type != 0 &&
+                                                 s_prop[buf ^ 1][4] == s_prop[buf][4]);
+            if (rebuild && j + 1 < g.k) {
+                if (wave == 0)
+                    scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                               s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV,
+                               L, s_lb, s_lsta, rl);
+                __syncthreads();
+            }
         }
     }
 
@@ -788,9 +840,9 @@ k_learned_births(Geo g, const double *__restrict__ draws, const double *__restri
                 py = T[8 * k + 1] + T[8 * k + 4] * e[4];
                 pt = T[8 * k + 2] + T[8 * k + 5] * e[5];
             }
-            x = __shfl(px, 0, 64);
-            y = __shfl(py, 0, 64);
-            t = __shfl(pt, 0, 64);
+            x = lane_f64(px, 0);
+            y = lane_f64(py, 0);
+            t = lane_f64(pt, 0);
         } else {
             x = x0 + d[1] * (x1 - x0);
             y = y0 + d[2] * (y1 - y0);
