@@ -42,6 +42,12 @@ def parse():
                     help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 32-chain workload measured next to the main one")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the batch of uneven instances")
+    ap.add_argument("--uneven-count", type=int, default=256)
+    ap.add_argument("--uneven-steps", type=int, default=10)
+    ap.add_argument("--uneven-block", type=int, default=64,
+                    help="sweep kernel form for the uneven batch (64: one wave per region)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain study on the 5x5-station worlds")
     ap.add_argument("--learned-worlds", type=int, default=8)
@@ -209,6 +215,51 @@ def learned_study(args, dev):
     return out
 
 
+def uneven_study(args, dev, block: int):
+    """Many independent instances of uneven size in one batch (every colour
+    phase one launch over all instances' regions of that colour): proposals/s
+    over graph-replayed sweeps and the algorithmic bytes the sweeps moved."""
+    import numpy as np
+    import torch
+
+    from paper_1612_00595_amd import chromh, workloads as W
+    ws = W.uneven_batch(args.uneven_count)
+    traces, models, samplers, seeds = [], [], [], []
+    for w in ws:
+        tr = W.truth_events(w.model, w.seed)
+        truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
+        traces.append(chromh.simulate(w.model, truth, 1000 + w.seed, "f32", dev))
+        models.append(w.model)
+        samplers.append(w.sampler)
+        seeds.append(w.seed)
+    b = chromh.Batch(models, samplers, traces, seeds, block=block)
+    b.run_sweeps(0, args.warmup)
+    torch.cuda.synchronize()
+    c0 = [b.read_counters(q) for q in range(len(ws))]
+    t0 = time.perf_counter()
+    b.run_sweeps(args.warmup, args.uneven_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c1 = [b.read_counters(q) for q in range(len(ws))]
+    d = sum(x - y for x, y in zip(c1, c0))
+    proposals = int(d[:15].reshape(5, 3)[:, 0].sum())
+    nbytes = int(d[15]) * 12 + int(d[16]) * 8
+    out = {"workload": f"{len(ws)} uneven instances (sides 8..32, 4000..36000 fp32 samples, "
+                       f"Poisson means 100..5000)",
+           "instances": len(ws), "stations": int(sum(m.nsta for m in models)),
+           "regions": int(sum(sp.nreg for sp in samplers)),
+           "poisson_mean_events": float(sum(m.lam for m in models)),
+           "value": proposals / el, "unit": "proposals/s",
+           "ms_per_step": el * 1e3 / args.uneven_steps,
+           "algorithmic_GBps_whole_sweep": nbytes / el / 1e9,
+           "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block}
+    log(f"[bench] uneven batch: {out['value']:.4g} proposals/s, {out['ms_per_step']:.2f} ms/sweep, "
+        f"{out['algorithmic_GBps_whole_sweep']:.1f} GB/s algorithmic")
+    b.close()
+    del traces, b
+    return out
+
+
 def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
     """Proposals/s over `steps` graph-replayed sweeps after `warmup`, and the
     sweep kernel's HIP-event-timed launch duration and algorithmic bytes."""
@@ -333,7 +384,9 @@ def main():
         truthb = chromh.as_events(trb["x"], trb["y"], trb["t"], trb["m"], trb["id"])
         traceb = chromh.simulate(wb.model, truthb, 1000 + wb.seed, wb.trace_dtype, dev)
         sb = chromh.ChromaticSampler(wb.model, wb.sampler, traceb, chains=wb.chains,
-                                     seed=wb.seed, block=block)
+                                     seed=wb.seed, block=args.block)
+        if args.block == 0:
+            sb.autotune(0, 2)
         rb = measure(sb, wb, args.warmup, max(args.steps // 5, 5), 2, stream)
         log(f"[bench] {wb.name}: {rb['value']:.4g} proposals/s, sweep kernel "
             f"{rb['avg_ms'] * 1e3:.1f} us/launch, {rb['achieved']:.1f} GB/s algorithmic")
@@ -343,9 +396,13 @@ def main():
             "sweep_kernel_us": rb["avg_ms"] * 1e3,
             "algorithmic_bytes_per_launch": rb["bytes_per_launch"],
             "achieved_GBps": rb["achieved"], "frac": rb["achieved"] / HBM_PEAK_GBS,
+            "block": sb.block,
         }
         sb.close()
         del traceb
+        torch.cuda.empty_cache()
+    if not args.no_uneven:
+        out["uneven"] = uneven_study(args, dev, args.uneven_block)
         torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned"] = learned_study(args, dev)

@@ -90,7 +90,10 @@ typedef struct {
     double  p_birth, p_death, p_loc, p_time, p_mag;   /* sum to 1 */
     double  step_xy, step_t, step_m;                  /* random-walk steps */
     int32_t prior_only;         /* 1: likelihood switched off */
-    int32_t block;              /* threads per workgroup: 128, 256, 512; 0 = default 256 */
+    int32_t block;              /* sweep kernel form: 128, 256, 512 threads per region (one
+                                   scout wave, the rest evaluate; for few regions per
+                                   colour), or 64: one wave per region, four regions per
+                                   workgroup (for many regions per colour); 0 = 256 */
 } cmh_sampler;
 
 typedef struct {
@@ -245,6 +248,24 @@ int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes);
 int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *weights_dev,
                         int32_t n_tau, double p_learned, void *work_dev, size_t work_bytes,
                         void *hip_stream);
+
+/* A batch of independent instances (each a model, sampler settings, trace
+ * and Philox seed; chain key 0) sampled together: every colour phase is one
+ * launch over the regions of that colour of every instance, so instances of
+ * uneven size share the device.  All instances share k, dynamic, block and
+ * the trace dtype; an instance with fewer colours simply has no regions in
+ * the later phases.  The returned state works with cmh_run_sweeps,
+ * cmh_sweep_color, cmh_read_events / cmh_read_stats (chain = instance
+ * index), cmh_set_record (chain = instance) and cmh_destroy; the other calls
+ * return CMH_EINVAL for it.  Every instance starts empty (no events, E = 0),
+ * and instance q of a batch follows the same chain as a one-chain state of
+ * its own with seed seeds[q].  traces_dev[q]: [nsta_q][n_samples_q]. */
+int32_t cmh_batch_bytes(int32_t n_instances, const cmh_model *models,
+                        const cmh_sampler *samplers, size_t *bytes);
+int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models,
+                       const cmh_sampler *samplers, const void *const *traces_dev,
+                       int32_t trace_dtype, const uint32_t *seeds, void *workspace_dev,
+                       size_t workspace_bytes, void *hip_stream, cmh_state **out);
 
 int32_t cmh_destroy(cmh_state *st);
 

@@ -55,7 +55,7 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
-           "cmh_set_learned", "cmh_set_record"]
+           "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init"]
 
 _lib = None
 
@@ -93,6 +93,8 @@ def lib():
         "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, I32, P, P], I32),
         "cmh_learned_bytes": ([P, I32, P], I32),
         "cmh_set_record": ([P, P, I64, I64, I32], I32),
+        "cmh_batch_bytes": ([I32, P, P, P], I32),
+        "cmh_batch_init": ([I32, P, P, P, I32, P, P, C.c_size_t, P, P], I32),
         "cmh_set_learned": ([P, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_mdn_sizes": ([P, P], I32),
         "cmh_mdn_param_bytes": ([P], I32),
@@ -488,3 +490,44 @@ def mixture_table(model: ModelSpec, head, first: int = 0):
     m = model_struct(model)
     check(lib().cmh_mixture_table(C.byref(m), _ptr(head), first, rows, _ptr(T), _stream()))
     return T
+
+
+class Batch(ChromaticSampler):
+    """Independent instances of uneven size sampled together: each colour
+    phase is one launch over that colour's regions of every instance.
+    Readers take the instance index where a chain index is expected."""
+
+    def __init__(self, models, samplers, traces, seeds, block: int = 0, stream=None):
+        import torch
+        n = len(models)
+        if not (len(samplers) == len(traces) == len(seeds) == n):
+            raise ValueError("models, samplers, traces and seeds must have equal lengths")
+        dt = traces[0].dtype
+        for tr, m in zip(traces, models):
+            if not (tr.is_cuda and tr.dim() == 2 and tr.is_contiguous() and tr.dtype == dt
+                    and tuple(tr.shape) == (m.nsta, m.N)):
+                raise ValueError("traces must be contiguous device tensors [stations, samples] "
+                                 "of one dtype")
+        self.models, self.samplers = list(models), list(samplers)
+        self.model, self.sampler = models[0], samplers[0]
+        self.chains = n
+        self.traces = list(traces)
+        self.trace = traces[0]
+        ms = (CmhModel * n)(*[model_struct(m) for m in models])
+        ss = (CmhSampler * n)(*[sampler_struct(sp, block) for sp in samplers])
+        self._ms, self._ss = ms, ss
+        nbytes = C.c_size_t()
+        check(lib().cmh_batch_bytes(n, ms, ss, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=traces[0].device)
+        ptrs = (C.c_void_p * n)(*[tr.data_ptr() for tr in traces])
+        sd = (C.c_uint32 * n)(*seeds)
+        h = C.c_void_p()
+        check(lib().cmh_batch_init(n, ms, ss, ptrs, CMH_F64 if dt == torch.float64 else CMH_F32,
+                                   sd, _ptr(self.workspace), self.workspace.numel(),
+                                   _stream(stream), C.byref(h)))
+        self._h = h
+        self.ncolors = max(
+            partition_and_color(m, sp.gx, sp.gy, 0.0, 0.0, sp.dynamic)[3] if sp.period == 0
+            else sp.period ** 2 for m, sp in zip(models, samplers))
+        self._feed = None
+        self._log = None

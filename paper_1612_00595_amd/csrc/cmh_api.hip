@@ -159,8 +159,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (std::fabs(sum - 1.0) > 1e-9) return fail(CMH_EINVAL, "move probabilities must sum to 1");
     if (!(s->step_xy >= 0.0) || !(s->step_t >= 0.0) || !(s->step_m >= 0.0))
         return fail(CMH_EINVAL, "step sizes must be non-negative");
-    if (s->block != 0 && s->block != 128 && s->block != 256 && s->block != 512)
-        return fail(CMH_EINVAL, "block must be 0, 128, 256 or 512");
+    if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512)
+        return fail(CMH_EINVAL, "block must be 0, 64, 128, 256 or 512");
     if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
@@ -245,7 +245,16 @@ struct cmh_state {
     int graph_block = 0;
     hipStream_t cap_stream = nullptr;
     int poisoned = 0;
+    int batch = 0;  // slots are different instances (cmh_batch_init)
     cmh::Learned learned{};  // tab == nullptr: plain births
+    // work items: one slot per chain, items (slot << 16) | region
+    int nslots = 0;
+    std::vector<cmh::Slot> slots_h;
+    cmh::Slot *slots_d = nullptr;
+    unsigned *items_all = nullptr;   // every region of every slot
+    int n_all = 0;
+    unsigned *items_col = nullptr;   // grouped by colour
+    std::vector<int> col_off, col_n;
     double *rec = nullptr;   // sample recording (NULL: off)
     long long rec_first = 0, rec_n = 0;
     int rec_max = 0;
@@ -268,7 +277,13 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     double *partials = c.take<double>((size_t)chains * cmh::refresh_blocks(g));
     double *llout = c.take<double>((size_t)chains);
     double *draws = c.take<double>((size_t)chains * g.R * (size_t)g.k * 8);
+    cmh::Slot *slots = c.take<cmh::Slot>((size_t)chains);
+    unsigned *items_all = c.take<unsigned>((size_t)chains * g.R);
+    unsigned *items_col = c.take<unsigned>((size_t)chains * g.R);
     if (st) {
+        st->slots_d = slots;
+        st->items_all = items_all;
+        st->items_col = items_col;
         st->draws = draws;
         st->E = E;
         st->ev[0] = ev0;
@@ -282,6 +297,70 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
         st->llout = llout;
     }
     return align_up(c.off);
+}
+
+// Slot c of a single-instance state: chain c's share of the chain-major
+// arrays.
+cmh::Slot chain_slot(const cmh_state *st, int c)
+{
+    const Geo &g = st->g;
+    cmh::Slot sl{};
+    sl.g = g;
+    sl.chain = (uint32_t)c;
+    sl.trace = st->trace;
+    sl.E = st->E + (size_t)c * g.nsta * (size_t)g.N;
+    for (int b = 0; b < 2; ++b) {
+        const Events &e = st->ev[b];
+        const size_t o = (size_t)c * g.R * g.cap;
+        sl.ev[b] = Events{e.x + o, e.y + o, e.t + o, e.m + o, e.id + o, e.cnt + (size_t)c * g.R,
+                          e.off + 2 * (size_t)c};
+    }
+    sl.draws = st->draws + (size_t)c * g.R * g.k * 8;
+    sl.stats = st->stats + (size_t)c * cmh::kStats;
+    sl.L = st->learned;
+    if (sl.L.tab) {
+        sl.L.birth = st->learned.birth + (size_t)c * g.R * g.k * 4;
+        sl.L.raw = st->learned.raw + (size_t)c * g.R * g.k * 8;
+    }
+    return sl;
+}
+
+// Host slot table and work items of a single-instance state, uploaded to
+// its workspace (synchronously: the host vectors are temporaries).
+int32_t upload_slots(cmh_state *st)
+{
+    const Geo &g = st->g;
+    st->nslots = st->chains;
+    st->slots_h.resize(st->chains);
+    for (int c = 0; c < st->chains; ++c) st->slots_h[c] = chain_slot(st, c);
+    std::vector<unsigned> all, col;
+    st->col_off.assign(g.ncolors, 0);
+    st->col_n.assign(g.ncolors, 0);
+    for (int c = 0; c < st->chains; ++c)
+        for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)c << 16) | (unsigned)r);
+    const int p = g.period;
+    for (int color = 0; color < g.ncolors; ++color) {
+        st->col_off[color] = (int)col.size();
+        for (int c = 0; c < st->chains; ++c)
+            for (int r = 0; r < g.R; ++r) {
+                const int i = r % g.nrx, k = r / g.nrx;
+                if ((i % p) + p * (k % p) == color) col.push_back(((unsigned)c << 16) | (unsigned)r);
+            }
+        st->col_n[color] = (int)col.size() - st->col_off[color];
+    }
+    st->n_all = (int)all.size();
+    HIPCHK(hipMemcpy(st->slots_d, st->slots_h.data(), sizeof(cmh::Slot) * st->slots_h.size(),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(st->items_all, all.data(), sizeof(unsigned) * all.size(),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(st->items_col, col.data(), sizeof(unsigned) * col.size(),
+                     hipMemcpyHostToDevice));
+    return CMH_OK;
+}
+
+int32_t check_single(cmh_state *st)
+{
+    return st->batch ? fail(CMH_EINVAL, "not available for a batch of instances") : CMH_OK;
 }
 
 int32_t check_state(cmh_state *st)
@@ -330,13 +409,14 @@ hipError_t enqueue_sweep_start(cmh_state *st, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     if (st->g.dynamic) {
-        e = cmh::launch_rebin(st->g, st->ev[st->cur], st->ev[st->cur ^ 1], st->sweep_ctr, st->err,
-                              st->chains, s);
+        e = cmh::launch_rebin(st->slots_d, st->items_all, st->n_all, st->cur, st->sweep_ctr,
+                              st->err, s);
         if (e) return e;
         st->cur ^= 1;
     }
-    return cmh::launch_sweep_draws(st->g, st->sweep_ctr, st->feed, st->feed_first, st->draws,
-                                   st->ev[st->cur].off, st->learned, st->err, st->chains, s);
+    return cmh::launch_sweep_draws(st->slots_d, st->items_all, st->n_all, st->g.k, st->cur,
+                                   st->sweep_ctr, st->feed, st->feed_first, st->feed_width,
+                                   st->learned.tab != nullptr, st->err, s);
 }
 
 // Enqueue one colour phase (colour 0 first starts the sweep), reading the
@@ -347,13 +427,12 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
         hipError_t e = enqueue_sweep_start(st, s);
         if (e) return e;
     }
-    hipError_t e = cmh::launch_sweep(st->g, st->ev[st->cur], st->trace, st->f64, st->E, color,
-                                     st->sweep_ctr, st->draws, st->logp, st->log_first,
-                                     st->log_n, st->stats, st->err, st->learned, st->block,
-                                     st->chains, s);
+    hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
+                                     st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
+                                     st->log_first, st->log_n, st->err, st->block, s);
     if (e || st->rec == nullptr || color != st->g.ncolors - 1) return e;
-    return cmh::launch_record(st->g, st->ev[st->cur], st->sweep_ctr, st->rec, st->rec_first,
-                              st->rec_n, st->rec_max, st->chains, s);
+    return cmh::launch_record(st->slots_d, st->nslots, st->cur, st->sweep_ctr, st->rec,
+                              st->rec_first, st->rec_n, st->rec_max, s);
 }
 
 void drop_graphs(cmh_state *st)
@@ -459,6 +538,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     int32_t rc = make_geo(model, sampler, &g);
     if (rc) return rc;
     if (n_chains < 1 || n_chains > 65535) return fail(CMH_EINVAL, "n_chains must be in 1..65535");
+    if (g.R > 65535) return fail(CMH_EINVAL, "at most 65535 regions");
     if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
         return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
     if (!trace_dev) return fail(CMH_EINVAL, "trace_dev is NULL");
@@ -491,6 +571,12 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
         if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
         delete st;
         return fail(CMH_EHIP, std::string("init: ") + hipGetErrorString(e));
+    }
+    rc = upload_slots(st);
+    if (rc) {
+        if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
+        delete st;
+        return rc;
     }
     *out = st;
     return CMH_OK;
@@ -549,14 +635,14 @@ int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64
     if (!n_out) return fail(CMH_EINVAL, "n_out is NULL");
     rc = sync_and_check(st);
     if (rc) return rc;
-    const Geo &g = st->g;
-    const Events &ev = st->ev[st->cur];
-    const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
+    // the chain's (or batch instance's) slot-local table
+    const Geo &g = st->slots_h[chain].g;
+    const Events &ev = st->slots_h[chain].ev[st->cur];
+    const size_t slots = (size_t)g.R * g.cap, o = 0;
     std::vector<int> cnt(g.R);
     std::vector<double> x(slots), y(slots), t(slots), m(slots);
     std::vector<unsigned long long> id(slots);
-    HIPCHK(hipMemcpy(cnt.data(), ev.cnt + (size_t)chain * g.R, g.R * sizeof(int),
-                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cnt.data(), ev.cnt, g.R * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(x.data(), ev.x + o, slots * 8, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(y.data(), ev.y + o, slots * 8, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(t.data(), ev.t + o, slots * 8, hipMemcpyDeviceToHost));
@@ -582,6 +668,7 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
     if (n < 0 || (n > 0 && !ev_host)) return fail(CMH_EINVAL, "bad event array");
     rc = sync_and_check(st);
@@ -632,6 +719,7 @@ int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (feed_dev && (first_sweep < 0 || n_sweeps < 1))
         return fail(CMH_EINVAL, "feed needs first_sweep >= 0 and n_sweeps >= 1");
     if (feed_dev && width != 8 && width != 16) return fail(CMH_EINVAL, "width must be 8 or 16");
@@ -661,6 +749,7 @@ int32_t cmh_set_log(cmh_state *st, double *log_dev, int64_t first_sweep, int64_t
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (log_dev && (first_sweep < 0 || n_sweeps < 1))
         return fail(CMH_EINVAL, "log needs first_sweep >= 0 and n_sweeps >= 1");
     st->logp = log_dev;
@@ -673,6 +762,7 @@ int32_t cmh_refresh(cmh_state *st, int32_t write_variance, double *out_host, voi
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     HIPCHK(cmh::launch_refresh(st->g, st->ev[st->cur], st->trace, st->f64, st->E,
                                write_variance ? 1 : 0, st->partials,
@@ -689,6 +779,7 @@ int32_t cmh_read_variance(cmh_state *st, int32_t chain, int64_t station0, int64_
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
     if (station0 < 0 || nsta < 0 || station0 + nsta > st->g.nsta || (nsta > 0 && !out_host))
         return fail(CMH_EINVAL, "station range out of bounds");
@@ -707,8 +798,7 @@ int32_t cmh_read_stats(cmh_state *st, int32_t chain, uint64_t *out_host)
     if (chain < 0 || chain >= st->chains || !out_host) return fail(CMH_EINVAL, "bad arguments");
     rc = sync_and_check(st);
     if (rc) return rc;
-    HIPCHK(hipMemcpy(out_host, st->stats + (size_t)chain * cmh::kStats, cmh::kStats * 8,
-                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(out_host, st->slots_h[chain].stats, cmh::kStats * 8, hipMemcpyDeviceToHost));
     return CMH_OK;
 }
 
@@ -723,6 +813,7 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
     if (st->feed || st->logp) return fail(CMH_EINVAL, "detach feed and log before tuning");
     const Geo &g = st->g;
@@ -755,7 +846,7 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const int cands[3] = {128, 256, 512};
+    const int cands[4] = {64, 128, 256, 512};
     int best = st->block;
     float best_ms = 1e30f;
     for (int b : cands) {
@@ -797,6 +888,7 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (!ms_out || n_sweeps < 1 || first_sweep < 0 || first_sweep + n_sweeps > (1LL << 32))
         return fail(CMH_EINVAL, "bad arguments");
     if (st->feed && (first_sweep < st->feed_first ||
@@ -865,6 +957,7 @@ int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes)
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
     if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
     *bytes = carve_learned(st, n_tau, nullptr, nullptr, nullptr);
@@ -877,10 +970,11 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
+    if ((rc = check_single(st))) return rc;
     drop_graphs(st);
     if (!table_dev) {
         st->learned = cmh::Learned{};
-        return CMH_OK;
+        return upload_slots(st);
     }
     if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
     if (!(p_learned >= 0.0 && p_learned < 1.0))
@@ -900,6 +994,157 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
                                     (double *)L.cum, (double *)L.norm, part, (double *)L.reach,
                                     (hipStream_t)hip_stream));
     st->learned = L;
+    HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
+    return upload_slots(st);
+}
+
+// ------------------------------------------------------------------- batch
+namespace {
+
+struct BatchPlan {
+    std::vector<Geo> g;
+    Geo head;  // what the sweep loop reads: k, dynamic, colours (the most of any instance)
+};
+
+int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *samplers, BatchPlan *P)
+{
+    if (n < 1 || n > 65535) return fail(CMH_EINVAL, "n_instances must be in 1..65535");
+    if (!models || !samplers) return fail(CMH_EINVAL, "NULL argument");
+    P->g.resize(n);
+    for (int q = 0; q < n; ++q) {
+        int32_t rc = make_geo(&models[q], &samplers[q], &P->g[q]);
+        if (rc) return rc;
+        if (P->g[q].R > 65535) return fail(CMH_EINVAL, "at most 65535 regions per instance");
+        if (P->g[q].k != P->g[0].k || P->g[q].dynamic != P->g[0].dynamic ||
+            samplers[q].block != samplers[0].block)
+            return fail(CMH_EINVAL, "instances of a batch share k, dynamic and block");
+    }
+    P->head = P->g[0];
+    for (int q = 0; q < n; ++q) P->head.ncolors = std::max(P->head.ncolors, P->g[q].ncolors);
+    return CMH_OK;
+}
+
+// Workspace of a batch: per instance E, two event tables, draws, statistics;
+// shared sweep counter, error word, slot table and work items.
+size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots,
+                   long long **sweep, int **err, cmh::Slot **slots_d, unsigned **items_all,
+                   unsigned **items_col)
+{
+    Carver c{base};
+    long long total_r = 0;
+    for (size_t q = 0; q < P.g.size(); ++q) {
+        const Geo &g = P.g[q];
+        cmh::Slot sl{};
+        sl.g = g;
+        sl.E = c.take<double>((size_t)g.nsta * (size_t)g.N);
+        for (int b = 0; b < 2; ++b) carve_events(c, g, 1, &sl.ev[b]);
+        sl.draws = c.take<double>((size_t)g.R * g.k * 8);
+        sl.stats = c.take<unsigned long long>(cmh::kStats);
+        if (slots) (*slots)[q] = sl;
+        total_r += g.R;
+    }
+    long long *sw = c.take<long long>(1);
+    int *er = c.take<int>(1);
+    cmh::Slot *sd = c.take<cmh::Slot>(P.g.size());
+    unsigned *ia = c.take<unsigned>((size_t)total_r);
+    unsigned *ic = c.take<unsigned>((size_t)total_r);
+    if (sweep) *sweep = sw;
+    if (err) *err = er;
+    if (slots_d) *slots_d = sd;
+    if (items_all) *items_all = ia;
+    if (items_col) *items_col = ic;
+    return align_up(c.off);
+}
+
+}  // namespace
+
+int32_t cmh_batch_bytes(int32_t n_instances, const cmh_model *models, const cmh_sampler *samplers,
+                        size_t *bytes)
+{
+    BatchPlan P;
+    int32_t rc = plan_batch(n_instances, models, samplers, &P);
+    if (rc) return rc;
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = carve_batch(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_sampler *samplers,
+                       const void *const *traces_dev, int32_t trace_dtype, const uint32_t *seeds,
+                       void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                       cmh_state **out)
+{
+    if (!out) return fail(CMH_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchPlan P;
+    int32_t rc = plan_batch(n_instances, models, samplers, &P);
+    if (rc) return rc;
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    if (!traces_dev || !seeds || !workspace_dev) return fail(CMH_EINVAL, "NULL argument");
+    for (int q = 0; q < n_instances; ++q)
+        if (!traces_dev[q]) return fail(CMH_EINVAL, "NULL trace");
+    const size_t need = carve_batch(P, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr);
+    if (workspace_bytes < need)
+        return fail(CMH_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    cmh_state *st = new cmh_state();
+    st->batch = 1;
+    st->g = P.head;
+    st->chains = n_instances;
+    st->nslots = n_instances;
+    st->f64 = trace_dtype == CMH_F64;
+    st->block = samplers[0].block ? samplers[0].block : 256;
+    st->slots_h.resize(n_instances);
+    carve_batch(P, (char *)workspace_dev, &st->slots_h, &st->sweep_ctr, &st->err, &st->slots_d,
+                &st->items_all, &st->items_col);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
+    std::vector<unsigned> all, col;
+    for (int q = 0; q < n_instances && !e; ++q) {
+        cmh::Slot &sl = st->slots_h[q];
+        sl.g.seed = seeds[q];
+        sl.chain = 0;
+        sl.trace = traces_dev[q];
+        const Geo &g = sl.g;
+        e = cmh::fill_f64(sl.E, (long long)g.nsta * g.N, 0.0, s);
+        for (int b = 0; b < 2 && !e; ++b) {
+            e = cmh::fill_i32(sl.ev[b].cnt, g.R, 0, s);
+            if (!e) e = cmh::fill_f64(sl.ev[b].off, 2, 0.0, s);
+        }
+        if (!e) e = cmh::fill_u64(sl.stats, cmh::kStats, s);
+        for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)q << 16) | (unsigned)r);
+    }
+    st->col_off.assign(P.head.ncolors, 0);
+    st->col_n.assign(P.head.ncolors, 0);
+    for (int color = 0; color < P.head.ncolors; ++color) {
+        st->col_off[color] = (int)col.size();
+        for (int q = 0; q < n_instances; ++q) {
+            const Geo &g = st->slots_h[q].g;
+            for (int r = 0; r < g.R; ++r) {
+                const int i = r % g.nrx, k = r / g.nrx;
+                if ((i % g.period) + g.period * (k % g.period) == color)
+                    col.push_back(((unsigned)q << 16) | (unsigned)r);
+            }
+        }
+        st->col_n[color] = (int)col.size() - st->col_off[color];
+    }
+    st->n_all = (int)all.size();
+    if (!e) e = cmh::fill_i32(st->err, 1, 0, s);
+    if (!e) e = cmh::set_sweep(st->sweep_ctr, 0, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (!e) e = hipMemcpy(st->slots_d, st->slots_h.data(), sizeof(cmh::Slot) * n_instances,
+                          hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(st->items_all, all.data(), sizeof(unsigned) * all.size(),
+                          hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(st->items_col, col.data(), sizeof(unsigned) * col.size(),
+                          hipMemcpyHostToDevice);
+    if (e) {
+        if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
+        delete st;
+        return fail(CMH_EHIP, std::string("batch init: ") + hipGetErrorString(e));
+    }
+    *out = st;
     return CMH_OK;
 }
 

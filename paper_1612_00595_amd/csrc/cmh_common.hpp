@@ -56,6 +56,10 @@ struct Learned {
     double pl;
 };
 
+// Work items of the sweep kernels: region r of slot s packed as (s << 16) | r.
+constexpr int kMaxItemRegions = 65536;
+constexpr int kMaxSlots = 65536;
+
 // Region-slot event table for all chains.  Slot s of region r of chain c is
 // element ((c * R) + r) * cap + s of each array; cnt[c * R + r] slots are
 // live, ordered by id.  off[2c], off[2c+1]: the partition offset the table
@@ -65,6 +69,23 @@ struct Events {
     unsigned long long *id;
     int *cnt;
     double *off;
+};
+
+// One chain of one instance as the sweep kernels see it: the instance's
+// constants, its Philox key word (seed in g, chain here), and its own
+// buffers.  The event tables are slot-local: region r's events at r * cap,
+// cnt[r], the offsets at off[0..1]; draws [R][k][8]; stats [kStats].  The
+// learned arrays birth and raw are slot-local too.
+struct Slot {
+    Geo g;
+    uint32_t chain;
+    int pad_;
+    const void *trace;
+    double *E;            // [nsta][N]
+    Events ev[2];         // ping-pong tables of the dynamic re-layout
+    double *draws;
+    unsigned long long *stats;
+    Learned L;
 };
 
 // ---------------------------------------------------------------- Philox

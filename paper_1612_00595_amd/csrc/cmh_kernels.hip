@@ -326,19 +326,17 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
 // draws and the region's current events, and its footprint, into buffer
 // `buf`.  Lane 0 owns the event table; the other lanes help with the
 // footprint.
-__device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i, int kk,
-                                  double offx, double offy, double x0, double x1, double y0,
-                                  double y1, int n, const double (*drw)[kDrawChunk][8],
-                                  const double *s_ex, const double *s_ey, const double *s_et,
-                                  const double *s_em, Seg (*s_seg)[kMaxSeg], MoveHdr *s_hdr,
-                                  double (*s_prop)[5], int max_samples, const Learned &L,
-                                  const double (*lbs)[kDrawChunk][4], const int *lsta,
+__device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk, double offx,
+                                  double offy, double x0, double x1, double y0, double y1, int n,
+                                  const double *d, const double *s_ex, const double *s_ey,
+                                  const double *s_et, const double *s_em, Seg (*s_seg)[kMaxSeg],
+                                  MoveHdr *s_hdr, double (*s_prop)[5], int max_samples,
+                                  const Learned &L, const double *lb, const int *lsta,
                                   const RegionLearned &rl)
 {
     int type = 0, valid = 0, idx = -1, mflags = 0;
     double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0, lr = 0;
     if (lane == 0) {
-        const double *d = drw[(jj >> 6) & 1][jj & 63];
         const double u = d[0];
         type = u < g.c1 ? 0 : u < g.c2 ? 1 : u < g.c3 ? 2 : u < g.c4 ? 3 : 4;
         if (type == 0) {
@@ -346,7 +344,6 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
                 mflags |= kFlagCap;
             } else {
                 if (L.tab != nullptr) {  // derived for the sweep by the draw kernel
-                    const double *lb = lbs[(jj >> 6) & 1][jj & 63];
                     nx = lb[0]; ny = lb[1]; nt = lb[2]; lr = lb[3];
                 } else {
                     nx = x0 + d[1] * (x1 - x0);
@@ -415,8 +412,8 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
     }
 }
 
-// One workgroup per region of colour `color` (blockIdx.x) and chain
-// (blockIdx.y); k MH moves in sequence (Algorithm 4's inner loop).
+// One workgroup per work item (slot, region) of one colour; k MH moves in
+// sequence (Algorithm 4's inner loop).
 //   Wave 0 (scout) builds each move's proposal and footprint.  While the
 //   other waves evaluate move j it already builds move j + 1 on the
 //   assumption that move j is rejected (the state is then unchanged); after
@@ -432,10 +429,9 @@ __device__ inline void scout_move(const Geo &g, int lane, int jj, int buf, int i
 // colour (the Markov-blanket argument of Section 4.1).
 template <typename TraceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E,
-              int color, const long long *__restrict__ sweep_ptr, const double *__restrict__ draws,
-              double *__restrict__ logp, long long log_first, long long log_n,
-              unsigned long long *__restrict__ stats, int *__restrict__ err, Learned L)
+k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
+              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
+              long long log_first, long long log_n, int *__restrict__ err)
 {
     static_assert(BLOCK >= 128 && BLOCK % 64 == 0, "one scout wave and at least one evaluator");
     constexpr int W = BLOCK / 64;
@@ -456,14 +452,17 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     __shared__ int s_n;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int p = g.period;
-    const int ci = color % p, ck = color / p;
-    const int ni = (g.nrx - ci + p - 1) / p;
-    const int i = ci + p * ((int)blockIdx.x % ni);
-    const int kk = ck + p * ((int)blockIdx.x / ni);
-    if (i >= g.nrx || kk >= g.nry) return;
-    const int r = kk * g.nrx + i;
-    const int chain = blockIdx.y;
+    const unsigned item = items[blockIdx.x];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
+    const Geo g = slots[slot].g;
+    const Events ev = slots[slot].ev[par];
+    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+    double *__restrict__ E = slots[slot].E;
+    const double *__restrict__ draws = slots[slot].draws;
+    unsigned long long *__restrict__ stats = slots[slot].stats;
+    const Learned L = slots[slot].L;
+    const int chain = 0;  // every array of the slot is slot-local
+    const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
 
     const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
@@ -514,7 +513,7 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         s_rl = rl;
     }
 
-    const bool use_log = logp != nullptr && chain == 0 && sweep >= log_first &&
+    const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
     unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
                  cnt_acc[5] = {0, 0, 0, 0, 0};
@@ -522,8 +521,8 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     __syncthreads();
     const RegionLearned rl = s_rl;
     if (wave == 0)
-        scout_move(g, lane, 0, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw, s_ex, s_ey, s_et,
-                   s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
+        scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex, s_ey,
+                   s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb[0][0], s_lsta, rl);
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -549,8 +548,10 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
         for (int q = 0; q < MAXQ; ++q) { gidx[q] = -1; enew[q] = 0.0; }
         if (wave == 0) {
             if (j + 1 < g.k)  // speculative: the state as if move j is rejected
-                scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                           s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb, s_lsta, rl);
+                scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                           s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em, s_seg,
+                           s_hdr, s_prop, MAXQ * EV, L, s_lb[((j + 1) >> 6) & 1][(j + 1) & 63],
+                           s_lsta, rl);
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
@@ -693,9 +694,10 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
                                                  s_prop[buf ^ 1][4] == s_prop[buf][4]);
             if (rebuild && j + 1 < g.k) {
                 if (wave == 0)
-                    scout_move(g, lane, j + 1, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                               s_draw, s_ex, s_ey, s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV,
-                               L, s_lb, s_lsta, rl);
+                    scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                               s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em,
+                               s_seg, s_hdr, s_prop, MAXQ * EV, L,
+                               s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
                 __syncthreads();
             }
         }
@@ -723,40 +725,336 @@ k_sweep_color(Geo g, Events ev, const TraceT *__restrict__ trace, double *__rest
     }
 }
 
-// Every move's draw record for one sweep: [chain][region][move][8], from
-// Philox (or, for chain 0 in replay mode, copied from the caller's feed,
-// records of 8, or of 16 with learned births, whose draws 8..15 go to
-// L.raw for k_learned_births).
-__global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
-                              const double *__restrict__ feed, long long feed_first,
-                              double *__restrict__ draws, Learned L)
+// ----------------------------------------------------- sweep colour, waves
+// Throughput form of a colour phase, for launches with many more work items
+// than the device holds workgroups: each of the four waves of a workgroup
+// runs one work item's k moves by itself, in sequence (proposal and
+// footprint as the scout builds them, then the likelihood change over the
+// footprint in passes of 64 kWaveQ samples, then the decision and, on
+// acceptance, a second pass writing the new variance).  No speculation and
+// no barrier once the tables are filled; the wave's LDS is about a quarter
+// of the latency form's, so a CU holds several times as many regions.
+constexpr int kWaveQ = 4;
+constexpr int kWaveDraws = 16;  // moves whose draws are staged at once
+
+// Flat footprint samples base + lane + 64 q of one pass: their run and
+// global index (-1 past the footprint).
+__device__ inline void wave_locate(const Geo &g, const Seg *sg, int nseg, int S, int base,
+                                   int lane, int *sidx, int *sbeg, int *gidx)
+{
+    int acc = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveQ; ++q) { sidx[q] = 0; sbeg[q] = 0; gidx[q] = -1; }
+    for (int t = 0; t < nseg; ++t) {
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q) {
+            const bool here = base + lane + 64 * q >= acc;
+            sidx[q] = here ? t : sidx[q];
+            sbeg[q] = here ? acc : sbeg[q];
+        }
+        acc += sg[t].len;
+    }
+#pragma unroll
+    for (int q = 0; q < kWaveQ; ++q) {
+        const int f = base + lane + 64 * q;
+        if (f < S) gidx[q] = sg[sidx[q]].j * g.N + sg[sidx[q]].lo + (f - sbeg[q]);
+    }
+}
+
+// New event variance at one footprint sample (old value e0).
+__device__ inline double wave_new_e(const Seg &a, const double *sT, int nn, double e0)
+{
+    const bool io = nn >= a.o0 && nn < a.o1;
+    const bool iw = nn >= a.w0 && nn < a.w1;
+    const double co = io ? a.Bo * sT[io ? nn - a.o0 : 0] : 0.0;
+    const double cn = iw ? a.Bn * sT[iw ? nn - a.w0 : 0] : 0.0;
+    const double en = (e0 - co) + cn;
+    return en > 0.0 ? en : 0.0;
+}
+
+// This lane's share of the log-likelihood change of a move.
+template <typename TraceT>
+__device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace,
+                                  const double *__restrict__ E, const Seg *sg, int nseg, int S,
+                                  const double *sT, int lane)
+{
+    double lp = 0.0, lin = 0.0;
+    for (int base = 0; base < S; base += 64 * kWaveQ) {
+        int sidx[kWaveQ], sbeg[kWaveQ], gidx[kWaveQ];
+        wave_locate(g, sg, nseg, S, base, lane, sidx, sbeg, gidx);
+        double eo[kWaveQ], sv[kWaveQ];
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q) {
+            eo[q] = 0.0;
+            sv[q] = 0.0;
+            if (base + 64 * q < S) {
+                const int gi = gidx[q] >= 0 ? gidx[q] : 0;
+                eo[q] = E[gi];
+                sv[q] = (double)trace[gi];
+            }
+        }
+        double prod = 1.0;
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q) {
+            if (base + 64 * q < S && gidx[q] >= 0) {
+                const Seg &a = sg[sidx[q]];
+                const int nn = gidx[q] - a.j * g.N;
+                const double e0 = eo[q];
+                const double en = wave_new_e(a, sT, nn, e0);
+                const double de = en - e0;
+                const double v = g.sigma2 + e0, vp = g.sigma2 + en;
+                const double inv = 1.0 / (v * vp);
+                prod *= de != 0.0 ? vp * vp * inv : 1.0;
+                lin += sv[q] * sv[q] * de * inv;
+            }
+        }
+        lp += log(prod);
+    }
+    return -0.5 * (lp - lin);
+}
+
+// After an acceptance: the new variance over the footprint, written in place.
+__device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg, int nseg, int S,
+                           const double *sT, int lane)
+{
+    for (int base = 0; base < S; base += 64 * kWaveQ) {
+        int sidx[kWaveQ], sbeg[kWaveQ], gidx[kWaveQ];
+        wave_locate(g, sg, nseg, S, base, lane, sidx, sbeg, gidx);
+        double eo[kWaveQ];
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q) {
+            eo[q] = 0.0;
+            if (base + 64 * q < S) eo[q] = E[gidx[q] >= 0 ? gidx[q] : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q)
+            if (base + 64 * q < S && gidx[q] >= 0) {
+                const Seg &a = sg[sidx[q]];
+                E[gidx[q]] = wave_new_e(a, sT, gidx[q] - a.j * g.N, eo[q]);
+            }
+    }
+}
+
+template <typename TraceT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
+             const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
+             long long log_first, long long log_n, int *__restrict__ err)
+{
+    __shared__ double s_log[kMaxCap + 2];
+    __shared__ double s_T[4][kMaxTs];
+    __shared__ double s_draw[4][kWaveDraws][8];
+    __shared__ double s_lb[4][kWaveDraws][4];
+    __shared__ double s_ex[4][kMaxCap], s_ey[4][kMaxCap], s_et[4][kMaxCap], s_em[4][kMaxCap];
+    __shared__ unsigned long long s_id[4][kMaxCap];
+    __shared__ Seg s_seg[4][1][kMaxSeg];
+    __shared__ MoveHdr s_hdr[4][1];
+    __shared__ double s_prop[4][1][5];
+    __shared__ int s_lsta[4][kMaxRegSta];
+    __shared__ RegionLearned s_rl[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int q = tid; q < kMaxCap + 2; q += 256) s_log[q] = log((double)q);
+    __syncthreads();  // the only barrier: every wave passes it before any leaves
+    const int it = blockIdx.x * 4 + wv;
+    if (it >= nitems) return;
+    const unsigned item = items[it];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
+    // the instance's constants live in LDS: held in registers they would
+    // halve the waves a CU can hold
+    __shared__ Geo s_g[4];
+    if (lane == 0) s_g[wv] = slots[slot].g;
+    __builtin_amdgcn_wave_barrier();
+    const Geo &g = s_g[wv];
+    const Events ev = slots[slot].ev[par];
+    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+    double *__restrict__ E = slots[slot].E;
+    const double *__restrict__ draws = slots[slot].draws;
+    unsigned long long *__restrict__ stats = slots[slot].stats;
+    const Learned L = slots[slot].L;
+    const int i = r % g.nrx, kk = r / g.nrx;
+    const long long sweep = *sweep_ptr;
+    const double offx = ev.off[0], offy = ev.off[1];
+    double x0, x1, y0, y1;
+    region_span(offx, g.wx, g.Lx, i, &x0, &x1);
+    region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
+    const double area = (x1 - x0) * (y1 - y0);
+    if (!(area > 0.0)) return;
+    const double lamR = g.lambda * area / (g.Lx * g.Ly);
+    const double log_lamR = log(lamR), log_pb = log(g.pb), log_pd = log(g.pd);
+
+    double *sT = s_T[wv];
+    double *ex = s_ex[wv], *ey = s_ey[wv], *et = s_et[wv], *em = s_em[wv];
+    unsigned long long *eid = s_id[wv];
+    const long long base = (long long)r * g.cap;
+    int n = ev.cnt[r];
+    for (int s = lane; s < n; s += 64) {
+        ex[s] = ev.x[base + s]; ey[s] = ev.y[base + s];
+        et[s] = ev.t[base + s]; em[s] = ev.m[base + s];
+        eid[s] = ev.id[base + s];
+    }
+    for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-2.0 * (double)q / g.decay);
+    int flags = 0;
+    if (lane == 0) {
+        RegionLearned rl;
+        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
+        if (L.tab != nullptr) {
+            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta[wv],
+                                           kMaxRegSta);
+            if (ns > kMaxRegSta) {
+                flags |= kFlagSta;
+            } else if (ns > 0) {
+                double W = 0.0;
+                for (int q = 0; q < ns; ++q)
+                    W = W + L.cum[(long long)s_lsta[wv][q] * L.ntau + L.ntau - 1];
+                rl.ns = ns; rl.W = W; rl.pl = L.pl;
+            }
+        }
+        s_rl[wv] = rl;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const RegionLearned rl = s_rl[wv];
+    const double *dsrc = draws + (long long)r * g.k * 8;
+    const double *lsrc = L.tab != nullptr ? L.birth + (long long)r * g.k * 4 : nullptr;
+    const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
+                         sweep < log_first + log_n;
+    unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
+                 cnt_acc[5] = {0, 0, 0, 0, 0};
+    unsigned long long samp_read = 0, samp_written = 0;
+
+    for (int j = 0; j < g.k; ++j) {
+        const int jw = j % kWaveDraws;
+        if (jw == 0) {  // stage the next kWaveDraws moves' records
+            const int m = min(kWaveDraws, g.k - j);
+            for (int q = lane; q < 8 * m; q += 64)
+                s_draw[wv][q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
+            if (lsrc != nullptr)
+                for (int q = lane; q < 4 * m; q += 64)
+                    s_lb[wv][q >> 2][q & 3] = lsrc[(long long)j * 4 + q];
+            __builtin_amdgcn_wave_barrier();
+        }
+        scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey, et,
+                   em, s_seg[wv], s_hdr[wv], s_prop[wv], kMaxFootprint, L, s_lb[wv][jw],
+                   s_lsta[wv], rl);
+        __builtin_amdgcn_wave_barrier();
+        const MoveHdr h = s_hdr[wv][0];
+        const double lnu = s_draw[wv][jw][7];
+        const bool evaluate = h.valid && !g.prior_only;
+        double delta = 0.0;
+        if (evaluate)
+            delta = wave_sum(wave_delta_part<TraceT>(g, trace, E, s_seg[wv][0], h.nseg, h.S, sT,
+                                                     lane));
+        double la;
+        if (h.type == 0)
+            la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
+        else if (h.type == 1)
+            la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
+        else if (h.type == 4)
+            la = delta - g.mrate * h.dm;
+        else
+            la = delta;
+        bool accept = h.valid && lnu < la;
+        if (!(delta == delta) || delta - delta != 0.0) {
+            accept = false;
+            flags |= kFlagNan;
+        }
+        if (lane == 0) {
+            flags |= h.flags;
+            cnt_att[h.type]++;
+            if (h.valid) {
+                cnt_val[h.type]++;
+                samp_read += (unsigned long long)h.S;
+            }
+            if (use_log) {
+                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
+                lg[0] = (double)h.type;
+                lg[1] = h.valid ? (accept ? 2.0 : 1.0) : 0.0;
+                lg[2] = h.valid ? delta : 0.0;
+                lg[3] = h.valid ? la : 0.0;
+            }
+        }
+        if (accept) {
+            if (!g.prior_only) wave_write(g, E, s_seg[wv][0], h.nseg, h.S, sT, lane);
+            if (lane == 0) {
+                cnt_acc[h.type]++;
+                samp_written += (unsigned long long)h.S;
+                const double *pr = s_prop[wv][0];
+                if (h.type == 0) {
+                    ex[n] = pr[0]; ey[n] = pr[1]; et[n] = pr[2]; em[n] = pr[3];
+                    eid[n] = ((unsigned long long)(uint32_t)sweep << 32) |
+                             ((unsigned long long)r << 12) | (unsigned long long)j;
+                    ++n;
+                } else if (h.type == 1) {
+                    const int idx = (int)pr[4];
+                    for (int q = idx; q + 1 < n; ++q) {
+                        ex[q] = ex[q + 1]; ey[q] = ey[q + 1];
+                        et[q] = et[q + 1]; em[q] = em[q + 1];
+                        eid[q] = eid[q + 1];
+                    }
+                    --n;
+                } else {
+                    const int idx = (int)pr[4];
+                    ex[idx] = pr[0]; ey[idx] = pr[1]; et[idx] = pr[2]; em[idx] = pr[3];
+                }
+            }
+            n = __builtin_amdgcn_readlane(n, 0);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+
+    for (int s = lane; s < n; s += 64) {
+        ev.x[base + s] = ex[s]; ev.y[base + s] = ey[s];
+        ev.t[base + s] = et[s]; ev.m[base + s] = em[s];
+        ev.id[base + s] = eid[s];
+    }
+    if (lane == 0) {
+        ev.cnt[r] = n;
+        for (int t = 0; t < 5; ++t) {
+            if (cnt_att[t]) atomicAdd(&stats[3 * t + 0], (unsigned long long)cnt_att[t]);
+            if (cnt_val[t]) atomicAdd(&stats[3 * t + 1], (unsigned long long)cnt_val[t]);
+            if (cnt_acc[t]) atomicAdd(&stats[3 * t + 2], (unsigned long long)cnt_acc[t]);
+        }
+        if (samp_read) atomicAdd(&stats[15], samp_read);
+        if (samp_written) atomicAdd(&stats[16], samp_written);
+        if (flags) atomicOr(err, flags);
+    }
+}
+
+// Every move's draw record for one sweep: per slot [region][move][8], from
+// Philox under the slot's key (or, for slot 0 in replay mode, copied from
+// the caller's feed, records of 8, or of 16 with learned births, whose draws
+// 8..15 go to the slot's L.raw for k_learned_births).  One thread per move
+// of every region of every slot (all slots take k moves per region).
+__global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
+                              long long nmoves, int k, const long long *__restrict__ sweep_ptr,
+                              const double *__restrict__ feed, long long feed_first, int width)
 {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const int chain = blockIdx.y;
-    const long long per = (long long)g.R * g.k;
-    if (q >= per) return;
+    if (q >= nmoves) return;
+    const unsigned item = items[q / k];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu), j = (int)(q % k);
+    const Slot &S = slots[slot];
     const long long sweep = *sweep_ptr;
-    const bool learned = L.tab != nullptr;
-    const int width = learned ? 16 : 8;
-    const int r = (int)(q / g.k);
+    const bool learned = S.L.tab != nullptr;
+    const long long mv = (long long)r * k + j;
     double d[16];
-    if (feed != nullptr && chain == 0) {
-        const double *row = feed + ((sweep - feed_first) * per + q) * width;
+    if (feed != nullptr && slot == 0) {
+        const double *row = feed + ((sweep - feed_first) * (long long)S.g.R * k + mv) * width;
         for (int c = 0; c < width; ++c) d[c] = row[c];
     } else if (learned) {
-        move_draws16(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)(q % g.k), d);
+        move_draws16(S.g.seed, S.chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
     } else {
-        move_draws(g.seed, (uint32_t)chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)(q % g.k), d);
+        move_draws(S.g.seed, S.chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
     }
-    double *out = draws + ((long long)chain * per + q) * 8;
+    double *out = S.draws + mv * 8;
     for (int c = 0; c < 8; ++c) out[c] = d[c];
     if (learned) {
-        double *raw = L.raw + ((long long)chain * per + q) * 8;
+        double *raw = S.L.raw + mv * 8;
         for (int c = 0; c < 8; ++c) raw[c] = d[8 + c];
     }
 }
 
-// Learned births of one sweep, one wave per (region, chain): each birth
+// Learned births of one sweep, one wave per (slot, region): each birth
 // move's proposal depends only on its draws and the sweep's partition, so
 // it is derived here, off the sweep's dependent chain of moves.  With
 // probability pl (regions holding a station) the anchor is picked by
@@ -766,13 +1064,20 @@ __global__ void k_sweep_draws(Geo g, const long long *__restrict__ sweep_ptr,
 // from the prior on the region.  Either way log(b / p_R) at the proposal,
 // summed over (station, window) pairs across the lanes, goes with it.
 __global__ void __launch_bounds__(64)
-k_learned_births(Geo g, const double *__restrict__ draws, const double *__restrict__ offs,
-                 Learned L, int *__restrict__ err)
+k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
+                 int *__restrict__ err)
 {
     __shared__ int s_sta[kMaxRegSta];
     __shared__ int s_ns;
     __shared__ double s_W;
-    const int r = blockIdx.x, chain = blockIdx.y, lane = threadIdx.x;
+    const unsigned item = items[blockIdx.x];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu), lane = threadIdx.x;
+    const Learned L = slots[slot].L;
+    if (L.tab == nullptr) return;
+    const Geo g = slots[slot].g;
+    const double *draws = slots[slot].draws;
+    const double *offs = slots[slot].ev[par].off;
+    const int chain = 0;
     const long long per = (long long)g.R * g.k;
     const int i = r % g.nrx, kk = r / g.nrx;
     const double offx = offs[2 * chain], offy = offs[2 * chain + 1];
@@ -866,15 +1171,17 @@ k_learned_births(Geo g, const double *__restrict__ draws, const double *__restri
 // rec[sweep - first][chain]: [0] the count, then (x, y, t, m) of the first
 // max_events of them.  One workgroup per chain.
 __global__ void __launch_bounds__(256)
-k_record(Geo g, Events ev, const long long *__restrict__ sweep_ptr, double *__restrict__ rec,
-         long long first, long long n, int max_events)
+k_record(const Slot *__restrict__ slots, int par, const long long *__restrict__ sweep_ptr,
+         double *__restrict__ rec, long long first, long long n, int max_events)
 {
     __shared__ int s_base[256];
     const long long sweep = *sweep_ptr;
     if (sweep < first || sweep >= first + n) return;
-    const int chain = blockIdx.x, tid = threadIdx.x;
+    const int slot = blockIdx.x, tid = threadIdx.x, chain = 0;
+    const Geo g = slots[slot].g;
+    const Events ev = slots[slot].ev[par];
     const long long stride = 1 + 4LL * max_events;
-    double *out = rec + ((sweep - first) * gridDim.x + chain) * stride;
+    double *out = rec + ((sweep - first) * gridDim.x + slot) * stride;
     int base = 0;
     // regions in chunks of 256: a block prefix sum of their counts places
     // each region's events
@@ -973,15 +1280,20 @@ __global__ void k_learned_reach(const double *__restrict__ part, int nblocks,
 // the events of the old layout that fall into it.  With both offsets in
 // [0, w) an event's region index moves by at most one per axis, so a 5x5
 // window of old regions is always enough.
-__global__ void k_rebin(Geo g, Events src, Events dst, const long long *__restrict__ sweep_ptr,
+__global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
+                        int nitems, int par, const long long *__restrict__ sweep_ptr,
                         int *__restrict__ err)
 {
-    const int chain = blockIdx.y;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= g.R) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nitems) return;
+    const unsigned item = items[q];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
+    const Geo g = slots[slot].g;
+    const Events src = slots[slot].ev[par], dst = slots[slot].ev[par ^ 1];
+    const int chain = 0;
     const long long sweep = *sweep_ptr;
     double offx, offy;
-    sweep_offset(g.seed, (uint32_t)chain, (uint32_t)sweep, g.wx, g.wy, &offx, &offy);
+    sweep_offset(g.seed, slots[slot].chain, (uint32_t)sweep, g.wx, g.wy, &offx, &offy);
     if (r == 0) {
         dst.off[2 * chain] = offx;
         dst.off[2 * chain + 1] = offy;
@@ -1232,63 +1544,63 @@ __global__ void k_advance_sweep(long long *p) { *p += 1; }
 
 // ------------------------------------------------------------- launchers
 template <typename TraceT>
-static hipError_t launch_sweep_t(const Geo &g, const Events &ev, const void *trace, double *E,
-                                 int color, const long long *sweep_ptr, const double *draws,
-                                 double *logp, long long log_first, long long log_n,
-                                 unsigned long long *stats, int *err, const Learned &L, int block,
-                                 int chains, hipStream_t s)
+static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
+                                 const long long *sweep_ptr, double *logp, long long log_first,
+                                 long long log_n, int *err, int block, hipStream_t s)
 {
-    const int p = g.period;
-    const int ci = color % p, ck = color / p;
-    const int ni = (g.nrx - ci + p - 1) / p, nk = (g.nry - ck + p - 1) / p;
-    const dim3 grid(ni * nk, chains);
-    const TraceT *tr = (const TraceT *)trace;
+    if (nitems <= 0) return hipSuccess;
     switch (block) {
+    case 64:  // one wave per work item, four per workgroup
+        k_sweep_wave<TraceT><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
+                                                              sweep_ptr, logp, log_first, log_n,
+                                                              err);
+        break;
     case 512:
-        k_sweep_color<TraceT, 512><<<grid, 512, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err, L);
+        k_sweep_color<TraceT, 512><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
+                                                          log_first, log_n, err);
         break;
     case 128:
-        k_sweep_color<TraceT, 128><<<grid, 128, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err, L);
+        k_sweep_color<TraceT, 128><<<nitems, 128, 0, s>>>(slots, items, par, sweep_ptr, logp,
+                                                          log_first, log_n, err);
         break;
     default:
-        k_sweep_color<TraceT, 256><<<grid, 256, 0, s>>>(g, ev, tr, E, color, sweep_ptr, draws,
-                                                         logp, log_first, log_n, stats, err, L);
+        k_sweep_color<TraceT, 256><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
+                                                          log_first, log_n, err);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
-                        int color, const long long *sweep_ptr, const double *draws, double *logp,
-                        long long log_first, long long log_n, unsigned long long *stats, int *err,
-                        const Learned &L, int block, int chains, hipStream_t s)
+hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
+                        const long long *sweep_ptr, double *logp, long long log_first,
+                        long long log_n, int *err, int block, hipStream_t s)
 {
     if (f64)
-        return launch_sweep_t<double>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
-                                      log_n, stats, err, L, block, chains, s);
-    return launch_sweep_t<float>(g, ev, trace, E, color, sweep_ptr, draws, logp, log_first,
-                                 log_n, stats, err, L, block, chains, s);
+        return launch_sweep_t<double>(slots, items, nitems, par, sweep_ptr, logp, log_first,
+                                      log_n, err, block, s);
+    return launch_sweep_t<float>(slots, items, nitems, par, sweep_ptr, logp, log_first, log_n,
+                                 err, block, s);
 }
 
-hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
-                              long long feed_first, double *draws, const double *offs,
-                              const Learned &L, int *err, int chains, hipStream_t s)
+hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
+                              int par, const long long *sweep_ptr, const double *feed,
+                              long long feed_first, int width, bool learned, int *err,
+                              hipStream_t s)
 {
-    const long long per = (long long)g.R * g.k;
-    const dim3 grid((unsigned)((per + 127) / 128), chains);
-    k_sweep_draws<<<grid, 128, 0, s>>>(g, sweep_ptr, feed, feed_first, draws, L);
+    const long long nmoves = (long long)nall * k;
+    k_sweep_draws<<<(unsigned)((nmoves + 127) / 128), 128, 0, s>>>(slots, items_all, nmoves, k,
+                                                                  sweep_ptr, feed, feed_first,
+                                                                  width);
     hipError_t e = hipGetLastError();
-    if (e || L.tab == nullptr) return e;
-    k_learned_births<<<dim3(g.R, chains), 64, 0, s>>>(g, draws, offs, L, err);
+    if (e || !learned) return e;
+    k_learned_births<<<nall, 64, 0, s>>>(slots, items_all, par, err);
     return hipGetLastError();
 }
 
-hipError_t launch_record(const Geo &g, const Events &ev, const long long *sweep_ptr, double *rec,
-                         long long first, long long n, int max_events, int chains, hipStream_t s)
+hipError_t launch_record(const Slot *slots, int nslots, int par, const long long *sweep_ptr,
+                         double *rec, long long first, long long n, int max_events, hipStream_t s)
 {
-    k_record<<<chains, 256, 0, s>>>(g, ev, sweep_ptr, rec, first, n, max_events);
+    k_record<<<nslots, 256, 0, s>>>(slots, par, sweep_ptr, rec, first, n, max_events);
     return hipGetLastError();
 }
 
@@ -1313,11 +1625,10 @@ hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int
     return hipGetLastError();
 }
 
-hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
-                        const long long *sweep_ptr, int *err, int chains, hipStream_t s)
+hipError_t launch_rebin(const Slot *slots, const unsigned *items_all, int nall, int par,
+                        const long long *sweep_ptr, int *err, hipStream_t s)
 {
-    const dim3 grid((g.R + 127) / 128, chains);
-    k_rebin<<<grid, 128, 0, s>>>(g, src, dst, sweep_ptr, err);
+    k_rebin<<<(nall + 127) / 128, 128, 0, s>>>(slots, items_all, nall, par, sweep_ptr, err);
     return hipGetLastError();
 }
 

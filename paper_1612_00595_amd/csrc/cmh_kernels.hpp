@@ -5,21 +5,21 @@
 
 namespace cmh {
 
-hipError_t launch_sweep(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
-                        int color, const long long *sweep_ptr, const double *draws, double *logp,
-                        long long log_first, long long log_n, unsigned long long *stats, int *err,
-                        const Learned &L, int block, int chains, hipStream_t s);
-hipError_t launch_sweep_draws(const Geo &g, const long long *sweep_ptr, const double *feed,
-                              long long feed_first, double *draws, const double *offs,
-                              const Learned &L, int *err, int chains, hipStream_t s);
-hipError_t launch_record(const Geo &g, const Events &ev, const long long *sweep_ptr, double *rec,
-                         long long first, long long n, int max_events, int chains, hipStream_t s);
+hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
+                        const long long *sweep_ptr, double *logp, long long log_first,
+                        long long log_n, int *err, int block, hipStream_t s);
+hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
+                              int par, const long long *sweep_ptr, const double *feed,
+                              long long feed_first, int width, bool learned, int *err,
+                              hipStream_t s);
+hipError_t launch_record(const Slot *slots, int nslots, int par, const long long *sweep_ptr,
+                         double *rec, long long first, long long n, int max_events, hipStream_t s);
 int learned_norm_blocks(long long ncomp);
 hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int nsta, double lz3,
                                double *cum, double *norm, double *part, double *reach,
                                hipStream_t s);
-hipError_t launch_rebin(const Geo &g, const Events &src, const Events &dst,
-                        const long long *sweep_ptr, int *err, int chains, hipStream_t s);
+hipError_t launch_rebin(const Slot *slots, const unsigned *items_all, int nall, int par,
+                        const long long *sweep_ptr, int *err, hipStream_t s);
 int refresh_blocks(const Geo &g);
 hipError_t launch_refresh(const Geo &g, const Events &ev, const void *trace, int f64, double *E,
                           int write, double *partials, double *out, int chain0, int nchains,

@@ -132,6 +132,27 @@ CHAINS32 = Workload(
 WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32)}
 
 
+def uneven_batch(count: int = 256, seed: int = 1000) -> list:
+    """Instances of uneven size served together (seeds seed .. seed + count -
+    1): station grid side n uniform on 8..32 (n x n stations, n x n dynamic
+    regions of one spacing), samples 64 * round(U[4000, 36000] / 64), fp32
+    traces.  The Poisson mean is the instance's station count times a
+    log-uniform density of 100/64 .. 5000/1024 events per station, so that it
+    spans 100 (8 x 8) to 5000 (32 x 32) while every region keeps about the
+    same number of events."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for q in range(count):
+        n = int(rng.integers(8, 33))
+        N = 64 * int(round(rng.uniform(4000, 36000) / 64))
+        rho = (100 / 64) * ((5000 / 1024) / (100 / 64)) ** rng.uniform()
+        lam = float(round(rho * n * n))
+        out.append(Workload(name=f"u{q}-s{n}x{n}-n{N}", model=ModelSpec(nsx=n, nsy=n, N=N, lam=lam),
+                            sampler=SamplerSpec(gx=n, gy=n, dynamic=1), trace_dtype="f32",
+                            seed=seed + q))
+    return out
+
+
 def scaled(w: Workload, *, side: int, N: int, lam: float, name: str | None = None,
            **sampler_kw) -> Workload:
     """Same physics on a smaller station grid (used by tests)."""

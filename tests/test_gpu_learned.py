@@ -83,7 +83,7 @@ def _learned_replay(w, nsw, block, table_seed, feed_seed=55, p_learned=0.5):
     return acc, births
 
 
-@pytest.mark.parametrize("block", [128, 256])
+@pytest.mark.parametrize("block", [64, 128, 256])
 def test_learned_replay_parity_small_static(block):
     say("learned replay", W.SMALL.name, "block", block)
     acc, births = _learned_replay(W.SMALL, 12, block, table_seed=11)

@@ -99,7 +99,7 @@ def _replay(w, nsw, block, feed_seed=77, compare_each_phase=True):
     return gpu, ref, m, s, acc
 
 
-@pytest.mark.parametrize("block", [128, 256, 512])
+@pytest.mark.parametrize("block", [64, 128, 256, 512])
 def test_replay_parity_small_static(block):
     say("replay", W.SMALL.name, "block", block)
     gpu, ref, m, s, acc = _replay(W.SMALL, 12, block)
@@ -111,10 +111,11 @@ def test_replay_parity_small_static(block):
     say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties, "max rel", acc.max_rel)
 
 
-def test_replay_parity_dynamic():
+@pytest.mark.parametrize("block", [64, 256])
+def test_replay_parity_dynamic(block):
     w = dynamic_small()
-    say("replay", w.name)
-    gpu, ref, m, s, acc = _replay(w, 8, 256)
+    say("replay", w.name, "block", block)
+    gpu, ref, m, s, acc = _replay(w, 8, block)
     assert acc.evaluated > 5000
     assert _variance_close(gpu.read_variance(0), O.event_variance(m, ref.events()))
 
@@ -140,7 +141,7 @@ def test_replay_parity_full_size_large():
     fd = torch.from_numpy(feed).to(DEV)
     rows = np.random.default_rng(1).choice(w.model.nsta, 48, replace=False)
     Er = {int(j): O.event_variance_rows(m, rev, int(j), 1)[0] for j in rows}
-    for block in (128, 256, 512):
+    for block in (64, 128, 256, 512):
         say("gpu sweep block", block)
         gpu = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3, block=block)
         gpu.set_feed(fd, 0)
