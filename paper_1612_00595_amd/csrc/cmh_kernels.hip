@@ -836,7 +836,7 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg, 
 }
 
 template <typename TraceT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
              long long log_first, long long log_n, int *__restrict__ err)
@@ -871,17 +871,28 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     double *__restrict__ E = slots[slot].E;
     const double *__restrict__ draws = slots[slot].draws;
     unsigned long long *__restrict__ stats = slots[slot].stats;
-    const Learned L = slots[slot].L;
+    __shared__ Learned s_L[4];
+    if (lane == 0) s_L[wv] = slots[slot].L;
+    __builtin_amdgcn_wave_barrier();
+    const Learned &L = s_L[wv];
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
-    const double offx = ev.off[0], offy = ev.off[1];
-    double x0, x1, y0, y1;
-    region_span(offx, g.wx, g.Lx, i, &x0, &x1);
-    region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
-    const double area = (x1 - x0) * (y1 - y0);
+    __shared__ double s_rc[4][10];
+    if (lane == 0) {
+        double *c = s_rc[wv];
+        c[0] = ev.off[0]; c[1] = ev.off[1];
+        region_span(c[0], g.wx, g.Lx, i, &c[2], &c[3]);
+        region_span(c[1], g.wy, g.Ly, kk, &c[4], &c[5]);
+        c[6] = (c[3] - c[2]) * (c[5] - c[4]);
+        c[7] = log(g.lambda * c[6] / (g.Lx * g.Ly));
+        c[8] = log(g.pb); c[9] = log(g.pd);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double *rc_ = s_rc[wv];
+    const double &offx = rc_[0], &offy = rc_[1], &x0 = rc_[2], &x1 = rc_[3], &y0 = rc_[4],
+                 &y1 = rc_[5], &area = rc_[6], &log_lamR = rc_[7], &log_pb = rc_[8],
+                 &log_pd = rc_[9];
     if (!(area > 0.0)) return;
-    const double lamR = g.lambda * area / (g.Lx * g.Ly);
-    const double log_lamR = log(lamR), log_pb = log(g.pb), log_pd = log(g.pd);
 
     double *sT = s_T[wv];
     double *ex = s_ex[wv], *ey = s_ey[wv], *et = s_et[wv], *em = s_em[wv];
@@ -918,9 +929,12 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     const double *lsrc = L.tab != nullptr ? L.birth + (long long)r * g.k * 4 : nullptr;
     const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
-    unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
-                 cnt_acc[5] = {0, 0, 0, 0, 0};
-    unsigned long long samp_read = 0, samp_written = 0;
+    // move counters of this wave (lane 0 counts): [3 t + 0..2], then the
+    // footprint samples read and written
+    __shared__ unsigned long long s_cnt[4][kStats];
+    unsigned long long *cnt = s_cnt[wv];
+    if (lane < kStats) cnt[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
 
     for (int j = 0; j < g.k; ++j) {
         const int jw = j % kWaveDraws;
@@ -960,10 +974,10 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         if (lane == 0) {
             flags |= h.flags;
-            cnt_att[h.type]++;
+            cnt[3 * h.type]++;
             if (h.valid) {
-                cnt_val[h.type]++;
-                samp_read += (unsigned long long)h.S;
+                cnt[3 * h.type + 1]++;
+                cnt[15] += (unsigned long long)h.S;
             }
             if (use_log) {
                 double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
@@ -976,8 +990,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         if (accept) {
             if (!g.prior_only) wave_write(g, E, s_seg[wv][0], h.nseg, h.S, sT, lane);
             if (lane == 0) {
-                cnt_acc[h.type]++;
-                samp_written += (unsigned long long)h.S;
+                cnt[3 * h.type + 2]++;
+                cnt[16] += (unsigned long long)h.S;
                 const double *pr = s_prop[wv][0];
                 if (h.type == 0) {
                     ex[n] = pr[0]; ey[n] = pr[1]; et[n] = pr[2]; em[n] = pr[3];
@@ -1009,13 +1023,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     }
     if (lane == 0) {
         ev.cnt[r] = n;
-        for (int t = 0; t < 5; ++t) {
-            if (cnt_att[t]) atomicAdd(&stats[3 * t + 0], (unsigned long long)cnt_att[t]);
-            if (cnt_val[t]) atomicAdd(&stats[3 * t + 1], (unsigned long long)cnt_val[t]);
-            if (cnt_acc[t]) atomicAdd(&stats[3 * t + 2], (unsigned long long)cnt_acc[t]);
-        }
-        if (samp_read) atomicAdd(&stats[15], samp_read);
-        if (samp_written) atomicAdd(&stats[16], samp_written);
+        for (int t = 0; t < kStats; ++t)
+            if (cnt[t]) atomicAdd(&stats[t], cnt[t]);
         if (flags) atomicOr(err, flags);
     }
 }
