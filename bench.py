@@ -38,8 +38,10 @@ def parse():
     ap.add_argument("--profile-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with rocprofv3 FETCH_SIZE/WRITE_SIZE per sweep-kernel launch")
+    ap.add_argument("--traffic", default=os.path.join(
+                        ROOT, "profiles", "k_sweep_color-s64x64-n144000-dyn64x64-f32.traffic.json"),
+                    help="JSON with rocprofv3 FETCH_SIZE/WRITE_SIZE bytes per sweep-kernel launch; "
+                         "used only while the kernel source hash it records is current")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 32-chain workload measured next to the main one")
     ap.add_argument("--no-uneven", action="store_true",
@@ -329,8 +331,12 @@ def main():
     avg_ms, bytes_per_launch, achieved = res["avg_ms"], res["bytes_per_launch"], res["achieved"]
     log(f"[bench] {args.steps} sweeps in {el * 1e3:.1f} ms: {value:.4g} proposals/s")
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    if args.traffic and os.path.exists(args.traffic) and w is W.LARGE and smp.block == 256:
+        import hashlib
+        t = json.load(open(args.traffic))
+        src = os.path.join(ROOT, "paper_1612_00595_amd", "csrc", "cmh_kernels.hip")
+        if t.get("source_sha256") == hashlib.sha256(open(src, "rb").read()).hexdigest():
+            traffic = t.get("bytes_per_launch")
     log(f"[bench] sweep kernel: {avg_ms * 1e3:.1f} us/launch, "
         f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s")
 

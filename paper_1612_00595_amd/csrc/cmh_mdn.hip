@@ -492,12 +492,13 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
     return hipGetLastError();
 }
 
-// Bias gradient db[N] = column sums of D[Mb][N], split like weight_grad.
+// Bias gradient db[N] = column sums of D[Mb][N]: partial sums over chunks of
+// kMdnColRows rows (many workgroups), then summed in a fixed order.
 static hipError_t bias_grad(int Mb, int N, const __bf16 *D, int ldd, float *db, float *part,
                             hipStream_t s)
 {
-    int per = 0;
-    const int nz = mdn_splits(Mb, &per);
+    const int per = kMdnColRows;
+    const int nz = (Mb + per - 1) / per;
     k_col_partial<<<dim3((N + 63) / 64, nz), 256, 0, s>>>(Mb, N, D, ldd, per, part);
     hipError_t e = hipGetLastError();
     if (e) return e;
