@@ -334,8 +334,10 @@ def main():
     if args.traffic and os.path.exists(args.traffic) and w is W.LARGE and smp.block == 256:
         import hashlib
         t = json.load(open(args.traffic))
-        src = os.path.join(ROOT, "paper_1612_00595_amd", "csrc", "cmh_kernels.hip")
-        if t.get("source_sha256") == hashlib.sha256(open(src, "rb").read()).hexdigest():
+        srcs = [os.path.join(ROOT, "paper_1612_00595_amd", "csrc", f)
+                for f in ("cmh_kernels.hip", "cmh_common.hpp")]
+        digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
+        if t.get("source_sha256") == digest:
             traffic = t.get("bytes_per_launch")
     log(f"[bench] sweep kernel: {avg_ms * 1e3:.1f} us/launch, "
         f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s")
