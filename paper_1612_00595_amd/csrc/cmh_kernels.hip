@@ -1063,33 +1063,39 @@ __global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__
     }
 }
 
-// Learned births of one sweep, one wave per (slot, region): each birth
-// move's proposal depends only on its draws and the sweep's partition, so
-// it is derived here, off the sweep's dependent chain of moves.  With
-// probability pl (regions holding a station) the anchor is picked by
-// u_anchor W_R against the running weight sums (stations ascending, then
-// windows), the component by u_comp against the cumulative mixture weights,
-// and (x, y, t) = mean + sd * (truncated normals); otherwise (x, y, t) come
-// from the prior on the region.  Either way log(b / p_R) at the proposal,
-// summed over (station, window) pairs across the lanes, goes with it.
+// Learned births of one sweep, one wave per move of every (slot, region):
+// each birth move's proposal depends only on its draws and the sweep's
+// partition, so it is derived here, off the sweep's dependent chain of
+// moves.  With probability pl (regions holding a station) the anchor is
+// picked by u_anchor W_R against the running weight sums (stations
+// ascending, then windows), the component by u_comp against the cumulative
+// mixture weights, and (x, y, t) = mean + sd * (truncated normals);
+// otherwise (x, y, t) come from the prior on the region.  Either way
+// log(b / p_R) at the proposal, summed over (station, window) pairs across
+// the lanes, goes with it.
 __global__ void __launch_bounds__(64)
-k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
-                 int *__restrict__ err)
+k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int k,
+                 int par, int *__restrict__ err)
 {
     __shared__ int s_sta[kMaxRegSta];
     __shared__ int s_ns;
     __shared__ double s_W;
-    const unsigned item = items[blockIdx.x];
+    const unsigned item = items[blockIdx.x / k];
+    const int j = (int)(blockIdx.x % k);
     const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu), lane = threadIdx.x;
-    const Learned L = slots[slot].L;
+    const Learned &L = slots[slot].L;
     if (L.tab == nullptr) return;
-    const Geo g = slots[slot].g;
-    const double *draws = slots[slot].draws;
+    const long long q = (long long)r * k + j;
+    const double *d = slots[slot].draws + q * 8;
+    double *lb = L.birth + q * 4;
+    if (!(d[0] < slots[slot].g.c1)) {  // not a birth
+        if (lane < 4) lb[lane] = 0.0;
+        return;
+    }
+    const Geo &g = slots[slot].g;
     const double *offs = slots[slot].ev[par].off;
-    const int chain = 0;
-    const long long per = (long long)g.R * g.k;
     const int i = r % g.nrx, kk = r / g.nrx;
-    const double offx = offs[2 * chain], offy = offs[2 * chain + 1];
+    const double offx = offs[0], offy = offs[1];
     double x0, x1, y0, y1;
     region_span(offx, g.wx, g.Lx, i, &x0, &x1);
     region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
@@ -1108,70 +1114,61 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
     const int ns = s_ns;
     const double W = s_W, pl = ns > 0 ? L.pl : 0.0;
     const double area = (x1 - x0) * (y1 - y0);
-    for (int j = 0; j < g.k; ++j) {
-        const long long q = (long long)chain * per + (long long)r * g.k + j;
-        const double *d = draws + q * 8;
-        double *lb = L.birth + q * 4;
-        if (!(d[0] < g.c1)) {
-            if (lane < 4) lb[lane] = 0.0;
-            continue;
-        }
-        const double *e = L.raw + q * 8;  // draws 8..15
-        double x, y, t;
-        if (pl > 0.0 && e[0] < pl) {
-            // lane 0 walks the running sums; the choice is broadcast
-            double px = 0.0, py = 0.0, pt = 0.0;
-            if (lane == 0) {
-                const double target = e[1] * W;
-                double acc = 0.0, rem = 0.0;
-                int pick = -1;
-                for (int s = 0; s < ns; ++s) {
-                    const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
-                    if (target < nxt) {
-                        pick = s_sta[s];
-                        rem = target - acc;
-                        break;
-                    }
-                    acc = nxt;
-                }
-                if (pick < 0) {
-                    pick = s_sta[ns - 1];
-                    rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
-                }
-                // smallest window with rem < cum (the last one if none)
-                const double *cum = L.cum + (long long)pick * L.ntau;
-                int lo = 0, hi = L.ntau - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (rem < cum[mid]) hi = mid;
-                    else lo = mid + 1;
-                }
-                const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
-                int k = 7;
-                for (int c = 0; c < 8; ++c)
-                    if (e[2] < T[8 * c + 7]) { k = c; break; }
-                px = T[8 * k + 0] + T[8 * k + 3] * e[3];
-                py = T[8 * k + 1] + T[8 * k + 4] * e[4];
-                pt = T[8 * k + 2] + T[8 * k + 5] * e[5];
-            }
-            x = lane_f64(px, 0);
-            y = lane_f64(py, 0);
-            t = lane_f64(pt, 0);
-        } else {
-            x = x0 + d[1] * (x1 - x0);
-            y = y0 + d[2] * (y1 - y0);
-            t = d[3] * (double)g.N;
-        }
-        double lr = 0.0;
-        if (pl > 0.0) {
-            int ilo, ihi;
-            learned_windows(L, t, &ilo, &ihi);
-            const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, x, y, t, lane, 64));
-            lr = learned_log_ratio(pl, S, W, area, g.N);
-        }
+    const double *e = L.raw + q * 8;  // draws 8..15
+    double x, y, t;
+    if (pl > 0.0 && e[0] < pl) {
+        // lane 0 walks the running sums; the choice is broadcast
+        double px = 0.0, py = 0.0, pt = 0.0;
         if (lane == 0) {
-            lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
+            const double target = e[1] * W;
+            double acc = 0.0, rem = 0.0;
+            int pick = -1;
+            for (int s = 0; s < ns; ++s) {
+                const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
+                if (target < nxt) {
+                    pick = s_sta[s];
+                    rem = target - acc;
+                    break;
+                }
+                acc = nxt;
+            }
+            if (pick < 0) {
+                pick = s_sta[ns - 1];
+                rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
+            }
+            // smallest window with rem < cum (the last one if none)
+            const double *cum = L.cum + (long long)pick * L.ntau;
+            int lo = 0, hi = L.ntau - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rem < cum[mid]) hi = mid;
+                else lo = mid + 1;
+            }
+            const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
+            int c = 7;
+            for (int u = 0; u < 8; ++u)
+                if (e[2] < T[8 * u + 7]) { c = u; break; }
+            px = T[8 * c + 0] + T[8 * c + 3] * e[3];
+            py = T[8 * c + 1] + T[8 * c + 4] * e[4];
+            pt = T[8 * c + 2] + T[8 * c + 5] * e[5];
         }
+        x = lane_f64(px, 0);
+        y = lane_f64(py, 0);
+        t = lane_f64(pt, 0);
+    } else {
+        x = x0 + d[1] * (x1 - x0);
+        y = y0 + d[2] * (y1 - y0);
+        t = d[3] * (double)g.N;
+    }
+    double lr = 0.0;
+    if (pl > 0.0) {
+        int ilo, ihi;
+        learned_windows(L, t, &ilo, &ihi);
+        const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, x, y, t, lane, 64));
+        lr = learned_log_ratio(pl, S, W, area, g.N);
+    }
+    if (lane == 0) {
+        lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
     }
 }
 
@@ -1602,7 +1599,7 @@ hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int 
                                                                   width);
     hipError_t e = hipGetLastError();
     if (e || !learned) return e;
-    k_learned_births<<<nall, 64, 0, s>>>(slots, items_all, par, err);
+    k_learned_births<<<(unsigned)nmoves, 64, 0, s>>>(slots, items_all, k, par, err);
     return hipGetLastError();
 }
 
