@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--uneven-steps", type=int, default=10)
     ap.add_argument("--uneven-block", type=int, default=64,
                     help="sweep kernel form for the uneven batch (64: one wave per region)")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the per-kernel rates (refresh, simulator, features, network)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain study on the 5x5-station worlds")
     ap.add_argument("--learned-worlds", type=int, default=8)
@@ -262,6 +264,66 @@ def uneven_study(args, dev, block: int):
     return out
 
 
+def kernel_rates(dev):
+    """The other rows of the path, each against its own roofline, on the
+    32x32-station, 36000-sample instance: the forward simulator, the exact
+    refresh (variance and log-likelihood), the anchor features of every
+    window, the network's forward pass over them and the mixture table.
+    Durations from HIP events on the stream the library launches on."""
+    import torch
+
+    from paper_1612_00595_amd import chromh, workloads as W
+    w = W.CHAINS32
+    m = w.model
+    samples = m.nsta * m.N
+    tr = W.truth_events(m, w.seed)
+    truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3, out
+
+    out = {"workload": w.name.replace("-c32", "") + " (one chain)"}
+    t, trace = timed(lambda: chromh.simulate(m, truth, 1000 + w.seed, "f32", dev), 2)
+    out["simulate"] = {"seconds": t, "GBps_written": samples * 4 / t / 1e9,
+                       "bound": "fp64 alu (Philox, Box-Muller per sample)"}
+    smp = chromh.ChromaticSampler(m, w.sampler, trace, chains=1, seed=w.seed, block=64)
+    smp.run_sweeps(0, 20)
+    t, _ = timed(lambda: smp.refresh(write_variance=True, loglik=True))
+    out["refresh"] = {"seconds": t, "GBps": samples * 12 / t / 1e9,
+                      "frac": samples * 12 / t / 1e9 / HBM_PEAK_GBS,
+                      "bytes_per_sample": 12, "bound": "hbm (4 B trace read, 8 B variance written)"}
+    smp.close()
+    na, ntau = chromh.anchor_count(m)
+    t, (X, wts) = timed(lambda: chromh.anchor_features(m, trace), 2)
+    out["anchor_features"] = {"anchors": na, "seconds": t, "anchors_per_s": na / t,
+                              "GBps_written": na * (576 * 2 + 8) / t / 1e9}
+    net = chromh.MDN(seed=1)
+    chunk = 1 << 18
+
+    def forward_all():
+        return torch.cat([net.forward(X[q:q + chunk]) for q in range(0, na, chunk)])
+
+    t, head = timed(forward_all, 2)
+    out["mdn_forward"] = {"rows": na, "seconds": t, "TFLOPs": na * MDN_FWD_FLOP / t / 1e12,
+                          "mfma_frac": na * MDN_FWD_FLOP / t / 1e12 / BF16_PEAK_TFLOPS,
+                          "bound": "mfma (bf16, fp32 accumulate)"}
+    t, _ = timed(lambda: chromh.mixture_table(m, head), 2)
+    out["mixture_table"] = {"rows": na, "seconds": t, "rows_per_s": na / t}
+    log(f"[bench] kernels: refresh {out['refresh']['GBps']:.0f} GB/s, simulate "
+        f"{out['simulate']['GBps_written']:.0f} GB/s written, features {na / out['anchor_features']['seconds']:.3g} "
+        f"anchors/s, network forward {out['mdn_forward']['TFLOPs']:.1f} TFLOP/s")
+    del X, wts, head, trace, net
+    return out
+
+
 def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
     """Proposals/s over `steps` graph-replayed sweeps after `warmup`, and the
     sweep kernel's HIP-event-timed launch duration and algorithmic bytes."""
@@ -342,6 +404,21 @@ def main():
     log(f"[bench] sweep kernel: {avg_ms * 1e3:.1f} us/launch, "
         f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s")
 
+    # the exact refresh (variance written, log-likelihood summed) on the same
+    # full-size instance: 12 B per sample streamed
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    smp.refresh(write_variance=True, loglik=True)
+    torch.cuda.synchronize()
+    e0.record()
+    smp.refresh(write_variance=True, loglik=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_ref = e0.elapsed_time(e1) * 1e-3
+    refresh_large = {"workload": w.name, "seconds": t_ref,
+                     "GBps": w.model.nsta * w.model.N * 12 / t_ref / 1e9,
+                     "frac": w.model.nsta * w.model.N * 12 / t_ref / 1e9 / HBM_PEAK_GBS,
+                     "bytes_per_sample": 12, "bound": "hbm"}
+    log(f"[bench] refresh on {w.name}: {refresh_large['GBps']:.0f} GB/s")
     nev = len(smp.read_events(0))
     out = {
         "metric": METRIC,
@@ -408,6 +485,10 @@ def main():
         }
         sb.close()
         del traceb
+        torch.cuda.empty_cache()
+    if not args.no_kernels:
+        out["kernels"] = kernel_rates(dev)
+        out["kernels"]["refresh_full_size"] = refresh_large
         torch.cuda.empty_cache()
     if not args.no_uneven:
         out["uneven"] = uneven_study(args, dev, args.uneven_block)

@@ -16,7 +16,8 @@ constexpr int kMaxSeg = 32;          // footprint segments per move
 constexpr int kMaxTs = 128;          // signal duration, samples
 constexpr int kMaxFootprint = 2048;  // samples touched by one move (16 * kMaxTs)
 constexpr int kDrawChunk = 64;       // moves whose draws are staged at once
-constexpr int kTile = 2048;          // samples per workgroup in streaming kernels
+constexpr int kTile = 8192;          // samples per workgroup in streaming kernels
+constexpr int kRefreshU = 8;         // samples per thread per step of a streaming loop
 constexpr int kMaxTileEvents = 640;  // events reaching one station tile
 constexpr int kMaxRegSta = 16;       // stations of one region, learned births
 

@@ -1343,58 +1343,76 @@ __global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restri
 }
 
 // ------------------------------------------------------- refresh / loglik
-// Gathers, for one station and one tile of kTile samples, every event of the
-// table that reaches the station with a window meeting the tile (regions in
-// index order, slots in id order), into LDS as (first sample, scale).
+// Gathers, for one station and one tile of samples [n_lo, n_hi), every event
+// of the table that reaches the station with a window meeting the tile, into
+// LDS as (first sample, scale), in table order (regions in index order, each
+// region's slots in id order).  The events of the few regions around the
+// station are flattened and their arrivals computed by the whole
+// workgroup; a block-wide prefix of ballots keeps the table order.
 __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int n_lo, int n_hi,
                            int *s_n0, double *s_B, int *s_cnt, int *flags)
 {
-    const int tid = threadIdx.x, lane = tid & 63;
-    if (tid == 0) *s_cnt = 0;
-    __syncthreads();
-    if (tid < 64) {
-        const int ix = j % g.nsx, iy = j / g.nsx;
+    __shared__ int s_roff[26];     // flat offsets of the regions around (at most 5 x 5)
+    __shared__ int s_rid[25];
+    __shared__ int s_wcnt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ix = j % g.nsx, iy = j / g.nsx;
+    if (tid == 0) {
         const double sx = station_pos(ix, g.ds), sy = station_pos(iy, g.ds);
         const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
         const int i0 = region_axis(sx - g.rc, offx, g.wx, g.gx);
         const int i1 = region_axis(sx + g.rc, offx, g.wx, g.gx);
         const int k0 = region_axis(sy - g.rc, offy, g.wy, g.gy);
         const int k1 = region_axis(sy + g.rc, offy, g.wy, g.gy);
-        int count = 0;
-        for (int kk = k0; kk <= k1; ++kk) {
+        int nr = 0, off = 0;
+        for (int kk = k0; kk <= k1; ++kk)
             for (int ii = i0; ii <= i1; ++ii) {
-                const int r = kk * g.nrx + ii;
-                const int nr = ev.cnt[chain * g.R + r];
-                const long long base = ((long long)chain * g.R + r) * g.cap;
-                for (int s0 = 0; s0 < nr; s0 += 64) {
-                    const int s = s0 + lane;
-                    bool take = false;
-                    Arrival ar;
-                    ar.in = 0;
-                    if (s < nr) {
-                        ar = arrive(g, ev.x[base + s], ev.y[base + s], ev.t[base + s],
-                                    ev.m[base + s], ix, iy);
-                        take = ar.in && ar.n0 < n_hi && ar.n1 > n_lo;
-                    }
-                    const unsigned long long mask = __ballot(take);
-                    const int before = __popcll(mask & ((1ull << lane) - 1ull));
-                    if (take) {
-                        const int pos = count + before;
-                        if (pos < kMaxTileEvents) {
-                            s_n0[pos] = ar.n0;
-                            s_B[pos] = ar.B;
-                        } else {
-                            *flags |= kFlagTile;
-                        }
-                    }
-                    count += __popcll(mask);
+                if (nr < 25) {
+                    const int r = kk * g.nrx + ii;
+                    s_rid[nr] = r;
+                    s_roff[nr] = off;
+                    off += ev.cnt[chain * g.R + r];
+                    ++nr;
+                } else {
+                    *flags |= kFlagTile;
                 }
             }
-        }
-        if (lane == 0) *s_cnt = count < kMaxTileEvents ? count : kMaxTileEvents;
+        for (int q = nr; q < 26; ++q) s_roff[q] = off;
+        *s_cnt = 0;
     }
     __syncthreads();
-    return *s_cnt;
+    const int total = s_roff[25];
+    int count = 0;
+    for (int base = 0; base < total; base += 256) {
+        const int f = base + tid;
+        bool take = false;
+        Arrival ar;
+        ar.in = 0; ar.n0 = 0; ar.n1 = 0; ar.B = 0.0;
+        if (f < total) {
+            int q = 0;
+            while (q < 24 && s_roff[q + 1] <= f) ++q;
+            const long long e = ((long long)chain * g.R + s_rid[q]) * g.cap + (f - s_roff[q]);
+            ar = arrive(g, ev.x[e], ev.y[e], ev.t[e], ev.m[e], ix, iy);
+            take = ar.in && ar.n0 < n_hi && ar.n1 > n_lo;
+        }
+        const unsigned long long mask = __ballot(take);
+        if (lane == 0) s_wcnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = __popcll(mask & ((1ull << lane) - 1ull));
+        for (int w = 0; w < wave; ++w) before += s_wcnt[w];
+        if (take) {
+            const int pos = count + before;
+            if (pos < kMaxTileEvents) {
+                s_n0[pos] = ar.n0;
+                s_B[pos] = ar.B;
+            } else {
+                *flags |= kFlagTile;
+            }
+        }
+        count += (s_wcnt[0] + s_wcnt[1]) + (s_wcnt[2] + s_wcnt[3]);
+        __syncthreads();
+    }
+    return count < kMaxTileEvents ? count : kMaxTileEvents;
 }
 
 // Exact event variance for every chain, station and sample, optionally
@@ -1425,21 +1443,34 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
     const long long row = (long long)j * g.N;
     double *Erow = E + (long long)chain * g.nsta * (long long)g.N + row;
     double acc = 0.0;
-    for (int nn = n_lo + tid; nn < n_hi; nn += 256) {
-        double e = 0.0;
-        for (int q = 0; q < ne; ++q) {
-            const int d = nn - s_n0[q];
-            if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+    // kRefreshU samples per thread per step, every trace load in flight
+    // before any is used
+    constexpr int U = kRefreshU;
+    for (int base = n_lo + tid; base < n_hi; base += 256 * U) {
+        double sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int nn = base + 256 * u;
+            sv[u] = nn < n_hi ? (double)trace[row + nn] : 0.0;
         }
-        const double sv = (double)trace[row + nn];
-        const double qv = sv * sv;
-        if (e > 0.0) {
-            const double v = g.sigma2 + e;
-            acc += -0.5 * (l2pi + log(v) + qv / v);
-        } else {
-            acc += null_c + null_q * qv;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int nn = base + 256 * u;
+            if (nn >= n_hi) break;
+            double e = 0.0;
+            for (int q = 0; q < ne; ++q) {
+                const int d = nn - s_n0[q];
+                if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+            }
+            const double qv = sv[u] * sv[u];
+            if (e > 0.0) {
+                const double v = g.sigma2 + e;
+                acc += -0.5 * (l2pi + log(v) + qv / v);
+            } else {
+                acc += null_c + null_q * qv;
+            }
+            if (write) Erow[nn] = e;
         }
-        if (write) Erow[nn] = e;
     }
     acc = wave_sum(acc);
     if ((tid & 63) == 0) s_part[tid >> 6] = acc;
