@@ -36,81 +36,125 @@ __device__ inline float gelu_grad_f(float z)
 
 // -------------------------------------------------------------------- GEMM
 // C[M][N] = sum_k op(A)[m][k] op(B)[k][n].  op(A)[m][k] = TA ? A[k*lda + m]
-// : A[m*lda + k]; op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  64x64 tile
-// per workgroup, four waves of 32x32, k-steps of 32 staged through LDS.
-// Vector loads need the contiguous extents (M for TA, K otherwise, and N
-// for !TB) and the leading dimensions to be multiples of 8 elements.
+// : A[m*lda + k]; op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  A
+// workgroup of four waves (2 x 2) computes a (2 WM) x (2 WN) tile, each wave
+// WM x WN as (WM/16) x (WN/16) MFMA 16x16x32 BF16 tiles with FP32
+// accumulators.  k-steps of 32 go through double-buffered LDS: the next
+// step's global loads are in flight while the current step's MFMAs run, one
+// barrier per step.  Loads are 16 bytes per lane along the operand's
+// contiguous dimension, so the contiguous extents (M for TA, K otherwise,
+// and N for !TB) and the leading dimensions must be multiples of 8.
 // EPI 0: C (fp32).  EPI 1: Z = C + bias (fp32) and GELU(Z) as BF16 into Cb.
 // EPI 2: C + bias (fp32).  Split K: workgroup z sums k in [z kper, (z + 1)
 // kper) and writes its partial product to C + z M ldc (EPI 0 only).
-template <bool TA, bool TB, int EPI>
+template <bool TA, bool TB, int EPI, int WM, int WN>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
        int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
        __bf16 *__restrict__ Cb, int ldcb, int kper)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sA[64][40];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[64][40];
+    constexpr int TMR = 2 * WM, TNC = 2 * WN;       // workgroup tile
+    constexpr int NVA = WM / 32, NVB = WN / 32;     // 16-byte loads per lane per step
+    constexpr int FA = WM / 16, FB = WN / 16;       // MFMA tiles per wave
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][TMR][40];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][TNC][40];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-    f32x4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int i0 = blockIdx.y * TMR, j0 = blockIdx.x * TNC;
+    const int wi = (wave >> 1) * WM, wj = (wave & 1) * WN;
+    f32x4 acc[FA][FB];
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const __bf16 zero = (__bf16)0.0f;
     const int kbeg = blockIdx.z * kper;
     const int kend = min(K, kbeg + kper);
     C += (long)blockIdx.z * M * ldc;
-    for (int k0 = kbeg; k0 < kend; k0 += 32) {
-        // one 16-byte load per thread and operand: 8 consecutive elements
-        // along the operand's contiguous dimension
-        {
-            bf16x8 v = {zero, zero, zero, zero, zero, zero, zero, zero};
+
+    bf16x8 ra[NVA], rb[NVB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NVA; ++u) {
+            const int v = tid + 256 * u;
+            ra[u] = (bf16x8){zero, zero, zero, zero, zero, zero, zero, zero};
             if (TA) {  // A[k][m]: 8 m's at one k
-                const int kq = tid >> 3, m8 = 8 * (tid & 7);
+                const int kq = v / (TMR / 8), m8 = 8 * (v % (TMR / 8));
                 const int gk = k0 + kq, gi = i0 + m8;
-                if (gk < kend && gi < M) v = *(const bf16x8 *)&A[(long)gk * lda + gi];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sA[m8 + u][kq] = v[u];
+                if (gk < kend && gi < M) ra[u] = *(const bf16x8 *)&A[(long)gk * lda + gi];
             } else {   // A[m][k]: 8 k's of one row
-                const int r = tid >> 2, k8 = 8 * (tid & 3);
+                const int r = v >> 2, k8 = 8 * (v & 3);
                 const int gi = i0 + r, gk = k0 + k8;
-                if (gi < M && gk < kend) v = *(const bf16x8 *)&A[(long)gi * lda + gk];
-                *(bf16x8 *)&sA[r][k8] = v;
+                if (gi < M && gk < kend) ra[u] = *(const bf16x8 *)&A[(long)gi * lda + gk];
             }
         }
-        {
-            bf16x8 v = {zero, zero, zero, zero, zero, zero, zero, zero};
+#pragma unroll
+        for (int u = 0; u < NVB; ++u) {
+            const int v = tid + 256 * u;
+            rb[u] = (bf16x8){zero, zero, zero, zero, zero, zero, zero, zero};
             if (TB) {  // B[n][k]: 8 k's of one row
-                const int r = tid >> 2, k8 = 8 * (tid & 3);
+                const int r = v >> 2, k8 = 8 * (v & 3);
                 const int gj = j0 + r, gk = k0 + k8;
-                if (gj < N && gk < kend) v = *(const bf16x8 *)&B[(long)gj * ldb + gk];
-                *(bf16x8 *)&sB[r][k8] = v;
+                if (gj < N && gk < kend) rb[u] = *(const bf16x8 *)&B[(long)gj * ldb + gk];
             } else {   // B[k][n]: 8 n's at one k
-                const int kq = tid >> 3, n8 = 8 * (tid & 7);
+                const int kq = v / (TNC / 8), n8 = 8 * (v % (TNC / 8));
                 const int gk = k0 + kq, gj = j0 + n8;
-                if (gk < kend && gj < N) v = *(const bf16x8 *)&B[(long)gk * ldb + gj];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) sB[n8 + u][kq] = v[u];
+                if (gk < kend && gj < N) rb[u] = *(const bf16x8 *)&B[(long)gk * ldb + gj];
             }
         }
-        __syncthreads();
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NVA; ++u) {
+            const int v = tid + 256 * u;
+            if (TA) {
+                const int kq = v / (TMR / 8), m8 = 8 * (v % (TMR / 8));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sA[buf][m8 + q][kq] = ra[u][q];
+            } else {
+                *(bf16x8 *)&sA[buf][v >> 2][8 * (v & 3)] = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NVB; ++u) {
+            const int v = tid + 256 * u;
+            if (TB) {
+                *(bf16x8 *)&sB[buf][v >> 2][8 * (v & 3)] = rb[u];
+            } else {
+                const int kq = v / (TNC / 8), n8 = 8 * (v % (TNC / 8));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sB[buf][n8 + q][kq] = rb[u][q];
+            }
+        }
+    };
+
+    int cur = 0;
+    if (kbeg < kend) {
+        load(kbeg);
+        store(0);
+    }
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+        const bool more = k0 + 32 < kend;
+        if (more) load(k0 + 32);           // in flight during the MFMAs below
         const int kk = 8 * (lane >> 4);
+        bf16x8 fa[FA], fb[FB];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const bf16x8 fa = *(const bf16x8 *)&sA[wi + 16 * a + (lane & 15)][kk];
+        for (int a = 0; a < FA; ++a) fa[a] = *(const bf16x8 *)&sA[cur][wi + 16 * a + (lane & 15)][kk];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const bf16x8 fb = *(const bf16x8 *)&sB[wj + 16 * b + (lane & 15)][kk];
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[a][b], 0, 0, 0);
-            }
-        }
+        for (int b = 0; b < FB; ++b) fb[b] = *(const bf16x8 *)&sB[cur][wj + 16 * b + (lane & 15)][kk];
+#pragma unroll
+        for (int a = 0; a < FA; ++a)
+#pragma unroll
+            for (int b = 0; b < FB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        if (more) store(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = i0 + wi + 16 * a + 4 * (lane >> 4) + v;
@@ -452,12 +496,23 @@ __global__ void k_mixture_table(Geo g, int ntau, long first, int rows, const flo
 }
 
 // ------------------------------------------------------------- launchers
+// Tile choice: 128 x 128 workgroup tiles once they still give at least
+// kMdnBigTiles workgroups (large row counts: inference over anchors), else
+// 64 x 64 (the training batch), so that the grid fills the device.
 template <bool TA, bool TB, int EPI>
 static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
                        float *C, int ldc, const float *bias, __bf16 *Cb, int ldcb, hipStream_t s)
 {
-    const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
-    k_gemm<TA, TB, EPI><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, Cb, ldcb, K);
+    const long big = (long)((M + 127) / 128) * ((N + 127) / 128);
+    if (N >= 128 && big >= kMdnBigTiles) {
+        const dim3 grid((N + 127) / 128, (M + 127) / 128, 1);
+        k_gemm<TA, TB, EPI, 64, 64><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
+                                                          Cb, ldcb, K);
+    } else {
+        const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+        k_gemm<TA, TB, EPI, 32, 32><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
+                                                          Cb, ldcb, K);
+    }
     return hipGetLastError();
 }
 
@@ -483,8 +538,9 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
     int per = 0;
     const int nz = mdn_splits(Mb, &per);
     const dim3 grid((N + 63) / 64, (Mo + 63) / 64, nz);
-    k_gemm<true, false, 0><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb, nz > 1 ? part : C, N,
-                                                nullptr, nullptr, 0, per);
+    k_gemm<true, false, 0, 32, 32><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb,
+                                                        nz > 1 ? part : C, N, nullptr, nullptr, 0,
+                                                        per);
     hipError_t e = hipGetLastError();
     if (e || nz == 1) return e;
     const long n = (long)Mo * N;
