@@ -34,7 +34,8 @@ class Model(C.Structure):
                 ("N", C.c_int64), ("sigma", C.c_double), ("atten", C.c_double),
                 ("vel", C.c_double), ("decay", C.c_double), ("ts", C.c_int32),
                 ("_pad0", C.c_int32), ("rc", C.c_double), ("lam", C.c_double),
-                ("mmin", C.c_double), ("mrate", C.c_double)]
+                ("mmin", C.c_double), ("mrate", C.c_double), ("line", C.c_int32),
+                ("_pad2", C.c_int32), ("xmax", C.c_double), ("sta_x", C.c_double * 8)]
 
 
 class Sampler(C.Structure):
@@ -84,6 +85,8 @@ def lib():
         L.orc_coloring_violations.argtypes = [P, C.c_int32, C.c_int32, C.c_double,
                                               C.c_double, C.c_int32]
         L.orc_coloring_violations.restype = C.c_int64
+        L.orc_line_tau_max.argtypes = [P]
+        L.orc_line_tau_max.restype = C.c_double
         L.orc_arrival_time.argtypes = [C.c_double] * 6 + [P]
         L.orc_arrival_time.restype = C.c_double
         L.orc_event_variance.argtypes = [P, P, C.c_int64, P]
@@ -145,6 +148,12 @@ def make_model(**kw) -> Model:
     m.sigma = kw["sigma"]; m.atten = kw["atten"]; m.vel = kw["vel"]; m.decay = kw["decay"]
     m.ts = kw["ts"]; m.rc = kw["rc"]; m.lam = kw["lam"]; m.mmin = kw["mmin"]
     m.mrate = kw["mrate"]
+    m.line = kw.get("line", 0)
+    m.xmax = kw.get("xmax", 0.0)
+    sx = tuple(kw.get("sta_x", ()))
+    assert len(sx) <= 8
+    for j, v in enumerate(sx):
+        m.sta_x[j] = v
     return m
 
 
@@ -207,7 +216,7 @@ def region_axis(x, off, w, g) -> int:
 
 def partition_and_color(model: Model, gx, gy, offx, offy, dynamic):
     nrx, nry, p, nc = (C.c_int32() for _ in range(4))
-    color = np.zeros((gx + 1) * (gy + 1), dtype=np.int32)
+    color = np.zeros((gx + 1) * (1 if model.line else gy + 1), dtype=np.int32)
     rc = lib().orc_partition_and_color(C.byref(model), gx, gy, offx, offy, dynamic,
                                        C.byref(nrx), C.byref(nry), C.byref(p), C.byref(nc),
                                        _ptr(color))
@@ -216,6 +225,10 @@ def partition_and_color(model: Model, gx, gy, offx, offy, dynamic):
 
 def coloring_violations(model: Model, gx, gy, offx, offy, period) -> int:
     return lib().orc_coloring_violations(C.byref(model), gx, gy, offx, offy, period)
+
+
+def line_tau_max(model: Model) -> float:
+    return lib().orc_line_tau_max(C.byref(model))
 
 
 def arrival_time(x, y, t, sx, sy, vel) -> float:

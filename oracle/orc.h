@@ -30,6 +30,18 @@
  *   - signal likelihood: zero-mean diagonal Gaussian whose variance at each
  *     sample is the noise variance sigma^2 plus the variances of all
  *     arriving signals (Section 3, the paragraph after the joint density).
+ *
+ * Line model (line = 1): the world of Section 3 as the paper states it, with
+ * the time partition of Section 4.1:
+ *   - stations on a line at sta_x[0 .. nsx) (nsy = 1, station y = 0);
+ *     events e = (x, t) with x uniform on [0, xmax), y = 0, and a fixed
+ *     amplitude: the magnitude field holds mmin for every event;
+ *   - every station detects every event; d = |x - sta_x[j]|, a = t + d / vel;
+ *   - the signal is iid Gaussian of constant variance mmin^2 on
+ *     [ceil(a), ceil(a) + ts): a boxcar, no attenuation, no decay;
+ *   - regions are intervals of onset time: region i holds onsets in
+ *     [off + (i-1) w, off + i w) clipped to [0, N), w = N / gx; the
+ *     colour of region i is i mod p.
  */
 #ifndef ORC_H
 #define ORC_H
@@ -55,6 +67,10 @@ typedef struct {
     double  lambda;     /* Poisson mean number of events in the domain */
     double  mmin;       /* magnitude lower bound */
     double  mrate;      /* rate of the exponential magnitude prior */
+    int32_t line;       /* 1: the line model (see above) */
+    int32_t _pad2;
+    double  xmax;       /* line model: locations uniform on [0, xmax) */
+    double  sta_x[8];   /* line model: station positions */
 } orc_model;
 
 enum { ORC_BIRTH = 0, ORC_DEATH = 1, ORC_LOC = 2, ORC_TIME = 3, ORC_MAG = 4 };
@@ -102,6 +118,7 @@ int32_t orc_partition_and_color(const orc_model *m, int32_t gx, int32_t gy,
                                 int32_t *ncolors, int32_t *color_of_region);
 int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
                                 double offx, double offy, int32_t period);
+double  orc_line_tau_max(const orc_model *m);
 
 /* ---- likelihood ------------------------------------------------------- */
 typedef struct {

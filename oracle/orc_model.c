@@ -112,8 +112,14 @@ void orc_offset(uint32_t seed, uint32_t chain, uint32_t sweep, double wx, double
  * Geometry.  Stations sit at the centres of an nsx x nsy grid of cells of
  * side ds.
  * ---------------------------------------------------------------------- */
-double orc_station_x(const orc_model *m, int32_t ix) { return ((double)ix + 0.5) * m->ds; }
-double orc_station_y(const orc_model *m, int32_t iy) { return ((double)iy + 0.5) * m->ds; }
+double orc_station_x(const orc_model *m, int32_t ix)
+{
+    return m->line ? m->sta_x[ix] : ((double)ix + 0.5) * m->ds;
+}
+double orc_station_y(const orc_model *m, int32_t iy)
+{
+    return m->line ? 0.0 : ((double)iy + 0.5) * m->ds;
+}
 
 /* Region index along one axis (Section 4.1 partitions the latent space into
  * intervals of length l; Section 4.3.2 shifts all boundaries by an offset).
@@ -145,6 +151,61 @@ static double rect_dist(double px, double py, double x0, double x1, double y0, d
     return sqrt(dx * dx + dy * dy);
 }
 
+/* Line model: distances from station j to the nearest and farthest event
+ * location in [0, xmax]. */
+static void line_reach(const orc_model *m, int32_t j, double *dmin, double *dmax)
+{
+    double sx = m->sta_x[j];
+    *dmin = sx < 0.0 ? -sx : (sx > m->xmax ? sx - m->xmax : 0.0);
+    double a = fabs(sx), b = fabs(sx - m->xmax);
+    *dmax = a > b ? a : b;
+}
+
+/* Line model: the longest travel time from any location to any station
+ * (Section 3's tau_max, the time a wave takes to cross the world when the
+ * stations sit at its ends). */
+double orc_line_tau_max(const orc_model *m)
+{
+    double t = 0.0;
+    for (int32_t j = 0; j < m->nsx; ++j) {
+        double dmin, dmax;
+        line_reach(m, j, &dmin, &dmax);
+        if (dmax / m->vel > t) t = dmax / m->vel;
+    }
+    return t;
+}
+
+/* Line model (Section 4.1's time partition): region i holds onsets in
+ * [t0, t1); its events arrive at station j within [t0 + dmin / vel,
+ * t1 + dmax / vel), so the samples they can touch lie in
+ * [ceil(t0 + dmin / vel), ceil(t1 + dmax / vel) + ts).  Two regions of one
+ * colour conflict when these sample ranges meet at some station: their
+ * events could then explain the same samples. */
+static int64_t line_violations(const orc_model *m, int32_t g, double off, int32_t period)
+{
+    double w = (double)m->N / (double)g;
+    int64_t bad = 0;
+    for (int32_t j = 0; j < m->nsx; ++j) {
+        double dmin, dmax;
+        line_reach(m, j, &dmin, &dmax);
+        for (int32_t a = 0; a <= g; ++a) {
+            double a0, a1;
+            region_bounds(off, w, (double)m->N, a, &a0, &a1);
+            if (!(a1 > a0)) continue;
+            double lo_a = ceil(a0 + dmin / m->vel), hi_a = ceil(a1 + dmax / m->vel) + m->ts;
+            for (int32_t b = a + 1; b <= g; ++b) {
+                if (a % period != b % period) continue;
+                double b0, b1;
+                region_bounds(off, w, (double)m->N, b, &b0, &b1);
+                if (!(b1 > b0)) continue;
+                double lo_b = ceil(b0 + dmin / m->vel), hi_b = ceil(b1 + dmax / m->vel) + m->ts;
+                if (lo_a < hi_b && lo_b < hi_a) ++bad;
+            }
+        }
+    }
+    return bad;
+}
+
 /* Number of (station, pair of same-coloured regions) conflicts: two regions
  * of one colour must not both lie within the detection cutoff of a common
  * station, otherwise their events could explain the same signal and the
@@ -153,6 +214,7 @@ static double rect_dist(double px, double py, double x0, double x1, double y0, d
 int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
                                 double offx, double offy, int32_t period)
 {
+    if (m->line) return line_violations(m, gx, offx, period);
     double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     double wx = Lx / (double)gx, wy = Ly / (double)gy;
     int32_t nrx = gx + 1;
@@ -189,6 +251,32 @@ int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
     return bad;
 }
 
+/* Line model partition: gx regions of onset time (gy unused), colour i mod p.
+ * Dynamic partitions need p - 1 region lengths to cover the longest travel
+ * time plus the signal duration, p = ceil((tau_max + ts) / w) + 1. */
+static int32_t line_partition(const orc_model *m, int32_t gx, double offt, int32_t dynamic,
+                              int32_t *nrx, int32_t *nry, int32_t *period, int32_t *ncolors,
+                              int32_t *color_of_region)
+{
+    double w = (double)m->N / (double)gx;
+    int32_t p;
+    if (dynamic) {
+        p = (int32_t)ceil((orc_line_tau_max(m) + (double)m->ts) / w) + 1;
+        if (line_violations(m, gx, offt, p) != 0) return -4;
+    } else {
+        for (p = 1; p <= gx + 1; ++p)
+            if (line_violations(m, gx, offt, p) == 0) break;
+        if (p > gx + 1) return -4;
+    }
+    *nrx = gx + 1;
+    *nry = 1;
+    *period = p;
+    *ncolors = p;
+    if (color_of_region)
+        for (int32_t i = 0; i <= gx; ++i) color_of_region[i] = i % p;
+    return 0;
+}
+
 /* Partition and colouring.  Colour of region (i, k) is (i mod p) + p (k mod p).
  * Static partitions (Section 4.3.1) use the smallest period whose colouring
  * passes the exact station check at the given offset; dynamic partitions
@@ -200,6 +288,8 @@ int32_t orc_partition_and_color(const orc_model *m, int32_t gx, int32_t gy,
                                 int32_t *nrx, int32_t *nry, int32_t *period,
                                 int32_t *ncolors, int32_t *color_of_region)
 {
+    if (m->line)
+        return line_partition(m, gx, offx, dynamic, nrx, nry, period, ncolors, color_of_region);
     double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     double wx = Lx / (double)gx, wy = Ly / (double)gy;
     double w = wx < wy ? wx : wy;
@@ -242,14 +332,15 @@ double orc_arrival_time(double x, double y, double t, double sx, double sy, doub
 
 /* Arrival of one event at station (ix, iy): distance d, detection d < rc,
  * arrival a = t + d / vel, amplitude A = m exp(-d / atten), and the samples
- * [n0, n1) = [ceil(a), ceil(a) + ts) clipped to the trace. */
+ * [n0, n1) = [ceil(a), ceil(a) + ts) clipped to the trace.  In the line
+ * model every station detects and the amplitude does not attenuate. */
 void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
                  orc_arrival_t *out)
 {
     out->a = orc_arrival_time(e->x, e->y, e->t, orc_station_x(m, ix), orc_station_y(m, iy),
                               m->vel, &out->d);
-    out->in = out->d < m->rc;
-    out->amp = e->m * exp(-out->d / m->atten);
+    out->in = m->line ? 1 : out->d < m->rc;
+    out->amp = m->line ? e->m : e->m * exp(-out->d / m->atten);
     int64_t n0 = (int64_t)ceil(out->a);
     int64_t n1 = n0 + m->ts;
     if (n0 < 0) n0 = 0;
@@ -261,11 +352,12 @@ void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
 
 /* Variance the event adds at sample n: its signal is zero-mean Gaussian with
  * standard deviation A phi(n - a), phi(tau) = exp(-tau / decay), during the
- * signal duration, and absent otherwise. */
+ * signal duration, and absent otherwise.  The line model's signal is iid
+ * over its duration (phi = 1). */
 double orc_arrival_variance(const orc_model *m, const orc_arrival_t *ar, int64_t n)
 {
     if (n < ar->n0 || n >= ar->n1) return 0.0;
-    double env = exp(-((double)n - ar->a) / m->decay);
+    double env = m->line ? 1.0 : exp(-((double)n - ar->a) / m->decay);
     double sd = ar->amp * env;
     return sd * sd;
 }
@@ -278,7 +370,7 @@ static int64_t events_at_station(const orc_model *m, const orc_event *ev, int64_
     double sx = orc_station_x(m, ix), sy = orc_station_y(m, iy);
     for (int64_t i = 0; i < nev; ++i) {
         double dx = ev[i].x - sx, dy = ev[i].y - sy;
-        if (sqrt(dx * dx + dy * dy) < m->rc) idx[k++] = i;
+        if (m->line || sqrt(dx * dx + dy * dy) < m->rc) idx[k++] = i;
     }
     return k;
 }
@@ -357,6 +449,11 @@ double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev)
 {
     double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     double total = -m->lambda;
+    if (m->line) {  /* uniform location on [0, xmax), no magnitude */
+        for (int64_t i = 0; i < nev; ++i)
+            total += log(m->lambda) - log(m->xmax) - log((double)m->N);
+        return total;
+    }
     for (int64_t i = 0; i < nev; ++i) {
         total += log(m->lambda) - log(Lx * Ly) - log((double)m->N) + log(m->mrate)
                  - m->mrate * (ev[i].m - m->mmin);

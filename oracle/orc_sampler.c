@@ -82,26 +82,42 @@ static void lat_coords(const orc_chain *c, int32_t ix, int32_t iy, int32_t it, i
                        orc_event *e)
 {
     e->x = ((double)ix + 0.5) * lat_hx(c);
-    e->y = ((double)iy + 0.5) * lat_hy(c);
+    e->y = c->m.line ? 0.0 : ((double)iy + 0.5) * lat_hy(c);
     e->t = ((double)it + 0.5) * lat_ht(c);
-    e->m = c->m.mmin + ((double)im + 0.5) * c->sp.hm;
+    e->m = c->m.line ? c->m.mmin : c->m.mmin + ((double)im + 0.5) * c->sp.hm;
 }
 
 static void lat_index(const orc_chain *c, const orc_event *e, int32_t *ix, int32_t *iy,
                       int32_t *it, int32_t *im)
 {
     *ix = (int32_t)floor(e->x / lat_hx(c));
-    *iy = (int32_t)floor(e->y / lat_hy(c));
     *it = (int32_t)floor(e->t / lat_ht(c));
+    if (c->m.line) {  /* one row of sites, the fixed amplitude */
+        *iy = 0;
+        *im = 0;
+        return;
+    }
+    *iy = (int32_t)floor(e->y / lat_hy(c));
     *im = (int32_t)floor((e->m - c->m.mmin) / c->sp.hm);
 }
 
 /* ------------------------------------------------------------- partition */
-static int32_t region_of(const orc_chain *c, double x, double y)
+/* Region of an event: by location on the grid, by onset time in the line
+ * model (whose partition axis is time, Section 4.1). */
+static int32_t region_of(const orc_chain *c, double x, double y, double t)
 {
+    if (c->m.line) return orc_region_axis(t, c->offx, c->wx, c->sp.gx);
     int32_t i = orc_region_axis(x, c->offx, c->wx, c->sp.gx);
     int32_t k = orc_region_axis(y, c->offy, c->wy, c->sp.gy);
     return k * c->nrx + i;
+}
+
+/* Line model: the onset interval [t0, t1) of region r. */
+static void region_times(const orc_chain *c, int32_t r, double *t0, double *t1)
+{
+    double a = c->offx + (double)(r - 1) * c->wx, b = c->offx + (double)r * c->wx;
+    *t0 = a > 0.0 ? a : 0.0;
+    *t1 = b < (double)c->m.N ? b : (double)c->m.N;
 }
 
 static void region_rect(const orc_chain *c, int32_t r, double *x0, double *x1, double *y0,
@@ -126,8 +142,25 @@ static int64_t lat_region_sites(const orc_chain *c, int32_t r, int64_t want, int
         for (int32_t a = 0; a < c->sp.kx; ++a) {
             orc_event e;
             lat_coords(c, a, b, 0, 0, &e);
-            if (region_of(c, e.x, e.y) != r) continue;
+            if (region_of(c, e.x, e.y, e.t) != r) continue;
             if (cnt == want) { *ix = a; *iy = b; }
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* Line model: lattice sites (x, onset) inside region r, onset-major. */
+static int64_t lat_line_region_sites(const orc_chain *c, int32_t r, int64_t want, int32_t *ix,
+                                     int32_t *it)
+{
+    int64_t cnt = 0;
+    for (int32_t b = 0; b < c->sp.kt; ++b) {
+        orc_event e;
+        lat_coords(c, 0, 0, b, 0, &e);
+        if (region_of(c, e.x, e.y, e.t) != r) continue;
+        for (int32_t a = 0; a < c->sp.kx; ++a) {
+            if (cnt == want) { *ix = a; *it = b; }
             ++cnt;
         }
     }
@@ -156,12 +189,21 @@ orc_chain *orc_chain_new(const orc_model *m, const orc_sampler *sp, const double
     c->s = s;
     c->seed = seed;
     c->chain = chain;
-    c->Lx = (double)m->nsx * m->ds;
-    c->Ly = (double)m->nsy * m->ds;
-    c->wx = c->Lx / (double)sp->gx;
-    c->wy = c->Ly / (double)sp->gy;
-    c->nrx = sp->gx + 1;
-    c->nry = sp->gy + 1;
+    if (m->line) {  /* regions of onset time along the first axis */
+        c->Lx = m->xmax;
+        c->Ly = 1.0;
+        c->wx = (double)m->N / (double)sp->gx;
+        c->wy = 0.0;
+        c->nrx = sp->gx + 1;
+        c->nry = 1;
+    } else {
+        c->Lx = (double)m->nsx * m->ds;
+        c->Ly = (double)m->nsy * m->ds;
+        c->wx = c->Lx / (double)sp->gx;
+        c->wy = c->Ly / (double)sp->gy;
+        c->nrx = sp->gx + 1;
+        c->nry = sp->gy + 1;
+    }
     c->nreg = (int64_t)c->nrx * c->nry;
     c->color = (int32_t *)calloc((size_t)c->nreg, sizeof(int32_t));
     c->reg = (evlist *)calloc((size_t)c->nreg, sizeof(evlist));
@@ -198,7 +240,7 @@ static int32_t relayout(orc_chain *c, double offx, double offy)
             if (orc_coloring_violations(&c->m, c->sp.gx, c->sp.gy, offx, offy, c->sp.period) != 0)
                 return -4;
             p = c->sp.period;
-            nc = p * p;
+            nc = c->m.line ? p : p * p;
             for (int32_t k = 0; k < nry; ++k)
                 for (int32_t i = 0; i < nrx; ++i) c->color[k * nrx + i] = (i % p) + p * (k % p);
         }
@@ -214,7 +256,7 @@ static int32_t relayout(orc_chain *c, double offx, double offy)
     int32_t status = 0;
     for (int64_t q = 0; q < all.n; ++q) {
         orc_event e = all.e[q];
-        e.region = region_of(c, e.x, e.y);
+        e.region = region_of(c, e.x, e.y, e.t);
         if (c->reg[e.region].n >= c->sp.cap) status = -3;
         ev_push(&c->reg[e.region], &e);
     }
@@ -274,10 +316,14 @@ int64_t orc_chain_overflows(const orc_chain *c) { return c->overflows; }
 static void build_snapshot(orc_chain *c)
 {
     for (int64_t j = 0; j < c->nsta; ++j) c->snap[j].n = 0;
-    int32_t reach = (int32_t)ceil(c->m.rc / c->m.ds) + 1;
+    int32_t reach = c->m.line ? 0 : (int32_t)ceil(c->m.rc / c->m.ds) + 1;
     for (int64_t r = 0; r < c->nreg; ++r) {
         for (int64_t q = 0; q < c->reg[r].n; ++q) {
             const orc_event *e = &c->reg[r].e[q];
+            if (c->m.line) {  /* every station detects every event */
+                for (int64_t j = 0; j < c->nsta; ++j) ev_push(&c->snap[j], e);
+                continue;
+            }
             int32_t cx = (int32_t)floor(e->x / c->m.ds), cy = (int32_t)floor(e->y / c->m.ds);
             for (int32_t iy = cy - reach; iy <= cy + reach; ++iy) {
                 if (iy < 0 || iy >= c->m.nsy) continue;
@@ -309,10 +355,13 @@ static double move_delta(orc_chain *c, int32_t r, int32_t type, int64_t idx,
     const evlist *own = &c->reg[r];
     const orc_event *old = (type == ORC_BIRTH) ? NULL : &own->e[idx];
     const orc_event *neu = (type == ORC_DEATH) ? NULL : nw;
-    int32_t reach = (int32_t)ceil(m->rc / m->ds) + 1;
+    int32_t reach = m->line ? 0 : (int32_t)ceil(m->rc / m->ds) + 1;
     int32_t lo_x = m->nsx, hi_x = -1, lo_y = m->nsy, hi_y = -1;
     const orc_event *pts[2] = {old, neu};
-    for (int q = 0; q < 2; ++q) {
+    if (m->line) {  /* every station */
+        lo_x = 0; hi_x = m->nsx - 1; lo_y = 0; hi_y = 0;
+    }
+    for (int q = 0; q < 2 && !m->line; ++q) {
         if (!pts[q]) continue;
         int32_t cx = (int32_t)floor(pts[q]->x / m->ds), cy = (int32_t)floor(pts[q]->y / m->ds);
         if (cx - reach < lo_x) lo_x = cx - reach;
@@ -432,6 +481,7 @@ int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *w
     c->lcum = NULL;
     c->ltab = NULL;
     if (!table) return 0;
+    if (c->m.line) return -1;  /* anchors are defined on the station grid only */
     if (n_tau < 1 || !weights || !(p_learned >= 0.0 && p_learned <= 1.0)) return -1;
     c->lcum = (double *)malloc(sizeof(double) * (size_t)(c->nsta * n_tau));
     for (int64_t st = 0; st < c->nsta; ++st) {
@@ -454,7 +504,7 @@ static int32_t region_stations(const orc_chain *c, int32_t r, int32_t *out, int3
     int32_t cnt = 0;
     for (int32_t st = 0; st < (int32_t)c->nsta; ++st) {
         double sx = orc_station_x(&c->m, st % c->m.nsx), sy = orc_station_y(&c->m, st / c->m.nsx);
-        if (region_of(c, sx, sy) != r) continue;
+        if (region_of(c, sx, sy, 0.0) != r) continue;
         if (cnt < cap) out[cnt] = st;
         ++cnt;
     }
@@ -593,6 +643,14 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
         if (n >= sp->cap) {
             valid = 0;
             c->overflows++;
+        } else if (sp->lattice && m->line) {
+            int32_t ix = 0, it = 0;
+            int64_t nr = lat_line_region_sites(c, r, -1, &ix, &it);
+            int64_t pick = (int64_t)floor(d[1] * (double)nr);
+            if (pick >= nr) pick = nr - 1;
+            lat_line_region_sites(c, r, pick, &ix, &it);
+            lat_coords(c, ix, 0, it, 0, &nw);
+            nw.m = m->mmin;
         } else if (sp->lattice) {
             int32_t ix = 0, iy = 0;
             int64_t nr = lat_region_sites(c, r, -1, &ix, &iy);
@@ -604,6 +662,17 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             if (it >= sp->kt) it = sp->kt - 1;
             if (im >= sp->km) im = sp->km - 1;
             lat_coords(c, ix, iy, it, im, &nw);
+        } else if (m->line) {
+            /* prior birth on the region: location on [0, xmax), onset in
+             * the region's interval, the fixed amplitude */
+            double t0, t1;
+            region_times(c, r, &t0, &t1);
+            nw.x = d[1] * c->Lx;
+            nw.y = 0.0;
+            nw.t = t0 + d[3] * (t1 - t0);
+            nw.m = m->mmin;
+            valid = nw.x >= 0.0 && nw.x < c->Lx && nw.t >= 0.0 && nw.t < (double)m->N &&
+                    region_of(c, nw.x, nw.y, nw.t) == r;
         } else {
             double x0, x1, y0, y1;
             region_rect(c, r, &x0, &x1, &y0, &y1);
@@ -616,7 +685,7 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             }
             nw.m = m->mmin + d[4] / m->mrate;
             valid = nw.x >= 0.0 && nw.x < c->Lx && nw.y >= 0.0 && nw.y < c->Ly &&
-                    nw.t >= 0.0 && nw.t < (double)m->N && region_of(c, nw.x, nw.y) == r;
+                    nw.t >= 0.0 && nw.t < (double)m->N && region_of(c, nw.x, nw.y, nw.t) == r;
         }
         nw.id = ((uint64_t)sweep << 32) | ((uint64_t)(uint32_t)r << 12) | (uint64_t)j;
         nw.region = r;
@@ -644,14 +713,23 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
                             it < sp->kt && im >= 0 && im < sp->km;
                     if (valid) {
                         lat_coords(c, ix, iy, it, im, &nw);
-                        valid = region_of(c, nw.x, nw.y) == r;
+                        valid = region_of(c, nw.x, nw.y, nw.t) == r;
                     }
                 }
+            } else if (m->line && type == ORC_LOC) {
+                /* the location is not a partition axis of the line model */
+                nw.x = nw.x + sp->sxy * d[5];
+                valid = nw.x >= 0.0 && nw.x < c->Lx;
+            } else if (m->line && type == ORC_TIME) {
+                nw.t = nw.t + sp->st * d[5];
+                valid = nw.t >= 0.0 && nw.t < (double)m->N && region_of(c, nw.x, nw.y, nw.t) == r;
+            } else if (m->line && type == ORC_MAG) {
+                valid = 0;  /* the line model's amplitude is fixed */
             } else if (type == ORC_LOC) {
                 nw.x = nw.x + sp->sxy * d[5];
                 nw.y = nw.y + sp->sxy * d[6];
                 valid = nw.x >= 0.0 && nw.x < c->Lx && nw.y >= 0.0 && nw.y < c->Ly &&
-                        region_of(c, nw.x, nw.y) == r;
+                        region_of(c, nw.x, nw.y, nw.t) == r;
             } else if (type == ORC_TIME) {
                 nw.t = nw.t + sp->st * d[5];
                 valid = nw.t >= 0.0 && nw.t < (double)m->N;
@@ -708,9 +786,21 @@ int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double
         double x0, x1, y0, y1;
         region_rect(c, (int32_t)r, &x0, &x1, &y0, &y1);
         double area = (x1 - x0) * (y1 - y0);
+        if (c->m.line) {  /* the region's share of the onset interval */
+            double t0, t1;
+            region_times(c, (int32_t)r, &t0, &t1);
+            area = t1 - t0;
+        }
         if (!(area > 0.0)) continue;
         double lam_r;
-        if (c->sp.lattice) {
+        if (c->sp.lattice && c->m.line) {
+            int32_t a, b;
+            int64_t nr = lat_line_region_sites(c, (int32_t)r, -1, &a, &b);
+            if (nr == 0) continue;
+            lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.kt);
+        } else if (c->m.line) {
+            lam_r = c->m.lambda * area / (double)c->m.N;
+        } else if (c->sp.lattice) {
             int32_t a, b;
             int64_t nr = lat_region_sites(c, (int32_t)r, -1, &a, &b);
             if (nr == 0) continue;
@@ -768,12 +858,12 @@ void orc_lattice_site(const orc_model *m, const orc_sampler *sp, int64_t site, o
     rest /= sp->kt;
     int32_t iy = (int32_t)(rest % sp->ky);
     int32_t ix = (int32_t)(rest / sp->ky);
-    double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
+    double Lx = m->line ? m->xmax : (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     memset(out, 0, sizeof *out);
     out->x = ((double)ix + 0.5) * (Lx / (double)sp->kx);
-    out->y = ((double)iy + 0.5) * (Ly / (double)sp->ky);
+    out->y = m->line ? 0.0 : ((double)iy + 0.5) * (Ly / (double)sp->ky);
     out->t = ((double)it + 0.5) * ((double)m->N / (double)sp->kt);
-    out->m = m->mmin + ((double)im + 0.5) * sp->hm;
+    out->m = m->line ? m->mmin : m->mmin + ((double)im + 0.5) * sp->hm;
 }
 
 /* Every multiset of at most nmax sites, with its unnormalised log posterior:

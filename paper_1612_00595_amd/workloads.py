@@ -42,14 +42,17 @@ class ModelSpec:
     lam: float = 20.0
     mmin: float = 2.0
     mrate: float = 1.0
+    line: int = 0              # 1: stations on a line, events (x, t), time partition
+    xmax: float = 0.0          # line: locations on [0, xmax)
+    sta_x: tuple = ()          # line: station positions (at most 8)
 
     @property
     def Lx(self) -> float:
-        return self.nsx * self.ds
+        return self.xmax if self.line else self.nsx * self.ds
 
     @property
     def Ly(self) -> float:
-        return self.nsy * self.ds
+        return 1.0 if self.line else self.nsy * self.ds
 
     @property
     def nsta(self) -> int:
@@ -129,7 +132,21 @@ CHAINS32 = Workload(
     sampler=SamplerSpec(gx=32, gy=32, dynamic=1),
     trace_dtype="f32", chains=32, sweeps=500, seed=2)
 
-WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32)}
+# The paper's own world (Section 3 as printed, Section 5's setting): four
+# stations at x = 0, 33, 66, 100 on a line of length x_max = 100, wave speed
+# 2, T = 240 unit samples, Poisson mean 8 events, each an iid Gaussian signal
+# of variance 4 over 10 samples on background variance 1 at every station;
+# four regions of onset time (l = 60 >= tau_max + t_s = 50 + 10, so two
+# colours, as in Section 4.1), k = 500 moves per region per phase (Section 5).
+PAPER1D_MODEL = ModelSpec(nsx=4, nsy=1, ds=1.0, N=240, sigma=1.0, atten=1.0, vel=2.0,
+                          decay=1.0, ts=10, rc=0.5, lam=8.0, mmin=2.0, mrate=1.0, line=1,
+                          xmax=100.0, sta_x=(0.0, 33.0, 66.0, 100.0))
+PAPER1D_SAMPLER = SamplerSpec(gx=4, gy=0, dynamic=0, k=500, cap=64, pb=0.2, pd=0.2, ploc=0.3,
+                              pt=0.3, pm=0.0, sxy=2.0, st=1.0, sm=0.0)
+PAPER1D = Workload(name="line4-x100-n240-t4-k500", model=PAPER1D_MODEL, sampler=PAPER1D_SAMPLER,
+                   trace_dtype="f64", chains=1, sweeps=200, seed=5)
+
+WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32, PAPER1D)}
 
 
 def uneven_batch(count: int = 256, seed: int = 1000) -> list:
@@ -171,6 +188,11 @@ def truth_events(model: ModelSpec, seed: int, n: int | None = None):
     rng = np.random.Generator(np.random.PCG64(seed))
     if n is None:
         n = int(rng.poisson(model.lam))
+    if model.line:  # locations on [0, xmax), y = 0, the fixed amplitude
+        x = np.minimum(rng.random(n) * model.xmax, np.nextafter(model.xmax, 0.0))
+        t = np.minimum(rng.random(n) * model.N, np.nextafter(float(model.N), 0.0))
+        return dict(x=x, y=np.zeros(n), t=t, m=np.full(n, model.mmin),
+                    id=np.arange(n, dtype=np.uint64))
     x = np.minimum(rng.random(n) * model.Lx, np.nextafter(model.Lx, 0.0))
     y = np.minimum(rng.random(n) * model.Ly, np.nextafter(model.Ly, 0.0))
     t = np.minimum(rng.random(n) * model.N, np.nextafter(float(model.N), 0.0))
