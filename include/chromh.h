@@ -79,6 +79,19 @@ typedef struct {
     double  lambda;       /* Poisson mean number of events */
     double  mag_min;      /* magnitude lower bound */
     double  mag_rate;     /* rate of the exponential magnitude prior */
+    /* Line model (line = 1): the 1-D world of Section 3 as printed.  nsx
+     * stations (1..8, nsy = 1) at station_x on a line; events (x, t) with
+     * y = 0, x uniform on [0, x_max); every station detects every event at
+     * a = t + |x - station_x[j]| / velocity; the signal is Gaussian with the
+     * constant variance m^2 on [ceil(a), ceil(a) + t_s) (m = mag_min for
+     * events the sampler creates).  The partition is in onset time
+     * (Section 4.1): grid_x regions, grid_y = 0.  ds, atten, env_decay, r_c
+     * and mag_rate are not used; magnitude moves are rejected; learned
+     * births, anchors and training pairs are not available. */
+    int32_t line;
+    int32_t _pad1;
+    double  x_max;
+    double  station_x[8];
 } cmh_model;
 
 typedef struct {
@@ -113,8 +126,13 @@ const char *cmh_last_error(void);
  * (i mod p) + p (k mod p).  Static partitions use the smallest p whose
  * colouring passes the exact check (no station within r_c of two regions of
  * one colour); dynamic ones use p = ceil(2 r_c / w) + 1, which holds for
- * every offset.  color_of_region: caller array of (grid_x+1)*(grid_y+1)
- * int32, may be NULL.  Pure host function.  CMH_ECOLOR if no p works. */
+ * every offset.  Line model: regions of onset time, w = n_samples / grid_x,
+ * off_x the time offset, off_y = 0, grid_y = 0; region i can touch samples
+ * [ceil(t0 + dmin / v), ceil(t1 + dmax / v) + t_s) of a station at distances
+ * dmin..dmax from the line, and no two regions of one colour may share a
+ * sample; dynamic p = ceil((tau_max + t_s) / w) + 1; colour i mod p.
+ * color_of_region: caller array of (grid_x+1)*(grid_y+1) int32, may be NULL.
+ * Pure host function.  CMH_ECOLOR if no p works. */
 int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t grid_y,
                                 double off_x, double off_y, int32_t dynamic,
                                 int32_t *n_reg_x, int32_t *n_reg_y, int32_t *period,

@@ -29,7 +29,8 @@ class CmhModel(C.Structure):
                 ("n_samples", C.c_int64), ("sigma", C.c_double), ("atten", C.c_double),
                 ("velocity", C.c_double), ("env_decay", C.c_double), ("t_s", C.c_int32),
                 ("_pad0", C.c_int32), ("r_c", C.c_double), ("lam", C.c_double),
-                ("mag_min", C.c_double), ("mag_rate", C.c_double)]
+                ("mag_min", C.c_double), ("mag_rate", C.c_double), ("line", C.c_int32),
+                ("_pad1", C.c_int32), ("x_max", C.c_double), ("station_x", C.c_double * 8)]
 
 
 class CmhSampler(C.Structure):
@@ -129,6 +130,11 @@ def model_struct(spec: ModelSpec) -> CmhModel:
     m.sigma, m.atten, m.velocity, m.env_decay = spec.sigma, spec.atten, spec.vel, spec.decay
     m.t_s, m.r_c, m.lam = spec.ts, spec.rc, spec.lam
     m.mag_min, m.mag_rate = spec.mmin, spec.mrate
+    m.line, m.x_max = spec.line, spec.xmax
+    if len(spec.sta_x) > 8:
+        raise ValueError("at most 8 stations on a line")
+    for j, v in enumerate(spec.sta_x):
+        m.station_x[j] = v
     return m
 
 
@@ -224,7 +230,8 @@ class ChromaticSampler:
         self._h = h
         _, _, self.period, self.ncolors, _ = partition_and_color(
             model, sampler.gx, sampler.gy, 0.0, 0.0, sampler.dynamic) \
-            if sampler.period == 0 else (0, 0, sampler.period, sampler.period ** 2, None)
+            if sampler.period == 0 else (0, 0, sampler.period,
+                                         sampler.period ** (1 if model.line else 2), None)
         self._feed = None
         self._log = None
 
@@ -528,6 +535,6 @@ class Batch(ChromaticSampler):
         self._h = h
         self.ncolors = max(
             partition_and_color(m, sp.gx, sp.gy, 0.0, 0.0, sp.dynamic)[3] if sp.period == 0
-            else sp.period ** 2 for m, sp in zip(models, samplers))
+            else sp.period ** (1 if m.line else 2) for m, sp in zip(models, samplers))
         self._feed = None
         self._log = None

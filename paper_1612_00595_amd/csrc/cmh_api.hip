@@ -39,9 +39,33 @@ int32_t fail(int32_t code, const std::string &msg)
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------- validation
+// The line model: 1..8 stations on a line, events on [0, x_max); atten,
+// env_decay, r_c and ds are not used.
+int32_t check_line_model(const cmh_model *m)
+{
+    if (m->nsy != 1 || m->nsx < 1 || m->nsx > 8)
+        return fail(CMH_EINVAL, "line model: nsy = 1 and 1..8 stations");
+    if (!(m->x_max > 0.0) || !std::isfinite(m->x_max))
+        return fail(CMH_EINVAL, "line model: x_max must be positive");
+    for (int j = 0; j < m->nsx; ++j)
+        if (!std::isfinite(m->station_x[j]))
+            return fail(CMH_EINVAL, "line model: station positions must be finite");
+    if (m->n_samples < 1) return fail(CMH_EINVAL, "n_samples must be positive");
+    if ((long long)m->nsx * m->n_samples >= (1LL << 31))
+        return fail(CMH_EINVAL, "stations x samples must stay below 2^31");
+    if (!(m->sigma > 0.0)) return fail(CMH_EINVAL, "sigma must be positive");
+    if (!(m->velocity > 0.0)) return fail(CMH_EINVAL, "velocity must be positive");
+    if (m->t_s < 1 || m->t_s > cmh::kMaxTs) return fail(CMH_EINVAL, "t_s must be in 1..128");
+    if (!(m->lambda > 0.0)) return fail(CMH_EINVAL, "lambda must be positive");
+    if (!std::isfinite(m->mag_min)) return fail(CMH_EINVAL, "mag_min must be finite");
+    return CMH_OK;
+}
+
 int32_t check_model(const cmh_model *m)
 {
     if (!m) return fail(CMH_EINVAL, "model is NULL");
+    if (m->line != 0 && m->line != 1) return fail(CMH_EINVAL, "line must be 0 or 1");
+    if (m->line) return check_line_model(m);
     if (m->nsx < 1 || m->nsy < 1) return fail(CMH_EINVAL, "station grid must be at least 1x1");
     if ((long long)m->nsx * m->nsy > (1LL << 22)) return fail(CMH_EINVAL, "too many stations");
     if (!(m->ds > 0.0)) return fail(CMH_EINVAL, "ds must be positive");
@@ -61,8 +85,14 @@ int32_t check_model(const cmh_model *m)
     return CMH_OK;
 }
 
-int32_t check_grid(int32_t gx, int32_t gy)
+int32_t check_grid(const cmh_model *m, int32_t gx, int32_t gy)
 {
+    if (m->line) {
+        if (gx < 1 || gy != 0)
+            return fail(CMH_EINVAL, "line model: grid_x >= 1 onset regions and grid_y = 0");
+        if (gx + 1 >= (1 << 20)) return fail(CMH_EINVAL, "at most 2^20 regions");
+        return CMH_OK;
+    }
     if (gx < 1 || gy < 1) return fail(CMH_EINVAL, "grid must be at least 1x1");
     if ((long long)(gx + 1) * (gy + 1) >= (1LL << 20))
         return fail(CMH_EINVAL, "at most 2^20 regions");
@@ -108,9 +138,83 @@ long long colour_conflicts(const cmh_model *m, int gx, int gy, double offx, doub
     return bad;
 }
 
+// Line model: nearest and farthest distance from station j to [0, x_max].
+void line_reach(const cmh_model *m, int j, double *dmin, double *dmax)
+{
+    const double s = m->station_x[j];
+    *dmin = s < 0.0 ? -s : (s > m->x_max ? s - m->x_max : 0.0);
+    *dmax = std::max(std::fabs(s), std::fabs(s - m->x_max));
+}
+
+// Line model: the longest travel time from the line to a station.
+double line_tmax(const cmh_model *m)
+{
+    double t = 0.0;
+    for (int j = 0; j < m->nsx; ++j) {
+        double lo, hi;
+        line_reach(m, j, &lo, &hi);
+        t = std::max(t, hi / m->velocity);
+    }
+    return t;
+}
+
+// Line model conflicts for period p: onset region [t0, t1) can touch
+// samples [ceil(t0 + dmin / v), ceil(t1 + dmax / v) + t_s) of station j;
+// two regions of one colour must not share a sample of any station.
+long long line_conflicts(const cmh_model *m, int gx, double offt, int p)
+{
+    const double N = (double)m->n_samples, w = N / (double)gx;
+    std::vector<double> lo(gx + 1), hi(gx + 1);
+    for (int i = 0; i <= gx; ++i) cmh::region_span(offt, w, N, i, &lo[i], &hi[i]);
+    long long bad = 0;
+    for (int j = 0; j < m->nsx; ++j) {
+        double dmin, dmax;
+        line_reach(m, j, &dmin, &dmax);
+        std::vector<double> a(gx + 1), b(gx + 1);
+        for (int i = 0; i <= gx; ++i) {
+            a[i] = std::ceil(lo[i] + dmin / m->velocity);
+            b[i] = std::ceil(hi[i] + dmax / m->velocity) + m->t_s;
+        }
+        for (int i = 0; i <= gx; ++i) {
+            if (!(hi[i] > lo[i])) continue;
+            for (int q = i + p; q <= gx; q += p)
+                if (hi[q] > lo[q] && a[q] < b[i] && a[i] < b[q]) ++bad;
+        }
+    }
+    return bad;
+}
+
+int32_t choose_line_period(const cmh_model *m, int gx, double offt, int dynamic, int requested,
+                           int *period)
+{
+    const double w = (double)m->n_samples / (double)gx;
+    int p;
+    if (dynamic) {
+        p = (int)std::ceil((line_tmax(m) + (double)m->t_s) / w) + 1;
+        if (requested > 0) {
+            if (requested < p)
+                return fail(CMH_ECOLOR, "requested period too small for shifted partitions");
+            p = requested;
+        }
+        if (line_conflicts(m, gx, offt, p) != 0)
+            return fail(CMH_ECOLOR, "colouring check failed");
+    } else if (requested > 0) {
+        p = requested;
+        if (line_conflicts(m, gx, offt, p) != 0)
+            return fail(CMH_ECOLOR, "requested period gives dependent regions of one colour");
+    } else {
+        for (p = 1; p <= gx + 1; ++p)
+            if (line_conflicts(m, gx, offt, p) == 0) break;
+        if (p > gx + 1) return fail(CMH_ECOLOR, "no colouring separates the regions");
+    }
+    *period = p;
+    return CMH_OK;
+}
+
 int32_t choose_period(const cmh_model *m, int gx, int gy, double offx, double offy, int dynamic,
                       int requested, int *period)
 {
+    if (m->line) return choose_line_period(m, gx, offx, dynamic, requested, period);
     const double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     const double w = std::min(Lx / (double)gx, Ly / (double)gy);
     int p;
@@ -142,7 +246,7 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     int32_t rc = check_model(m);
     if (rc) return rc;
     if (!s) return fail(CMH_EINVAL, "sampler is NULL");
-    rc = check_grid(s->grid_x, s->grid_y);
+    rc = check_grid(m, s->grid_x, s->grid_y);
     if (rc) return rc;
     if (s->moves_per_region < 1 || s->moves_per_region > 4095)
         return fail(CMH_EINVAL, "moves_per_region must be in 1..4095");
@@ -189,6 +293,25 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     g->c4 = g->c3 + g->pt;
     g->att2 = 2.0 / g->atten;
     g->dec2 = 2.0 / g->decay;
+    if (m->line) {
+        // regions of onset time; every station detects, no attenuation, a
+        // constant signal variance over t_s samples
+        g->ncolors = p;
+        g->nry = 1;
+        g->R = g->nrx;
+        g->Lx = m->x_max;
+        g->Ly = 1.0;
+        g->wx = (double)m->n_samples / (double)s->grid_x;
+        g->wy = 0.0;
+        g->rc = INFINITY;
+        g->atten = INFINITY;
+        g->decay = INFINITY;
+        g->att2 = 0.0;
+        g->dec2 = 0.0;
+        g->line = 1;
+        g->tmax = line_tmax(m);
+        for (int j = 0; j < m->nsx; ++j) g->sx[j] = m->station_x[j];
+    }
     return CMH_OK;
 }
 
@@ -495,9 +618,24 @@ int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t 
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
-    rc = check_grid(grid_x, grid_y);
+    rc = check_grid(model, grid_x, grid_y);
     if (rc) return rc;
     if (!n_reg_x || !n_reg_y || !period || !n_colors) return fail(CMH_EINVAL, "NULL output");
+    if (model->line) {
+        const double w = (double)model->n_samples / grid_x;
+        if (!(off_x >= 0.0 && off_x < w) || off_y != 0.0)
+            return fail(CMH_EINVAL, "line model: offset in [0, w), off_y = 0");
+        int p = 0;
+        rc = choose_line_period(model, grid_x, off_x, dynamic ? 1 : 0, 0, &p);
+        if (rc) return rc;
+        *n_reg_x = grid_x + 1;
+        *n_reg_y = 1;
+        *period = p;
+        *n_colors = p;
+        if (color_of_region)
+            for (int i = 0; i <= grid_x; ++i) color_of_region[i] = i % p;
+        return CMH_OK;
+    }
     const double Lx = (double)model->nsx * model->ds, Ly = (double)model->nsy * model->ds;
     const double wx = Lx / grid_x, wy = Ly / grid_y;
     if (!(off_x >= 0.0 && off_x < wx && off_y >= 0.0 && off_y < wy))
@@ -683,9 +821,7 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
         if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
               e.t < (double)g.N && e.m >= g.mmin))
             return fail(CMH_EINVAL, "event outside the model's support");
-        const int i = cmh::region_axis(e.x, off[0], g.wx, g.gx);
-        const int k = cmh::region_axis(e.y, off[1], g.wy, g.gy);
-        reg[k * g.nrx + i].push_back(e);
+        reg[cmh::event_region(g, off[0], off[1], e.x, e.y, e.t)].push_back(e);
     }
     const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
     std::vector<int> cnt(g.R, 0);
@@ -958,6 +1094,7 @@ int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes)
     int32_t rc = check_state(st);
     if (rc) return rc;
     if ((rc = check_single(st))) return rc;
+    if (st->g.line) return fail(CMH_EINVAL, "learned births need the station grid model");
     if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
     if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
     *bytes = carve_learned(st, n_tau, nullptr, nullptr, nullptr);
@@ -971,6 +1108,8 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
     int32_t rc = check_state(st);
     if (rc) return rc;
     if ((rc = check_single(st))) return rc;
+    if (table_dev && st->g.line)
+        return fail(CMH_EINVAL, "learned births need the station grid model");
     drop_graphs(st);
     if (!table_dev) {
         st->learned = cmh::Learned{};
@@ -1182,15 +1321,26 @@ int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, 
     g.att2 = 2.0 / g.atten; g.dec2 = 2.0 / g.decay;
     g.Lx = (double)model->nsx * model->ds; g.Ly = (double)model->nsy * model->ds;
     g.wx = g.Lx / (double)g.gx; g.wy = g.Ly / (double)g.gy;
+    if (model->line) {
+        // cells of onset time, long enough that a tile's gather spans at
+        // most 25 of them
+        g.line = 1;
+        g.tmax = line_tmax(model);
+        for (int j = 0; j < model->nsx; ++j) g.sx[j] = model->station_x[j];
+        g.rc = INFINITY; g.atten = INFINITY; g.decay = INFINITY; g.att2 = 0.0; g.dec2 = 0.0;
+        g.Lx = model->x_max; g.Ly = 1.0;
+        const double wmin = std::max(512.0, (cmh::kTile + g.tmax + g.ts + 1.0) / 23.0);
+        g.gx = std::max(1, (int)((double)g.N / wmin));
+        g.gy = 0; g.nrx = g.gx + 1; g.nry = 1; g.R = g.nrx;
+        g.wx = (double)g.N / (double)g.gx; g.wy = 0.0;
+    }
     L->cells.assign(g.R, {});
     for (int64_t q = 0; q < n; ++q) {
         const cmh_event &e = truth[q];
         if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
               e.t < (double)g.N && std::isfinite(e.m)))
             return fail(CMH_EINVAL, "truth event outside the domain");
-        const int i = cmh::region_axis(e.x, 0.0, g.wx, g.gx);
-        const int k = cmh::region_axis(e.y, 0.0, g.wy, g.gy);
-        L->cells[k * g.nrx + i].push_back(e);
+        L->cells[cmh::event_region(g, 0.0, 0.0, e.x, e.y, e.t)].push_back(e);
     }
     L->cap = 1;
     for (auto &c : L->cells) {
@@ -1480,6 +1630,7 @@ int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair,
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
+    if (model->line) return fail(CMH_EINVAL, "training pairs need the station grid model");
     if (count < 0 || first_pair < 0 || (count > 0 && (!x_dev || !z_dev)))
         return fail(CMH_EINVAL, "bad arguments");
     Geo g;
@@ -1493,6 +1644,7 @@ int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
+    if (model->line) return fail(CMH_EINVAL, "anchors need the station grid model");
     if (model->n_samples < cmh::kMdnWin + 3)
         return fail(CMH_EINVAL, "anchors need at least 67 samples");
     const long ntau = (long)((model->n_samples - (cmh::kMdnWin + 3)) / cmh::kMdnTScale) + 1;

@@ -40,6 +40,14 @@ struct Geo {
     double pb, pd, ploc, pt, pm, sxy, st, sm;
     double c1, c2, c3, c4;  // cumulative move-type thresholds
     double att2, dec2;      // 2 / atten, 2 / decay
+    // Line model (the paper's 1-D world): stations at sx[0 .. nsx) on a line
+    // (nsy = 1), events (x, t) with y = 0, regions of onset time along the
+    // first region axis (wx is the region length in samples, wy = 0).  The
+    // host sets rc, atten and decay to infinity there, so every station
+    // detects every event with a constant (boxcar) signal variance m^2.
+    int line, pad_line;
+    double tmax;            // longest travel time from the line to a station
+    double sx[8];
 };
 
 // Learned birth proposal: a mixture over the anchors (station, window) of
@@ -150,6 +158,15 @@ __host__ __device__ inline void region_span(double off, double w, double L, int 
 // Station position on the cell-centred grid.
 __host__ __device__ inline double station_pos(int i, double ds) { return ((double)i + 0.5) * ds; }
 
+// Region of an event under offsets (offx, offy): by location on the grid, by
+// onset time in the line model.
+__host__ __device__ inline int event_region(const Geo &g, double offx, double offy, double x,
+                                            double y, double t)
+{
+    if (g.line) return region_axis(t, offx, g.wx, g.gx);
+    return region_axis(y, offy, g.wy, g.gy) * g.nrx + region_axis(x, offx, g.wx, g.gx);
+}
+
 // Arrival of an event at a station: distance, arrival time, first sample and
 // the variance scale B = A^2 exp(-2 (n0 - a) / decay), so that the variance
 // the event adds at sample n0 + q is B exp(-2 q / decay).
@@ -163,8 +180,8 @@ __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, dou
                                  int iy)
 {
     Arrival ar;
-    const double dx = x - station_pos(ix, g.ds);
-    const double dy = y - station_pos(iy, g.ds);
+    const double dx = x - (g.line ? g.sx[ix] : station_pos(ix, g.ds));
+    const double dy = y - (g.line ? 0.0 : station_pos(iy, g.ds));
     const double d = sqrt(dx * dx + dy * dy);
     const double a = t + d / g.vel;
     const double c = ceil(a);

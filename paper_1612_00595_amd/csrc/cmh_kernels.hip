@@ -228,6 +228,32 @@ __device__ inline bool in_region_axis(double x, double lo, double hi, double off
     return region_axis(x, off, w, g) == want;
 }
 
+// A region's extent and prior mean count Lambda_R.  On the grid: its
+// rectangle [x0, x1) x [y0, y1).  In the line model: the whole line
+// [x0, x1) = [0, x_max) and the region's onset interval [y0, y1) (time is the
+// partition axis there).
+struct RegionBox {
+    double x0, x1, y0, y1, area, lamR;
+};
+
+__device__ inline RegionBox region_box(const Geo &g, double offx, double offy, int i, int kk)
+{
+    RegionBox b;
+    if (g.line) {
+        b.x0 = 0.0;
+        b.x1 = g.Lx;
+        region_span(offx, g.wx, (double)g.N, i, &b.y0, &b.y1);
+        b.area = b.y1 - b.y0;
+        b.lamR = g.lambda * b.area / (double)g.N;
+    } else {
+        region_span(offx, g.wx, g.Lx, i, &b.x0, &b.x1);
+        region_span(offy, g.wy, g.Ly, kk, &b.y0, &b.y1);
+        b.area = (b.x1 - b.x0) * (b.y1 - b.y0);
+        b.lamR = g.lambda * b.area / (g.Lx * g.Ly);
+    }
+    return b;
+}
+
 // Footprint of a move, computed by the 64 lanes of wave 0: every station
 // within the detection cutoff of the old or the new event, with the union of
 // their sample windows.  Candidate stations are the cells around both events;
@@ -250,6 +276,9 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
     }
     cx0 = max(cx0 - 1, 0); cy0 = max(cy0 - 1, 0);
     cx1 = min(cx1 + 1, g.nsx - 1); cy1 = min(cy1 + 1, g.nsy - 1);
+    if (g.line) {  // every station of the line
+        cx0 = 0; cx1 = g.nsx - 1; cy0 = 0; cy1 = 0;
+    }
     const int bw = cx1 - cx0 + 1;
     const int nbox = bw * (cy1 - cy0 + 1);
     const int half = lane >> 5, hl = lane & 31;
@@ -342,6 +371,13 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
         if (type == 0) {
             if (n >= g.cap) {
                 mflags |= kFlagCap;
+            } else if (g.line) {  // [y0, y1) is the region's onset interval
+                nx = d[1] * g.Lx;
+                ny = 0.0;
+                nt = y0 + d[3] * (y1 - y0);
+                nm = g.mmin;
+                valid = nx >= 0.0 && nx < g.Lx && nt >= 0.0 && nt < (double)g.N &&
+                        in_region_axis(nt, y0, y1, offx, g.wx, g.gx, i);
             } else {
                 if (L.tab != nullptr) {  // derived for the sweep by the draw kernel
                     nx = lb[0]; ny = lb[1]; nt = lb[2]; lr = lb[3];
@@ -361,7 +397,18 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
             ox = s_ex[idx]; oy = s_ey[idx]; ot = s_et[idx]; om = s_em[idx];
             nx = ox; ny = oy; nt = ot; nm = om;
             valid = 1;
-            if (type == 2) {
+            if (g.line) {  // location moves keep the region; onset moves must
+                if (type == 2) {
+                    nx = ox + g.sxy * d[5];
+                    valid = nx >= 0.0 && nx < g.Lx;
+                } else if (type == 3) {
+                    nt = ot + g.st * d[5];
+                    valid = nt >= 0.0 && nt < (double)g.N &&
+                            in_region_axis(nt, y0, y1, offx, g.wx, g.gx, i);
+                } else if (type == 4) {
+                    valid = 0;  // fixed amplitude
+                }
+            } else if (type == 2) {
                 nx = ox + g.sxy * d[5];
                 ny = oy + g.sxy * d[6];
                 valid = nx >= 0.0 && nx < g.Lx && ny >= 0.0 && ny < g.Ly &&
@@ -466,12 +513,10 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     const long long sweep = *sweep_ptr;
 
     const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
-    double x0, x1, y0, y1;
-    region_span(offx, g.wx, g.Lx, i, &x0, &x1);
-    region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
-    const double area = (x1 - x0) * (y1 - y0);
+    const RegionBox box = region_box(g, offx, offy, i, kk);
+    const double x0 = box.x0, x1 = box.x1, y0 = box.y0, y1 = box.y1, area = box.area;
     if (!(area > 0.0)) return;
-    const double lamR = g.lambda * area / (g.Lx * g.Ly);
+    const double lamR = box.lamR;
     const double log_lamR = log(lamR), log_pb = log(g.pb), log_pd = log(g.pd);
 
     const long long base = ((long long)chain * g.R + r) * g.cap;
@@ -881,10 +926,9 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     if (lane == 0) {
         double *c = s_rc[wv];
         c[0] = ev.off[0]; c[1] = ev.off[1];
-        region_span(c[0], g.wx, g.Lx, i, &c[2], &c[3]);
-        region_span(c[1], g.wy, g.Ly, kk, &c[4], &c[5]);
-        c[6] = (c[3] - c[2]) * (c[5] - c[4]);
-        c[7] = log(g.lambda * c[6] / (g.Lx * g.Ly));
+        const RegionBox b = region_box(g, c[0], c[1], i, kk);
+        c[2] = b.x0; c[3] = b.x1; c[4] = b.y0; c[5] = b.y1; c[6] = b.area;
+        c[7] = log(b.lamR);
         c[8] = log(g.pb); c[9] = log(g.pd);
     }
     __builtin_amdgcn_wave_barrier();
@@ -1314,8 +1358,7 @@ __global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restri
             const int no = src.cnt[chain * g.R + ro];
             for (int s = 0; s < no; ++s) {
                 const double x = src.x[sbase + s], y = src.y[sbase + s];
-                if (region_axis(x, offx, g.wx, g.gx) != i || region_axis(y, offy, g.wy, g.gy) != k)
-                    continue;
+                if (event_region(g, offx, offy, x, y, src.t[sbase + s]) != r) continue;
                 if (n >= g.cap) {
                     atomicOr(err, kFlagCap);
                     continue;
@@ -1360,10 +1403,18 @@ __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int
     if (tid == 0) {
         const double sx = station_pos(ix, g.ds), sy = station_pos(iy, g.ds);
         const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
-        const int i0 = region_axis(sx - g.rc, offx, g.wx, g.gx);
-        const int i1 = region_axis(sx + g.rc, offx, g.wx, g.gx);
-        const int k0 = region_axis(sy - g.rc, offy, g.wy, g.gy);
-        const int k1 = region_axis(sy + g.rc, offy, g.wy, g.gy);
+        int i0, i1, k0, k1;
+        if (g.line) {  // onsets whose signal can meet the tile at any station
+            i0 = region_axis((double)n_lo - g.tmax - (double)g.ts - 1.0, offx, g.wx, g.gx);
+            i1 = region_axis((double)n_hi, offx, g.wx, g.gx);
+            k0 = 0;
+            k1 = 0;
+        } else {
+            i0 = region_axis(sx - g.rc, offx, g.wx, g.gx);
+            i1 = region_axis(sx + g.rc, offx, g.wx, g.gx);
+            k0 = region_axis(sy - g.rc, offy, g.wy, g.gy);
+            k1 = region_axis(sy + g.rc, offy, g.wy, g.gy);
+        }
         int nr = 0, off = 0;
         for (int kk = k0; kk <= k1; ++kk)
             for (int ii = i0; ii <= i1; ++ii) {

@@ -78,3 +78,33 @@ def test_partition_matches_oracle(orc, side, grid, dynamic):
         assert rc == 0
         assert got[:4] == tuple(want[:4])
         assert np.array_equal(got[4], want[4])
+
+
+@pytest.mark.parametrize("ts,gx,dynamic", [(10, 4, 0), (10, 4, 1), (11, 4, 0), (11, 4, 1),
+                                           (10, 8, 1), (3, 12, 0)])
+def test_line_partition_matches_oracle(orc, ts, gx, dynamic):
+    """The line model's time partition and colours (host code of the library)
+    against the oracle's, at shifted and unshifted onset offsets."""
+    import dataclasses
+    spec = dataclasses.replace(W.PAPER1D_MODEL, ts=ts)
+    om = orc.make_model(**spec.asdict())
+    w = spec.N / gx
+    rng = np.random.default_rng(ts * 100 + gx)
+    offs = [0.0] + ([float(v) for v in rng.random(25) * w] if dynamic else [])
+    for off in offs:
+        got = chromh.partition_and_color(spec, gx, 0, off, 0.0, dynamic)
+        rc, *want = orc.partition_and_color(om, gx, 0, off, 0.0, dynamic)
+        assert rc == 0
+        assert got[:4] == tuple(want[:4])
+        assert np.array_equal(got[4], want[4])
+
+
+def test_line_model_validation():
+    import dataclasses
+    spec = W.PAPER1D_MODEL
+    with pytest.raises(chromh.CmhError):  # a second region axis
+        chromh.partition_and_color(spec, 4, 1, 0.0, 0.0, 0)
+    with pytest.raises(chromh.CmhError):  # more than 8 stations on a line
+        chromh.partition_and_color(dataclasses.replace(spec, nsx=9), 4, 0, 0.0, 0.0, 0)
+    with pytest.raises(chromh.CmhError):  # offset outside [0, w)
+        chromh.partition_and_color(spec, 4, 0, 60.0, 0.0, 1)
