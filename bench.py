@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MH proposals/s + event-location ESS/s per GPU, learned vs plain at equal F1"
+TIME_THRESH_1D = 12.0   # Section 5's matching threshold in time, the paper's own units
 
 
 def parse():
@@ -58,6 +59,11 @@ def parse():
     ap.add_argument("--learned-sweeps", type=int, default=2000)
     ap.add_argument("--learned-chains", type=int, default=16)
     ap.add_argument("--learned-pairs", type=int, default=10_000_000)
+    ap.add_argument("--no-paper-world", action="store_true",
+                    help="skip the paper's own 1-D experiment (50 worlds x 5 runs)")
+    ap.add_argument("--paper-worlds", type=int, default=50)
+    ap.add_argument("--paper-runs", type=int, default=5)
+    ap.add_argument("--paper-sweeps", type=int, default=100)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating hardware byte counters)")
@@ -216,6 +222,125 @@ def learned_study(args, dev):
     log(f"[bench] learned study: F1 plain {pl['f1']:.3f} learned {le['f1']:.3f}; ESS/s plain "
         f"{pl['ess_per_s']:.4g} learned {le['ess_per_s']:.4g}; training {tr.seconds:.2f} s "
         f"({train_tflops:.1f} TFLOP/s)")
+    return out
+
+
+def paper_world_study(args, dev):
+    """Section 5's experiment on the paper's own 1-D world (four stations on
+    a line, T = 240, Section 4.1's time partition): worlds from the model
+    (seeds 2000, 2001, ...), several runs each, under three schedules run as
+    one batch of every (world, run) chain each: serial MH (one region,
+    2000 moves per sweep), chromatic static and chromatic dynamic (four onset
+    regions, two colours, k = 500 moves per region per phase, so the same
+    2000 moves per sweep).  Every state is recorded on the device; precision,
+    recall, F1 and location error (Section 5's matching, 12 units in space and
+    time) against sweeps and wall time, and 95% bootstrap intervals over worlds
+    of the final values.  The oracle runs the same schedules on two worlds for
+    the CPU rate."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1612_00595_amd import chromh, metrics as M, workloads as W
+    spec = W.PAPER1D_MODEL
+    scheds = {"serial": dataclasses.replace(W.PAPER1D_SAMPLER, gx=1, k=2000),
+              "chromatic_static": W.PAPER1D_SAMPLER,
+              "chromatic_dynamic": dataclasses.replace(W.PAPER1D_SAMPLER, dynamic=1)}
+    nw, nr, S = args.paper_worlds, args.paper_runs, args.paper_sweeps
+    truths, traces = [], []
+    for wi in range(nw):
+        tr = W.truth_events(spec, 2000 + wi)
+        truths.append(tr)
+        traces.append(chromh.simulate(spec, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"]),
+                                      3000 + wi, "f64", dev))
+    every = 5
+    out = {"workload": W.PAPER1D.name + " worlds", "worlds": nw, "runs": nr, "sweeps": S,
+           "moves_per_sweep": 2000, "match_thresholds": [M.PAPER_DIST_THRESH, TIME_THRESH_1D],
+           "true_events_mean": float(np.mean([len(t["x"]) for t in truths]))}
+    n = nw * nr
+
+    def batch(sp, block):
+        return chromh.Batch([spec] * n, [sp] * n, [traces[q // nr] for q in range(n)],
+                            [7919 * (q // nr) + q % nr for q in range(n)], block=block)
+
+    for name, sp in scheds.items():
+        # kernel form by a short trial (few work items per colour favour the
+        # latency form, many the wave form)
+        trial = {}
+        for block in (64, 128, 256):
+            b = batch(sp, block)
+            b.run_sweeps(0, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run_sweeps(1, 3)
+            torch.cuda.synchronize()
+            trial[block] = time.perf_counter() - t0
+            b.close()
+        block = min(trial, key=trial.get)
+        b = batch(sp, block)
+        rec = b.set_record(0, S + 1, 64)
+        b.run_sweeps(0, 1)                 # graphs built outside the timed region
+        torch.cuda.synchronize()
+        c0 = sum(b.read_counters(q) for q in range(n))
+        t0 = time.perf_counter()
+        b.run_sweeps(1, S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = sum(b.read_counters(q) for q in range(n)) - c0
+        proposals = float(d[:15].reshape(5, 3)[:, 0].sum())
+        pts = list(range(every - 1, S, every))
+        P = np.zeros((n, len(pts))); Rc = np.zeros_like(P); F = np.zeros_like(P)
+        E = np.full_like(P, np.nan)
+        recc = rec[1:].cpu().numpy()
+        for q in range(n):
+            states = chromh.ChromaticSampler.recorded_states(recc, q)
+            for a, sw in enumerate(pts):
+                r = M.match(truths[q // nr], states[sw], dist_thresh=M.PAPER_DIST_THRESH,
+                            time_thresh=TIME_THRESH_1D)
+                P[q, a], Rc[q, a], F[q, a], E[q, a] = r.precision, r.recall, r.f1, \
+                    r.location_error
+        b.close()
+        ms = el * 1e3 / S
+
+        def final(v):
+            per_world = np.nanmean(v[:, -1].reshape(nw, nr), axis=1)
+            mean, lo, hi = M.bootstrap_ci(per_world[np.isfinite(per_world)])
+            return [mean, lo, hi]
+        out[name] = {
+            "ms_per_sweep": ms, "proposals_per_s": proposals / el, "block": block,
+            "final_precision_ci95": final(P), "final_recall_ci95": final(Rc),
+            "final_f1_ci95": final(F), "final_location_error_ci95": final(E),
+            "curve": {"sweeps": [p + 1 for p in pts],
+                      "ms": [(p + 1) * ms for p in pts],
+                      "precision": P.mean(0).round(4).tolist(),
+                      "recall": Rc.mean(0).round(4).tolist(),
+                      "f1": F.mean(0).round(4).tolist(),
+                      "location_error": np.nanmean(E, 0).round(3).tolist()}}
+        log(f"[bench] paper world, {name} (block {block}): {ms:.3f} ms/sweep for {n} chains, "
+            f"{proposals / el:.4g} proposals/s, final F1 {out[name]['final_f1_ci95'][0]:.3f}")
+    # the oracle: the same schedules, two worlds, one run each
+    osw = max(S // 5, 4)
+    m = O.make_model(**spec.asdict())
+    orc = {}
+    for name, sp in scheds.items():
+        t0, moves = time.perf_counter(), 0
+        for wi in range(2):
+            s = O.simulate(m, O.as_events(truths[wi]["x"], truths[wi]["y"], truths[wi]["t"],
+                                          truths[wi]["m"]), 3000 + wi)
+            ch = O.Chain(m, O.make_sampler(**sp.asdict()), s, seed=7919 * wi)
+            for sw in range(osw):
+                assert ch.sweep(sw) == 0
+            moves += osw * 2000
+        el = time.perf_counter() - t0
+        orc[name] = {"proposals_per_s": moves / el, "ms_per_sweep": el * 1e3 / (2 * osw)}
+    out["cpu_baseline"] = dict(orc, kind="oracle", cores=1,
+                               sample=f"2 worlds x 1 run x {osw} sweeps per schedule")
+    st, se = out["chromatic_static"], out["serial"]
+    out["per_chain_sweep_speedup_static_vs_serial"] = se["ms_per_sweep"] / st["ms_per_sweep"]
+    out["gpu_vs_oracle_proposals"] = {k: out[k]["proposals_per_s"] / orc[k]["proposals_per_s"]
+                                      for k in scheds}
     return out
 
 
@@ -495,6 +620,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_learned:
         out["learned"] = learned_study(args, dev)
+        torch.cuda.empty_cache()
+    if not args.no_paper_world:
+        out["paper_world"] = paper_world_study(args, dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

@@ -23,6 +23,7 @@ import numpy as np
 
 DIST_THRESH = 0.12
 TIME_THRESH = 12.0
+PAPER_DIST_THRESH = 12.0   # the 1-D world of the paper, in its own units
 
 
 @dataclasses.dataclass
