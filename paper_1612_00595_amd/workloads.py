@@ -10,12 +10,13 @@ attenuating form Section 4.1 names as the natural case for spatial
 partitioning; the paper evaluates only on synthetic worlds sampled from its
 own model (Section 5), so every input here is synthetic by construction.
 
-Physical constants shared by every workload: stations on a cell-centred grid
-of spacing 0.2, amplitude m exp(-d / 0.2), onset-delayed exponential envelope
-of decay 20 samples, arrival t + d / 0.05, noise sigma 0.1, detection cutoff
-0.19, signal duration 128 samples, magnitude 2 + Exp(1).  Larger workloads
-keep the station spacing and grow the domain, so that an event still reaches
-at most four stations.
+Physical constants shared by the grid workloads: stations on a cell-centred
+grid of spacing 0.2, amplitude m exp(-d / 0.2), onset-delayed exponential
+envelope of decay 20 samples, arrival t + d / 0.05, noise sigma 0.1,
+detection cutoff 0.19, signal duration 128 samples, magnitude 2 + Exp(1).
+Larger workloads keep the station spacing and grow the domain, so that an
+event still reaches at most four stations.  The line workload is the paper's
+own 1-D world (Section 3 as printed, partitioned in time as in Section 4.1).
 """
 from __future__ import annotations
 
