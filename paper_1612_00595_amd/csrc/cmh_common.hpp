@@ -176,12 +176,14 @@ struct Arrival {
     double B;
 };
 
-__device__ inline Arrival arrive(const Geo &g, double x, double y, double t, double m, int ix,
-                                 int iy)
+// The station sits at (px, py): station_pos of its grid cell, or its place
+// on the line (y = 0) in the line model.
+__device__ inline Arrival arrive(const Geo &g, double x, double y, double t, double m, double px,
+                                 double py)
 {
     Arrival ar;
-    const double dx = x - (g.line ? g.sx[ix] : station_pos(ix, g.ds));
-    const double dy = y - (g.line ? 0.0 : station_pos(iy, g.ds));
+    const double dx = x - px;
+    const double dy = y - py;
     const double d = sqrt(dx * dx + dy * dy);
     const double a = t + d / g.vel;
     const double c = ceil(a);

@@ -92,6 +92,27 @@ __device__ inline int wave_sum_i32(int v)
            (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
+// Exclusive prefix sum of an int over the lanes of a wave.
+__device__ inline int wave_excl_prefix_i32(int v, int lane)
+{
+    int x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x - v;
+}
+
+// 1 / x for the positive, well-scaled model variances: the hardware
+// reciprocal refined by two Newton steps (each squares the relative error).
+__device__ inline double rcp_refined(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
 // Draw record of 16 for learned births: the 8 above, then [8] mixture
 // uniform, [9] anchor uniform (counter block 4), [10] component uniform
 // (block 5), [11..13] standard normals truncated to [-4, 4]: Box-Muller
@@ -203,6 +224,73 @@ struct Seg {
     double Bo, Bn;
 };
 
+// Flat start of every run of a move's footprint and its global base (the
+// station's row offset plus the run's first sample, minus the flat start),
+// so that flat position f inside run t is sample gb[t] + f of E and the trace.
+struct __attribute__((aligned(16))) SegIndex {
+    int fs[kMaxSeg];
+    int gb[kMaxSeg];
+};
+
+// Flat footprint positions f0 + q stride (q < Q): the run holding each and
+// its global sample index (-1 past the footprint's S samples).  Run starts
+// are read four at a time and compared without a data-dependent branch.
+template <int Q>
+__device__ inline void locate_runs(const SegIndex &six, int nseg, int S, int f0, int stride,
+                                   int *run, int *gidx)
+{
+    int base[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) { run[q] = 0; base[q] = 0; }
+    for (int t0 = 0; t0 < nseg; t0 += 4) {
+        const int4 a = *(const int4 *)&six.fs[t0];
+        const int4 b = *(const int4 *)&six.gb[t0];
+        const int fa[4] = {a.x, a.y, a.z, a.w}, ba[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int f = f0 + q * stride;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool take = t0 + u < nseg && fa[u] <= f;
+                run[q] = take ? t0 + u : run[q];
+                base[q] = take ? ba[u] : base[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int f = f0 + q * stride;
+        gidx[q] = f < S ? base[q] + f : -1;
+    }
+}
+
+// Change of the event variance at sample nn of run a: the new event's
+// contribution minus the old event's, envelope from the table sT.
+__device__ inline double run_dvar(const Seg &a, const double *sT, int nn)
+{
+    const bool io = nn >= a.o0 && nn < a.o1;
+    const bool iw = nn >= a.w0 && nn < a.w1;
+    const double co = io ? a.Bo * sT[io ? nn - a.o0 : 0] : 0.0;
+    const double cn = iw ? a.Bn * sT[iw ? nn - a.w0 : 0] : 0.0;
+    return cn - co;
+}
+
+// One sample's share of the log-likelihood change, accumulated as
+// -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')], v = sigma^2 + E (the
+// Gaussian log density of Section 3 differenced); returns the new E.
+__device__ inline double sample_term(double sigma2, double e0, double dc, double s, double *prod,
+                                     double *lin)
+{
+    double en = e0 + dc;
+    en = en > 0.0 ? en : 0.0;
+    const double de = en - e0;
+    const double v = sigma2 + e0, vp = sigma2 + en;
+    const double inv = rcp_refined(v * vp);
+    *prod *= de != 0.0 ? vp * vp * inv : 1.0;
+    *lin += s * s * de * inv;
+    return en;
+}
+
 struct MoveHdr {
     int valid, type, n, nseg, S;
     int flags;  // error flags, raised only when the move is consumed
@@ -261,9 +349,10 @@ __device__ inline RegionBox region_box(const Geo &g, double offx, double offy, i
 // 32-63 the new event's at candidate `lane - 32`, so the two arrival
 // computations run side by side.  A wave prefix sum then places each
 // candidate's one or two sample runs.
-__device__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
+__device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
                           double om, bool has_new, double nx, double ny, double nt, double nm,
-                          Seg *segs, int *nseg_out, int *S_out, int *flags)
+                          Seg *segs, SegIndex *six, const double *lsx, int *nseg_out, int *S_out,
+                          int *flags)
 {
     int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
     if (has_old) {
@@ -294,7 +383,11 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
         if (cidx < nbox) {
             ix = cx0 + cidx % bw;
             iy = cy0 + cidx / bw;
-            if (mine) ar = arrive(g, ex, ey, et, em, ix, iy);
+            // line stations from lsx (LDS): a Geo held in registers must not
+            // be indexed dynamically, which would move it to scratch memory
+            if (mine)
+                ar = arrive(g, ex, ey, et, em, g.line ? lsx[ix] : station_pos(ix, g.ds),
+                            g.line ? 0.0 : station_pos(iy, g.ds));
         }
         // lanes 0-31 take the new event's arrival from their partner lane
         // (the two halves of the wave swapped in registers)
@@ -335,10 +428,17 @@ __device__ void footprint(const Geo &g, int lane, bool has_old, double ox, doubl
         const unsigned long long m1 = __ballot(ns >= 1), m2 = __ballot(ns == 2);
         const unsigned long long below = (1ull << lane) - 1ull;
         const int sbase = seg_base + __popcll(m1 & below) + __popcll(m2 & below);
+        const int fpos = samp_base + wave_excl_prefix_i32(nsamp, lane);
         if (ns >= 1) {
             if (sbase + ns <= kMaxSeg) {
                 segs[sbase] = sa;
-                if (ns == 2) segs[sbase + 1] = sb;
+                six->fs[sbase] = fpos;
+                six->gb[sbase] = sa.j * g.N + sa.lo - fpos;
+                if (ns == 2) {
+                    segs[sbase + 1] = sb;
+                    six->fs[sbase + 1] = fpos + sa.len;
+                    six->gb[sbase + 1] = sb.j * g.N + sb.lo - (fpos + sa.len);
+                }
             } else {
                 *flags |= kFlagSeg;
             }
@@ -359,7 +459,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
                                   double offy, double x0, double x1, double y0, double y1, int n,
                                   const double *d, const double *s_ex, const double *s_ey,
                                   const double *s_et, const double *s_em, Seg (*s_seg)[kMaxSeg],
-                                  MoveHdr *s_hdr, double (*s_prop)[5], int max_samples,
+                                  SegIndex *s_six, const double *lsx, MoveHdr *s_hdr, double (*s_prop)[5], int max_samples,
                                   const Learned &L, const double *lb, const int *lsta,
                                   const RegionLearned &rl)
 {
@@ -442,7 +542,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
         nt = lane_f64(nt, 0); nm = lane_f64(nm, 0);
         int fl = 0;
         footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
-                  &nseg, &S, &fl);
+                  &s_six[buf], lsx, &nseg, &S, &fl);
         if (__ballot(fl != 0) != 0ull || S > max_samples) {
             valid = 0;
             mflags |= kFlagSeg;
@@ -483,7 +583,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     static_assert(BLOCK >= 128 && BLOCK % 64 == 0, "one scout wave and at least one evaluator");
     constexpr int W = BLOCK / 64;
     constexpr int EV = BLOCK - 64;
-    constexpr int MAXQ = (kMaxFootprint + EV - 1) / EV;
+    constexpr int QP = 4;  // footprint positions per evaluator thread per pass
     __shared__ double s_draw[2][kDrawChunk][8];
     __shared__ double s_lb[2][kDrawChunk][4];
     __shared__ int s_lsta[kMaxRegSta];
@@ -493,6 +593,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
     __shared__ unsigned long long s_id[kMaxCap];
     __shared__ Seg s_seg[2][kMaxSeg];
+    __shared__ SegIndex s_six[2];
+    __shared__ double s_lsx[8];  // line model: station positions
     __shared__ MoveHdr s_hdr[2];
     __shared__ double s_prop[2][5];
     __shared__ double s_part[2][W];
@@ -532,6 +634,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     }
     for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-2.0 * (double)q / g.decay);
     for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
+    if (tid < 8) s_lsx[tid] = slots[slot].g.sx[tid];
     for (int c = 0; c < 2 && 64 * c < g.k; ++c) {
         const int m = min(kDrawChunk, g.k - 64 * c) * 8;
         for (int q = tid; q < m; q += BLOCK) s_draw[c][q >> 3][q & 7] = dsrc[64LL * 8 * c + q];
@@ -567,7 +670,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     const RegionLearned rl = s_rl;
     if (wave == 0)
         scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex, s_ey,
-                   s_et, s_em, s_seg, s_hdr, s_prop, MAXQ * EV, L, s_lb[0][0], s_lsta, rl);
+                   s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L, s_lb[0][0],
+                   s_lsta, rl);
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -587,78 +691,59 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         const double lnu = s_draw[(j >> 6) & 1][j & 63][7];
         const bool evaluate = h.valid && !g.prior_only;
 
-        double enew[MAXQ];
-        int gidx[MAXQ];  // station * N + sample of this thread's samples, or -1
+        // the first pass's samples (global index or -1) and their new variance,
+        // kept for the write-back of an accepted move
+        double enew[QP];
+        int gidx[QP];
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) { gidx[q] = -1; enew[q] = 0.0; }
+        for (int q = 0; q < QP; ++q) { gidx[q] = -1; enew[q] = 0.0; }
+        double prod = 1.0, lin = 0.0;
         if (wave == 0) {
             if (j + 1 < g.k)  // speculative: the state as if move j is rejected
                 scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
                            s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em, s_seg,
-                           s_hdr, s_prop, MAXQ * EV, L, s_lb[((j + 1) >> 6) & 1][(j + 1) & 63],
-                           s_lsta, rl);
+                           s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
+                           s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
-            int sidx[MAXQ], sbeg[MAXQ];  // run holding flat position f, and its start
-            int S = 0;
+            // passes of QP strided footprint positions per thread: one pass
+            // unless the footprint exceeds QP * EV samples
+            for (int p = 0; p * QP * EV < h.S; ++p) {
+                int run[QP], gi[QP];
+                locate_runs<QP>(s_six[buf], h.nseg, h.S, et + p * QP * EV, EV, run, gi);
+                // every sample's variance and trace value in flight at once;
+                // slots past the footprint are skipped by a block-uniform
+                // test, idle lanes of a used slot read element 0
+                double eo[QP], sv[QP], dc[QP];
 #pragma unroll
-            for (int q = 0; q < MAXQ; ++q) { sidx[q] = 0; sbeg[q] = 0; }
-            for (int t = 0; t < h.nseg; ++t) {
-#pragma unroll
-                for (int q = 0; q < MAXQ; ++q) {
-                    const bool here = et + q * EV >= S;
-                    sidx[q] = here ? t : sidx[q];
-                    sbeg[q] = here ? S : sbeg[q];
+                for (int q = 0; q < QP; ++q) {
+                    eo[q] = 0.0;
+                    sv[q] = 0.0;
+                    if ((p * QP + q) * EV < h.S) {
+                        const int g0 = gi[q] >= 0 ? gi[q] : 0;
+                        eo[q] = E[ebase + g0];
+                        sv[q] = (double)trace[g0];
+                    }
                 }
-                S += sg[t].len;
-            }
+                // variance changes from the LDS tables while the loads fly
 #pragma unroll
-            for (int q = 0; q < MAXQ; ++q) {
-                const int f = et + q * EV;
-                if (f < S) {
-                    const Seg &a = sg[sidx[q]];
-                    gidx[q] = a.j * g.N + a.lo + (f - sbeg[q]);
+                for (int q = 0; q < QP; ++q) {
+                    dc[q] = 0.0;
+                    if ((p * QP + q) * EV < h.S && gi[q] >= 0) {
+                        const Seg &a = sg[run[q]];
+                        dc[q] = run_dvar(a, s_T, gi[q] - a.j * g.N);
+                    }
                 }
-            }
-            // load: every sample's variance and trace value in flight at once;
-            // slots past the footprint are skipped by a block-uniform test,
-            // idle lanes of a used slot read element 0 (no per-lane branch)
-            double eo[MAXQ], sv[MAXQ];
 #pragma unroll
-            for (int q = 0; q < MAXQ; ++q) {
-                eo[q] = 0.0;
-                sv[q] = 0.0;
-                if (q * EV < S) {
-                    const int gi = gidx[q] >= 0 ? gidx[q] : 0;
-                    eo[q] = E[ebase + gi];
-                    sv[q] = (double)trace[gi];
-                }
-            }
-            // sum of -1/2 [log(v'/v) + s^2 (1/v' - 1/v)], v = sigma^2 + E, as
-            // -1/2 [log(prod v'/v) - sum s^2 (v' - v) / (v v')]
-            double prod = 1.0, lin = 0.0;
-#pragma unroll
-            for (int q = 0; q < MAXQ; ++q) {
-                if (q * EV < S) {
-                    const bool ok = gidx[q] >= 0;
-                    const Seg &a = sg[sidx[q]];
-                    const int nn = gidx[q] - a.j * g.N;
-                    const bool io = ok && nn >= a.o0 && nn < a.o1;
-                    const bool iw = ok && nn >= a.w0 && nn < a.w1;
-                    const double to = s_T[io ? nn - a.o0 : 0], tw = s_T[iw ? nn - a.w0 : 0];
-                    const double e0 = ok ? eo[q] : 0.0;
-                    const double co = io ? a.Bo * to : 0.0;
-                    const double cn = iw ? a.Bn * tw : 0.0;
-                    double en = (e0 - co) + cn;
-                    en = en > 0.0 ? en : 0.0;
-                    const double de = en - e0;
-                    const double v = g.sigma2 + e0;
-                    const double vp = g.sigma2 + en;
-                    const double inv = 1.0 / (v * vp);
-                    prod *= de != 0.0 ? vp * vp * inv : 1.0;
-                    lin += (ok ? sv[q] * sv[q] : 0.0) * de * inv;
-                    enew[q] = en;
+                for (int q = 0; q < QP; ++q) {
+                    if ((p * QP + q) * EV < h.S && gi[q] >= 0) {
+                        const double en = sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
+                        if (p == 0) {
+                            enew[q] = en;
+                            gidx[q] = gi[q];
+                        }
+                    }
                 }
             }
             double part = -0.5 * (log(prod) - lin);
@@ -704,8 +789,27 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         if (accept) {
             if (wave > 0 && !g.prior_only) {
 #pragma unroll
-                for (int q = 0; q < MAXQ; ++q)
+                for (int q = 0; q < QP; ++q)
                     if (gidx[q] >= 0) E[ebase + gidx[q]] = enew[q];
+                // later passes (footprints over QP * EV samples) recompute the
+                // same new variance from the unchanged old one
+                for (int p = 1; p * QP * EV < h.S; ++p) {
+                    int run[QP], gi[QP];
+                    locate_runs<QP>(s_six[buf], h.nseg, h.S, tid - 64 + p * QP * EV, EV, run,
+                                    gi);
+                    double eo[QP];
+#pragma unroll
+                    for (int q = 0; q < QP; ++q)
+                        eo[q] = gi[q] >= 0 ? E[ebase + gi[q]] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < QP; ++q) {
+                        if (gi[q] >= 0) {
+                            const Seg &a = s_seg[buf][run[q]];
+                            const double en = eo[q] + run_dvar(a, s_T, gi[q] - a.j * g.N);
+                            E[ebase + gi[q]] = en > 0.0 ? en : 0.0;
+                        }
+                    }
+                }
             }
             if (tid == 0) {
                 cnt_acc[h.type]++;
@@ -733,17 +837,46 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             __syncthreads();  // the new events and variance are visible
             // The speculative move j + 1 assumed move j rejected.  After an
             // accepted change of one event (n unchanged) it still holds
-            // unless it proposes to change that same event; a birth or
-            // death changes the list, so move j + 1 is built again.
-            const bool rebuild = h.type <= 1 || (s_hdr[buf ^ 1].type != 0 &&
-                                                 s_prop[buf ^ 1][4] == s_prop[buf][4]);
-            if (rebuild && j + 1 < g.k) {
-                if (wave == 0)
-                    scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                               s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em,
-                               s_seg, s_hdr, s_prop, MAXQ * EV, L,
-                               s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
-                __syncthreads();
+            // unless it proposes to change that same event.  A birth or a
+            // death changes the event count and shifts list positions: a
+            // birth proposal stands with the new count (capacity aside), and
+            // a move of an event stands when its draw picks the same event at
+            // its new position (the count and index are patched); anything
+            // else is built again.
+            const MoveHdr nx = s_hdr[buf ^ 1];
+            bool rebuild;
+            int patch_idx = -1;
+            const int n1 = h.type == 0 ? h.n + 1 : h.n - 1;
+            if (h.type >= 2) {
+                rebuild = nx.type != 0 && s_prop[buf ^ 1][4] == s_prop[buf][4];
+            } else if (nx.type == 0) {
+                rebuild = !(h.n < g.cap && n1 < g.cap);
+            } else if (h.n == 0 || n1 == 0) {
+                rebuild = true;
+            } else {
+                const double u = s_draw[((j + 1) >> 6) & 1][(j + 1) & 63][1];
+                int in = (int)floor(u * (double)n1);  // the scout's index rule
+                if (in >= n1) in = n1 - 1;
+                const int dead = (int)s_prop[buf][4];
+                const int was = h.type == 0 ? in : (in >= dead ? in + 1 : in);
+                rebuild = was != (int)s_prop[buf ^ 1][4];
+                patch_idx = in;
+            }
+            if (j + 1 < g.k) {
+                if (rebuild) {
+                    if (wave == 0)
+                        scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                                   s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et,
+                                   s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
+                                   s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
+                    __syncthreads();
+                } else if (h.type <= 1) {
+                    if (tid == 0) {
+                        s_hdr[buf ^ 1].n = n1;
+                        if (patch_idx >= 0) s_prop[buf ^ 1][4] = (double)patch_idx;
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
@@ -782,52 +915,18 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
 constexpr int kWaveQ = 4;
 constexpr int kWaveDraws = 16;  // moves whose draws are staged at once
 
-// Flat footprint samples base + lane + 64 q of one pass: their run and
-// global index (-1 past the footprint).
-__device__ inline void wave_locate(const Geo &g, const Seg *sg, int nseg, int S, int base,
-                                   int lane, int *sidx, int *sbeg, int *gidx)
-{
-    int acc = 0;
-#pragma unroll
-    for (int q = 0; q < kWaveQ; ++q) { sidx[q] = 0; sbeg[q] = 0; gidx[q] = -1; }
-    for (int t = 0; t < nseg; ++t) {
-#pragma unroll
-        for (int q = 0; q < kWaveQ; ++q) {
-            const bool here = base + lane + 64 * q >= acc;
-            sidx[q] = here ? t : sidx[q];
-            sbeg[q] = here ? acc : sbeg[q];
-        }
-        acc += sg[t].len;
-    }
-#pragma unroll
-    for (int q = 0; q < kWaveQ; ++q) {
-        const int f = base + lane + 64 * q;
-        if (f < S) gidx[q] = sg[sidx[q]].j * g.N + sg[sidx[q]].lo + (f - sbeg[q]);
-    }
-}
-
-// New event variance at one footprint sample (old value e0).
-__device__ inline double wave_new_e(const Seg &a, const double *sT, int nn, double e0)
-{
-    const bool io = nn >= a.o0 && nn < a.o1;
-    const bool iw = nn >= a.w0 && nn < a.w1;
-    const double co = io ? a.Bo * sT[io ? nn - a.o0 : 0] : 0.0;
-    const double cn = iw ? a.Bn * sT[iw ? nn - a.w0 : 0] : 0.0;
-    const double en = (e0 - co) + cn;
-    return en > 0.0 ? en : 0.0;
-}
-
-// This lane's share of the log-likelihood change of a move.
+// This lane's share of the log-likelihood change of a move: passes of
+// 64 kWaveQ footprint samples, every load of a pass in flight at once.
 template <typename TraceT>
 __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace,
-                                  const double *__restrict__ E, const Seg *sg, int nseg, int S,
-                                  const double *sT, int lane)
+                                  const double *__restrict__ E, const Seg *sg,
+                                  const SegIndex &six, int nseg, int S, const double *sT, int lane)
 {
-    double lp = 0.0, lin = 0.0;
+    double prod = 1.0, lin = 0.0;
     for (int base = 0; base < S; base += 64 * kWaveQ) {
-        int sidx[kWaveQ], sbeg[kWaveQ], gidx[kWaveQ];
-        wave_locate(g, sg, nseg, S, base, lane, sidx, sbeg, gidx);
-        double eo[kWaveQ], sv[kWaveQ];
+        int run[kWaveQ], gidx[kWaveQ];
+        locate_runs<kWaveQ>(six, nseg, S, base + lane, 64, run, gidx);
+        double eo[kWaveQ], sv[kWaveQ], dc[kWaveQ];
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
             eo[q] = 0.0;
@@ -838,33 +937,30 @@ __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace
                 sv[q] = (double)trace[gi];
             }
         }
-        double prod = 1.0;
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
+            dc[q] = 0.0;
             if (base + 64 * q < S && gidx[q] >= 0) {
-                const Seg &a = sg[sidx[q]];
-                const int nn = gidx[q] - a.j * g.N;
-                const double e0 = eo[q];
-                const double en = wave_new_e(a, sT, nn, e0);
-                const double de = en - e0;
-                const double v = g.sigma2 + e0, vp = g.sigma2 + en;
-                const double inv = 1.0 / (v * vp);
-                prod *= de != 0.0 ? vp * vp * inv : 1.0;
-                lin += sv[q] * sv[q] * de * inv;
+                const Seg &a = sg[run[q]];
+                dc[q] = run_dvar(a, sT, gidx[q] - a.j * g.N);
             }
         }
-        lp += log(prod);
+#pragma unroll
+        for (int q = 0; q < kWaveQ; ++q)
+            if (base + 64 * q < S && gidx[q] >= 0)
+                (void)sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
     }
-    return -0.5 * (lp - lin);
+    return -0.5 * (log(prod) - lin);
 }
 
 // After an acceptance: the new variance over the footprint, written in place.
-__device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg, int nseg, int S,
-                           const double *sT, int lane)
+// The new variance max(E + change, 0) is the one sample_term used for Delta.
+__device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
+                           const SegIndex &six, int nseg, int S, const double *sT, int lane)
 {
     for (int base = 0; base < S; base += 64 * kWaveQ) {
-        int sidx[kWaveQ], sbeg[kWaveQ], gidx[kWaveQ];
-        wave_locate(g, sg, nseg, S, base, lane, sidx, sbeg, gidx);
+        int run[kWaveQ], gidx[kWaveQ];
+        locate_runs<kWaveQ>(six, nseg, S, base + lane, 64, run, gidx);
         double eo[kWaveQ];
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
@@ -874,8 +970,9 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg, 
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q)
             if (base + 64 * q < S && gidx[q] >= 0) {
-                const Seg &a = sg[sidx[q]];
-                E[gidx[q]] = wave_new_e(a, sT, gidx[q] - a.j * g.N, eo[q]);
+                const Seg &a = sg[run[q]];
+                const double en = eo[q] + run_dvar(a, sT, gidx[q] - a.j * g.N);
+                E[gidx[q]] = en > 0.0 ? en : 0.0;
             }
     }
 }
@@ -893,6 +990,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     __shared__ double s_ex[4][kMaxCap], s_ey[4][kMaxCap], s_et[4][kMaxCap], s_em[4][kMaxCap];
     __shared__ unsigned long long s_id[4][kMaxCap];
     __shared__ Seg s_seg[4][1][kMaxSeg];
+    __shared__ SegIndex s_six[4][1];
     __shared__ MoveHdr s_hdr[4][1];
     __shared__ double s_prop[4][1][5];
     __shared__ int s_lsta[4][kMaxRegSta];
@@ -992,7 +1090,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             __builtin_amdgcn_wave_barrier();
         }
         scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey, et,
-                   em, s_seg[wv], s_hdr[wv], s_prop[wv], kMaxFootprint, L, s_lb[wv][jw],
+                   em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L, s_lb[wv][jw],
                    s_lsta[wv], rl);
         __builtin_amdgcn_wave_barrier();
         const MoveHdr h = s_hdr[wv][0];
@@ -1000,8 +1098,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         const bool evaluate = h.valid && !g.prior_only;
         double delta = 0.0;
         if (evaluate)
-            delta = wave_sum(wave_delta_part<TraceT>(g, trace, E, s_seg[wv][0], h.nseg, h.S, sT,
-                                                     lane));
+            delta = wave_sum(wave_delta_part<TraceT>(g, trace, E, s_seg[wv][0], s_six[wv][0],
+                                                     h.nseg, h.S, sT, lane));
         double la;
         if (h.type == 0)
             la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
@@ -1032,7 +1130,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             }
         }
         if (accept) {
-            if (!g.prior_only) wave_write(g, E, s_seg[wv][0], h.nseg, h.S, sT, lane);
+            if (!g.prior_only)
+                wave_write(g, E, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
             if (lane == 0) {
                 cnt[3 * h.type + 2]++;
                 cnt[16] += (unsigned long long)h.S;
@@ -1443,7 +1542,9 @@ __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int
             int q = 0;
             while (q < 24 && s_roff[q + 1] <= f) ++q;
             const long long e = ((long long)chain * g.R + s_rid[q]) * g.cap + (f - s_roff[q]);
-            ar = arrive(g, ev.x[e], ev.y[e], ev.t[e], ev.m[e], ix, iy);
+            ar = arrive(g, ev.x[e], ev.y[e], ev.t[e], ev.m[e],
+                        g.line ? g.sx[ix] : station_pos(ix, g.ds),
+                        g.line ? 0.0 : station_pos(iy, g.ds));
             take = ar.in && ar.n0 < n_hi && ar.n1 > n_lo;
         }
         const unsigned long long mask = __ballot(take);
