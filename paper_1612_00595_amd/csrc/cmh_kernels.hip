@@ -92,15 +92,21 @@ __device__ inline int wave_sum_i32(int v)
            (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
-// Exclusive prefix sum of an int over the lanes of a wave.
-__device__ inline int wave_excl_prefix_i32(int v, int lane)
+// Exclusive prefix sum over the lanes of a wave of a value in [0, 2^BITS):
+// bit by bit, the lanes below with that bit set, counted from a ballot
+// (no LDS round trip).
+template <int BITS>
+__device__ inline int wave_excl_prefix_small(int v)
 {
-    int x = v;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
+    int acc = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const unsigned long long m = __ballot((v >> b) & 1);
+        const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        acc += below << b;
     }
-    return x - v;
+    return acc;
 }
 
 // 1 / x for the positive, well-scaled model variances: the hardware
@@ -428,7 +434,8 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
         const unsigned long long m1 = __ballot(ns >= 1), m2 = __ballot(ns == 2);
         const unsigned long long below = (1ull << lane) - 1ull;
         const int sbase = seg_base + __popcll(m1 & below) + __popcll(m2 & below);
-        const int fpos = samp_base + wave_excl_prefix_i32(nsamp, lane);
+        static_assert(2 * kMaxTs < (1 << 9), "a candidate's samples fit in 9 bits");
+        const int fpos = samp_base + wave_excl_prefix_small<9>(nsamp);
         if (ns >= 1) {
             if (sbase + ns <= kMaxSeg) {
                 segs[sbase] = sa;
