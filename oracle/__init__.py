@@ -35,7 +35,7 @@ class Model(C.Structure):
                 ("vel", C.c_double), ("decay", C.c_double), ("ts", C.c_int32),
                 ("_pad0", C.c_int32), ("rc", C.c_double), ("lam", C.c_double),
                 ("mmin", C.c_double), ("mrate", C.c_double), ("line", C.c_int32),
-                ("_pad2", C.c_int32), ("xmax", C.c_double), ("sta_x", C.c_double * 8)]
+                ("tmpl", C.c_int32), ("xmax", C.c_double), ("sta_x", C.c_double * 8)]
 
 
 class Sampler(C.Structure):
@@ -149,6 +149,7 @@ def make_model(**kw) -> Model:
     m.ts = kw["ts"]; m.rc = kw["rc"]; m.lam = kw["lam"]; m.mmin = kw["mmin"]
     m.mrate = kw["mrate"]
     m.line = kw.get("line", 0)
+    m.tmpl = kw.get("tmpl", 0)
     m.xmax = kw.get("xmax", 0.0)
     sx = tuple(kw.get("sta_x", ()))
     assert len(sx) <= 8

@@ -42,6 +42,14 @@
  *   - regions are intervals of onset time: region i holds onsets in
  *     [off + (i-1) w, off + i w) clipped to [0, N), w = N / gx; the
  *     colour of region i is i mod p.
+ *
+ * Mean-template likelihood (tmpl = 1), the alternative reading of the
+ * signal model: an event adds the deterministic waveform A phi(n - a) (not
+ * a variance) on [ceil(a), ceil(a) + ts), and the trace is the sum of the
+ * waveforms plus Gaussian noise of variance sigma^2.  The per-sample
+ * quantity the sampler tracks is then the sum of waveforms (the mean), and
+ * a move changes the log-likelihood by sum g (r - g / 2) / sigma^2 over its
+ * footprint, r the residual and g the change of the mean.
  */
 #ifndef ORC_H
 #define ORC_H
@@ -68,7 +76,7 @@ typedef struct {
     double  mmin;       /* magnitude lower bound */
     double  mrate;      /* rate of the exponential magnitude prior */
     int32_t line;       /* 1: the line model (see above) */
-    int32_t _pad2;
+    int32_t tmpl;       /* 1: mean-template likelihood (see above) */
     double  xmax;       /* line model: locations uniform on [0, xmax) */
     double  sta_x[8];   /* line model: station positions */
 } orc_model;

@@ -350,16 +350,18 @@ void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
     out->n1 = n1;
 }
 
-/* Variance the event adds at sample n: its signal is zero-mean Gaussian with
- * standard deviation A phi(n - a), phi(tau) = exp(-tau / decay), during the
- * signal duration, and absent otherwise.  The line model's signal is iid
- * over its duration (phi = 1). */
+/* What the event adds at sample n.  Variance model: its signal is zero-mean
+ * Gaussian with standard deviation A phi(n - a), phi(tau) = exp(-tau /
+ * decay), during the signal duration, and absent otherwise, so it adds the
+ * variance (A phi)^2; the line model's signal is iid over its duration
+ * (phi = 1).  Mean-template model: it adds the waveform value A phi(n - a)
+ * to the mean. */
 double orc_arrival_variance(const orc_model *m, const orc_arrival_t *ar, int64_t n)
 {
     if (n < ar->n0 || n >= ar->n1) return 0.0;
     double env = m->line ? 1.0 : exp(-((double)n - ar->a) / m->decay);
     double sd = ar->amp * env;
-    return sd * sd;
+    return m->tmpl ? sd : sd * sd;
 }
 
 /* Events whose signal reaches station (ix, iy) at all. */
@@ -423,6 +425,13 @@ double orc_single_term(double sigma, double s, double e)
     return -0.5 * (log(2.0 * M_PI) + log(v) + s * s / v);
 }
 
+/* Mean-template model: Gaussian with mean e and variance sigma^2. */
+static double template_term(double sigma, double s, double e)
+{
+    double r = s - e;
+    return -0.5 * (log(2.0 * M_PI) + log(sigma * sigma) + r * r / (sigma * sigma));
+}
+
 /* Signal log-likelihood log P(s | e) summed over every station and sample. */
 double orc_loglik(const orc_model *m, const double *s, const orc_event *ev, int64_t nev)
 {
@@ -434,7 +443,9 @@ double orc_loglik(const orc_model *m, const double *s, const orc_event *ev, int6
             const double *sr = s + ((int64_t)iy * m->nsx + ix) * m->N;
             int64_t k = events_at_station(m, ev, nev, ix, iy, idx);
             station_row(m, ev, idx, k, ix, iy, row);
-            for (int64_t n = 0; n < m->N; ++n) total += orc_single_term(m->sigma, sr[n], row[n]);
+            for (int64_t n = 0; n < m->N; ++n)
+                total += m->tmpl ? template_term(m->sigma, sr[n], row[n])
+                                 : orc_single_term(m->sigma, sr[n], row[n]);
         }
     }
     free(row);
@@ -492,7 +503,7 @@ void orc_simulate_rows(const orc_model *m, const orc_event *truth, int64_t nev, 
             double u2 = orc_u01(w[2], w[3]);
             double r = sqrt(-2.0 * log(u1));
             double z = (n & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
-            out[n] = sqrt(m->sigma * m->sigma + row[n]) * z;
+            out[n] = m->tmpl ? row[n] + m->sigma * z : sqrt(m->sigma * m->sigma + row[n]) * z;
         }
     }
     free(row);
@@ -513,7 +524,8 @@ void orc_trace_from_noise_f32(const orc_model *m, const orc_event *truth, int64_
             station_row(m, truth, idx, k, ix, iy, row);
             for (int64_t n = 0; n < m->N; ++n)
                 s_out[j * m->N + n] =
-                    (float)(sqrt(m->sigma * m->sigma + row[n]) * (double)z[j * m->N + n]);
+                    (float)(m->tmpl ? row[n] + m->sigma * (double)z[j * m->N + n]
+                                    : sqrt(m->sigma * m->sigma + row[n]) * (double)z[j * m->N + n]);
         }
     }
     free(row);

@@ -343,6 +343,15 @@ static double gauss_logpdf(double s, double v)
     return -0.5 * (log(2.0 * M_PI) + log(v) + s * s / v);
 }
 
+/* Log density of a sample under the model: variance c (variance model, c
+ * includes sigma^2) or mean c and variance sigma^2 (mean-template model). */
+static double sample_logpdf(const orc_model *m, double s, double c)
+{
+    if (!m->tmpl) return gauss_logpdf(s, c);
+    double r = s - c;
+    return -0.5 * (log(2.0 * M_PI) + log(m->sigma * m->sigma) + r * r / (m->sigma * m->sigma));
+}
+
 /* Change of log P(s | e) when, in region r, the event at index idx of the
  * region's list is removed (death), replaced by *nw (location, time and
  * magnitude moves), or *nw is added (birth).  Every other region contributes
@@ -412,11 +421,12 @@ static double move_delta(orc_chain *c, int32_t r, int32_t type, int64_t idx,
             }
             for (int64_t n = lo; n < hi; ++n) {
                 double sv = trace_at(c, j, n);
-                double base = m->sigma * m->sigma;
+                /* noise variance (variance model) plus what every other event adds */
+                double base = m->tmpl ? 0.0 : m->sigma * m->sigma;
                 for (int64_t q = 0; q < no; ++q) base += orc_arrival_variance(m, &others[q], n);
-                double v_old = base + (old ? orc_arrival_variance(m, &ao, n) : 0.0);
-                double v_new = base + (neu ? orc_arrival_variance(m, &an, n) : 0.0);
-                delta += gauss_logpdf(sv, v_new) - gauss_logpdf(sv, v_old);
+                double c_old = base + (old ? orc_arrival_variance(m, &ao, n) : 0.0);
+                double c_new = base + (neu ? orc_arrival_variance(m, &an, n) : 0.0);
+                delta += sample_logpdf(m, sv, c_new) - sample_logpdf(m, sv, c_old);
             }
         }
     }
@@ -481,7 +491,7 @@ int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *w
     c->lcum = NULL;
     c->ltab = NULL;
     if (!table) return 0;
-    if (c->m.line) return -1;  /* anchors are defined on the station grid only */
+    if (c->m.line || c->m.tmpl) return -1;  /* anchors: grid stations, variance signals */
     if (n_tau < 1 || !weights || !(p_learned >= 0.0 && p_learned <= 1.0)) return -1;
     c->lcum = (double *)malloc(sizeof(double) * (size_t)(c->nsta * n_tau));
     for (int64_t st = 0; st < c->nsta; ++st) {

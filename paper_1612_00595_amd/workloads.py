@@ -44,6 +44,7 @@ class ModelSpec:
     mmin: float = 2.0
     mrate: float = 1.0
     line: int = 0              # 1: stations on a line, events (x, t), time partition
+    tmpl: int = 0              # 1: mean-template likelihood (waveforms add to the mean)
     xmax: float = 0.0          # line: locations on [0, xmax)
     sta_x: tuple = ()          # line: station positions (at most 8)
 
