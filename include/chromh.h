@@ -89,7 +89,16 @@ typedef struct {
      * and mag_rate are not used; magnitude moves are rejected; learned
      * births, anchors and training pairs are not available. */
     int32_t line;
-    int32_t _pad1;
+    /* Mean-template likelihood (template_mean = 1), the alternative reading
+     * of Section 3's signal model: an event adds the deterministic waveform
+     * A phi(n - a) (A = m exp(-d / atten), phi(tau) = exp(-tau / env_decay),
+     * or the constant m on the line) to the mean of the trace, and the trace
+     * is that mean plus Gaussian noise of variance sigma^2.  The state's
+     * per-sample array then holds the residual trace - mean (cmh_read_variance
+     * returns it), a move's log-likelihood change is sum g (r - g / 2) /
+     * sigma^2 over its footprint, and the trace is not read by the sweeps.
+     * Learned births, anchors and training pairs need the variance model. */
+    int32_t template_mean;
     double  x_max;
     double  station_x[8];
 } cmh_model;

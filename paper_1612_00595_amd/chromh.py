@@ -30,7 +30,8 @@ class CmhModel(C.Structure):
                 ("velocity", C.c_double), ("env_decay", C.c_double), ("t_s", C.c_int32),
                 ("_pad0", C.c_int32), ("r_c", C.c_double), ("lam", C.c_double),
                 ("mag_min", C.c_double), ("mag_rate", C.c_double), ("line", C.c_int32),
-                ("_pad1", C.c_int32), ("x_max", C.c_double), ("station_x", C.c_double * 8)]
+                ("template_mean", C.c_int32), ("x_max", C.c_double),
+                ("station_x", C.c_double * 8)]
 
 
 class CmhSampler(C.Structure):
@@ -130,7 +131,7 @@ def model_struct(spec: ModelSpec) -> CmhModel:
     m.sigma, m.atten, m.velocity, m.env_decay = spec.sigma, spec.atten, spec.vel, spec.decay
     m.t_s, m.r_c, m.lam = spec.ts, spec.rc, spec.lam
     m.mag_min, m.mag_rate = spec.mmin, spec.mrate
-    m.line, m.x_max = spec.line, spec.xmax
+    m.line, m.x_max, m.template_mean = spec.line, spec.xmax, spec.tmpl
     if len(spec.sta_x) > 8:
         raise ValueError("at most 8 stations on a line")
     for j, v in enumerate(spec.sta_x):

@@ -65,6 +65,8 @@ int32_t check_model(const cmh_model *m)
 {
     if (!m) return fail(CMH_EINVAL, "model is NULL");
     if (m->line != 0 && m->line != 1) return fail(CMH_EINVAL, "line must be 0 or 1");
+    if (m->template_mean != 0 && m->template_mean != 1)
+        return fail(CMH_EINVAL, "template_mean must be 0 or 1");
     if (m->line) return check_line_model(m);
     if (m->nsx < 1 || m->nsy < 1) return fail(CMH_EINVAL, "station grid must be at least 1x1");
     if ((long long)m->nsx * m->nsy > (1LL << 22)) return fail(CMH_EINVAL, "too many stations");
@@ -293,6 +295,11 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     g->c4 = g->c3 + g->pt;
     g->att2 = 2.0 / g->atten;
     g->dec2 = 2.0 / g->decay;
+    g->tmpl = m->template_mean;
+    if (g->tmpl) {  // waveform amplitudes: A = m exp(-d / atten), phi = exp(-tau / decay)
+        g->att2 = 1.0 / g->atten;
+        g->dec2 = 1.0 / g->decay;
+    }
     if (m->line) {
         // regions of onset time; every station detects, no attenuation, a
         // constant signal variance over t_s samples
@@ -697,7 +704,12 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
     const long long nE = (long long)n_chains * g.nsta * (long long)g.N;
     const long long nR = (long long)n_chains * g.R;
-    if (!e) e = cmh::fill_f64(st->E, nE, 0.0, s);
+    // the empty world's state: no event variance, or under templates the
+    // residual, the trace itself
+    if (!e)
+        e = g.tmpl ? cmh::residual_init(st->E, trace_dev, st->f64,
+                                        (long long)g.nsta * (long long)g.N, nE, s)
+                   : cmh::fill_f64(st->E, nE, 0.0, s);
     for (int b = 0; b < 2 && !e; ++b) {
         e = cmh::fill_i32(st->ev[b].cnt, nR, 0, s);
         if (!e) e = cmh::fill_f64(st->ev[b].off, 2LL * n_chains, 0.0, s);
@@ -1094,7 +1106,8 @@ int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes)
     int32_t rc = check_state(st);
     if (rc) return rc;
     if ((rc = check_single(st))) return rc;
-    if (st->g.line) return fail(CMH_EINVAL, "learned births need the station grid model");
+    if (st->g.line || st->g.tmpl)
+        return fail(CMH_EINVAL, "learned births need the grid model's variance signals");
     if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
     if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
     *bytes = carve_learned(st, n_tau, nullptr, nullptr, nullptr);
@@ -1108,8 +1121,8 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
     int32_t rc = check_state(st);
     if (rc) return rc;
     if ((rc = check_single(st))) return rc;
-    if (table_dev && st->g.line)
-        return fail(CMH_EINVAL, "learned births need the station grid model");
+    if (table_dev && (st->g.line || st->g.tmpl))
+        return fail(CMH_EINVAL, "learned births need the grid model's variance signals");
     drop_graphs(st);
     if (!table_dev) {
         st->learned = cmh::Learned{};
@@ -1246,7 +1259,9 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
         sl.chain = 0;
         sl.trace = traces_dev[q];
         const Geo &g = sl.g;
-        e = cmh::fill_f64(sl.E, (long long)g.nsta * g.N, 0.0, s);
+        const long long nE = (long long)g.nsta * g.N;
+        e = g.tmpl ? cmh::residual_init(sl.E, sl.trace, trace_dtype == CMH_F64, nE, nE, s)
+                   : cmh::fill_f64(sl.E, nE, 0.0, s);
         for (int b = 0; b < 2 && !e; ++b) {
             e = cmh::fill_i32(sl.ev[b].cnt, g.R, 0, s);
             if (!e) e = cmh::fill_f64(sl.ev[b].off, 2, 0.0, s);
@@ -1319,6 +1334,11 @@ int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, 
     g.ds = model->ds; g.sigma2 = model->sigma * model->sigma; g.atten = model->atten;
     g.vel = model->velocity; g.decay = model->env_decay; g.rc = model->r_c;
     g.att2 = 2.0 / g.atten; g.dec2 = 2.0 / g.decay;
+    g.tmpl = model->template_mean;
+    if (g.tmpl) {
+        g.att2 = 1.0 / g.atten;
+        g.dec2 = 1.0 / g.decay;
+    }
     g.Lx = (double)model->nsx * model->ds; g.Ly = (double)model->nsy * model->ds;
     g.wx = g.Lx / (double)g.gx; g.wy = g.Ly / (double)g.gy;
     if (model->line) {
@@ -1630,7 +1650,8 @@ int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair,
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
-    if (model->line) return fail(CMH_EINVAL, "training pairs need the station grid model");
+    if (model->line || model->template_mean)
+        return fail(CMH_EINVAL, "training pairs need the grid model's variance signals");
     if (count < 0 || first_pair < 0 || (count > 0 && (!x_dev || !z_dev)))
         return fail(CMH_EINVAL, "bad arguments");
     Geo g;
@@ -1644,7 +1665,8 @@ int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_
 {
     int32_t rc = check_model(model);
     if (rc) return rc;
-    if (model->line) return fail(CMH_EINVAL, "anchors need the station grid model");
+    if (model->line || model->template_mean)
+        return fail(CMH_EINVAL, "anchors need the grid model's variance signals");
     if (model->n_samples < cmh::kMdnWin + 3)
         return fail(CMH_EINVAL, "anchors need at least 67 samples");
     const long ntau = (long)((model->n_samples - (cmh::kMdnWin + 3)) / cmh::kMdnTScale) + 1;

@@ -39,13 +39,14 @@ struct Geo {
     double wx, wy;
     double pb, pd, ploc, pt, pm, sxy, st, sm;
     double c1, c2, c3, c4;  // cumulative move-type thresholds
-    double att2, dec2;      // 2 / atten, 2 / decay
+    double att2, dec2;      // 2 / atten, 2 / decay (1 / atten, 1 / decay for templates)
     // Line model (the paper's 1-D world): stations at sx[0 .. nsx) on a line
     // (nsy = 1), events (x, t) with y = 0, regions of onset time along the
     // first region axis (wx is the region length in samples, wy = 0).  The
     // host sets rc, atten and decay to infinity there, so every station
     // detects every event with a constant (boxcar) signal variance m^2.
-    int line, pad_line;
+    int line;
+    int tmpl;               // 1: mean-template likelihood (B is an amplitude)
     double tmax;            // longest travel time from the line to a station
     double sx[8];
 };
@@ -169,7 +170,9 @@ __host__ __device__ inline int event_region(const Geo &g, double offx, double of
 
 // Arrival of an event at a station: distance, arrival time, first sample and
 // the variance scale B = A^2 exp(-2 (n0 - a) / decay), so that the variance
-// the event adds at sample n0 + q is B exp(-2 q / decay).
+// the event adds at sample n0 + q is B exp(-2 q / decay).  Under the
+// mean-template likelihood B = A exp(-(n0 - a) / decay) scales the waveform
+// B exp(-q / decay) the event adds to the mean.
 struct Arrival {
     int in;       // d < rc and the window meets the trace
     int n0, n1;   // [n0, n1): affected samples; n0 = ceil(a)
@@ -195,7 +198,7 @@ __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, dou
         ar.n0 = (int)c;
         ar.n1 = ar.n0 + g.ts < g.N ? ar.n0 + g.ts : g.N;
         // A^2 exp(-2 (c - a) / decay) with A = m exp(-d / atten), one exponential
-        ar.B = m * m * exp(-(g.att2 * d + g.dec2 * (c - a)));
+        ar.B = (g.tmpl ? m : m * m) * exp(-(g.att2 * d + g.dec2 * (c - a)));
         ar.in = 1;
     }
     return ar;

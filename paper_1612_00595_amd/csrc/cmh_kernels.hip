@@ -297,6 +297,15 @@ __device__ inline double sample_term(double sigma2, double e0, double dc, double
     return en;
 }
 
+// Mean-template likelihood: one sample's share of sum g (r - g / 2) (to be
+// divided by sigma^2), g the change of the mean and r the residual s - mean
+// before the move; returns the new residual.
+__device__ inline double template_term(double r, double g, double *lin)
+{
+    *lin += g * (r - 0.5 * g);
+    return r - g;
+}
+
 struct MoveHdr {
     int valid, type, n, nseg, S;
     int flags;  // error flags, raised only when the move is consumed
@@ -639,7 +648,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         s_et[s] = ev.t[base + s]; s_em[s] = ev.m[base + s];
         s_id[s] = ev.id[base + s];
     }
-    for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
     if (tid < 8) s_lsx[tid] = slots[slot].g.sx[tid];
     for (int c = 0; c < 2 && 64 * c < g.k; ++c) {
@@ -729,8 +738,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                     sv[q] = 0.0;
                     if ((p * QP + q) * EV < h.S) {
                         const int g0 = gi[q] >= 0 ? gi[q] : 0;
-                        eo[q] = E[ebase + g0];
-                        sv[q] = (double)trace[g0];
+                        eo[q] = E[ebase + g0];  // the residual, under templates
+                        if (!g.tmpl) sv[q] = (double)trace[g0];
                     }
                 }
                 // variance changes from the LDS tables while the loads fly
@@ -745,7 +754,9 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
 #pragma unroll
                 for (int q = 0; q < QP; ++q) {
                     if ((p * QP + q) * EV < h.S && gi[q] >= 0) {
-                        const double en = sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
+                        const double en =
+                            g.tmpl ? template_term(eo[q], dc[q], &lin)
+                                   : sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
                         if (p == 0) {
                             enew[q] = en;
                             gidx[q] = gi[q];
@@ -753,7 +764,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                     }
                 }
             }
-            double part = -0.5 * (log(prod) - lin);
+            double part = g.tmpl ? lin / g.sigma2 : -0.5 * (log(prod) - lin);
             part = wave_sum(part);
             if (lane == 0) s_part[buf][wave] = part;
         }
@@ -812,8 +823,9 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                     for (int q = 0; q < QP; ++q) {
                         if (gi[q] >= 0) {
                             const Seg &a = s_seg[buf][run[q]];
-                            const double en = eo[q] + run_dvar(a, s_T, gi[q] - a.j * g.N);
-                            E[ebase + gi[q]] = en > 0.0 ? en : 0.0;
+                            const double dv = run_dvar(a, s_T, gi[q] - a.j * g.N);
+                            const double en = g.tmpl ? eo[q] - dv : eo[q] + dv;
+                            E[ebase + gi[q]] = g.tmpl || en > 0.0 ? en : 0.0;
                         }
                     }
                 }
@@ -940,8 +952,8 @@ __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace
             sv[q] = 0.0;
             if (base + 64 * q < S) {
                 const int gi = gidx[q] >= 0 ? gidx[q] : 0;
-                eo[q] = E[gi];
-                sv[q] = (double)trace[gi];
+                eo[q] = E[gi];  // the residual, under templates
+                if (!g.tmpl) sv[q] = (double)trace[gi];
             }
         }
 #pragma unroll
@@ -954,14 +966,19 @@ __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace
         }
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q)
-            if (base + 64 * q < S && gidx[q] >= 0)
-                (void)sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
+            if (base + 64 * q < S && gidx[q] >= 0) {
+                if (g.tmpl)
+                    (void)template_term(eo[q], dc[q], &lin);
+                else
+                    (void)sample_term(g.sigma2, eo[q], dc[q], sv[q], &prod, &lin);
+            }
     }
-    return -0.5 * (log(prod) - lin);
+    return g.tmpl ? lin / g.sigma2 : -0.5 * (log(prod) - lin);
 }
 
 // After an acceptance: the new variance over the footprint, written in place.
-// The new variance max(E + change, 0) is the one sample_term used for Delta.
+// The new variance max(E + change, 0) is the one sample_term used for Delta
+// (the new residual E - change under templates).
 __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
                            const SegIndex &six, int nseg, int S, const double *sT, int lane)
 {
@@ -978,8 +995,9 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
         for (int q = 0; q < kWaveQ; ++q)
             if (base + 64 * q < S && gidx[q] >= 0) {
                 const Seg &a = sg[run[q]];
-                const double en = eo[q] + run_dvar(a, sT, gidx[q] - a.j * g.N);
-                E[gidx[q]] = en > 0.0 ? en : 0.0;
+                const double dv = run_dvar(a, sT, gidx[q] - a.j * g.N);
+                const double en = g.tmpl ? eo[q] - dv : eo[q] + dv;
+                E[gidx[q]] = g.tmpl || en > 0.0 ? en : 0.0;
             }
     }
 }
@@ -1053,7 +1071,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         et[s] = ev.t[base + s]; em[s] = ev.m[base + s];
         eid[s] = ev.id[base + s];
     }
-    for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-2.0 * (double)q / g.decay);
+    for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     int flags = 0;
     if (lane == 0) {
         RegionLearned rl;
@@ -1577,7 +1595,10 @@ __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int
 // Exact event variance for every chain, station and sample, optionally
 // written to E, and per-workgroup partial sums of the signal log-likelihood
 // (Section 3: zero-mean Gaussian with variance sigma^2 plus the arriving
-// signals' variances).  One workgroup per (station, tile), blockIdx.y chain.
+// signals' variances).  Under the mean-template likelihood the events' sum
+// is the mean, E the residual trace - mean, and each sample a Gaussian of
+// variance sigma^2 around the mean.  One workgroup per (station, tile),
+// blockIdx.y chain.
 template <typename TraceT>
 __global__ void __launch_bounds__(256)
 k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict__ E, int write,
@@ -1594,7 +1615,7 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
     const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
     const int tid = threadIdx.x;
     int flags = 0;
-    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     const int ne = gather_tile(g, ev, chain, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
     const double l2pi = log(2.0 * M_PI);
     const double null_c = -0.5 * (l2pi + log(g.sigma2));
@@ -1620,6 +1641,12 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
             for (int q = 0; q < ne; ++q) {
                 const int d = nn - s_n0[q];
                 if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+            }
+            if (g.tmpl) {  // e is the mean; E holds the residual
+                const double rr = sv[u] - e;
+                acc += null_c + null_q * (rr * rr);
+                if (write) Erow[nn] = rr;
+                continue;
             }
             const double qv = sv[u] * sv[u];
             if (e > 0.0) {
@@ -1659,7 +1686,8 @@ k_sum_partials(const double *__restrict__ partials, int per_chain, double *__res
 }
 
 // ----------------------------------------------------------------- simulate
-// trace[j][n] = sqrt(sigma^2 + E_j[n]) z_jn, z from Philox under key
+// trace[j][n] = sqrt(sigma^2 + E_j[n]) z_jn (mean-template likelihood:
+// E_j[n] + sigma z_jn, E the sum of waveforms), z from Philox under key
 // (seed, 0x80000001), counter (n / 2, j, 0, 0), Box-Muller (even n cosine,
 // odd n sine).  E gathered from the truth events binned like an event table.
 template <typename TraceT>
@@ -1675,7 +1703,7 @@ k_simulate(Geo g, Events ev, uint32_t seed, TraceT *__restrict__ trace, int *__r
     const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
     const int tid = threadIdx.x;
     int flags = 0;
-    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-2.0 * (double)q / g.decay);
+    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     const int ne = gather_tile(g, ev, 0, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
     const long long row = (long long)j * g.N;
     for (int n2 = n_lo + 2 * tid; n2 < n_hi; n2 += 512) {
@@ -1694,7 +1722,8 @@ k_simulate(Geo g, Events ev, uint32_t seed, TraceT *__restrict__ trace, int *__r
                 const int d = nn - s_n0[q];
                 if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
             }
-            trace[row + nn] = (TraceT)(sqrt(g.sigma2 + e) * z[h]);
+            trace[row + nn] = (TraceT)(g.tmpl ? e + sqrt(g.sigma2) * z[h]
+                                              : sqrt(g.sigma2 + e) * z[h]);
         }
     }
     if (tid == 0 && flags) atomicOr(err, flags);
@@ -1712,6 +1741,17 @@ __global__ void k_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t 
     else
         move_draws(seed, chain, sweep, region, j0 + (uint32_t)q, d);
     for (int c = 0; c < width; ++c) out[(long long)q * width + c] = d[c];
+}
+
+// Residual of an empty world under the mean-template likelihood: the trace
+// itself, copied into every chain's E (chain-major, per_chain elements each).
+template <typename TraceT>
+__global__ void k_residual_init(double *__restrict__ E, const TraceT *__restrict__ trace,
+                                long long per_chain, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        E[q] = (double)trace[q % per_chain];
 }
 
 __global__ void k_fill_f64(double *__restrict__ p, long long n, double v)
@@ -1863,6 +1903,19 @@ hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t 
                         uint32_t j0, int count, int width, double *out, hipStream_t s)
 {
     k_draws<<<(count + 127) / 128, 128, 0, s>>>(seed, chain, sweep, region, j0, count, width, out);
+    return hipGetLastError();
+}
+
+hipError_t residual_init(double *E, const void *trace, int f64, long long per_chain,
+                         long long n, hipStream_t s)
+{
+    const long long nb = (n + 255) / 256;
+    const int blocks = (int)(nb < 65536 ? nb : 65536);
+    if (n <= 0) return hipSuccess;
+    if (f64)
+        k_residual_init<double><<<blocks, 256, 0, s>>>(E, (const double *)trace, per_chain, n);
+    else
+        k_residual_init<float><<<blocks, 256, 0, s>>>(E, (const float *)trace, per_chain, n);
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ hipError_t launch_simulate(const Geo &g, const Events &ev, uint32_t seed, void *
                            int *err, hipStream_t s);
 hipError_t launch_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
                         uint32_t j0, int count, int width, double *out, hipStream_t s);
+hipError_t residual_init(double *E, const void *trace, int f64, long long per_chain,
+                         long long n, hipStream_t s);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t s);
 hipError_t fill_u64(unsigned long long *p, long long n, hipStream_t s);
