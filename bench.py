@@ -15,6 +15,7 @@ sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -59,6 +60,8 @@ def parse():
     ap.add_argument("--learned-sweeps", type=int, default=2000)
     ap.add_argument("--learned-chains", type=int, default=16)
     ap.add_argument("--learned-pairs", type=int, default=10_000_000)
+    ap.add_argument("--no-template", action="store_true",
+                    help="skip the mean-template likelihood on the main workload's shape")
     ap.add_argument("--no-paper-world", action="store_true",
                     help="skip the paper's own 1-D experiment (50 worlds x 5 runs)")
     ap.add_argument("--paper-worlds", type=int, default=50)
@@ -469,7 +472,9 @@ def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
     c3 = sum(smp.read_counters(c) for c in range(w.chains))
     launches = profile_sweeps * smp.ncolors
     avg_ms = float(ms[:smp.ncolors].sum()) / launches
-    tb = 4 if w.trace_dtype == "f32" else 8
+    # the variance model reads the trace and E per footprint sample; the
+    # mean-template model reads only its residual
+    tb = 0 if w.model.tmpl else (4 if w.trace_dtype == "f32" else 8)
     samp_read = int(c3[15] - c1[15])
     samp_written = int(c3[16] - c1[16])
     bytes_per_launch = (samp_read * (tb + 8) + samp_written * 8) / launches
@@ -610,6 +615,28 @@ def main():
         }
         sb.close()
         del traceb
+        torch.cuda.empty_cache()
+    if not args.no_template:
+        # the mean-template likelihood on the main workload's shape: the
+        # state is the residual (8 B read per footprint sample, no trace)
+        wt = dataclasses.replace(w, name=w.name + "-template",
+                                 model=dataclasses.replace(w.model, tmpl=1))
+        trt = chromh.simulate(wt.model, truth, 1000 + wt.seed, wt.trace_dtype, dev)
+        st_ = chromh.ChromaticSampler(wt.model, wt.sampler, trt, chains=1, seed=wt.seed,
+                                      block=block)
+        rt = measure(st_, wt, args.warmup, args.steps, args.profile_sweeps, stream)
+        log(f"[bench] {wt.name}: {rt['value']:.4g} proposals/s, sweep kernel "
+            f"{rt['avg_ms'] * 1e3:.1f} us/launch, {rt['achieved']:.1f} GB/s algorithmic")
+        out["template"] = {
+            "workload": wt.name, "value": rt["value"], "unit": "proposals/s",
+            "ms_per_step": rt["elapsed"] * 1e3 / args.steps, "block": block,
+            "sweep_kernel_us": rt["avg_ms"] * 1e3,
+            "algorithmic_bytes_per_launch": rt["bytes_per_launch"],
+            "bytes_per_sample": "8 read (residual) + 8 written on accept",
+            "achieved_GBps": rt["achieved"], "frac": rt["achieved"] / HBM_PEAK_GBS,
+            "events_after_run": len(st_.read_events(0))}
+        st_.close()
+        del trt
         torch.cuda.empty_cache()
     if not args.no_kernels:
         out["kernels"] = kernel_rates(dev)
