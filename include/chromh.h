@@ -116,6 +116,14 @@ typedef struct {
                                    scout wave, the rest evaluate; for few regions per
                                    colour), or 64: one wave per region, four regions per
                                    workgroup (for many regions per colour); 0 = 256 */
+    int32_t schedule;           /* 0: chromatic (Algorithm 4).  1: naive parallel MH
+                                   (Algorithm 3, the paper's negative control): every region
+                                   in one phase, each evaluating against the phase-start
+                                   state plus its own changes; the variance is then
+                                   recomputed from the merged events.  Naive needs
+                                   n_stations x n_samples <= 2048 (a private copy per
+                                   region in LDS) and runs the block-64 form. */
+    int32_t _pad0;
 } cmh_sampler;
 
 typedef struct {

@@ -40,7 +40,8 @@ class CmhSampler(C.Structure):
                 ("region_capacity", C.c_int32), ("p_birth", C.c_double),
                 ("p_death", C.c_double), ("p_loc", C.c_double), ("p_time", C.c_double),
                 ("p_mag", C.c_double), ("step_xy", C.c_double), ("step_t", C.c_double),
-                ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32)]
+                ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32),
+                ("schedule", C.c_int32), ("_pad0", C.c_int32)]
 
 
 class CmhError(RuntimeError):
@@ -145,7 +146,7 @@ def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
     s.moves_per_region, s.region_capacity = spec.k, spec.cap
     s.p_birth, s.p_death, s.p_loc, s.p_time, s.p_mag = spec.pb, spec.pd, spec.ploc, spec.pt, spec.pm
     s.step_xy, s.step_t, s.step_m = spec.sxy, spec.st, spec.sm
-    s.prior_only, s.block = spec.prior_only, block
+    s.prior_only, s.block, s.schedule = spec.prior_only, block, spec.schedule
     return s
 
 
@@ -233,6 +234,8 @@ class ChromaticSampler:
             model, sampler.gx, sampler.gy, 0.0, 0.0, sampler.dynamic) \
             if sampler.period == 0 else (0, 0, sampler.period,
                                          sampler.period ** (1 if model.line else 2), None)
+        if sampler.schedule == 1:  # naive: every region in one phase
+            self.ncolors = 1
         self._feed = None
         self._log = None
 
@@ -537,5 +540,7 @@ class Batch(ChromaticSampler):
         self.ncolors = max(
             partition_and_color(m, sp.gx, sp.gy, 0.0, 0.0, sp.dynamic)[3] if sp.period == 0
             else sp.period ** (1 if m.line else 2) for m, sp in zip(models, samplers))
+        if samplers[0].schedule == 1:
+            self.ncolors = 1
         self._feed = None
         self._log = None

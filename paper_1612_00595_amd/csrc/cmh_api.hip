@@ -270,6 +270,13 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
+    if (s->schedule != 0 && s->schedule != 1) return fail(CMH_EINVAL, "schedule must be 0 or 1");
+    if (s->schedule == 1) {
+        if ((long long)m->nsx * m->nsy * m->n_samples > cmh::kNaiveMax)
+            return fail(CMH_EINVAL, "the naive schedule needs stations x samples <= 2048");
+        if (s->block != 0 && s->block != 64)
+            return fail(CMH_EINVAL, "the naive schedule runs the block-64 form");
+    }
     int p = 0;
     rc = choose_period(m, s->grid_x, s->grid_y, 0.0, 0.0, s->dynamic, s->period, &p);
     if (rc) return rc;
@@ -318,6 +325,10 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         g->line = 1;
         g->tmax = line_tmax(m);
         for (int j = 0; j < m->nsx; ++j) g->sx[j] = m->station_x[j];
+    }
+    if (s->schedule == 1) {  // Algorithm 3: every region in the one phase
+        g->naive = 1;
+        g->ncolors = 1;
     }
     return CMH_OK;
 }
@@ -379,6 +390,7 @@ struct cmh_state {
     cmh::Learned learned{};  // tab == nullptr: plain births
     // work items: one slot per chain, items (slot << 16) | region
     int nslots = 0;
+    int refresh_max = 0;  // the most (station, tile) blocks of a slot (naive refresh)
     std::vector<cmh::Slot> slots_h;
     cmh::Slot *slots_d = nullptr;
     unsigned *items_all = nullptr;   // every region of every slot
@@ -474,11 +486,13 @@ int32_t upload_slots(cmh_state *st)
         for (int c = 0; c < st->chains; ++c)
             for (int r = 0; r < g.R; ++r) {
                 const int i = r % g.nrx, k = r / g.nrx;
-                if ((i % p) + p * (k % p) == color) col.push_back(((unsigned)c << 16) | (unsigned)r);
+                const int cr = g.naive ? 0 : (i % p) + p * (k % p);
+                if (cr == color) col.push_back(((unsigned)c << 16) | (unsigned)r);
             }
         st->col_n[color] = (int)col.size() - st->col_off[color];
     }
     st->n_all = (int)all.size();
+    st->refresh_max = cmh::refresh_blocks(g);
     HIPCHK(hipMemcpy(st->slots_d, st->slots_h.data(), sizeof(cmh::Slot) * st->slots_h.size(),
                      hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(st->items_all, all.data(), sizeof(unsigned) * all.size(),
@@ -559,7 +573,11 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
     }
     hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
                                      st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
-                                     st->log_first, st->log_n, st->err, st->block, s);
+                                     st->log_first, st->log_n, st->err, st->block,
+                                     st->g.naive != 0, s);
+    if (!e && st->g.naive)  // the merged events' variance after the single naive phase
+        e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
+                                      st->f64, st->err, s);
     if (e || st->rec == nullptr || color != st->g.ncolors - 1) return e;
     return cmh::launch_record(st->slots_d, st->nslots, st->cur, st->sweep_ctr, st->rec,
                               st->rec_first, st->rec_n, st->rec_max, s);
@@ -610,7 +628,7 @@ int32_t build_graphs(cmh_state *st)
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, int> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int, int, int, int, int, int, int>, int> g_tune_cache;
 
 }  // namespace
 
@@ -698,7 +716,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     st->chains = n_chains;
     st->f64 = trace_dtype == CMH_F64;
     st->trace = trace_dev;
-    st->block = sampler->block ? sampler->block : 256;
+    st->block = g.naive ? 64 : (sampler->block ? sampler->block : 256);
     carve_state(g, n_chains, (char *)workspace_dev, st);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
@@ -965,8 +983,12 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
     if (st->feed || st->logp) return fail(CMH_EINVAL, "detach feed and log before tuning");
     const Geo &g = st->g;
+    if (g.naive) {  // one form only
+        st->block = 64;
+        return CMH_OK;
+    }
     const auto key = std::make_tuple(g.nsx, g.nsy, g.N, g.gx, g.gy, g.k, g.cap, st->chains,
-                                     st->f64, g.dynamic);
+                                     st->f64, g.dynamic, g.line * 2 + g.tmpl);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -1168,8 +1190,8 @@ int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *sample
         if (rc) return rc;
         if (P->g[q].R > 65535) return fail(CMH_EINVAL, "at most 65535 regions per instance");
         if (P->g[q].k != P->g[0].k || P->g[q].dynamic != P->g[0].dynamic ||
-            samplers[q].block != samplers[0].block)
-            return fail(CMH_EINVAL, "instances of a batch share k, dynamic and block");
+            samplers[q].block != samplers[0].block || P->g[q].naive != P->g[0].naive)
+            return fail(CMH_EINVAL, "instances of a batch share k, dynamic, block and schedule");
     }
     P->head = P->g[0];
     for (int q = 0; q < n; ++q) P->head.ncolors = std::max(P->head.ncolors, P->g[q].ncolors);
@@ -1246,7 +1268,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
     st->chains = n_instances;
     st->nslots = n_instances;
     st->f64 = trace_dtype == CMH_F64;
-    st->block = samplers[0].block ? samplers[0].block : 256;
+    st->block = P.head.naive ? 64 : (samplers[0].block ? samplers[0].block : 256);
     st->slots_h.resize(n_instances);
     carve_batch(P, (char *)workspace_dev, &st->slots_h, &st->sweep_ctr, &st->err, &st->slots_d,
                 &st->items_all, &st->items_col);
@@ -1268,6 +1290,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
         }
         if (!e) e = cmh::fill_u64(sl.stats, cmh::kStats, s);
         for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)q << 16) | (unsigned)r);
+        st->refresh_max = std::max(st->refresh_max, cmh::refresh_blocks(g));
     }
     st->col_off.assign(P.head.ncolors, 0);
     st->col_n.assign(P.head.ncolors, 0);
@@ -1277,7 +1300,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
             const Geo &g = st->slots_h[q].g;
             for (int r = 0; r < g.R; ++r) {
                 const int i = r % g.nrx, k = r / g.nrx;
-                if ((i % g.period) + g.period * (k % g.period) == color)
+                if ((g.naive ? 0 : (i % g.period) + g.period * (k % g.period)) == color)
                     col.push_back(((unsigned)q << 16) | (unsigned)r);
             }
         }

@@ -20,6 +20,7 @@ constexpr int kTile = 8192;          // samples per workgroup in streaming kerne
 constexpr int kRefreshU = 8;         // samples per thread per step of a streaming loop
 constexpr int kMaxTileEvents = 640;  // events reaching one station tile
 constexpr int kMaxRegSta = 16;       // stations of one region, learned births
+constexpr int kNaiveMax = 2048;      // stations x samples of an instance, naive schedule
 
 enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16 };
 
@@ -47,6 +48,7 @@ struct Geo {
     // detects every event with a constant (boxcar) signal variance m^2.
     int line;
     int tmpl;               // 1: mean-template likelihood (B is an amplitude)
+    int naive, pad_naive;   // 1: the naive schedule (Algorithm 3), one phase
     double tmax;            // longest travel time from the line to a station
     double sx[8];
 };

@@ -1002,8 +1002,13 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
     }
 }
 
-template <typename TraceT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// NAIVE: the naive parallel schedule of Algorithm 3, every region in one
+// phase.  Each wave then evaluates against a private copy of the variance
+// (the phase-start state plus its own region's changes, as the regions of a
+// naive phase see each other), held in LDS; the shared variance is never
+// written and is recomputed from the merged events after the phase.
+template <typename TraceT, bool NAIVE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : 3)))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
              long long log_first, long long log_n, int *__restrict__ err)
@@ -1072,6 +1077,13 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         eid[s] = ev.id[base + s];
     }
     for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
+    double *Ew = E;  // the variance (or residual) this wave reads and writes
+    if constexpr (NAIVE) {
+        __shared__ double s_pe[4][kNaiveMax];
+        for (int q = lane; q < g.nsta * g.N; q += 64) s_pe[wv][q] = E[q];
+        __builtin_amdgcn_wave_barrier();
+        Ew = s_pe[wv];
+    }
     int flags = 0;
     if (lane == 0) {
         RegionLearned rl;
@@ -1123,7 +1135,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         const bool evaluate = h.valid && !g.prior_only;
         double delta = 0.0;
         if (evaluate)
-            delta = wave_sum(wave_delta_part<TraceT>(g, trace, E, s_seg[wv][0], s_six[wv][0],
+            delta = wave_sum(wave_delta_part<TraceT>(g, trace, Ew, s_seg[wv][0], s_six[wv][0],
                                                      h.nseg, h.S, sT, lane));
         double la;
         if (h.type == 0)
@@ -1156,7 +1168,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         if (accept) {
             if (!g.prior_only)
-                wave_write(g, E, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
+                wave_write(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
             if (lane == 0) {
                 cnt[3 * h.type + 2]++;
                 cnt[16] += (unsigned long long)h.S;
@@ -1668,6 +1680,44 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
     }
 }
 
+// After a naive phase (Algorithm 3): every slot's variance (the residual,
+// under templates) recomputed from its merged events, as k_refresh does for
+// one instance.  blockIdx.y slot, blockIdx.x (station, tile) of that slot;
+// the slot's constants are staged in LDS (station positions are indexed).
+template <typename TraceT>
+__global__ void __launch_bounds__(256)
+k_refresh_slots(const Slot *__restrict__ slots, int par, int *__restrict__ err)
+{
+    __shared__ Geo s_g;
+    __shared__ int s_n0[kMaxTileEvents];
+    __shared__ double s_B[kMaxTileEvents];
+    __shared__ double s_T[kMaxTs];
+    __shared__ int s_cnt;
+    const int slot = blockIdx.y, tid = threadIdx.x;
+    if (tid == 0) s_g = slots[slot].g;
+    __syncthreads();
+    const Geo &g = s_g;
+    const int tiles = (g.N + kTile - 1) / kTile;
+    if ((int)blockIdx.x >= g.nsta * tiles) return;  // the slot has fewer tiles (whole block)
+    const int j = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
+    const Events ev = slots[slot].ev[par];
+    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+    double *__restrict__ Erow = slots[slot].E + (long long)j * g.N;
+    int flags = 0;
+    for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
+    const int ne = gather_tile(g, ev, 0, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
+    for (int nn = n_lo + tid; nn < n_hi; nn += 256) {
+        double e = 0.0;
+        for (int q = 0; q < ne; ++q) {
+            const int d = nn - s_n0[q];
+            if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+        }
+        Erow[nn] = g.tmpl ? (double)trace[(long long)j * g.N + nn] - e : e;
+    }
+    if (tid == 0 && flags) atomicOr(err, flags);
+}
+
 // Sums each chain's partials in a fixed order (deterministic result).
 __global__ void __launch_bounds__(256)
 k_sum_partials(const double *__restrict__ partials, int per_chain, double *__restrict__ out)
@@ -1782,14 +1832,20 @@ __global__ void k_advance_sweep(long long *p) { *p += 1; }
 template <typename TraceT>
 static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
                                  const long long *sweep_ptr, double *logp, long long log_first,
-                                 long long log_n, int *err, int block, hipStream_t s)
+                                 long long log_n, int *err, int block, bool naive, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+    if (naive) {
+        k_sweep_wave<TraceT, true><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
+                                                                    sweep_ptr, logp, log_first,
+                                                                    log_n, err);
+        return hipGetLastError();
+    }
     switch (block) {
     case 64:  // one wave per work item, four per workgroup
-        k_sweep_wave<TraceT><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
-                                                              sweep_ptr, logp, log_first, log_n,
-                                                              err);
+        k_sweep_wave<TraceT, false><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
+                                                                     sweep_ptr, logp, log_first,
+                                                                     log_n, err);
         break;
     case 512:
         k_sweep_color<TraceT, 512><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
@@ -1809,13 +1865,25 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
 
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
-                        long long log_n, int *err, int block, hipStream_t s)
+                        long long log_n, int *err, int block, bool naive, hipStream_t s)
 {
     if (f64)
         return launch_sweep_t<double>(slots, items, nitems, par, sweep_ptr, logp, log_first,
-                                      log_n, err, block, s);
+                                      log_n, err, block, naive, s);
     return launch_sweep_t<float>(slots, items, nitems, par, sweep_ptr, logp, log_first, log_n,
-                                 err, block, s);
+                                 err, block, naive, s);
+}
+
+hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
+                                int *err, hipStream_t s)
+{
+    if (nslots <= 0 || max_blocks <= 0) return hipSuccess;
+    const dim3 grid(max_blocks, nslots);
+    if (f64)
+        k_refresh_slots<double><<<grid, 256, 0, s>>>(slots, par, err);
+    else
+        k_refresh_slots<float><<<grid, 256, 0, s>>>(slots, par, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
