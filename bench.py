@@ -231,11 +231,12 @@ def learned_study(args, dev):
 def paper_world_study(args, dev):
     """Section 5's experiment on the paper's own 1-D world (four stations on
     a line, T = 240, Section 4.1's time partition): worlds from the model
-    (seeds 2000, 2001, ...), several runs each, under three schedules run as
-    one batch of every (world, run) chain each: serial MH (one region,
-    2000 moves per sweep), chromatic static and chromatic dynamic (four onset
-    regions, two colours, k = 500 moves per region per phase, so the same
-    2000 moves per sweep).  Every state is recorded on the device; precision,
+    (seeds 2000, 2001, ...), several runs each, under the paper's four
+    schedules, each run as one batch of every (world, run) chain: serial MH
+    (one region, 2000 moves per sweep), naive parallel MH (Algorithm 3: four
+    onset regions in one phase), chromatic static and chromatic dynamic (four
+    onset regions, two colours), k = 500 moves per region per phase, so the
+    same 2000 moves per sweep.  Every state is recorded on the device; precision,
     recall, F1 and location error (Section 5's matching, 12 units in space and
     time) against sweeps and wall time, and 95% bootstrap intervals over worlds
     of the final values.  The oracle runs the same schedules on two worlds for
@@ -249,6 +250,7 @@ def paper_world_study(args, dev):
     from paper_1612_00595_amd import chromh, metrics as M, workloads as W
     spec = W.PAPER1D_MODEL
     scheds = {"serial": dataclasses.replace(W.PAPER1D_SAMPLER, gx=1, k=2000),
+              "naive": dataclasses.replace(W.PAPER1D_SAMPLER, schedule=1),
               "chromatic_static": W.PAPER1D_SAMPLER,
               "chromatic_dynamic": dataclasses.replace(W.PAPER1D_SAMPLER, dynamic=1)}
     nw, nr, S = args.paper_worlds, args.paper_runs, args.paper_sweeps
@@ -272,7 +274,7 @@ def paper_world_study(args, dev):
         # kernel form by a short trial (few work items per colour favour the
         # latency form, many the wave form)
         trial = {}
-        for block in (64, 128, 256):
+        for block in ((64,) if sp.schedule == 1 else (64, 128, 256)):
             b = batch(sp, block)
             b.run_sweeps(0, 1)
             torch.cuda.synchronize()

@@ -8,8 +8,9 @@
  * region of one colour while the other regions are held at their values from
  * the start of the phase.  Section 4.3.2 (dynamic colouring) redraws the
  * partition offset after every full round of colours.  Algorithm 3 (naive
- * parallel MH) is the same phase with every region in one colour; it is kept
- * only as a negative control.
+ * parallel MH) runs every region in one phase, each region accepting against
+ * the posterior of its own events alone; it is kept only as a negative
+ * control.
  *
  * The log-likelihood change of a move is evaluated directly: for every sample
  * the move can affect, the model variance is summed from scratch over the
@@ -784,13 +785,19 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
 
 /* One colour phase of Algorithm 4: every region of the colour runs k moves;
  * the other regions are held at the phase-start snapshot.  With the naive
- * schedule (Algorithm 3) every region belongs to the phase.
+ * schedule (Algorithm 3) every region belongs to the phase and each accepts
+ * against the posterior of its own events alone (the algorithm's pi(x_m)):
+ * the other regions' events are invisible to it.
  * feed (optional): draws [region][k][8] ([16] with learned births); log
  * (optional): [region][k][4]. */
 int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double *feed,
                         double *log_out)
 {
-    build_snapshot(c);
+    if (c->sp.schedule == ORC_SCHED_NAIVE) {
+        for (int64_t j = 0; j < c->nsta; ++j) c->snap[j].n = 0;
+    } else {
+        build_snapshot(c);
+    }
     for (int64_t r = 0; r < c->nreg; ++r) {
         if (c->sp.schedule == ORC_SCHED_CHROMATIC && c->color[r] != color) continue;
         double x0, x1, y0, y1;

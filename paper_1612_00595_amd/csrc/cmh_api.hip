@@ -391,6 +391,7 @@ struct cmh_state {
     // work items: one slot per chain, items (slot << 16) | region
     int nslots = 0;
     int refresh_max = 0;  // the most (station, tile) blocks of a slot (naive refresh)
+    int naive_elems = 0;  // naive schedule: the largest stations x samples of a slot
     std::vector<cmh::Slot> slots_h;
     cmh::Slot *slots_d = nullptr;
     unsigned *items_all = nullptr;   // every region of every slot
@@ -493,6 +494,7 @@ int32_t upload_slots(cmh_state *st)
     }
     st->n_all = (int)all.size();
     st->refresh_max = cmh::refresh_blocks(g);
+    st->naive_elems = g.nsta * g.N;
     HIPCHK(hipMemcpy(st->slots_d, st->slots_h.data(), sizeof(cmh::Slot) * st->slots_h.size(),
                      hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(st->items_all, all.data(), sizeof(unsigned) * all.size(),
@@ -574,7 +576,7 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
     hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
                                      st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
                                      st->log_first, st->log_n, st->err, st->block,
-                                     st->g.naive != 0, s);
+                                     st->g.naive ? st->naive_elems : 0, s);
     if (!e && st->g.naive)  // the merged events' variance after the single naive phase
         e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
                                       st->f64, st->err, s);
@@ -1291,6 +1293,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
         if (!e) e = cmh::fill_u64(sl.stats, cmh::kStats, s);
         for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)q << 16) | (unsigned)r);
         st->refresh_max = std::max(st->refresh_max, cmh::refresh_blocks(g));
+        st->naive_elems = std::max(st->naive_elems, g.nsta * g.N);
     }
     st->col_off.assign(P.head.ncolors, 0);
     st->col_n.assign(P.head.ncolors, 0);

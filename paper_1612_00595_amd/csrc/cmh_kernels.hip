@@ -1003,15 +1003,15 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
 }
 
 // NAIVE: the naive parallel schedule of Algorithm 3, every region in one
-// phase.  Each wave then evaluates against a private copy of the variance
-// (the phase-start state plus its own region's changes, as the regions of a
-// naive phase see each other), held in LDS; the shared variance is never
-// written and is recomputed from the merged events after the phase.
+// phase, each accepting against the posterior of its own events alone.  Each
+// wave then evaluates against a private variance in LDS built from its own
+// events; the shared variance is never written and is recomputed from the
+// merged events after the phase.
 template <typename TraceT, bool NAIVE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : 3)))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
-             long long log_first, long long log_n, int *__restrict__ err)
+             long long log_first, long long log_n, int *__restrict__ err, int naive_elems)
 {
     __shared__ double s_log[kMaxCap + 2];
     __shared__ double s_T[4][kMaxTs];
@@ -1077,14 +1077,27 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         eid[s] = ev.id[base + s];
     }
     for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
+    int flags = 0;
     double *Ew = E;  // the variance (or residual) this wave reads and writes
     if constexpr (NAIVE) {
-        __shared__ double s_pe[4][kNaiveMax];
-        for (int q = lane; q < g.nsta * g.N; q += 64) s_pe[wv][q] = E[q];
+        // Algorithm 3: the region accepts against its own events alone, so
+        // its private variance starts from no event (the trace itself as the
+        // residual, under templates) and takes in each of its events in turn
+        extern __shared__ double s_pe[];  // 4 x naive_elems, sized at launch
+        double *pe = s_pe + (long long)wv * naive_elems;
+        for (int q = lane; q < g.nsta * g.N; q += 64) pe[q] = g.tmpl ? (double)trace[q] : 0.0;
         __builtin_amdgcn_wave_barrier();
-        Ew = s_pe[wv];
+        for (int q = 0; q < n; ++q) {
+            int nseg = 0, S = 0, fl = 0;
+            footprint(g, lane, false, 0.0, 0.0, 0.0, 0.0, true, ex[q], ey[q], et[q], em[q],
+                      s_seg[wv][0], &s_six[wv][0], g.sx, &nseg, &S, &fl);
+            __builtin_amdgcn_wave_barrier();
+            if (__ballot(fl != 0) != 0ull) flags |= kFlagSeg;
+            else wave_write(g, pe, s_seg[wv][0], s_six[wv][0], nseg, S, sT, lane);
+            __builtin_amdgcn_wave_barrier();
+        }
+        Ew = pe;
     }
-    int flags = 0;
     if (lane == 0) {
         RegionLearned rl;
         rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
@@ -1832,20 +1845,24 @@ __global__ void k_advance_sweep(long long *p) { *p += 1; }
 template <typename TraceT>
 static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
                                  const long long *sweep_ptr, double *logp, long long log_first,
-                                 long long log_n, int *err, int block, bool naive, hipStream_t s)
+                                 long long log_n, int *err, int block, int naive_elems,
+                                 hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    if (naive) {
-        k_sweep_wave<TraceT, true><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
-                                                                    sweep_ptr, logp, log_first,
-                                                                    log_n, err);
+    if (naive_elems > 0) {
+        const size_t lds = (size_t)4 * naive_elems * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void *)k_sweep_wave<TraceT, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_sweep_wave<TraceT, true><<<(nitems + 3) / 4, 256, lds, s>>>(
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, naive_elems);
         return hipGetLastError();
     }
     switch (block) {
     case 64:  // one wave per work item, four per workgroup
         k_sweep_wave<TraceT, false><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
                                                                      sweep_ptr, logp, log_first,
-                                                                     log_n, err);
+                                                                     log_n, err, 0);
         break;
     case 512:
         k_sweep_color<TraceT, 512><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
@@ -1865,13 +1882,13 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
 
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
-                        long long log_n, int *err, int block, bool naive, hipStream_t s)
+                        long long log_n, int *err, int block, int naive_elems, hipStream_t s)
 {
     if (f64)
         return launch_sweep_t<double>(slots, items, nitems, par, sweep_ptr, logp, log_first,
-                                      log_n, err, block, naive, s);
+                                      log_n, err, block, naive_elems, s);
     return launch_sweep_t<float>(slots, items, nitems, par, sweep_ptr, logp, log_first, log_n,
-                                 err, block, naive, s);
+                                 err, block, naive_elems, s);
 }
 
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
