@@ -444,12 +444,20 @@ def kernel_rates(dev):
     t, head = timed(forward_all, 2)
     out["mdn_forward"] = {"rows": na, "seconds": t, "TFLOPs": na * MDN_FWD_FLOP / t / 1e12,
                           "mfma_frac": na * MDN_FWD_FLOP / t / 1e12 / BF16_PEAK_TFLOPS,
-                          "bound": "mfma (bf16, fp32 accumulate)"}
+                          "bound": "mfma (bf16, fp32 accumulate)",
+                          "kind": "layer by layer (training path: pre-activations kept)"}
+    # the fused inference kernel the anchor tables use: activations stay in
+    # LDS, one launch over every anchor
+    t, head = timed(lambda: net.infer(X), 2)
+    out["mdn_infer"] = {"rows": na, "seconds": t, "TFLOPs": na * MDN_FWD_FLOP / t / 1e12,
+                        "mfma_frac": na * MDN_FWD_FLOP / t / 1e12 / BF16_PEAK_TFLOPS,
+                        "bound": "mfma (bf16, fp32 accumulate)", "kind": "fused, one kernel"}
     t, _ = timed(lambda: chromh.mixture_table(m, head), 2)
     out["mixture_table"] = {"rows": na, "seconds": t, "rows_per_s": na / t}
     log(f"[bench] kernels: refresh {out['refresh']['GBps']:.0f} GB/s, simulate "
         f"{out['simulate']['GBps_written']:.0f} GB/s written, features {na / out['anchor_features']['seconds']:.3g} "
-        f"anchors/s, network forward {out['mdn_forward']['TFLOPs']:.1f} TFLOP/s")
+        f"anchors/s, network forward {out['mdn_forward']['TFLOPs']:.1f} TFLOP/s, fused inference "
+        f"{out['mdn_infer']['TFLOPs']:.1f} TFLOP/s")
     del X, wts, head, trace, net
     return out
 

@@ -366,6 +366,14 @@ int32_t cmh_mdn_work_bytes(int32_t rows, size_t *bytes);
 int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
                         void *work_dev, size_t work_bytes, void *hip_stream);
 
+/* The same head outputs from one fused kernel for inference (anchor tables):
+ * no work buffer, the hidden activations never leave LDS, only
+ * out_dev[rows][64] (FP32) is written.  Hidden activations are rounded to
+ * BF16 exactly as cmh_mdn_forward stores them.  x_dev 16-byte aligned;
+ * rows in 1..2^31 - 1. */
+int32_t cmh_mdn_infer(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
+                      void *hip_stream);
+
 /* Mean mixture negative log-likelihood of targets z_dev[rows][3] and its
  * gradient w.r.t. every FP32 parameter (grad_dev[n_params]); per-row losses
  * into loss_dev[rows] when not NULL.  Mixture components are untruncated

@@ -56,6 +56,7 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_get_block", "cmh_autotune", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
            "cmh_move_draws", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
+           "cmh_mdn_infer",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
            "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init"]
@@ -106,6 +107,7 @@ def lib():
         "cmh_mdn_get_params": ([P, P], I32),
         "cmh_mdn_work_bytes": ([I32, P], I32),
         "cmh_mdn_forward": ([P, P, I32, P, P, C.c_size_t, P], I32),
+        "cmh_mdn_infer": ([P, P, I32, P, P], I32),
         "cmh_mdn_gradients": ([P, P, P, I32, P, P, P, C.c_size_t, P], I32),
         "cmh_mdn_train_step": ([P, P, P, I32, I32, C.c_float, P, P, C.c_size_t, P], I32),
         "cmh_mdn_pairs": ([P, U32, I64, I32, P, P, P], I32),
@@ -440,6 +442,14 @@ class MDN:
         w = self.work(rows)
         check(lib().cmh_mdn_forward(_ptr(self.params), _ptr(X), rows, _ptr(out), _ptr(w),
                                     w.numel(), _stream()))
+        return out
+
+    def infer(self, X):
+        """The head outputs of forward() from the fused inference kernel."""
+        import torch
+        rows = X.shape[0]
+        out = torch.empty((rows, 64), dtype=torch.float32, device=self.device)
+        check(lib().cmh_mdn_infer(_ptr(self.params), _ptr(X), rows, _ptr(out), _stream()))
         return out
 
     def gradients(self, X, Z):

@@ -1627,6 +1627,19 @@ int32_t cmh_mdn_forward(const void *params_dev, const void *x_dev, int32_t rows,
     return CMH_OK;
 }
 
+int32_t cmh_mdn_infer(const void *params_dev, const void *x_dev, int32_t rows, float *out_dev,
+                      void *hip_stream)
+{
+    if (rows < 1) return fail(CMH_EINVAL, "rows must be positive");
+    if (!params_dev || !x_dev || !out_dev) return fail(CMH_EINVAL, "NULL argument");
+    int32_t rc = check_aligned(x_dev, "x_dev");
+    if (rc) return rc;
+    const MdnBlob b = mdn_blob(params_dev);
+    HIPCHK(cmh::mdn_infer(b.params, b.hcopy, (const __bf16 *)x_dev, rows, out_dev,
+                          (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
 int32_t cmh_mdn_gradients(const void *params_dev, const void *x_dev, const float *z_dev,
                           int32_t rows, float *grad_dev, float *loss_dev, void *work_dev,
                           size_t work_bytes, void *hip_stream)

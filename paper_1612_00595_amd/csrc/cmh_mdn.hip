@@ -614,6 +614,159 @@ hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s)
     return hipSuccess;
 }
 
+// ------------------------------------------------------- fused inference
+// The whole network for a tile of kInfRows rows in one workgroup: layer 1
+// streams the features and every layer streams its BF16 weights through
+// double-buffered LDS chunks of 32 inputs, the hidden activations stay in
+// LDS between layers (GELU(Z + b) rounded to BF16, as the layer-by-layer
+// forward stores them), and only the head output (Z + b, fp32) goes to HBM.
+// Eight waves as 4 x 2: a wave owns 32 rows x 128 outputs of a hidden layer
+// (16 MFMA 16x16x32 tiles) and 32 rows x 32 outputs of the head; two waves
+// per SIMD hide each other's LDS and barrier latency.
+constexpr int kInfRows = 128;
+// Offsets of layer l's BF16 weights and FP32 bias in the parameter blobs (the
+// layout mdn_layout describes), as constants so that no layout object lives
+// in the kernel's private memory.
+__host__ __device__ constexpr long mdn_fin(int l) { return l == 0 ? kMdnIn : kMdnHid; }
+__host__ __device__ constexpr long mdn_fout(int l) { return l == 3 ? kMdnOutPad : kMdnHid; }
+__host__ __device__ constexpr long mdn_wh_off(int l)
+{
+    return (l > 0 ? (long)kMdnIn * kMdnHid : 0) + (l > 1 ? (long)(l - 1) * kMdnHid * kMdnHid : 0);
+}
+// the FP32 blob holds each layer's weights followed by its bias; the BF16 copy
+// holds the weights alone
+__host__ __device__ constexpr long mdn_b_off(int l)
+{
+    return mdn_wh_off(l) + (long)l * kMdnHid + mdn_fin(l) * mdn_fout(l);
+}
+constexpr int kInfPitch = kMdnHid + 8;  // LDS row pitch of the activations (bank spread)
+
+__global__ void __launch_bounds__(512)
+k_mdn_infer(int M, const __bf16 *__restrict__ X, const __bf16 *__restrict__ W,
+            const float *__restrict__ params, float *__restrict__ out)
+{
+    extern __shared__ __attribute__((aligned(16))) __bf16 s_inf[];
+    __bf16 (*sH)[kInfPitch] = (__bf16 (*)[kInfPitch])s_inf;                       // 128 x 264
+    __bf16 (*sA)[kInfRows][40] = (__bf16 (*)[kInfRows][40])(s_inf + kInfRows * kInfPitch);
+    __bf16 (*sB)[kMdnHid][40] = (__bf16 (*)[kMdnHid][40])(s_inf + kInfRows * kInfPitch +
+                                                          2 * kInfRows * 40);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * kInfRows;
+    const int wr = (wave >> 1) * 32;
+    const __bf16 zero = (__bf16)0.0f;
+    const bf16x8 z8 = (bf16x8){zero, zero, zero, zero, zero, zero, zero, zero};
+    const int kk = 8 * (lane >> 4);
+
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {  // unrolled: every layer's shape is a constant
+        const int K = l == 0 ? kMdnIn : kMdnHid;
+        const int NO = l == 3 ? kMdnOutPad : kMdnHid;
+        const int wc = (wave & 1) * (NO / 2);
+        const __bf16 *Wl = W + mdn_wh_off(l);  // [NO][K]
+        constexpr int FA = 2;
+        const int FB = NO / 32;          // 8 hidden, 2 head
+        f32x4 acc[FA][8];
+#pragma unroll
+        for (int a = 0; a < FA; ++a)
+#pragma unroll
+            for (int b = 0; b < 8; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // chunk loads: W rows (NO x 32), and for layer 1 the feature rows
+        bf16x8 rb[2], ra;
+        auto load = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int v = tid + 512 * u, n = v >> 2;
+                rb[u] = n < NO ? *(const bf16x8 *)&Wl[(long)n * K + k0 + 8 * (v & 3)] : z8;
+            }
+            if (l == 0) {
+                const int r = tid >> 2, gr = r0 + r;
+                ra = gr < M ? *(const bf16x8 *)&X[(long)gr * kMdnIn + k0 + 8 * (tid & 3)] : z8;
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int v = tid + 512 * u, n = v >> 2;
+                if (n < NO) *(bf16x8 *)&sB[buf][n][8 * (v & 3)] = rb[u];
+            }
+            if (l == 0) *(bf16x8 *)&sA[buf][tid >> 2][8 * (tid & 3)] = ra;
+        };
+        int cur = 0;
+        load(0);
+        store(0);
+        __syncthreads();
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            const bool more = k0 + 32 < K;
+            if (more) load(k0 + 32);
+            bf16x8 fa[FA];
+#pragma unroll
+            for (int a = 0; a < FA; ++a) {
+                const int row = wr + 16 * a + (lane & 15);
+                fa[a] = l == 0 ? *(const bf16x8 *)&sA[cur][row][kk]
+                               : *(const bf16x8 *)&sH[row][k0 + kk];
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < FB) {  // one weight fragment live at a time
+                    const bf16x8 fb = *(const bf16x8 *)&sB[cur][wc + 16 * b + (lane & 15)][kk];
+#pragma unroll
+                    for (int a = 0; a < FA; ++a)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a][b],
+                                                                           0, 0, 0);
+                }
+            }
+            if (more) store(cur ^ 1);
+            __syncthreads();  // also: every read of sH by this layer is done
+            cur ^= 1;
+        }
+        const float *bias = params + mdn_b_off(l);
+        if (l < 3) {  // GELU(Z + b) as BF16 into the activations
+#pragma unroll
+            for (int a = 0; a < FA; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = wr + 16 * a + 4 * (lane >> 4) + v;
+                        const int j = wc + 16 * b + (lane & 15);
+                        sH[i][j] = (__bf16)gelu_f(acc[a][b][v] + bias[j]);
+                    }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int a = 0; a < FA; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = r0 + wr + 16 * a + 4 * (lane >> 4) + v;
+                        const int j = wc + 16 * b + (lane & 15);
+                        if (i < M) out[(long)i * kMdnOutPad + j] = acc[a][b][v] + bias[j];
+                    }
+        }
+    }
+}
+
+size_t mdn_infer_lds()
+{
+    return sizeof(__bf16) * ((size_t)kInfRows * kInfPitch + 2 * kInfRows * 40 + 2 * kMdnHid * 40);
+}
+
+hipError_t mdn_infer(const float *params, const __bf16 *hcopy, const __bf16 *X, int M, float *O,
+                     hipStream_t s)
+{
+    if (M <= 0) return hipSuccess;
+    const MdnLayout L = mdn_layout();
+    for (int l = 0; l < 4; ++l)
+        if (L.Wh[l] != mdn_wh_off(l) || L.b[l] != mdn_b_off(l)) return hipErrorInvalidValue;
+    const size_t lds = mdn_infer_lds();
+    hipError_t e = hipFuncSetAttribute((const void *)k_mdn_infer,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_mdn_infer<<<(M + kInfRows - 1) / kInfRows, 512, lds, s>>>(M, X, hcopy, params, O);
+    return hipGetLastError();
+}
+
 // Forward pass for M rows of features.  Buffers: Z[l] fp32 pre-activations
 // and A[l] BF16 activations of the three hidden layers, O fp32 head output.
 hipError_t mdn_forward(const float *params, const __bf16 *hcopy, const __bf16 *X, int M,

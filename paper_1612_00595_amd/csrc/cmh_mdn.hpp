@@ -42,6 +42,10 @@ struct MdnLayout {
     long np, nh;
 };
 MdnLayout mdn_layout();
+// The whole network for M rows of features in one fused kernel (inference):
+// head output O [M][64] fp32 only.
+hipError_t mdn_infer(const float *params, const __bf16 *hcopy, const __bf16 *X, int M, float *O,
+                     hipStream_t s);
 
 struct MdnBuffers {
     float *Z[3];      // pre-activations, M x 256

@@ -61,7 +61,7 @@ def anchor_table(net: "chromh.MDN", model: ModelSpec, trace, chunk: int = 65536)
     for first in range(0, na, chunk):
         cnt = min(chunk, na - first)
         X, w = chromh.anchor_features(model, trace, first, cnt)
-        head = net.forward(X)
+        head = net.infer(X)
         table[first:first + cnt] = chromh.mixture_table(model, head, first)
         weights[first:first + cnt] = w
     return table, weights, ntau
