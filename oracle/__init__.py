@@ -22,11 +22,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 _SOURCES = ["orc_model.c", "orc_sampler.c"]
 
-BIRTH, DEATH, LOC, TIME, MAG = range(5)
+BIRTH, DEATH, LOC, TIME, MAG, ARR, JOINT = range(7)
+ARR_TRUNC = 4.0  # the arrival-time jitter is truncated at this many sds
 SCHED_CHROMATIC, SCHED_NAIVE = 0, 1
 
 EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("t", "<f8"), ("m", "<f8"),
-                        ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4")])
+                        ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4"),
+                        ("da", "<f8", (8,))])
 
 
 class Model(C.Structure):
@@ -35,7 +37,8 @@ class Model(C.Structure):
                 ("vel", C.c_double), ("decay", C.c_double), ("ts", C.c_int32),
                 ("_pad0", C.c_int32), ("rc", C.c_double), ("lam", C.c_double),
                 ("mmin", C.c_double), ("mrate", C.c_double), ("line", C.c_int32),
-                ("tmpl", C.c_int32), ("xmax", C.c_double), ("sta_x", C.c_double * 8)]
+                ("tmpl", C.c_int32), ("xmax", C.c_double), ("sta_x", C.c_double * 8),
+                ("arr_sd", C.c_double)]
 
 
 class Sampler(C.Structure):
@@ -46,7 +49,8 @@ class Sampler(C.Structure):
                 ("st", C.c_double), ("sm", C.c_double), ("prior_only", C.c_int32),
                 ("schedule", C.c_int32), ("lattice", C.c_int32), ("kx", C.c_int32),
                 ("ky", C.c_int32), ("kt", C.c_int32), ("km", C.c_int32),
-                ("_pad1", C.c_int32), ("hm", C.c_double)]
+                ("_pad1", C.c_int32), ("hm", C.c_double), ("pa", C.c_double),
+                ("pj", C.c_double), ("sa", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -125,6 +129,8 @@ def lib():
         L.orc_chain_set_learned.argtypes = [P, P, P, C.c_int32, C.c_double]
         L.orc_chain_set_learned.restype = C.c_int32
         L.orc_move_draws16.argtypes = [C.c_uint32] * 5 + [P]
+        L.orc_move_draws_arr.argtypes = [C.c_uint32] * 5 + [P]
+        L.orc_line_fit.argtypes = [P, P, P, P]
         L.orc_chain_learned_q.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_double]
         L.orc_chain_learned_q.restype = C.c_double
         L.orc_chain_learned_draw.argtypes = [P, C.c_int32, P, P]
@@ -151,6 +157,7 @@ def make_model(**kw) -> Model:
     m.line = kw.get("line", 0)
     m.tmpl = kw.get("tmpl", 0)
     m.xmax = kw.get("xmax", 0.0)
+    m.arr_sd = kw.get("arr_sd", 0.0)
     sx = tuple(kw.get("sta_x", ()))
     assert len(sx) <= 8
     for j, v in enumerate(sx):
@@ -172,10 +179,12 @@ def events_array(n: int = 0) -> np.ndarray:
     return np.zeros(n, dtype=EVENT_DTYPE)
 
 
-def as_events(x, y, t, m, ids=None) -> np.ndarray:
+def as_events(x, y, t, m, ids=None, da=None) -> np.ndarray:
     ev = events_array(len(x))
     ev["x"], ev["y"], ev["t"], ev["m"] = x, y, t, m
     ev["id"] = np.arange(len(x), dtype=np.uint64) if ids is None else ids
+    if da is not None:
+        ev["da"] = da
     return ev
 
 
@@ -203,6 +212,20 @@ def move_draws16(seed, chain, sweep, region, j) -> np.ndarray:
     out = np.zeros(16)
     lib().orc_move_draws16(seed, chain, sweep, region, j, _ptr(out))
     return out
+
+
+def move_draws_arr(seed, chain, sweep, region, j) -> np.ndarray:
+    out = np.zeros(16)
+    lib().orc_move_draws_arr(seed, chain, sweep, region, j, _ptr(out))
+    return out
+
+
+def line_fit(model: Model, arrivals) -> tuple[float, float]:
+    a = np.zeros(8)
+    a[:model.nsx] = arrivals
+    x, t = C.c_double(), C.c_double()
+    lib().orc_line_fit(C.byref(model), _ptr(a), C.byref(x), C.byref(t))
+    return x.value, t.value
 
 
 def offset(seed, chain, sweep, wx, wy):

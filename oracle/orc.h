@@ -42,6 +42,16 @@
  *   - regions are intervals of onset time: region i holds onsets in
  *     [off + (i-1) w, off + i w) clipped to [0, N), w = N / gx; the
  *     colour of region i is i mod p.
+ *   - latent arrival times (arr_sd > 0), Section 3's arrival density: the
+ *     arrival at station j is a_j = t + d_j / vel + da[j], the offset da[j]
+ *     Gaussian with standard deviation arr_sd, truncated to
+ *     |da[j]| <= ORC_ARR_TRUNC arr_sd so that the colouring stays exact (the
+ *     reach of a region widens by that bound on both sides).  The event
+ *     stores the offsets; moves of Section 3 act on them: births draw them
+ *     from the prior, the arrival-time move steps one station's arrival,
+ *     the location and onset moves carry the arrivals along with the event,
+ *     and the joint move exchanges two events' arrivals at the stations
+ *     from a split onwards and refits both locations.
  *
  * Mean-template likelihood (tmpl = 1), the alternative reading of the
  * signal model: an event adds the deterministic waveform A phi(n - a) (not
@@ -79,9 +89,14 @@ typedef struct {
     int32_t tmpl;       /* 1: mean-template likelihood (see above) */
     double  xmax;       /* line model: locations uniform on [0, xmax) */
     double  sta_x[8];   /* line model: station positions */
+    double  arr_sd;     /* line model: arrival-time jitter sd (0: a = t + d / vel) */
 } orc_model;
 
-enum { ORC_BIRTH = 0, ORC_DEATH = 1, ORC_LOC = 2, ORC_TIME = 3, ORC_MAG = 4 };
+/* The arrival-time jitter is truncated at this many standard deviations. */
+#define ORC_ARR_TRUNC 4.0
+
+enum { ORC_BIRTH = 0, ORC_DEATH = 1, ORC_LOC = 2, ORC_TIME = 3, ORC_MAG = 4, ORC_ARR = 5,
+       ORC_JOINT = 6 };
 enum { ORC_SCHED_CHROMATIC = 0, ORC_SCHED_NAIVE = 1 };
 
 typedef struct {
@@ -99,6 +114,10 @@ typedef struct {
     int32_t kx, ky, kt, km;   /* sites per axis */
     int32_t _pad1;
     double  hm;               /* magnitude site spacing */
+    /* latent arrivals (line model with arr_sd > 0): probabilities of the
+     * arrival-time and joint moves (added to the five above, all seven sum
+     * to 1) and the arrival step */
+    double  pa, pj, sa;
 } orc_sampler;
 
 typedef struct {
@@ -106,6 +125,7 @@ typedef struct {
     uint64_t id;
     int32_t  region;
     int32_t  _pad;
+    double   da[8];    /* latent arrival offsets per station (line model) */
 } orc_event;
 
 /* ---- Philox4x32-10 and the conversions built on it ------------------- */
@@ -127,6 +147,7 @@ int32_t orc_partition_and_color(const orc_model *m, int32_t gx, int32_t gy,
 int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
                                 double offx, double offy, int32_t period);
 double  orc_line_tau_max(const orc_model *m);
+void    orc_line_fit(const orc_model *m, const double *a, double *x, double *t);
 
 /* ---- likelihood ------------------------------------------------------- */
 typedef struct {
@@ -179,6 +200,8 @@ int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *w
                               int32_t n_tau, double p_learned);
 void    orc_move_draws16(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
                          uint32_t j, double out[16]);
+void    orc_move_draws_arr(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                           uint32_t j, double out[16]);
 double  orc_chain_learned_q(orc_chain *c, int32_t region, double x, double y, double t);
 int32_t orc_chain_learned_draw(orc_chain *c, int32_t region, const double *d, double *out);
 int64_t orc_chain_events(const orc_chain *c, orc_event *out, int64_t cap);

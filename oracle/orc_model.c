@@ -176,14 +176,16 @@ double orc_line_tau_max(const orc_model *m)
 }
 
 /* Line model (Section 4.1's time partition): region i holds onsets in
- * [t0, t1); its events arrive at station j within [t0 + dmin / vel,
- * t1 + dmax / vel), so the samples they can touch lie in
- * [ceil(t0 + dmin / vel), ceil(t1 + dmax / vel) + ts).  Two regions of one
- * colour conflict when these sample ranges meet at some station: their
- * events could then explain the same samples. */
+ * [t0, t1); its events arrive at station j within [t0 + dmin / vel - e,
+ * t1 + dmax / vel + e), e the bound of the arrival jitter (0 without latent
+ * arrivals), so the samples they can touch lie in
+ * [ceil(t0 + dmin / vel - e), ceil(t1 + dmax / vel + e) + ts).  Two regions
+ * of one colour conflict when these sample ranges meet at some station:
+ * their events could then explain the same samples. */
 static int64_t line_violations(const orc_model *m, int32_t g, double off, int32_t period)
 {
     double w = (double)m->N / (double)g;
+    double e = ORC_ARR_TRUNC * m->arr_sd;
     int64_t bad = 0;
     for (int32_t j = 0; j < m->nsx; ++j) {
         double dmin, dmax;
@@ -192,18 +194,85 @@ static int64_t line_violations(const orc_model *m, int32_t g, double off, int32_
             double a0, a1;
             region_bounds(off, w, (double)m->N, a, &a0, &a1);
             if (!(a1 > a0)) continue;
-            double lo_a = ceil(a0 + dmin / m->vel), hi_a = ceil(a1 + dmax / m->vel) + m->ts;
+            double lo_a = ceil(a0 + dmin / m->vel - e);
+            double hi_a = ceil(a1 + dmax / m->vel + e) + m->ts;
             for (int32_t b = a + 1; b <= g; ++b) {
                 if (a % period != b % period) continue;
                 double b0, b1;
                 region_bounds(off, w, (double)m->N, b, &b0, &b1);
                 if (!(b1 > b0)) continue;
-                double lo_b = ceil(b0 + dmin / m->vel), hi_b = ceil(b1 + dmax / m->vel) + m->ts;
+                double lo_b = ceil(b0 + dmin / m->vel - e);
+                double hi_b = ceil(b1 + dmax / m->vel + e) + m->ts;
                 if (lo_a < hi_b && lo_b < hi_a) ++bad;
             }
         }
     }
     return bad;
+}
+
+/* Line model: least-squares location and onset of an event from its arrival
+ * times a[0 .. nsx) at the stations: minimise
+ * F(x, t) = sum_j (a_j - t - |x - sx_j| / vel)^2 over x in [0, xmax] and t.
+ * Between consecutive breakpoints (0, xmax and the station positions inside
+ * (0, xmax)) every |x - sx_j| is linear in x, with sign g_j = +1 for stations
+ * at or left of the interval's midpoint and -1 otherwise; there
+ * c_j = a_j + g_j sx_j / vel = t + g_j x / vel is a straight-line regression
+ * of c on g, whose slope gives x / vel (the midpoint when every g_j is the
+ * same).  x is clamped to the interval, t is the mean of a_j - |x - sx_j| /
+ * vel at that x, and the interval with the smallest F wins (the first in
+ * breakpoint order on ties).  This is the geometric analysis behind the
+ * joint move of Section 3: it places an event where a set of arrivals says
+ * it must be. */
+void orc_line_fit(const orc_model *m, const double *a, double *x_out, double *t_out)
+{
+    const int32_t ns = m->nsx;
+    double bp[10];
+    int32_t nb = 0;
+    bp[nb++] = 0.0;
+    for (int32_t j = 0; j < ns; ++j)
+        if (m->sta_x[j] > 0.0 && m->sta_x[j] < m->xmax) bp[nb++] = m->sta_x[j];
+    bp[nb++] = m->xmax;
+    double best_f = INFINITY, best_x = 0.0, best_t = 0.0;
+    for (int32_t q = 0; q < nb; ++q) {
+        double lo = bp[q], hi = INFINITY;
+        for (int32_t r = 0; r < nb; ++r)
+            if (bp[r] > lo && bp[r] < hi) hi = bp[r];
+        if (hi == INFINITY) continue;  /* lo is the last breakpoint */
+        double mid = 0.5 * (lo + hi);
+        double sgn[8], cj[8], gbar = 0.0, cbar = 0.0;
+        for (int32_t j = 0; j < ns; ++j) {
+            sgn[j] = m->sta_x[j] <= mid ? 1.0 : -1.0;
+            cj[j] = a[j] + sgn[j] * m->sta_x[j] / m->vel;
+            gbar += sgn[j];
+            cbar += cj[j];
+        }
+        gbar /= (double)ns;
+        cbar /= (double)ns;
+        double sgg = 0.0, sgc = 0.0;
+        for (int32_t j = 0; j < ns; ++j) {
+            double dg = sgn[j] - gbar;
+            sgg += dg * dg;
+            sgc += dg * (cj[j] - cbar);
+        }
+        double x = sgg > 0.0 ? m->vel * (sgc / sgg) : mid;
+        if (x < lo) x = lo;
+        if (x > hi) x = hi;
+        double t = 0.0;
+        for (int32_t j = 0; j < ns; ++j) t += a[j] - fabs(x - m->sta_x[j]) / m->vel;
+        t /= (double)ns;
+        double f = 0.0;
+        for (int32_t j = 0; j < ns; ++j) {
+            double r = (a[j] - t) - fabs(x - m->sta_x[j]) / m->vel;
+            f += r * r;
+        }
+        if (f < best_f) {
+            best_f = f;
+            best_x = x;
+            best_t = t;
+        }
+    }
+    *x_out = best_x;
+    *t_out = best_t;
 }
 
 /* Number of (station, pair of same-coloured regions) conflicts: two regions
@@ -253,7 +322,8 @@ int64_t orc_coloring_violations(const orc_model *m, int32_t gx, int32_t gy,
 
 /* Line model partition: gx regions of onset time (gy unused), colour i mod p.
  * Dynamic partitions need p - 1 region lengths to cover the longest travel
- * time plus the signal duration, p = ceil((tau_max + ts) / w) + 1. */
+ * time plus the signal duration plus twice the jitter bound e,
+ * p = ceil((tau_max + ts + 2 e) / w) + 1. */
 static int32_t line_partition(const orc_model *m, int32_t gx, double offt, int32_t dynamic,
                               int32_t *nrx, int32_t *nry, int32_t *period, int32_t *ncolors,
                               int32_t *color_of_region)
@@ -261,7 +331,8 @@ static int32_t line_partition(const orc_model *m, int32_t gx, double offt, int32
     double w = (double)m->N / (double)gx;
     int32_t p;
     if (dynamic) {
-        p = (int32_t)ceil((orc_line_tau_max(m) + (double)m->ts) / w) + 1;
+        p = (int32_t)ceil((orc_line_tau_max(m) + (double)m->ts + 2.0 * ORC_ARR_TRUNC * m->arr_sd)
+                          / w) + 1;
         if (line_violations(m, gx, offt, p) != 0) return -4;
     } else {
         for (p = 1; p <= gx + 1; ++p)
@@ -331,7 +402,8 @@ double orc_arrival_time(double x, double y, double t, double sx, double sy, doub
 }
 
 /* Arrival of one event at station (ix, iy): distance d, detection d < rc,
- * arrival a = t + d / vel, amplitude A = m exp(-d / atten), and the samples
+ * arrival a = t + d / vel (plus the event's offset da[ix] when the line
+ * model's arrivals are latent), amplitude A = m exp(-d / atten), and the samples
  * [n0, n1) = [ceil(a), ceil(a) + ts) clipped to the trace.  In the line
  * model every station detects and the amplitude does not attenuate. */
 void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
@@ -339,6 +411,7 @@ void orc_arrival(const orc_model *m, const orc_event *e, int32_t ix, int32_t iy,
 {
     out->a = orc_arrival_time(e->x, e->y, e->t, orc_station_x(m, ix), orc_station_y(m, iy),
                               m->vel, &out->d);
+    if (m->line && m->arr_sd > 0.0) out->a = out->a + e->da[ix];  /* latent arrival */
     out->in = m->line ? 1 : out->d < m->rc;
     out->amp = m->line ? e->m : e->m * exp(-out->d / m->atten);
     int64_t n0 = (int64_t)ceil(out->a);
@@ -461,8 +534,17 @@ double orc_logprior(const orc_model *m, const orc_event *ev, int64_t nev)
     double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     double total = -m->lambda;
     if (m->line) {  /* uniform location on [0, xmax), no magnitude */
-        for (int64_t i = 0; i < nev; ++i)
+        for (int64_t i = 0; i < nev; ++i) {
             total += log(m->lambda) - log(m->xmax) - log((double)m->N);
+            if (!(m->arr_sd > 0.0)) continue;
+            /* latent arrivals: a truncated normal density per station */
+            double z = ORC_ARR_TRUNC, mass = erf(z / sqrt(2.0));
+            for (int32_t j = 0; j < m->nsx; ++j) {
+                double u = ev[i].da[j] / m->arr_sd;
+                if (fabs(u) > z) return -INFINITY;
+                total += -0.5 * u * u - log(m->arr_sd * sqrt(2.0 * M_PI) * mass);
+            }
+        }
         return total;
     }
     for (int64_t i = 0; i < nev; ++i) {

@@ -442,16 +442,66 @@ double orc_chain_delta(orc_chain *c, int32_t region, int32_t type, int64_t idx,
     return move_delta(c, region, type, idx, proposed);
 }
 
+/* Log-likelihood change of replacing events i and k of region r (line
+ * model) by ni and nk, evaluated directly like move_delta: at every station,
+ * over the samples any of the four windows covers, the variance is summed
+ * from scratch over the other events before and after. */
+static double pair_delta(orc_chain *c, int32_t r, int64_t i, int64_t k, const orc_event *ni,
+                         const orc_event *nk)
+{
+    const orc_model *m = &c->m;
+    const evlist *own = &c->reg[r];
+    double delta = 0.0;
+    int64_t cap = 0;
+    orc_arrival_t *others = NULL;
+    for (int32_t ix = 0; ix < m->nsx; ++ix) {
+        orc_arrival_t w[4];
+        orc_arrival(m, &own->e[i], ix, 0, &w[0]);
+        orc_arrival(m, &own->e[k], ix, 0, &w[1]);
+        orc_arrival(m, ni, ix, 0, &w[2]);
+        orc_arrival(m, nk, ix, 0, &w[3]);
+        int64_t lo = m->N, hi = 0;
+        for (int q = 0; q < 4; ++q) {
+            if (w[q].n1 <= w[q].n0) continue;
+            if (w[q].n0 < lo) lo = w[q].n0;
+            if (w[q].n1 > hi) hi = w[q].n1;
+        }
+        if (hi <= lo) continue;
+        int64_t need = c->snap[ix].n + own->n;
+        if (need > cap) {
+            cap = need;
+            others = (orc_arrival_t *)realloc(others, sizeof(orc_arrival_t) * (size_t)need);
+        }
+        int64_t no = 0;
+        for (int64_t q = 0; q < c->snap[ix].n; ++q)
+            if (c->snap[ix].e[q].region != r) orc_arrival(m, &c->snap[ix].e[q], ix, 0, &others[no++]);
+        for (int64_t q = 0; q < own->n; ++q)
+            if (q != i && q != k) orc_arrival(m, &own->e[q], ix, 0, &others[no++]);
+        for (int64_t n = lo; n < hi; ++n) {
+            double sv = trace_at(c, ix, n);
+            double base = m->tmpl ? 0.0 : m->sigma * m->sigma;
+            for (int64_t q = 0; q < no; ++q) base += orc_arrival_variance(m, &others[q], n);
+            double c_old = base + orc_arrival_variance(m, &w[0], n) + orc_arrival_variance(m, &w[1], n);
+            double c_new = base + orc_arrival_variance(m, &w[2], n) + orc_arrival_variance(m, &w[3], n);
+            delta += sample_logpdf(m, sv, c_new) - sample_logpdf(m, sv, c_old);
+        }
+    }
+    free(others);
+    return delta;
+}
+
 /* --------------------------------------------------------------- moves */
 
 /* One MH move inside region r (Algorithm 2's step, confined to the region
  * as in Algorithm 4).  Move types (Section 3): birth from the region's prior
  * and death of a uniformly chosen event (Geyer-Moller birth-death for a
  * Poisson process restricted to the region), a Gaussian location offset, a
- * Gaussian time offset and a Gaussian magnitude offset.  A proposal that
- * leaves the region, the trace or the magnitude support is rejected without
- * evaluating the likelihood.  log entry: type, status (0 invalid,
- * 1 rejected, 2 accepted), delta, log alpha. */
+ * Gaussian time offset and a Gaussian magnitude offset; with latent arrival
+ * times (line model) also the arrival-time move and the joint two-event move
+ * (joint_proposal).  A proposal that leaves the region, the trace or the
+ * magnitude or offset support is rejected without evaluating the
+ * likelihood.  log entry: type, status (0 invalid, 1 rejected, 2 accepted),
+ * delta, log alpha. */
 /* ------------------------------------------------------ learned births */
 /* Draw record of 16 for the learned birth proposal: the 8 of
  * orc_move_draws, then [8] mixture uniform, [9] anchor uniform, [10]
@@ -483,6 +533,30 @@ void orc_move_draws16(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t re
     while (got < 3) out[11 + got++] = 0.0;
     out[14] = 0.0;
     out[15] = 0.0;
+}
+
+/* Draw record of 16 for latent arrivals: the 8 of orc_move_draws, then
+ * [8..15] eight standard normals truncated to [-4, 4] (the birth's arrival
+ * offsets in station order; the joint move's second event takes [8], [9]):
+ * Box-Muller pairs from counter blocks 4, 5, ... (cosine then sine), the
+ * first eight of absolute value at most 4; after blocks 4 .. 19 any still
+ * missing are 0. */
+void orc_move_draws_arr(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                        uint32_t j, double out[16])
+{
+    orc_move_draws(seed, chain, sweep, region, j, out);
+    uint32_t key[2] = {seed, chain}, w[4];
+    int got = 0;
+    for (uint32_t blk = 4; blk < 20 && got < 8; ++blk) {
+        uint32_t cb[4] = {sweep, region, j, blk};
+        orc_philox4x32_10(cb, key, w);
+        double u1 = orc_u01(w[0], w[1]), u2 = orc_u01(w[2], w[3]);
+        double r = sqrt(-2.0 * log(u1));
+        double z[2] = {r * cos(2.0 * M_PI * u2), r * sin(2.0 * M_PI * u2)};
+        for (int h = 0; h < 2 && got < 8; ++h)
+            if (fabs(z[h]) <= 4.0) out[8 + got++] = z[h];
+    }
+    while (got < 8) out[8 + got++] = 0.0;
 }
 
 int32_t orc_chain_set_learned(orc_chain *c, const double *table, const double *weights,
@@ -621,6 +695,79 @@ int32_t orc_chain_learned_draw(orc_chain *c, int32_t region, const double *d, do
     return 0;
 }
 
+/* Latent arrival times are on: the line model with arr_sd > 0. */
+static int latent(const orc_chain *c)
+{
+    return c->m.line && c->m.arr_sd > 0.0 && !c->sp.lattice;
+}
+
+/* The joint move of Section 3 (line model with latent arrivals).  Events i
+ * and k of region r exchange their arrival times at stations split .. nsx-1.
+ * Each then moves to a Gaussian draw (steps sxy and st; normals d[5], d[6]
+ * for i, d[8], d[9] for k) around the least-squares fit of its new arrivals
+ * (orc_line_fit), and its offsets become whatever places its arrivals
+ * exactly where they are.  The reverse move (the same pair and split)
+ * exchanges them back and proposes around the fits of the original
+ * arrivals.  The move is valid only for two events of equal amplitude (the
+ * exchange then leaves every station's set of signals as it was), new
+ * locations and onsets inside the domain and the region, offsets within the
+ * jitter bound, and new windows that start at the sample of the arrival they
+ * take over.  *lx receives the prior and proposal part of log alpha: the
+ * change of the offsets' log prior density, summed over both events and all
+ * stations, plus log q(reverse) - log q(forward). */
+static int joint_proposal(const orc_chain *c, int32_t r, int64_t i, int64_t k, int32_t split,
+                          const double *d, orc_event *ni, orc_event *nk, double *lx)
+{
+    const orc_model *m = &c->m;
+    const orc_event *ev[2] = {&c->reg[r].e[i], &c->reg[r].e[k]};
+    orc_event *nw[2] = {ni, nk};
+    if (ev[0]->m != ev[1]->m) return 0;
+    double A[2][8], B[2][8];
+    for (int e = 0; e < 2; ++e)
+        for (int32_t j = 0; j < m->nsx; ++j) {
+            orc_arrival_t ar;
+            orc_arrival(m, ev[e], j, 0, &ar);
+            A[e][j] = ar.a;
+        }
+    for (int e = 0; e < 2; ++e)
+        for (int32_t j = 0; j < m->nsx; ++j) B[e][j] = j >= split ? A[1 - e][j] : A[e][j];
+    const double zx[2] = {d[5], d[8]}, zt[2] = {d[6], d[9]};
+    const double bound = ORC_ARR_TRUNC * m->arr_sd, v2 = 2.0 * (m->arr_sd * m->arr_sd);
+    for (int e = 0; e < 2; ++e) {
+        double fx, ft;
+        orc_line_fit(m, B[e], &fx, &ft);
+        *nw[e] = *ev[e];
+        nw[e]->x = fx + c->sp.sxy * zx[e];
+        nw[e]->t = ft + c->sp.st * zt[e];
+        if (!(nw[e]->x >= 0.0 && nw[e]->x < c->Lx && nw[e]->t >= 0.0 &&
+              nw[e]->t < (double)m->N && region_of(c, nw[e]->x, 0.0, nw[e]->t) == r))
+            return 0;
+        for (int32_t j = 0; j < 8; ++j) nw[e]->da[j] = 0.0;
+        for (int32_t j = 0; j < m->nsx; ++j) {
+            double mean = orc_arrival_time(nw[e]->x, 0.0, nw[e]->t, m->sta_x[j], 0.0, m->vel, NULL);
+            nw[e]->da[j] = B[e][j] - mean;
+            if (fabs(nw[e]->da[j]) > bound) return 0;
+        }
+        for (int32_t j = 0; j < m->nsx; ++j) {
+            orc_arrival_t ar;
+            orc_arrival(m, nw[e], j, 0, &ar);
+            if (ceil(ar.a) != ceil(B[e][j])) return 0;
+        }
+    }
+    double lp = 0.0, lq = 0.0;
+    for (int e = 0; e < 2; ++e)
+        for (int32_t j = 0; j < m->nsx; ++j)
+            lp += (ev[e]->da[j] * ev[e]->da[j] - nw[e]->da[j] * nw[e]->da[j]) / v2;
+    for (int e = 0; e < 2; ++e) {
+        double bx, bt;
+        orc_line_fit(m, A[e], &bx, &bt);  /* the reverse move's centre */
+        double rx = (ev[e]->x - bx) / c->sp.sxy, rt = (ev[e]->t - bt) / c->sp.st;
+        lq += 0.5 * (zx[e] * zx[e] + zt[e] * zt[e]) - 0.5 * (rx * rx + rt * rt);
+    }
+    *lx = lp + lq;
+    return 1;
+}
+
 static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const double *d,
                      double lam_r, double area, double *logentry)
 {
@@ -640,15 +787,21 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             pl = c->plearn;
         }
     }
+    const int lat = latent(c);
     double c1 = sp->pb, c2 = c1 + sp->pd, c3 = c2 + sp->ploc, c4 = c3 + sp->pt;
+    double c5 = c4 + sp->pm, c6 = c5 + sp->pa;
     int32_t type = d[0] < c1 ? ORC_BIRTH
                  : d[0] < c2 ? ORC_DEATH
                  : d[0] < c3 ? ORC_LOC
-                 : d[0] < c4 ? ORC_TIME : ORC_MAG;
+                 : d[0] < c4 ? ORC_TIME
+                 : (!lat || d[0] < c5) ? ORC_MAG
+                 : d[0] < c6 ? ORC_ARR : ORC_JOINT;
     int valid = 1;
-    int64_t idx = -1;
-    orc_event nw;
+    int64_t idx = -1, idx2 = -1;
+    double lx = 0.0;  /* prior and proposal part of log alpha (latent moves) */
+    orc_event nw, nw2;
     memset(&nw, 0, sizeof nw);
+    memset(&nw2, 0, sizeof nw2);
 
     if (type == ORC_BIRTH) {
         if (n >= sp->cap) {
@@ -684,6 +837,8 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             nw.m = m->mmin;
             valid = nw.x >= 0.0 && nw.x < c->Lx && nw.t >= 0.0 && nw.t < (double)m->N &&
                     region_of(c, nw.x, nw.y, nw.t) == r;
+            if (lat)  /* arrival offsets from their prior: arr_sd times truncated normals */
+                for (int32_t q = 0; q < m->nsx; ++q) nw.da[q] = m->arr_sd * d[8 + q];
         } else {
             double x0, x1, y0, y1;
             region_rect(c, r, &x0, &x1, &y0, &y1);
@@ -700,6 +855,19 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
         }
         nw.id = ((uint64_t)sweep << 32) | ((uint64_t)(uint32_t)r << 12) | (uint64_t)j;
         nw.region = r;
+    } else if (type == ORC_JOINT) {
+        if (n < 2 || m->nsx < 2) {
+            valid = 0;
+        } else {
+            idx = (int64_t)floor(d[1] * (double)n);
+            if (idx >= n) idx = n - 1;
+            idx2 = (int64_t)floor(d[2] * (double)(n - 1));
+            if (idx2 >= n - 1) idx2 = n - 2;
+            if (idx2 >= idx) idx2 += 1;
+            int32_t split = 1 + (int32_t)floor(d[3] * (double)(m->nsx - 1));
+            if (split >= m->nsx) split = m->nsx - 1;
+            valid = joint_proposal(c, r, idx, idx2, split, d, &nw, &nw2, &lx);
+        }
     } else {
         if (n == 0) {
             valid = 0;
@@ -736,6 +904,15 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
                 valid = nw.t >= 0.0 && nw.t < (double)m->N && region_of(c, nw.x, nw.y, nw.t) == r;
             } else if (m->line && type == ORC_MAG) {
                 valid = 0;  /* the line model's amplitude is fixed */
+            } else if (type == ORC_ARR) {
+                /* one station's arrival moves by a Gaussian step; the prior
+                 * density of its offset enters the ratio */
+                int32_t js = (int32_t)floor(d[2] * (double)m->nsx);
+                if (js >= m->nsx) js = m->nsx - 1;
+                double o = nw.da[js];
+                nw.da[js] = o + sp->sa * d[5];
+                valid = fabs(nw.da[js]) <= ORC_ARR_TRUNC * m->arr_sd;
+                lx = (o * o - nw.da[js] * nw.da[js]) / (2.0 * (m->arr_sd * m->arr_sd));
             } else if (type == ORC_LOC) {
                 nw.x = nw.x + sp->sxy * d[5];
                 nw.y = nw.y + sp->sxy * d[6];
@@ -754,7 +931,9 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
     double delta = 0.0, la = 0.0;
     int32_t status = 0;
     if (valid) {
-        if (!sp->prior_only) delta = move_delta(c, r, type, idx, &nw);
+        if (!sp->prior_only)
+            delta = type == ORC_JOINT ? pair_delta(c, r, idx, idx2, &nw, &nw2)
+                                      : move_delta(c, r, type, idx, &nw);
         if (type == ORC_BIRTH) {
             la = delta + log(lam_r) + log(sp->pd) - log((double)(n + 1)) - log(sp->pb);
             if (pl > 0.0) la -= learned_log_ratio(c, sta, ns, W, pl, area, nw.x, nw.y, nw.t);
@@ -763,6 +942,8 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             if (pl > 0.0) la += learned_log_ratio(c, sta, ns, W, pl, area, nw.x, nw.y, nw.t);
         } else if (type == ORC_MAG && !sp->lattice) {
             la = delta - m->mrate * (nw.m - own->e[idx].m);
+        } else if (type == ORC_ARR || type == ORC_JOINT) {
+            la = delta + lx;
         } else {
             la = delta;
         }
@@ -770,6 +951,7 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
             status = 2;
             if (type == ORC_BIRTH) ev_push(own, &nw);
             else if (type == ORC_DEATH) ev_remove(own, idx);
+            else if (type == ORC_JOINT) { own->e[idx] = nw; own->e[idx2] = nw2; }
             else own->e[idx] = nw;
         } else {
             status = 1;
@@ -825,14 +1007,16 @@ int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double
         } else {
             lam_r = c->m.lambda * area / (c->Lx * c->Ly);
         }
-        const int64_t stride = c->ltab ? 16 : 8;
+        const int64_t stride = c->ltab || latent(c) ? 16 : 8;
         for (int32_t j = 0; j < c->sp.k; ++j) {
             double d[16];
             const double *dp;
             if (feed) {
                 dp = feed + ((r * c->sp.k) + j) * stride;
             } else {
-                if (c->ltab)
+                if (latent(c))
+                    orc_move_draws_arr(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+                else if (c->ltab)
                     orc_move_draws16(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
                 else
                     orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);

@@ -47,6 +47,7 @@ class ModelSpec:
     tmpl: int = 0              # 1: mean-template likelihood (waveforms add to the mean)
     xmax: float = 0.0          # line: locations on [0, xmax)
     sta_x: tuple = ()          # line: station positions (at most 8)
+    arr_sd: float = 0.0        # line: arrival-time jitter sd (latent arrivals when > 0)
 
     @property
     def Lx(self) -> float:
@@ -88,6 +89,9 @@ class SamplerSpec:
     kt: int = 0
     km: int = 0
     hm: float = 0.0
+    pa: float = 0.0            # latent arrivals: arrival-time move probability
+    pj: float = 0.0            # latent arrivals: joint two-event move probability
+    sa: float = 0.0            # latent arrivals: arrival step
 
     @property
     def nreg(self) -> int:
@@ -148,7 +152,29 @@ PAPER1D_SAMPLER = SamplerSpec(gx=4, gy=0, dynamic=0, k=500, cap=64, pb=0.2, pd=0
 PAPER1D = Workload(name="line4-x100-n240-t4-k500", model=PAPER1D_MODEL, sampler=PAPER1D_SAMPLER,
                    trace_dtype="f64", chains=1, sweeps=200, seed=5)
 
-WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32, PAPER1D)}
+# The same world with Section 3's latent arrival times: every arrival is the
+# mean travel time plus a Gaussian offset of sd 1 sample (truncated at 4 sd),
+# and the sampler adds the arrival-time move and the joint two-event move.
+# The jitter bound widens each region's reach by 4 samples on both sides, so
+# the four regions need three colours.
+PAPER1D_LATENT_MODEL = dataclasses.replace(PAPER1D_MODEL, arr_sd=1.0)
+PAPER1D_LATENT_SAMPLER = dataclasses.replace(PAPER1D_SAMPLER, pb=0.15, pd=0.15, ploc=0.25,
+                                             pt=0.25, pa=0.1, pj=0.1, sa=1.0)
+PAPER1D_LATENT = Workload(name="line4-x100-n240-t4-k500-latent", model=PAPER1D_LATENT_MODEL,
+                          sampler=PAPER1D_LATENT_SAMPLER, trace_dtype="f64", chains=1,
+                          sweeps=200, seed=6)
+
+WORKLOADS = {w.name: w for w in (SMALL, LARGE, CHAINS32, PAPER1D, PAPER1D_LATENT)}
+
+
+def truncated_normals(rng, shape, bound: float = 4.0) -> np.ndarray:
+    """Standard normals redrawn until |z| <= bound."""
+    z = rng.standard_normal(shape)
+    bad = np.abs(z) > bound
+    while bad.any():
+        z[bad] = rng.standard_normal(int(bad.sum()))
+        bad = np.abs(z) > bound
+    return z
 
 
 def uneven_batch(count: int = 256, seed: int = 1000) -> list:
@@ -193,8 +219,11 @@ def truth_events(model: ModelSpec, seed: int, n: int | None = None):
     if model.line:  # locations on [0, xmax), y = 0, the fixed amplitude
         x = np.minimum(rng.random(n) * model.xmax, np.nextafter(model.xmax, 0.0))
         t = np.minimum(rng.random(n) * model.N, np.nextafter(float(model.N), 0.0))
+        da = np.zeros((n, 8))
+        if model.arr_sd > 0:  # latent arrivals: offsets from their truncated prior
+            da[:, :model.nsx] = model.arr_sd * truncated_normals(rng, (n, model.nsx))
         return dict(x=x, y=np.zeros(n), t=t, m=np.full(n, model.mmin),
-                    id=np.arange(n, dtype=np.uint64))
+                    id=np.arange(n, dtype=np.uint64), da=da)
     x = np.minimum(rng.random(n) * model.Lx, np.nextafter(model.Lx, 0.0))
     y = np.minimum(rng.random(n) * model.Ly, np.nextafter(model.Ly, 0.0))
     t = np.minimum(rng.random(n) * model.N, np.nextafter(float(model.N), 0.0))
@@ -202,16 +231,18 @@ def truth_events(model: ModelSpec, seed: int, n: int | None = None):
     return dict(x=x, y=y, t=t, m=m, id=np.arange(n, dtype=np.uint64))
 
 
-def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int, learned: bool = False) -> np.ndarray:
+def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int, learned: bool = False,
+               latent: bool = False) -> np.ndarray:
     """Per-move random draws for replay runs, shape [nsweeps, regions, k, 8]:
     [0..3] uniforms on [0,1), [4] Exp(1), [5],[6] standard normals, [7] log of
     a uniform on (0,1].  With learned births the records are 16 wide: [8..10]
     uniforms on [0,1), [11..13] standard normals truncated to [-4, 4],
-    [14], [15] zero.  Both the GPU path and the oracle consume the same
-    array, so their proposals coincide bit for bit."""
+    [14], [15] zero.  With latent arrivals they are 16 wide too: [8..15]
+    standard normals truncated to [-4, 4].  Both the GPU path and the oracle
+    consume the same array, so their proposals coincide bit for bit."""
     rng = np.random.Generator(np.random.PCG64(seed))
     shape = (nsweeps, sampler.nreg, sampler.k)
-    out = np.zeros(shape + ((16,) if learned else (8,)), dtype=np.float64)
+    out = np.zeros(shape + ((16,) if learned or latent else (8,)), dtype=np.float64)
     out[..., 0:4] = rng.random(shape + (4,))
     out[..., 4] = rng.standard_exponential(shape)
     out[..., 5:7] = rng.standard_normal(shape + (2,))
@@ -224,6 +255,8 @@ def feed_draws(sampler: SamplerSpec, nsweeps: int, seed: int, learned: bool = Fa
             z[bad] = rng.standard_normal(int(bad.sum()))
             bad = np.abs(z) > 4.0
         out[..., 11:14] = z
+    if latent:
+        out[..., 8:16] = truncated_normals(rng, shape + (8,))
     return out
 
 
