@@ -64,6 +64,8 @@ extern "C" {
 #define CMH_LOC   2
 #define CMH_TIME  3
 #define CMH_MAG   4
+#define CMH_ARR   5   /* arrival-time move (latent arrivals) */
+#define CMH_JOINT 6   /* joint two-event move (latent arrivals) */
 
 typedef struct {
     int32_t nsx, nsy;     /* station grid */
@@ -101,6 +103,17 @@ typedef struct {
     int32_t template_mean;
     double  x_max;
     double  station_x[8];
+    /* Latent arrival times (line model only; 0 = off), Section 3's arrival
+     * density: every event carries offsets da[j] (cmh_event) and arrives at
+     * station j at t + |x - station_x[j]| / velocity + da[j]; each offset is
+     * Gaussian with standard deviation arrival_sd, truncated to
+     * |da[j]| <= 4 arrival_sd so that the colouring stays exact (every
+     * region's reach widens by that bound on both sides).  Births draw the
+     * offsets from this prior, location and onset moves carry them along
+     * (the arrivals move with the event), and the sampler gains the
+     * arrival-time move and the joint move (cmh_sampler).  Runs the
+     * block-256 form of the chromatic schedule. */
+    double  arrival_sd;
 } cmh_model;
 
 typedef struct {
@@ -124,6 +137,19 @@ typedef struct {
                                    n_stations x n_samples <= 2048 (a private copy per
                                    region in LDS) and runs the block-64 form. */
     int32_t _pad0;
+    /* Latent arrivals only (0 otherwise).  p_arrival: the arrival-time move
+     * of Section 3 (one event, one station drawn uniformly, its offset plus
+     * step_arrival times a standard normal; the offset prior enters the
+     * ratio).  p_joint: the joint move of Section 3: two events of a region
+     * (of equal magnitude) exchange their arrival times at the stations
+     * from a uniformly drawn split s in 1..n-1 onwards (station index
+     * order), each then moves to its least-squares location fit to the new
+     * arrivals plus Gaussian steps (step_xy, step_t), with offsets that keep
+     * its arrivals where they are; the signal is unchanged, so only the
+     * offset prior and the proposal densities (around the fits of the new
+     * and of the old arrivals) enter the ratio.  All seven probabilities sum
+     * to 1. */
+    double  p_arrival, p_joint, step_arrival;
 } cmh_sampler;
 
 typedef struct {
@@ -131,6 +157,7 @@ typedef struct {
     uint64_t id;       /* (sweep << 32) | (region << 12) | move, or caller's */
     int32_t  region;   /* linear region index k * (grid_x + 1) + i */
     int32_t  _pad;
+    double   da[8];    /* latent arrivals: offset per station (0 otherwise) */
 } cmh_event;
 
 typedef struct cmh_state cmh_state;
@@ -146,8 +173,10 @@ const char *cmh_last_error(void);
  * every offset.  Line model: regions of onset time, w = n_samples / grid_x,
  * off_x the time offset, off_y = 0, grid_y = 0; region i can touch samples
  * [ceil(t0 + dmin / v), ceil(t1 + dmax / v) + t_s) of a station at distances
- * dmin..dmax from the line, and no two regions of one colour may share a
- * sample; dynamic p = ceil((tau_max + t_s) / w) + 1; colour i mod p.
+ * dmin..dmax from the line (each end widened by the jitter bound e =
+ * 4 arrival_sd with latent arrivals), and no two regions of one colour may
+ * share a sample; dynamic p = ceil((tau_max + t_s + 2 e) / w) + 1; colour
+ * i mod p.
  * color_of_region: caller array of (grid_x+1)*(grid_y+1) int32, may be NULL.
  * Pure host function.  CMH_ECOLOR if no p works. */
 int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t grid_y,
@@ -200,9 +229,11 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
  * standard normals, [7] log of the acceptance uniform.  With learned births
  * (cmh_set_learned) the records are [16]: the same 8, then [8] mixture
  * uniform, [9] anchor uniform, [10] component uniform, [11..13] standard
- * normals truncated to [-4, 4], [14], [15] unused.  width (8 or 16) states
- * the record size; a sweep whose mode needs the other size fails with
- * CMH_EINVAL before any launch.  Chain 0 only.  NULL detaches. */
+ * normals truncated to [-4, 4], [14], [15] unused.  With latent arrivals
+ * they are [16] too: the same 8, then [8..15] standard normals truncated to
+ * [-4, 4] (cmh_move_draws_arrivals).  width (8 or 16) states the record
+ * size; a sweep whose mode needs the other size fails with CMH_EINVAL before
+ * any launch.  Chain 0 only.  NULL detaches. */
 int32_t cmh_set_feed(cmh_state *st, const double *feed_dev, int64_t first_sweep,
                      int64_t n_sweeps, int32_t width);
 
@@ -234,10 +265,11 @@ int32_t cmh_refresh(cmh_state *st, int32_t write_variance, double *out_host, voi
 int32_t cmh_read_variance(cmh_state *st, int32_t chain, int64_t station0, int64_t nsta,
                           double *out_host);
 
-/* Per-chain move statistics since init, out_host[17]: [3 t + 0], [3 t + 1],
+/* Per-chain move statistics since init, out_host[23]: [3 t + 0], [3 t + 1],
  * [3 t + 2] = attempted, evaluated (valid proposals) and accepted moves of
  * type t (CMH_BIRTH .. CMH_MAG); [15] footprint samples evaluated; [16]
- * footprint samples rewritten on acceptance.  Synchronises. */
+ * footprint samples rewritten on acceptance; [17 + 3 (t - 5) + 0..2] the
+ * same three counts for CMH_ARR and CMH_JOINT.  Synchronises. */
 int32_t cmh_read_stats(cmh_state *st, int32_t chain, uint64_t *out_host);
 
 /* Threads per workgroup of the sweep kernel in use (after tuning). */
@@ -324,6 +356,15 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
 int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
                        uint32_t j0, int32_t count, int32_t width, double *out_dev,
                        void *hip_stream);
+
+/* The same for latent arrival times: records [count][16], the 8 above, then
+ * eight standard normals truncated to [-4, 4] (a birth's offsets in station
+ * order; the joint move's second event takes the first two): Box-Muller
+ * pairs from counter blocks 4, 5, ... (cosine, then sine), the first eight
+ * of absolute value at most 4; after blocks 4 .. 19 missing ones are 0.
+ * Enqueues on hip_stream. */
+int32_t cmh_move_draws_arrivals(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                                uint32_t j0, int32_t count, double *out_dev, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Learned birth proposal: a mixture-density network (MDN).

@@ -21,7 +21,9 @@ CMH_F32, CMH_F64 = 0, 1
 ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ECAP", -4: "ECOLOR", -5: "ENAN", -6: "ESTATE"}
 
 EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("t", "<f8"), ("m", "<f8"),
-                        ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4")])
+                        ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4"),
+                        ("da", "<f8", (8,))])
+N_STATS = 23
 
 
 class CmhModel(C.Structure):
@@ -31,7 +33,7 @@ class CmhModel(C.Structure):
                 ("_pad0", C.c_int32), ("r_c", C.c_double), ("lam", C.c_double),
                 ("mag_min", C.c_double), ("mag_rate", C.c_double), ("line", C.c_int32),
                 ("template_mean", C.c_int32), ("x_max", C.c_double),
-                ("station_x", C.c_double * 8)]
+                ("station_x", C.c_double * 8), ("arrival_sd", C.c_double)]
 
 
 class CmhSampler(C.Structure):
@@ -41,7 +43,8 @@ class CmhSampler(C.Structure):
                 ("p_death", C.c_double), ("p_loc", C.c_double), ("p_time", C.c_double),
                 ("p_mag", C.c_double), ("step_xy", C.c_double), ("step_t", C.c_double),
                 ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32),
-                ("schedule", C.c_int32), ("_pad0", C.c_int32)]
+                ("schedule", C.c_int32), ("_pad0", C.c_int32), ("p_arrival", C.c_double),
+                ("p_joint", C.c_double), ("step_arrival", C.c_double)]
 
 
 class CmhError(RuntimeError):
@@ -54,7 +57,7 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_sweep_color", "cmh_run_sweeps", "cmh_read_events", "cmh_write_events",
            "cmh_set_feed", "cmh_set_log", "cmh_refresh", "cmh_read_variance", "cmh_read_stats",
            "cmh_get_block", "cmh_autotune", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
-           "cmh_move_draws", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
+           "cmh_move_draws", "cmh_move_draws_arrivals", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_infer",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
@@ -95,6 +98,7 @@ def lib():
         "cmh_simulate_bytes": ([P, P, I64, P], I32),
         "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
         "cmh_move_draws": ([U32, U32, U32, U32, U32, I32, I32, P, P], I32),
+        "cmh_move_draws_arrivals": ([U32, U32, U32, U32, U32, I32, P, P], I32),
         "cmh_learned_bytes": ([P, I32, P], I32),
         "cmh_set_record": ([P, P, I64, I64, I32], I32),
         "cmh_batch_bytes": ([I32, P, P, P], I32),
@@ -135,6 +139,7 @@ def model_struct(spec: ModelSpec) -> CmhModel:
     m.t_s, m.r_c, m.lam = spec.ts, spec.rc, spec.lam
     m.mag_min, m.mag_rate = spec.mmin, spec.mrate
     m.line, m.x_max, m.template_mean = spec.line, spec.xmax, spec.tmpl
+    m.arrival_sd = spec.arr_sd
     if len(spec.sta_x) > 8:
         raise ValueError("at most 8 stations on a line")
     for j, v in enumerate(spec.sta_x):
@@ -149,6 +154,7 @@ def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
     s.p_birth, s.p_death, s.p_loc, s.p_time, s.p_mag = spec.pb, spec.pd, spec.ploc, spec.pt, spec.pm
     s.step_xy, s.step_t, s.step_m = spec.sxy, spec.st, spec.sm
     s.prior_only, s.block, s.schedule = spec.prior_only, block, spec.schedule
+    s.p_arrival, s.p_joint, s.step_arrival = spec.pa, spec.pj, spec.sa
     return s
 
 
@@ -164,10 +170,12 @@ def _stream(stream=None) -> C.c_void_p:
     return C.c_void_p(s.cuda_stream)
 
 
-def as_events(x, y, t, m, ids=None) -> np.ndarray:
+def as_events(x, y, t, m, ids=None, da=None) -> np.ndarray:
     ev = np.zeros(len(x), dtype=EVENT_DTYPE)
     ev["x"], ev["y"], ev["t"], ev["m"] = x, y, t, m
     ev["id"] = np.arange(len(x), dtype=np.uint64) if ids is None else ids
+    if da is not None:
+        ev["da"] = da
     return ev
 
 
@@ -205,6 +213,17 @@ def move_draws(seed: int, chain: int, sweep: int, region: int, j0: int, count: i
     out = torch.empty((count, width), dtype=torch.float64, device=device)
     check(lib().cmh_move_draws(seed, chain, sweep, region, j0, count, width, _ptr(out),
                                _stream()))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def move_draws_arrivals(seed: int, chain: int, sweep: int, region: int, j0: int, count: int,
+                        device="cuda") -> np.ndarray:
+    """Latent-arrival draw records [count, 16] computed on the device."""
+    import torch
+    out = torch.empty((count, 16), dtype=torch.float64, device=device)
+    check(lib().cmh_move_draws_arrivals(seed, chain, sweep, region, j0, count, _ptr(out),
+                                        _stream()))
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -269,7 +288,7 @@ class ChromaticSampler:
 
     def set_feed(self, feed, first: int):
         """feed: float64 device tensor [n_sweeps, regions, k, 8] ([.., 16]
-        with learned births), or None."""
+        with learned births or latent arrivals), or None."""
         if feed is not None:
             self._check_buffer(feed, feed.shape[-1] if feed.dim() == 4 else 8, "feed")
             if feed.shape[-1] not in (8, 16):
@@ -367,13 +386,16 @@ class ChromaticSampler:
         return out
 
     def read_stats(self, chain: int = 0) -> np.ndarray:
-        """[5, 3] attempted / evaluated / accepted moves per move type."""
-        return self.read_counters(chain)[:15].reshape(5, 3)
+        """[7, 3] attempted / evaluated / accepted moves per move type (rows 5
+        and 6: the arrival-time and joint moves of latent arrivals)."""
+        c = self.read_counters(chain)
+        return np.concatenate([c[:15], c[17:23]]).reshape(7, 3)
 
     def read_counters(self, chain: int = 0) -> np.ndarray:
-        """All 17 counters: the move table, then footprint samples evaluated
-        and footprint samples rewritten."""
-        out = np.zeros(17, dtype=np.uint64)
+        """All 23 counters: the move table of types 0..4, footprint samples
+        evaluated and rewritten, then the table of the latent-arrival moves
+        (types 5 and 6)."""
+        out = np.zeros(N_STATS, dtype=np.uint64)
         check(lib().cmh_read_stats(self._h, chain, _ptr(out)))
         return out
 

@@ -58,6 +58,8 @@ int32_t check_line_model(const cmh_model *m)
     if (m->t_s < 1 || m->t_s > cmh::kMaxTs) return fail(CMH_EINVAL, "t_s must be in 1..128");
     if (!(m->lambda > 0.0)) return fail(CMH_EINVAL, "lambda must be positive");
     if (!std::isfinite(m->mag_min)) return fail(CMH_EINVAL, "mag_min must be finite");
+    if (!(m->arrival_sd >= 0.0) || !std::isfinite(m->arrival_sd))
+        return fail(CMH_EINVAL, "arrival_sd must be finite and non-negative");
     return CMH_OK;
 }
 
@@ -68,6 +70,8 @@ int32_t check_model(const cmh_model *m)
     if (m->template_mean != 0 && m->template_mean != 1)
         return fail(CMH_EINVAL, "template_mean must be 0 or 1");
     if (m->line) return check_line_model(m);
+    if (m->arrival_sd != 0.0)
+        return fail(CMH_EINVAL, "latent arrival times (arrival_sd > 0) need the line model");
     if (m->nsx < 1 || m->nsy < 1) return fail(CMH_EINVAL, "station grid must be at least 1x1");
     if ((long long)m->nsx * m->nsy > (1LL << 22)) return fail(CMH_EINVAL, "too many stations");
     if (!(m->ds > 0.0)) return fail(CMH_EINVAL, "ds must be positive");
@@ -161,11 +165,14 @@ double line_tmax(const cmh_model *m)
 }
 
 // Line model conflicts for period p: onset region [t0, t1) can touch
-// samples [ceil(t0 + dmin / v), ceil(t1 + dmax / v) + t_s) of station j;
-// two regions of one colour must not share a sample of any station.
+// samples [ceil(t0 + dmin / v - e), ceil(t1 + dmax / v + e) + t_s) of
+// station j, e the bound of the arrival-time jitter (0 without latent
+// arrivals); two regions of one colour must not share a sample of any
+// station.
 long long line_conflicts(const cmh_model *m, int gx, double offt, int p)
 {
     const double N = (double)m->n_samples, w = N / (double)gx;
+    const double e = cmh::kArrTrunc * m->arrival_sd;
     std::vector<double> lo(gx + 1), hi(gx + 1);
     for (int i = 0; i <= gx; ++i) cmh::region_span(offt, w, N, i, &lo[i], &hi[i]);
     long long bad = 0;
@@ -174,8 +181,8 @@ long long line_conflicts(const cmh_model *m, int gx, double offt, int p)
         line_reach(m, j, &dmin, &dmax);
         std::vector<double> a(gx + 1), b(gx + 1);
         for (int i = 0; i <= gx; ++i) {
-            a[i] = std::ceil(lo[i] + dmin / m->velocity);
-            b[i] = std::ceil(hi[i] + dmax / m->velocity) + m->t_s;
+            a[i] = std::ceil(lo[i] + dmin / m->velocity - e);
+            b[i] = std::ceil(hi[i] + dmax / m->velocity + e) + m->t_s;
         }
         for (int i = 0; i <= gx; ++i) {
             if (!(hi[i] > lo[i])) continue;
@@ -192,7 +199,9 @@ int32_t choose_line_period(const cmh_model *m, int gx, double offt, int dynamic,
     const double w = (double)m->n_samples / (double)gx;
     int p;
     if (dynamic) {
-        p = (int)std::ceil((line_tmax(m) + (double)m->t_s) / w) + 1;
+        // p - 1 region lengths cover tau_max, t_s and twice the jitter bound
+        p = (int)std::ceil((line_tmax(m) + (double)m->t_s + 2.0 * cmh::kArrTrunc * m->arrival_sd)
+                           / w) + 1;
         if (requested > 0) {
             if (requested < p)
                 return fail(CMH_ECOLOR, "requested period too small for shifted partitions");
@@ -254,7 +263,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         return fail(CMH_EINVAL, "moves_per_region must be in 1..4095");
     if (s->region_capacity < 1 || s->region_capacity > cmh::kMaxCap)
         return fail(CMH_EINVAL, "region_capacity must be in 1..64");
-    const double ps[5] = {s->p_birth, s->p_death, s->p_loc, s->p_time, s->p_mag};
+    const double ps[7] = {s->p_birth, s->p_death, s->p_loc, s->p_time, s->p_mag, s->p_arrival,
+                          s->p_joint};
     double sum = 0.0;
     for (double v : ps) {
         if (!(v >= 0.0)) return fail(CMH_EINVAL, "move probabilities must be non-negative");
@@ -271,6 +281,19 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
     if (s->schedule != 0 && s->schedule != 1) return fail(CMH_EINVAL, "schedule must be 0 or 1");
+    const bool latent = m->line && m->arrival_sd > 0.0;
+    if (!latent && (s->p_arrival != 0.0 || s->p_joint != 0.0))
+        return fail(CMH_EINVAL, "arrival-time and joint moves need latent arrivals");
+    if (latent) {
+        if (s->p_arrival > 0.0 && !(s->step_arrival > 0.0 && std::isfinite(s->step_arrival)))
+            return fail(CMH_EINVAL, "step_arrival must be positive");
+        if (s->p_joint > 0.0 && !(s->step_xy > 0.0 && s->step_t > 0.0))
+            return fail(CMH_EINVAL, "the joint move needs positive step_xy and step_t");
+        if (s->block != 0 && s->block != 256)
+            return fail(CMH_EINVAL, "latent arrivals run the block-256 form");
+        if (s->schedule != 0)
+            return fail(CMH_EINVAL, "latent arrivals run the chromatic schedule");
+    }
     if (s->schedule == 1) {
         if ((long long)m->nsx * m->nsy * m->n_samples > cmh::kNaiveMax)
             return fail(CMH_EINVAL, "the naive schedule needs stations x samples <= 2048");
@@ -330,6 +353,17 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         g->naive = 1;
         g->ncolors = 1;
     }
+    g->c5 = g->c4 + g->pm;
+    if (latent) {  // Section 3's arrival density, truncated at kArrTrunc sd
+        g->latent = 1;
+        g->arr_sd = m->arrival_sd;
+        g->arr_e = cmh::kArrTrunc * m->arrival_sd;
+        g->arr_2v = 2.0 * (m->arrival_sd * m->arrival_sd);
+        g->pa = s->p_arrival;
+        g->pj = s->p_joint;
+        g->sa = s->step_arrival;
+        g->c6 = g->c5 + g->pa;
+    }
     return CMH_OK;
 }
 
@@ -356,6 +390,7 @@ void carve_events(Carver &c, const Geo &g, int chains, Events *ev)
     ev->id = c.take<unsigned long long>(slots);
     ev->cnt = c.take<int>((size_t)chains * g.R);
     ev->off = c.take<double>((size_t)chains * 2);
+    ev->da = g.latent ? c.take<double>(slots * 8) : nullptr;  // latent arrival offsets
 }
 
 }  // namespace
@@ -376,6 +411,7 @@ struct cmh_state {
     double *partials = nullptr;
     double *llout = nullptr;
     double *draws = nullptr;  // [chain][region][move][8] for the current sweep
+    double *draws2 = nullptr; // latent arrivals: draws 8..15, same layout
     int block = 256;
     const double *feed = nullptr;
     long long feed_first = 0, feed_n = 0;
@@ -420,6 +456,7 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     double *partials = c.take<double>((size_t)chains * cmh::refresh_blocks(g));
     double *llout = c.take<double>((size_t)chains);
     double *draws = c.take<double>((size_t)chains * g.R * (size_t)g.k * 8);
+    double *draws2 = g.latent ? c.take<double>((size_t)chains * g.R * (size_t)g.k * 8) : nullptr;
     cmh::Slot *slots = c.take<cmh::Slot>((size_t)chains);
     unsigned *items_all = c.take<unsigned>((size_t)chains * g.R);
     unsigned *items_col = c.take<unsigned>((size_t)chains * g.R);
@@ -428,6 +465,7 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
         st->items_all = items_all;
         st->items_col = items_col;
         st->draws = draws;
+        st->draws2 = draws2;
         st->E = E;
         st->ev[0] = ev0;
         st->ev[1] = ev1;
@@ -456,9 +494,10 @@ cmh::Slot chain_slot(const cmh_state *st, int c)
         const Events &e = st->ev[b];
         const size_t o = (size_t)c * g.R * g.cap;
         sl.ev[b] = Events{e.x + o, e.y + o, e.t + o, e.m + o, e.id + o, e.cnt + (size_t)c * g.R,
-                          e.off + 2 * (size_t)c};
+                          e.off + 2 * (size_t)c, e.da ? e.da + 8 * o : nullptr};
     }
     sl.draws = st->draws + (size_t)c * g.R * g.k * 8;
+    sl.draws2 = st->draws2 ? st->draws2 + (size_t)c * g.R * g.k * 8 : nullptr;
     sl.stats = st->stats + (size_t)c * cmh::kStats;
     sl.L = st->learned;
     if (sl.L.tab) {
@@ -543,6 +582,8 @@ hipError_t copy_events(const Events &dst, const Events &src, const Geo &g, int c
     if ((e = hipMemcpyAsync(dst.t, src.t, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
     if ((e = hipMemcpyAsync(dst.m, src.m, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
     if ((e = hipMemcpyAsync(dst.id, src.id, slots * 8, hipMemcpyDeviceToDevice, s))) return e;
+    if (src.da && (e = hipMemcpyAsync(dst.da, src.da, slots * 64, hipMemcpyDeviceToDevice, s)))
+        return e;
     if ((e = hipMemcpyAsync(dst.cnt, src.cnt, (size_t)chains * g.R * 4, hipMemcpyDeviceToDevice,
                             s)))
         return e;
@@ -576,7 +617,7 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
     hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
                                      st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
                                      st->log_first, st->log_n, st->err, st->block,
-                                     st->g.naive ? st->naive_elems : 0, s);
+                                     st->g.naive ? st->naive_elems : 0, st->g.latent, s);
     if (!e && st->g.naive)  // the merged events' variance after the single naive phase
         e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
                                       st->f64, st->err, s);
@@ -760,8 +801,9 @@ int32_t cmh_sweep_color(cmh_state *st, int64_t sweep, int32_t color, void *hip_s
     if (sweep < 0 || sweep >= (1LL << 32)) return fail(CMH_EINVAL, "sweep out of range");
     if (st->feed && (sweep < st->feed_first || sweep >= st->feed_first + st->feed_n))
         return fail(CMH_EINVAL, "sweep outside the attached feed");
-    if (st->feed && st->feed_width != (st->learned.tab ? 16 : 8))
-        return fail(CMH_EINVAL, "feed records must be 16 wide with learned births, else 8");
+    if (st->feed && st->feed_width != (st->learned.tab || st->g.latent ? 16 : 8))
+        return fail(CMH_EINVAL,
+                    "feed records must be 16 wide with learned births or latent arrivals, else 8");
     hipStream_t s = (hipStream_t)hip_stream;
     HIPCHK(cmh::set_sweep(st->sweep_ctr, sweep, s));
     HIPCHK(enqueue_phase(st, color, color == 0, s));
@@ -818,6 +860,8 @@ int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64
     HIPCHK(hipMemcpy(t.data(), ev.t + o, slots * 8, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(m.data(), ev.m + o, slots * 8, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(id.data(), ev.id + o, slots * 8, hipMemcpyDeviceToHost));
+    std::vector<double> da(ev.da ? slots * 8 : 0);
+    if (ev.da) HIPCHK(hipMemcpy(da.data(), ev.da, slots * 64, hipMemcpyDeviceToHost));
     int64_t n = 0;
     for (int r = 0; r < g.R; ++r) n += cnt[r];
     *n_out = n;
@@ -830,6 +874,7 @@ int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64
             cmh_event &e = out_host[q++];
             e.x = x[a]; e.y = y[a]; e.t = t[a]; e.m = m[a]; e.id = id[a];
             e.region = r; e._pad = 0;
+            for (int c = 0; c < 8; ++c) e.da[c] = ev.da ? da[a * 8 + c] : 0.0;
         }
     return CMH_OK;
 }
@@ -853,9 +898,14 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
         if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
               e.t < (double)g.N && e.m >= g.mmin))
             return fail(CMH_EINVAL, "event outside the model's support");
+        if (g.latent)
+            for (int c = 0; c < g.nsx; ++c)
+                if (!(std::fabs(e.da[c]) <= g.arr_e))
+                    return fail(CMH_EINVAL, "arrival offset beyond the jitter bound");
         reg[cmh::event_region(g, off[0], off[1], e.x, e.y, e.t)].push_back(e);
     }
     const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
+    std::vector<double> da(g.latent ? slots * 8 : 0, 0.0);
     std::vector<int> cnt(g.R, 0);
     std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0);
     std::vector<unsigned long long> id(slots, 0);
@@ -868,8 +918,11 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
         for (size_t s = 0; s < L.size(); ++s) {
             const size_t a = (size_t)r * g.cap + s;
             x[a] = L[s].x; y[a] = L[s].y; t[a] = L[s].t; m[a] = L[s].m; id[a] = L[s].id;
+            if (g.latent)
+                for (int c = 0; c < g.nsx; ++c) da[a * 8 + c] = L[s].da[c];
         }
     }
+    if (g.latent) HIPCHK(hipMemcpy(ev.da + 8 * o, da.data(), slots * 64, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.cnt + (size_t)chain * g.R, cnt.data(), g.R * sizeof(int),
                      hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.x + o, x.data(), slots * 8, hipMemcpyHostToDevice));
@@ -985,8 +1038,8 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
     if (st->feed || st->logp) return fail(CMH_EINVAL, "detach feed and log before tuning");
     const Geo &g = st->g;
-    if (g.naive) {  // one form only
-        st->block = 64;
+    if (g.naive || g.latent) {  // one form only
+        st->block = g.naive ? 64 : 256;
         return CMH_OK;
     }
     const auto key = std::make_tuple(g.nsx, g.nsy, g.N, g.gx, g.gy, g.k, g.cap, st->chains,
@@ -1066,8 +1119,9 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
     if (st->feed && (first_sweep < st->feed_first ||
                      first_sweep + n_sweeps > st->feed_first + st->feed_n))
         return fail(CMH_EINVAL, "sweeps outside the attached feed");
-    if (st->feed && st->feed_width != (st->learned.tab ? 16 : 8))
-        return fail(CMH_EINVAL, "feed records must be 16 wide with learned births, else 8");
+    if (st->feed && st->feed_width != (st->learned.tab || st->g.latent ? 16 : 8))
+        return fail(CMH_EINVAL,
+                    "feed records must be 16 wide with learned births or latent arrivals, else 8");
     hipStream_t s = (hipStream_t)hip_stream;
     const int nc = st->g.ncolors;
     std::vector<hipEvent_t> ev((size_t)n_sweeps * (nc + 2));
@@ -1192,8 +1246,10 @@ int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *sample
         if (rc) return rc;
         if (P->g[q].R > 65535) return fail(CMH_EINVAL, "at most 65535 regions per instance");
         if (P->g[q].k != P->g[0].k || P->g[q].dynamic != P->g[0].dynamic ||
-            samplers[q].block != samplers[0].block || P->g[q].naive != P->g[0].naive)
-            return fail(CMH_EINVAL, "instances of a batch share k, dynamic, block and schedule");
+            samplers[q].block != samplers[0].block || P->g[q].naive != P->g[0].naive ||
+            P->g[q].latent != P->g[0].latent)
+            return fail(CMH_EINVAL,
+                        "instances of a batch share k, dynamic, block, schedule and latent arrivals");
     }
     P->head = P->g[0];
     for (int q = 0; q < n; ++q) P->head.ncolors = std::max(P->head.ncolors, P->g[q].ncolors);
@@ -1215,6 +1271,7 @@ size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots
         sl.E = c.take<double>((size_t)g.nsta * (size_t)g.N);
         for (int b = 0; b < 2; ++b) carve_events(c, g, 1, &sl.ev[b]);
         sl.draws = c.take<double>((size_t)g.R * g.k * 8);
+        sl.draws2 = g.latent ? c.take<double>((size_t)g.R * g.k * 8) : nullptr;
         sl.stats = c.take<unsigned long long>(cmh::kStats);
         if (slots) (*slots)[q] = sl;
         total_r += g.R;
@@ -1375,7 +1432,12 @@ int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, 
         for (int j = 0; j < model->nsx; ++j) g.sx[j] = model->station_x[j];
         g.rc = INFINITY; g.atten = INFINITY; g.decay = INFINITY; g.att2 = 0.0; g.dec2 = 0.0;
         g.Lx = model->x_max; g.Ly = 1.0;
-        const double wmin = std::max(512.0, (cmh::kTile + g.tmax + g.ts + 1.0) / 23.0);
+        if (model->arrival_sd > 0.0) {  // latent arrivals: offsets stored per event
+            g.latent = 1;
+            g.arr_e = cmh::kArrTrunc * model->arrival_sd;
+        }
+        const double wmin =
+            std::max(512.0, (cmh::kTile + g.tmax + g.ts + 2.0 * g.arr_e + 1.0) / 23.0);
         g.gx = std::max(1, (int)((double)g.N / wmin));
         g.gy = 0; g.nrx = g.gx + 1; g.nry = 1; g.R = g.nrx;
         g.wx = (double)g.N / (double)g.gx; g.wy = 0.0;
@@ -1386,6 +1448,10 @@ int32_t truth_layout(const cmh_model *model, const cmh_event *truth, int64_t n, 
         if (!(e.x >= 0.0 && e.x < g.Lx && e.y >= 0.0 && e.y < g.Ly && e.t >= 0.0 &&
               e.t < (double)g.N && std::isfinite(e.m)))
             return fail(CMH_EINVAL, "truth event outside the domain");
+        if (g.latent)
+            for (int c = 0; c < g.nsx; ++c)
+                if (!(std::fabs(e.da[c]) <= g.arr_e))
+                    return fail(CMH_EINVAL, "truth arrival offset beyond the jitter bound");
         L->cells[cmh::event_region(g, 0.0, 0.0, e.x, e.y, e.t)].push_back(e);
     }
     L->cap = 1;
@@ -1444,12 +1510,15 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
     std::vector<int> cnt(g.R, 0);
     std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0), off(2, 0.0);
     std::vector<unsigned long long> id(slots, 0);
+    std::vector<double> da(g.latent ? slots * 8 : 0, 0.0);
     for (int r = 0; r < g.R; ++r) {
         cnt[r] = (int)L.cells[r].size();
         for (size_t s = 0; s < L.cells[r].size(); ++s) {
             const size_t a = (size_t)r * g.cap + s;
             const cmh_event &e = L.cells[r][s];
             x[a] = e.x; y[a] = e.y; t[a] = e.t; m[a] = e.m; id[a] = e.id;
+            if (g.latent)
+                for (int c = 0; c < g.nsx; ++c) da[a * 8 + c] = e.da[c];
         }
     }
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1460,6 +1529,7 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
     HIPCHK(hipMemcpyAsync(ev.m, m.data(), slots * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ev.id, id.data(), slots * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ev.off, off.data(), 16, hipMemcpyHostToDevice, s));
+    if (g.latent) HIPCHK(hipMemcpyAsync(ev.da, da.data(), slots * 64, hipMemcpyHostToDevice, s));
     HIPCHK(cmh::fill_i32(err, 1, 0, s));
     HIPCHK(cmh::launch_simulate(g, ev, seed, trace_dev, trace_dtype == CMH_F64, err, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1476,6 +1546,17 @@ int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t r
     if (width != 8 && width != 16) return fail(CMH_EINVAL, "width must be 8 or 16");
     if (count == 0) return CMH_OK;
     HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, width, out_dev,
+                             (hipStream_t)hip_stream));
+    return CMH_OK;
+}
+
+int32_t cmh_move_draws_arrivals(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region,
+                                uint32_t j0, int32_t count, double *out_dev, void *hip_stream)
+{
+    if (count < 0 || (count > 0 && !out_dev)) return fail(CMH_EINVAL, "bad arguments");
+    if (count == 0) return CMH_OK;
+    // width code 17: the latent-arrival records (16 wide) of the draw kernel
+    HIPCHK(cmh::launch_draws(seed, chain, sweep, region, j0, count, 17, out_dev,
                              (hipStream_t)hip_stream));
     return CMH_OK;
 }

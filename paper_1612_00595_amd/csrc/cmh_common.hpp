@@ -25,8 +25,15 @@ constexpr int kNaiveMax = 2048;      // stations x samples of an instance, naive
 enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16 };
 
 // Per-chain statistics: [3 t + 0..2] attempted / evaluated / accepted moves of
-// type t, [15] footprint samples evaluated, [16] footprint samples rewritten.
-constexpr int kStats = 17;
+// type t < 5, [15] footprint samples evaluated, [16] footprint samples
+// rewritten, [17 + 3 (t - 5) + 0..2] the same for the latent-arrival moves
+// t = 5 (arrival time) and t = 6 (joint).
+constexpr int kStats = 23;
+__host__ __device__ constexpr int stat_base(int t) { return t < 5 ? 3 * t : 17 + 3 * (t - 5); }
+
+// The arrival-time jitter of latent arrivals is truncated at this many
+// standard deviations.
+constexpr double kArrTrunc = 4.0;
 
 // Model, partition and sampler constants (by value in every kernel).
 struct Geo {
@@ -51,6 +58,14 @@ struct Geo {
     int naive, pad_naive;   // 1: the naive schedule (Algorithm 3), one phase
     double tmax;            // longest travel time from the line to a station
     double sx[8];
+    // Latent arrival times (line model, arrival_sd > 0): every event carries
+    // per-station offsets (Events::da), its arrival at station j is
+    // t + d / vel + da[j] with |da[j]| <= arr_e, and two more move types
+    // exist: 5, the arrival-time move, and 6, the joint two-event move.
+    int latent, pad_latent;
+    double arr_sd, arr_e, arr_2v;  // arrival_sd; kArrTrunc * arrival_sd; 2 arrival_sd^2
+    double pa, pj, sa;      // arrival and joint move probabilities, arrival step
+    double c5, c6;          // cumulative thresholds after the magnitude, arrival moves
 };
 
 // Learned birth proposal: a mixture over the anchors (station, window) of
@@ -81,6 +96,7 @@ struct Events {
     unsigned long long *id;
     int *cnt;
     double *off;
+    double *da;  // latent arrivals: [slot][8] per-station offsets, else nullptr
 };
 
 // One chain of one instance as the sweep kernels see it: the instance's
@@ -96,6 +112,7 @@ struct Slot {
     double *E;            // [nsta][N]
     Events ev[2];         // ping-pong tables of the dynamic re-layout
     double *draws;
+    double *draws2;       // latent arrivals: draws 8..15 of each record [R][k][8]
     unsigned long long *stats;
     Learned L;
 };
@@ -182,15 +199,16 @@ struct Arrival {
 };
 
 // The station sits at (px, py): station_pos of its grid cell, or its place
-// on the line (y = 0) in the line model.
+// on the line (y = 0) in the line model.  eps is the event's arrival offset
+// at this station (latent arrivals; 0 otherwise).
 __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, double m, double px,
-                                 double py)
+                                 double py, double eps)
 {
     Arrival ar;
     const double dx = x - px;
     const double dy = y - py;
     const double d = sqrt(dx * dx + dy * dy);
-    const double a = t + d / g.vel;
+    const double a = t + d / g.vel + eps;
     const double c = ceil(a);
     ar.in = 0;
     ar.n0 = 0;

@@ -151,6 +151,116 @@ __device__ inline void move_draws16(uint32_t seed, uint32_t chain, uint32_t swee
     out[14] = 0.0; out[15] = 0.0;
 }
 
+// Draw record of 16 for latent arrival times: the 8 above, then [8..15]
+// eight standard normals truncated to [-4, 4] (a birth's arrival offsets in
+// station order; the joint move's second event takes [8], [9]): Box-Muller
+// pairs from counter blocks 4, 5, ... (cosine, then sine), the first eight
+// of absolute value at most 4; after blocks 4 .. 19 missing ones are 0.
+__device__ inline void move_draws_arr(uint32_t seed, uint32_t chain, uint32_t sweep,
+                                      uint32_t region, uint32_t j, double out[16])
+{
+    move_draws(seed, chain, sweep, region, j, out);
+    int got = 0;
+    for (uint32_t blk = 4; blk < 20 && got < 8; ++blk) {
+        uint32_t c[4] = {sweep, region, j, blk};
+        philox10(c, seed, chain);
+        const double u1 = unit_open(c[0], c[1]), u2 = unit_open(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1));
+        const double zc = rad * cos(2.0 * M_PI * u2), zs = rad * sin(2.0 * M_PI * u2);
+        if (fabs(zc) <= 4.0) out[8 + got++] = zc;
+        if (got < 8 && fabs(zs) <= 4.0) out[8 + got++] = zs;
+    }
+    for (; got < 8; ++got) out[8 + got] = 0.0;
+}
+
+// ------------------------------------------------ latent arrivals (line model)
+// Arrival time of a line-model event at (x, t) at the station at px, with
+// offset eps (the arithmetic of arrive).
+__device__ inline double line_arrival(const Geo &g, double x, double t, double px, double eps)
+{
+    const double dx = x - px;
+    const double dy = 0.0 - 0.0;
+    const double d = sqrt(dx * dx + dy * dy);
+    return t + d / g.vel + eps;
+}
+
+// One interval of the least-squares location fit that the joint move of
+// Section 3 proposes around: minimise F(x, t) = sum_j (a_j - t - |x - sx_j|
+// / vel)^2.  Breakpoints are 0, the stations strictly inside (0, x_max) in
+// index order, and x_max; breakpoint q is the interval's lower end, the next
+// larger breakpoint its upper end.  On the interval |x - sx_j| = g_j (x -
+// sx_j), g_j = +1 for stations at or left of its midpoint, else -1, so
+// c_j = a_j + g_j sx_j / vel = t + g_j x / vel is a straight-line regression
+// of c on g (slope x / vel; the midpoint when all g_j agree).  x is clamped
+// to the interval and t is the mean of a_j - |x - sx_j| / vel.  Returns F,
+// or infinity when q names no interval.  The fit is the interval with the
+// smallest F, the first on ties.
+__device__ inline double fit_interval(const Geo &g, const double *lsx, const double *a, int q,
+                                      double *xo, double *to)
+{
+    const int ns = g.nsx;
+    double lo = 0.0;
+    bool found = q == 0;
+    int cnt = 1;
+    for (int j = 0; j < ns; ++j) {
+        const double sj = lsx[j];
+        if (sj > 0.0 && sj < g.Lx) {
+            if (cnt == q) { lo = sj; found = true; }
+            ++cnt;
+        }
+    }
+    if (!found && q == cnt) { lo = g.Lx; found = true; }
+    *xo = 0.0;
+    *to = 0.0;
+    if (!found) return INFINITY;
+    double hi = INFINITY;
+    for (int j = 0; j < ns; ++j) {
+        const double sj = lsx[j];
+        if (sj > 0.0 && sj < g.Lx && sj > lo && sj < hi) hi = sj;
+    }
+    if (g.Lx > lo && g.Lx < hi) hi = g.Lx;
+    if (hi == INFINITY) return INFINITY;
+    const double mid = 0.5 * (lo + hi);
+    double gbar = 0.0, cbar = 0.0;
+    for (int j = 0; j < ns; ++j) {
+        const double sg = lsx[j] <= mid ? 1.0 : -1.0;
+        gbar += sg;
+        cbar += a[j] + sg * lsx[j] / g.vel;
+    }
+    gbar /= (double)ns;
+    cbar /= (double)ns;
+    double sgg = 0.0, sgc = 0.0;
+    for (int j = 0; j < ns; ++j) {
+        const double sg = lsx[j] <= mid ? 1.0 : -1.0;
+        const double cj = a[j] + sg * lsx[j] / g.vel;
+        const double dg = sg - gbar;
+        sgg += dg * dg;
+        sgc += dg * (cj - cbar);
+    }
+    double x = sgg > 0.0 ? g.vel * (sgc / sgg) : mid;
+    if (x < lo) x = lo;
+    if (x > hi) x = hi;
+    double t = 0.0;
+    for (int j = 0; j < ns; ++j) t += a[j] - fabs(x - lsx[j]) / g.vel;
+    t /= (double)ns;
+    double f = 0.0;
+    for (int j = 0; j < ns; ++j) {
+        const double r = (a[j] - t) - fabs(x - lsx[j]) / g.vel;
+        f += r * r;
+    }
+    *xo = x;
+    *to = t;
+    return f;
+}
+
+// LDS scratch of the joint move: the four fits' arrivals (exchanged
+// arrivals of both events, then their original arrivals) and every
+// interval's result.
+struct JointScratch {
+    double in[4][8];
+    double f[4][10], x[4][10], t[4][10];
+};
+
 // Stations whose position falls in region (i, kk) of a partition with
 // offsets (offx, offy), in ascending index; returns their number (only the
 // first `cap` are stored).  Candidates are the cells around the region's
@@ -311,6 +421,7 @@ struct MoveHdr {
     int flags;  // error flags, raised only when the move is consumed
     double dm;  // magnitude change (magnitude move)
     double lr;  // learned births: log(b / p_R) at the born or dying event
+    double lx;  // latent arrivals: prior and proposal part of log alpha (moves 5, 6)
 };
 
 // A region's learned-birth constants, staged in LDS by the sweep workgroup.
@@ -367,7 +478,7 @@ __device__ inline RegionBox region_box(const Geo &g, double offx, double offy, i
 __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
                           double om, bool has_new, double nx, double ny, double nt, double nm,
                           Seg *segs, SegIndex *six, const double *lsx, int *nseg_out, int *S_out,
-                          int *flags)
+                          int *flags, const double *oda = nullptr, const double *nda = nullptr)
 {
     int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
     if (has_old) {
@@ -400,9 +511,12 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
             iy = cy0 + cidx / bw;
             // line stations from lsx (LDS): a Geo held in registers must not
             // be indexed dynamically, which would move it to scratch memory
-            if (mine)
+            if (mine) {
+                // latent arrivals: the event's offset at this station (LDS)
+                const double *eda = half ? nda : oda;
                 ar = arrive(g, ex, ey, et, em, g.line ? lsx[ix] : station_pos(ix, g.ds),
-                            g.line ? 0.0 : station_pos(iy, g.ds));
+                            g.line ? 0.0 : station_pos(iy, g.ds), eda != nullptr ? eda[ix] : 0.0);
+            }
         }
         // lanes 0-31 take the new event's arrival from their partner lane
         // (the two halves of the wave swapped in registers)
@@ -467,23 +581,42 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
 }
 
 // ------------------------------------------------------------ sweep colour
+// Latent arrivals' per-move LDS of the latency form: the proposed offsets of
+// the (up to two) changed events, the joint move's second event (x, t,
+// index), and the joint move's fit scratch.
+struct LatentLds {
+    double pda[2][2][8];
+    double prop2[2][3];
+    JointScratch js;
+};
+
 // Wave 0 of a sweep workgroup ("scout"): builds move jj's proposal from its
 // draws and the region's current events, and its footprint, into buffer
 // `buf`.  Lane 0 owns the event table; the other lanes help with the
-// footprint.
+// footprint.  LAT: latent arrival times (line model), with the arrival-time
+// move (type 5) and the joint two-event move (type 6); d2 holds draws 8..15
+// and s_da the events' offsets.
+template <bool LAT>
 __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk, double offx,
                                   double offy, double x0, double x1, double y0, double y1, int n,
                                   const double *d, const double *s_ex, const double *s_ey,
                                   const double *s_et, const double *s_em, Seg (*s_seg)[kMaxSeg],
                                   SegIndex *s_six, const double *lsx, MoveHdr *s_hdr, double (*s_prop)[5], int max_samples,
                                   const Learned &L, const double *lb, const int *lsta,
-                                  const RegionLearned &rl)
+                                  const RegionLearned &rl, const double *d2 = nullptr,
+                                  const double (*s_da)[8] = nullptr, LatentLds *lat = nullptr)
 {
     int type = 0, valid = 0, idx = -1, mflags = 0;
-    double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0, lr = 0;
+    double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0, lr = 0, lx = 0;
+    int idx2 = -1, split = 0;
     if (lane == 0) {
         const double u = d[0];
         type = u < g.c1 ? 0 : u < g.c2 ? 1 : u < g.c3 ? 2 : u < g.c4 ? 3 : 4;
+        if (LAT && type == 4 && !(u < g.c5)) type = u < g.c6 ? 5 : 6;
+        if (LAT) {  // the new event's offsets start as the old one's (or none)
+            double *pd = lat->pda[buf][0];
+            for (int q = 0; q < 8; ++q) pd[q] = 0.0;
+        }
         if (type == 0) {
             if (n >= g.cap) {
                 mflags |= kFlagCap;
@@ -494,6 +627,8 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
                 nm = g.mmin;
                 valid = nx >= 0.0 && nx < g.Lx && nt >= 0.0 && nt < (double)g.N &&
                         in_region_axis(nt, y0, y1, offx, g.wx, g.gx, i);
+                if (LAT)  // offsets from their prior: arrival_sd times truncated normals
+                    for (int q = 0; q < g.nsx; ++q) lat->pda[buf][0][q] = g.arr_sd * d2[q];
             } else {
                 if (L.tab != nullptr) {  // derived for the sweep by the draw kernel
                     nx = lb[0]; ny = lb[1]; nt = lb[2]; lr = lb[3];
@@ -507,13 +642,49 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
                         nt < (double)g.N && in_region_axis(nx, x0, x1, offx, g.wx, g.gx, i) &&
                         in_region_axis(ny, y0, y1, offy, g.wy, g.gy, kk);
             }
+        } else if (LAT && type == 6) {
+            // joint move: the pair and the station split; the arrivals to
+            // fit go to LDS for the wave
+            if (n >= 2 && g.nsx >= 2) {
+                idx = (int)floor(d[1] * (double)n);
+                if (idx >= n) idx = n - 1;
+                idx2 = (int)floor(d[2] * (double)(n - 1));
+                if (idx2 >= n - 1) idx2 = n - 2;
+                if (idx2 >= idx) idx2 += 1;
+                split = 1 + (int)floor(d[3] * (double)(g.nsx - 1));
+                if (split >= g.nsx) split = g.nsx - 1;
+                valid = s_em[idx] == s_em[idx2];
+                if (valid)
+                    for (int q = 0; q < g.nsx; ++q) {
+                        const double ai = line_arrival(g, s_ex[idx], s_et[idx], lsx[q], s_da[idx][q]);
+                        const double ak = line_arrival(g, s_ex[idx2], s_et[idx2], lsx[q], s_da[idx2][q]);
+                        lat->js.in[0][q] = q >= split ? ak : ai;
+                        lat->js.in[1][q] = q >= split ? ai : ak;
+                        lat->js.in[2][q] = ai;
+                        lat->js.in[3][q] = ak;
+                    }
+            }
         } else if (n > 0) {
             idx = (int)floor(d[1] * (double)n);
             if (idx >= n) idx = n - 1;
             ox = s_ex[idx]; oy = s_ey[idx]; ot = s_et[idx]; om = s_em[idx];
             nx = ox; ny = oy; nt = ot; nm = om;
             valid = 1;
-            if (g.line) {  // location moves keep the region; onset moves must
+            if (LAT) {  // carried along by location and onset moves
+                double *pd = lat->pda[buf][0];
+                for (int q = 0; q < 8; ++q) pd[q] = s_da[idx][q];
+            }
+            if (LAT && type == 5) {
+                // arrival-time move: one station's offset takes a Gaussian
+                // step; its prior density enters the ratio
+                int js = (int)floor(d[2] * (double)g.nsx);
+                if (js >= g.nsx) js = g.nsx - 1;
+                const double o = s_da[idx][js];
+                const double w = o + g.sa * d[5];
+                lat->pda[buf][0][js] = w;
+                valid = fabs(w) <= g.arr_e;
+                lx = (o * o - w * w) / g.arr_2v;
+            } else if (g.line) {  // location moves keep the region; onset moves must
                 if (type == 2) {
                     nx = ox + g.sxy * d[5];
                     valid = nx >= 0.0 && nx < g.Lx;
@@ -541,6 +712,80 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
     }
     type = __builtin_amdgcn_readlane(type, 0);
     valid = __builtin_amdgcn_readlane(valid, 0);
+    if (LAT && type == 6 && valid) {
+        // the four least-squares fits, one interval per lane, then the
+        // proposal around the exchanged arrivals' fits (lane 0)
+        __builtin_amdgcn_wave_barrier();
+        JointScratch &js = lat->js;
+        if (lane < 40) {
+            const int f = lane / 10, q = lane % 10;
+            double fx, ft;
+            const double F = fit_interval(g, lsx, js.in[f], q, &fx, &ft);
+            js.f[f][q] = F;
+            js.x[f][q] = fx;
+            js.t[f][q] = ft;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            double bx[4], bt[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                double best = INFINITY;
+                bx[f] = 0.0;
+                bt[f] = 0.0;
+                for (int q = 0; q < 10; ++q)
+                    if (js.f[f][q] < best) {
+                        best = js.f[f][q];
+                        bx[f] = js.x[f][q];
+                        bt[f] = js.t[f][q];
+                    }
+            }
+            const int ev2[2] = {idx, idx2};
+            const double zx[2] = {d[5], d2[0]}, zt[2] = {d[6], d2[1]};
+            double px[2], pt[2];
+            int ok = 1;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                px[e] = bx[e] + g.sxy * zx[e];
+                pt[e] = bt[e] + g.st * zt[e];
+                ok = ok && px[e] >= 0.0 && px[e] < g.Lx && pt[e] >= 0.0 && pt[e] < (double)g.N &&
+                     in_region_axis(pt[e], y0, y1, offx, g.wx, g.gx, i);
+                double *pd = lat->pda[buf][e];
+                for (int q = 0; q < 8; ++q) pd[q] = 0.0;
+                for (int q = 0; q < g.nsx && ok; ++q) {
+                    const double target = js.in[e][q];
+                    const double w = target - line_arrival(g, px[e], pt[e], lsx[q], 0.0);
+                    pd[q] = w;
+                    // the offset stays in its support, and the window starts
+                    // at the sample of the arrival it takes over
+                    ok = fabs(w) <= g.arr_e &&
+                         ceil(line_arrival(g, px[e], pt[e], lsx[q], w)) == ceil(target);
+                }
+            }
+            valid = ok;
+            if (ok) {
+                double lp = 0.0, lq = 0.0;
+                for (int e = 0; e < 2; ++e)
+                    for (int q = 0; q < g.nsx; ++q) {
+                        const double o = s_da[ev2[e]][q], w = lat->pda[buf][e][q];
+                        lp += (o * o - w * w) / g.arr_2v;
+                    }
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double rx = (s_ex[ev2[e]] - bx[2 + e]) / g.sxy;
+                    const double rt = (s_et[ev2[e]] - bt[2 + e]) / g.st;
+                    lq += 0.5 * (zx[e] * zx[e] + zt[e] * zt[e]) - 0.5 * (rx * rx + rt * rt);
+                }
+                lx = lp + lq;
+                nx = px[0]; ny = 0.0; nt = pt[0]; nm = s_em[idx];
+                ox = s_ex[idx]; ot = s_et[idx]; om = nm;
+                lat->prop2[buf][0] = px[1];
+                lat->prop2[buf][1] = pt[1];
+                lat->prop2[buf][2] = (double)idx2;
+            }
+        }
+        valid = __builtin_amdgcn_readlane(valid, 0);
+    }
     if (type == 1 && valid && rl.pl > 0.0) {
         // death under learned births: the birth density at the dying event,
         // (station, window) pairs spread over the lanes
@@ -551,14 +796,23 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
         lr = learned_log_ratio(rl.pl, S, rl.W, rl.area, g.N);
     }
     int nseg = 0, S = 0;
-    if (valid && !g.prior_only) {
+    // the joint move leaves every station's set of signals unchanged: no
+    // footprint, a likelihood change of zero
+    if (valid && !g.prior_only && !(LAT && type == 6)) {
         ox = lane_f64(ox, 0); oy = lane_f64(oy, 0);
         ot = lane_f64(ot, 0); om = lane_f64(om, 0);
         nx = lane_f64(nx, 0); ny = lane_f64(ny, 0);
         nt = lane_f64(nt, 0); nm = lane_f64(nm, 0);
         int fl = 0;
+        const double *oda = nullptr, *nda = nullptr;
+        if (LAT) {
+            __builtin_amdgcn_wave_barrier();  // lane 0's offsets are in LDS
+            const int io = __builtin_amdgcn_readlane(idx, 0);
+            oda = type != 0 ? s_da[io] : nullptr;
+            nda = type != 1 ? lat->pda[buf][0] : nullptr;
+        }
         footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
-                  &s_six[buf], lsx, &nseg, &S, &fl);
+                  &s_six[buf], lsx, &nseg, &S, &fl, oda, nda);
         if (__ballot(fl != 0) != 0ull || S > max_samples) {
             valid = 0;
             mflags |= kFlagSeg;
@@ -569,6 +823,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
         h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.flags = mflags;
         h.dm = nm - om;
         h.lr = lr;
+        h.lx = lx;
         s_hdr[buf] = h;
         s_prop[buf][0] = nx; s_prop[buf][1] = ny; s_prop[buf][2] = nt; s_prop[buf][3] = nm;
         s_prop[buf][4] = (double)idx;
@@ -590,7 +845,10 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
 // The event variance of other regions is read but never written: the
 // colouring guarantees that no station is reached from two regions of one
 // colour (the Markov-blanket argument of Section 4.1).
-template <typename TraceT, int BLOCK>
+// LAT: latent arrival times (line model): the events' offsets live in LDS
+// next to their coordinates, draws 8..15 come from the slot's draws2, and
+// the scout also builds arrival-time and joint moves.
+template <typename TraceT, int BLOCK, bool LAT>
 __global__ void __launch_bounds__(BLOCK)
 k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
               const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
@@ -615,6 +873,10 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     __shared__ double s_prop[2][5];
     __shared__ double s_part[2][W];
     __shared__ int s_n;
+    // latent arrivals only (one-element stand-ins when LAT is false)
+    __shared__ double s_draw2[LAT ? 2 : 1][LAT ? kDrawChunk : 1][8];
+    __shared__ double s_da[LAT ? kMaxCap : 1][8];
+    __shared__ LatentLds s_lat[1];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned item = items[blockIdx.x];
@@ -648,12 +910,19 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         s_et[s] = ev.t[base + s]; s_em[s] = ev.m[base + s];
         s_id[s] = ev.id[base + s];
     }
+    const double *dsrc2 = nullptr;
+    if constexpr (LAT) {
+        for (int q = tid; q < n * 8; q += BLOCK) s_da[q >> 3][q & 7] = ev.da[base * 8 + q];
+        dsrc2 = slots[slot].draws2 + ((long long)chain * g.R + r) * (long long)g.k * 8;
+    }
     for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
     if (tid < 8) s_lsx[tid] = slots[slot].g.sx[tid];
     for (int c = 0; c < 2 && 64 * c < g.k; ++c) {
         const int m = min(kDrawChunk, g.k - 64 * c) * 8;
         for (int q = tid; q < m; q += BLOCK) s_draw[c][q >> 3][q & 7] = dsrc[64LL * 8 * c + q];
+        if constexpr (LAT)
+            for (int q = tid; q < m; q += BLOCK) s_draw2[c][q >> 3][q & 7] = dsrc2[64LL * 8 * c + q];
         if (lsrc != nullptr)
             for (int q = tid; q < m / 2; q += BLOCK)
                 s_lb[c][q >> 2][q & 3] = lsrc[64LL * 4 * c + q];
@@ -679,15 +948,15 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
 
     const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
-    unsigned int cnt_att[5] = {0, 0, 0, 0, 0}, cnt_val[5] = {0, 0, 0, 0, 0},
-                 cnt_acc[5] = {0, 0, 0, 0, 0};
+    constexpr int NT = LAT ? 7 : 5;  // move types
+    unsigned int cnt_att[NT] = {}, cnt_val[NT] = {}, cnt_acc[NT] = {};
     unsigned long long samp_read = 0, samp_written = 0;
     __syncthreads();
     const RegionLearned rl = s_rl;
     if (wave == 0)
-        scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex, s_ey,
-                   s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L, s_lb[0][0],
-                   s_lsta, rl);
+        scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex,
+                        s_ey, s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
+                        s_lb[0][0], s_lsta, rl, LAT ? s_draw2[0][0] : nullptr, s_da, s_lat);
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -698,6 +967,9 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             const int m = min(kDrawChunk, g.k - (j + 1)) * 8;
             for (int q = tid; q < m; q += BLOCK)
                 s_draw[c & 1][q >> 3][q & 7] = dsrc[(long long)(j + 1) * 8 + q];
+            if constexpr (LAT)
+                for (int q = tid; q < m; q += BLOCK)
+                    s_draw2[c & 1][q >> 3][q & 7] = dsrc2[(long long)(j + 1) * 8 + q];
             if (lsrc != nullptr)
                 for (int q = tid; q < m / 2; q += BLOCK)
                     s_lb[c & 1][q >> 2][q & 3] = lsrc[(long long)(j + 1) * 4 + q];
@@ -716,10 +988,12 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         double prod = 1.0, lin = 0.0;
         if (wave == 0) {
             if (j + 1 < g.k)  // speculative: the state as if move j is rejected
-                scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                           s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em, s_seg,
-                           s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
-                           s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
+                scout_move<LAT>(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                                s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em,
+                                s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
+                                s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl,
+                                LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr, s_da,
+                                s_lat);
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
@@ -782,6 +1056,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
         else if (h.type == 4)
             la = delta - g.mrate * h.dm;
+        else if (LAT && h.type >= 5)
+            la = delta + h.lx;
         else
             la = delta;
         bool accept = h.valid && lnu < la;
@@ -838,6 +1114,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                     s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
                     s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
                               ((unsigned long long)r << 12) | (unsigned long long)j;
+                    if constexpr (LAT)
+                        for (int q = 0; q < 8; ++q) s_da[n][q] = s_lat->pda[buf][0][q];
                     ++n;
                 } else if (h.type == 1) {
                     const int idx = (int)pr[4];
@@ -845,11 +1123,22 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                         s_ex[q] = s_ex[q + 1]; s_ey[q] = s_ey[q + 1];
                         s_et[q] = s_et[q + 1]; s_em[q] = s_em[q + 1];
                         s_id[q] = s_id[q + 1];
+                        if constexpr (LAT)
+                            for (int c = 0; c < 8; ++c) s_da[q][c] = s_da[q + 1][c];
                     }
                     --n;
                 } else {
                     const int idx = (int)pr[4];
                     s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
+                    if constexpr (LAT) {
+                        for (int q = 0; q < 8; ++q) s_da[idx][q] = s_lat->pda[buf][0][q];
+                        if (h.type == 6) {  // the joint move's second event
+                            const double *p2 = s_lat->prop2[buf];
+                            const int i2 = (int)p2[2];
+                            s_ex[i2] = p2[0]; s_et[i2] = p2[1];
+                            for (int q = 0; q < 8; ++q) s_da[i2][q] = s_lat->pda[buf][1][q];
+                        }
+                    }
                 }
             }
             n = __builtin_amdgcn_readlane(n, 0);
@@ -866,7 +1155,9 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             bool rebuild;
             int patch_idx = -1;
             const int n1 = h.type == 0 ? h.n + 1 : h.n - 1;
-            if (h.type >= 2) {
+            if (LAT && (h.type == 6 || nx.type == 6)) {
+                rebuild = true;  // two events involved: built again
+            } else if (h.type >= 2) {
                 rebuild = nx.type != 0 && s_prop[buf ^ 1][4] == s_prop[buf][4];
             } else if (nx.type == 0) {
                 rebuild = !(h.n < g.cap && n1 < g.cap);
@@ -884,10 +1175,13 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             if (j + 1 < g.k) {
                 if (rebuild) {
                     if (wave == 0)
-                        scout_move(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
-                                   s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et,
-                                   s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
-                                   s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl);
+                        scout_move<LAT>(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
+                                        s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey,
+                                        s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop,
+                                        kMaxFootprint, L, s_lb[((j + 1) >> 6) & 1][(j + 1) & 63],
+                                        s_lsta, rl,
+                                        LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr,
+                                        s_da, s_lat);
                     __syncthreads();
                 } else if (h.type <= 1) {
                     if (tid == 0) {
@@ -908,13 +1202,16 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         ev.t[base + s] = s_et[s]; ev.m[base + s] = s_em[s];
         ev.id[base + s] = s_id[s];
     }
+    if constexpr (LAT)
+        for (int q = tid; q < nf * 8; q += BLOCK) ev.da[base * 8 + q] = s_da[q >> 3][q & 7];
     if (tid == 0) {
         ev.cnt[chain * g.R + r] = nf;
         unsigned long long *st = stats + (long long)chain * kStats;
-        for (int t = 0; t < 5; ++t) {
-            if (cnt_att[t]) atomicAdd(&st[3 * t + 0], (unsigned long long)cnt_att[t]);
-            if (cnt_val[t]) atomicAdd(&st[3 * t + 1], (unsigned long long)cnt_val[t]);
-            if (cnt_acc[t]) atomicAdd(&st[3 * t + 2], (unsigned long long)cnt_acc[t]);
+        for (int t = 0; t < NT; ++t) {
+            const int sb = stat_base(t);
+            if (cnt_att[t]) atomicAdd(&st[sb + 0], (unsigned long long)cnt_att[t]);
+            if (cnt_val[t]) atomicAdd(&st[sb + 1], (unsigned long long)cnt_val[t]);
+            if (cnt_acc[t]) atomicAdd(&st[sb + 2], (unsigned long long)cnt_acc[t]);
         }
         if (samp_read) atomicAdd(&st[15], samp_read);
         if (samp_written) atomicAdd(&st[16], samp_written);
@@ -1139,7 +1436,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                     s_lb[wv][q >> 2][q & 3] = lsrc[(long long)j * 4 + q];
             __builtin_amdgcn_wave_barrier();
         }
-        scout_move(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey, et,
+        scout_move<false>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey, et,
                    em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L, s_lb[wv][jw],
                    s_lsta[wv], rl);
         __builtin_amdgcn_wave_barrier();
@@ -1225,7 +1522,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
 // Every move's draw record for one sweep: per slot [region][move][8], from
 // Philox under the slot's key (or, for slot 0 in replay mode, copied from
 // the caller's feed, records of 8, or of 16 with learned births, whose draws
-// 8..15 go to the slot's L.raw for k_learned_births).  One thread per move
+// 8..15 go to the slot's L.raw for k_learned_births, or with latent
+// arrivals, whose draws 8..15 go to the slot's draws2).  One thread per move
 // of every region of every slot (all slots take k moves per region).
 __global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                               long long nmoves, int k, const long long *__restrict__ sweep_ptr,
@@ -1238,11 +1536,14 @@ __global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__
     const Slot &S = slots[slot];
     const long long sweep = *sweep_ptr;
     const bool learned = S.L.tab != nullptr;
+    const bool latent = S.draws2 != nullptr;
     const long long mv = (long long)r * k + j;
     double d[16];
     if (feed != nullptr && slot == 0) {
         const double *row = feed + ((sweep - feed_first) * (long long)S.g.R * k + mv) * width;
         for (int c = 0; c < width; ++c) d[c] = row[c];
+    } else if (latent) {
+        move_draws_arr(S.g.seed, S.chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
     } else if (learned) {
         move_draws16(S.g.seed, S.chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
     } else {
@@ -1253,6 +1554,10 @@ __global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__
     if (learned) {
         double *raw = S.L.raw + mv * 8;
         for (int c = 0; c < 8; ++c) raw[c] = d[8 + c];
+    }
+    if (latent) {
+        double *d2 = S.draws2 + mv * 8;
+        for (int c = 0; c < 8; ++c) d2[c] = d[8 + c];
     }
 }
 
@@ -1520,6 +1825,9 @@ __global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restri
                     dst.t[dbase + pos] = dst.t[dbase + pos - 1];
                     dst.m[dbase + pos] = dst.m[dbase + pos - 1];
                     dst.id[dbase + pos] = dst.id[dbase + pos - 1];
+                    if (g.latent)
+                        for (int q = 0; q < 8; ++q)
+                            dst.da[(dbase + pos) * 8 + q] = dst.da[(dbase + pos - 1) * 8 + q];
                     --pos;
                 }
                 dst.x[dbase + pos] = x;
@@ -1527,6 +1835,9 @@ __global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restri
                 dst.t[dbase + pos] = src.t[sbase + s];
                 dst.m[dbase + pos] = src.m[sbase + s];
                 dst.id[dbase + pos] = id;
+                if (g.latent)
+                    for (int q = 0; q < 8; ++q)
+                        dst.da[(dbase + pos) * 8 + q] = src.da[(sbase + s) * 8 + q];
                 ++n;
             }
         }
@@ -1554,8 +1865,9 @@ __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int
         const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
         int i0, i1, k0, k1;
         if (g.line) {  // onsets whose signal can meet the tile at any station
-            i0 = region_axis((double)n_lo - g.tmax - (double)g.ts - 1.0, offx, g.wx, g.gx);
-            i1 = region_axis((double)n_hi, offx, g.wx, g.gx);
+            i0 = region_axis((double)n_lo - g.tmax - (double)g.ts - 1.0 - g.arr_e, offx, g.wx,
+                             g.gx);
+            i1 = region_axis((double)n_hi + g.arr_e, offx, g.wx, g.gx);
             k0 = 0;
             k1 = 0;
         } else {
@@ -1594,7 +1906,8 @@ __device__ int gather_tile(const Geo &g, const Events &ev, int chain, int j, int
             const long long e = ((long long)chain * g.R + s_rid[q]) * g.cap + (f - s_roff[q]);
             ar = arrive(g, ev.x[e], ev.y[e], ev.t[e], ev.m[e],
                         g.line ? g.sx[ix] : station_pos(ix, g.ds),
-                        g.line ? 0.0 : station_pos(iy, g.ds));
+                        g.line ? 0.0 : station_pos(iy, g.ds),
+                        ev.da != nullptr ? ev.da[e * 8 + ix] : 0.0);
             take = ar.in && ar.n0 < n_hi && ar.n1 > n_lo;
         }
         const unsigned long long mask = __ballot(take);
@@ -1799,11 +2112,14 @@ __global__ void k_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t 
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= count) return;
     double d[16];
-    if (width == 16)
+    if (width == 17)  // latent-arrival records (16 wide)
+        move_draws_arr(seed, chain, sweep, region, j0 + (uint32_t)q, d);
+    else if (width == 16)
         move_draws16(seed, chain, sweep, region, j0 + (uint32_t)q, d);
     else
         move_draws(seed, chain, sweep, region, j0 + (uint32_t)q, d);
-    for (int c = 0; c < width; ++c) out[(long long)q * width + c] = d[c];
+    const int w = width == 17 ? 16 : width;
+    for (int c = 0; c < w; ++c) out[(long long)q * w + c] = d[c];
 }
 
 // Residual of an empty world under the mean-template likelihood: the trace
@@ -1845,10 +2161,15 @@ __global__ void k_advance_sweep(long long *p) { *p += 1; }
 template <typename TraceT>
 static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
                                  const long long *sweep_ptr, double *logp, long long log_first,
-                                 long long log_n, int *err, int block, int naive_elems,
+                                 long long log_n, int *err, int block, int naive_elems, int latent,
                                  hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
+    if (latent) {  // latent arrivals: the latency form of 256 threads only
+        k_sweep_color<TraceT, 256, true><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
+                                                                log_first, log_n, err);
+        return hipGetLastError();
+    }
     if (naive_elems > 0) {
         const size_t lds = (size_t)4 * naive_elems * sizeof(double);
         hipError_t e = hipFuncSetAttribute((const void *)k_sweep_wave<TraceT, true>,
@@ -1865,15 +2186,15 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
                                                                      log_n, err, 0);
         break;
     case 512:
-        k_sweep_color<TraceT, 512><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
+        k_sweep_color<TraceT, 512, false><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
                                                           log_first, log_n, err);
         break;
     case 128:
-        k_sweep_color<TraceT, 128><<<nitems, 128, 0, s>>>(slots, items, par, sweep_ptr, logp,
+        k_sweep_color<TraceT, 128, false><<<nitems, 128, 0, s>>>(slots, items, par, sweep_ptr, logp,
                                                           log_first, log_n, err);
         break;
     default:
-        k_sweep_color<TraceT, 256><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
+        k_sweep_color<TraceT, 256, false><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
                                                           log_first, log_n, err);
         break;
     }
@@ -1882,13 +2203,14 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
 
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
-                        long long log_n, int *err, int block, int naive_elems, hipStream_t s)
+                        long long log_n, int *err, int block, int naive_elems, int latent,
+                        hipStream_t s)
 {
     if (f64)
         return launch_sweep_t<double>(slots, items, nitems, par, sweep_ptr, logp, log_first,
-                                      log_n, err, block, naive_elems, s);
+                                      log_n, err, block, naive_elems, latent, s);
     return launch_sweep_t<float>(slots, items, nitems, par, sweep_ptr, logp, log_first, log_n,
-                                 err, block, naive_elems, s);
+                                 err, block, naive_elems, latent, s);
 }
 
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,

@@ -27,7 +27,7 @@ def instance(w: W.Workload, trace_seed: int = 1000):
     m = O.make_model(**w.model.asdict())
     sp = O.make_sampler(**w.sampler.asdict())
     tr = W.truth_events(w.model, w.seed)
-    truth = O.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
+    truth = O.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"], da=tr.get("da"))
     if w.trace_dtype == "f64":
         s = O.simulate(m, truth, trace_seed + w.seed)
     else:
@@ -47,7 +47,7 @@ def dynamic_small() -> W.Workload:
 
 def compare_events(a: np.ndarray, b: np.ndarray, where: str):
     assert len(a) == len(b), f"{where}: {len(a)} events on the GPU, {len(b)} in the oracle"
-    for f in ("id", "region", "x", "y", "t", "m"):
+    for f in ("id", "region", "x", "y", "t", "m", "da"):
         if not np.array_equal(a[f], b[f]):
             bad = np.nonzero(a[f] != b[f])[0][:5]
             raise AssertionError(f"{where}: field {f} differs at {bad}: {a[f][bad]} vs {b[f][bad]}")
