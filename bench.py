@@ -64,6 +64,8 @@ def parse():
                     help="skip the mean-template likelihood on the main workload's shape")
     ap.add_argument("--no-paper-world", action="store_true",
                     help="skip the paper's own 1-D experiment (50 worlds x 5 runs)")
+    ap.add_argument("--no-paper-latent", action="store_true",
+                    help="skip the paper's world with latent arrival times")
     ap.add_argument("--paper-worlds", type=int, default=50)
     ap.add_argument("--paper-runs", type=int, default=5)
     ap.add_argument("--paper-sweeps", type=int, default=100)
@@ -228,7 +230,7 @@ def learned_study(args, dev):
     return out
 
 
-def paper_world_study(args, dev):
+def paper_world_study(args, dev, latent: bool = False):
     """Section 5's experiment on the paper's own 1-D world (four stations on
     a line, T = 240, Section 4.1's time partition): worlds from the model
     (seeds 2000, 2001, ...), several runs each, under the paper's four
@@ -240,7 +242,12 @@ def paper_world_study(args, dev):
     recall, F1 and location error (Section 5's matching, 12 units in space and
     time) against sweeps and wall time, and 95% bootstrap intervals over worlds
     of the final values.  The oracle runs the same schedules on two worlds for
-    the CPU rate."""
+    the CPU rate.
+
+    latent: the same world with Section 3's latent arrival times (offsets of
+    sd 1 sample, truncated at 4 sd) and the arrival-time and joint moves; the
+    four onset regions then need three colours, and the naive schedule is not
+    part of the mode."""
     import dataclasses
 
     import numpy as np
@@ -248,20 +255,23 @@ def paper_world_study(args, dev):
 
     import oracle as O
     from paper_1612_00595_amd import chromh, metrics as M, workloads as W
-    spec = W.PAPER1D_MODEL
-    scheds = {"serial": dataclasses.replace(W.PAPER1D_SAMPLER, gx=1, k=2000),
-              "naive": dataclasses.replace(W.PAPER1D_SAMPLER, schedule=1),
-              "chromatic_static": W.PAPER1D_SAMPLER,
-              "chromatic_dynamic": dataclasses.replace(W.PAPER1D_SAMPLER, dynamic=1)}
+    wl = W.PAPER1D_LATENT if latent else W.PAPER1D
+    spec, base = wl.model, wl.sampler
+    scheds = {"serial": dataclasses.replace(base, gx=1, k=2000)}
+    if not latent:
+        scheds["naive"] = dataclasses.replace(base, schedule=1)
+    scheds["chromatic_static"] = base
+    scheds["chromatic_dynamic"] = dataclasses.replace(base, dynamic=1)
     nw, nr, S = args.paper_worlds, args.paper_runs, args.paper_sweeps
     truths, traces = [], []
     for wi in range(nw):
         tr = W.truth_events(spec, 2000 + wi)
         truths.append(tr)
-        traces.append(chromh.simulate(spec, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"]),
+        traces.append(chromh.simulate(spec, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"],
+                                                             da=tr["da"]),
                                       3000 + wi, "f64", dev))
     every = 5
-    out = {"workload": W.PAPER1D.name + " worlds", "worlds": nw, "runs": nr, "sweeps": S,
+    out = {"workload": wl.name + " worlds", "worlds": nw, "runs": nr, "sweeps": S,
            "moves_per_sweep": 2000, "match_thresholds": [M.PAPER_DIST_THRESH, TIME_THRESH_1D],
            "true_events_mean": float(np.mean([len(t["x"]) for t in truths]))}
     n = nw * nr
@@ -274,7 +284,8 @@ def paper_world_study(args, dev):
         # kernel form by a short trial (few work items per colour favour the
         # latency form, many the wave form)
         trial = {}
-        for block in ((64,) if sp.schedule == 1 else (64, 128, 256)):
+        forms = (64,) if sp.schedule == 1 else (256,) if latent else (64, 128, 256)
+        for block in forms:
             b = batch(sp, block)
             b.run_sweeps(0, 1)
             torch.cuda.synchronize()
@@ -313,6 +324,8 @@ def paper_world_study(args, dev):
             per_world = np.nanmean(v[:, -1].reshape(nw, nr), axis=1)
             mean, lo, hi = M.bootstrap_ci(per_world[np.isfinite(per_world)])
             return [mean, lo, hi]
+        if latent:  # arrival-time and joint moves: attempted, valid, accepted
+            proposals += float(d[17:23].reshape(2, 3)[:, 0].sum())
         out[name] = {
             "ms_per_sweep": ms, "proposals_per_s": proposals / el, "block": block,
             "final_precision_ci95": final(P), "final_recall_ci95": final(Rc),
@@ -323,8 +336,12 @@ def paper_world_study(args, dev):
                       "recall": Rc.mean(0).round(4).tolist(),
                       "f1": F.mean(0).round(4).tolist(),
                       "location_error": np.nanmean(E, 0).round(3).tolist()}}
-        log(f"[bench] paper world, {name} (block {block}): {ms:.3f} ms/sweep for {n} chains, "
-            f"{proposals / el:.4g} proposals/s, final F1 {out[name]['final_f1_ci95'][0]:.3f}")
+        if latent:
+            out[name]["arrival_moves"] = [int(v) for v in d[17:20]]
+            out[name]["joint_moves"] = [int(v) for v in d[20:23]]
+        log(f"[bench] paper world{' (latent arrivals)' if latent else ''}, {name} (block {block}): "
+            f"{ms:.3f} ms/sweep for {n} chains, {proposals / el:.4g} proposals/s, "
+            f"final F1 {out[name]['final_f1_ci95'][0]:.3f}")
     # the oracle: the same schedules, two worlds, one run each
     osw = max(S // 5, 4)
     m = O.make_model(**spec.asdict())
@@ -333,7 +350,7 @@ def paper_world_study(args, dev):
         t0, moves = time.perf_counter(), 0
         for wi in range(2):
             s = O.simulate(m, O.as_events(truths[wi]["x"], truths[wi]["y"], truths[wi]["t"],
-                                          truths[wi]["m"]), 3000 + wi)
+                                          truths[wi]["m"], da=truths[wi]["da"]), 3000 + wi)
             ch = O.Chain(m, O.make_sampler(**sp.asdict()), s, seed=7919 * wi)
             for sw in range(osw):
                 assert ch.sweep(sw) == 0
@@ -660,6 +677,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_paper_world:
         out["paper_world"] = paper_world_study(args, dev)
+    if not args.no_paper_latent:
+        out["paper_world_latent"] = paper_world_study(args, dev, latent=True)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

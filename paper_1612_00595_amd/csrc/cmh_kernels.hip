@@ -259,6 +259,10 @@ __device__ inline double fit_interval(const Geo &g, const double *lsx, const dou
 struct JointScratch {
     double in[4][8];
     double f[4][10], x[4][10], t[4][10];
+    double bx[4], bt[4];          // each fit's best interval
+    double lpt[2][8], lqt[2];     // each event's terms of the ratio
+    double px[2], pt[2];          // each event's proposed location and onset
+    int ok[2];
 };
 
 // Stations whose position falls in region (i, kk) of a partition with
@@ -726,61 +730,63 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
             js.t[f][q] = ft;
         }
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            double bx[4], bt[4];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                double best = INFINITY;
-                bx[f] = 0.0;
-                bt[f] = 0.0;
-                for (int q = 0; q < 10; ++q)
-                    if (js.f[f][q] < best) {
-                        best = js.f[f][q];
-                        bx[f] = js.x[f][q];
-                        bt[f] = js.t[f][q];
-                    }
-            }
-            const int ev2[2] = {idx, idx2};
-            const double zx[2] = {d[5], d2[0]}, zt[2] = {d[6], d2[1]};
-            double px[2], pt[2];
-            int ok = 1;
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                px[e] = bx[e] + g.sxy * zx[e];
-                pt[e] = bt[e] + g.st * zt[e];
-                ok = ok && px[e] >= 0.0 && px[e] < g.Lx && pt[e] >= 0.0 && pt[e] < (double)g.N &&
-                     in_region_axis(pt[e], y0, y1, offx, g.wx, g.gx, i);
-                double *pd = lat->pda[buf][e];
-                for (int q = 0; q < 8; ++q) pd[q] = 0.0;
-                for (int q = 0; q < g.nsx && ok; ++q) {
-                    const double target = js.in[e][q];
-                    const double w = target - line_arrival(g, px[e], pt[e], lsx[q], 0.0);
-                    pd[q] = w;
-                    // the offset stays in its support, and the window starts
-                    // at the sample of the arrival it takes over
-                    ok = fabs(w) <= g.arr_e &&
-                         ceil(line_arrival(g, px[e], pt[e], lsx[q], w)) == ceil(target);
+        if (lane < 4) {  // fit `lane`: its best interval, the first on ties
+            double best = INFINITY, bx = 0.0, bt = 0.0;
+            for (int q = 0; q < 10; ++q)
+                if (js.f[lane][q] < best) {
+                    best = js.f[lane][q];
+                    bx = js.x[lane][q];
+                    bt = js.t[lane][q];
                 }
+            js.bx[lane] = bx;
+            js.bt[lane] = bt;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int pi0 = __builtin_amdgcn_readlane(idx, 0), pi1 = __builtin_amdgcn_readlane(idx2, 0);
+        if (lane < 2) {
+            // event `lane` of the pair: a Gaussian step around the fit of its
+            // exchanged arrivals, offsets that keep those arrivals, and its
+            // terms of the ratio (the reverse move centres on the fit of its
+            // original arrivals, fit 2 + lane)
+            const int e = lane, ie = e ? pi1 : pi0;
+            const double zx = e ? d2[0] : d[5], zt = e ? d2[1] : d[6];
+            const double px = js.bx[e] + g.sxy * zx, pt = js.bt[e] + g.st * zt;
+            int ok = px >= 0.0 && px < g.Lx && pt >= 0.0 && pt < (double)g.N &&
+                     in_region_axis(pt, y0, y1, offx, g.wx, g.gx, i);
+            double *pd = lat->pda[buf][e];
+            for (int q = 0; q < 8; ++q) pd[q] = 0.0;
+            for (int q = 0; q < g.nsx && ok; ++q) {
+                const double target = js.in[e][q];
+                const double w = target - line_arrival(g, px, pt, lsx[q], 0.0);
+                pd[q] = w;
+                // the offset stays in its support, and the window starts at
+                // the sample of the arrival it takes over
+                ok = fabs(w) <= g.arr_e && ceil(line_arrival(g, px, pt, lsx[q], w)) == ceil(target);
             }
-            valid = ok;
-            if (ok) {
+            for (int q = 0; q < g.nsx; ++q) {
+                const double o = s_da[ie][q], w = pd[q];
+                js.lpt[e][q] = (o * o - w * w) / g.arr_2v;
+            }
+            const double rx = (s_ex[ie] - js.bx[2 + e]) / g.sxy;
+            const double rt = (s_et[ie] - js.bt[2 + e]) / g.st;
+            js.lqt[e] = 0.5 * (zx * zx + zt * zt) - 0.5 * (rx * rx + rt * rt);
+            js.px[e] = px;
+            js.pt[e] = pt;
+            js.ok[e] = ok;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            valid = js.ok[0] && js.ok[1];
+            if (valid) {  // the terms summed in event, then station order
                 double lp = 0.0, lq = 0.0;
                 for (int e = 0; e < 2; ++e)
-                    for (int q = 0; q < g.nsx; ++q) {
-                        const double o = s_da[ev2[e]][q], w = lat->pda[buf][e][q];
-                        lp += (o * o - w * w) / g.arr_2v;
-                    }
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const double rx = (s_ex[ev2[e]] - bx[2 + e]) / g.sxy;
-                    const double rt = (s_et[ev2[e]] - bt[2 + e]) / g.st;
-                    lq += 0.5 * (zx[e] * zx[e] + zt[e] * zt[e]) - 0.5 * (rx * rx + rt * rt);
-                }
+                    for (int q = 0; q < g.nsx; ++q) lp += js.lpt[e][q];
+                for (int e = 0; e < 2; ++e) lq += js.lqt[e];
                 lx = lp + lq;
-                nx = px[0]; ny = 0.0; nt = pt[0]; nm = s_em[idx];
+                nx = js.px[0]; ny = 0.0; nt = js.pt[0]; nm = s_em[idx];
                 ox = s_ex[idx]; ot = s_et[idx]; om = nm;
-                lat->prop2[buf][0] = px[1];
-                lat->prop2[buf][1] = pt[1];
+                lat->prop2[buf][0] = js.px[1];
+                lat->prop2[buf][1] = js.pt[1];
                 lat->prop2[buf][2] = (double)idx2;
             }
         }
@@ -849,7 +855,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
 // next to their coordinates, draws 8..15 come from the slot's draws2, and
 // the scout also builds arrival-time and joint moves.
 template <typename TraceT, int BLOCK, bool LAT>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LAT ? 2 : 1)))
 k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
               const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
               long long log_first, long long log_n, int *__restrict__ err)
