@@ -125,6 +125,51 @@ def test_latent_replay_parity_joint_moves():
     assert st[6, 2] >= 20 and st[5, 2] > 0
 
 
+@pytest.mark.parametrize("tmpl,dtype", [(1, "f64"), (0, "f32")])
+def test_latent_replay_parity_template_and_f32(tmpl, dtype):
+    w = W.PAPER1D_LATENT
+    w = dataclasses.replace(w, name=w.name + f"-t{tmpl}-{dtype}", trace_dtype=dtype,
+                            model=dataclasses.replace(w.model, tmpl=tmpl),
+                            sampler=dataclasses.replace(w.sampler, dynamic=1))
+    say("latent replay", w.name)
+    gpu, ref, m, s, acc, types, status = _replay(w, 6)
+    say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties)
+    assert acc.evaluated > 5000
+    ev = ref.events()
+    assert len(ev) > 0
+    got = gpu.read_variance(0)
+    Er = O.event_variance(m, ev)
+    if tmpl:
+        assert np.max(np.abs(got - (s.astype(np.float64) - Er))) <= 1e-10 * np.abs(s).max()
+    else:
+        assert np.all(np.abs(got - Er) <= 1e-9 * (w.model.sigma ** 2 + Er))
+    ll = gpu.refresh(write_variance=False, loglik=True)[0]
+    assert ll == pytest.approx(O.loglik(m, s, ev), rel=1e-10)
+
+
+def test_latent_graph_replay_matches_eager():
+    from paper_1612_00595_amd import chromh
+    w = dataclasses.replace(W.PAPER1D_LATENT, sampler=dataclasses.replace(
+        W.PAPER1D_LATENT.sampler, dynamic=1))
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    a = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=4)
+    b = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=4)
+    say("latent graph replay vs eager")
+    a.run_sweeps(0, 2)
+    torch.cuda.synchronize()
+    a.run_sweeps(2, 3)
+    for sw in range(5):
+        for c in range(b.ncolors):
+            b.sweep_color(sw, c)
+    compare_events(a.read_events(0), b.read_events(0), "after 5 sweeps")
+    assert np.array_equal(a.read_variance(0), b.read_variance(0))
+    assert np.array_equal(a.read_stats(0), b.read_stats(0))
+    assert a.read_stats(0)[6, 0] > 0 and a.read_stats(0)[5, 2] > 0
+    a.close()
+    b.close()
+
+
 def test_latent_batch_matches_single_runs():
     from paper_1612_00595_amd import chromh
     spec = W.PAPER1D_LATENT_MODEL

@@ -15,7 +15,8 @@ the line model, with the arrival-time move and the joint two-event move.
 - the arrival move's local change equals two full recomputations; the joint
   move's likelihood change equals two full recomputations and is zero up to
   rounding (the exchange keeps every station's set of signals), and its log
-  alpha is the prior change (orc_logprior) plus the proposal log ratio;
+  alpha is the prior change (orc_logprior) plus the proposal log ratio; both
+  under the variance and the mean-template likelihood;
 - with the likelihood off the chain samples the prior: Poisson count,
   uniform location and onset, truncated-normal offsets, in a two-station
   world where the joint move is often accepted and in the paper's world;
@@ -184,8 +185,9 @@ def _world(orc, spec, m, seed):
     return truth, orc.simulate(m, truth, 100 + seed)
 
 
-def test_arrival_move_delta_equals_full_recompute(orc):
-    spec, m = latent_model(orc)
+@pytest.mark.parametrize("tmpl", [0, 1])
+def test_arrival_move_delta_equals_full_recompute(orc, tmpl):
+    spec, m = latent_model(orc, tmpl=tmpl)
     sp = latent_sampler(orc, dynamic=1)
     truth, s = _world(orc, spec, m, 3)
     ch = orc.Chain(m, sp, s, seed=1)
@@ -233,9 +235,10 @@ def _forced_joint_run(orc, spec, m, s, X0, sweeps, seed):
     return out
 
 
-@pytest.mark.parametrize("stations", [(0.0, 100.0), (0.0, 33.0, 66.0, 100.0)])
-def test_joint_move_ratio_and_unchanged_likelihood(orc, stations):
-    spec, m = latent_model(orc, nsx=len(stations), sta_x=stations, lam=10.0)
+@pytest.mark.parametrize("stations,tmpl", [((0.0, 100.0), 0), ((0.0, 33.0, 66.0, 100.0), 0),
+                                           ((0.0, 100.0), 1)])
+def test_joint_move_ratio_and_unchanged_likelihood(orc, stations, tmpl):
+    spec, m = latent_model(orc, nsx=len(stations), sta_x=stations, lam=10.0, tmpl=tmpl)
     truth, s = _world(orc, spec, m, 4)
     if len(stations) == 4:
         # pairs between the middle stations: exchanging the arrivals at the
