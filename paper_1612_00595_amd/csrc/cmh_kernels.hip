@@ -1311,7 +1311,7 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
 // events; the shared variance is never written and is recomputed from the
 // merged events after the phase.
 template <typename TraceT, bool NAIVE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : 3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : 4)))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
              long long log_first, long long log_n, int *__restrict__ err, int naive_elems)
