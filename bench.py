@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--profile-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-parallel", action="store_true",
+                    help="skip the oracle on all host threads (context for the CPU baseline)")
     ap.add_argument("--traffic", default=os.path.join(
                         ROOT, "profiles", "k_sweep_color-s64x64-n144000-dyn64x64-f32.traffic.json"),
                     help="JSON with rocprofv3 FETCH_SIZE/WRITE_SIZE bytes per sweep-kernel launch; "
@@ -79,10 +81,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, warmup: int, budget_s: float):
-    """The oracle as it stands, single-threaded, on the same workload: its own
-    synthetic trace of the same shape (seeded normals scaled by the model
-    variance), sweeps 0 .. warmup-1 untimed, then sweeps until budget_s."""
+def host_cpu():
+    """(threads this process may use, CPU model name)."""
+    n = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
+def cpu_baseline(w, warmup: int, budget_s: float, threads: int = 1):
+    """The oracle as it stands on the same workload: its own synthetic trace of
+    the same shape (seeded normals scaled by the model variance), sweeps
+    0 .. warmup-1 untimed, then sweeps until budget_s.  threads > 1 runs the
+    regions of each colour phase across that many host threads (the paper's
+    own CPU parallelism; the chain is the same)."""
     import numpy as np
 
     import oracle as O
@@ -97,6 +115,7 @@ def cpu_baseline(w, warmup: int, budget_s: float):
     s = O.trace_from_noise_f32(m, truth, z)
     del z
     ch = O.Chain(m, sp, s, seed=w.seed)
+    ch.set_threads(threads)
     for sw in range(warmup):
         ch.sweep(sw)
     R, k = w.sampler.nreg, w.sampler.k
@@ -110,10 +129,13 @@ def cpu_baseline(w, warmup: int, budget_s: float):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return dict(value=moves / el, unit="proposals/s", cores=1, kind="oracle",
+    how = "single thread" if threads == 1 else \
+        f"{threads} threads over the regions of each colour phase"
+    return dict(value=moves / el, unit="proposals/s", cores=threads,
+                kind="oracle" if threads == 1 else "oracle-threads",
                 sample=f"{w.name}: oracle sweeps {warmup}..{warmup + sweeps - 1} "
                        f"({sweeps} sweeps, {moves} proposals, {el:.1f} s) on its own "
-                       f"instance of the same shape, single thread")
+                       f"instance of the same shape, {how}")
 
 
 # network FLOPs per row: forward 2 (576*256 + 2*256*256 + 256*64) multiply-adds
@@ -683,6 +705,15 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.warmup, args.cpu_seconds)
+        threads, cpu_model = host_cpu()
+        out["cpu_baseline"]["cpu_model"] = cpu_model
+        if not args.no_cpu_parallel and threads > 1:
+            # context, not the baseline: the oracle's colour phases across
+            # the host's cores (the parallelism of the paper's own runs)
+            out["cpu_parallel"] = cpu_baseline(w, args.warmup, args.cpu_seconds, threads)
+            out["cpu_parallel"]["cpu_model"] = cpu_model
+            log(f"[bench] oracle on {threads} host threads: "
+                f"{out['cpu_parallel']['value']:.4g} proposals/s")
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

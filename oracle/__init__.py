@@ -60,7 +60,7 @@ def build(force: bool = True) -> str:
             os.path.getmtime(_LIB_PATH) >= os.path.getmtime(s) for s in srcs):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-fopenmp",
            "-shared", "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
@@ -115,6 +115,7 @@ def lib():
         L.orc_chain_phase.restype = C.c_int32
         L.orc_chain_sweep.argtypes = [P, C.c_int64, P, P]
         L.orc_chain_sweep.restype = C.c_int32
+        L.orc_chain_set_threads.argtypes = [P, C.c_int32]
         L.orc_chain_count.argtypes = [P]
         L.orc_chain_count.restype = C.c_int64
         L.orc_chain_events.argtypes = [P, P, C.c_int64]
@@ -345,6 +346,10 @@ class Chain:
 
     def count(self) -> int:
         return lib().orc_chain_count(self._h)
+
+    def set_threads(self, threads: int):
+        """Run the regions of each colour phase on `threads` host threads."""
+        lib().orc_chain_set_threads(self._h, threads)
 
     def events(self) -> np.ndarray:
         n = self.count()

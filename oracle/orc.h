@@ -192,6 +192,9 @@ int32_t orc_chain_begin_sweep(orc_chain *c, int64_t sweep);
 int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color,
                         const double *feed, double *log);
 int32_t orc_chain_sweep(orc_chain *c, int64_t sweep, const double *feed, double *log);
+/* threads > 1: the regions of each colour phase run on that many OpenMP
+ * threads (when built with OpenMP); the chain is the same. */
+void    orc_chain_set_threads(orc_chain *c, int32_t threads);
 int64_t orc_chain_count(const orc_chain *c);
 /* learned birth proposal: table [nsta * n_tau][8][8] of (mean x, y, t, sd x,
  * y, t, log weight, cumulative weight) and anchor weights [nsta * n_tau],

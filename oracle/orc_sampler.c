@@ -72,6 +72,7 @@ struct orc_chain {
     double *lcum;         /* per station: running sums of its anchors' weights */
     int32_t ntau;
     double plearn;
+    int32_t threads;      /* host threads for the regions of one phase (1: serial) */
 };
 
 /* ---------------------------------------------------------------- lattice */
@@ -806,6 +807,7 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
     if (type == ORC_BIRTH) {
         if (n >= sp->cap) {
             valid = 0;
+#pragma omp atomic
             c->overflows++;
         } else if (sp->lattice && m->line) {
             int32_t ix = 0, it = 0;
@@ -965,12 +967,62 @@ static void run_move(orc_chain *c, int32_t r, uint32_t sweep, uint32_t j, const 
     }
 }
 
+/* The k moves of region r in one phase (Algorithm 4's inner loop). */
+static void run_region(orc_chain *c, int64_t r, int64_t sweep, const double *feed,
+                       double *log_out)
+{
+    double x0, x1, y0, y1;
+    region_rect(c, (int32_t)r, &x0, &x1, &y0, &y1);
+    double area = (x1 - x0) * (y1 - y0);
+    if (c->m.line) {  /* the region's share of the onset interval */
+        double t0, t1;
+        region_times(c, (int32_t)r, &t0, &t1);
+        area = t1 - t0;
+    }
+    if (!(area > 0.0)) return;
+    double lam_r;
+    if (c->sp.lattice && c->m.line) {
+        int32_t a, b;
+        int64_t nr = lat_line_region_sites(c, (int32_t)r, -1, &a, &b);
+        if (nr == 0) return;
+        lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.kt);
+    } else if (c->m.line) {
+        lam_r = c->m.lambda * area / (double)c->m.N;
+    } else if (c->sp.lattice) {
+        int32_t a, b;
+        int64_t nr = lat_region_sites(c, (int32_t)r, -1, &a, &b);
+        if (nr == 0) return;
+        lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.ky);
+    } else {
+        lam_r = c->m.lambda * area / (c->Lx * c->Ly);
+    }
+    const int64_t stride = c->ltab || latent(c) ? 16 : 8;
+    for (int32_t j = 0; j < c->sp.k; ++j) {
+        double d[16];
+        const double *dp;
+        if (feed) {
+            dp = feed + ((r * c->sp.k) + j) * stride;
+        } else {
+            if (latent(c))
+                orc_move_draws_arr(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+            else if (c->ltab)
+                orc_move_draws16(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+            else
+                orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
+            dp = d;
+        }
+        run_move(c, (int32_t)r, (uint32_t)sweep, (uint32_t)j, dp, lam_r, area,
+                 log_out ? log_out + ((r * c->sp.k) + j) * 4 : NULL);
+    }
+}
+
 /* One colour phase of Algorithm 4: every region of the colour runs k moves;
  * the other regions are held at the phase-start snapshot.  With the naive
  * schedule (Algorithm 3) every region belongs to the phase and each accepts
  * against the posterior of its own events alone (the algorithm's pi(x_m)):
  * the other regions' events are invisible to it.
- * feed (optional): draws [region][k][8] ([16] with learned births); log
+ * feed (optional): draws [region][k][8] ([16] with learned births or latent
+ * arrivals); log
  * (optional): [region][k][4]. */
 int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double *feed,
                         double *log_out)
@@ -980,53 +1032,22 @@ int32_t orc_chain_phase(orc_chain *c, int64_t sweep, int32_t color, const double
     } else {
         build_snapshot(c);
     }
+    /* The regions of one colour are conditionally independent given the
+     * snapshot of the others (Section 4.1), so they may run on several host
+     * threads, as the paper's own implementation ran them on several cores;
+     * each writes only its own event list and its own log entries, and the
+     * result does not depend on the thread count. */
+#pragma omp parallel for schedule(dynamic, 1) num_threads(c->threads > 1 ? c->threads : 1) if (c->threads > 1)
     for (int64_t r = 0; r < c->nreg; ++r) {
         if (c->sp.schedule == ORC_SCHED_CHROMATIC && c->color[r] != color) continue;
-        double x0, x1, y0, y1;
-        region_rect(c, (int32_t)r, &x0, &x1, &y0, &y1);
-        double area = (x1 - x0) * (y1 - y0);
-        if (c->m.line) {  /* the region's share of the onset interval */
-            double t0, t1;
-            region_times(c, (int32_t)r, &t0, &t1);
-            area = t1 - t0;
-        }
-        if (!(area > 0.0)) continue;
-        double lam_r;
-        if (c->sp.lattice && c->m.line) {
-            int32_t a, b;
-            int64_t nr = lat_line_region_sites(c, (int32_t)r, -1, &a, &b);
-            if (nr == 0) continue;
-            lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.kt);
-        } else if (c->m.line) {
-            lam_r = c->m.lambda * area / (double)c->m.N;
-        } else if (c->sp.lattice) {
-            int32_t a, b;
-            int64_t nr = lat_region_sites(c, (int32_t)r, -1, &a, &b);
-            if (nr == 0) continue;
-            lam_r = c->m.lambda * (double)nr / ((double)c->sp.kx * (double)c->sp.ky);
-        } else {
-            lam_r = c->m.lambda * area / (c->Lx * c->Ly);
-        }
-        const int64_t stride = c->ltab || latent(c) ? 16 : 8;
-        for (int32_t j = 0; j < c->sp.k; ++j) {
-            double d[16];
-            const double *dp;
-            if (feed) {
-                dp = feed + ((r * c->sp.k) + j) * stride;
-            } else {
-                if (latent(c))
-                    orc_move_draws_arr(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
-                else if (c->ltab)
-                    orc_move_draws16(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
-                else
-                    orc_move_draws(c->seed, c->chain, (uint32_t)sweep, (uint32_t)r, (uint32_t)j, d);
-                dp = d;
-            }
-            run_move(c, (int32_t)r, (uint32_t)sweep, (uint32_t)j, dp, lam_r, area,
-                     log_out ? log_out + ((r * c->sp.k) + j) * 4 : NULL);
-        }
+        run_region(c, r, sweep, feed, log_out);
     }
     return 0;
+}
+
+void orc_chain_set_threads(orc_chain *c, int32_t threads)
+{
+    c->threads = threads > 1 ? threads : 1;
 }
 
 /* One full sweep: lay out the partition (a fresh offset when dynamic), then
