@@ -186,8 +186,9 @@ int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t 
 
 /* Workspace bytes for n_chains chains: the per-chain event-variance
  * accumulator (n_stations x n_samples doubles), two event tables of
- * region_capacity slots per region, offsets, the sweep's per-move draw
- * records, statistics and flags. */
+ * region_capacity slots per region (with latent arrivals also eight offsets
+ * per slot), offsets, the sweep's per-move draw records (with latent
+ * arrivals a second array for draws 8..15), statistics and flags. */
 int32_t cmh_state_bytes(const cmh_model *model, const cmh_sampler *sampler,
                         int32_t n_chains, size_t *bytes);
 

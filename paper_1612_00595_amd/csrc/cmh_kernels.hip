@@ -717,8 +717,9 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
     type = __builtin_amdgcn_readlane(type, 0);
     valid = __builtin_amdgcn_readlane(valid, 0);
     if (LAT && type == 6 && valid) {
-        // the four least-squares fits, one interval per lane, then the
-        // proposal around the exchanged arrivals' fits (lane 0)
+        // the four least-squares fits, one interval per lane; then one lane
+        // per event builds its proposal around the fit of its exchanged
+        // arrivals, and lane 0 sums the ratio's terms
         __builtin_amdgcn_wave_barrier();
         JointScratch &js = lat->js;
         if (lane < 40) {
