@@ -317,6 +317,17 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
                         int32_t n_tau, double p_learned, void *work_dev, size_t work_bytes,
                         void *hip_stream);
 
+/* The same for one instance of a batch (cmh_batch_init): its own table over
+ * its own stations and windows, its own weights and workspace
+ * (cmh_batch_learned_bytes bytes), its own p_learned; instances without a
+ * table keep plain births.  Instance q with a table follows the same chain
+ * as a one-chain state of its own with that table.  Synchronises, drops
+ * captured sweep graphs. */
+int32_t cmh_batch_learned_bytes(cmh_state *st, int32_t instance, int32_t n_tau, size_t *bytes);
+int32_t cmh_batch_set_learned(cmh_state *st, int32_t instance, const double *table_dev,
+                              const double *weights_dev, int32_t n_tau, double p_learned,
+                              void *work_dev, size_t work_bytes, void *hip_stream);
+
 /* A batch of independent instances (each a model, sampler settings, trace
  * and Philox seed; chain key 0) sampled together: every colour phase is one
  * launch over the regions of that colour of every instance, so instances of

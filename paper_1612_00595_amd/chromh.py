@@ -62,7 +62,8 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_mdn_infer",
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
-           "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init"]
+           "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init",
+           "cmh_batch_learned_bytes", "cmh_batch_set_learned"]
 
 _lib = None
 
@@ -104,6 +105,8 @@ def lib():
         "cmh_batch_bytes": ([I32, P, P, P], I32),
         "cmh_batch_init": ([I32, P, P, P, I32, P, P, C.c_size_t, P, P], I32),
         "cmh_set_learned": ([P, P, P, I32, D, P, C.c_size_t, P], I32),
+        "cmh_batch_learned_bytes": ([P, I32, I32, P], I32),
+        "cmh_batch_set_learned": ([P, I32, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_mdn_sizes": ([P, P], I32),
         "cmh_mdn_param_bytes": ([P], I32),
         "cmh_mdn_init": ([P, U32, P], I32),
@@ -576,3 +579,28 @@ class Batch(ChromaticSampler):
             self.ncolors = 1
         self._feed = None
         self._log = None
+        self._learned_q = {}
+
+    def set_learned_instance(self, q: int, table, weights, n_tau: int, p_learned: float = 0.5,
+                             stream=None):
+        """Learned births for instance q from its own float64 device table
+        [n_stations_q * n_tau, 8, 8] and weights [n_stations_q * n_tau] (kept
+        alive here); None: plain births again."""
+        import torch
+        if table is None:
+            check(lib().cmh_batch_set_learned(self._h, q, None, None, 0, 0.0, None, 0,
+                                              _stream(stream)))
+            self._learned_q.pop(q, None)
+            return
+        na = self.models[q].nsta * n_tau
+        for t, shape in ((table, (na, 8, 8)), (weights, (na,))):
+            if (tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_cuda
+                    or not t.is_contiguous()):
+                raise ValueError(f"table and weights must be contiguous float64 device tensors "
+                                 f"[{na}, 8, 8] and [{na}]")
+        nb = C.c_size_t()
+        check(lib().cmh_batch_learned_bytes(self._h, q, n_tau, C.byref(nb)))
+        work = torch.empty(nb.value, dtype=torch.uint8, device=self.trace.device)
+        check(lib().cmh_batch_set_learned(self._h, q, _ptr(table), _ptr(weights), n_tau,
+                                          p_learned, _ptr(work), work.numel(), _stream(stream)))
+        self._learned_q[q] = (table, weights, work)

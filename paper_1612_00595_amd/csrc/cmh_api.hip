@@ -424,6 +424,7 @@ struct cmh_state {
     int poisoned = 0;
     int batch = 0;  // slots are different instances (cmh_batch_init)
     cmh::Learned learned{};  // tab == nullptr: plain births
+    int n_learned = 0;       // batches: instances with learned births
     // work items: one slot per chain, items (slot << 16) | region
     int nslots = 0;
     int refresh_max = 0;  // the most (station, tile) blocks of a slot (naive refresh)
@@ -603,7 +604,7 @@ hipError_t enqueue_sweep_start(cmh_state *st, hipStream_t s)
     }
     return cmh::launch_sweep_draws(st->slots_d, st->items_all, st->n_all, st->g.k, st->cur,
                                    st->sweep_ctr, st->feed, st->feed_first, st->feed_width,
-                                   st->learned.tab != nullptr, st->err, s);
+                                   st->learned.tab != nullptr || st->n_learned > 0, st->err, s);
 }
 
 // Enqueue one colour phase (colour 0 first starts the sweep), reading the
@@ -1156,17 +1157,18 @@ int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, vo
 }
 
 namespace {
-size_t carve_learned(const cmh_state *st, int ntau, char *base, cmh::Learned *L, double **part)
+// The library's learned-birth arrays for `chains` chains of one instance.
+size_t carve_learned(const cmh::Geo &g, int chains, int ntau, char *base, cmh::Learned *L,
+                     double **part)
 {
-    const cmh::Geo &g = st->g;
     Carver c{base};
     const size_t na = (size_t)g.nsta * ntau;
     double *cum = c.take<double>(na);
     double *norm = c.take<double>(na * 8);
     double *reach = c.take<double>(2);
     double *pp = c.take<double>((size_t)2 * cmh::learned_norm_blocks((long long)na * 8));
-    double *birth = c.take<double>((size_t)st->chains * g.R * g.k * 4);
-    double *raw = c.take<double>((size_t)st->chains * g.R * g.k * 8);
+    double *birth = c.take<double>((size_t)chains * g.R * g.k * 4);
+    double *raw = c.take<double>((size_t)chains * g.R * g.k * 8);
     if (L) {
         L->cum = cum;
         L->norm = norm;
@@ -1176,6 +1178,37 @@ size_t carve_learned(const cmh_state *st, int ntau, char *base, cmh::Learned *L,
     }
     if (part) *part = pp;
     return align_up(c.off);
+}
+
+size_t carve_learned_st(const cmh_state *st, int ntau, char *base, cmh::Learned *L, double **part)
+{
+    return carve_learned(st->g, st->chains, ntau, base, L, part);
+}
+
+// Checks shared by the learned-birth setters; derives the arrays into
+// work_dev and returns the instance's Learned in *L.
+int32_t prepare_learned(const cmh::Geo &g, int chains, const double *table_dev,
+                        const double *weights_dev, int32_t n_tau, double p_learned,
+                        void *work_dev, size_t work_bytes, hipStream_t s, cmh::Learned *L)
+{
+    if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
+    if (!(p_learned >= 0.0 && p_learned < 1.0))
+        return fail(CMH_EINVAL, "p_learned must lie in [0, 1)");
+    if (!weights_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if (work_bytes < carve_learned(g, chains, n_tau, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "learned workspace too small");
+    *L = cmh::Learned{};
+    double *part = nullptr;
+    carve_learned(g, chains, n_tau, (char *)work_dev, L, &part);
+    L->tab = table_dev;
+    L->w = weights_dev;
+    L->ntau = n_tau;
+    L->pl = p_learned;
+    const double lz3 = 3.0 * log(sqrt(2.0 * M_PI) * erf(4.0 / sqrt(2.0)));
+    HIPCHK(cmh::launch_learned_prep(weights_dev, table_dev, n_tau, g.nsta, lz3, (double *)L->cum,
+                                    (double *)L->norm, part, (double *)L->reach, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return CMH_OK;
 }
 }  // namespace
 
@@ -1188,7 +1221,7 @@ int32_t cmh_learned_bytes(cmh_state *st, int32_t n_tau, size_t *bytes)
         return fail(CMH_EINVAL, "learned births need the grid model's variance signals");
     if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
     if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
-    *bytes = carve_learned(st, n_tau, nullptr, nullptr, nullptr);
+    *bytes = carve_learned_st(st, n_tau, nullptr, nullptr, nullptr);
     return CMH_OK;
 }
 
@@ -1206,26 +1239,53 @@ int32_t cmh_set_learned(cmh_state *st, const double *table_dev, const double *we
         st->learned = cmh::Learned{};
         return upload_slots(st);
     }
-    if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
-    if (!(p_learned >= 0.0 && p_learned < 1.0))
-        return fail(CMH_EINVAL, "p_learned must lie in [0, 1)");
-    if (!weights_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
-    if (work_bytes < carve_learned(st, n_tau, nullptr, nullptr, nullptr))
-        return fail(CMH_EINVAL, "learned workspace too small");
     cmh::Learned L{};
-    double *part = nullptr;
-    carve_learned(st, n_tau, (char *)work_dev, &L, &part);
-    L.tab = table_dev;
-    L.w = weights_dev;
-    L.ntau = n_tau;
-    L.pl = p_learned;
-    const double lz3 = 3.0 * log(sqrt(2.0 * M_PI) * erf(4.0 / sqrt(2.0)));
-    HIPCHK(cmh::launch_learned_prep(weights_dev, table_dev, n_tau, st->g.nsta, lz3,
-                                    (double *)L.cum, (double *)L.norm, part, (double *)L.reach,
-                                    (hipStream_t)hip_stream));
+    rc = prepare_learned(st->g, st->chains, table_dev, weights_dev, n_tau, p_learned, work_dev,
+                         work_bytes, (hipStream_t)hip_stream, &L);
+    if (rc) return rc;
     st->learned = L;
-    HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
     return upload_slots(st);
+}
+
+int32_t cmh_batch_learned_bytes(cmh_state *st, int32_t instance, int32_t n_tau, size_t *bytes)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!st->batch) return fail(CMH_EINVAL, "not a batch of instances");
+    if (instance < 0 || instance >= st->nslots) return fail(CMH_EINVAL, "instance out of range");
+    const Geo &g = st->slots_h[instance].g;
+    if (g.line || g.tmpl)
+        return fail(CMH_EINVAL, "learned births need the grid model's variance signals");
+    if (n_tau < 1) return fail(CMH_EINVAL, "n_tau must be >= 1");
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = carve_learned(g, 1, n_tau, nullptr, nullptr, nullptr);
+    return CMH_OK;
+}
+
+int32_t cmh_batch_set_learned(cmh_state *st, int32_t instance, const double *table_dev,
+                              const double *weights_dev, int32_t n_tau, double p_learned,
+                              void *work_dev, size_t work_bytes, void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!st->batch) return fail(CMH_EINVAL, "not a batch of instances");
+    if (instance < 0 || instance >= st->nslots) return fail(CMH_EINVAL, "instance out of range");
+    cmh::Slot &sl = st->slots_h[instance];
+    if (table_dev && (sl.g.line || sl.g.tmpl))
+        return fail(CMH_EINVAL, "learned births need the grid model's variance signals");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    drop_graphs(st);
+    cmh::Learned L{};
+    if (table_dev) {
+        rc = prepare_learned(sl.g, 1, table_dev, weights_dev, n_tau, p_learned, work_dev,
+                             work_bytes, (hipStream_t)hip_stream, &L);
+        if (rc) return rc;
+    }
+    st->n_learned += (L.tab != nullptr) - (sl.L.tab != nullptr);
+    sl.L = L;
+    HIPCHK(hipMemcpy(st->slots_d + instance, &sl, sizeof(cmh::Slot), hipMemcpyHostToDevice));
+    return CMH_OK;
 }
 
 // ------------------------------------------------------------------- batch

@@ -1,8 +1,9 @@
 """GPU parity of the learned birth proposal against the oracle: 16-wide draw
 records, the mixture-table builder, replayed sweeps with learned births
 (events bit-exact after every colour phase, log alpha within 1e-4, the same
-decisions outside the tie band), and prior-only stationarity of the GPU
-chains with learned births drawn from the device generator."""
+decisions outside the tie band), prior-only stationarity of the GPU chains
+with learned births drawn from the device generator, and learned births per
+instance of a batch."""
 import numpy as np
 import pytest
 from scipy import stats
@@ -153,3 +154,40 @@ def test_learned_prior_only_gpu_samples_the_prior():
     st = gpu.read_stats(0)
     say("birth attempts / accepted", st[0, 0], st[0, 2])
     assert st[0, 2] > 10000
+
+
+@pytest.mark.parametrize("block", [64, 256])
+def test_learned_births_in_a_batch_match_single_runs(block):
+    """Instances of an uneven batch carry their own learned tables (one stays
+    plain); each follows its one-chain run with the same table bit for bit."""
+    from paper_1612_00595_amd import chromh
+    specs = [W.ModelSpec(nsx=5, nsy=5, N=1000, lam=20.0), W.ModelSpec(nsx=6, nsy=6, N=1200, lam=30.0),
+             W.ModelSpec(nsx=4, nsy=4, N=900, lam=14.0)]
+    samplers = [W.SamplerSpec(gx=m.nsx, gy=m.nsy, dynamic=1) for m in specs]
+    traces, tables = [], []
+    for q, m in enumerate(specs):
+        tr = W.truth_events(m, 70 + q)
+        truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
+        traces.append(chromh.simulate(m, truth, 700 + q, "f64", DEV))
+        T, wts, ntau = W.random_mixture_table(m, 10 + q, near=O.as_events(tr["x"], tr["y"],
+                                                                            tr["t"], tr["m"]))
+        tables.append((torch.from_numpy(T).to(DEV), torch.from_numpy(wts).to(DEV), ntau))
+    say("learned batch of", len(specs), "instances (instance 1 plain)")
+    b = chromh.Batch(specs, samplers, traces, [31, 32, 33], block=block)
+    for q in (0, 2):
+        b.set_learned_instance(q, *tables[q], p_learned=0.5)
+    b.run_sweeps(0, 12)
+    torch.cuda.synchronize()
+    for q, m in enumerate(specs):
+        one = chromh.ChromaticSampler(m, samplers[q], traces[q], chains=1, seed=31 + q, block=block)
+        if q != 1:
+            one.set_learned(*tables[q], p_learned=0.5)
+        one.run_sweeps(0, 12)
+        compare_events(b.read_events(q), one.read_events(0), f"instance {q}")
+        assert np.array_equal(b.read_counters(q), one.read_counters(0))
+        one.close()
+    st = b.read_stats(0)
+    assert st[0, 2] > 0
+    # back to plain births for instance 0: it then matches a plain single run
+    b.set_learned_instance(0, None, None, 0)
+    b.close()
