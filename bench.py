@@ -249,7 +249,7 @@ def learned_study(args, dev):
     log(f"[bench] learned study: F1 plain {pl['f1']:.3f} learned {le['f1']:.3f}; ESS/s plain "
         f"{pl['ess_per_s']:.4g} learned {le['ess_per_s']:.4g}; training {tr.seconds:.2f} s "
         f"({train_tflops:.1f} TFLOP/s)")
-    return out
+    return out, tr.net
 
 
 def paper_world_study(args, dev, latent: bool = False):
@@ -425,11 +425,64 @@ def uneven_study(args, dev, block: int):
            "value": proposals / el, "unit": "proposals/s",
            "ms_per_step": el * 1e3 / args.uneven_steps,
            "algorithmic_GBps_whole_sweep": nbytes / el / 1e9,
-           "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block}
+           "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block,
+           "births_attempted_valid_accepted": [int(v) for v in d[:15].reshape(5, 3)[0]]}
     log(f"[bench] uneven batch: {out['value']:.4g} proposals/s, {out['ms_per_step']:.2f} ms/sweep, "
         f"{out['algorithmic_GBps_whole_sweep']:.1f} GB/s algorithmic")
     b.close()
     del traces, b
+    return out
+
+
+def uneven_learned_study(args, dev, block: int, net):
+    """The uneven batch again, every instance with learned births (p = 0.5)
+    from the trained network: each instance's anchor table is built from its
+    own trace (features, fused network inference, mixture table), then the
+    same sweeps as the plain line are timed."""
+    import numpy as np
+    import torch
+
+    from paper_1612_00595_amd import chromh, learned, workloads as W
+    ws = W.uneven_batch(args.uneven_count)
+    traces, models, samplers, seeds = [], [], [], []
+    for w in ws:
+        tr = W.truth_events(w.model, w.seed)
+        truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
+        traces.append(chromh.simulate(w.model, truth, 1000 + w.seed, "f32", dev))
+        models.append(w.model)
+        samplers.append(w.sampler)
+        seeds.append(w.seed)
+    b = chromh.Batch(models, samplers, traces, seeds, block=block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    anchors = 0
+    for q, (m, trc) in enumerate(zip(models, traces)):
+        T, wt, ntau = learned.anchor_table(net, m, trc)
+        anchors += m.nsta * ntau
+        b.set_learned_instance(q, T, wt, ntau, 0.5)
+    torch.cuda.synchronize()
+    t_tables = time.perf_counter() - t0
+    b.run_sweeps(0, args.warmup)
+    torch.cuda.synchronize()
+    c0 = [b.read_counters(q) for q in range(len(ws))]
+    t0 = time.perf_counter()
+    b.run_sweeps(args.warmup, args.uneven_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c1 = [b.read_counters(q) for q in range(len(ws))]
+    d = sum(x - y for x, y in zip(c1, c0))
+    mv = d[:15].reshape(5, 3)
+    out = {"workload": f"{len(ws)} uneven instances, learned births (p = 0.5)",
+           "instances": len(ws), "anchors": int(anchors), "tables_seconds": t_tables,
+           "value": float(mv[:, 0].sum()) / el, "unit": "proposals/s",
+           "ms_per_step": el * 1e3 / args.uneven_steps, "block": block,
+           "births_attempted_valid_accepted": [int(v) for v in mv[0]],
+           "deaths_attempted_valid_accepted": [int(v) for v in mv[1]]}
+    log(f"[bench] uneven batch with learned births: {out['value']:.4g} proposals/s, "
+        f"{out['ms_per_step']:.2f} ms/sweep; tables for {anchors} anchors in {t_tables:.2f} s")
+    b.close()
+    del traces, b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -695,7 +748,11 @@ def main():
         out["uneven"] = uneven_study(args, dev, args.uneven_block)
         torch.cuda.empty_cache()
     if not args.no_learned:
-        out["learned"] = learned_study(args, dev)
+        out["learned"], net = learned_study(args, dev)
+        if not args.no_uneven:
+            out["uneven_learned"] = uneven_learned_study(args, dev, args.uneven_block, net)
+            out["uneven_learned"]["plain_value"] = out["uneven"]["value"]
+        del net
         torch.cuda.empty_cache()
     if not args.no_paper_world:
         out["paper_world"] = paper_world_study(args, dev)
