@@ -306,7 +306,7 @@ def paper_world_study(args, dev, latent: bool = False):
         # kernel form by a short trial (few work items per colour favour the
         # latency form, many the wave form)
         trial = {}
-        forms = (64,) if sp.schedule == 1 else (256,) if latent else (64, 128, 256)
+        forms = (64,) if sp.schedule == 1 else (64, 256) if latent else (64, 128, 256)
         for block in forms:
             b = batch(sp, block)
             b.run_sweeps(0, 1)

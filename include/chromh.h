@@ -112,7 +112,7 @@ typedef struct {
      * offsets from this prior, location and onset moves carry them along
      * (the arrivals move with the event), and the sampler gains the
      * arrival-time move and the joint move (cmh_sampler).  Runs the
-     * block-256 form of the chromatic schedule. */
+     * block-64 or block-256 forms of the chromatic schedule. */
     double  arrival_sd;
 } cmh_model;
 

@@ -289,8 +289,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
             return fail(CMH_EINVAL, "step_arrival must be positive");
         if (s->p_joint > 0.0 && !(s->step_xy > 0.0 && s->step_t > 0.0))
             return fail(CMH_EINVAL, "the joint move needs positive step_xy and step_t");
-        if (s->block != 0 && s->block != 256)
-            return fail(CMH_EINVAL, "latent arrivals run the block-256 form");
+        if (s->block != 0 && s->block != 64 && s->block != 256)
+            return fail(CMH_EINVAL, "latent arrivals run the block-64 or block-256 form");
         if (s->schedule != 0)
             return fail(CMH_EINVAL, "latent arrivals run the chromatic schedule");
     }
@@ -1039,8 +1039,8 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
     if (st->feed || st->logp) return fail(CMH_EINVAL, "detach feed and log before tuning");
     const Geo &g = st->g;
-    if (g.naive || g.latent) {  // one form only
-        st->block = g.naive ? 64 : 256;
+    if (g.naive) {  // one form only
+        st->block = 64;
         return CMH_OK;
     }
     const auto key = std::make_tuple(g.nsx, g.nsy, g.N, g.gx, g.gy, g.k, g.cap, st->chains,
@@ -1072,7 +1072,9 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    const int cands[4] = {64, 128, 256, 512};
+    // latent arrivals have the wave form and the 256-thread latency form
+    const std::vector<int> cands =
+        g.latent ? std::vector<int>{64, 256} : std::vector<int>{64, 128, 256, 512};
     int best = st->block;
     float best_ms = 1e30f;
     for (int b : cands) {

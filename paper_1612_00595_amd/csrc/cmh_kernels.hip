@@ -1311,8 +1311,12 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
 // wave then evaluates against a private variance in LDS built from its own
 // events; the shared variance is never written and is recomputed from the
 // merged events after the phase.
-template <typename TraceT, bool NAIVE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : 4)))
+// LAT: latent arrival times (line model), as in the latency form: each
+// wave keeps its region's arrival offsets, its draws 8..15 and the joint
+// move's scratch in LDS (about 27 KB more per workgroup, two waves per SIMD).
+template <typename TraceT, bool NAIVE, bool LAT = false>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : (LAT ? 2 : 4))))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
              long long log_first, long long log_n, int *__restrict__ err, int naive_elems)
@@ -1329,6 +1333,10 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     __shared__ double s_prop[4][1][5];
     __shared__ int s_lsta[4][kMaxRegSta];
     __shared__ RegionLearned s_rl[4];
+    // latent arrivals only (one-element stand-ins when LAT is false)
+    __shared__ double s_draw2[LAT ? 4 : 1][LAT ? kWaveDraws : 1][8];
+    __shared__ double s_daw[LAT ? 4 : 1][LAT ? kMaxCap : 1][8];
+    __shared__ LatentLds s_latw[LAT ? 4 : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int q = tid; q < kMaxCap + 2; q += 256) s_log[q] = log((double)q);
@@ -1379,6 +1387,15 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         ex[s] = ev.x[base + s]; ey[s] = ev.y[base + s];
         et[s] = ev.t[base + s]; em[s] = ev.m[base + s];
         eid[s] = ev.id[base + s];
+    }
+    double (*da)[8] = nullptr;
+    LatentLds *lat = nullptr;
+    const double *dsrc2 = nullptr;
+    if constexpr (LAT) {
+        da = s_daw[wv];
+        lat = &s_latw[wv];
+        for (int q = lane; q < n * 8; q += 64) da[q >> 3][q & 7] = ev.da[base * 8 + q];
+        dsrc2 = slots[slot].draws2 + (long long)r * g.k * 8;
     }
     for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     int flags = 0;
@@ -1438,14 +1455,17 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             const int m = min(kWaveDraws, g.k - j);
             for (int q = lane; q < 8 * m; q += 64)
                 s_draw[wv][q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
+            if constexpr (LAT)
+                for (int q = lane; q < 8 * m; q += 64)
+                    s_draw2[wv][q >> 3][q & 7] = dsrc2[(long long)j * 8 + q];
             if (lsrc != nullptr)
                 for (int q = lane; q < 4 * m; q += 64)
                     s_lb[wv][q >> 2][q & 3] = lsrc[(long long)j * 4 + q];
             __builtin_amdgcn_wave_barrier();
         }
-        scout_move<false>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey, et,
-                   em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L, s_lb[wv][jw],
-                   s_lsta[wv], rl);
+        scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey,
+                        et, em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L,
+                        s_lb[wv][jw], s_lsta[wv], rl, LAT ? s_draw2[wv][jw] : nullptr, da, lat);
         __builtin_amdgcn_wave_barrier();
         const MoveHdr h = s_hdr[wv][0];
         const double lnu = s_draw[wv][jw][7];
@@ -1461,6 +1481,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
         else if (h.type == 4)
             la = delta - g.mrate * h.dm;
+        else if (LAT && h.type >= 5)
+            la = delta + h.lx;
         else
             la = delta;
         bool accept = h.valid && lnu < la;
@@ -1470,9 +1492,9 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         if (lane == 0) {
             flags |= h.flags;
-            cnt[3 * h.type]++;
+            cnt[stat_base(h.type)]++;
             if (h.valid) {
-                cnt[3 * h.type + 1]++;
+                cnt[stat_base(h.type) + 1]++;
                 cnt[15] += (unsigned long long)h.S;
             }
             if (use_log) {
@@ -1487,13 +1509,15 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             if (!g.prior_only)
                 wave_write(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
             if (lane == 0) {
-                cnt[3 * h.type + 2]++;
+                cnt[stat_base(h.type) + 2]++;
                 cnt[16] += (unsigned long long)h.S;
                 const double *pr = s_prop[wv][0];
                 if (h.type == 0) {
                     ex[n] = pr[0]; ey[n] = pr[1]; et[n] = pr[2]; em[n] = pr[3];
                     eid[n] = ((unsigned long long)(uint32_t)sweep << 32) |
                              ((unsigned long long)r << 12) | (unsigned long long)j;
+                    if constexpr (LAT)
+                        for (int q = 0; q < 8; ++q) da[n][q] = lat->pda[0][0][q];
                     ++n;
                 } else if (h.type == 1) {
                     const int idx = (int)pr[4];
@@ -1501,11 +1525,22 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                         ex[q] = ex[q + 1]; ey[q] = ey[q + 1];
                         et[q] = et[q + 1]; em[q] = em[q + 1];
                         eid[q] = eid[q + 1];
+                        if constexpr (LAT)
+                            for (int c = 0; c < 8; ++c) da[q][c] = da[q + 1][c];
                     }
                     --n;
                 } else {
                     const int idx = (int)pr[4];
                     ex[idx] = pr[0]; ey[idx] = pr[1]; et[idx] = pr[2]; em[idx] = pr[3];
+                    if constexpr (LAT) {
+                        for (int q = 0; q < 8; ++q) da[idx][q] = lat->pda[0][0][q];
+                        if (h.type == 6) {  // the joint move's second event
+                            const double *p2 = lat->prop2[0];
+                            const int i2 = (int)p2[2];
+                            ex[i2] = p2[0]; et[i2] = p2[1];
+                            for (int q = 0; q < 8; ++q) da[i2][q] = lat->pda[0][1][q];
+                        }
+                    }
                 }
             }
             n = __builtin_amdgcn_readlane(n, 0);
@@ -1518,6 +1553,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         ev.t[base + s] = et[s]; ev.m[base + s] = em[s];
         ev.id[base + s] = eid[s];
     }
+    if constexpr (LAT)
+        for (int q = lane; q < n * 8; q += 64) ev.da[base * 8 + q] = da[q >> 3][q & 7];
     if (lane == 0) {
         ev.cnt[r] = n;
         for (int t = 0; t < kStats; ++t)
@@ -2172,9 +2209,13 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
                                  hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    if (latent) {  // latent arrivals: the latency form of 256 threads only
-        k_sweep_color<TraceT, 256, true><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
-                                                                log_first, log_n, err);
+    if (latent) {  // latent arrivals: the wave form (block 64) or the 256-thread latency form
+        if (block == 64)
+            k_sweep_wave<TraceT, false, true><<<(nitems + 3) / 4, 256, 0, s>>>(
+                slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0);
+        else
+            k_sweep_color<TraceT, 256, true><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr,
+                                                                    logp, log_first, log_n, err);
         return hipGetLastError();
     }
     if (naive_elems > 0) {

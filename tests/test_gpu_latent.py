@@ -61,13 +61,13 @@ def test_latent_simulator_matches_oracle():
         assert np.allclose(g64, ref, rtol=1e-12, atol=1e-15)
 
 
-def _replay(w, nsw, feed_seed=41):
+def _replay(w, nsw, feed_seed=41, block=0):
     from paper_1612_00595_amd import chromh
     m, sp, truth, s = instance(w)
     feed = W.feed_draws(w.sampler, nsw, seed=feed_seed, latent=True)
     R, k = w.sampler.nreg, w.sampler.k
     gpu = chromh.ChromaticSampler(w.model, w.sampler, torch.from_numpy(s).to(DEV), chains=1,
-                                  seed=3)
+                                  seed=3, block=block)
     gpu.set_feed(torch.from_numpy(feed).to(DEV), 0)
     glog = torch.full((nsw, R, k, 4), -1.0, dtype=torch.float64, device=DEV)
     gpu.set_log(glog, 0)
@@ -100,11 +100,12 @@ def _check_state(gpu, ref, m, s, w):
 
 
 @pytest.mark.parametrize("dynamic", [0, 1])
-def test_latent_replay_parity_paper_world(dynamic):
+@pytest.mark.parametrize("block", [64, 256])
+def test_latent_replay_parity_paper_world(block, dynamic):
     w = dataclasses.replace(W.PAPER1D_LATENT, sampler=dataclasses.replace(
         W.PAPER1D_LATENT.sampler, dynamic=dynamic))
-    say("latent replay", w.name, "dynamic", dynamic)
-    gpu, ref, m, s, acc, types, status = _replay(w, 8)
+    say("latent replay", w.name, "dynamic", dynamic, "block", block)
+    gpu, ref, m, s, acc, types, status = _replay(w, 8, block=block)
     acc_arr = int(((types == O.ARR) & (status == 2)).sum())
     say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties, "max rel", acc.max_rel,
         "arrival moves accepted", acc_arr, "joint valid", int(((types == O.JOINT) & (status > 0)).sum()))
@@ -113,10 +114,11 @@ def test_latent_replay_parity_paper_world(dynamic):
     _check_state(gpu, ref, m, s, w)
 
 
-def test_latent_replay_parity_joint_moves():
+@pytest.mark.parametrize("block", [64, 256])
+def test_latent_replay_parity_joint_moves(block):
     w = two_station()
-    say("latent replay", w.name)
-    gpu, ref, m, s, acc, types, status = _replay(w, 10)
+    say("latent replay", w.name, "block", block)
+    gpu, ref, m, s, acc, types, status = _replay(w, 10, block=block)
     joint_acc = int(((types == O.JOINT) & (status == 2)).sum())
     say("moves", acc.moves, "evaluated", acc.evaluated, "joint accepted", joint_acc)
     assert joint_acc >= 20
@@ -125,14 +127,14 @@ def test_latent_replay_parity_joint_moves():
     assert st[6, 2] >= 20 and st[5, 2] > 0
 
 
-@pytest.mark.parametrize("tmpl,dtype", [(1, "f64"), (0, "f32")])
-def test_latent_replay_parity_template_and_f32(tmpl, dtype):
+@pytest.mark.parametrize("tmpl,dtype,block", [(1, "f64", 256), (0, "f32", 256), (1, "f32", 64)])
+def test_latent_replay_parity_template_and_f32(tmpl, dtype, block):
     w = W.PAPER1D_LATENT
     w = dataclasses.replace(w, name=w.name + f"-t{tmpl}-{dtype}", trace_dtype=dtype,
                             model=dataclasses.replace(w.model, tmpl=tmpl),
                             sampler=dataclasses.replace(w.sampler, dynamic=1))
     say("latent replay", w.name)
-    gpu, ref, m, s, acc, types, status = _replay(w, 6)
+    gpu, ref, m, s, acc, types, status = _replay(w, 6, block=block)
     say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties)
     assert acc.evaluated > 5000
     ev = ref.events()
@@ -170,7 +172,8 @@ def test_latent_graph_replay_matches_eager():
     b.close()
 
 
-def test_latent_batch_matches_single_runs():
+@pytest.mark.parametrize("block", [64, 256])
+def test_latent_batch_matches_single_runs(block):
     from paper_1612_00595_amd import chromh
     spec = W.PAPER1D_LATENT_MODEL
     sampler = dataclasses.replace(W.PAPER1D_LATENT_SAMPLER, dynamic=1)
@@ -182,11 +185,12 @@ def test_latent_batch_matches_single_runs():
         traces.append(chromh.simulate(spec, truth, 600 + q, "f64", DEV))
         seeds.append(90 + q)
     say("latent batch of", n, "worlds")
-    b = chromh.Batch([spec] * n, [sampler] * n, traces, seeds)
+    b = chromh.Batch([spec] * n, [sampler] * n, traces, seeds, block=block)
     b.run_sweeps(0, 5)
     torch.cuda.synchronize()
     for q in range(n):
-        one = chromh.ChromaticSampler(spec, sampler, traces[q], chains=1, seed=seeds[q])
+        one = chromh.ChromaticSampler(spec, sampler, traces[q], chains=1, seed=seeds[q],
+                                      block=256 if block == 64 else 64)
         one.run_sweeps(0, 5)
         ref = one.read_events(0)
         compare_events(b.read_events(q), ref, f"world {q}")
@@ -231,8 +235,8 @@ def test_latent_limits_are_checked():
     from paper_1612_00595_amd import chromh
     w = W.PAPER1D_LATENT
     s = torch.zeros((w.model.nsta, w.model.N), dtype=torch.float64, device=DEV)
-    with pytest.raises(chromh.CmhError):  # the throughput form has no latent arrivals
-        chromh.ChromaticSampler(w.model, w.sampler, s, seed=1, block=64)
+    with pytest.raises(chromh.CmhError):  # only the wave and 256-thread latency forms
+        chromh.ChromaticSampler(w.model, w.sampler, s, seed=1, block=128)
     with pytest.raises(chromh.CmhError):  # nor the naive schedule
         chromh.ChromaticSampler(w.model, dataclasses.replace(w.sampler, schedule=1), s, seed=1)
     g = dataclasses.replace(W.SMALL.model, arr_sd=1.0)
