@@ -223,6 +223,23 @@ int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64
  * variance exactly.  Synchronises. */
 int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host, int64_t n);
 
+/* Checkpoint and resume.  cmh_save copies every chain's (or batch
+ * instance's) current event table (with arrival offsets under latent
+ * arrivals), its event variance as the sweeps left it (not recomputed, so a
+ * resumed chain continues bit for bit), its move counters and the layout
+ * parity into the caller's host buffer of cmh_checkpoint_bytes bytes (about
+ * n_stations x n_samples x 8 bytes per chain).  cmh_load writes such a
+ * buffer back into a state made with the same model, sampler settings,
+ * chain count, seed and trace (CMH_EINVAL on any other shape, before
+ * anything is written).  The random draws are keyed by (seed, chain, sweep,
+ * region, move), so the caller resumes with the next sweep index: N sweeps,
+ * save, load into a fresh state, N more sweeps equal 2N sweeps.  Feeds,
+ * logs, recordings and learned tables are not part of the checkpoint (attach
+ * them again).  Both synchronise. */
+int32_t cmh_checkpoint_bytes(cmh_state *st, size_t *bytes);
+int32_t cmh_save(cmh_state *st, void *host_buf, size_t bytes);
+int32_t cmh_load(cmh_state *st, const void *host_buf, size_t bytes);
+
 /* Replay mode.  feed_dev: doubles [n_sweeps][regions][k][8] holding, per
  * move, the draws the sampler would otherwise take from Philox: [0] uniform
  * for the move type, [1] uniform a (index or birth x), [2] uniform b (birth

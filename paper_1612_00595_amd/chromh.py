@@ -63,7 +63,8 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
            "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init",
-           "cmh_batch_learned_bytes", "cmh_batch_set_learned"]
+           "cmh_batch_learned_bytes", "cmh_batch_set_learned", "cmh_checkpoint_bytes", "cmh_save",
+           "cmh_load"]
 
 _lib = None
 
@@ -106,6 +107,9 @@ def lib():
         "cmh_batch_init": ([I32, P, P, P, I32, P, P, C.c_size_t, P, P], I32),
         "cmh_set_learned": ([P, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_batch_learned_bytes": ([P, I32, I32, P], I32),
+        "cmh_checkpoint_bytes": ([P, P], I32),
+        "cmh_save": ([P, P, C.c_size_t], I32),
+        "cmh_load": ([P, P, C.c_size_t], I32),
         "cmh_batch_set_learned": ([P, I32, P, P, I32, D, P, C.c_size_t, P], I32),
         "cmh_mdn_sizes": ([P, P], I32),
         "cmh_mdn_param_bytes": ([P], I32),
@@ -371,6 +375,19 @@ class ChromaticSampler:
         out = np.zeros(n.value, dtype=EVENT_DTYPE)
         check(lib().cmh_read_events(self._h, chain, _ptr(out), len(out), C.byref(n)))
         return out
+
+    def save(self) -> np.ndarray:
+        """A checkpoint of every chain (host bytes); resume with load() on a
+        sampler made the same way, then continue at the next sweep index."""
+        nb = C.c_size_t()
+        check(lib().cmh_checkpoint_bytes(self._h, C.byref(nb)))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        check(lib().cmh_save(self._h, _ptr(buf), buf.nbytes))
+        return buf
+
+    def load(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lib().cmh_load(self._h, _ptr(buf), buf.nbytes))
 
     def write_events(self, chain: int, ev: np.ndarray):
         ev = np.ascontiguousarray(ev, dtype=EVENT_DTYPE)

@@ -839,6 +839,129 @@ int32_t cmh_run_sweeps(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, voi
     return CMH_OK;
 }
 
+// ------------------------------------------------------ checkpoint / resume
+namespace {
+struct CkptHead {
+    char magic[8];
+    uint32_t version, nslots;
+    int32_t cur, pad;
+};
+struct CkptSlot {
+    int32_t nsta, N, R, cap, latent, pad;
+};
+constexpr char kCkptMagic[8] = {'C', 'M', 'H', 'C', 'K', 'P', 'T', '1'};
+
+// Bytes of one slot's part: its current event table (x, y, t, m, id, counts,
+// offsets, arrival offsets when latent), its event variance and counters.
+size_t ckpt_slot_bytes(const Geo &g)
+{
+    const size_t n = (size_t)g.R * g.cap;
+    return sizeof(CkptSlot) + n * (5 * 8 + (g.latent ? 64 : 0)) + (size_t)g.R * 4 + 16 +
+           (size_t)g.nsta * g.N * 8 + (size_t)cmh::kStats * 8;
+}
+
+size_t ckpt_bytes(const cmh_state *st)
+{
+    size_t b = sizeof(CkptHead);
+    for (const cmh::Slot &sl : st->slots_h) b += ckpt_slot_bytes(sl.g);
+    return b;
+}
+
+// Copies between the slot's device arrays and a host record (to_host: device
+// to host).
+int32_t ckpt_copy(const cmh::Slot &sl, int cur, char *rec, bool to_host)
+{
+    const Geo &g = sl.g;
+    const Events &ev = sl.ev[cur];
+    const size_t n = (size_t)g.R * g.cap;
+    struct Part {
+        void *dev;
+        size_t bytes;
+    };
+    const Part parts[] = {{ev.x, n * 8}, {ev.y, n * 8}, {ev.t, n * 8}, {ev.m, n * 8},
+                          {ev.id, n * 8}, {ev.cnt, (size_t)g.R * 4}, {ev.off, 16},
+                          {ev.da, g.latent ? n * 64 : 0}, {sl.E, (size_t)g.nsta * g.N * 8},
+                          {sl.stats, (size_t)cmh::kStats * 8}};
+    char *p = rec;
+    for (const Part &q : parts) {
+        if (q.bytes == 0) continue;
+        if (to_host) HIPCHK(hipMemcpy(p, q.dev, q.bytes, hipMemcpyDeviceToHost));
+        else HIPCHK(hipMemcpy(q.dev, p, q.bytes, hipMemcpyHostToDevice));
+        p += q.bytes;
+    }
+    return CMH_OK;
+}
+}  // namespace
+
+int32_t cmh_checkpoint_bytes(cmh_state *st, size_t *bytes)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!bytes) return fail(CMH_EINVAL, "bytes is NULL");
+    *bytes = ckpt_bytes(st);
+    return CMH_OK;
+}
+
+int32_t cmh_save(cmh_state *st, void *host_buf, size_t bytes)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!host_buf) return fail(CMH_EINVAL, "host_buf is NULL");
+    if (bytes < ckpt_bytes(st)) return fail(CMH_EINVAL, "checkpoint buffer too small");
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    char *p = (char *)host_buf;
+    CkptHead h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.nslots = (uint32_t)st->slots_h.size();
+    h.cur = st->cur;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    for (const cmh::Slot &sl : st->slots_h) {
+        const CkptSlot cs{sl.g.nsta, sl.g.N, sl.g.R, sl.g.cap, sl.g.latent, 0};
+        std::memcpy(p, &cs, sizeof cs);
+        rc = ckpt_copy(sl, st->cur, p + sizeof cs, true);
+        if (rc) return rc;
+        p += ckpt_slot_bytes(sl.g);
+    }
+    return CMH_OK;
+}
+
+int32_t cmh_load(cmh_state *st, const void *host_buf, size_t bytes)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!host_buf) return fail(CMH_EINVAL, "host_buf is NULL");
+    if (bytes < ckpt_bytes(st)) return fail(CMH_EINVAL, "checkpoint buffer too small");
+    const char *p = (const char *)host_buf;
+    CkptHead h;
+    std::memcpy(&h, p, sizeof h);
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+        return fail(CMH_EINVAL, "not a checkpoint of this library");
+    if (h.nslots != st->slots_h.size() || (h.cur != 0 && h.cur != 1))
+        return fail(CMH_EINVAL, "checkpoint of a state with a different number of chains");
+    const char *q = p + sizeof h;
+    for (const cmh::Slot &sl : st->slots_h) {  // validate every slot before writing any
+        CkptSlot cs;
+        std::memcpy(&cs, q, sizeof cs);
+        if (cs.nsta != sl.g.nsta || cs.N != sl.g.N || cs.R != sl.g.R || cs.cap != sl.g.cap ||
+            cs.latent != sl.g.latent)
+            return fail(CMH_EINVAL, "checkpoint of a state with a different shape");
+        q += ckpt_slot_bytes(sl.g);
+    }
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    q = p + sizeof h;
+    for (const cmh::Slot &sl : st->slots_h) {
+        rc = ckpt_copy(sl, h.cur, const_cast<char *>(q) + sizeof(CkptSlot), false);
+        if (rc) return rc;
+        q += ckpt_slot_bytes(sl.g);
+    }
+    st->cur = h.cur;
+    return CMH_OK;
+}
+
 int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64_t cap,
                         int64_t *n_out)
 {

@@ -1,0 +1,107 @@
+"""Checkpoint and resume through the C-ABI: N sweeps, save, N more sweeps
+must equal loading the checkpoint into a fresh state and running the same N
+sweeps, bit for bit (events, arrival offsets, event variance, counters), for
+several chains of a dynamic grid, the line model with latent arrivals, and a
+batch of uneven instances; a checkpoint of another shape is refused."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1612_00595_amd import workloads as W  # noqa: E402
+
+from gpu_cases import compare_events, dynamic_small, instance, say  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check_resume(make, chains, n1, n2):
+    a = make()
+    a.run_sweeps(0, n1)
+    ck = a.save()
+    a.run_sweeps(n1, n2)
+    b = make()
+    b.load(ck)
+    b.run_sweeps(n1, n2)
+    torch.cuda.synchronize()
+    for c in range(chains):
+        compare_events(b.read_events(c), a.read_events(c), f"chain {c}")
+        assert np.array_equal(b.read_counters(c), a.read_counters(c))
+    fresh = make()  # without the checkpoint the same sweeps give another state
+    fresh.run_sweeps(n1, n2)
+    assert any(len(fresh.read_events(c)) != len(a.read_events(c)) or
+               not np.array_equal(fresh.read_events(c)["x"], a.read_events(c)["x"])
+               for c in range(chains))
+    return a, b
+
+
+def test_resume_dynamic_grid_chains():
+    from paper_1612_00595_amd import chromh
+    w = dynamic_small()
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    say("checkpoint: 3 chains of", w.name)
+    a, b = _check_resume(lambda: chromh.ChromaticSampler(w.model, w.sampler, trace, chains=3,
+                                                         seed=8, block=128), 3, 5, 4)
+    for c in range(3):
+        assert np.array_equal(a.read_variance(c), b.read_variance(c))
+
+
+@pytest.mark.parametrize("dynamic", [0, 1])
+def test_resume_latent_line_world(dynamic):
+    from paper_1612_00595_amd import chromh
+    w = dataclasses.replace(W.PAPER1D_LATENT, sampler=dataclasses.replace(
+        W.PAPER1D_LATENT.sampler, dynamic=dynamic, k=100))
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    say("checkpoint: latent line world, dynamic", dynamic)
+    a, b = _check_resume(lambda: chromh.ChromaticSampler(w.model, w.sampler, trace, chains=2,
+                                                         seed=5), 2, 7, 6)
+    assert np.any(a.read_events(0)["da"] != 0.0)
+
+
+def test_resume_uneven_batch():
+    from paper_1612_00595_amd import chromh
+    specs = [W.ModelSpec(nsx=6, nsy=6, N=2000, lam=60.0), W.ModelSpec(nsx=9, nsy=5, N=2500, lam=70.0),
+             W.ModelSpec(nsx=5, nsy=5, N=1500, lam=30.0)]
+    samplers = [W.SamplerSpec(gx=m.nsx, gy=m.nsy, dynamic=1) for m in specs]
+    traces = []
+    for q, m in enumerate(specs):
+        tr = W.truth_events(m, 40 + q)
+        traces.append(chromh.simulate(m, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"]),
+                                      500 + q, "f32", DEV))
+    say("checkpoint: uneven batch of 3")
+    _check_resume(lambda: chromh.Batch(specs, samplers, traces, [1, 2, 3], block=64), 3, 5, 5)
+
+
+def test_checkpoint_of_another_shape_is_refused():
+    from paper_1612_00595_amd import chromh
+    w = dynamic_small()
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    a = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=2, seed=8)
+    ck = a.save()
+    b = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=3, seed=8)
+    with pytest.raises(chromh.CmhError):
+        b.load(ck)
+    w2 = W.SMALL
+    m2, sp2, truth2, s2 = instance(w2)
+    c = chromh.ChromaticSampler(w2.model, w2.sampler, torch.from_numpy(s2).to(DEV), chains=2,
+                                seed=8)
+    with pytest.raises(chromh.CmhError):
+        c.load(ck)
+    bad = ck.copy()
+    bad[0] ^= 0xFF
+    with pytest.raises(chromh.CmhError):
+        a.load(bad)
+    with pytest.raises(chromh.CmhError):
+        a.load(ck[:100])
