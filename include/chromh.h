@@ -55,6 +55,7 @@ extern "C" {
 #define CMH_ECOLOR (-4)   /* no colouring satisfies the independence check */
 #define CMH_ENAN   (-5)   /* NaN/Inf met in a likelihood evaluation */
 #define CMH_ESTATE (-6)   /* state poisoned by an earlier device error */
+#define CMH_ERACE  (-7)   /* debug owner check: two regions of one colour shared a sample */
 
 #define CMH_F32 0
 #define CMH_F64 1
@@ -136,7 +137,15 @@ typedef struct {
                                    recomputed from the merged events.  Naive needs
                                    n_stations x n_samples <= 2048 (a private copy per
                                    region in LDS) and runs the block-64 form. */
-    int32_t _pad0;
+    int32_t debug;              /* bit 0: owner check.  Every sample a move reads or writes
+                                   is tagged with (sweep, colour, region) in a workspace array
+                                   of 8 bytes per sample per chain; meeting another region's
+                                   tag of the same colour phase latches CMH_ERACE (the
+                                   colouring of Section 4.1 failed to make the regions of one
+                                   colour independent).  Chromatic schedule only.  Bit 1
+                                   (with bit 0 and a period): take the period without the
+                                   independence check, so that a test can force a breach
+                                   for the owner check to catch.  0 for production runs. */
     /* Latent arrivals only (0 otherwise).  p_arrival: the arrival-time move
      * of Section 3 (one event, one station drawn uniformly, its offset plus
      * step_arrival times a standard normal; the offset prior enters the

@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchromh.so")
 
 CMH_F32, CMH_F64 = 0, 1
-ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ECAP", -4: "ECOLOR", -5: "ENAN", -6: "ESTATE"}
+ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ECAP", -4: "ECOLOR", -5: "ENAN", -6: "ESTATE",
+          -7: "ERACE"}
 
 EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("t", "<f8"), ("m", "<f8"),
                         ("id", "<u8"), ("region", "<i4"), ("_pad", "<i4"),
@@ -43,7 +44,7 @@ class CmhSampler(C.Structure):
                 ("p_death", C.c_double), ("p_loc", C.c_double), ("p_time", C.c_double),
                 ("p_mag", C.c_double), ("step_xy", C.c_double), ("step_t", C.c_double),
                 ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32),
-                ("schedule", C.c_int32), ("_pad0", C.c_int32), ("p_arrival", C.c_double),
+                ("schedule", C.c_int32), ("debug", C.c_int32), ("p_arrival", C.c_double),
                 ("p_joint", C.c_double), ("step_arrival", C.c_double)]
 
 
@@ -161,6 +162,7 @@ def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
     s.p_birth, s.p_death, s.p_loc, s.p_time, s.p_mag = spec.pb, spec.pd, spec.ploc, spec.pt, spec.pm
     s.step_xy, s.step_t, s.step_m = spec.sxy, spec.st, spec.sm
     s.prior_only, s.block, s.schedule = spec.prior_only, block, spec.schedule
+    s.debug = spec.debug
     s.p_arrival, s.p_joint, s.step_arrival = spec.pa, spec.pj, spec.sa
     return s
 

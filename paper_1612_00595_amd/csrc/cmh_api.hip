@@ -194,8 +194,12 @@ long long line_conflicts(const cmh_model *m, int gx, double offt, int p)
 }
 
 int32_t choose_line_period(const cmh_model *m, int gx, double offt, int dynamic, int requested,
-                           int *period)
+                           int *period, bool unchecked)
 {
+    if (unchecked && requested > 0) {  // debug: the owner check is to catch the breach
+        *period = requested;
+        return CMH_OK;
+    }
     const double w = (double)m->n_samples / (double)gx;
     int p;
     if (dynamic) {
@@ -223,9 +227,13 @@ int32_t choose_line_period(const cmh_model *m, int gx, double offt, int dynamic,
 }
 
 int32_t choose_period(const cmh_model *m, int gx, int gy, double offx, double offy, int dynamic,
-                      int requested, int *period)
+                      int requested, int *period, bool unchecked = false)
 {
-    if (m->line) return choose_line_period(m, gx, offx, dynamic, requested, period);
+    if (m->line) return choose_line_period(m, gx, offx, dynamic, requested, period, unchecked);
+    if (unchecked && requested > 0) {  // debug: the owner check is to catch the breach
+        *period = requested;
+        return CMH_OK;
+    }
     const double Lx = (double)m->nsx * m->ds, Ly = (double)m->nsy * m->ds;
     const double w = std::min(Lx / (double)gx, Ly / (double)gy);
     int p;
@@ -294,6 +302,11 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         if (s->schedule != 0)
             return fail(CMH_EINVAL, "latent arrivals run the chromatic schedule");
     }
+    if (s->debug & ~3) return fail(CMH_EINVAL, "debug takes bits 0 and 1 only");
+    if ((s->debug & 1) && s->schedule != 0)
+        return fail(CMH_EINVAL, "the owner check needs the chromatic schedule");
+    if ((s->debug & 2) && !(s->debug & 1 && s->period > 0))
+        return fail(CMH_EINVAL, "an unchecked period needs the owner check and a period");
     if (s->schedule == 1) {
         if ((long long)m->nsx * m->nsy * m->n_samples > cmh::kNaiveMax)
             return fail(CMH_EINVAL, "the naive schedule needs stations x samples <= 2048");
@@ -301,7 +314,8 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
             return fail(CMH_EINVAL, "the naive schedule runs the block-64 form");
     }
     int p = 0;
-    rc = choose_period(m, s->grid_x, s->grid_y, 0.0, 0.0, s->dynamic, s->period, &p);
+    rc = choose_period(m, s->grid_x, s->grid_y, 0.0, 0.0, s->dynamic, s->period, &p,
+                       (s->debug & 2) != 0);
     if (rc) return rc;
 
     std::memset(g, 0, sizeof *g);
@@ -364,6 +378,7 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         g->sa = s->step_arrival;
         g->c6 = g->c5 + g->pa;
     }
+    g->owner = s->debug & 1;
     return CMH_OK;
 }
 
@@ -412,6 +427,7 @@ struct cmh_state {
     double *llout = nullptr;
     double *draws = nullptr;  // [chain][region][move][8] for the current sweep
     double *draws2 = nullptr; // latent arrivals: draws 8..15, same layout
+    unsigned long long *owner = nullptr;  // debug owner check: [chain][nsta][N] tags
     int block = 256;
     const double *feed = nullptr;
     long long feed_first = 0, feed_n = 0;
@@ -461,7 +477,10 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     cmh::Slot *slots = c.take<cmh::Slot>((size_t)chains);
     unsigned *items_all = c.take<unsigned>((size_t)chains * g.R);
     unsigned *items_col = c.take<unsigned>((size_t)chains * g.R);
+    unsigned long long *owner =
+        g.owner ? c.take<unsigned long long>((size_t)chains * g.nsta * (size_t)g.N) : nullptr;
     if (st) {
+        st->owner = owner;
         st->slots_d = slots;
         st->items_all = items_all;
         st->items_col = items_col;
@@ -500,6 +519,7 @@ cmh::Slot chain_slot(const cmh_state *st, int c)
     sl.draws = st->draws + (size_t)c * g.R * g.k * 8;
     sl.draws2 = st->draws2 ? st->draws2 + (size_t)c * g.R * g.k * 8 : nullptr;
     sl.stats = st->stats + (size_t)c * cmh::kStats;
+    sl.owner = st->owner ? st->owner + (size_t)c * g.nsta * (size_t)g.N : nullptr;
     sl.L = st->learned;
     if (sl.L.tab) {
         sl.L.birth = st->learned.birth + (size_t)c * g.R * g.k * 4;
@@ -564,6 +584,8 @@ int32_t sync_and_check(cmh_state *st)
     HIPCHK(hipMemcpy(&flags, st->err, sizeof(int), hipMemcpyDeviceToHost));
     if (flags) {
         st->poisoned = 1;
+        if (flags & cmh::kFlagRace)
+            return fail(CMH_ERACE, "two regions of one colour shared a sample in one phase");
         if (flags & cmh::kFlagCap) return fail(CMH_ECAP, "a region exceeded its event capacity");
         if (flags & cmh::kFlagNan) return fail(CMH_ENAN, "NaN or Inf in a likelihood change");
         if (flags & cmh::kFlagSta)
@@ -695,7 +717,7 @@ int32_t cmh_partition_and_color(const cmh_model *model, int32_t grid_x, int32_t 
         if (!(off_x >= 0.0 && off_x < w) || off_y != 0.0)
             return fail(CMH_EINVAL, "line model: offset in [0, w), off_y = 0");
         int p = 0;
-        rc = choose_line_period(model, grid_x, off_x, dynamic ? 1 : 0, 0, &p);
+        rc = choose_line_period(model, grid_x, off_x, dynamic ? 1 : 0, 0, &p, false);
         if (rc) return rc;
         *n_reg_x = grid_x + 1;
         *n_reg_y = 1;
@@ -778,6 +800,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     }
     if (!e) e = cmh::fill_i32(st->err, 1, 0, s);
     if (!e) e = cmh::fill_u64(st->stats, (long long)cmh::kStats * n_chains, s);
+    if (!e && st->owner) e = cmh::fill_u64(st->owner, nE, s);
     if (!e) e = cmh::set_sweep(st->sweep_ctr, 0, s);
     if (e) {
         if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
@@ -958,6 +981,9 @@ int32_t cmh_load(cmh_state *st, const void *host_buf, size_t bytes)
         if (rc) return rc;
         q += ckpt_slot_bytes(sl.g);
     }
+    for (const cmh::Slot &sl : st->slots_h)  // the resumed run starts with no owner tags
+        if (sl.owner) HIPCHK(cmh::fill_u64(sl.owner, (long long)sl.g.nsta * sl.g.N, nullptr));
+    HIPCHK(hipDeviceSynchronize());
     st->cur = h.cur;
     return CMH_OK;
 }
@@ -1458,6 +1484,7 @@ size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots
         sl.draws = c.take<double>((size_t)g.R * g.k * 8);
         sl.draws2 = g.latent ? c.take<double>((size_t)g.R * g.k * 8) : nullptr;
         sl.stats = c.take<unsigned long long>(cmh::kStats);
+        sl.owner = g.owner ? c.take<unsigned long long>((size_t)g.nsta * (size_t)g.N) : nullptr;
         if (slots) (*slots)[q] = sl;
         total_r += g.R;
     }
@@ -1533,6 +1560,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
             if (!e) e = cmh::fill_f64(sl.ev[b].off, 2, 0.0, s);
         }
         if (!e) e = cmh::fill_u64(sl.stats, cmh::kStats, s);
+        if (!e && sl.owner) e = cmh::fill_u64(sl.owner, nE, s);
         for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)q << 16) | (unsigned)r);
         st->refresh_max = std::max(st->refresh_max, cmh::refresh_blocks(g));
         st->naive_elems = std::max(st->naive_elems, g.nsta * g.N);

@@ -22,7 +22,7 @@ constexpr int kMaxTileEvents = 640;  // events reaching one station tile
 constexpr int kMaxRegSta = 16;       // stations of one region, learned births
 constexpr int kNaiveMax = 2048;      // stations x samples of an instance, naive schedule
 
-enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16 };
+enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16, kFlagRace = 32 };
 
 // Per-chain statistics: [3 t + 0..2] attempted / evaluated / accepted moves of
 // type t < 5, [15] footprint samples evaluated, [16] footprint samples
@@ -66,6 +66,7 @@ struct Geo {
     double arr_sd, arr_e, arr_2v;  // arrival_sd; kArrTrunc * arrival_sd; 2 arrival_sd^2
     double pa, pj, sa;      // arrival and joint move probabilities, arrival step
     double c5, c6;          // cumulative thresholds after the magnitude, arrival moves
+    int owner, pad_owner;   // 1: the debug owner check (Slot::owner)
 };
 
 // Learned birth proposal: a mixture over the anchors (station, window) of
@@ -115,6 +116,12 @@ struct Slot {
     double *draws2;       // latent arrivals: draws 8..15 of each record [R][k][8]
     unsigned long long *stats;
     Learned L;
+    // Debug owner check (else nullptr): per sample of E the tag
+    // (phase << 16) | region of the last move that read or wrote it, with
+    // phase = sweep * colours + colour + 1.  A move that finds another
+    // region's tag of its own phase proves that two regions of one colour
+    // share a sample, which the colouring must rule out.
+    unsigned long long *owner;  // [nsta][N]
 };
 
 // ---------------------------------------------------------------- Philox
@@ -191,10 +198,12 @@ __host__ __device__ inline int event_region(const Geo &g, double offx, double of
 // the variance scale B = A^2 exp(-2 (n0 - a) / decay), so that the variance
 // the event adds at sample n0 + q is B exp(-2 q / decay).  Under the
 // mean-template likelihood B = A exp(-(n0 - a) / decay) scales the waveform
-// B exp(-q / decay) the event adds to the mean.
+// B exp(-q / decay) the event adds to the mean.  n0 = ceil(a) is negative
+// where a latent offset puts the arrival before the trace; the samples the
+// event affects are then [0, n1).
 struct Arrival {
     int in;       // d < rc and the window meets the trace
-    int n0, n1;   // [n0, n1): affected samples; n0 = ceil(a)
+    int n0, n1;   // n0 = ceil(a), n1 = min(n0 + ts, N): the window, [max(n0, 0), n1) in the trace
     double B;
 };
 
@@ -214,7 +223,10 @@ __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, dou
     ar.n0 = 0;
     ar.n1 = 0;
     ar.B = 0.0;
-    if (d < g.rc && c < (double)g.N) {
+    // the window [ceil(a), ceil(a) + ts) must meet the trace [0, N): a latent
+    // offset can put an arrival before the first sample, and n0 is then
+    // negative (users clip the runs they touch at 0)
+    if (d < g.rc && c < (double)g.N && c + (double)g.ts > 0.0) {
         ar.n0 = (int)c;
         ar.n1 = ar.n0 + g.ts < g.N ? ar.n0 + g.ts : g.N;
         // A^2 exp(-2 (c - a) / decay) with A = m exp(-d / atten), one exponential

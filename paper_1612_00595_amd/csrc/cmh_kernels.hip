@@ -539,22 +539,25 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
             sa.w0 = an.in ? an.n0 : 0; sa.w1 = an.in ? an.n1 : 0;
             sa.Bo = ao.B; sa.Bn = an.B;
             sb = sa;
+            // the runs start at the first sample of the trace at the
+            // earliest (o0 and w0 keep the arrival's own first sample)
+            const int ob = max(ao.n0, 0), nb = max(an.n0, 0);
             if (ao.in && an.in) {
-                if (max(ao.n0, an.n0) <= min(ao.n1, an.n1)) {  // overlapping or touching
-                    sa.lo = min(ao.n0, an.n0);
+                if (max(ob, nb) <= min(ao.n1, an.n1)) {  // overlapping or touching
+                    sa.lo = min(ob, nb);
                     sa.len = max(ao.n1, an.n1) - sa.lo;
                     ns = 1;
-                } else {                                         // disjoint, sample order
-                    sa.lo = min(ao.n0, an.n0);
-                    sa.len = (ao.n0 < an.n0 ? ao.n1 : an.n1) - sa.lo;
-                    sb.lo = max(ao.n0, an.n0);
-                    sb.len = (ao.n0 < an.n0 ? an.n1 : ao.n1) - sb.lo;
+                } else {                                   // disjoint, sample order
+                    sa.lo = min(ob, nb);
+                    sa.len = (ob < nb ? ao.n1 : an.n1) - sa.lo;
+                    sb.lo = max(ob, nb);
+                    sb.len = (ob < nb ? an.n1 : ao.n1) - sb.lo;
                     ns = 2;
                 }
             } else if (ao.in) {
-                sa.lo = ao.n0; sa.len = ao.n1 - ao.n0; ns = 1;
+                sa.lo = ob; sa.len = ao.n1 - ob; ns = 1;
             } else {
-                sa.lo = an.n0; sa.len = an.n1 - an.n0; ns = 1;
+                sa.lo = nb; sa.len = an.n1 - nb; ns = 1;
             }
             nsamp = sa.len + (ns == 2 ? sb.len : 0);
         }
@@ -594,6 +597,14 @@ struct LatentLds {
     JointScratch js;
 };
 
+// Debug owner tag of region r = (i, kk) in its colour phase of a sweep; the
+// region's colour is (i mod p) + p (kk mod p) (i mod p on the line).
+__device__ inline unsigned long long owner_tag(const Geo &g, long long sweep, int i, int kk, int r)
+{
+    const long long colour = (long long)(i % g.period) + (long long)g.period * (kk % g.period);
+    return ((unsigned long long)(sweep * g.ncolors + colour + 1) << 16) | (unsigned long long)r;
+}
+
 // Wave 0 of a sweep workgroup ("scout"): builds move jj's proposal from its
 // draws and the region's current events, and its footprint, into buffer
 // `buf`.  Lane 0 owns the event table; the other lanes help with the
@@ -608,7 +619,8 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
                                   SegIndex *s_six, const double *lsx, MoveHdr *s_hdr, double (*s_prop)[5], int max_samples,
                                   const Learned &L, const double *lb, const int *lsta,
                                   const RegionLearned &rl, const double *d2 = nullptr,
-                                  const double (*s_da)[8] = nullptr, LatentLds *lat = nullptr)
+                                  const double (*s_da)[8] = nullptr, LatentLds *lat = nullptr,
+                                  unsigned long long *own = nullptr, unsigned long long tag = 0)
 {
     int type = 0, valid = 0, idx = -1, mflags = 0;
     double ox = 0, oy = 0, ot = 0, om = 0, nx = 0, ny = 0, nt = 0, nm = 0, lr = 0, lx = 0;
@@ -825,6 +837,22 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
             mflags |= kFlagSeg;
         }
     }
+    if (own != nullptr && valid && nseg > 0) {
+        // debug owner check: every sample the move reads (and, if accepted,
+        // writes) takes this region's tag; another region's tag of this
+        // phase means the colouring let two regions share the sample
+        __builtin_amdgcn_wave_barrier();
+        int race = 0;
+        for (int t = 0; t < nseg; ++t) {
+            const Seg &sg = s_seg[buf][t];
+            unsigned long long *row = own + (long long)sg.j * g.N + sg.lo;
+            for (int f = lane; f < sg.len; f += 64) {
+                const unsigned long long old = atomicExch(row + f, tag);
+                race |= (old >> 16) == (tag >> 16) && old != tag;
+            }
+        }
+        if (__ballot(race != 0) != 0ull) mflags |= kFlagRace;
+    }
     if (lane == 0) {
         MoveHdr h;
         h.valid = valid; h.type = type; h.n = n; h.nseg = nseg; h.S = S; h.flags = mflags;
@@ -898,6 +926,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     const int chain = 0;  // every array of the slot is slot-local
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
+    unsigned long long *const own = slots[slot].owner;
+    const unsigned long long tag = own != nullptr ? owner_tag(g, sweep, i, kk, r) : 0ull;
 
     const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
     const RegionBox box = region_box(g, offx, offy, i, kk);
@@ -963,7 +993,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     if (wave == 0)
         scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex,
                         s_ey, s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
-                        s_lb[0][0], s_lsta, rl, LAT ? s_draw2[0][0] : nullptr, s_da, s_lat);
+                        s_lb[0][0], s_lsta, rl, LAT ? s_draw2[0][0] : nullptr, s_da, s_lat, own,
+                        tag);
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -1000,7 +1031,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                                 s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
                                 s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl,
                                 LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr, s_da,
-                                s_lat);
+                                s_lat, own, tag);
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
@@ -1188,7 +1219,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                                         kMaxFootprint, L, s_lb[((j + 1) >> 6) & 1][(j + 1) & 63],
                                         s_lsta, rl,
                                         LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr,
-                                        s_da, s_lat);
+                                        s_da, s_lat, own, tag);
                     __syncthreads();
                 } else if (h.type <= 1) {
                     if (tid == 0) {
@@ -1338,7 +1369,10 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     __shared__ double s_daw[LAT ? 4 : 1][LAT ? kMaxCap : 1][8];
     __shared__ LatentLds s_latw[LAT ? 4 : 1];
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave's index, and everything derived from it (work item, slot,
+    // region), held in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < kMaxCap + 2; q += 256) s_log[q] = log((double)q);
     __syncthreads();  // the only barrier: every wave passes it before any leaves
     const int it = blockIdx.x * 4 + wv;
@@ -1362,6 +1396,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     const Learned &L = s_L[wv];
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
+    unsigned long long *const own = slots[slot].owner;
+    const unsigned long long tag = own != nullptr ? owner_tag(g, sweep, i, kk, r) : 0ull;
     __shared__ double s_rc[4][10];
     if (lane == 0) {
         double *c = s_rc[wv];
@@ -1465,7 +1501,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey,
                         et, em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L,
-                        s_lb[wv][jw], s_lsta[wv], rl, LAT ? s_draw2[wv][jw] : nullptr, da, lat);
+                        s_lb[wv][jw], s_lsta[wv], rl, LAT ? s_draw2[wv][jw] : nullptr, da, lat,
+                        own, tag);
         __builtin_amdgcn_wave_barrier();
         const MoveHdr h = s_hdr[wv][0];
         const double lnu = s_draw[wv][jw][7];

@@ -92,6 +92,7 @@ class SamplerSpec:
     pa: float = 0.0            # latent arrivals: arrival-time move probability
     pj: float = 0.0            # latent arrivals: joint two-event move probability
     sa: float = 0.0            # latent arrivals: arrival step
+    debug: int = 0             # library only: bit 0 owner check, bit 1 unchecked period
 
     @property
     def nreg(self) -> int:

@@ -61,9 +61,18 @@ def test_latent_simulator_matches_oracle():
         assert np.allclose(g64, ref, rtol=1e-12, atol=1e-15)
 
 
-def _replay(w, nsw, feed_seed=41, block=0):
+def _early_arrivals(model, ev) -> int:
+    """Events of ev with an arrival at least one sample before the trace."""
+    n = 0
+    for e in ev:
+        a = [e["t"] + abs(e["x"] - sx) / model.vel + e["da"][j] for j, sx in enumerate(model.sta_x)]
+        n += min(np.ceil(a)) < 0
+    return n
+
+
+def _replay(w, nsw, feed_seed=41, block=0, inst=None, early=None, start=None):
     from paper_1612_00595_amd import chromh
-    m, sp, truth, s = instance(w)
+    m, sp, truth, s = instance(w) if inst is None else inst
     feed = W.feed_draws(w.sampler, nsw, seed=feed_seed, latent=True)
     R, k = w.sampler.nreg, w.sampler.k
     gpu = chromh.ChromaticSampler(w.model, w.sampler, torch.from_numpy(s).to(DEV), chains=1,
@@ -72,6 +81,9 @@ def _replay(w, nsw, feed_seed=41, block=0):
     glog = torch.full((nsw, R, k, 4), -1.0, dtype=torch.float64, device=DEV)
     gpu.set_log(glog, 0)
     ref = O.Chain(m, sp, s, seed=3)
+    if start is not None:  # both chains start from the same events
+        gpu.write_events(0, start)
+        assert ref.set_events(start) == 0
     rlog = np.full((nsw, R, k, 4), -1.0)
     acc = LogCheck()
     for sw in range(nsw):
@@ -81,6 +93,8 @@ def _replay(w, nsw, feed_seed=41, block=0):
             assert ref.phase(sw, c, feed=np.ascontiguousarray(feed[sw]), log=rlog[sw]) == 0
             gpu.sweep_color(sw, c)
             compare_events(gpu.read_events(0), ref.events(), f"sweep {sw} colour {c}")
+            if early is not None:
+                early.append(_early_arrivals(w.model, ref.events()))
         if not compare_logs(glog[sw].cpu().numpy(), rlog[sw], feed[sw], acc, f"sweep {sw}"):
             say("decision tie at sweep", sw, "- stopping the bit-exact comparison")
             break
@@ -125,6 +139,60 @@ def test_latent_replay_parity_joint_moves(block):
     _check_state(gpu, ref, m, s, w)
     st = gpu.read_stats(0)
     assert st[6, 2] >= 20 and st[5, 2] > 0
+
+
+def early_world():
+    """The paper's line with a wide offset prior (sd 3, so offsets reach 12
+    samples) and true events at the very start of the trace whose arrivals
+    at the nearest stations precede the first sample."""
+    model = dataclasses.replace(W.PAPER1D_LATENT_MODEL, arr_sd=3.0)
+    return W.Workload(name="line4-x100-n240-latent-sd3-early", model=model,
+                      sampler=W.PAPER1D_LATENT_SAMPLER, trace_dtype="f64", sweeps=8, seed=2)
+
+
+def early_instance(w):
+    m = O.make_model(**w.model.asdict())
+    sp = O.make_sampler(**w.sampler.asdict())
+    da = np.zeros((4, 8))
+    da[0, :4] = [-9.0, 2.0, -3.0, 1.0]
+    da[1, :4] = [4.0, -10.0, 0.5, -1.0]
+    da[2, :4] = [-11.0, -6.0, 0.0, 3.0]
+    truth = O.as_events([0.5, 34.0, 2.0, 70.0], [0.0] * 4, [0.3, 1.5, 4.0, 120.0],
+                        [w.model.mmin] * 4, da=da)
+    return m, sp, truth, O.simulate(m, truth, 1000 + w.seed)
+
+
+def test_latent_refresh_with_arrivals_before_the_trace():
+    from paper_1612_00595_amd import chromh
+    w = early_world()
+    m, sp, truth, s = early_instance(w)
+    assert _early_arrivals(w.model, truth) >= 3
+    say("latent refresh, arrivals before the trace")
+    gpu = chromh.ChromaticSampler(w.model, w.sampler, torch.from_numpy(s).to(DEV), chains=1, seed=3)
+    gpu.write_events(0, truth)
+    gpu.refresh(write_variance=True, loglik=False)
+    E = gpu.read_variance(0)
+    Er = O.event_variance(m, gpu.read_events(0))
+    assert np.array_equal(E, Er)
+    ll = gpu.refresh(write_variance=False, loglik=True)[0]
+    assert ll == pytest.approx(O.loglik(m, s, truth), rel=1e-10)
+
+
+@pytest.mark.parametrize("block", [64, 256])
+def test_latent_replay_parity_arrivals_before_the_trace(block):
+    """Footprints whose windows start before the first sample: the runs are
+    cut at sample 0, exactly as the oracle's windows."""
+    w = early_world()
+    say("latent replay, arrivals before the trace, block", block)
+    early = []
+    inst = early_instance(w)
+    gpu, ref, m, s, acc, types, status = _replay(w, 8, block=block, inst=inst, early=early,
+                                                 start=inst[2])
+    say("moves", acc.moves, "evaluated", acc.evaluated, "states with early arrivals",
+        sum(1 for q in early if q), "of", len(early))
+    assert acc.evaluated > 5000
+    assert sum(1 for q in early if q) >= len(early) // 2
+    _check_state(gpu, ref, m, s, w)
 
 
 @pytest.mark.parametrize("tmpl,dtype,block", [(1, "f64", 256), (0, "f32", 256), (1, "f32", 64)])

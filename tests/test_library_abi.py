@@ -108,3 +108,37 @@ def test_line_model_validation():
         chromh.partition_and_color(dataclasses.replace(spec, nsx=9), 4, 0, 0.0, 0.0, 0)
     with pytest.raises(chromh.CmhError):  # offset outside [0, w)
         chromh.partition_and_color(spec, 4, 0, 60.0, 0.0, 1)
+
+
+def test_owner_check_validation_and_workspace(orc):
+    """The debug owner check: its bits, its modes, its workspace (8 bytes per
+    sample per chain), and the unchecked period that only it may request."""
+    L = chromh.lib()
+    m = chromh.model_struct(W.SMALL.model)
+    nb = C.c_size_t()
+    sizes = {}
+    for debug in (0, 1):
+        s = chromh.sampler_struct(W.SMALL.sampler)
+        s.debug = debug
+        assert L.cmh_state_bytes(C.byref(m), C.byref(s), 3, C.byref(nb)) == 0
+        sizes[debug] = nb.value
+    assert sizes[1] - sizes[0] >= 3 * W.SMALL.model.nsta * W.SMALL.model.N * 8
+    assert sizes[1] - sizes[0] <= 3 * W.SMALL.model.nsta * W.SMALL.model.N * 8 + 4096
+
+    def rc(**kw):
+        s = chromh.sampler_struct(W.SMALL.sampler)
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return L.cmh_state_bytes(C.byref(m), C.byref(s), 1, C.byref(nb))
+
+    assert rc(debug=4) == -1
+    assert rc(debug=2, period=1) == -1      # unchecked period without the owner check
+    assert rc(debug=3, period=0) == -1      # unchecked, but no period given
+    assert rc(debug=1, schedule=1, block=64) == -1  # naive regions share samples by design
+    # period 1 puts neighbouring regions in one colour: refused, unless forced
+    om = orc.make_model(**W.SMALL.model.asdict())
+    assert orc.coloring_violations(om, W.SMALL.sampler.gx, W.SMALL.sampler.gy, 0.0, 0.0, 1) > 0
+    assert rc(period=1) == -4
+    assert rc(debug=1, period=1) == -4
+    assert rc(debug=3, period=1) == 0
+    assert chromh.ERRORS[-7] == "ERACE"

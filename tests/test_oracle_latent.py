@@ -354,3 +354,65 @@ def test_latent_chromatic_agrees_with_serial(orc):
         dc = abs(serial[0].mean() - other[0].mean())
         tv = 0.5 * np.abs(serial[1] - other[1]).sum()
         assert dc < 4 * math.hypot(*se) + 0.05 and tv < 0.08, (name, dc, se, tv)
+
+
+@pytest.mark.parametrize("arr_sd", [1.0, 3.0])
+def test_arrivals_before_the_trace(orc, arr_sd):
+    """A negative offset can put an arrival before the first sample: the
+    signal is then present on the part of its window inside the trace only,
+    [max(ceil a, 0), ceil a + ts); a window that ends before the trace starts
+    leaves no trace at all."""
+    spec, m = latent_model(orc, arr_sd=arr_sd)
+    e = 4.0 * arr_sd
+    cases = [(0.2, 0.0, -0.9 * e), (1.0, 10.0, -0.6 * e), (0.05, 0.0, -0.99 * e), (3.7, 40.0, 0.0),
+             (0.0, 100.0, -0.5 * e)]
+    for t, x, d in cases:
+        da = np.zeros(8)
+        da[:4] = [d, d / 2, -d / 3, d]
+        E = orc.event_variance(m, orc.as_events([x], [0.0], [t], [spec.mmin], da=[da]))
+        for j, sx in enumerate(spec.sta_x):
+            c = math.ceil(t + abs(x - sx) / spec.vel + da[j])
+            want = np.zeros(spec.N)
+            for n in range(spec.N):
+                if c <= n < c + spec.ts:
+                    want[n] = spec.mmin ** 2
+            assert np.array_equal(E[j], want), (t, x, j, c)
+    # an arrival ten or more samples before the trace leaves nothing
+    if e > spec.ts + 1:
+        da = np.zeros(8)
+        da[0] = -(spec.ts + 0.5)
+        E = orc.event_variance(m, orc.as_events([0.0], [0.0], [0.1], [spec.mmin], da=[da]))
+        assert not E[0].any() and E[1].any()
+
+
+def test_arrival_move_delta_before_the_trace(orc):
+    """Arrival moves that carry a window across the first sample: the
+    oracle's change equals the full recomputation."""
+    spec, m = latent_model(orc, arr_sd=3.0)
+    sp = latent_sampler(orc, dynamic=0)
+    truth = orc.as_events([0.5, 34.0, 60.0], [0.0] * 3, [0.3, 1.5, 20.0], [spec.mmin] * 3,
+                          da=[[-9.0, 2.0, -3.0, 1.0, 0, 0, 0, 0], [4.0, -10.0, 0.5, -1.0, 0, 0, 0, 0],
+                              [0.0] * 8])
+    s = orc.simulate(m, truth, 11)
+    ch = orc.Chain(m, sp, s, seed=1)
+    ch.set_events(truth)
+    ch.begin_sweep(0)
+    X = ch.events()
+    base = orc.loglik(m, s, X)
+    rng = np.random.default_rng(9)
+    crossed = 0
+    for trial in range(80):
+        q = int(rng.integers(2))
+        r = int(X["region"][q])
+        own = np.nonzero(X["region"] == r)[0]
+        p = X[q].copy()
+        j = int(rng.integers(spec.nsx))
+        p["da"][j] = rng.uniform(-12.0, 12.0)
+        a_old = X[q]["t"] + abs(X[q]["x"] - spec.sta_x[j]) / spec.vel + X[q]["da"][j]
+        a_new = p["t"] + abs(p["x"] - spec.sta_x[j]) / spec.vel + p["da"][j]
+        crossed += (math.ceil(a_old) < 0) != (math.ceil(a_new) < 0)
+        X2 = X.copy()
+        X2[q] = p
+        d = ch.delta(r, orc.ARR, int(np.nonzero(own == q)[0][0]), p)
+        assert d == pytest.approx(orc.loglik(m, s, X2) - base, rel=1e-9, abs=1e-8)
+    assert crossed >= 10
