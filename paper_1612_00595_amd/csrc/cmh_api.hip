@@ -428,6 +428,7 @@ struct cmh_state {
     double *draws = nullptr;  // [chain][region][move][8] for the current sweep
     double *draws2 = nullptr; // latent arrivals: draws 8..15, same layout
     unsigned long long *owner = nullptr;  // debug owner check: [chain][nsta][N] tags
+    int owner_any = 0;  // some slot runs the owner check (its kernel instantiations)
     int block = 256;
     const double *feed = nullptr;
     long long feed_first = 0, feed_n = 0;
@@ -640,7 +641,8 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
     hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
                                      st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
                                      st->log_first, st->log_n, st->err, st->block,
-                                     st->g.naive ? st->naive_elems : 0, st->g.latent, s);
+                                     st->g.naive ? st->naive_elems : 0, st->g.latent,
+                                     st->owner_any, s);
     if (!e && st->g.naive)  // the merged events' variance after the single naive phase
         e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
                                       st->f64, st->err, s);
@@ -801,6 +803,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     if (!e) e = cmh::fill_i32(st->err, 1, 0, s);
     if (!e) e = cmh::fill_u64(st->stats, (long long)cmh::kStats * n_chains, s);
     if (!e && st->owner) e = cmh::fill_u64(st->owner, nE, s);
+    st->owner_any = st->owner != nullptr;
     if (!e) e = cmh::set_sweep(st->sweep_ctr, 0, s);
     if (e) {
         if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
@@ -1561,6 +1564,7 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
         }
         if (!e) e = cmh::fill_u64(sl.stats, cmh::kStats, s);
         if (!e && sl.owner) e = cmh::fill_u64(sl.owner, nE, s);
+        if (sl.owner) st->owner_any = 1;
         for (int r = 0; r < g.R; ++r) all.push_back(((unsigned)q << 16) | (unsigned)r);
         st->refresh_max = std::max(st->refresh_max, cmh::refresh_blocks(g));
         st->naive_elems = std::max(st->naive_elems, g.nsta * g.N);

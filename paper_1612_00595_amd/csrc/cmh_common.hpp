@@ -202,7 +202,7 @@ __host__ __device__ inline int event_region(const Geo &g, double offx, double of
 // where a latent offset puts the arrival before the trace; the samples the
 // event affects are then [0, n1).
 struct Arrival {
-    int in;       // d < rc and the window meets the trace
+    int in;       // d < rc and the window starts before the end of the trace
     int n0, n1;   // n0 = ceil(a), n1 = min(n0 + ts, N): the window, [max(n0, 0), n1) in the trace
     double B;
 };
@@ -223,10 +223,10 @@ __device__ inline Arrival arrive(const Geo &g, double x, double y, double t, dou
     ar.n0 = 0;
     ar.n1 = 0;
     ar.B = 0.0;
-    // the window [ceil(a), ceil(a) + ts) must meet the trace [0, N): a latent
-    // offset can put an arrival before the first sample, and n0 is then
-    // negative (users clip the runs they touch at 0)
-    if (d < g.rc && c < (double)g.N && c + (double)g.ts > 0.0) {
+    // a latent offset can put an arrival before the first sample: n0 is then
+    // negative, and n1 <= 0 if the whole window precedes the trace (users of
+    // the window cut it at sample 0)
+    if (d < g.rc && c < (double)g.N) {
         ar.n0 = (int)c;
         ar.n1 = ar.n0 + g.ts < g.N ? ar.n0 + g.ts : g.N;
         // A^2 exp(-2 (c - a) / decay) with A = m exp(-d / atten), one exponential

@@ -478,7 +478,10 @@ __device__ inline RegionBox region_box(const Geo &g, double offx, double offy, i
 // lanes 0-31 evaluate the old event's arrival at candidate `lane`, lanes
 // 32-63 the new event's at candidate `lane - 32`, so the two arrival
 // computations run side by side.  A wave prefix sum then places each
-// candidate's one or two sample runs.
+// candidate's one or two sample runs.  CLIP (latent arrivals, which can
+// precede the trace): windows are cut at sample 0, and one that ends there
+// is absent.
+template <bool CLIP = false>
 __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, double ox, double oy, double ot,
                           double om, bool has_new, double nx, double ny, double nt, double nm,
                           Seg *segs, SegIndex *six, const double *lsx, int *nseg_out, int *S_out,
@@ -529,7 +532,11 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
         an.n0 = upper_half(ar.n0);
         an.n1 = upper_half(ar.n1);
         an.B = __hiloint2double(upper_half(__double2hiint(ar.B)), upper_half(__double2loint(ar.B)));
-        const Arrival ao = ar;
+        Arrival ao = ar;
+        if (CLIP) {
+            ao.in = ao.in && ao.n1 > 0;
+            an.in = an.in && an.n1 > 0;
+        }
         int ns = 0, nsamp = 0;
         Seg sa, sb;
         if (half == 0 && cidx < nbox && (ao.in || an.in)) {
@@ -541,7 +548,7 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
             sb = sa;
             // the runs start at the first sample of the trace at the
             // earliest (o0 and w0 keep the arrival's own first sample)
-            const int ob = max(ao.n0, 0), nb = max(an.n0, 0);
+            const int ob = CLIP ? max(ao.n0, 0) : ao.n0, nb = CLIP ? max(an.n0, 0) : an.n0;
             if (ao.in && an.in) {
                 if (max(ob, nb) <= min(ao.n1, an.n1)) {  // overlapping or touching
                     sa.lo = min(ob, nb);
@@ -830,8 +837,8 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
             oda = type != 0 ? s_da[io] : nullptr;
             nda = type != 1 ? lat->pda[buf][0] : nullptr;
         }
-        footprint(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
-                  &s_six[buf], lsx, &nseg, &S, &fl, oda, nda);
+        footprint<LAT>(g, lane, type != 0, ox, oy, ot, om, type != 1, nx, ny, nt, nm, s_seg[buf],
+                       &s_six[buf], lsx, &nseg, &S, &fl, oda, nda);
         if (__ballot(fl != 0) != 0ull || S > max_samples) {
             valid = 0;
             mflags |= kFlagSeg;
@@ -883,7 +890,7 @@ __device__ inline void scout_move(const Geo &g, int lane, int buf, int i, int kk
 // LAT: latent arrival times (line model): the events' offsets live in LDS
 // next to their coordinates, draws 8..15 come from the slot's draws2, and
 // the scout also builds arrival-time and joint moves.
-template <typename TraceT, int BLOCK, bool LAT>
+template <typename TraceT, int BLOCK, bool LAT, bool OWN = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LAT ? 2 : 1)))
 k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
               const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
@@ -926,8 +933,10 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     const int chain = 0;  // every array of the slot is slot-local
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
-    unsigned long long *const own = slots[slot].owner;
-    const unsigned long long tag = own != nullptr ? owner_tag(g, sweep, i, kk, r) : 0ull;
+    // debug owner check (OWN: a separate instantiation, so production
+    // kernels carry none of it)
+    unsigned long long *const own = OWN ? slots[slot].owner : nullptr;
+    const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
 
     const double offx = ev.off[2 * chain], offy = ev.off[2 * chain + 1];
     const RegionBox box = region_box(g, offx, offy, i, kk);
@@ -1345,7 +1354,7 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
 // LAT: latent arrival times (line model), as in the latency form: each
 // wave keeps its region's arrival offsets, its draws 8..15 and the joint
 // move's scratch in LDS (about 27 KB more per workgroup, two waves per SIMD).
-template <typename TraceT, bool NAIVE, bool LAT = false>
+template <typename TraceT, bool NAIVE, bool LAT = false, bool OWN = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : (LAT ? 2 : 4))))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
@@ -1396,8 +1405,8 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     const Learned &L = s_L[wv];
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
-    unsigned long long *const own = slots[slot].owner;
-    const unsigned long long tag = own != nullptr ? owner_tag(g, sweep, i, kk, r) : 0ull;
+    unsigned long long *const own = OWN ? slots[slot].owner : nullptr;  // debug owner check
+    const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
     __shared__ double s_rc[4][10];
     if (lane == 0) {
         double *c = s_rc[wv];
@@ -2239,7 +2248,8 @@ __global__ void k_set_sweep(long long *p, long long v) { *p = v; }
 __global__ void k_advance_sweep(long long *p) { *p += 1; }
 
 // ------------------------------------------------------------- launchers
-template <typename TraceT>
+// OWN: the debug owner check's instantiations (the naive schedule has none).
+template <typename TraceT, bool OWN>
 static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
                                  const long long *sweep_ptr, double *logp, long long log_first,
                                  long long log_n, int *err, int block, int naive_elems, int latent,
@@ -2248,11 +2258,11 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
     if (nitems <= 0) return hipSuccess;
     if (latent) {  // latent arrivals: the wave form (block 64) or the 256-thread latency form
         if (block == 64)
-            k_sweep_wave<TraceT, false, true><<<(nitems + 3) / 4, 256, 0, s>>>(
+            k_sweep_wave<TraceT, false, true, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
                 slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0);
         else
-            k_sweep_color<TraceT, 256, true><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr,
-                                                                    logp, log_first, log_n, err);
+            k_sweep_color<TraceT, 256, true, OWN><<<nitems, 256, 0, s>>>(
+                slots, items, par, sweep_ptr, logp, log_first, log_n, err);
         return hipGetLastError();
     }
     if (naive_elems > 0) {
@@ -2266,21 +2276,20 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
     }
     switch (block) {
     case 64:  // one wave per work item, four per workgroup
-        k_sweep_wave<TraceT, false><<<(nitems + 3) / 4, 256, 0, s>>>(slots, items, nitems, par,
-                                                                     sweep_ptr, logp, log_first,
-                                                                     log_n, err, 0);
+        k_sweep_wave<TraceT, false, false, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0);
         break;
     case 512:
-        k_sweep_color<TraceT, 512, false><<<nitems, 512, 0, s>>>(slots, items, par, sweep_ptr, logp,
-                                                          log_first, log_n, err);
+        k_sweep_color<TraceT, 512, false, OWN><<<nitems, 512, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
         break;
     case 128:
-        k_sweep_color<TraceT, 128, false><<<nitems, 128, 0, s>>>(slots, items, par, sweep_ptr, logp,
-                                                          log_first, log_n, err);
+        k_sweep_color<TraceT, 128, false, OWN><<<nitems, 128, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
         break;
     default:
-        k_sweep_color<TraceT, 256, false><<<nitems, 256, 0, s>>>(slots, items, par, sweep_ptr, logp,
-                                                          log_first, log_n, err);
+        k_sweep_color<TraceT, 256, false, OWN><<<nitems, 256, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
         break;
     }
     return hipGetLastError();
@@ -2289,13 +2298,21 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
                         long long log_n, int *err, int block, int naive_elems, int latent,
-                        hipStream_t s)
+                        int owner, hipStream_t s)
 {
     if (f64)
-        return launch_sweep_t<double>(slots, items, nitems, par, sweep_ptr, logp, log_first,
-                                      log_n, err, block, naive_elems, latent, s);
-    return launch_sweep_t<float>(slots, items, nitems, par, sweep_ptr, logp, log_first, log_n,
-                                 err, block, naive_elems, latent, s);
+        return owner ? launch_sweep_t<double, true>(slots, items, nitems, par, sweep_ptr, logp,
+                                                    log_first, log_n, err, block, naive_elems,
+                                                    latent, s)
+                     : launch_sweep_t<double, false>(slots, items, nitems, par, sweep_ptr, logp,
+                                                     log_first, log_n, err, block, naive_elems,
+                                                     latent, s);
+    return owner ? launch_sweep_t<float, true>(slots, items, nitems, par, sweep_ptr, logp,
+                                               log_first, log_n, err, block, naive_elems, latent,
+                                               s)
+                 : launch_sweep_t<float, false>(slots, items, nitems, par, sweep_ptr, logp,
+                                                log_first, log_n, err, block, naive_elems, latent,
+                                                s);
 }
 
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,

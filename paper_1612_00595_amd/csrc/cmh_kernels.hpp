@@ -8,7 +8,7 @@ namespace cmh {
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
                         long long log_n, int *err, int block, int naive_elems, int latent,
-                        hipStream_t s);
+                        int owner, hipStream_t s);
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
                                 int *err, hipStream_t s);
 hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
