@@ -379,6 +379,7 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         g->c6 = g->c5 + g->pa;
     }
     g->owner = s->debug & 1;
+    g->inv_ds = 1.0 / m->ds;
     return CMH_OK;
 }
 

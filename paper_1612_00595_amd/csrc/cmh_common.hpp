@@ -67,6 +67,8 @@ struct Geo {
     double pa, pj, sa;      // arrival and joint move probabilities, arrival step
     double c5, c6;          // cumulative thresholds after the magnitude, arrival moves
     int owner, pad_owner;   // 1: the debug owner check (Slot::owner)
+    double inv_ds;          // 1 / ds: candidate cells of a footprint (a cell off by one at
+                            // a cell edge still leaves every station within rc in the box)
 };
 
 // Learned birth proposal: a mixture over the anchors (station, window) of

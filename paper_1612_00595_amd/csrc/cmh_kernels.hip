@@ -487,13 +487,16 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
                           Seg *segs, SegIndex *six, const double *lsx, int *nseg_out, int *S_out,
                           int *flags, const double *oda = nullptr, const double *nda = nullptr)
 {
+    // candidate cells: the events' cells (by a product with 1 / ds: at a cell
+    // edge the cell may be off by one, and the one-cell margin still holds
+    // every station within rc < ds) widened by one cell
     int cx0 = 1 << 30, cx1 = -1, cy0 = 1 << 30, cy1 = -1;
     if (has_old) {
-        const int cx = (int)floor(ox / g.ds), cy = (int)floor(oy / g.ds);
+        const int cx = (int)floor(ox * g.inv_ds), cy = (int)floor(oy * g.inv_ds);
         cx0 = min(cx0, cx); cx1 = max(cx1, cx); cy0 = min(cy0, cy); cy1 = max(cy1, cy);
     }
     if (has_new) {
-        const int cx = (int)floor(nx / g.ds), cy = (int)floor(ny / g.ds);
+        const int cx = (int)floor(nx * g.inv_ds), cy = (int)floor(ny * g.inv_ds);
         cx0 = min(cx0, cx); cx1 = max(cx1, cx); cy0 = min(cy0, cy); cy1 = max(cy1, cy);
     }
     cx0 = max(cx0 - 1, 0); cy0 = max(cy0 - 1, 0);
@@ -503,6 +506,11 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
     }
     const int bw = cx1 - cx0 + 1;
     const int nbox = bw * (cy1 - cy0 + 1);
+    // row of a candidate: (cidx + 1/2) / bw lies at least 1 / (2 bw) from an
+    // integer, beyond the error of a float reciprocal for cidx < 2^16 and
+    // bw <= 2^12 (checked exhaustively); larger boxes divide
+    const float rbw = __builtin_amdgcn_rcpf((float)bw);
+    const bool small_box = nbox < (1 << 16) && bw <= (1 << 12);
     const int half = lane >> 5, hl = lane & 31;
     const bool mine = half == 0 ? has_old : has_new;
     const double ex = half ? nx : ox, ey = half ? ny : oy, et = half ? nt : ot,
@@ -514,8 +522,9 @@ __device__ __forceinline__ void footprint(const Geo &g, int lane, bool has_old, 
         ar.in = 0; ar.n0 = 0; ar.n1 = 0; ar.B = 0.0;
         int ix = 0, iy = 0;
         if (cidx < nbox) {
-            ix = cx0 + cidx % bw;
-            iy = cy0 + cidx / bw;
+            const int row = small_box ? (int)(((float)cidx + 0.5f) * rbw) : cidx / bw;
+            ix = cx0 + (cidx - row * bw);
+            iy = cy0 + row;
             // line stations from lsx (LDS): a Geo held in registers must not
             // be indexed dynamically, which would move it to scratch memory
             if (mine) {
