@@ -956,6 +956,12 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
 
     const long long base = ((long long)chain * g.R + r) * g.cap;
     const long long ebase = (long long)chain * g.nsta * (long long)g.N;
+    // E and the trace as global pointers: their loads are then counted apart
+    // from LDS operations
+    const __attribute__((address_space(1))) double *const gE =
+        (const __attribute__((address_space(1))) double *)(E + ebase);
+    const __attribute__((address_space(1))) TraceT *const gT =
+        (const __attribute__((address_space(1))) TraceT *)trace;
     const double *dsrc = draws + ((long long)chain * g.R + r) * (long long)g.k * 8;
     const double *lsrc =
         L.tab != nullptr ? L.birth + ((long long)chain * g.R + r) * (long long)g.k * 4 : nullptr;
@@ -1008,11 +1014,12 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     unsigned long long samp_read = 0, samp_written = 0;
     __syncthreads();
     const RegionLearned rl = s_rl;
-    if (wave == 0)
+    if (wave == 0) {
         scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[0][0], s_ex,
                         s_ey, s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
                         s_lb[0][0], s_lsta, rl, LAT ? s_draw2[0][0] : nullptr, s_da, s_lat, own,
                         tag);
+    }
     __syncthreads();
 
     for (int j = 0; j < g.k; ++j) {
@@ -1043,13 +1050,14 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         for (int q = 0; q < QP; ++q) { gidx[q] = -1; enew[q] = 0.0; }
         double prod = 1.0, lin = 0.0;
         if (wave == 0) {
-            if (j + 1 < g.k)  // speculative: the state as if move j is rejected
+            if (j + 1 < g.k) {  // speculative: the state as if move j is rejected
                 scout_move<LAT>(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
                                 s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey, s_et, s_em,
                                 s_seg, s_six, s_lsx, s_hdr, s_prop, kMaxFootprint, L,
                                 s_lb[((j + 1) >> 6) & 1][(j + 1) & 63], s_lsta, rl,
                                 LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr, s_da,
                                 s_lat, own, tag);
+            }
         } else if (evaluate) {
             const int et = tid - 64;
             const Seg *sg = s_seg[buf];
@@ -1061,21 +1069,26 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                 // every sample's variance and trace value in flight at once;
                 // slots past the footprint are skipped by a block-uniform
                 // test, idle lanes of a used slot read element 0
+                // (raw trace elements, converted only after every load is
+                // issued, through global pointers, so that no load waits for
+                // another and LDS reads do not wait for the loads)
                 double eo[QP], sv[QP], dc[QP];
+                TraceT tv[QP];
 #pragma unroll
                 for (int q = 0; q < QP; ++q) {
                     eo[q] = 0.0;
-                    sv[q] = 0.0;
+                    tv[q] = (TraceT)0;
                     if ((p * QP + q) * EV < h.S) {
                         const int g0 = gi[q] >= 0 ? gi[q] : 0;
-                        eo[q] = E[ebase + g0];  // the residual, under templates
-                        if (!g.tmpl) sv[q] = (double)trace[g0];
+                        eo[q] = gE[g0];  // the residual, under templates
+                        if (!g.tmpl) tv[q] = gT[g0];
                     }
                 }
                 // variance changes from the LDS tables while the loads fly
 #pragma unroll
                 for (int q = 0; q < QP; ++q) {
                     dc[q] = 0.0;
+                    sv[q] = (double)tv[q];
                     if ((p * QP + q) * EV < h.S && gi[q] >= 0) {
                         const Seg &a = sg[run[q]];
                         dc[q] = run_dvar(a, s_T, gi[q] - a.j * g.N);
@@ -1230,7 +1243,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             }
             if (j + 1 < g.k) {
                 if (rebuild) {
-                    if (wave == 0)
+                    if (wave == 0) {
                         scout_move<LAT>(g, lane, buf ^ 1, i, kk, offx, offy, x0, x1, y0, y1, n,
                                         s_draw[((j + 1) >> 6) & 1][(j + 1) & 63], s_ex, s_ey,
                                         s_et, s_em, s_seg, s_six, s_lsx, s_hdr, s_prop,
@@ -1238,6 +1251,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                                         s_lsta, rl,
                                         LAT ? s_draw2[((j + 1) >> 6) & 1][(j + 1) & 63] : nullptr,
                                         s_da, s_lat, own, tag);
+                    }
                     __syncthreads();
                 } else if (h.type <= 1) {
                     if (tid == 0) {
@@ -1289,7 +1303,8 @@ constexpr int kWaveDraws = 16;  // moves whose draws are staged at once
 
 // This lane's share of the log-likelihood change of a move: passes of
 // 64 kWaveQ footprint samples, every load of a pass in flight at once.
-template <typename TraceT>
+// EG: E is in global memory (not the naive schedule's private copy in LDS).
+template <typename TraceT, bool EG>
 __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace,
                                   const double *__restrict__ E, const Seg *sg,
                                   const SegIndex &six, int nseg, int S, const double *sT, int lane)
@@ -1298,20 +1313,29 @@ __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace
     for (int base = 0; base < S; base += 64 * kWaveQ) {
         int run[kWaveQ], gidx[kWaveQ];
         locate_runs<kWaveQ>(six, nseg, S, base + lane, 64, run, gidx);
+        // raw trace elements, converted once every load is issued; the trace
+        // (always) and E (unless it is the naive schedule's LDS copy) through
+        // global pointers, whose loads are counted apart from LDS operations
+        const __attribute__((address_space(1))) TraceT *gT =
+            (const __attribute__((address_space(1))) TraceT *)trace;
+        // every load is issued, positions past the footprint reading element
+        // 0 (their terms are dropped below): loads under a branch would each
+        // be waited for at the join
         double eo[kWaveQ], sv[kWaveQ], dc[kWaveQ];
+        TraceT tv[kWaveQ];
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
-            eo[q] = 0.0;
-            sv[q] = 0.0;
-            if (base + 64 * q < S) {
-                const int gi = gidx[q] >= 0 ? gidx[q] : 0;
-                eo[q] = E[gi];  // the residual, under templates
-                if (!g.tmpl) sv[q] = (double)trace[gi];
-            }
+            const int gi = gidx[q] >= 0 ? gidx[q] : 0;
+            if constexpr (EG)  // the residual, under templates
+                eo[q] = ((const __attribute__((address_space(1))) double *)E)[gi];
+            else
+                eo[q] = E[gi];
+            tv[q] = gT[g.tmpl ? 0 : gi];
         }
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
             dc[q] = 0.0;
+            sv[q] = (double)tv[q];
             if (base + 64 * q < S && gidx[q] >= 0) {
                 const Seg &a = sg[run[q]];
                 dc[q] = run_dvar(a, sT, gidx[q] - a.j * g.N);
@@ -1527,7 +1551,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         const bool evaluate = h.valid && !g.prior_only;
         double delta = 0.0;
         if (evaluate)
-            delta = wave_sum(wave_delta_part<TraceT>(g, trace, Ew, s_seg[wv][0], s_six[wv][0],
+            delta = wave_sum(wave_delta_part<TraceT, !NAIVE>(g, trace, Ew, s_seg[wv][0], s_six[wv][0],
                                                      h.nseg, h.S, sT, lane));
         double la;
         if (h.type == 0)
