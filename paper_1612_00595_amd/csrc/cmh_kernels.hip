@@ -1356,6 +1356,9 @@ __device__ double wave_delta_part(const Geo &g, const TraceT *__restrict__ trace
 // After an acceptance: the new variance over the footprint, written in place.
 // The new variance max(E + change, 0) is the one sample_term used for Delta
 // (the new residual E - change under templates).
+// EG: E is in global memory (not the naive schedule's private copy in LDS);
+// its loads are then issued together through a global pointer.
+template <bool EG>
 __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
                            const SegIndex &six, int nseg, int S, const double *sT, int lane)
 {
@@ -1365,8 +1368,11 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
         double eo[kWaveQ];
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q) {
-            eo[q] = 0.0;
-            if (base + 64 * q < S) eo[q] = E[gidx[q] >= 0 ? gidx[q] : 0];
+            const int gi = gidx[q] >= 0 ? gidx[q] : 0;
+            if constexpr (EG)
+                eo[q] = ((const __attribute__((address_space(1))) double *)E)[gi];
+            else
+                eo[q] = E[gi];
         }
 #pragma unroll
         for (int q = 0; q < kWaveQ; ++q)
@@ -1492,7 +1498,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                       s_seg[wv][0], &s_six[wv][0], g.sx, &nseg, &S, &fl);
             __builtin_amdgcn_wave_barrier();
             if (__ballot(fl != 0) != 0ull) flags |= kFlagSeg;
-            else wave_write(g, pe, s_seg[wv][0], s_six[wv][0], nseg, S, sT, lane);
+            else wave_write<false>(g, pe, s_seg[wv][0], s_six[wv][0], nseg, S, sT, lane);
             __builtin_amdgcn_wave_barrier();
         }
         Ew = pe;
@@ -1586,7 +1592,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         if (accept) {
             if (!g.prior_only)
-                wave_write(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
+                wave_write<!NAIVE>(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
             if (lane == 0) {
                 cnt[stat_base(h.type) + 2]++;
                 cnt[16] += (unsigned long long)h.S;
