@@ -2091,31 +2091,33 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
     double *Erow = E + (long long)chain * g.nsta * (long long)g.N + row;
     double acc = 0.0;
     // kRefreshU samples per thread per step, every trace load in flight
-    // before any is used
+    // before any is used: raw elements, loaded unconditionally (past the
+    // tile's end from its first sample) and converted only when used
     constexpr int U = kRefreshU;
     for (int base = n_lo + tid; base < n_hi; base += 256 * U) {
-        double sv[U];
+        TraceT tv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int nn = base + 256 * u;
-            sv[u] = nn < n_hi ? (double)trace[row + nn] : 0.0;
+            tv[u] = trace[row + (nn < n_hi ? nn : n_lo)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int nn = base + 256 * u;
             if (nn >= n_hi) break;
+            const double svu = (double)tv[u];
             double e = 0.0;
             for (int q = 0; q < ne; ++q) {
                 const int d = nn - s_n0[q];
                 if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
             }
             if (g.tmpl) {  // e is the mean; E holds the residual
-                const double rr = sv[u] - e;
+                const double rr = svu - e;
                 acc += null_c + null_q * (rr * rr);
                 if (write) Erow[nn] = rr;
                 continue;
             }
-            const double qv = sv[u] * sv[u];
+            const double qv = svu * svu;
             if (e > 0.0) {
                 const double v = g.sigma2 + e;
                 acc += -0.5 * (l2pi + log(v) + qv / v);
