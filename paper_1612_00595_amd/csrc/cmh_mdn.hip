@@ -429,15 +429,32 @@ k_anchor_feat(Geo g, const TraceT *__restrict__ trace, int ntau, long first,
     const int cx = c % g.nsx, cy = c / g.nsx;
     const long tau = (long)kMdnTScale * ti;
     const double ls2 = log(g.sigma2);
-    for (int e = lane; e < kMdnIn; e += 64) {
+    // the lane's kMdnIn / 64 features: every raw trace element loaded first
+    // (stations off the grid read the anchor's own first element, unused),
+    // then the features in the same summation order
+    constexpr int K = kMdnIn / 64;
+    static_assert(K * 64 == kMdnIn, "features split evenly over the lanes");
+    TraceT raw[K][4];
+    bool on[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = lane + 64 * k;
         const int b = e / kMdnWin, n = e % kMdnWin;
         const int ix = cx + b % 3 - 1, iy = cy + b / 3 - 1;
+        on[k] = ix >= 0 && ix < g.nsx && iy >= 0 && iy < g.nsy;
+        const TraceT *row = trace + (on[k] ? ((long)iy * g.nsx + ix) * g.N + tau + n
+                                           : ((long)cy * g.nsx + cx) * g.N + tau);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) raw[k][u] = row[u];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = lane + 64 * k;
         double f = 0.0;
-        if (ix >= 0 && ix < g.nsx && iy >= 0 && iy < g.nsy) {
-            const TraceT *row = trace + ((long)iy * g.nsx + ix) * g.N + tau + n;
+        if (on[k]) {
             double acc = 0.0;
             for (int u = 0; u < 4; ++u) {
-                const double v = (double)row[u];
+                const double v = (double)raw[k][u];
                 acc += v * v;
             }
             f = log(g.sigma2 + acc * 0.25) - ls2;
