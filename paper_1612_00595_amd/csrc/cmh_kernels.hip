@@ -962,6 +962,8 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         (const __attribute__((address_space(1))) double *)(E + ebase);
     const __attribute__((address_space(1))) TraceT *const gT =
         (const __attribute__((address_space(1))) TraceT *)trace;
+    __attribute__((address_space(1))) double *const gEw =
+        (__attribute__((address_space(1))) double *)(E + ebase);
     const double *dsrc = draws + ((long long)chain * g.R + r) * (long long)g.k * 8;
     const double *lsrc =
         L.tab != nullptr ? L.birth + ((long long)chain * g.R + r) * (long long)g.k * 4 : nullptr;
@@ -1153,7 +1155,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
             if (wave > 0 && !g.prior_only) {
 #pragma unroll
                 for (int q = 0; q < QP; ++q)
-                    if (gidx[q] >= 0) E[ebase + gidx[q]] = enew[q];
+                    if (gidx[q] >= 0) gEw[gidx[q]] = enew[q];
                 // later passes (footprints over QP * EV samples) recompute the
                 // same new variance from the unchanged old one
                 for (int p = 1; p * QP * EV < h.S; ++p) {
@@ -1163,14 +1165,14 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                     double eo[QP];
 #pragma unroll
                     for (int q = 0; q < QP; ++q)
-                        eo[q] = gi[q] >= 0 ? E[ebase + gi[q]] : 0.0;
+                        eo[q] = gE[gi[q] >= 0 ? gi[q] : 0];
 #pragma unroll
                     for (int q = 0; q < QP; ++q) {
                         if (gi[q] >= 0) {
                             const Seg &a = s_seg[buf][run[q]];
                             const double dv = run_dvar(a, s_T, gi[q] - a.j * g.N);
                             const double en = g.tmpl ? eo[q] - dv : eo[q] + dv;
-                            E[ebase + gi[q]] = g.tmpl || en > 0.0 ? en : 0.0;
+                            gEw[gi[q]] = g.tmpl || en > 0.0 ? en : 0.0;
                         }
                     }
                 }
@@ -1380,7 +1382,11 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
                 const Seg &a = sg[run[q]];
                 const double dv = run_dvar(a, sT, gidx[q] - a.j * g.N);
                 const double en = g.tmpl ? eo[q] - dv : eo[q] + dv;
-                E[gidx[q]] = g.tmpl || en > 0.0 ? en : 0.0;
+                const double v = g.tmpl || en > 0.0 ? en : 0.0;
+                if constexpr (EG)
+                    ((__attribute__((address_space(1))) double *)E)[gidx[q]] = v;
+                else
+                    E[gidx[q]] = v;
             }
     }
 }
