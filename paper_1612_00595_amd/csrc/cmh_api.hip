@@ -697,7 +697,27 @@ int32_t build_graphs(cmh_state *st)
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int, int, int, int, int, int>, int> g_tune_cache;
+std::map<std::string, int> g_tune_cache;
+
+// Tuning-cache key: every constant of the problem that changes the kernel
+// form or the work per move (sizes, partition, move mix, likelihood form,
+// footprint geometry, prior occupancy, latent arrivals, learned births), not
+// the seed.
+std::string tune_key(const cmh::Geo &g, int chains, int f64, bool learned)
+{
+    std::string k;
+    auto put = [&k](const void *p, size_t n) { k.append((const char *)p, n); };
+    const int iv[] = {g.nsx, g.nsy, g.N, g.ts, g.gx, g.gy, g.period, g.dynamic, g.k, g.cap,
+                      g.prior_only, g.line, g.tmpl, g.naive, g.latent, g.owner, chains, f64,
+                      learned ? 1 : 0};
+    const double dv[] = {g.ds, g.sigma2, g.atten, g.vel, g.decay, g.rc, g.lambda, g.mmin,
+                         g.mrate, g.pb, g.pd, g.ploc, g.pt, g.pm, g.sxy, g.st, g.sm,
+                         g.arr_sd, g.pa, g.pj, g.sa, g.Lx, g.Ly};
+    put(iv, sizeof iv);
+    put(dv, sizeof dv);
+    if (g.line) put(g.sx, sizeof g.sx);
+    return k;
+}
 
 }  // namespace
 
@@ -918,6 +938,65 @@ int32_t ckpt_copy(const cmh::Slot &sl, int cur, char *rec, bool to_host)
     }
     return CMH_OK;
 }
+
+// Checks one slot's record (the part after its CkptSlot header) against what
+// a state of this shape can hold, on the host, before anything reaches the
+// device: counts in [0, cap]; offsets in [0, w) per axis when the offset is
+// redrawn (0 otherwise); every live event inside the model's support, binned
+// to its region under the saved offsets, ids strictly increasing within a
+// region, arrival offsets within the jitter bound; the per-sample array
+// finite (and non-negative when it is a variance).  Returns the reason for
+// a refusal, or nullptr.
+const char *ckpt_validate(const Geo &g, const char *rec)
+{
+    const size_t n = (size_t)g.R * g.cap;
+    std::vector<double> x(n), y(n), t(n), m(n), da(g.latent ? n * 8 : 0);
+    std::vector<unsigned long long> id(n);
+    std::vector<int> cnt(g.R);
+    double off[2];
+    const char *p = rec;
+    auto take = [&p](void *dst, size_t bytes) {
+        if (bytes) std::memcpy(dst, p, bytes);
+        p += bytes;
+    };
+    take(x.data(), n * 8);
+    take(y.data(), n * 8);
+    take(t.data(), n * 8);
+    take(m.data(), n * 8);
+    take(id.data(), n * 8);
+    take(cnt.data(), (size_t)g.R * 4);
+    take(off, 16);
+    take(da.data(), da.size() * 8);
+    for (int a = 0; a < 2; ++a) {
+        const double w = a == 0 ? g.wx : g.wy;
+        const bool ok = (g.dynamic && w > 0.0) ? (off[a] >= 0.0 && off[a] < w) : off[a] == 0.0;
+        if (!ok) return "partition offset outside [0, region width)";
+    }
+    for (int r = 0; r < g.R; ++r) {
+        if (cnt[r] < 0 || cnt[r] > g.cap) return "region event count outside [0, capacity]";
+        for (int s = 0; s < cnt[r]; ++s) {
+            const size_t a = (size_t)r * g.cap + s;
+            if (!(x[a] >= 0.0 && x[a] < g.Lx && y[a] >= 0.0 && y[a] < g.Ly && t[a] >= 0.0 &&
+                  t[a] < (double)g.N && m[a] >= g.mmin && std::isfinite(m[a])))
+                return "event outside the model's support";
+            if (cmh::event_region(g, off[0], off[1], x[a], y[a], t[a]) != r)
+                return "event stored in a region that does not hold it";
+            if (s > 0 && !(id[a - 1] < id[a])) return "event ids not increasing within a region";
+            if (g.latent)
+                for (int c = 0; c < g.nsx; ++c)
+                    if (!(std::fabs(da[a * 8 + c]) <= g.arr_e))
+                        return "arrival offset beyond the jitter bound";
+        }
+    }
+    const size_t ns = (size_t)g.nsta * g.N;
+    for (size_t i = 0; i < ns; ++i) {
+        double e;
+        std::memcpy(&e, p + i * 8, 8);
+        if (!std::isfinite(e) || (!g.tmpl && e < 0.0))
+            return g.tmpl ? "residual not finite" : "event variance negative or not finite";
+    }
+    return nullptr;
+}
 }  // namespace
 
 int32_t cmh_checkpoint_bytes(cmh_state *st, size_t *bytes)
@@ -975,6 +1054,8 @@ int32_t cmh_load(cmh_state *st, const void *host_buf, size_t bytes)
         if (cs.nsta != sl.g.nsta || cs.N != sl.g.N || cs.R != sl.g.R || cs.cap != sl.g.cap ||
             cs.latent != sl.g.latent)
             return fail(CMH_EINVAL, "checkpoint of a state with a different shape");
+        if (const char *why = ckpt_validate(sl.g, q + sizeof cs))
+            return fail(CMH_EINVAL, std::string("corrupt checkpoint: ") + why);
         q += ckpt_slot_bytes(sl.g);
     }
     rc = sync_and_check(st);
@@ -1196,8 +1277,7 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
         st->block = 64;
         return CMH_OK;
     }
-    const auto key = std::make_tuple(g.nsx, g.nsy, g.N, g.gx, g.gy, g.k, g.cap, st->chains,
-                                     st->f64, g.dynamic, g.line * 2 + g.tmpl);
+    const std::string key = tune_key(g, st->chains, st->f64, st->learned.tab != nullptr);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);

@@ -105,3 +105,80 @@ def test_checkpoint_of_another_shape_is_refused():
         a.load(bad)
     with pytest.raises(chromh.CmhError):
         a.load(ck[:100])
+
+
+def _slot_fields(w, latent=False):
+    """Byte offsets of one slot's fields inside a checkpoint of a
+    single-instance state (header of 24 bytes, then per slot a 24-byte shape
+    record, x, y, t, m, id, counts, offsets, [arrival offsets], variance,
+    counters)."""
+    R, cap = w.sampler.nreg, w.sampler.cap
+    n = R * cap
+    o = {"x": 24, "y": 24 + 8 * n, "t": 24 + 16 * n, "m": 24 + 24 * n, "id": 24 + 32 * n,
+         "cnt": 24 + 40 * n}
+    o["off"] = o["cnt"] + 4 * R
+    o["E"] = o["off"] + 16 + (64 * n if latent else 0)
+    o["stats"] = o["E"] + 8 * w.model.nsta * w.model.N
+    o["end"] = o["stats"] + 8 * 23
+    return o, R, cap
+
+
+def test_corrupt_checkpoint_is_refused_before_any_write():
+    """A record whose counts, events, offsets or variance no state of this
+    shape can hold is refused on the host (CMH_EINVAL) and the state keeps
+    what it had; nothing corrupt ever reaches a sweep."""
+    from paper_1612_00595_amd import chromh
+    w = dynamic_small()
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    a = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=8)
+    a.run_sweeps(0, 4)
+    ck = a.save()
+    before = a.read_events(0)
+    stats_before = a.read_counters(0)
+    o, R, cap = _slot_fields(w)
+    base = 24                                     # the state header
+    assert ck.nbytes == base + o["end"]
+    f = lambda name: base + o[name]               # noqa: E731
+    cnt = ck[f("cnt"):f("cnt") + 4 * R].view(np.int32)
+    r_full = int(np.argmax(cnt))
+    assert cnt[r_full] > 0
+    say("corrupt checkpoints: region", r_full, "holds", int(cnt[r_full]))
+
+    def refused(mutate, why):
+        bad = ck.copy()
+        mutate(bad)
+        with pytest.raises(chromh.CmhError) as e:
+            a.load(bad)
+        assert why in str(e.value), str(e.value)
+
+    def set_i32(buf, off, v):
+        buf[off:off + 4] = np.frombuffer(np.int32(v).tobytes(), np.uint8)
+
+    def set_f64(buf, off, v):
+        buf[off:off + 8] = np.frombuffer(np.float64(v).tobytes(), np.uint8)
+
+    refused(lambda b: set_i32(b, f("cnt") + 4 * r_full, cap + 1), "count")
+    refused(lambda b: set_i32(b, f("cnt") + 4 * r_full, -1), "count")
+    slot0 = r_full * cap
+    refused(lambda b: set_f64(b, f("x") + 8 * slot0, -0.5), "support")
+    refused(lambda b: set_f64(b, f("t") + 8 * slot0, float(w.model.N)), "support")
+    refused(lambda b: set_f64(b, f("m") + 8 * slot0, np.nan), "support")
+    # an event moved to the far corner stays in the domain but not in its region
+    x0 = float(ck[f("x") + 8 * slot0:f("x") + 8 * slot0 + 8].view(np.float64)[0])
+    far = w.model.Lx - 1e-9 if x0 < w.model.Lx / 2 else 1e-9
+    refused(lambda b: set_f64(b, f("x") + 8 * slot0, far), "region")
+    refused(lambda b: set_f64(b, f("off"), 0.25), "offset")
+    refused(lambda b: set_f64(b, f("off") + 8, -0.01), "offset")
+    refused(lambda b: set_f64(b, f("E") + 8 * 17, np.inf), "variance")
+    refused(lambda b: set_f64(b, f("E") + 8 * 17, -1.0), "variance")
+    if cnt[r_full] > 1:
+        def dup_id(b):
+            b[f("id") + 8 * (slot0 + 1):f("id") + 8 * (slot0 + 2)] = \
+                b[f("id") + 8 * slot0:f("id") + 8 * (slot0 + 1)]
+        refused(dup_id, "ids")
+    compare_events(a.read_events(0), before, "after refused loads")
+    assert np.array_equal(a.read_counters(0), stats_before)
+    a.load(ck)                                    # the intact record still loads
+    a.run_sweeps(4, 2)
+    torch.cuda.synchronize()
