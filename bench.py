@@ -33,11 +33,13 @@ TIME_THRESH_1D = 12.0   # Section 5's matching threshold in time, the paper's ow
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--burn-in", type=int, default=-1,
+                    help="sweeps before the warm-up; -1: as many as make the timed sweeps the "
+                         "last of the workload's stated run (500 sweeps for the main line)")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--block", type=int, default=0, help="sweep workgroup size, 0 = autotune")
-    ap.add_argument("--profile-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-parallel", action="store_true",
@@ -95,36 +97,31 @@ def host_cpu():
     return n, model
 
 
-def cpu_baseline(w, warmup: int, budget_s: float, threads: int = 1):
-    """The oracle as it stands on the same workload: its own synthetic trace of
-    the same shape (seeded normals scaled by the model variance), sweeps
-    0 .. warmup-1 untimed, then sweeps until budget_s.  threads > 1 runs the
-    regions of each colour phase across that many host threads (the paper's
-    own CPU parallelism; the chain is the same)."""
+def cpu_baseline(w, state, budget_s: float, threads: int = 1):
+    """The oracle as it stands on the same instance and the same chain: the
+    GPU's trace and its events after the timed sweeps (state = (trace,
+    events, next sweep)), the same seed, then sweeps until budget_s.
+    threads > 1 runs the regions of each colour phase across that many host
+    threads (the paper's own CPU parallelism; the chain is the same)."""
     import numpy as np
 
     import oracle as O
-    from paper_1612_00595_amd import workloads as W
 
+    trace, events, first = state
     m = O.make_model(**w.model.asdict())
     sp = O.make_sampler(**w.sampler.asdict())
-    tr = W.truth_events(w.model, w.seed)
-    truth = O.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
-    rng = np.random.Generator(np.random.PCG64(10_000 + w.seed))
-    z = rng.standard_normal((w.model.nsta, w.model.N), dtype=np.float32)
-    s = O.trace_from_noise_f32(m, truth, z)
-    del z
-    ch = O.Chain(m, sp, s, seed=w.seed)
+    ch = O.Chain(m, sp, trace, seed=w.seed)
+    ev = O.as_events(events["x"], events["y"], events["t"], events["m"], events["id"])
+    assert ch.set_events(ev) == 0
     ch.set_threads(threads)
-    for sw in range(warmup):
-        ch.sweep(sw)
     R, k = w.sampler.nreg, w.sampler.k
     logbuf = np.full((R, k, 4), -1.0)
-    moves, sweeps, t0 = 0, 0, time.perf_counter()
+    moves, evaluated, sweeps, t0 = 0, 0, 0, time.perf_counter()
     while True:
         logbuf[...] = -1.0
-        ch.sweep(warmup + sweeps, log=logbuf)
+        assert ch.sweep(first + sweeps, log=logbuf) == 0
         moves += int(np.sum(logbuf[..., 1] >= 0))
+        evaluated += int(np.sum(logbuf[..., 1] >= 1))
         sweeps += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
@@ -133,9 +130,10 @@ def cpu_baseline(w, warmup: int, budget_s: float, threads: int = 1):
         f"{threads} threads over the regions of each colour phase"
     return dict(value=moves / el, unit="proposals/s", cores=threads,
                 kind="oracle" if threads == 1 else "oracle-threads",
-                sample=f"{w.name}: oracle sweeps {warmup}..{warmup + sweeps - 1} "
-                       f"({sweeps} sweeps, {moves} proposals, {el:.1f} s) on its own "
-                       f"instance of the same shape, {how}")
+                evaluated_per_s=evaluated / el,
+                sample=f"{w.name}: oracle sweeps {first}..{first + sweeps - 1} ({sweeps} sweeps, "
+                       f"{moves} proposals, {el:.1f} s) continuing the GPU chain from its state "
+                       f"after the timed sweeps ({len(events)} events) on the same trace, {how}")
 
 
 # network FLOPs per row: forward 2 (576*256 + 2*256*256 + 256*64) multiply-adds
@@ -388,6 +386,14 @@ def paper_world_study(args, dev, latent: bool = False):
     return out
 
 
+UNEVEN_SWEEPS = 200   # the uneven batch's run: timed sweeps end here
+
+
+def uneven_burn_in(args) -> int:
+    return args.burn_in if args.burn_in >= 0 else \
+        max(0, UNEVEN_SWEEPS - args.warmup - args.uneven_steps)
+
+
 def uneven_study(args, dev, block: int):
     """Many independent instances of uneven size in one batch (every colour
     phase one launch over all instances' regions of that colour): proposals/s
@@ -406,11 +412,12 @@ def uneven_study(args, dev, block: int):
         samplers.append(w.sampler)
         seeds.append(w.seed)
     b = chromh.Batch(models, samplers, traces, seeds, block=block)
-    b.run_sweeps(0, args.warmup)
+    bu = uneven_burn_in(args)
+    b.run_sweeps(0, bu + args.warmup)
     torch.cuda.synchronize()
     c0 = [b.read_counters(q) for q in range(len(ws))]
     t0 = time.perf_counter()
-    b.run_sweeps(args.warmup, args.uneven_steps)
+    b.run_sweeps(bu + args.warmup, args.uneven_steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     c1 = [b.read_counters(q) for q in range(len(ws))]
@@ -424,6 +431,7 @@ def uneven_study(args, dev, block: int):
            "poisson_mean_events": float(sum(m.lam for m in models)),
            "value": proposals / el, "unit": "proposals/s",
            "ms_per_step": el * 1e3 / args.uneven_steps,
+           "burn_in_sweeps": bu,
            "algorithmic_GBps_whole_sweep": nbytes / el / 1e9,
            "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block,
            "births_attempted_valid_accepted": [int(v) for v in d[:15].reshape(5, 3)[0]]}
@@ -462,11 +470,12 @@ def uneven_learned_study(args, dev, block: int, net):
         b.set_learned_instance(q, T, wt, ntau, 0.5)
     torch.cuda.synchronize()
     t_tables = time.perf_counter() - t0
-    b.run_sweeps(0, args.warmup)
+    bu = uneven_burn_in(args)
+    b.run_sweeps(0, bu + args.warmup)
     torch.cuda.synchronize()
     c0 = [b.read_counters(q) for q in range(len(ws))]
     t0 = time.perf_counter()
-    b.run_sweeps(args.warmup, args.uneven_steps)
+    b.run_sweeps(bu + args.warmup, args.uneven_steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     c1 = [b.read_counters(q) for q in range(len(ws))]
@@ -554,36 +563,65 @@ def kernel_rates(dev):
     return out
 
 
-def measure(smp, w, warmup: int, steps: int, profile_sweeps: int, stream):
-    """Proposals/s over `steps` graph-replayed sweeps after `warmup`, and the
-    sweep kernel's HIP-event-timed launch duration and algorithmic bytes."""
+def burn_in_for(w, warmup: int, steps: int) -> int:
+    """Sweeps run before the warm-up so that the timed sweeps are the last of
+    the workload's stated run length (the chain starts from the empty world;
+    its event count only reaches the posterior's level after a few hundred
+    sweeps)."""
+    return max(0, w.sweeps - warmup - steps)
+
+
+def measure(smp, w, warmup: int, steps: int, burn_in: int = 0, tune: bool = False):
+    """Proposals/s over `steps` graph-replayed sweeps that follow `burn_in`
+    + `warmup` untimed ones, and from those same sweeps the sweep kernel's
+    launch spans (device steady-clock stamps taken by the kernel's own
+    workgroups inside the replayed graphs) and the algorithmic bytes they
+    moved (the kernels' own counts of footprint samples read and
+    rewritten).  tune: choose the kernel form after the burn-in, on the
+    state the timed sweeps start from."""
+    import numpy as np
     import torch
-    smp.run_sweeps(0, warmup)
+
+    from paper_1612_00595_amd import chromh
+    if burn_in:
+        smp.run_sweeps(0, burn_in)
+    if tune:
+        smp.autotune(burn_in, 3)
+    first = burn_in + warmup
+    stamps = smp.set_stamps(first, steps)  # before the sweep graphs are built
+    smp.run_sweeps(burn_in, warmup)
     torch.cuda.synchronize()
     c0 = sum(smp.read_counters(c) for c in range(w.chains))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    smp.run_sweeps(warmup, steps)
+    smp.run_sweeps(first, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     c1 = sum(smp.read_counters(c) for c in range(w.chains))
+    spans = chromh.ChromaticSampler.stamp_seconds(stamps)
+    smp.set_stamps(0, 0)
     el = t1 - t0
-    proposals = int((c1 - c0)[:15].reshape(5, 3)[:, 0].sum())
-    first = warmup + steps
-    ms = smp.time_phases(first, profile_sweeps, stream)
-    c3 = sum(smp.read_counters(c) for c in range(w.chains))
-    launches = profile_sweeps * smp.ncolors
-    avg_ms = float(ms[:smp.ncolors].sum()) / launches
+    d = c1 - c0
+    tab = d[:15].reshape(5, 3)
+    if w.model.arr_sd > 0:
+        tab = np.concatenate([tab, d[17:23].reshape(2, 3)])
+    proposals, evaluated, accepted = (int(v) for v in tab.sum(0))
+    # colours without regions launch nothing: their stamps stay (max, 0)
+    live = spans > 0
+    kernel_s = float(spans[live].sum())
     # the variance model reads the trace and E per footprint sample; the
     # mean-template model reads only its residual
     tb = 0 if w.model.tmpl else (4 if w.trace_dtype == "f32" else 8)
-    samp_read = int(c3[15] - c1[15])
-    samp_written = int(c3[16] - c1[16])
-    bytes_per_launch = (samp_read * (tb + 8) + samp_written * 8) / launches
-    return dict(elapsed=el, proposals=proposals, value=proposals / el, avg_ms=avg_ms,
-                bytes_per_launch=bytes_per_launch,
-                achieved=bytes_per_launch / (avg_ms * 1e-3) / 1e9,
-                start_ms=float(ms[smp.ncolors]) / profile_sweeps)
+    nbytes = int(d[15]) * (tb + 8) + int(d[16]) * 8
+    launches = int(live.sum())
+    return dict(elapsed=el, proposals=proposals, evaluated=evaluated, accepted=accepted,
+                value=proposals / el, first=first, launches=launches,
+                avg_launch_s=kernel_s / max(launches, 1), kernel_s=kernel_s,
+                bytes_per_launch=nbytes / max(launches, 1),
+                achieved=nbytes / kernel_s / 1e9 if kernel_s > 0 else 0.0,
+                span_ms_per_sweep=spans.clip(min=0).sum(1).round(4).tolist(),
+                acceptance=(tab[:, 2] / np.maximum(tab[:, 0], 1)).round(4).tolist(),
+                events_after=[len(smp.read_events(c)) for c in range(min(w.chains, 4))])
 
 
 def main():
@@ -616,25 +654,31 @@ def main():
     trace = chromh.simulate(w.model, truth, 1000 + w.seed, w.trace_dtype, dev)
     smp = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=w.chains, seed=w.seed,
                                   block=args.block)
-    if args.block == 0:
-        smp.autotune(0, 3)
-    log(f"[bench] sweep workgroup size {smp.block}, {smp.ncolors} colours")
-
-    res = measure(smp, w, args.warmup, args.steps, args.profile_sweeps, stream)
+    burn = args.burn_in if args.burn_in >= 0 else burn_in_for(w, args.warmup, args.steps)
+    res = measure(smp, w, args.warmup, args.steps, burn, tune=args.block == 0)
     el, value = res["elapsed"], res["value"]
-    avg_ms, bytes_per_launch, achieved = res["avg_ms"], res["bytes_per_launch"], res["achieved"]
-    log(f"[bench] {args.steps} sweeps in {el * 1e3:.1f} ms: {value:.4g} proposals/s")
+    avg_s, bytes_per_launch, achieved = res["avg_launch_s"], res["bytes_per_launch"], res["achieved"]
+    log(f"[bench] sweep kernel form {smp.block}, {smp.ncolors} colours; sweeps "
+        f"{res['first']}..{res['first'] + args.steps - 1} timed after {burn} of burn-in")
+    log(f"[bench] {args.steps} sweeps in {el * 1e3:.1f} ms: {value:.4g} proposals/s "
+        f"({res['evaluated'] / el:.4g} evaluated), events {res['events_after']}")
     traffic = None
-    if args.traffic and os.path.exists(args.traffic) and w is W.LARGE and smp.block == 256:
+    if args.traffic and os.path.exists(args.traffic) and w is W.LARGE:
         import hashlib
         t = json.load(open(args.traffic))
         srcs = [os.path.join(ROOT, "paper_1612_00595_amd", "csrc", f)
                 for f in ("cmh_kernels.hip", "cmh_common.hpp")]
         digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
-        if t.get("source_sha256") == digest:
+        if t.get("source_sha256") == digest and t.get("block") == smp.block:
             traffic = t.get("bytes_per_launch")
-    log(f"[bench] sweep kernel: {avg_ms * 1e3:.1f} us/launch, "
-        f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s")
+    log(f"[bench] sweep kernel: {avg_s * 1e6:.1f} us/launch (device stamps), "
+        f"{bytes_per_launch / 1e6:.3f} MB/launch algorithmic, {achieved:.1f} GB/s; "
+        f"{res['kernel_s'] / el * 100:.1f} % of the timed region in the sweep kernel")
+    # the chain's trace and state at the end of the timed sweeps: the CPU
+    # oracle continues from exactly there
+    cpu_state = None
+    if not args.no_cpu_baseline:
+        cpu_state = (trace.cpu().numpy(), smp.read_events(0), res["first"] + args.steps)
 
     # the exact refresh (variance written, log-likelihood summed) on the same
     # full-size instance: 12 B per sample streamed
@@ -676,8 +720,17 @@ def main():
             "moves_per_region": w.sampler.k,
             "chains": w.chains,
             "poisson_mean_events": w.model.lam,
+            "burn_in_sweeps": burn,
+            "timed_sweeps": [res["first"], res["first"] + args.steps - 1],
             "events_after_run": nev,
             "block": smp.block,
+        },
+        "proposals": {
+            "attempted": res["proposals"], "evaluated": res["evaluated"],
+            "rejected_without_delta": res["proposals"] - res["evaluated"],
+            "accepted": res["accepted"],
+            "evaluated_per_s": res["evaluated"] / el,
+            "acceptance_birth_death_loc_time_mag": res["acceptance"],
         },
         "roofline": {
             "bound": "hbm",
@@ -686,8 +739,11 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_sweep_color",
-            "avg_launch_us": avg_ms * 1e3,
+            "kernel": "sweep colour phase (form %d)" % smp.block,
+            "avg_launch_us": avg_s * 1e6,
+            "launches": res["launches"],
+            "duration_source": "device steady-clock stamps of the timed sweeps",
+            "kernel_share_of_step": res["kernel_s"] / el,
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
     }
@@ -702,17 +758,21 @@ def main():
         traceb = chromh.simulate(wb.model, truthb, 1000 + wb.seed, wb.trace_dtype, dev)
         sb = chromh.ChromaticSampler(wb.model, wb.sampler, traceb, chains=wb.chains,
                                      seed=wb.seed, block=args.block)
-        if args.block == 0:
-            sb.autotune(0, 2)
-        rb = measure(sb, wb, args.warmup, max(args.steps // 5, 5), 2, stream)
-        log(f"[bench] {wb.name}: {rb['value']:.4g} proposals/s, sweep kernel "
-            f"{rb['avg_ms'] * 1e3:.1f} us/launch, {rb['achieved']:.1f} GB/s algorithmic")
+        kb = max(args.steps // 5, 5)
+        bb = args.burn_in if args.burn_in >= 0 else burn_in_for(wb, args.warmup, kb)
+        rb = measure(sb, wb, args.warmup, kb, bb, tune=args.block == 0)
+        log(f"[bench] {wb.name}: {rb['value']:.4g} proposals/s (form {sb.block}), sweep kernel "
+            f"{rb['avg_launch_s'] * 1e6:.1f} us/launch, {rb['achieved']:.1f} GB/s algorithmic")
         out["batched"] = {
             "workload": wb.name, "chains": wb.chains, "value": rb["value"],
-            "unit": "proposals/s", "ms_per_step": rb["elapsed"] * 1e3 / max(args.steps // 5, 5),
-            "sweep_kernel_us": rb["avg_ms"] * 1e3,
+            "unit": "proposals/s", "ms_per_step": rb["elapsed"] * 1e3 / kb,
+            "burn_in_sweeps": bb, "timed_sweeps": [rb["first"], rb["first"] + kb - 1],
+            "sweep_kernel_us": rb["avg_launch_s"] * 1e6,
+            "kernel_share_of_step": rb["kernel_s"] / rb["elapsed"],
             "algorithmic_bytes_per_launch": rb["bytes_per_launch"],
             "achieved_GBps": rb["achieved"], "frac": rb["achieved"] / HBM_PEAK_GBS,
+            "rejected_without_delta": rb["proposals"] - rb["evaluated"],
+            "acceptance_birth_death_loc_time_mag": rb["acceptance"],
             "block": sb.block,
         }
         sb.close()
@@ -726,13 +786,14 @@ def main():
         trt = chromh.simulate(wt.model, truth, 1000 + wt.seed, wt.trace_dtype, dev)
         st_ = chromh.ChromaticSampler(wt.model, wt.sampler, trt, chains=1, seed=wt.seed,
                                       block=block)
-        rt = measure(st_, wt, args.warmup, args.steps, args.profile_sweeps, stream)
+        rt = measure(st_, wt, args.warmup, args.steps, burn)
         log(f"[bench] {wt.name}: {rt['value']:.4g} proposals/s, sweep kernel "
-            f"{rt['avg_ms'] * 1e3:.1f} us/launch, {rt['achieved']:.1f} GB/s algorithmic")
+            f"{rt['avg_launch_s'] * 1e6:.1f} us/launch, {rt['achieved']:.1f} GB/s algorithmic")
         out["template"] = {
             "workload": wt.name, "value": rt["value"], "unit": "proposals/s",
             "ms_per_step": rt["elapsed"] * 1e3 / args.steps, "block": block,
-            "sweep_kernel_us": rt["avg_ms"] * 1e3,
+            "burn_in_sweeps": burn, "timed_sweeps": [rt["first"], rt["first"] + args.steps - 1],
+            "sweep_kernel_us": rt["avg_launch_s"] * 1e6,
             "algorithmic_bytes_per_launch": rt["bytes_per_launch"],
             "bytes_per_sample": "8 read (residual) + 8 written on accept",
             "achieved_GBps": rt["achieved"], "frac": rt["achieved"] / HBM_PEAK_GBS,
@@ -761,13 +822,13 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w, args.warmup, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, cpu_state, args.cpu_seconds)
         threads, cpu_model = host_cpu()
         out["cpu_baseline"]["cpu_model"] = cpu_model
         if not args.no_cpu_parallel and threads > 1:
             # context, not the baseline: the oracle's colour phases across
             # the host's cores (the parallelism of the paper's own runs)
-            out["cpu_parallel"] = cpu_baseline(w, args.warmup, args.cpu_seconds, threads)
+            out["cpu_parallel"] = cpu_baseline(w, cpu_state, args.cpu_seconds, threads)
             out["cpu_parallel"]["cpu_model"] = cpu_model
             log(f"[bench] oracle on {threads} host threads: "
                 f"{out['cpu_parallel']['value']:.4g} proposals/s")

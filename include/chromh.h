@@ -117,6 +117,8 @@ typedef struct {
     double  arrival_sd;
 } cmh_model;
 
+#define CMH_BLOCK_SPEC 1024
+
 typedef struct {
     int32_t grid_x, grid_y;     /* regions per axis of the unshifted grid */
     int32_t dynamic;            /* 1: offset redrawn every sweep */
@@ -129,7 +131,12 @@ typedef struct {
     int32_t block;              /* sweep kernel form: 128, 256, 512 threads per region (one
                                    scout wave, the rest evaluate; for few regions per
                                    colour), or 64: one wave per region, four regions per
-                                   workgroup (for many regions per colour); 0 = 256 */
+                                   workgroup (for many regions per colour), or
+                                   CMH_BLOCK_SPEC + 128 / 256 / 512: 2, 4 or 8 waves per
+                                   region, each taking one of the region's next moves from
+                                   the same state, the first accepted one committed (the
+                                   chain is the sequential one; not with latent arrivals
+                                   or the naive schedule); 0 = 256 */
     int32_t schedule;           /* 0: chromatic (Algorithm 4).  1: naive parallel MH
                                    (Algorithm 3, the paper's negative control): every region
                                    in one phase, each evaluating against the phase-start
@@ -159,6 +166,11 @@ typedef struct {
      * and of the old arrivals) enter the ratio.  All seven probabilities sum
      * to 1. */
     double  p_arrival, p_joint, step_arrival;
+    int32_t refresh_every;      /* > 0: after every sweep s with (s + 1) % refresh_every == 0
+                                   the event variance of every chain is recomputed exactly
+                                   from its events (removing the rounding that in-place
+                                   updates accumulate); 0: never */
+    int32_t _pad0;
 } cmh_sampler;
 
 typedef struct {
@@ -228,8 +240,10 @@ int32_t cmh_run_sweeps(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, voi
 int32_t cmh_read_events(cmh_state *st, int32_t chain, cmh_event *out_host, int64_t cap,
                         int64_t *n_out);
 
-/* Replace one chain's events (host array, ids kept) and recompute its event
- * variance exactly.  Synchronises. */
+/* Replace one chain's (one instance's, in a batch) events (host array, ids
+ * kept) and recompute its event variance exactly.  Events must lie in the
+ * model's support; a region over capacity is CMH_ECAP, with the state
+ * unchanged.  Synchronises. */
 int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host, int64_t n);
 
 /* Checkpoint and resume.  cmh_save copies every chain's (or batch
@@ -299,14 +313,48 @@ int32_t cmh_read_variance(cmh_state *st, int32_t chain, int64_t station0, int64_
  * same three counts for CMH_ARR and CMH_JOINT.  Synchronises. */
 int32_t cmh_read_stats(cmh_state *st, int32_t chain, uint64_t *out_host);
 
-/* Threads per workgroup of the sweep kernel in use (after tuning). */
+/* The sweep kernel form in use (the sampler's block code, after tuning). */
 int32_t cmh_get_block(cmh_state *st, int32_t *block);
 
-/* Times each sweep-kernel workgroup size on n_trial sweeps starting at
+/* Times each sweep-kernel form on n_trial sweeps starting at
  * first_sweep, keeps the fastest, then restores the chains' events and
  * recomputes their event variance.  Results are cached per problem shape.
  * Synchronises. */
 int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream);
+
+/* Log-posterior of every chain (instance, in a batch) as its current
+ * events stand (Section 3's joint density of events and signals, as a set
+ * density, up to the constant of the signal model): out_host[3 c] = the
+ * signals' log-likelihood ln p(s | X), out_host[3 c + 1] = the events' log
+ * prior (-lambda + sum over events of ln lambda, the uniform location and
+ * onset densities, the magnitude's exponential density, and with latent
+ * arrivals each offset's truncated-normal density), out_host[3 c + 2] their
+ * sum.  The variance is recomputed exactly from the events on the way
+ * (written back to the state when write_variance is set).  Synchronises. */
+int32_t cmh_log_posterior(cmh_state *st, int32_t write_variance, double *out_host,
+                          void *hip_stream);
+
+/* Log-probability records taken by the scheduled refresh (refresh_every >
+ * 0): for each sweep s in first_sweep .. first_sweep + n_sweeps - 1 at which
+ * the refresh runs, rec_dev[((s - first_sweep) n_chains + c) 2 + 0 / 1]
+ * receive chain c's log-likelihood / log prior after the sweep (rows of
+ * other sweeps are not written).  rec_dev: caller-owned device memory of
+ * n_sweeps x n_chains x 2 doubles.  NULL switches recording off. */
+int32_t cmh_set_logprob(cmh_state *st, double *rec_dev, int64_t first_sweep, int64_t n_sweeps);
+
+/* Sweep-kernel time stamps (measurement), read live from the sweeps as they
+ * run, graph replays included.  stamps_dev: caller-owned device memory of
+ * n_sweeps x n_colors x 2 uint64, which the caller fills with (UINT64_MAX,
+ * 0) pairs before the stamped sweeps run.  For sweep first_sweep + s, the
+ * colour-c kernel folds the device's steady clock (cmh_stamp_rate ticks per
+ * second) at the start of each workgroup into element 2 (s n_colors + c)
+ * (minimum) and at the end into element 2 (s n_colors + c) + 1 (maximum):
+ * end - start is the kernel's span from its first workgroup's start to its
+ * last workgroup's end.  NULL switches stamping off.  Drops the captured
+ * sweep graphs (they are rebuilt on the next cmh_run_sweeps). */
+int32_t cmh_set_stamps(cmh_state *st, uint64_t *stamps_dev, int64_t first_sweep,
+                       int64_t n_sweeps);
+int32_t cmh_stamp_rate(int32_t device, int64_t *hz);
 
 /* Runs sweeps first_sweep .. first_sweep + n_sweeps - 1 like cmh_run_sweeps
  * but launched one kernel at a time, with HIP events recorded on hip_stream

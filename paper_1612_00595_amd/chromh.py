@@ -45,7 +45,8 @@ class CmhSampler(C.Structure):
                 ("p_mag", C.c_double), ("step_xy", C.c_double), ("step_t", C.c_double),
                 ("step_m", C.c_double), ("prior_only", C.c_int32), ("block", C.c_int32),
                 ("schedule", C.c_int32), ("debug", C.c_int32), ("p_arrival", C.c_double),
-                ("p_joint", C.c_double), ("step_arrival", C.c_double)]
+                ("p_joint", C.c_double), ("step_arrival", C.c_double),
+                ("refresh_every", C.c_int32), ("_pad0", C.c_int32)]
 
 
 class CmhError(RuntimeError):
@@ -65,7 +66,7 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
            "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init",
            "cmh_batch_learned_bytes", "cmh_batch_set_learned", "cmh_checkpoint_bytes", "cmh_save",
-           "cmh_load"]
+           "cmh_load", "cmh_set_stamps", "cmh_stamp_rate", "cmh_log_posterior", "cmh_set_logprob"]
 
 _lib = None
 
@@ -97,6 +98,10 @@ def lib():
         "cmh_get_block": ([P, P], I32),
         "cmh_autotune": ([P, I64, I32, P], I32),
         "cmh_time_phases": ([P, I64, I64, P, P], I32),
+        "cmh_set_stamps": ([P, P, I64, I64], I32),
+        "cmh_log_posterior": ([P, I32, P, P], I32),
+        "cmh_set_logprob": ([P, P, I64, I64], I32),
+        "cmh_stamp_rate": ([I32, P], I32),
         "cmh_destroy": ([P], I32),
         "cmh_simulate_bytes": ([P, P, I64, P], I32),
         "cmh_simulate": ([P, P, I64, U32, P, I32, P, C.c_size_t, P], I32),
@@ -155,6 +160,12 @@ def model_struct(spec: ModelSpec) -> CmhModel:
     return m
 
 
+# sweep-kernel forms beyond the workgroup sizes 64/128/256/512: the
+# speculative form with 2, 4 or 8 waves per region (include/chromh.h)
+BLOCK_SPEC = 1024
+SPEC2, SPEC4, SPEC8 = BLOCK_SPEC + 128, BLOCK_SPEC + 256, BLOCK_SPEC + 512
+
+
 def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
     s = CmhSampler()
     s.grid_x, s.grid_y, s.dynamic, s.period = spec.gx, spec.gy, spec.dynamic, spec.period
@@ -164,6 +175,7 @@ def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:
     s.prior_only, s.block, s.schedule = spec.prior_only, block, spec.schedule
     s.debug = spec.debug
     s.p_arrival, s.p_joint, s.step_arrival = spec.pa, spec.pj, spec.sa
+    s.refresh_every = spec.refresh_every
     return s
 
 
@@ -426,6 +438,54 @@ class ChromaticSampler:
         out = np.zeros(self.ncolors + 1, dtype=np.float32)
         check(lib().cmh_time_phases(self._h, first, n, _stream(stream), _ptr(out)))
         return out
+
+    def log_posterior(self, write_variance: bool = False, stream=None) -> np.ndarray:
+        """[chains][3]: log-likelihood, log prior and their sum for every
+        chain (instance, in a batch), from an exact recomputation."""
+        out = np.zeros((self.chains, 3))
+        check(lib().cmh_log_posterior(self._h, 1 if write_variance else 0, _ptr(out),
+                                      _stream(stream)))
+        return out
+
+    def set_logprob(self, first: int, n: int):
+        """Device records [n][chains][2] (log-likelihood, log prior) taken by
+        the scheduled refresh after sweeps first .. first + n - 1 (NaN where
+        no refresh ran); returns the buffer (n <= 0 switches recording off)."""
+        import torch
+        if n <= 0:
+            check(lib().cmh_set_logprob(self._h, None, 0, 0))
+            self._lp = None
+            return None
+        buf = torch.full((n, self.chains, 2), float("nan"), dtype=torch.float64,
+                         device=self.trace.device)
+        torch.cuda.synchronize(self.trace.device)
+        check(lib().cmh_set_logprob(self._h, C.c_void_p(buf.data_ptr()), first, n))
+        self._lp = buf
+        return buf
+
+    def set_stamps(self, first: int, n: int):
+        """Sweep-kernel time stamps for sweeps first .. first + n - 1 into a
+        device buffer [n][colours][2] (start minimum, end maximum of the
+        steady clock); returns it (None, 0, 0 switches stamping off)."""
+        import torch
+        if n <= 0:
+            check(lib().cmh_set_stamps(self._h, None, 0, 0))
+            self._stamps = None
+            return None
+        buf = torch.zeros((n, self.ncolors, 2), dtype=torch.int64, device=self.trace.device)
+        buf[..., 0] = -1  # all ones: the minimum's identity
+        torch.cuda.synchronize(self.trace.device)
+        check(lib().cmh_set_stamps(self._h, C.c_void_p(buf.data_ptr()), first, n))
+        self._stamps = buf
+        return buf
+
+    @staticmethod
+    def stamp_seconds(buf) -> np.ndarray:
+        """Kernel spans [n][colours] in seconds from a stamp buffer."""
+        hz = C.c_int64()
+        check(lib().cmh_stamp_rate(0, C.byref(hz)))
+        a = buf.cpu().numpy().view(np.uint64)
+        return (a[..., 1].astype(np.float64) - a[..., 0].astype(np.float64)) / hz.value
 
     def close(self):
         if getattr(self, "_h", None):

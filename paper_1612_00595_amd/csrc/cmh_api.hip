@@ -283,9 +283,12 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (std::fabs(sum - 1.0) > 1e-9) return fail(CMH_EINVAL, "move probabilities must sum to 1");
     if (!(s->step_xy >= 0.0) || !(s->step_t >= 0.0) || !(s->step_m >= 0.0))
         return fail(CMH_EINVAL, "step sizes must be non-negative");
-    if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512)
-        return fail(CMH_EINVAL, "block must be 0, 64, 128, 256 or 512");
+    if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512 &&
+        !cmh::is_spec_block(s->block))
+        return fail(CMH_EINVAL, "block must be 0, 64, 128, 256, 512 or CMH_BLOCK_SPEC + 128, "
+                                "256 or 512");
     if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
+    if (s->refresh_every < 0) return fail(CMH_EINVAL, "refresh_every must be non-negative");
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
     if (s->schedule != 0 && s->schedule != 1) return fail(CMH_EINVAL, "schedule must be 0 or 1");
@@ -436,6 +439,11 @@ struct cmh_state {
     int feed_width = 8;
     double *logp = nullptr;
     long long log_first = 0, log_n = 0;
+    int refresh_every = 0;   // exact refresh after every this many sweeps (0: never)
+    double *lp_rec = nullptr;  // log-probability records [sweeps][slot][2] (NULL: off)
+    long long lp_first = 0, lp_n = 0;
+    unsigned long long *stamps = nullptr;  // sweep-kernel time stamps (NULL: off)
+    long long stamp_first = 0, stamp_n = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_block = 0;
     hipStream_t cap_stream = nullptr;
@@ -473,7 +481,7 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     unsigned long long *stats = c.take<unsigned long long>((size_t)chains * cmh::kStats);
     unsigned long long *stats_snap = c.take<unsigned long long>((size_t)chains * cmh::kStats);
     double *partials = c.take<double>((size_t)chains * cmh::refresh_blocks(g));
-    double *llout = c.take<double>((size_t)chains);
+    double *llout = c.take<double>((size_t)chains * 2);
     double *draws = c.take<double>((size_t)chains * g.R * (size_t)g.k * 8);
     double *draws2 = g.latent ? c.take<double>((size_t)chains * g.R * (size_t)g.k * 8) : nullptr;
     cmh::Slot *slots = c.take<cmh::Slot>((size_t)chains);
@@ -639,17 +647,32 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
         hipError_t e = enqueue_sweep_start(st, s);
         if (e) return e;
     }
+    const cmh::StampArg sa{st->stamps, st->stamp_first, st->stamp_n, color, st->g.ncolors};
     hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
                                      st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
                                      st->log_first, st->log_n, st->err, st->block,
                                      st->g.naive ? st->naive_elems : 0, st->g.latent,
-                                     st->owner_any, s);
+                                     st->owner_any, sa, s);
     if (!e && st->g.naive)  // the merged events' variance after the single naive phase
         e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
                                       st->f64, st->err, s);
     if (e || st->rec == nullptr || color != st->g.ncolors - 1) return e;
     return cmh::launch_record(st->slots_d, st->nslots, st->cur, st->sweep_ctr, st->rec,
                               st->rec_first, st->rec_n, st->rec_max, s);
+}
+
+// The scheduled exact refresh after sweep `sweep` (every refresh_every
+// sweeps): every slot's event variance recomputed from its events, removing
+// the rounding the incremental updates accumulate; within the log-probability
+// record's range also each slot's log-likelihood and log prior.
+hipError_t enqueue_refresh(cmh_state *st, long long sweep, hipStream_t s)
+{
+    if (st->refresh_every <= 0 || (sweep + 1) % st->refresh_every != 0) return hipSuccess;
+    double *out = nullptr;
+    if (st->lp_rec && sweep >= st->lp_first && sweep < st->lp_first + st->lp_n)
+        out = st->lp_rec + (sweep - st->lp_first) * 2LL * st->nslots;
+    return cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur, st->f64,
+                                     st->err, s, 1, st->partials, out);
 }
 
 void drop_graphs(cmh_state *st)
@@ -806,6 +829,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     st->f64 = trace_dtype == CMH_F64;
     st->trace = trace_dev;
     st->block = g.naive ? 64 : (sampler->block ? sampler->block : 256);
+    st->refresh_every = sampler->refresh_every;
     carve_state(g, n_chains, (char *)workspace_dev, st);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
@@ -855,6 +879,7 @@ int32_t cmh_sweep_color(cmh_state *st, int64_t sweep, int32_t color, void *hip_s
     hipStream_t s = (hipStream_t)hip_stream;
     HIPCHK(cmh::set_sweep(st->sweep_ctr, sweep, s));
     HIPCHK(enqueue_phase(st, color, color == 0, s));
+    if (color == st->g.ncolors - 1) HIPCHK(enqueue_refresh(st, sweep, s));
     return CMH_OK;
 }
 
@@ -882,6 +907,7 @@ int32_t cmh_run_sweeps(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, voi
     for (int64_t q = 0; q < n_sweeps; ++q) {
         HIPCHK(hipGraphLaunch(st->graph[st->g.dynamic ? st->cur : 0], s));
         if (st->g.dynamic) st->cur ^= 1;
+        HIPCHK(enqueue_refresh(st, first_sweep + q, s));
     }
     return CMH_OK;
 }
@@ -1118,15 +1144,17 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
 {
     int32_t rc = check_state(st);
     if (rc) return rc;
-    if ((rc = check_single(st))) return rc;
     if (chain < 0 || chain >= st->chains) return fail(CMH_EINVAL, "chain out of range");
     if (n < 0 || (n > 0 && !ev_host)) return fail(CMH_EINVAL, "bad event array");
     rc = sync_and_check(st);
     if (rc) return rc;
-    const Geo &g = st->g;
-    const Events &ev = st->ev[st->cur];
+    // the chain's (the instance's, in a batch) own view: its constants and
+    // its slot-local event table
+    const cmh::Slot &sl = st->slots_h[chain];
+    const Geo &g = sl.g;
+    const Events &ev = sl.ev[st->cur];
     double off[2];
-    HIPCHK(hipMemcpy(off, ev.off + 2 * chain, 16, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(off, ev.off, 16, hipMemcpyDeviceToHost));
     std::vector<std::vector<cmh_event>> reg(g.R);
     for (int64_t q = 0; q < n; ++q) {
         const cmh_event &e = ev_host[q];
@@ -1139,7 +1167,7 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
                     return fail(CMH_EINVAL, "arrival offset beyond the jitter bound");
         reg[cmh::event_region(g, off[0], off[1], e.x, e.y, e.t)].push_back(e);
     }
-    const size_t slots = (size_t)g.R * g.cap, o = (size_t)chain * slots;
+    const size_t slots = (size_t)g.R * g.cap, o = 0;
     std::vector<double> da(g.latent ? slots * 8 : 0, 0.0);
     std::vector<int> cnt(g.R, 0);
     std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0);
@@ -1158,15 +1186,15 @@ int32_t cmh_write_events(cmh_state *st, int32_t chain, const cmh_event *ev_host,
         }
     }
     if (g.latent) HIPCHK(hipMemcpy(ev.da + 8 * o, da.data(), slots * 64, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(ev.cnt + (size_t)chain * g.R, cnt.data(), g.R * sizeof(int),
-                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ev.cnt, cnt.data(), g.R * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.x + o, x.data(), slots * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.y + o, y.data(), slots * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.t + o, t.data(), slots * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.m + o, m.data(), slots * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ev.id + o, id.data(), slots * 8, hipMemcpyHostToDevice));
-    HIPCHK(cmh::launch_refresh(g, ev, st->trace, st->f64, st->E, 1, st->partials, nullptr, chain,
-                               1, st->err, nullptr));
+    // the variance of this chain alone, recomputed from the new events
+    HIPCHK(cmh::launch_refresh_slots(st->slots_d + chain, 1, cmh::refresh_blocks(g), st->cur,
+                                     st->f64, st->err, nullptr));
     return sync_and_check(st);
 }
 
@@ -1211,6 +1239,67 @@ int32_t cmh_set_log(cmh_state *st, double *log_dev, int64_t first_sweep, int64_t
     st->logp = log_dev;
     st->log_first = log_dev ? first_sweep : 0;
     st->log_n = log_dev ? n_sweeps : 0;
+    return CMH_OK;
+}
+
+int32_t cmh_log_posterior(cmh_state *st, int32_t write_variance, double *out_host,
+                          void *hip_stream)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!out_host) return fail(CMH_EINVAL, "out_host is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur, st->f64,
+                                     st->err, s, write_variance ? 1 : 0, st->partials,
+                                     st->llout));
+    rc = sync_and_check(st);
+    if (rc) return rc;
+    std::vector<double> v((size_t)st->nslots * 2);
+    HIPCHK(hipMemcpy(v.data(), st->llout, v.size() * 8, hipMemcpyDeviceToHost));
+    for (int q = 0; q < st->nslots; ++q) {
+        out_host[3 * q] = v[2 * q];
+        out_host[3 * q + 1] = v[2 * q + 1];
+        out_host[3 * q + 2] = v[2 * q] + v[2 * q + 1];
+    }
+    return CMH_OK;
+}
+
+int32_t cmh_set_logprob(cmh_state *st, double *rec_dev, int64_t first_sweep, int64_t n_sweeps)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (rec_dev && (first_sweep < 0 || n_sweeps < 1))
+        return fail(CMH_EINVAL, "log-probability records need first_sweep >= 0, n_sweeps >= 1");
+    if (rec_dev && st->refresh_every <= 0)
+        return fail(CMH_EINVAL, "log-probability records are taken at the scheduled refresh: "
+                                "set refresh_every");
+    st->lp_rec = rec_dev;
+    st->lp_first = rec_dev ? first_sweep : 0;
+    st->lp_n = rec_dev ? n_sweeps : 0;
+    return CMH_OK;
+}
+
+int32_t cmh_set_stamps(cmh_state *st, uint64_t *stamps_dev, int64_t first_sweep,
+                       int64_t n_sweeps)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (stamps_dev && (first_sweep < 0 || n_sweeps < 1))
+        return fail(CMH_EINVAL, "stamps need first_sweep >= 0 and n_sweeps >= 1");
+    drop_graphs(st);  // the graphs carry the kernels' arguments
+    st->stamps = (unsigned long long *)stamps_dev;
+    st->stamp_first = stamps_dev ? first_sweep : 0;
+    st->stamp_n = stamps_dev ? n_sweeps : 0;
+    return CMH_OK;
+}
+
+int32_t cmh_stamp_rate(int32_t device, int64_t *hz)
+{
+    if (!hz) return fail(CMH_EINVAL, "NULL argument");
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+    if (khz <= 0) return fail(CMH_EHIP, "no steady clock rate");
+    *hz = (int64_t)khz * 1000;
     return CMH_OK;
 }
 
@@ -1307,7 +1396,9 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     HIPCHK(hipEventCreate(&e1));
     // latent arrivals have the wave form and the 256-thread latency form
     const std::vector<int> cands =
-        g.latent ? std::vector<int>{64, 256} : std::vector<int>{64, 128, 256, 512};
+        g.latent ? std::vector<int>{64, 256}
+                 : std::vector<int>{64, 128, 256, 512, cmh::kSpecBase + 128,
+                                    cmh::kSpecBase + 256, cmh::kSpecBase + 512};
     int best = st->block;
     float best_ms = 1e30f;
     for (int b : cands) {
@@ -1542,9 +1633,10 @@ int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *sample
         if (P->g[q].R > 65535) return fail(CMH_EINVAL, "at most 65535 regions per instance");
         if (P->g[q].k != P->g[0].k || P->g[q].dynamic != P->g[0].dynamic ||
             samplers[q].block != samplers[0].block || P->g[q].naive != P->g[0].naive ||
-            P->g[q].latent != P->g[0].latent)
-            return fail(CMH_EINVAL,
-                        "instances of a batch share k, dynamic, block, schedule and latent arrivals");
+            P->g[q].latent != P->g[0].latent ||
+            samplers[q].refresh_every != samplers[0].refresh_every)
+            return fail(CMH_EINVAL, "instances of a batch share k, dynamic, block, schedule, "
+                                    "latent arrivals and refresh_every");
     }
     P->head = P->g[0];
     for (int q = 0; q < n; ++q) P->head.ncolors = std::max(P->head.ncolors, P->g[q].ncolors);
@@ -1555,10 +1647,11 @@ int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *sample
 // shared sweep counter, error word, slot table and work items.
 size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots,
                    long long **sweep, int **err, cmh::Slot **slots_d, unsigned **items_all,
-                   unsigned **items_col)
+                   unsigned **items_col, double **partials = nullptr, double **llout = nullptr)
 {
     Carver c{base};
     long long total_r = 0;
+    int per_max = 0;
     for (size_t q = 0; q < P.g.size(); ++q) {
         const Geo &g = P.g[q];
         cmh::Slot sl{};
@@ -1571,7 +1664,12 @@ size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots
         sl.owner = g.owner ? c.take<unsigned long long>((size_t)g.nsta * (size_t)g.N) : nullptr;
         if (slots) (*slots)[q] = sl;
         total_r += g.R;
+        per_max = std::max(per_max, cmh::refresh_blocks(g));
     }
+    double *pp = c.take<double>(P.g.size() * (size_t)per_max);
+    double *lo = c.take<double>(P.g.size() * 2);
+    if (partials) *partials = pp;
+    if (llout) *llout = lo;
     long long *sw = c.take<long long>(1);
     int *er = c.take<int>(1);
     cmh::Slot *sd = c.take<cmh::Slot>(P.g.size());
@@ -1626,7 +1724,8 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
     st->block = P.head.naive ? 64 : (samplers[0].block ? samplers[0].block : 256);
     st->slots_h.resize(n_instances);
     carve_batch(P, (char *)workspace_dev, &st->slots_h, &st->sweep_ctr, &st->err, &st->slots_d,
-                &st->items_all, &st->items_col);
+                &st->items_all, &st->items_col, &st->partials, &st->llout);
+    st->refresh_every = samplers[0].refresh_every;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
     std::vector<unsigned> all, col;

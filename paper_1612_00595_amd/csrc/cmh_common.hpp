@@ -86,6 +86,15 @@ struct Learned {
     double pl;
 };
 
+// Sweep-kernel forms (the sampler's block): 64, one wave per work item; 128,
+// 256, 512, the latency form with that workgroup size; kSpecBase + 64 D,
+// the speculative form with D = 2, 4 or 8 waves per work item.
+constexpr int kSpecBase = 1024;
+__host__ __device__ constexpr bool is_spec_block(int b)
+{
+    return b == kSpecBase + 128 || b == kSpecBase + 256 || b == kSpecBase + 512;
+}
+
 // Work items of the sweep kernels: region r of slot s packed as (s << 16) | r.
 constexpr int kMaxItemRegions = 65536;
 constexpr int kMaxSlots = 65536;
@@ -125,6 +134,28 @@ struct Slot {
     // share a sample, which the colouring must rule out.
     unsigned long long *owner;  // [nsta][N]
 };
+
+// Kernel time stamps (measurement): for sweeps first .. first + n - 1, the
+// sweep kernel of colour `colour` folds the steady clock (wall_clock64) at
+// the start of each of its workgroups into p[2 q] with a minimum and at the
+// end into p[2 q + 1] with a maximum, q = (sweep - first) ncol + colour.
+// The caller clears p (all ones, zeros) before the stamped sweeps run.
+struct StampArg {
+    unsigned long long *p;
+    long long first, n;
+    int colour, ncol;
+};
+
+__device__ inline void stamp_at(const StampArg &sa, long long sweep, int end)
+{
+    if (sa.p == nullptr || sweep < sa.first || sweep >= sa.first + sa.n) return;
+    unsigned long long *q = sa.p + 2 * ((sweep - sa.first) * sa.ncol + sa.colour) + end;
+    const unsigned long long t = (unsigned long long)wall_clock64();
+    if (end)
+        atomicMax(q, t);
+    else
+        atomicMin(q, t);
+}
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, each multiplying counter

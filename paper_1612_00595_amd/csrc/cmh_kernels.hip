@@ -903,7 +903,7 @@ template <typename TraceT, int BLOCK, bool LAT, bool OWN = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LAT ? 2 : 1)))
 k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
               const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
-              long long log_first, long long log_n, int *__restrict__ err)
+              long long log_first, long long log_n, int *__restrict__ err, StampArg sa)
 {
     static_assert(BLOCK >= 128 && BLOCK % 64 == 0, "one scout wave and at least one evaluator");
     constexpr int W = BLOCK / 64;
@@ -942,6 +942,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
     const int chain = 0;  // every array of the slot is slot-local
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
+    if (tid == 0) stamp_at(sa, sweep, 0);
     // debug owner check (OWN: a separate instantiation, so production
     // kernels carry none of it)
     unsigned long long *const own = OWN ? slots[slot].owner : nullptr;
@@ -1288,6 +1289,7 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
         if (samp_read) atomicAdd(&st[15], samp_read);
         if (samp_written) atomicAdd(&st[16], samp_written);
         if (flags) atomicOr(err, flags);
+        stamp_at(sa, sweep, 1);
     }
 }
 
@@ -1404,7 +1406,8 @@ __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : (LAT ? 2 : 4))))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
-             long long log_first, long long log_n, int *__restrict__ err, int naive_elems)
+             long long log_first, long long log_n, int *__restrict__ err, int naive_elems,
+             StampArg sa)
 {
     __shared__ double s_log[kMaxCap + 2];
     __shared__ double s_T[4][kMaxTs];
@@ -1450,6 +1453,7 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     const Learned &L = s_L[wv];
     const int i = r % g.nrx, kk = r / g.nrx;
     const long long sweep = *sweep_ptr;
+    if (lane == 0) stamp_at(sa, sweep, 0);
     unsigned long long *const own = OWN ? slots[slot].owner : nullptr;  // debug owner check
     const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
     __shared__ double s_rc[4][10];
@@ -1651,6 +1655,240 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         for (int t = 0; t < kStats; ++t)
             if (cnt[t]) atomicAdd(&stats[t], cnt[t]);
         if (flags) atomicOr(err, flags);
+        stamp_at(sa, sweep, 1);
+    }
+}
+
+// ------------------------------------------------- sweep colour, speculative
+// Speculative form of a colour phase: one workgroup of D waves per work
+// item.  In each round wave w takes move j + w of the region: it builds the
+// proposal and footprint, evaluates the log-likelihood change over the
+// footprint and decides, all from the region's state before move j.  That is
+// the state the sequential chain hands to move j + w whenever moves j ..
+// j + w - 1 are all rejected.  The first accepted move of the round (in move
+// order) is committed by its wave; the moves after it are dropped and built
+// again from the new state in the next round.  Without an acceptance all D
+// moves stand.  The chain of states is therefore exactly the sequential one
+// (Algorithm 4's inner loop), while a round costs about one move's latency
+// and consumes sum_{w < D} (1 - a)^w moves at acceptance rate a.
+// Plain and mean-template likelihoods, grid and line models; latent arrivals
+// and the naive schedule keep their own forms.
+template <typename TraceT, int D, bool OWN = false>
+__global__ void __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(D <= 4 ? 1 : 2)))
+k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int par,
+             const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
+             long long log_first, long long log_n, int *__restrict__ err, StampArg sa)
+{
+    static_assert(D >= 2 && D <= 16, "two to sixteen waves");
+    constexpr int BLOCK = 64 * D;
+    __shared__ double s_draw[2][kDrawChunk][8];
+    __shared__ double s_lb[2][kDrawChunk][4];
+    __shared__ int s_lsta[kMaxRegSta];
+    __shared__ RegionLearned s_rl;
+    __shared__ double s_T[kMaxTs];
+    __shared__ double s_log[kMaxCap + 2];  // s_log[q] = log(q)
+    __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
+    __shared__ unsigned long long s_id[kMaxCap];
+    __shared__ double s_lsx[8];  // line model: station positions
+    __shared__ Seg s_seg[D][1][kMaxSeg];
+    __shared__ SegIndex s_six[D][1];
+    __shared__ MoveHdr s_hdr[D][1];
+    __shared__ double s_prop[D][1][5];
+    __shared__ int s_acc[2][D];  // per round parity: wave w's move accepted
+    __shared__ int s_n;
+    __shared__ unsigned long long s_cnt[D][kStats];
+    __shared__ int s_flags[D];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const unsigned item = items[blockIdx.x];
+    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
+    // the instance's constants are read where they sit (scalar loads): a
+    // private copy would live in scratch memory
+    const Geo &g = slots[slot].g;
+    const Events ev = slots[slot].ev[par];
+    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+    double *__restrict__ E = slots[slot].E;
+    const double *__restrict__ draws = slots[slot].draws;
+    unsigned long long *__restrict__ stats = slots[slot].stats;
+    const Learned L = slots[slot].L;
+    const int i = r % g.nrx, kk = r / g.nrx;
+    const long long sweep = *sweep_ptr;
+    if (tid == 0) stamp_at(sa, sweep, 0);
+    unsigned long long *const own = OWN ? slots[slot].owner : nullptr;  // debug owner check
+    const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
+
+    const double offx = ev.off[0], offy = ev.off[1];
+    const RegionBox box = region_box(g, offx, offy, i, kk);
+    const double x0 = box.x0, x1 = box.x1, y0 = box.y0, y1 = box.y1, area = box.area;
+    if (!(area > 0.0)) return;  // the same for every thread of the workgroup
+    const double log_lamR = log(box.lamR), log_pb = log(g.pb), log_pd = log(g.pd);
+
+    const long long base = (long long)r * g.cap;
+    const double *dsrc = draws + (long long)r * (long long)g.k * 8;
+    const double *lsrc = L.tab != nullptr ? L.birth + (long long)r * (long long)g.k * 4 : nullptr;
+    int n = ev.cnt[r];
+    for (int s = tid; s < n; s += BLOCK) {
+        s_ex[s] = ev.x[base + s]; s_ey[s] = ev.y[base + s];
+        s_et[s] = ev.t[base + s]; s_em[s] = ev.m[base + s];
+        s_id[s] = ev.id[base + s];
+    }
+    for (int q = tid; q < g.ts; q += BLOCK) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
+    for (int q = tid; q < kMaxCap + 2; q += BLOCK) s_log[q] = log((double)q);
+    if (tid < 8) s_lsx[tid] = g.sx[tid];
+    for (int q = tid; q < D * kStats; q += BLOCK) s_cnt[q / kStats][q % kStats] = 0ull;
+    // draw records of moves 0 .. 127 (chunks of 64 in a double buffer)
+    int loaded = 0;
+    for (int c = 0; c < 2 && loaded < g.k; ++c) {
+        const int m = min(kDrawChunk, g.k - loaded);
+        for (int q = tid; q < m * 8; q += BLOCK) s_draw[c][q >> 3][q & 7] = dsrc[64LL * 8 * c + q];
+        if (lsrc != nullptr)
+            for (int q = tid; q < m * 4; q += BLOCK) s_lb[c][q >> 2][q & 3] = lsrc[64LL * 4 * c + q];
+        loaded += m;
+    }
+    int flags = 0;
+    if (tid == 0) {
+        RegionLearned rl;
+        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
+        if (L.tab != nullptr) {
+            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta,
+                                           kMaxRegSta);
+            if (ns > kMaxRegSta) {
+                flags |= kFlagSta;
+            } else if (ns > 0) {
+                double W = 0.0;
+                for (int q = 0; q < ns; ++q)
+                    W = W + L.cum[(long long)s_lsta[q] * L.ntau + L.ntau - 1];
+                rl.ns = ns; rl.W = W; rl.pl = L.pl;
+            }
+        }
+        s_rl = rl;
+    }
+    const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
+                         sweep < log_first + log_n;
+    __syncthreads();
+    const RegionLearned rl = s_rl;
+    unsigned long long *cnt = s_cnt[wv];
+
+    int j = 0, round = 0;
+    while (j < g.k) {
+        const int m = min(D, g.k - j);
+        if (j + m > loaded) {
+            // the next chunk replaces the one two chunks back, whose moves
+            // (all below j) every wave has finished with
+            const int c = loaded >> 6;
+            const int cm = min(kDrawChunk, g.k - loaded);
+            for (int q = tid; q < cm * 8; q += BLOCK)
+                s_draw[c & 1][q >> 3][q & 7] = dsrc[(long long)loaded * 8 + q];
+            if (lsrc != nullptr)
+                for (int q = tid; q < cm * 4; q += BLOCK)
+                    s_lb[c & 1][q >> 2][q & 3] = lsrc[(long long)loaded * 4 + q];
+            loaded += cm;
+            __syncthreads();
+        }
+        const int jm = j + wv;  // this wave's move
+        const int db = (jm >> 6) & 1, dj = jm & 63;
+        MoveHdr h = {};
+        double delta = 0.0, la = 0.0;
+        bool accept = false, nan = false;
+        if (wv < m) {
+            scout_move<false>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[db][dj],
+                              s_ex, s_ey, s_et, s_em, s_seg[wv], s_six[wv], s_lsx, s_hdr[wv],
+                              s_prop[wv], kMaxFootprint, L, s_lb[db][dj], s_lsta, rl, nullptr,
+                              nullptr, nullptr, own, tag);
+            __builtin_amdgcn_wave_barrier();
+            h = s_hdr[wv][0];
+            const double lnu = s_draw[db][dj][7];
+            if (h.valid && !g.prior_only)
+                delta = wave_sum(wave_delta_part<TraceT, true>(g, trace, E, s_seg[wv][0],
+                                                               s_six[wv][0], h.nseg, h.S, s_T,
+                                                               lane));
+            if (h.type == 0)
+                la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
+            else if (h.type == 1)
+                la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
+            else if (h.type == 4)
+                la = delta - g.mrate * h.dm;
+            else
+                la = delta;
+            accept = h.valid && lnu < la;
+            nan = !(delta == delta) || delta - delta != 0.0;  // NaN or Inf
+            if (nan) accept = false;
+            if (lane == 0) s_acc[round & 1][wv] = accept ? 1 : 0;
+        }
+        __syncthreads();
+        int first = m;  // the first accepted move of the round, m if none
+        for (int w = m - 1; w >= 0; --w)
+            if (s_acc[round & 1][w]) first = w;
+        const int used = first < m ? first + 1 : m;
+        if (wv < used && lane == 0) {  // this wave's move is consumed
+            flags |= h.flags | (nan ? kFlagNan : 0);
+            cnt[stat_base(h.type)]++;
+            if (h.valid) {
+                cnt[stat_base(h.type) + 1]++;
+                cnt[15] += (unsigned long long)h.S;
+            }
+            if (use_log) {
+                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + jm) * 4;
+                lg[0] = (double)h.type;
+                lg[1] = h.valid ? (accept ? 2.0 : 1.0) : 0.0;
+                lg[2] = h.valid ? delta : 0.0;
+                lg[3] = h.valid ? la : 0.0;
+            }
+        }
+        if (first < m) {
+            if (wv == first) {
+                if (!g.prior_only)
+                    wave_write<true>(g, E, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, s_T, lane);
+                if (lane == 0) {
+                    cnt[stat_base(h.type) + 2]++;
+                    cnt[16] += (unsigned long long)h.S;
+                    const double *pr = s_prop[wv][0];
+                    if (h.type == 0) {
+                        s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
+                        s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
+                                  ((unsigned long long)r << 12) | (unsigned long long)jm;
+                        ++n;
+                    } else if (h.type == 1) {
+                        const int idx = (int)pr[4];
+                        for (int q = idx; q + 1 < n; ++q) {
+                            s_ex[q] = s_ex[q + 1]; s_ey[q] = s_ey[q + 1];
+                            s_et[q] = s_et[q + 1]; s_em[q] = s_em[q + 1];
+                            s_id[q] = s_id[q + 1];
+                        }
+                        --n;
+                    } else {
+                        const int idx = (int)pr[4];
+                        s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
+                    }
+                    s_n = n;
+                }
+            }
+            __syncthreads();  // the new events and variance are visible
+            n = s_n;
+        }
+        j += used;
+        ++round;
+    }
+
+    if (lane == 0) s_flags[wv] = flags;
+    __syncthreads();
+    for (int s = tid; s < n; s += BLOCK) {
+        ev.x[base + s] = s_ex[s]; ev.y[base + s] = s_ey[s];
+        ev.t[base + s] = s_et[s]; ev.m[base + s] = s_em[s];
+        ev.id[base + s] = s_id[s];
+    }
+    if (tid < kStats) {
+        unsigned long long v = 0;
+        for (int w = 0; w < D; ++w) v += s_cnt[w][tid];
+        if (v) atomicAdd(&stats[tid], v);
+    }
+    if (tid == 0) {
+        ev.cnt[r] = n;
+        int f = 0;
+        for (int w = 0; w < D; ++w) f |= s_flags[w];
+        if (f) atomicOr(err, f);
+        stamp_at(sa, sweep, 1);
     }
 }
 
@@ -2143,18 +2381,24 @@ k_refresh(Geo g, Events ev, const TraceT *__restrict__ trace, double *__restrict
     }
 }
 
-// After a naive phase (Algorithm 3): every slot's variance (the residual,
-// under templates) recomputed from its merged events, as k_refresh does for
-// one instance.  blockIdx.y slot, blockIdx.x (station, tile) of that slot;
-// the slot's constants are staged in LDS (station positions are indexed).
+// Every slot's exact event variance (the residual, under templates),
+// recomputed from its events and written to E when `write` is set, and
+// per-workgroup partial sums of its log-likelihood into partials[slot *
+// per_max + block] when partials is not NULL (as k_refresh does for the
+// chains of one instance).  Used after a naive phase (Algorithm 3), for the
+// scheduled refresh and for the log-posterior of any state.  blockIdx.y
+// slot, blockIdx.x (station, tile) of that slot; the slot's constants are
+// staged in LDS (station positions are indexed).
 template <typename TraceT>
 __global__ void __launch_bounds__(256)
-k_refresh_slots(const Slot *__restrict__ slots, int par, int *__restrict__ err)
+k_refresh_slots(const Slot *__restrict__ slots, int par, int write, double *__restrict__ partials,
+                int per_max, int *__restrict__ err)
 {
     __shared__ Geo s_g;
     __shared__ int s_n0[kMaxTileEvents];
     __shared__ double s_B[kMaxTileEvents];
     __shared__ double s_T[kMaxTs];
+    __shared__ double s_part[4];
     __shared__ int s_cnt;
     const int slot = blockIdx.y, tid = threadIdx.x;
     if (tid == 0) s_g = slots[slot].g;
@@ -2165,20 +2409,123 @@ k_refresh_slots(const Slot *__restrict__ slots, int par, int *__restrict__ err)
     const int j = blockIdx.x / tiles, tile = blockIdx.x % tiles;
     const int n_lo = tile * kTile, n_hi = min(n_lo + kTile, g.N);
     const Events ev = slots[slot].ev[par];
-    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace + (long long)j * g.N;
     double *__restrict__ Erow = slots[slot].E + (long long)j * g.N;
     int flags = 0;
     for (int q = tid; q < g.ts; q += 256) s_T[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
     const int ne = gather_tile(g, ev, 0, j, n_lo, n_hi, s_n0, s_B, &s_cnt, &flags);
-    for (int nn = n_lo + tid; nn < n_hi; nn += 256) {
-        double e = 0.0;
-        for (int q = 0; q < ne; ++q) {
-            const int d = nn - s_n0[q];
-            if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+    const double l2pi = log(2.0 * M_PI);
+    const double null_c = -0.5 * (l2pi + log(g.sigma2));
+    const double null_q = -0.5 / g.sigma2;
+    double acc = 0.0;
+    // kRefreshU samples per thread per step, every trace load in flight
+    // before any is used
+    constexpr int U = kRefreshU;
+    for (int base = n_lo + tid; base < n_hi; base += 256 * U) {
+        TraceT tv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int nn = base + 256 * u;
+            tv[u] = trace[nn < n_hi ? nn : n_lo];
         }
-        Erow[nn] = g.tmpl ? (double)trace[(long long)j * g.N + nn] - e : e;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int nn = base + 256 * u;
+            if (nn >= n_hi) break;
+            const double svu = (double)tv[u];
+            double e = 0.0;
+            for (int q = 0; q < ne; ++q) {
+                const int d = nn - s_n0[q];
+                if (d >= 0 && d < g.ts) e += s_B[q] * s_T[d];
+            }
+            if (g.tmpl) {  // e is the mean; E holds the residual
+                const double rr = svu - e;
+                acc += null_c + null_q * (rr * rr);
+                if (write) Erow[nn] = rr;
+                continue;
+            }
+            const double qv = svu * svu;
+            if (e > 0.0) {
+                const double v = g.sigma2 + e;
+                acc += -0.5 * (l2pi + log(v) + qv / v);
+            } else {
+                acc += null_c + null_q * qv;
+            }
+            if (write) Erow[nn] = e;
+        }
+    }
+    if (partials != nullptr) {
+        acc = wave_sum(acc);
+        if ((tid & 63) == 0) s_part[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0)
+            partials[(long long)slot * per_max + blockIdx.x] =
+                ((s_part[0] + s_part[1]) + s_part[2]) + s_part[3];
     }
     if (tid == 0 && flags) atomicOr(err, flags);
+}
+
+// Each slot's log-likelihood: its (station, tile) partials summed in a
+// fixed order into out[2 slot].
+__global__ void __launch_bounds__(256)
+k_sum_slots(const Slot *__restrict__ slots, const double *__restrict__ partials, int per_max,
+            double *__restrict__ out)
+{
+    __shared__ double s[256];
+    const int slot = blockIdx.x;
+    const Geo &g = slots[slot].g;
+    const int nb = g.nsta * ((g.N + kTile - 1) / kTile);
+    const double *p = partials + (long long)slot * per_max;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += 256) acc += p[q];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[2 * slot] = s[0];
+}
+
+// Each slot's log prior of its current events (Section 3's prior as a set
+// density): -lambda plus, per event, log lambda and the log densities of a
+// uniform location on the domain (the line [0, x_max) in the line model), a
+// uniform onset on [0, N) and, on the grid, an exponential magnitude above
+// m_min; with latent arrivals each offset adds the log density of a normal
+// of sd arrival_sd truncated at kArrTrunc sd (-inf outside).  Per-event terms
+// summed in a fixed order into out[2 slot + 1].
+__global__ void __launch_bounds__(256)
+k_logprior_slots(const Slot *__restrict__ slots, int par, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    const int slot = blockIdx.x;
+    const Geo &g = slots[slot].g;
+    const Events ev = slots[slot].ev[par];
+    const double per_event = g.line ? log(g.lambda) - log(g.Lx) - log((double)g.N)
+                                    : log(g.lambda) - log(g.Lx * g.Ly) - log((double)g.N) +
+                                          log(g.mrate);
+    const double lz = g.latent ? log(g.arr_sd * sqrt(2.0 * M_PI) * erf(kArrTrunc / sqrt(2.0)))
+                               : 0.0;
+    double acc = 0.0;
+    for (long long q = threadIdx.x; q < (long long)g.R * g.cap; q += 256) {
+        const int r = (int)(q / g.cap), c = (int)(q % g.cap);
+        if (c >= ev.cnt[r]) continue;
+        double t = per_event;
+        if (!g.line) t -= g.mrate * (ev.m[q] - g.mmin);
+        if (g.latent)
+            for (int jj = 0; jj < g.nsx; ++jj) {
+                const double u = ev.da[q * 8 + jj] / g.arr_sd;
+                t += fabs(u) > kArrTrunc ? -INFINITY : -0.5 * u * u - lz;
+            }
+        acc += t;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[2 * slot + 1] = s[0] - g.lambda;
 }
 
 // Sums each chain's partials in a fixed order (deterministic result).
@@ -2300,16 +2647,16 @@ template <typename TraceT, bool OWN>
 static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int nitems, int par,
                                  const long long *sweep_ptr, double *logp, long long log_first,
                                  long long log_n, int *err, int block, int naive_elems, int latent,
-                                 hipStream_t s)
+                                 const StampArg &sa, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     if (latent) {  // latent arrivals: the wave form (block 64) or the 256-thread latency form
         if (block == 64)
             k_sweep_wave<TraceT, false, true, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
-                slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0);
+                slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa);
         else
             k_sweep_color<TraceT, 256, true, OWN><<<nitems, 256, 0, s>>>(
-                slots, items, par, sweep_ptr, logp, log_first, log_n, err);
+                slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
         return hipGetLastError();
     }
     if (naive_elems > 0) {
@@ -2318,25 +2665,37 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         k_sweep_wave<TraceT, true><<<(nitems + 3) / 4, 256, lds, s>>>(
-            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, naive_elems);
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, naive_elems, sa);
         return hipGetLastError();
     }
     switch (block) {
+    case kSpecBase + 128:  // speculative form: one region per workgroup, D waves
+        k_sweep_spec<TraceT, 2, OWN><<<nitems, 128, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
+        break;
+    case kSpecBase + 256:
+        k_sweep_spec<TraceT, 4, OWN><<<nitems, 256, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
+        break;
+    case kSpecBase + 512:
+        k_sweep_spec<TraceT, 8, OWN><<<nitems, 512, 0, s>>>(
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
+        break;
     case 64:  // one wave per work item, four per workgroup
         k_sweep_wave<TraceT, false, false, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
-            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0);
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa);
         break;
     case 512:
         k_sweep_color<TraceT, 512, false, OWN><<<nitems, 512, 0, s>>>(
-            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
         break;
     case 128:
         k_sweep_color<TraceT, 128, false, OWN><<<nitems, 128, 0, s>>>(
-            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
         break;
     default:
         k_sweep_color<TraceT, 256, false, OWN><<<nitems, 256, 0, s>>>(
-            slots, items, par, sweep_ptr, logp, log_first, log_n, err);
+            slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
         break;
     }
     return hipGetLastError();
@@ -2345,32 +2704,38 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
                         long long log_n, int *err, int block, int naive_elems, int latent,
-                        int owner, hipStream_t s)
+                        int owner, const StampArg &sa, hipStream_t s)
 {
     if (f64)
         return owner ? launch_sweep_t<double, true>(slots, items, nitems, par, sweep_ptr, logp,
                                                     log_first, log_n, err, block, naive_elems,
-                                                    latent, s)
+                                                    latent, sa, s)
                      : launch_sweep_t<double, false>(slots, items, nitems, par, sweep_ptr, logp,
                                                      log_first, log_n, err, block, naive_elems,
-                                                     latent, s);
+                                                     latent, sa, s);
     return owner ? launch_sweep_t<float, true>(slots, items, nitems, par, sweep_ptr, logp,
                                                log_first, log_n, err, block, naive_elems, latent,
-                                               s)
+                                               sa, s)
                  : launch_sweep_t<float, false>(slots, items, nitems, par, sweep_ptr, logp,
                                                 log_first, log_n, err, block, naive_elems, latent,
-                                                s);
+                                                sa, s);
 }
 
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
-                                int *err, hipStream_t s)
+                                int *err, hipStream_t s, int write, double *partials, double *out)
 {
     if (nslots <= 0 || max_blocks <= 0) return hipSuccess;
     const dim3 grid(max_blocks, nslots);
+    double *part = out != nullptr ? partials : nullptr;
     if (f64)
-        k_refresh_slots<double><<<grid, 256, 0, s>>>(slots, par, err);
+        k_refresh_slots<double><<<grid, 256, 0, s>>>(slots, par, write, part, max_blocks, err);
     else
-        k_refresh_slots<float><<<grid, 256, 0, s>>>(slots, par, err);
+        k_refresh_slots<float><<<grid, 256, 0, s>>>(slots, par, write, part, max_blocks, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || out == nullptr) return e;
+    k_sum_slots<<<nslots, 256, 0, s>>>(slots, partials, max_blocks, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_logprior_slots<<<nslots, 256, 0, s>>>(slots, par, out);
     return hipGetLastError();
 }
 

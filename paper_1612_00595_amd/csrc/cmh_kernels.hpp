@@ -8,9 +8,13 @@ namespace cmh {
 hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, int par, int f64,
                         const long long *sweep_ptr, double *logp, long long log_first,
                         long long log_n, int *err, int block, int naive_elems, int latent,
-                        int owner, hipStream_t s);
+                        int owner, const StampArg &sa, hipStream_t s);
+// Every slot's event variance recomputed (written to E when `write`); with
+// out, also each slot's log-likelihood and log prior into out[2 slot],
+// out[2 slot + 1] (partials: max_blocks doubles per slot).
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
-                                int *err, hipStream_t s);
+                                int *err, hipStream_t s, int write = 1,
+                                double *partials = nullptr, double *out = nullptr);
 hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
                               int par, const long long *sweep_ptr, const double *feed,
                               long long feed_first, int width, bool learned, int *err,

@@ -93,6 +93,7 @@ class SamplerSpec:
     pj: float = 0.0            # latent arrivals: joint two-event move probability
     sa: float = 0.0            # latent arrivals: arrival step
     debug: int = 0             # library only: bit 0 owner check, bit 1 unchecked period
+    refresh_every: int = 0     # library only: exact variance refresh every this many sweeps
 
     @property
     def nreg(self) -> int:

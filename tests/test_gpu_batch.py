@@ -23,7 +23,7 @@ def _instances():
     return specs, samplers
 
 
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, 1024 + 256])
 def test_batch_instances_match_single_runs(block):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -40,8 +40,9 @@ def test_batch_instances_match_single_runs(block):
     b.run_sweeps(0, 6)
     torch.cuda.synchronize()
     for q, m in enumerate(specs):
+        # the latency form alone: every batch form against it
         one = chromh.ChromaticSampler(m, samplers[q], traces[q], chains=1, seed=seeds[q],
-                                      block=256)   # the latency form: both forms, one chain
+                                      block=256)
         one.run_sweeps(0, 6)
         got, ref = b.read_events(q), one.read_events(0)
         say("instance", q, "events", len(ref))

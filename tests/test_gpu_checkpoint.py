@@ -51,7 +51,7 @@ def test_resume_dynamic_grid_chains():
     trace = torch.from_numpy(s).to(DEV)
     say("checkpoint: 3 chains of", w.name)
     a, b = _check_resume(lambda: chromh.ChromaticSampler(w.model, w.sampler, trace, chains=3,
-                                                         seed=8, block=128), 3, 5, 4)
+                                                         seed=8, block=1024 + 256), 3, 5, 4)
     for c in range(3):
         assert np.array_equal(a.read_variance(c), b.read_variance(c))
 

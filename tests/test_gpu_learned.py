@@ -84,7 +84,7 @@ def _learned_replay(w, nsw, block, table_seed, feed_seed=55, p_learned=0.5):
     return acc, births
 
 
-@pytest.mark.parametrize("block", [64, 128, 256])
+@pytest.mark.parametrize("block", [64, 128, 256, 1024 + 256])
 def test_learned_replay_parity_small_static(block):
     say("learned replay", W.SMALL.name, "block", block)
     acc, births = _learned_replay(W.SMALL, 12, block, table_seed=11)
@@ -156,7 +156,7 @@ def test_learned_prior_only_gpu_samples_the_prior():
     assert st[0, 2] > 10000
 
 
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, 1024 + 256])
 def test_learned_births_in_a_batch_match_single_runs(block):
     """Instances of an uneven batch carry their own learned tables (one stays
     plain); each follows its one-chain run with the same table bit for bit."""

@@ -71,7 +71,7 @@ def _line_replay(w, nsw, block, feed_seed=31):
 
 
 @pytest.mark.parametrize("dynamic", [0, 1])
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, 1024 + 256])
 def test_line_replay_parity(block, dynamic):
     w = dataclasses.replace(W.PAPER1D, sampler=dataclasses.replace(W.PAPER1D.sampler,
                                                                    dynamic=dynamic))

@@ -38,10 +38,13 @@ def _cases():
     return [
         ("grid-dynamic", dynamic_small(), 64, 2),
         ("grid-dynamic", dynamic_small(), 256, 2),
+        ("grid-dynamic", dynamic_small(), 1024 + 256, 2),
         ("grid-static", W.SMALL, 128, 1),
         ("grid-template", small_t, 256, 1),
+        ("grid-template", small_t, 1024 + 512, 1),
         ("line-static", W.PAPER1D, 64, 1),
         ("line-dynamic", _with(W.PAPER1D, dynamic=1), 256, 1),
+        ("line-dynamic", _with(W.PAPER1D, dynamic=1), 1024 + 256, 1),
         ("latent-dynamic", _with(W.PAPER1D_LATENT, dynamic=1, k=200), 64, 1),
         ("latent-static", _with(W.PAPER1D_LATENT, k=200), 256, 1),
     ]
@@ -91,8 +94,8 @@ def test_owner_check_batch_of_uneven_worlds():
         assert np.array_equal(runs[1].read_counters(q), runs[0].read_counters(q))
 
 
-@pytest.mark.parametrize("world,block", [("grid", 64), ("grid", 256), ("line", 64),
-                                         ("line", 256)])
+@pytest.mark.parametrize("world,block", [("grid", 64), ("grid", 256), ("grid", 1024 + 256),
+                                         ("line", 64), ("line", 256)])
 def test_owner_check_reports_a_forced_breach(world, block):
     """Period 1 puts neighbouring regions in one colour (the oracle counts
     the dependent pairs); forced past the check, the run must end in

@@ -99,7 +99,7 @@ def _replay(w, nsw, block, feed_seed=77, compare_each_phase=True):
     return gpu, ref, m, s, acc
 
 
-@pytest.mark.parametrize("block", [64, 128, 256, 512])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, chromh.SPEC2, chromh.SPEC4, chromh.SPEC8])
 def test_replay_parity_small_static(block):
     say("replay", W.SMALL.name, "block", block)
     gpu, ref, m, s, acc = _replay(W.SMALL, 12, block)
@@ -111,7 +111,7 @@ def test_replay_parity_small_static(block):
     say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties, "max rel", acc.max_rel)
 
 
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, chromh.SPEC4, chromh.SPEC8])
 def test_replay_parity_dynamic(block):
     w = dynamic_small()
     say("replay", w.name, "block", block)
@@ -141,7 +141,7 @@ def test_replay_parity_full_size_large():
     fd = torch.from_numpy(feed).to(DEV)
     rows = np.random.default_rng(1).choice(w.model.nsta, 48, replace=False)
     Er = {int(j): O.event_variance_rows(m, rev, int(j), 1)[0] for j in rows}
-    for block in (64, 128, 256, 512):
+    for block in (64, 128, 256, 512, chromh.SPEC4, chromh.SPEC8):
         say("gpu sweep block", block)
         gpu = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3, block=block)
         gpu.set_feed(fd, 0)
@@ -244,12 +244,13 @@ def test_philox_mode_tracks_the_oracle():
 
 # --------------------------------------------------------------- statistics
 
-def test_prior_only_gpu_chain_samples_the_prior():
+@pytest.mark.parametrize("block", [256, chromh.SPEC4])
+def test_prior_only_gpu_chain_samples_the_prior(block):
     from scipy import stats
     w = W.SMALL
     spec = W.SamplerSpec(**dict(w.sampler.asdict(), prior_only=1, k=8))
     trace = torch.zeros((w.model.nsta, w.model.N), dtype=torch.float64, device=DEV)
-    gpu = chromh.ChromaticSampler(w.model, spec, trace, seed=2)
+    gpu = chromh.ChromaticSampler(w.model, spec, trace, seed=2, block=block)
     gpu.run_sweeps(0, 100)
     counts, xs, ms = [], [], []
     for q in range(600):
@@ -270,14 +271,15 @@ def test_prior_only_gpu_chain_samples_the_prior():
 
 # ------------------------------------------------------------ error paths
 
-def test_capacity_overflow_is_reported():
+@pytest.mark.parametrize("block", [256, chromh.SPEC4])
+def test_capacity_overflow_is_reported(block):
     w = W.SMALL
     spec = W.SamplerSpec(**dict(w.sampler.asdict(), cap=2))
     m, sp, truth, s = instance(w)
     feed = W.feed_draws(spec, 1, seed=1)
     feed[..., 0] = 0.01      # every move a birth
     feed[..., 7] = -1e300    # every birth accepted
-    gpu = chromh.ChromaticSampler(w.model, spec, torch.from_numpy(s).to(DEV), seed=1)
+    gpu = chromh.ChromaticSampler(w.model, spec, torch.from_numpy(s).to(DEV), seed=1, block=block)
     gpu.set_feed(torch.from_numpy(feed).to(DEV), 0)
     gpu.run_sweeps(0, 1)
     with pytest.raises(chromh.CmhError) as e:

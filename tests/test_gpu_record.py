@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 
 from paper_1612_00595_amd import workloads as W
 
-from gpu_cases import dynamic_small, instance, say
+from gpu_cases import compare_events, dynamic_small, instance, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,3 +51,39 @@ def test_recorded_states_match_read_back():
     gpu.run_sweeps(12, 2)
     torch.cuda.synchronize()
     assert n_last > 0
+
+
+def test_kernel_stamps_from_graph_replays():
+    """Stamps taken by the sweep kernels inside replayed graphs: one span per
+    colour and stamped sweep, positive, together no longer than the sweeps'
+    wall time, none outside the stamped range, and the chain itself is the
+    unstamped one."""
+    import time
+
+    import numpy as np
+
+    from paper_1612_00595_amd import chromh
+    w = dynamic_small()
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to("cuda:0")
+    for block in (64, 256, chromh.SPEC4):
+        say("stamps, form", block)
+        a = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=5, block=block)
+        b = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=5, block=block)
+        st = a.set_stamps(3, 4)
+        a.run_sweeps(0, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.run_sweeps(3, 4)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        a.run_sweeps(7, 2)                 # past the range: no stamps
+        spans = chromh.ChromaticSampler.stamp_seconds(st)
+        assert spans.shape == (4, a.ncolors)
+        assert np.all(spans > 0) and np.all(spans < 0.1)
+        assert spans.sum() <= el
+        b.run_sweeps(0, 9)
+        compare_events(a.read_events(0), b.read_events(0), f"form {block}")
+        assert np.array_equal(a.read_variance(0), b.read_variance(0))
+        a.close()
+        b.close()

@@ -86,7 +86,7 @@ def _check_state(gpu, ref, m, s):
     assert ll == pytest.approx(O.loglik(m, s, ev), rel=1e-10)
 
 
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, 1024 + 256])
 def test_template_replay_parity_small_static(block):
     w = templ(W.SMALL)
     say("template replay", w.name, "block", block)
@@ -96,7 +96,7 @@ def test_template_replay_parity_small_static(block):
     _check_state(gpu, ref, m, s)
 
 
-@pytest.mark.parametrize("block", [64, 256])
+@pytest.mark.parametrize("block", [64, 256, 1024 + 512])
 def test_template_replay_parity_dynamic(block):
     w = templ(dynamic_small())
     say("template replay", w.name, "block", block)

@@ -2,6 +2,7 @@
 header declares, validates arguments on the host, and its partition and
 colouring (a pure host function) agree bit for bit with the oracle."""
 import ctypes as C
+import dataclasses
 import os
 import re
 
@@ -52,6 +53,17 @@ def test_host_validation_errors():
     bad = chromh.sampler_struct(W.SMALL.sampler)
     bad.block = 96
     assert L.cmh_state_bytes(C.byref(m), C.byref(bad), 1, C.byref(nbytes)) == -1
+    # the speculative forms: 2, 4 or 8 waves per region, not with latent
+    # arrivals or the naive schedule
+    for block, want in ((chromh.SPEC2, 0), (chromh.SPEC4, 0), (chromh.SPEC8, 0),
+                        (chromh.BLOCK_SPEC + 64, -1), (chromh.BLOCK_SPEC + 1024, -1)):
+        sb = chromh.sampler_struct(W.SMALL.sampler, block)
+        assert L.cmh_state_bytes(C.byref(m), C.byref(sb), 1, C.byref(nbytes)) == want, block
+    lm = chromh.model_struct(W.PAPER1D_LATENT.model)
+    sb = chromh.sampler_struct(W.PAPER1D_LATENT.sampler, chromh.SPEC4)
+    assert L.cmh_state_bytes(C.byref(lm), C.byref(sb), 1, C.byref(nbytes)) == -1
+    sb = chromh.sampler_struct(dataclasses.replace(W.SMALL.sampler, schedule=1), chromh.SPEC4)
+    assert L.cmh_state_bytes(C.byref(m), C.byref(sb), 1, C.byref(nbytes)) == -1
     assert L.cmh_state_bytes(C.byref(m), C.byref(s), 0, C.byref(nbytes)) == -1
     # a static period that leaves dependent regions in one colour
     bad = chromh.sampler_struct(W.SMALL.sampler)
