@@ -2153,69 +2153,104 @@ __global__ void k_learned_reach(const double *__restrict__ part, int nblocks,
 
 // ------------------------------------------------------------------ rebin
 // Dynamic partition (Section 4.3.2): the sweep's offset comes from Philox;
-// each thread owns one region of the new layout and collects, in id order,
+// each wave owns one region of the new layout and collects, in id order,
 // the events of the old layout that fall into it.  With both offsets in
 // [0, w) an event's region index moves by at most one per axis, so a 5x5
-// window of old regions is always enough.
-__global__ void k_rebin(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
-                        int nitems, int par, const long long *__restrict__ sweep_ptr,
-                        int *__restrict__ err)
+// window of old regions is always enough.  The lanes take the window's
+// events side by side (flattened in window order, each old list in id
+// order), a ballot packs the ones that land in the region, and each packed
+// event's rank by (id, window position) places it, so that the list is in
+// id order as the sweep kernels expect (equal ids keep window order).
+constexpr int kRebinWaves = 4;
+
+__global__ void __launch_bounds__(64 * kRebinWaves)
+k_rebin(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
+        const long long *__restrict__ sweep_ptr, int *__restrict__ err)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nitems) return;
+    __shared__ int s_off[kRebinWaves][26];  // flat start of each old region of the window
+    __shared__ int s_ro[kRebinWaves][25];
+    __shared__ unsigned long long s_key[kRebinWaves][kMaxCap];
+    __shared__ int s_f[kRebinWaves][kMaxCap];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q = blockIdx.x * kRebinWaves + wv;
+    if (q >= nitems) return;  // whole waves; no workgroup barrier follows
     const unsigned item = items[q];
     const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
-    const Geo g = slots[slot].g;
+    const Geo &g = slots[slot].g;
     const Events src = slots[slot].ev[par], dst = slots[slot].ev[par ^ 1];
-    const int chain = 0;
     const long long sweep = *sweep_ptr;
     double offx, offy;
     sweep_offset(g.seed, slots[slot].chain, (uint32_t)sweep, g.wx, g.wy, &offx, &offy);
-    if (r == 0) {
-        dst.off[2 * chain] = offx;
-        dst.off[2 * chain + 1] = offy;
+    if (r == 0 && lane == 0) {
+        dst.off[0] = offx;
+        dst.off[1] = offy;
     }
     const int i = r % g.nrx, k = r / g.nrx;
-    const long long dbase = ((long long)chain * g.R + r) * g.cap;
-    int n = 0;
-    for (int ko = max(k - 2, 0); ko <= min(k + 2, g.gy); ++ko) {
-        for (int io = max(i - 2, 0); io <= min(i + 2, g.gx); ++io) {
-            const int ro = ko * g.nrx + io;
-            const long long sbase = ((long long)chain * g.R + ro) * g.cap;
-            const int no = src.cnt[chain * g.R + ro];
-            for (int s = 0; s < no; ++s) {
-                const double x = src.x[sbase + s], y = src.y[sbase + s];
-                if (event_region(g, offx, offy, x, y, src.t[sbase + s]) != r) continue;
-                if (n >= g.cap) {
-                    atomicOr(err, kFlagCap);
-                    continue;
-                }
-                const unsigned long long id = src.id[sbase + s];
-                int pos = n;
-                while (pos > 0 && dst.id[dbase + pos - 1] > id) {
-                    dst.x[dbase + pos] = dst.x[dbase + pos - 1];
-                    dst.y[dbase + pos] = dst.y[dbase + pos - 1];
-                    dst.t[dbase + pos] = dst.t[dbase + pos - 1];
-                    dst.m[dbase + pos] = dst.m[dbase + pos - 1];
-                    dst.id[dbase + pos] = dst.id[dbase + pos - 1];
-                    if (g.latent)
-                        for (int q = 0; q < 8; ++q)
-                            dst.da[(dbase + pos) * 8 + q] = dst.da[(dbase + pos - 1) * 8 + q];
-                    --pos;
-                }
-                dst.x[dbase + pos] = x;
-                dst.y[dbase + pos] = y;
-                dst.t[dbase + pos] = src.t[sbase + s];
-                dst.m[dbase + pos] = src.m[sbase + s];
-                dst.id[dbase + pos] = id;
-                if (g.latent)
-                    for (int q = 0; q < 8; ++q)
-                        dst.da[(dbase + pos) * 8 + q] = src.da[(sbase + s) * 8 + q];
-                ++n;
-            }
+    // the window's old regions (lane w < 25: row w / 5, column w % 5)
+    int cnt = 0, ro = 0;
+    if (lane < 25) {
+        const int ko = k - 2 + lane / 5, io = i - 2 + lane % 5;
+        if (ko >= 0 && ko <= g.gy && io >= 0 && io <= g.gx) {
+            ro = ko * g.nrx + io;
+            cnt = src.cnt[ro];
         }
     }
-    dst.cnt[chain * g.R + r] = n;
+    const int start = wave_excl_prefix_small<7>(cnt);
+    const int total = wave_sum_i32(cnt);
+    if (lane < 25) {
+        s_off[wv][lane] = start;
+        s_ro[wv][lane] = ro;
+    }
+    if (lane == 25) s_off[wv][25] = total;
+    __builtin_amdgcn_wave_barrier();
+    int n = 0;
+    for (int base = 0; base < total; base += 64) {
+        const int f = base + lane;
+        bool take = false;
+        unsigned long long id = 0;
+        if (f < total) {
+            int w = 0;
+            while (w < 24 && s_off[wv][w + 1] <= f) ++w;
+            const long long e = (long long)s_ro[wv][w] * g.cap + (f - s_off[wv][w]);
+            take = event_region(g, offx, offy, src.x[e], src.y[e], src.t[e]) == r;
+            id = src.id[e];
+        }
+        const unsigned long long m = __ballot(take);
+        const int pos = n + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (take && pos < kMaxCap) {
+            s_key[wv][pos] = id;
+            s_f[wv][pos] = f;
+        }
+        n += __popcll(m);
+    }
+    if (n > g.cap) {
+        if (lane == 0) atomicOr(err, kFlagCap);
+        n = g.cap;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const unsigned long long key = s_key[wv][lane];
+        const int f = s_f[wv][lane];
+        int rank = 0;
+        for (int o = 0; o < n; ++o) {
+            const unsigned long long ko = s_key[wv][o];
+            rank += ko < key || (ko == key && s_f[wv][o] < f);
+        }
+        int w = 0;
+        while (w < 24 && s_off[wv][w + 1] <= f) ++w;
+        const long long e = (long long)s_ro[wv][w] * g.cap + (f - s_off[wv][w]);
+        const long long d = (long long)r * g.cap + rank;
+        dst.x[d] = src.x[e];
+        dst.y[d] = src.y[e];
+        dst.t[d] = src.t[e];
+        dst.m[d] = src.m[e];
+        dst.id[d] = key;
+        if (g.latent)
+            for (int c = 0; c < 8; ++c) dst.da[d * 8 + c] = src.da[e * 8 + c];
+    }
+    if (lane == 0) dst.cnt[r] = n;
 }
 
 // ------------------------------------------------------- refresh / loglik
@@ -2785,7 +2820,8 @@ hipError_t launch_learned_prep(const double *w, const double *tab, int ntau, int
 hipError_t launch_rebin(const Slot *slots, const unsigned *items_all, int nall, int par,
                         const long long *sweep_ptr, int *err, hipStream_t s)
 {
-    k_rebin<<<(nall + 127) / 128, 128, 0, s>>>(slots, items_all, nall, par, sweep_ptr, err);
+    k_rebin<<<(nall + kRebinWaves - 1) / kRebinWaves, 64 * kRebinWaves, 0, s>>>(
+        slots, items_all, nall, par, sweep_ptr, err);
     return hipGetLastError();
 }
 
