@@ -109,21 +109,29 @@ def mixture_nll(o: np.ndarray, z: np.ndarray):
     return -logp, g
 
 
-def loss_and_grads(P: dict, X: np.ndarray, Z: np.ndarray, bf16: bool = True):
-    """Mean loss and gradients of every parameter (dict like P)."""
+def loss_and_grads(P: dict, X: np.ndarray, Z: np.ndarray, bf16: bool = True,
+                   parts: bool = False):
+    """Mean loss and gradients of every parameter (dict like P).  parts:
+    also the operands of each weight gradient, {layer: (output gradient,
+    input activation)}, so that a test can bound a BF16 implementation's
+    error element by element."""
     r = to_bf16 if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
     o, Zs, As, W = forward(P, X, bf16)
     M = X.shape[0]
     per_row, g = mixture_nll(o, Z)
     dO = r(g / M)
     G = {"W4": dO.T @ As[3], "b4": dO.sum(0)}
+    ops = {4: (dO, As[3])}
     dnext = dO
     for l in (2, 1, 0):
         dA = dnext @ W[l + 1]
         dH = r(dA * gelu_grad(Zs[l]))
         G[f"W{l + 1}"] = dH.T @ As[l]
         G[f"b{l + 1}"] = dH.sum(0)
+        ops[l + 1] = (dH, As[l])
         dnext = dH
+    if parts:
+        return float(per_row.mean()), per_row, G, ops
     return float(per_row.mean()), per_row, G
 
 
