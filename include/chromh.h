@@ -435,6 +435,17 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
                      uint32_t seed, void *trace_dev, int32_t trace_dtype,
                      void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
+/* The same simulator for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument; the truth table is staged in a library-owned device
+ * array of 8 MiB per device (held until the process ends), so a truth
+ * layout needing more (cmh_simulate_bytes) is CMH_EINVAL.  The caller still
+ * owns trace_dev.  Every call on one device uses the same array: calls that
+ * overlap on one device (other host threads) race.  Synchronises. */
+int32_t cmh_simulate_noalloc(const cmh_model *model, const cmh_event *truth_host,
+                             int64_t n_events, uint32_t seed, void *trace_dev,
+                             int32_t trace_dtype, void *hip_stream);
+
 /* Draw records [count][width] (width 8, or 16 for learned births) that
  * chain `chain` takes for moves j0 .. j0+count-1 of region `region` in sweep
  * `sweep` (the same layout as the feed), computed on the device into

@@ -66,7 +66,8 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
            "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init",
            "cmh_batch_learned_bytes", "cmh_batch_set_learned", "cmh_checkpoint_bytes", "cmh_save",
-           "cmh_load", "cmh_set_stamps", "cmh_stamp_rate", "cmh_log_posterior", "cmh_set_logprob"]
+           "cmh_load", "cmh_set_stamps", "cmh_stamp_rate", "cmh_log_posterior", "cmh_set_logprob",
+           "cmh_simulate_noalloc"]
 
 _lib = None
 
@@ -99,6 +100,7 @@ def lib():
         "cmh_autotune": ([P, I64, I32, P], I32),
         "cmh_time_phases": ([P, I64, I64, P, P], I32),
         "cmh_set_stamps": ([P, P, I64, I64], I32),
+        "cmh_simulate_noalloc": ([P, P, I64, U32, P, I32, P], I32),
         "cmh_log_posterior": ([P, I32, P, P], I32),
         "cmh_set_logprob": ([P, P, I64, I64], I32),
         "cmh_stamp_rate": ([I32, P], I32),

@@ -1887,22 +1887,18 @@ int32_t cmh_simulate_bytes(const cmh_model *model, const cmh_event *truth_host, 
     return CMH_OK;
 }
 
-int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_t n_events,
-                     uint32_t seed, void *trace_dev, int32_t trace_dtype, void *workspace_dev,
-                     size_t workspace_bytes, void *hip_stream)
+namespace {
+
+// The simulator on a laid-out truth table: the table is staged in `ws` (at
+// least carve_truth bytes of device memory), then every station's trace is
+// written.  Synchronises.
+int32_t simulate_into(const TruthLayout &L, uint32_t seed, void *trace_dev, int32_t trace_dtype,
+                      void *ws, hipStream_t s)
 {
-    TruthLayout L;
-    int32_t rc = truth_layout(model, truth_host, n_events, &L);
-    if (rc) return rc;
-    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
-        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
-    if (!trace_dev || !workspace_dev) return fail(CMH_EINVAL, "NULL device buffer");
     const Geo &g = L.g;
-    const size_t need = carve_truth(g, nullptr, nullptr, nullptr);
-    if (workspace_bytes < need) return fail(CMH_EINVAL, "simulator workspace too small");
     Events ev;
     int *err = nullptr;
-    carve_truth(g, (char *)workspace_dev, &ev, &err);
+    carve_truth(g, (char *)ws, &ev, &err);
     const size_t slots = (size_t)g.R * g.cap;
     std::vector<int> cnt(g.R, 0);
     std::vector<double> x(slots, 0), y(slots, 0), t(slots, 0), m(slots, 0), off(2, 0.0);
@@ -1910,15 +1906,14 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
     std::vector<double> da(g.latent ? slots * 8 : 0, 0.0);
     for (int r = 0; r < g.R; ++r) {
         cnt[r] = (int)L.cells[r].size();
-        for (size_t s = 0; s < L.cells[r].size(); ++s) {
-            const size_t a = (size_t)r * g.cap + s;
-            const cmh_event &e = L.cells[r][s];
+        for (size_t q = 0; q < L.cells[r].size(); ++q) {
+            const size_t a = (size_t)r * g.cap + q;
+            const cmh_event &e = L.cells[r][q];
             x[a] = e.x; y[a] = e.y; t[a] = e.t; m[a] = e.m; id[a] = e.id;
             if (g.latent)
                 for (int c = 0; c < g.nsx; ++c) da[a * 8 + c] = e.da[c];
         }
     }
-    hipStream_t s = (hipStream_t)hip_stream;
     HIPCHK(hipMemcpyAsync(ev.cnt, cnt.data(), g.R * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ev.x, x.data(), slots * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ev.y, y.data(), slots * 8, hipMemcpyHostToDevice, s));
@@ -1934,6 +1929,69 @@ int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_
     HIPCHK(hipMemcpy(&flags, err, sizeof(int), hipMemcpyDeviceToHost));
     if (flags) return fail(CMH_ESTATE, "simulator tile capacity exceeded");
     return CMH_OK;
+}
+
+// Scratch of the no-allocation simulator: one array per device, reached
+// through the address hipGetSymbolAddress returns on that device (the
+// symbol's name is a host-side stand-in).  Calls on one device share it.
+constexpr size_t kSimScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kSimScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> device address of `scratch`
+
+int32_t scratch_address(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(CMH_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return CMH_OK;
+}
+
+}  // namespace
+
+int32_t cmh_simulate(const cmh_model *model, const cmh_event *truth_host, int64_t n_events,
+                     uint32_t seed, void *trace_dev, int32_t trace_dtype, void *workspace_dev,
+                     size_t workspace_bytes, void *hip_stream)
+{
+    TruthLayout L;
+    int32_t rc = truth_layout(model, truth_host, n_events, &L);
+    if (rc) return rc;
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    if (!trace_dev || !workspace_dev) return fail(CMH_EINVAL, "NULL device buffer");
+    const size_t need = carve_truth(L.g, nullptr, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(CMH_EINVAL, "simulator workspace too small");
+    return simulate_into(L, seed, trace_dev, trace_dtype, workspace_dev, (hipStream_t)hip_stream);
+}
+
+int32_t cmh_simulate_noalloc(const cmh_model *model, const cmh_event *truth_host,
+                             int64_t n_events, uint32_t seed, void *trace_dev,
+                             int32_t trace_dtype, void *hip_stream)
+{
+    TruthLayout L;
+    int32_t rc = truth_layout(model, truth_host, n_events, &L);
+    if (rc) return rc;
+    if (trace_dtype != CMH_F32 && trace_dtype != CMH_F64)
+        return fail(CMH_EINVAL, "trace_dtype must be CMH_F32 or CMH_F64");
+    if (!trace_dev) return fail(CMH_EINVAL, "NULL device buffer");
+    const size_t need = carve_truth(L.g, nullptr, nullptr, nullptr);
+    if (need > kSimScratchBytes)
+        return fail(CMH_EINVAL, "truth table needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the " +
+                                    std::to_string(kSimScratchBytes) + " this call holds");
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    return simulate_into(L, seed, trace_dev, trace_dtype, ws, (hipStream_t)hip_stream);
 }
 
 int32_t cmh_move_draws(uint32_t seed, uint32_t chain, uint32_t sweep, uint32_t region, uint32_t j0,
