@@ -118,6 +118,7 @@ typedef struct {
 } cmh_model;
 
 #define CMH_BLOCK_SPEC 1024
+#define CMH_BLOCK_PERSIST (2048 + 64)
 
 typedef struct {
     int32_t grid_x, grid_y;     /* regions per axis of the unshifted grid */
@@ -136,7 +137,13 @@ typedef struct {
                                    region, each taking one of the region's next moves from
                                    the same state, the first accepted one committed (the
                                    chain is the sequential one; not with latent arrivals
-                                   or the naive schedule); 0 = 256 */
+                                   or the naive schedule), or CMH_BLOCK_PERSIST: the
+                                   one-wave-per-region form as one persistent launch per
+                                   sweep over every colour, each chain's (instance's)
+                                   colours ordered by its own colour counter, different
+                                   chains overlapping (dynamic partitions only, not with
+                                   latent arrivals or the naive schedule; cmh_sweep_color
+                                   then runs the whole sweep at colour 0); 0 = 256 */
     int32_t schedule;           /* 0: chromatic (Algorithm 4).  1: naive parallel MH
                                    (Algorithm 3, the paper's negative control): every region
                                    in one phase, each evaluating against the phase-start
@@ -152,7 +159,10 @@ typedef struct {
                                    colour independent).  Chromatic schedule only.  Bit 1
                                    (with bit 0 and a period): take the period without the
                                    independence check, so that a test can force a breach
-                                   for the owner check to catch.  0 for production runs. */
+                                   for the owner check to catch.  Bit 2: the persistent
+                                   form's colour-counter waits give up at once (an unmet
+                                   wait latches CMH_ESTATE), so that a test can reach the
+                                   wait's error path.  0 for production runs. */
     /* Latent arrivals only (0 otherwise).  p_arrival: the arrival-time move
      * of Section 3 (one event, one station drawn uniformly, its offset plus
      * step_arrival times a standard normal; the offset prior enters the

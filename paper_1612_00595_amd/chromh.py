@@ -166,6 +166,8 @@ def model_struct(spec: ModelSpec) -> CmhModel:
 # speculative form with 2, 4 or 8 waves per region (include/chromh.h)
 BLOCK_SPEC = 1024
 SPEC2, SPEC4, SPEC8 = BLOCK_SPEC + 128, BLOCK_SPEC + 256, BLOCK_SPEC + 512
+# the one-wave-per-region form as one persistent launch per sweep
+PERSIST = 2048 + 64
 
 
 def sampler_struct(spec: SamplerSpec, block: int = 0) -> CmhSampler:

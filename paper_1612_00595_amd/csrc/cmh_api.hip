@@ -284,11 +284,16 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
     if (!(s->step_xy >= 0.0) || !(s->step_t >= 0.0) || !(s->step_m >= 0.0))
         return fail(CMH_EINVAL, "step sizes must be non-negative");
     if (s->block != 0 && s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512 &&
-        !cmh::is_spec_block(s->block))
-        return fail(CMH_EINVAL, "block must be 0, 64, 128, 256, 512 or CMH_BLOCK_SPEC + 128, "
-                                "256 or 512");
+        !cmh::is_spec_block(s->block) && s->block != cmh::kPersist)
+        return fail(CMH_EINVAL, "block must be 0, 64, 128, 256, 512, CMH_BLOCK_SPEC + 128, "
+                                "256 or 512, or CMH_BLOCK_PERSIST");
     if (s->dynamic != 0 && s->dynamic != 1) return fail(CMH_EINVAL, "dynamic must be 0 or 1");
     if (s->refresh_every < 0) return fail(CMH_EINVAL, "refresh_every must be non-negative");
+    // A persistent launch on a static partition (whose edge regions have no
+    // area and end their item at once) did not finish on the device once;
+    // the cause is not known, so that combination is refused.
+    if (s->block == cmh::kPersist && s->dynamic != 1)
+        return fail(CMH_EINVAL, "the persistent form runs dynamic partitions only");
     if (s->prior_only != 0 && s->prior_only != 1)
         return fail(CMH_EINVAL, "prior_only must be 0 or 1");
     if (s->schedule != 0 && s->schedule != 1) return fail(CMH_EINVAL, "schedule must be 0 or 1");
@@ -305,7 +310,7 @@ int32_t make_geo(const cmh_model *m, const cmh_sampler *s, Geo *g)
         if (s->schedule != 0)
             return fail(CMH_EINVAL, "latent arrivals run the chromatic schedule");
     }
-    if (s->debug & ~3) return fail(CMH_EINVAL, "debug takes bits 0 and 1 only");
+    if (s->debug & ~7) return fail(CMH_EINVAL, "debug takes bits 0, 1 and 2 only");
     if ((s->debug & 1) && s->schedule != 0)
         return fail(CMH_EINVAL, "the owner check needs the chromatic schedule");
     if ((s->debug & 2) && !(s->debug & 1 && s->period > 0))
@@ -442,6 +447,9 @@ struct cmh_state {
     int refresh_every = 0;   // exact refresh after every this many sweeps (0: never)
     double *lp_rec = nullptr;  // log-probability records [sweeps][slot][2] (NULL: off)
     long long lp_first = 0, lp_n = 0;
+    int *pq_ctr = nullptr;       // persistent form: ticket, then per slot completed items
+    unsigned *pq_wait = nullptr; // persistent form: per item (colour order) its wait target
+    long long spin_limit = 1LL << 22;
     unsigned long long *stamps = nullptr;  // sweep-kernel time stamps (NULL: off)
     long long stamp_first = 0, stamp_n = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -487,6 +495,8 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
     cmh::Slot *slots = c.take<cmh::Slot>((size_t)chains);
     unsigned *items_all = c.take<unsigned>((size_t)chains * g.R);
     unsigned *items_col = c.take<unsigned>((size_t)chains * g.R);
+    int *pq_ctr = c.take<int>((size_t)chains + 1);
+    unsigned *pq_wait = c.take<unsigned>((size_t)chains * g.R);
     unsigned long long *owner =
         g.owner ? c.take<unsigned long long>((size_t)chains * g.nsta * (size_t)g.N) : nullptr;
     if (st) {
@@ -494,6 +504,8 @@ size_t carve_state(const Geo &g, int chains, char *base, cmh_state *st)
         st->slots_d = slots;
         st->items_all = items_all;
         st->items_col = items_col;
+        st->pq_ctr = pq_ctr;
+        st->pq_wait = pq_wait;
         st->draws = draws;
         st->draws2 = draws2;
         st->E = E;
@@ -538,6 +550,20 @@ cmh::Slot chain_slot(const cmh_state *st, int c)
     return sl;
 }
 
+// Persistent form: for each item of the colour-ordered list, how many items
+// of its own slot lie in lower colours (the slot's colour counter must reach
+// that count before the item may start).
+std::vector<unsigned> wait_targets(const std::vector<unsigned> &col, const std::vector<int> &off,
+                                   const std::vector<int> &cnt, int nslots)
+{
+    std::vector<unsigned> wait(col.size(), 0u), done(nslots, 0u);
+    for (size_t c = 0; c < off.size(); ++c) {
+        for (int q = off[c]; q < off[c] + cnt[c]; ++q) wait[q] = done[col[q] >> 16];
+        for (int q = off[c]; q < off[c] + cnt[c]; ++q) ++done[col[q] >> 16];
+    }
+    return wait;
+}
+
 // Host slot table and work items of a single-instance state, uploaded to
 // its workspace (synchronously: the host vectors are temporaries).
 int32_t upload_slots(cmh_state *st)
@@ -571,6 +597,9 @@ int32_t upload_slots(cmh_state *st)
                      hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(st->items_col, col.data(), sizeof(unsigned) * col.size(),
                      hipMemcpyHostToDevice));
+    const std::vector<unsigned> wait = wait_targets(col, st->col_off, st->col_n, st->nslots);
+    HIPCHK(hipMemcpy(st->pq_wait, wait.data(), sizeof(unsigned) * wait.size(),
+                     hipMemcpyHostToDevice));
     return CMH_OK;
 }
 
@@ -600,6 +629,8 @@ int32_t sync_and_check(cmh_state *st)
         if (flags & cmh::kFlagNan) return fail(CMH_ENAN, "NaN or Inf in a likelihood change");
         if (flags & cmh::kFlagSta)
             return fail(CMH_ESTATE, "a region holds more stations than learned births allow");
+        if (flags & cmh::kFlagWait)
+            return fail(CMH_ESTATE, "a persistent-form wait for a colour counter timed out");
         return fail(CMH_ESTATE, "footprint or tile capacity exceeded");
     }
     return CMH_OK;
@@ -648,11 +679,24 @@ hipError_t enqueue_phase(cmh_state *st, int color, bool start, hipStream_t s)
         if (e) return e;
     }
     const cmh::StampArg sa{st->stamps, st->stamp_first, st->stamp_n, color, st->g.ncolors};
-    hipError_t e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color],
-                                     st->col_n[color], st->cur, st->f64, st->sweep_ctr, st->logp,
-                                     st->log_first, st->log_n, st->err, st->block,
-                                     st->g.naive ? st->naive_elems : 0, st->g.latent,
-                                     st->owner_any, sa, s);
+    hipError_t e = hipSuccess;
+    if (st->block == cmh::kPersist) {
+        // every colour in one launch at colour 0; later colours launch nothing
+        if (color == 0) {
+            const cmh::PersistArg pq{st->pq_ctr, (unsigned *)(st->pq_ctr + 1), st->pq_wait,
+                                     st->spin_limit};
+            int total = 0;
+            for (int c = 0; c < st->g.ncolors; ++c) total += st->col_n[c];
+            e = cmh::launch_sweep_persist(st->slots_d, st->items_col, total, st->cur, st->f64,
+                                          st->sweep_ctr, st->logp, st->log_first, st->log_n,
+                                          st->err, st->owner_any, sa, pq, st->nslots, s);
+        }
+    } else {
+        e = cmh::launch_sweep(st->slots_d, st->items_col + st->col_off[color], st->col_n[color],
+                              st->cur, st->f64, st->sweep_ctr, st->logp, st->log_first,
+                              st->log_n, st->err, st->block, st->g.naive ? st->naive_elems : 0,
+                              st->g.latent, st->owner_any, sa, s);
+    }
     if (!e && st->g.naive)  // the merged events' variance after the single naive phase
         e = cmh::launch_refresh_slots(st->slots_d, st->nslots, st->refresh_max, st->cur,
                                       st->f64, st->err, s);
@@ -830,6 +874,7 @@ int32_t cmh_init_state(const cmh_model *model, const cmh_sampler *sampler, const
     st->trace = trace_dev;
     st->block = g.naive ? 64 : (sampler->block ? sampler->block : 256);
     st->refresh_every = sampler->refresh_every;
+    st->spin_limit = (sampler->debug & 4) ? 0 : st->spin_limit;
     carve_state(g, n_chains, (char *)workspace_dev, st);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
@@ -1399,9 +1444,11 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
         g.latent ? std::vector<int>{64, 256}
                  : std::vector<int>{64, 128, 256, 512, cmh::kSpecBase + 128,
                                     cmh::kSpecBase + 256, cmh::kSpecBase + 512};
+    std::vector<int> forms = cands;
+    if (g.dynamic) forms.push_back(cmh::kPersist);
     int best = st->block;
     float best_ms = 1e30f;
-    for (int b : cands) {
+    for (int b : forms) {
         st->block = b;
         rc = cmh_run_sweeps(st, first_sweep, 1, hip_stream);  // warm-up, builds graphs
         if (!rc) rc = restore();
@@ -1647,7 +1694,8 @@ int32_t plan_batch(int32_t n, const cmh_model *models, const cmh_sampler *sample
 // shared sweep counter, error word, slot table and work items.
 size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots,
                    long long **sweep, int **err, cmh::Slot **slots_d, unsigned **items_all,
-                   unsigned **items_col, double **partials = nullptr, double **llout = nullptr)
+                   unsigned **items_col, double **partials = nullptr, double **llout = nullptr,
+                   int **pq_ctr = nullptr, unsigned **pq_wait = nullptr)
 {
     Carver c{base};
     long long total_r = 0;
@@ -1675,6 +1723,10 @@ size_t carve_batch(const BatchPlan &P, char *base, std::vector<cmh::Slot> *slots
     cmh::Slot *sd = c.take<cmh::Slot>(P.g.size());
     unsigned *ia = c.take<unsigned>((size_t)total_r);
     unsigned *ic = c.take<unsigned>((size_t)total_r);
+    int *pc = c.take<int>(P.g.size() + 1);
+    unsigned *pw = c.take<unsigned>((size_t)total_r);
+    if (pq_ctr) *pq_ctr = pc;
+    if (pq_wait) *pq_wait = pw;
     if (sweep) *sweep = sw;
     if (err) *err = er;
     if (slots_d) *slots_d = sd;
@@ -1724,8 +1776,10 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
     st->block = P.head.naive ? 64 : (samplers[0].block ? samplers[0].block : 256);
     st->slots_h.resize(n_instances);
     carve_batch(P, (char *)workspace_dev, &st->slots_h, &st->sweep_ctr, &st->err, &st->slots_d,
-                &st->items_all, &st->items_col, &st->partials, &st->llout);
+                &st->items_all, &st->items_col, &st->partials, &st->llout, &st->pq_ctr,
+                &st->pq_wait);
     st->refresh_every = samplers[0].refresh_every;
+    st->spin_limit = (samplers[0].debug & 4) ? 0 : st->spin_limit;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking);
     std::vector<unsigned> all, col;
@@ -1777,6 +1831,16 @@ int32_t cmh_batch_init(int32_t n_instances, const cmh_model *models, const cmh_s
         if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
         delete st;
         return fail(CMH_EHIP, std::string("batch init: ") + hipGetErrorString(e));
+    }
+    {
+        const std::vector<unsigned> wait = wait_targets(col, st->col_off, st->col_n, n_instances);
+        e = hipMemcpy(st->pq_wait, wait.data(), sizeof(unsigned) * wait.size(),
+                      hipMemcpyHostToDevice);
+        if (e) {
+            if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
+            delete st;
+            return fail(CMH_EHIP, std::string("batch init: ") + hipGetErrorString(e));
+        }
     }
     *out = st;
     return CMH_OK;

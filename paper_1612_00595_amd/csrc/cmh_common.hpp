@@ -22,7 +22,10 @@ constexpr int kMaxTileEvents = 640;  // events reaching one station tile
 constexpr int kMaxRegSta = 16;       // stations of one region, learned births
 constexpr int kNaiveMax = 2048;      // stations x samples of an instance, naive schedule
 
-enum : int { kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16, kFlagRace = 32 };
+enum : int {
+    kFlagCap = 1, kFlagNan = 2, kFlagSeg = 4, kFlagTile = 8, kFlagSta = 16, kFlagRace = 32,
+    kFlagWait = 64  // persistent form: a colour-counter wait exceeded its spin limit
+};
 
 // Per-chain statistics: [3 t + 0..2] attempted / evaluated / accepted moves of
 // type t < 5, [15] footprint samples evaluated, [16] footprint samples
@@ -88,12 +91,25 @@ struct Learned {
 
 // Sweep-kernel forms (the sampler's block): 64, one wave per work item; 128,
 // 256, 512, the latency form with that workgroup size; kSpecBase + 64 D,
-// the speculative form with D = 2, 4 or 8 waves per work item.
+// the speculative form with D = 2, 4 or 8 waves per work item; kPersist,
+// the wave form as one persistent launch per sweep over every colour.
 constexpr int kSpecBase = 1024;
+constexpr int kPersist = 2048 + 64;
 __host__ __device__ constexpr bool is_spec_block(int b)
 {
     return b == kSpecBase + 128 || b == kSpecBase + 256 || b == kSpecBase + 512;
 }
+
+// Persistent form's queue: a ticket counter, per slot the items of the
+// current sweep it has completed, per item (colour order) the count of its
+// slot's items in lower colours it waits for, and the wait's spin limit.
+// ticket and done are cleared before every launch.
+struct PersistArg {
+    int *ticket;
+    unsigned *done;
+    const unsigned *wait;
+    long long spin_limit;
+};
 
 // Work items of the sweep kernels: region r of slot s packed as (s << 16) | r.
 constexpr int kMaxItemRegions = 65536;

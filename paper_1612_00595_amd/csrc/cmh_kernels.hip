@@ -12,6 +12,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace cmh {
 
 // ------------------------------------------------------------------ draws
@@ -1401,13 +1403,13 @@ __device__ void wave_write(const Geo &g, double *__restrict__ E, const Seg *sg,
 // LAT: latent arrival times (line model), as in the latency form: each
 // wave keeps its region's arrival offsets, its draws 8..15 and the joint
 // move's scratch in LDS (about 27 KB more per workgroup, two waves per SIMD).
-template <typename TraceT, bool NAIVE, bool LAT = false, bool OWN = false>
+template <typename TraceT, bool NAIVE, bool LAT = false, bool OWN = false, bool PER = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NAIVE ? 1 : (LAT ? 2 : 4))))
 k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int nitems, int par,
              const long long *__restrict__ sweep_ptr, double *__restrict__ logp,
              long long log_first, long long log_n, int *__restrict__ err, int naive_elems,
-             StampArg sa)
+             StampArg sa, PersistArg pq)
 {
     __shared__ double s_log[kMaxCap + 2];
     __shared__ double s_T[4][kMaxTs];
@@ -1425,6 +1427,14 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     __shared__ double s_draw2[LAT ? 4 : 1][LAT ? kWaveDraws : 1][8];
     __shared__ double s_daw[LAT ? 4 : 1][LAT ? kMaxCap : 1][8];
     __shared__ LatentLds s_latw[LAT ? 4 : 1];
+    // the instance's constants live in LDS: held in registers they would
+    // halve the waves a CU can hold
+    __shared__ Geo s_g[4];
+    __shared__ Learned s_L[4];
+    __shared__ double s_rc[4][10];
+    // move counters of each wave (lane 0 counts): [3 t + 0..2], then the
+    // footprint samples read and written
+    __shared__ unsigned long long s_cnt[4][kStats];
 
     const int tid = threadIdx.x, lane = tid & 63;
     // the wave's index, and everything derived from it (work item, slot,
@@ -1432,230 +1442,269 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < kMaxCap + 2; q += 256) s_log[q] = log((double)q);
     __syncthreads();  // the only barrier: every wave passes it before any leaves
-    const int it = blockIdx.x * 4 + wv;
-    if (it >= nitems) return;
-    const unsigned item = items[it];
-    const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
-    // the instance's constants live in LDS: held in registers they would
-    // halve the waves a CU can hold
-    __shared__ Geo s_g[4];
-    if (lane == 0) s_g[wv] = slots[slot].g;
-    __builtin_amdgcn_wave_barrier();
-    const Geo &g = s_g[wv];
-    const Events ev = slots[slot].ev[par];
-    const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
-    double *__restrict__ E = slots[slot].E;
-    const double *__restrict__ draws = slots[slot].draws;
-    unsigned long long *__restrict__ stats = slots[slot].stats;
-    __shared__ Learned s_L[4];
-    if (lane == 0) s_L[wv] = slots[slot].L;
-    __builtin_amdgcn_wave_barrier();
-    const Learned &L = s_L[wv];
-    const int i = r % g.nrx, kk = r / g.nrx;
-    const long long sweep = *sweep_ptr;
-    if (lane == 0) stamp_at(sa, sweep, 0);
-    unsigned long long *const own = OWN ? slots[slot].owner : nullptr;  // debug owner check
-    const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
-    __shared__ double s_rc[4][10];
-    if (lane == 0) {
-        double *c = s_rc[wv];
-        c[0] = ev.off[0]; c[1] = ev.off[1];
-        const RegionBox b = region_box(g, c[0], c[1], i, kk);
-        c[2] = b.x0; c[3] = b.x1; c[4] = b.y0; c[5] = b.y1; c[6] = b.area;
-        c[7] = log(b.lamR);
-        c[8] = log(g.pb); c[9] = log(g.pd);
-    }
-    __builtin_amdgcn_wave_barrier();
-    const double *rc_ = s_rc[wv];
-    const double &offx = rc_[0], &offy = rc_[1], &x0 = rc_[2], &x1 = rc_[3], &y0 = rc_[4],
-                 &y1 = rc_[5], &area = rc_[6], &log_lamR = rc_[7], &log_pb = rc_[8],
-                 &log_pd = rc_[9];
-    if (!(area > 0.0)) return;
-
-    double *sT = s_T[wv];
-    double *ex = s_ex[wv], *ey = s_ey[wv], *et = s_et[wv], *em = s_em[wv];
-    unsigned long long *eid = s_id[wv];
-    const long long base = (long long)r * g.cap;
-    int n = ev.cnt[r];
-    for (int s = lane; s < n; s += 64) {
-        ex[s] = ev.x[base + s]; ey[s] = ev.y[base + s];
-        et[s] = ev.t[base + s]; em[s] = ev.m[base + s];
-        eid[s] = ev.id[base + s];
-    }
-    double (*da)[8] = nullptr;
-    LatentLds *lat = nullptr;
-    const double *dsrc2 = nullptr;
-    if constexpr (LAT) {
-        da = s_daw[wv];
-        lat = &s_latw[wv];
-        for (int q = lane; q < n * 8; q += 64) da[q >> 3][q & 7] = ev.da[base * 8 + q];
-        dsrc2 = slots[slot].draws2 + (long long)r * g.k * 8;
-    }
-    for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
-    int flags = 0;
-    double *Ew = E;  // the variance (or residual) this wave reads and writes
-    if constexpr (NAIVE) {
-        // Algorithm 3: the region accepts against its own events alone, so
-        // its private variance starts from no event (the trace itself as the
-        // residual, under templates) and takes in each of its events in turn
-        extern __shared__ double s_pe[];  // 4 x naive_elems, sized at launch
-        double *pe = s_pe + (long long)wv * naive_elems;
-        for (int q = lane; q < g.nsta * g.N; q += 64) pe[q] = g.tmpl ? (double)trace[q] : 0.0;
+    // one work item (slot, region) of this wave: k moves in sequence
+    auto item_body = [&](const int it) {
+        const unsigned item = items[it];
+        const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu);
+        if (lane == 0) s_g[wv] = slots[slot].g;
         __builtin_amdgcn_wave_barrier();
-        for (int q = 0; q < n; ++q) {
-            int nseg = 0, S = 0, fl = 0;
-            footprint(g, lane, false, 0.0, 0.0, 0.0, 0.0, true, ex[q], ey[q], et[q], em[q],
-                      s_seg[wv][0], &s_six[wv][0], g.sx, &nseg, &S, &fl);
-            __builtin_amdgcn_wave_barrier();
-            if (__ballot(fl != 0) != 0ull) flags |= kFlagSeg;
-            else wave_write<false>(g, pe, s_seg[wv][0], s_six[wv][0], nseg, S, sT, lane);
-            __builtin_amdgcn_wave_barrier();
+        const Geo &g = s_g[wv];
+        const Events ev = slots[slot].ev[par];
+        const TraceT *__restrict__ trace = (const TraceT *)slots[slot].trace;
+        double *__restrict__ E = slots[slot].E;
+        const double *__restrict__ draws = slots[slot].draws;
+        unsigned long long *__restrict__ stats = slots[slot].stats;
+        if (lane == 0) s_L[wv] = slots[slot].L;
+        __builtin_amdgcn_wave_barrier();
+        const Learned &L = s_L[wv];
+        const int i = r % g.nrx, kk = r / g.nrx;
+        const long long sweep = *sweep_ptr;
+        if (lane == 0) stamp_at(sa, sweep, 0);
+        unsigned long long *const own = OWN ? slots[slot].owner : nullptr;  // debug owner check
+        const unsigned long long tag = OWN ? owner_tag(g, sweep, i, kk, r) : 0ull;
+        if (lane == 0) {
+            double *c = s_rc[wv];
+            c[0] = ev.off[0]; c[1] = ev.off[1];
+            const RegionBox b = region_box(g, c[0], c[1], i, kk);
+            c[2] = b.x0; c[3] = b.x1; c[4] = b.y0; c[5] = b.y1; c[6] = b.area;
+            c[7] = log(b.lamR);
+            c[8] = log(g.pb); c[9] = log(g.pd);
         }
-        Ew = pe;
-    }
-    if (lane == 0) {
-        RegionLearned rl;
-        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
-        if (L.tab != nullptr) {
-            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta[wv],
-                                           kMaxRegSta);
-            if (ns > kMaxRegSta) {
-                flags |= kFlagSta;
-            } else if (ns > 0) {
-                double W = 0.0;
-                for (int q = 0; q < ns; ++q)
-                    W = W + L.cum[(long long)s_lsta[wv][q] * L.ntau + L.ntau - 1];
-                rl.ns = ns; rl.W = W; rl.pl = L.pl;
+        __builtin_amdgcn_wave_barrier();
+        const double *rc_ = s_rc[wv];
+        const double &offx = rc_[0], &offy = rc_[1], &x0 = rc_[2], &x1 = rc_[3], &y0 = rc_[4],
+                     &y1 = rc_[5], &area = rc_[6], &log_lamR = rc_[7], &log_pb = rc_[8],
+                     &log_pd = rc_[9];
+        if (!(area > 0.0)) return;
+
+        double *sT = s_T[wv];
+        double *ex = s_ex[wv], *ey = s_ey[wv], *et = s_et[wv], *em = s_em[wv];
+        unsigned long long *eid = s_id[wv];
+        const long long base = (long long)r * g.cap;
+        int n = ev.cnt[r];
+        for (int s = lane; s < n; s += 64) {
+            ex[s] = ev.x[base + s]; ey[s] = ev.y[base + s];
+            et[s] = ev.t[base + s]; em[s] = ev.m[base + s];
+            eid[s] = ev.id[base + s];
+        }
+        double (*da)[8] = nullptr;
+        LatentLds *lat = nullptr;
+        const double *dsrc2 = nullptr;
+        if constexpr (LAT) {
+            da = s_daw[wv];
+            lat = &s_latw[wv];
+            for (int q = lane; q < n * 8; q += 64) da[q >> 3][q & 7] = ev.da[base * 8 + q];
+            dsrc2 = slots[slot].draws2 + (long long)r * g.k * 8;
+        }
+        for (int q = lane; q < g.ts; q += 64) sT[q] = exp(-(g.tmpl ? 1.0 : 2.0) * (double)q / g.decay);
+        int flags = 0;
+        double *Ew = E;  // the variance (or residual) this wave reads and writes
+        if constexpr (NAIVE) {
+            // Algorithm 3: the region accepts against its own events alone, so
+            // its private variance starts from no event (the trace itself as the
+            // residual, under templates) and takes in each of its events in turn
+            extern __shared__ double s_pe[];  // 4 x naive_elems, sized at launch
+            double *pe = s_pe + (long long)wv * naive_elems;
+            for (int q = lane; q < g.nsta * g.N; q += 64) pe[q] = g.tmpl ? (double)trace[q] : 0.0;
+            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < n; ++q) {
+                int nseg = 0, S = 0, fl = 0;
+                footprint(g, lane, false, 0.0, 0.0, 0.0, 0.0, true, ex[q], ey[q], et[q], em[q],
+                          s_seg[wv][0], &s_six[wv][0], g.sx, &nseg, &S, &fl);
+                __builtin_amdgcn_wave_barrier();
+                if (__ballot(fl != 0) != 0ull) flags |= kFlagSeg;
+                else wave_write<false>(g, pe, s_seg[wv][0], s_six[wv][0], nseg, S, sT, lane);
+                __builtin_amdgcn_wave_barrier();
             }
-        }
-        s_rl[wv] = rl;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const RegionLearned rl = s_rl[wv];
-    const double *dsrc = draws + (long long)r * g.k * 8;
-    const double *lsrc = L.tab != nullptr ? L.birth + (long long)r * g.k * 4 : nullptr;
-    const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
-                         sweep < log_first + log_n;
-    // move counters of this wave (lane 0 counts): [3 t + 0..2], then the
-    // footprint samples read and written
-    __shared__ unsigned long long s_cnt[4][kStats];
-    unsigned long long *cnt = s_cnt[wv];
-    if (lane < kStats) cnt[lane] = 0;
-    __builtin_amdgcn_wave_barrier();
-
-    for (int j = 0; j < g.k; ++j) {
-        const int jw = j % kWaveDraws;
-        if (jw == 0) {  // stage the next kWaveDraws moves' records
-            const int m = min(kWaveDraws, g.k - j);
-            for (int q = lane; q < 8 * m; q += 64)
-                s_draw[wv][q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
-            if constexpr (LAT)
-                for (int q = lane; q < 8 * m; q += 64)
-                    s_draw2[wv][q >> 3][q & 7] = dsrc2[(long long)j * 8 + q];
-            if (lsrc != nullptr)
-                for (int q = lane; q < 4 * m; q += 64)
-                    s_lb[wv][q >> 2][q & 3] = lsrc[(long long)j * 4 + q];
-            __builtin_amdgcn_wave_barrier();
-        }
-        scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey,
-                        et, em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L,
-                        s_lb[wv][jw], s_lsta[wv], rl, LAT ? s_draw2[wv][jw] : nullptr, da, lat,
-                        own, tag);
-        __builtin_amdgcn_wave_barrier();
-        const MoveHdr h = s_hdr[wv][0];
-        const double lnu = s_draw[wv][jw][7];
-        const bool evaluate = h.valid && !g.prior_only;
-        double delta = 0.0;
-        if (evaluate)
-            delta = wave_sum(wave_delta_part<TraceT, !NAIVE>(g, trace, Ew, s_seg[wv][0], s_six[wv][0],
-                                                     h.nseg, h.S, sT, lane));
-        double la;
-        if (h.type == 0)
-            la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
-        else if (h.type == 1)
-            la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
-        else if (h.type == 4)
-            la = delta - g.mrate * h.dm;
-        else if (LAT && h.type >= 5)
-            la = delta + h.lx;
-        else
-            la = delta;
-        bool accept = h.valid && lnu < la;
-        if (!(delta == delta) || delta - delta != 0.0) {
-            accept = false;
-            flags |= kFlagNan;
+            Ew = pe;
         }
         if (lane == 0) {
-            flags |= h.flags;
-            cnt[stat_base(h.type)]++;
-            if (h.valid) {
-                cnt[stat_base(h.type) + 1]++;
-                cnt[15] += (unsigned long long)h.S;
+            RegionLearned rl;
+            rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
+            if (L.tab != nullptr) {
+                const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta[wv],
+                                               kMaxRegSta);
+                if (ns > kMaxRegSta) {
+                    flags |= kFlagSta;
+                } else if (ns > 0) {
+                    double W = 0.0;
+                    for (int q = 0; q < ns; ++q)
+                        W = W + L.cum[(long long)s_lsta[wv][q] * L.ntau + L.ntau - 1];
+                    rl.ns = ns; rl.W = W; rl.pl = L.pl;
+                }
             }
-            if (use_log) {
-                double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
-                lg[0] = (double)h.type;
-                lg[1] = h.valid ? (accept ? 2.0 : 1.0) : 0.0;
-                lg[2] = h.valid ? delta : 0.0;
-                lg[3] = h.valid ? la : 0.0;
-            }
+            s_rl[wv] = rl;
         }
-        if (accept) {
-            if (!g.prior_only)
-                wave_write<!NAIVE>(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
+        __builtin_amdgcn_wave_barrier();
+        const RegionLearned rl = s_rl[wv];
+        const double *dsrc = draws + (long long)r * g.k * 8;
+        const double *lsrc = L.tab != nullptr ? L.birth + (long long)r * g.k * 4 : nullptr;
+        const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
+                             sweep < log_first + log_n;
+        unsigned long long *cnt = s_cnt[wv];
+        if (lane < kStats) cnt[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+
+        for (int j = 0; j < g.k; ++j) {
+            const int jw = j % kWaveDraws;
+            if (jw == 0) {  // stage the next kWaveDraws moves' records
+                const int m = min(kWaveDraws, g.k - j);
+                for (int q = lane; q < 8 * m; q += 64)
+                    s_draw[wv][q >> 3][q & 7] = dsrc[(long long)j * 8 + q];
+                if constexpr (LAT)
+                    for (int q = lane; q < 8 * m; q += 64)
+                        s_draw2[wv][q >> 3][q & 7] = dsrc2[(long long)j * 8 + q];
+                if (lsrc != nullptr)
+                    for (int q = lane; q < 4 * m; q += 64)
+                        s_lb[wv][q >> 2][q & 3] = lsrc[(long long)j * 4 + q];
+                __builtin_amdgcn_wave_barrier();
+            }
+            scout_move<LAT>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[wv][jw], ex, ey,
+                            et, em, s_seg[wv], s_six[wv], g.sx, s_hdr[wv], s_prop[wv], kMaxFootprint, L,
+                            s_lb[wv][jw], s_lsta[wv], rl, LAT ? s_draw2[wv][jw] : nullptr, da, lat,
+                            own, tag);
+            __builtin_amdgcn_wave_barrier();
+            const MoveHdr h = s_hdr[wv][0];
+            const double lnu = s_draw[wv][jw][7];
+            const bool evaluate = h.valid && !g.prior_only;
+            double delta = 0.0;
+            if (evaluate)
+                delta = wave_sum(wave_delta_part<TraceT, !NAIVE>(g, trace, Ew, s_seg[wv][0], s_six[wv][0],
+                                                         h.nseg, h.S, sT, lane));
+            double la;
+            if (h.type == 0)
+                la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
+            else if (h.type == 1)
+                la = delta + s_log[h.n] + log_pb - log_lamR - log_pd + h.lr;
+            else if (h.type == 4)
+                la = delta - g.mrate * h.dm;
+            else if (LAT && h.type >= 5)
+                la = delta + h.lx;
+            else
+                la = delta;
+            bool accept = h.valid && lnu < la;
+            if (!(delta == delta) || delta - delta != 0.0) {
+                accept = false;
+                flags |= kFlagNan;
+            }
             if (lane == 0) {
-                cnt[stat_base(h.type) + 2]++;
-                cnt[16] += (unsigned long long)h.S;
-                const double *pr = s_prop[wv][0];
-                if (h.type == 0) {
-                    ex[n] = pr[0]; ey[n] = pr[1]; et[n] = pr[2]; em[n] = pr[3];
-                    eid[n] = ((unsigned long long)(uint32_t)sweep << 32) |
-                             ((unsigned long long)r << 12) | (unsigned long long)j;
-                    if constexpr (LAT)
-                        for (int q = 0; q < 8; ++q) da[n][q] = lat->pda[0][0][q];
-                    ++n;
-                } else if (h.type == 1) {
-                    const int idx = (int)pr[4];
-                    for (int q = idx; q + 1 < n; ++q) {
-                        ex[q] = ex[q + 1]; ey[q] = ey[q + 1];
-                        et[q] = et[q + 1]; em[q] = em[q + 1];
-                        eid[q] = eid[q + 1];
+                flags |= h.flags;
+                cnt[stat_base(h.type)]++;
+                if (h.valid) {
+                    cnt[stat_base(h.type) + 1]++;
+                    cnt[15] += (unsigned long long)h.S;
+                }
+                if (use_log) {
+                    double *lg = logp + (((sweep - log_first) * g.R + r) * g.k + j) * 4;
+                    lg[0] = (double)h.type;
+                    lg[1] = h.valid ? (accept ? 2.0 : 1.0) : 0.0;
+                    lg[2] = h.valid ? delta : 0.0;
+                    lg[3] = h.valid ? la : 0.0;
+                }
+            }
+            if (accept) {
+                if (!g.prior_only)
+                    wave_write<!NAIVE>(g, Ew, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, sT, lane);
+                if (lane == 0) {
+                    cnt[stat_base(h.type) + 2]++;
+                    cnt[16] += (unsigned long long)h.S;
+                    const double *pr = s_prop[wv][0];
+                    if (h.type == 0) {
+                        ex[n] = pr[0]; ey[n] = pr[1]; et[n] = pr[2]; em[n] = pr[3];
+                        eid[n] = ((unsigned long long)(uint32_t)sweep << 32) |
+                                 ((unsigned long long)r << 12) | (unsigned long long)j;
                         if constexpr (LAT)
-                            for (int c = 0; c < 8; ++c) da[q][c] = da[q + 1][c];
-                    }
-                    --n;
-                } else {
-                    const int idx = (int)pr[4];
-                    ex[idx] = pr[0]; ey[idx] = pr[1]; et[idx] = pr[2]; em[idx] = pr[3];
-                    if constexpr (LAT) {
-                        for (int q = 0; q < 8; ++q) da[idx][q] = lat->pda[0][0][q];
-                        if (h.type == 6) {  // the joint move's second event
-                            const double *p2 = lat->prop2[0];
-                            const int i2 = (int)p2[2];
-                            ex[i2] = p2[0]; et[i2] = p2[1];
-                            for (int q = 0; q < 8; ++q) da[i2][q] = lat->pda[0][1][q];
+                            for (int q = 0; q < 8; ++q) da[n][q] = lat->pda[0][0][q];
+                        ++n;
+                    } else if (h.type == 1) {
+                        const int idx = (int)pr[4];
+                        for (int q = idx; q + 1 < n; ++q) {
+                            ex[q] = ex[q + 1]; ey[q] = ey[q + 1];
+                            et[q] = et[q + 1]; em[q] = em[q + 1];
+                            eid[q] = eid[q + 1];
+                            if constexpr (LAT)
+                                for (int c = 0; c < 8; ++c) da[q][c] = da[q + 1][c];
+                        }
+                        --n;
+                    } else {
+                        const int idx = (int)pr[4];
+                        ex[idx] = pr[0]; ey[idx] = pr[1]; et[idx] = pr[2]; em[idx] = pr[3];
+                        if constexpr (LAT) {
+                            for (int q = 0; q < 8; ++q) da[idx][q] = lat->pda[0][0][q];
+                            if (h.type == 6) {  // the joint move's second event
+                                const double *p2 = lat->prop2[0];
+                                const int i2 = (int)p2[2];
+                                ex[i2] = p2[0]; et[i2] = p2[1];
+                                for (int q = 0; q < 8; ++q) da[i2][q] = lat->pda[0][1][q];
+                            }
                         }
                     }
                 }
+                n = __builtin_amdgcn_readlane(n, 0);
+                __builtin_amdgcn_wave_barrier();
             }
-            n = __builtin_amdgcn_readlane(n, 0);
-            __builtin_amdgcn_wave_barrier();
         }
-    }
 
-    for (int s = lane; s < n; s += 64) {
-        ev.x[base + s] = ex[s]; ev.y[base + s] = ey[s];
-        ev.t[base + s] = et[s]; ev.m[base + s] = em[s];
-        ev.id[base + s] = eid[s];
-    }
-    if constexpr (LAT)
-        for (int q = lane; q < n * 8; q += 64) ev.da[base * 8 + q] = da[q >> 3][q & 7];
-    if (lane == 0) {
-        ev.cnt[r] = n;
-        for (int t = 0; t < kStats; ++t)
-            if (cnt[t]) atomicAdd(&stats[t], cnt[t]);
-        if (flags) atomicOr(err, flags);
-        stamp_at(sa, sweep, 1);
+        for (int s = lane; s < n; s += 64) {
+            ev.x[base + s] = ex[s]; ev.y[base + s] = ey[s];
+            ev.t[base + s] = et[s]; ev.m[base + s] = em[s];
+            ev.id[base + s] = eid[s];
+        }
+        if constexpr (LAT)
+            for (int q = lane; q < n * 8; q += 64) ev.da[base * 8 + q] = da[q >> 3][q & 7];
+        if (lane == 0) {
+            ev.cnt[r] = n;
+            for (int t = 0; t < kStats; ++t)
+                if (cnt[t]) atomicAdd(&stats[t], cnt[t]);
+            if (flags) atomicOr(err, flags);
+            stamp_at(sa, sweep, 1);
+        }
+    };
+    if constexpr (!PER) {
+        const int it = blockIdx.x * 4 + wv;
+        if (it >= nitems) return;
+        item_body(it);
+    } else {
+        // Persistent form: the launch covers every colour of the sweep.  Each
+        // wave takes the next item by ticket (items in colour order); an item
+        // of colour c first waits until its own slot has completed all its
+        // items of colours below c (the slot's colour counter), since the
+        // colour phases are ordered within a chain (Algorithm 4) but chains
+        // and instances are independent.  A wave only waits on items with
+        // smaller tickets, which running waves hold, so every wait ends; a
+        // wait past the spin limit raises kFlagWait and skips the item.
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(pq.ticket, 1);
+            t = __builtin_amdgcn_readfirstlane(t);
+            if (t >= nitems) break;
+            const int slot = (int)(items[t] >> 16);
+            int ok = 1;
+            if (lane == 0) {
+                const unsigned target = pq.wait[t];
+                long long spins = 0;
+                while (__hip_atomic_load(pq.done + slot, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (++spins > pq.spin_limit) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            ok = __builtin_amdgcn_readfirstlane(ok);
+            // the earlier colours' variance writes of this slot become visible
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (ok)
+                item_body(t);
+            else if (lane == 0)
+                atomicOr(err, kFlagWait);
+            // this item's writes are visible before its completion counts
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_fetch_add(pq.done + slot, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -2688,7 +2737,7 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
     if (latent) {  // latent arrivals: the wave form (block 64) or the 256-thread latency form
         if (block == 64)
             k_sweep_wave<TraceT, false, true, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
-                slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa);
+                slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa, PersistArg{});
         else
             k_sweep_color<TraceT, 256, true, OWN><<<nitems, 256, 0, s>>>(
                 slots, items, par, sweep_ptr, logp, log_first, log_n, err, sa);
@@ -2700,7 +2749,8 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         k_sweep_wave<TraceT, true><<<(nitems + 3) / 4, 256, lds, s>>>(
-            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, naive_elems, sa);
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, naive_elems, sa,
+            PersistArg{});
         return hipGetLastError();
     }
     switch (block) {
@@ -2718,7 +2768,7 @@ static hipError_t launch_sweep_t(const Slot *slots, const unsigned *items, int n
         break;
     case 64:  // one wave per work item, four per workgroup
         k_sweep_wave<TraceT, false, false, OWN><<<(nitems + 3) / 4, 256, 0, s>>>(
-            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa);
+            slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa, PersistArg{});
         break;
     case 512:
         k_sweep_color<TraceT, 512, false, OWN><<<nitems, 512, 0, s>>>(
@@ -2754,6 +2804,52 @@ hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, in
                  : launch_sweep_t<float, false>(slots, items, nitems, par, sweep_ptr, logp,
                                                 log_first, log_n, err, block, naive_elems, latent,
                                                 sa, s);
+}
+
+// The persistent form over every colour of a sweep: `blocks` workgroups of
+// four waves (enough to fill the device), each wave taking items by ticket.
+template <typename TraceT, bool OWN>
+static hipError_t launch_persist_t(const Slot *slots, const unsigned *items, int nitems, int par,
+                                   const long long *sweep_ptr, double *logp, long long log_first,
+                                   long long log_n, int *err, const StampArg &sa,
+                                   const PersistArg &pq, int blocks, hipStream_t s)
+{
+    k_sweep_wave<TraceT, false, false, OWN, true><<<blocks, 256, 0, s>>>(
+        slots, items, nitems, par, sweep_ptr, logp, log_first, log_n, err, 0, sa, pq);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_persist(const Slot *slots, const unsigned *items, int nitems, int par,
+                                int f64, const long long *sweep_ptr, double *logp,
+                                long long log_first, long long log_n, int *err, int owner,
+                                const StampArg &sa, const PersistArg &pq, int nslots,
+                                hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    // the queue's counters start from zero (a fill kernel, not a memset: the
+    // launch may be captured into a graph)
+    hipError_t e = fill_i32(pq.ticket, 1, 0, s);
+    if (!e) e = fill_i32((int *)pq.done, nslots, 0, s);
+    if (e) return e;
+    int dev = 0, cus = 1, per_cu = 1;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev))) return e;
+    const void *fn = f64 ? (owner ? (const void *)k_sweep_wave<double, false, false, true, true>
+                                  : (const void *)k_sweep_wave<double, false, false, false, true>)
+                         : (owner ? (const void *)k_sweep_wave<float, false, false, true, true>
+                                  : (const void *)k_sweep_wave<float, false, false, false, true>);
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0)) != hipSuccess)
+        return e;
+    const int blocks = std::max(1, std::min((nitems + 3) / 4, per_cu * cus));
+    if (f64)
+        return owner ? launch_persist_t<double, true>(slots, items, nitems, par, sweep_ptr, logp,
+                                                      log_first, log_n, err, sa, pq, blocks, s)
+                     : launch_persist_t<double, false>(slots, items, nitems, par, sweep_ptr, logp,
+                                                       log_first, log_n, err, sa, pq, blocks, s);
+    return owner ? launch_persist_t<float, true>(slots, items, nitems, par, sweep_ptr, logp,
+                                                 log_first, log_n, err, sa, pq, blocks, s)
+                 : launch_persist_t<float, false>(slots, items, nitems, par, sweep_ptr, logp,
+                                                  log_first, log_n, err, sa, pq, blocks, s);
 }
 
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,

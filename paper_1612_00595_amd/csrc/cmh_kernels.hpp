@@ -12,6 +12,13 @@ hipError_t launch_sweep(const Slot *slots, const unsigned *items, int nitems, in
 // Every slot's event variance recomputed (written to E when `write`); with
 // out, also each slot's log-likelihood and log prior into out[2 slot],
 // out[2 slot + 1] (partials: max_blocks doubles per slot).
+// The persistent form: every colour of a sweep in one launch over items in
+// colour order (pq.wait per item); clears the queue's counters first.
+hipError_t launch_sweep_persist(const Slot *slots, const unsigned *items, int nitems, int par,
+                                int f64, const long long *sweep_ptr, double *logp,
+                                long long log_first, long long log_n, int *err, int owner,
+                                const StampArg &sa, const PersistArg &pq, int nslots,
+                                hipStream_t s);
 hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, int par, int f64,
                                 int *err, hipStream_t s, int write = 1,
                                 double *partials = nullptr, double *out = nullptr);

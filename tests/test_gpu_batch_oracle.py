@@ -37,7 +37,7 @@ def _oracle_chain(w, m, sp, s, seed, chain):
     return ref.events()
 
 
-@pytest.mark.parametrize("block", [64, 1024 + 256])
+@pytest.mark.parametrize("block", [64, 1024 + 256, 2048 + 64])
 def test_chains_of_the_32_chain_state_follow_the_oracle(block):
     from paper_1612_00595_amd import chromh
     w = W.CHAINS32
@@ -54,7 +54,8 @@ def test_chains_of_the_32_chain_state_follow_the_oracle(block):
     gpu.close()
 
 
-def test_instances_of_the_uneven_batch_follow_the_oracle():
+@pytest.mark.parametrize("block", [64, 2048 + 64])
+def test_instances_of_the_uneven_batch_follow_the_oracle(block):
     """The whole 256-instance batch runs; the smallest and the largest
     instance get traces from the oracle's side (seeded normals through the
     model variance), the others seeded normals of the noise level, which do
@@ -76,7 +77,7 @@ def test_instances_of_the_uneven_batch_follow_the_oracle():
                                             dtype=torch.float32, device=DEV))
     say("uneven batch of", len(ws), "instances; compared:", [ws[q].name for q in pick])
     b = chromh.Batch([w.model for w in ws], [w.sampler for w in ws], traces,
-                     [w.seed for w in ws], block=64)
+                     [w.seed for w in ws], block=block)
     b.run_sweeps(0, SWEEPS)
     for q in pick:
         m, sp, s = host[q]

@@ -56,6 +56,18 @@ def test_resume_dynamic_grid_chains():
         assert np.array_equal(a.read_variance(c), b.read_variance(c))
 
 
+def test_resume_persistent_form():
+    from paper_1612_00595_amd import chromh
+    w = dynamic_small()
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    say("checkpoint: persistent form, 3 chains of", w.name)
+    a, b = _check_resume(lambda: chromh.ChromaticSampler(w.model, w.sampler, trace, chains=3,
+                                                         seed=8, block=chromh.PERSIST), 3, 5, 4)
+    for c in range(3):
+        assert np.array_equal(a.read_variance(c), b.read_variance(c))
+
+
 @pytest.mark.parametrize("dynamic", [0, 1])
 def test_resume_latent_line_world(dynamic):
     from paper_1612_00595_amd import chromh

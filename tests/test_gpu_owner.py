@@ -39,6 +39,7 @@ def _cases():
         ("grid-dynamic", dynamic_small(), 64, 2),
         ("grid-dynamic", dynamic_small(), 256, 2),
         ("grid-dynamic", dynamic_small(), 1024 + 256, 2),
+        ("grid-dynamic", dynamic_small(), 2048 + 64, 3),
         ("grid-static", W.SMALL, 128, 1),
         ("grid-template", small_t, 256, 1),
         ("grid-template", small_t, 1024 + 512, 1),
@@ -94,8 +95,12 @@ def test_owner_check_batch_of_uneven_worlds():
         assert np.array_equal(runs[1].read_counters(q), runs[0].read_counters(q))
 
 
-@pytest.mark.parametrize("world,block", [("grid", 64), ("grid", 256), ("grid", 1024 + 256),
-                                         ("line", 64), ("line", 256)])
+@pytest.mark.parametrize("world,block", [
+    ("grid", 64), ("grid", 256), ("grid", 1024 + 256),
+    pytest.param("grid", 2048 + 64, marks=pytest.mark.skip(
+        reason="the persistent form on this static partition did not finish on the device "
+               "once, cause not found; the library now refuses static partitions for it")),
+    ("line", 64), ("line", 256)])
 def test_owner_check_reports_a_forced_breach(world, block):
     """Period 1 puts neighbouring regions in one colour (the oracle counts
     the dependent pairs); forced past the check, the run must end in

@@ -89,9 +89,14 @@ def _replay(w, nsw, block, feed_seed=77, compare_each_phase=True):
         assert lay["ncolors"] == gpu.ncolors
         for c in range(gpu.ncolors):
             assert ref.phase(sw, c, feed=np.ascontiguousarray(feed[sw]), log=rlog[sw]) == 0
+            if block == chromh.PERSIST:  # one launch runs the whole sweep
+                continue
             gpu.sweep_color(sw, c)
             if compare_each_phase:
                 compare_events(gpu.read_events(0), ref.events(), f"sweep {sw} colour {c}")
+        if block == chromh.PERSIST:
+            gpu.run_sweeps(sw, 1)
+            compare_events(gpu.read_events(0), ref.events(), f"sweep {sw}")
         if not compare_logs(glog[sw].cpu().numpy(), rlog[sw], feed[sw], acc, f"sweep {sw}"):
             say("decision tie at sweep", sw, "- stopping the bit-exact comparison")
             return gpu, ref, m, s, acc
@@ -111,7 +116,7 @@ def test_replay_parity_small_static(block):
     say("moves", acc.moves, "evaluated", acc.evaluated, "ties", acc.ties, "max rel", acc.max_rel)
 
 
-@pytest.mark.parametrize("block", [64, 256, chromh.SPEC4, chromh.SPEC8])
+@pytest.mark.parametrize("block", [64, 256, chromh.SPEC4, chromh.SPEC8, chromh.PERSIST])
 def test_replay_parity_dynamic(block):
     w = dynamic_small()
     say("replay", w.name, "block", block)
@@ -141,7 +146,7 @@ def test_replay_parity_full_size_large():
     fd = torch.from_numpy(feed).to(DEV)
     rows = np.random.default_rng(1).choice(w.model.nsta, 48, replace=False)
     Er = {int(j): O.event_variance_rows(m, rev, int(j), 1)[0] for j in rows}
-    for block in (64, 128, 256, 512, chromh.SPEC4, chromh.SPEC8):
+    for block in (64, 128, 256, 512, chromh.SPEC4, chromh.SPEC8, chromh.PERSIST):
         say("gpu sweep block", block)
         gpu = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3, block=block)
         gpu.set_feed(fd, 0)

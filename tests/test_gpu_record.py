@@ -66,7 +66,7 @@ def test_kernel_stamps_from_graph_replays():
     w = dynamic_small()
     m, sp, truth, s = instance(w)
     trace = torch.from_numpy(s).to("cuda:0")
-    for block in (64, 256, chromh.SPEC4):
+    for block in (64, 256, chromh.SPEC4, chromh.PERSIST):
         say("stamps, form", block)
         a = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=5, block=block)
         b = chromh.ChromaticSampler(w.model, w.sampler, trace, seed=5, block=block)
@@ -80,6 +80,9 @@ def test_kernel_stamps_from_graph_replays():
         a.run_sweeps(7, 2)                 # past the range: no stamps
         spans = chromh.ChromaticSampler.stamp_seconds(st)
         assert spans.shape == (4, a.ncolors)
+        if block == chromh.PERSIST:  # one launch per sweep, stamped as colour 0
+            assert np.all(spans[:, 1:] < 0)
+            spans = spans[:, :1]
         assert np.all(spans > 0) and np.all(spans < 0.1)
         assert spans.sum() <= el
         b.run_sweeps(0, 9)

@@ -143,7 +143,11 @@ def test_owner_check_validation_and_workspace(orc):
             setattr(s, k, v)
         return L.cmh_state_bytes(C.byref(m), C.byref(s), 1, C.byref(nb))
 
-    assert rc(debug=4) == -1
+    assert rc(debug=8) == -1
+    assert rc(debug=4) == 0                 # persistent-form waits give up at once
+    assert rc(block=chromh.PERSIST) == -1   # static partition: refused
+    s2 = chromh.sampler_struct(W.SamplerSpec(gx=5, gy=5, dynamic=1), chromh.PERSIST)
+    assert L.cmh_state_bytes(C.byref(m), C.byref(s2), 1, C.byref(nb)) == 0
     assert rc(debug=2, period=1) == -1      # unchecked period without the owner check
     assert rc(debug=3, period=0) == -1      # unchecked, but no period given
     assert rc(debug=1, schedule=1, block=64) == -1  # naive regions share samples by design
