@@ -60,9 +60,9 @@ def parse():
                     help="skip the per-kernel rates (refresh, simulator, features, network)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain study on the 5x5-station worlds")
-    ap.add_argument("--learned-worlds", type=int, default=8)
-    ap.add_argument("--learned-sweeps", type=int, default=2000)
-    ap.add_argument("--learned-chains", type=int, default=16)
+    ap.add_argument("--learned-worlds", type=int, default=50)
+    ap.add_argument("--learned-sweeps", type=int, default=1000)
+    ap.add_argument("--learned-chains", type=int, default=8)
     ap.add_argument("--learned-pairs", type=int, default=10_000_000)
     ap.add_argument("--no-template", action="store_true",
                     help="skip the mean-template likelihood on the main workload's shape")
@@ -210,8 +210,8 @@ def learned_study(args, dev):
         del trace, T, wt
     for mode in ("plain", "learned"):
         rs = per[mode]
-        f1 = np.concatenate([r["f1"] for r in rs])
-        mean, lo, hi = M.bootstrap_ci(f1)
+        # worlds are the independent units: the interval is over world means
+        mean, lo, hi = M.bootstrap_ci(np.array([np.mean(r["f1"]) for r in rs]))
         # ESS/s per GPU: mean ESS per chain times the chains that run together
         ess_s = [np.nanmean(r["ess"]) * args.learned_chains / r["seconds"] for r in rs]
         out[mode] = {"f1": mean, "f1_ci95": [lo, hi],
@@ -394,82 +394,46 @@ def uneven_burn_in(args) -> int:
         max(0, UNEVEN_SWEEPS - args.warmup - args.uneven_steps)
 
 
-def uneven_study(args, dev, block: int):
+UNEVEN_RECORD = 32        # sweeps recorded after the timed ones for the per-instance report
+UNEVEN_ESS_MAX_LAMBDA = 400.0   # location ESS for instances up to this Poisson mean
+
+
+def uneven_study(args, dev, block: int, net=None):
     """Many independent instances of uneven size in one batch (every colour
     phase one launch over all instances' regions of that colour): proposals/s
-    over graph-replayed sweeps and the algorithmic bytes the sweeps moved."""
+    over graph-replayed sweeps and the algorithmic bytes the sweeps moved.
+    net: learned births (p = 0.5) from the trained network, each instance's
+    anchor table built from its own trace (features, fused network
+    inference, mixture table).  After the timed sweeps UNEVEN_RECORD more are
+    recorded on the device for a per-instance report: precision, recall and
+    F1 of the last state, and event-location ESS/s (ESS over the recorded
+    sweeps per second of the batch's sweep time) for the instances of
+    Poisson mean up to UNEVEN_ESS_MAX_LAMBDA."""
     import numpy as np
     import torch
 
-    from paper_1612_00595_amd import chromh, workloads as W
+    from paper_1612_00595_amd import chromh, learned, metrics as M, workloads as W
     ws = W.uneven_batch(args.uneven_count)
-    traces, models, samplers, seeds = [], [], [], []
+    traces, models, samplers, seeds, truths = [], [], [], [], []
     for w in ws:
         tr = W.truth_events(w.model, w.seed)
+        truths.append(tr)
         truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
         traces.append(chromh.simulate(w.model, truth, 1000 + w.seed, "f32", dev))
         models.append(w.model)
         samplers.append(w.sampler)
         seeds.append(w.seed)
     b = chromh.Batch(models, samplers, traces, seeds, block=block)
-    bu = uneven_burn_in(args)
-    b.run_sweeps(0, bu + args.warmup)
-    torch.cuda.synchronize()
-    c0 = [b.read_counters(q) for q in range(len(ws))]
-    t0 = time.perf_counter()
-    b.run_sweeps(bu + args.warmup, args.uneven_steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    c1 = [b.read_counters(q) for q in range(len(ws))]
-    d = sum(x - y for x, y in zip(c1, c0))
-    proposals = int(d[:15].reshape(5, 3)[:, 0].sum())
-    nbytes = int(d[15]) * 12 + int(d[16]) * 8
-    out = {"workload": f"{len(ws)} uneven instances (sides 8..32, 4000..36000 fp32 samples, "
-                       f"Poisson means 100..5000)",
-           "instances": len(ws), "stations": int(sum(m.nsta for m in models)),
-           "regions": int(sum(sp.nreg for sp in samplers)),
-           "poisson_mean_events": float(sum(m.lam for m in models)),
-           "value": proposals / el, "unit": "proposals/s",
-           "ms_per_step": el * 1e3 / args.uneven_steps,
-           "burn_in_sweeps": bu,
-           "algorithmic_GBps_whole_sweep": nbytes / el / 1e9,
-           "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block,
-           "births_attempted_valid_accepted": [int(v) for v in d[:15].reshape(5, 3)[0]]}
-    log(f"[bench] uneven batch: {out['value']:.4g} proposals/s, {out['ms_per_step']:.2f} ms/sweep, "
-        f"{out['algorithmic_GBps_whole_sweep']:.1f} GB/s algorithmic")
-    b.close()
-    del traces, b
-    return out
-
-
-def uneven_learned_study(args, dev, block: int, net):
-    """The uneven batch again, every instance with learned births (p = 0.5)
-    from the trained network: each instance's anchor table is built from its
-    own trace (features, fused network inference, mixture table), then the
-    same sweeps as the plain line are timed."""
-    import numpy as np
-    import torch
-
-    from paper_1612_00595_amd import chromh, learned, workloads as W
-    ws = W.uneven_batch(args.uneven_count)
-    traces, models, samplers, seeds = [], [], [], []
-    for w in ws:
-        tr = W.truth_events(w.model, w.seed)
-        truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
-        traces.append(chromh.simulate(w.model, truth, 1000 + w.seed, "f32", dev))
-        models.append(w.model)
-        samplers.append(w.sampler)
-        seeds.append(w.seed)
-    b = chromh.Batch(models, samplers, traces, seeds, block=block)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    anchors = 0
-    for q, (m, trc) in enumerate(zip(models, traces)):
-        T, wt, ntau = learned.anchor_table(net, m, trc)
-        anchors += m.nsta * ntau
-        b.set_learned_instance(q, T, wt, ntau, 0.5)
-    torch.cuda.synchronize()
-    t_tables = time.perf_counter() - t0
+    anchors, t_tables = 0, 0.0
+    if net is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q, (m, trc) in enumerate(zip(models, traces)):
+            T, wt, ntau = learned.anchor_table(net, m, trc)
+            anchors += m.nsta * ntau
+            b.set_learned_instance(q, T, wt, ntau, 0.5)
+        torch.cuda.synchronize()
+        t_tables = time.perf_counter() - t0
     bu = uneven_burn_in(args)
     b.run_sweeps(0, bu + args.warmup)
     torch.cuda.synchronize()
@@ -481,18 +445,74 @@ def uneven_learned_study(args, dev, block: int, net):
     c1 = [b.read_counters(q) for q in range(len(ws))]
     d = sum(x - y for x, y in zip(c1, c0))
     mv = d[:15].reshape(5, 3)
-    out = {"workload": f"{len(ws)} uneven instances, learned births (p = 0.5)",
-           "instances": len(ws), "anchors": int(anchors), "tables_seconds": t_tables,
-           "value": float(mv[:, 0].sum()) / el, "unit": "proposals/s",
-           "ms_per_step": el * 1e3 / args.uneven_steps, "block": block,
+    proposals = int(mv[:, 0].sum())
+    nbytes = int(d[15]) * 12 + int(d[16]) * 8
+    out = {"workload": f"{len(ws)} uneven instances (sides 8..32, 4000..36000 fp32 samples, "
+                       f"Poisson means 100..5000)" + (", learned births (p = 0.5)" if net else ""),
+           "instances": len(ws), "stations": int(sum(m.nsta for m in models)),
+           "regions": int(sum(sp.nreg for sp in samplers)),
+           "poisson_mean_events": float(sum(m.lam for m in models)),
+           "value": proposals / el, "unit": "proposals/s",
+           "ms_per_step": el * 1e3 / args.uneven_steps,
+           "burn_in_sweeps": bu,
+           "algorithmic_GBps_whole_sweep": nbytes / el / 1e9,
+           "frac_whole_sweep": nbytes / el / 1e9 / HBM_PEAK_GBS, "block": block,
            "births_attempted_valid_accepted": [int(v) for v in mv[0]],
            "deaths_attempted_valid_accepted": [int(v) for v in mv[1]]}
-    log(f"[bench] uneven batch with learned births: {out['value']:.4g} proposals/s, "
-        f"{out['ms_per_step']:.2f} ms/sweep; tables for {anchors} anchors in {t_tables:.2f} s")
+    if net is not None:
+        out.update(anchors=int(anchors), tables_seconds=t_tables)
+    # the per-instance report (untimed)
+    first = bu + args.warmup + args.uneven_steps
+    rec = b.set_record(first, UNEVEN_RECORD, 8192)
+    b.run_sweeps(first, UNEVEN_RECORD)
+    torch.cuda.synchronize()
+    recc = rec.cpu().numpy()
+    b.set_record(0, 0, 0)
+    sweep_s = el / args.uneven_steps
+    per = {"lam": [], "precision": [], "recall": [], "f1": [], "ess_per_s": []}
+    for q, w in enumerate(ws):
+        states = chromh.ChromaticSampler.recorded_states(recc, q)
+        r = M.match(truths[q], states[-1])
+        per["lam"].append(w.model.lam)
+        per["precision"].append(round(r.precision, 4))
+        per["recall"].append(round(r.recall, 4))
+        per["f1"].append(round(r.f1, 4))
+        e = None
+        if w.model.lam <= UNEVEN_ESS_MAX_LAMBDA:
+            ess, k = M.location_ess(states, truths[q], burn_frac=0.0)
+            e = ess / (UNEVEN_RECORD * sweep_s) if k else None
+        per["ess_per_s"].append(e)
+    out["per_instance"] = per
+    f1 = np.array(per["f1"])
+    out["f1_mean_ci95"] = list(M.bootstrap_ci(f1))
+    out["precision_mean"] = float(np.mean(per["precision"]))
+    out["recall_mean"] = float(np.mean(per["recall"]))
+    es = [v for v in per["ess_per_s"] if v is not None]
+    out["ess_per_s_median"] = float(np.median(es)) if es else None
+    log(f"[bench] uneven batch{' with learned births' if net else ''}: {out['value']:.4g} "
+        f"proposals/s, {out['ms_per_step']:.2f} ms/sweep, "
+        f"{out['algorithmic_GBps_whole_sweep']:.1f} GB/s algorithmic; mean F1 "
+        f"{out['f1_mean_ci95'][0]:.3f}, median ESS/s {out['ess_per_s_median']}")
     b.close()
-    del traces, b
+    del traces, b, rec
     torch.cuda.empty_cache()
     return out
+
+
+def compare_uneven(plain, learn):
+    """Per-instance learned against plain: F1 difference and the ratio of
+    location ESS/s where both chains have one."""
+    import numpy as np
+    pl, le = plain["per_instance"], learn["per_instance"]
+    df1 = np.array(le["f1"]) - np.array(pl["f1"])
+    ratios = [b / a for a, b in zip(pl["ess_per_s"], le["ess_per_s"])
+              if a is not None and b is not None and a > 0]
+    return {"f1_learned_minus_plain_mean": float(df1.mean()),
+            "f1_learned_minus_plain_quartiles": np.quantile(df1, [0.25, 0.5, 0.75]).round(4).tolist(),
+            "ess_per_s_ratio_quartiles": (np.quantile(ratios, [0.25, 0.5, 0.75]).round(3).tolist()
+                                          if ratios else None),
+            "instances_with_ess": len(ratios),
+            "proposals_per_s_ratio": learn["value"] / plain["value"]}
 
 
 def kernel_rates(dev):
@@ -560,6 +580,31 @@ def kernel_rates(dev):
         f"anchors/s, network forward {out['mdn_forward']['TFLOPs']:.1f} TFLOP/s, fused inference "
         f"{out['mdn_infer']['TFLOPs']:.1f} TFLOP/s")
     del X, wts, head, trace, net
+    return out
+
+
+def stream_peaks(dev, gib: int = 4):
+    """The device's own streaming rates, for context beside the spec peak:
+    a device-to-device copy (read + write counted) and a fill (write only)
+    of `gib` GiB, timed with HIP events on the current stream."""
+    import torch
+    n = gib << 28  # float32 elements
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: dst.copy_(src), 8 * n),
+                             ("fill", lambda: dst.fill_(2.0), 4 * n)):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_GBps"] = nbytes * 3 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
     return out
 
 
@@ -694,7 +739,10 @@ def main():
                      "GBps": w.model.nsta * w.model.N * 12 / t_ref / 1e9,
                      "frac": w.model.nsta * w.model.N * 12 / t_ref / 1e9 / HBM_PEAK_GBS,
                      "bytes_per_sample": 12, "bound": "hbm"}
-    log(f"[bench] refresh on {w.name}: {refresh_large['GBps']:.0f} GB/s")
+    peaks = stream_peaks(dev)
+    refresh_large["frac_of_measured_copy"] = refresh_large["GBps"] / peaks["copy_GBps"]
+    log(f"[bench] refresh on {w.name}: {refresh_large['GBps']:.0f} GB/s; device copy "
+        f"{peaks['copy_GBps']:.0f} GB/s, fill {peaks['fill_GBps']:.0f} GB/s")
     nev = len(smp.read_events(0))
     out = {
         "metric": METRIC,
@@ -745,6 +793,7 @@ def main():
             "duration_source": "device steady-clock stamps of the timed sweeps",
             "kernel_share_of_step": res["kernel_s"] / el,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "measured_stream_GBps": peaks,
         },
     }
     block = smp.block
@@ -811,8 +860,9 @@ def main():
     if not args.no_learned:
         out["learned"], net = learned_study(args, dev)
         if not args.no_uneven:
-            out["uneven_learned"] = uneven_learned_study(args, dev, args.uneven_block, net)
-            out["uneven_learned"]["plain_value"] = out["uneven"]["value"]
+            out["uneven_learned"] = uneven_study(args, dev, args.uneven_block, net)
+            out["uneven_learned"]["vs_plain"] = compare_uneven(out["uneven"],
+                                                                out["uneven_learned"])
         del net
         torch.cuda.empty_cache()
     if not args.no_paper_world:

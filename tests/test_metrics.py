@@ -96,3 +96,72 @@ def test_location_ess_of_synthetic_chains():
     e, k = M.location_ess(states, truth, burn_frac=0.0)
     assert k == 2
     assert e == pytest.approx(n * (1 - rho) / (1 + rho), rel=0.3)
+
+
+def _dense_match(true_ev, inf_ev, dt, tt):
+    """The matching rule written out over every pair (the definition)."""
+    tx, ty, tn = (np.asarray(true_ev[f], dtype=float) for f in ("x", "y", "t"))
+    ix, iy, inn = (np.asarray(inf_ev[f], dtype=float) for f in ("x", "y", "t"))
+    taken = np.zeros(len(ix), dtype=bool)
+    pairs = []
+    for a in np.lexsort((np.arange(len(tx)), tn)):
+        best, bi = np.inf, -1
+        for b in range(len(ix)):
+            if taken[b]:
+                continue
+            d = np.hypot(ix[b] - tx[a], iy[b] - ty[a])
+            s = max(d / dt, abs(inn[b] - tn[a]) / tt)
+            if s < best:
+                best, bi = s, b
+        if bi >= 0:
+            d = np.hypot(ix[bi] - tx[a], iy[bi] - ty[a])
+            if d < dt and abs(inn[bi] - tn[a]) < tt:
+                pairs.append((int(a), bi))
+                taken[bi] = True
+    return pairs
+
+
+def test_match_equals_the_pairwise_definition():
+    """Random clustered sets (many near-ties, events at the thresholds'
+    edges, duplicated onsets): the windowed matcher gives the pairs the
+    all-pairs rule gives."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        nt, ni = rng.integers(0, 30), rng.integers(0, 40)
+        tx = rng.random(nt); ty = rng.random(nt); tn = np.round(rng.random(nt) * 80)
+        base = rng.integers(0, max(nt, 1), ni)
+        ix = (tx[base] if nt else rng.random(ni)) + rng.normal(0, 0.08, ni)
+        iy = (ty[base] if nt else rng.random(ni)) + rng.normal(0, 0.08, ni)
+        inn = (tn[base] if nt else rng.random(ni) * 80) + np.round(rng.normal(0, 8, ni))
+        if trial % 5 == 0 and ni:  # exactly at the time threshold
+            inn[0] = (tn[base[0]] if nt else 0.0) + 12.0
+        tru = {"x": tx, "y": ty, "t": tn}
+        inf = {"x": ix, "y": iy, "t": inn}
+        want = _dense_match(tru, inf, 0.12, 12.0)
+        assert M.match(tru, inf).pairs == want, trial
+        for go in (M._match_dense, M._match_windowed):
+            if len(tx) and len(ix):
+                pairs, dists = [], []
+                go(tx, ty, tn, ix, iy, inn, 0.12, 12.0, pairs, dists)
+                assert pairs == want, (trial, go.__name__)
+
+
+def test_match_states_equals_match_per_state():
+    """The side-by-side matching of many states (padding, ties, states left
+    empty, blocks split across the states) against `match` state by state."""
+    rng = np.random.default_rng(11)
+    nt = 25
+    tru = {"x": rng.random(nt), "y": rng.random(nt), "t": np.round(rng.random(nt) * 200)}
+    states = []
+    for q in range(60):
+        n = 0 if q % 17 == 0 else int(rng.integers(1, 40))
+        base = rng.integers(0, nt, n)
+        states.append({"x": tru["x"][base] + rng.normal(0, 0.06, n),
+                       "y": tru["y"][base] + rng.normal(0, 0.06, n),
+                       "t": tru["t"][base] + np.round(rng.normal(0, 6, n))})
+    for chunk in (1 << 22, 3000):
+        idx = M.match_states(tru, states, chunk_elems=chunk)
+        for q, st in enumerate(states):
+            got = [(a, int(idx[q, a])) for a in np.lexsort((np.arange(nt), tru["t"]))
+                   if idx[q, a] >= 0]
+            assert sorted(got) == sorted(M.match(tru, st).pairs), (chunk, q)
