@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--paper-worlds", type=int, default=50)
     ap.add_argument("--paper-runs", type=int, default=5)
     ap.add_argument("--paper-sweeps", type=int, default=100)
+    ap.add_argument("--no-small-full", action="store_true",
+                    help="skip the 5x5-station workload run in full on the GPU and by the oracle")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic for calibrating hardware byte counters)")
@@ -134,6 +136,48 @@ def cpu_baseline(w, state, budget_s: float, threads: int = 1):
                 sample=f"{w.name}: oracle sweeps {first}..{first + sweeps - 1} ({sweeps} sweeps, "
                        f"{moves} proposals, {el:.1f} s) continuing the GPU chain from its state "
                        f"after the timed sweeps ({len(events)} events) on the same trace, {how}")
+
+
+def small_full(dev):
+    """The 5x5-station, 1000-sample fp64 workload run as stated (2000 sweeps
+    from the empty world, seed 0) twice on the same simulated instance: on
+    the GPU (one chain, graph-replayed sweeps, graph construction included)
+    and by the oracle on one host thread; each run's final state is scored
+    against the truth."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1612_00595_amd import chromh, metrics as M, workloads as W
+    w = W.SMALL
+    tr = W.truth_events(w.model, w.seed)
+    truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"], tr["id"])
+    trace = chromh.simulate(w.model, truth, 1000 + w.seed, w.trace_dtype, dev)
+    smp = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=w.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.run_sweeps(0, w.sweeps)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    st = smp.read_counters(0)
+    gpu_moves = int(st[:15].reshape(5, 3)[:, 0].sum())
+    f1_gpu = M.match(tr, smp.read_events(0)).f1
+    block = smp.block
+    smp.close()
+    m = O.make_model(**w.model.asdict())
+    sp = O.make_sampler(**w.sampler.asdict())
+    ch = O.Chain(m, sp, trace.cpu().numpy(), seed=w.seed)
+    t0 = time.perf_counter()
+    for sw in range(w.sweeps):
+        assert ch.sweep(sw) == 0
+    t_cpu = time.perf_counter() - t0
+    f1_cpu = M.match(tr, ch.events()).f1
+    out = {"workload": w.name, "sweeps": w.sweeps, "proposals": gpu_moves, "block": block,
+           "gpu_seconds": t_gpu, "oracle_seconds": t_cpu, "oracle_cores": 1,
+           "gpu_over_oracle": t_cpu / t_gpu, "f1_gpu": f1_gpu, "f1_oracle": f1_cpu}
+    log(f"[bench] {w.name} in full ({w.sweeps} sweeps): GPU {t_gpu:.2f} s, oracle {t_cpu:.2f} s "
+        f"on one host thread; final F1 {f1_gpu:.3f} (GPU), {f1_cpu:.3f} (oracle)")
+    return out
 
 
 # network FLOPs per row: forward 2 (576*256 + 2*256*256 + 256*64) multiply-adds
@@ -870,6 +914,8 @@ def main():
     if not args.no_paper_latent:
         out["paper_world_latent"] = paper_world_study(args, dev, latent=True)
         torch.cuda.empty_cache()
+    if not args.no_small_full:
+        out["small_full"] = small_full(dev)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, cpu_state, args.cpu_seconds)

@@ -1983,35 +1983,30 @@ __global__ void k_sweep_draws(const Slot *__restrict__ slots, const unsigned *__
     }
 }
 
-// Learned births of one sweep, one wave per move of every (slot, region):
-// each birth move's proposal depends only on its draws and the sweep's
-// partition, so it is derived here, off the sweep's dependent chain of
-// moves.  With probability pl (regions holding a station) the anchor is
-// picked by u_anchor W_R against the running weight sums (stations
-// ascending, then windows), the component by u_comp against the cumulative
-// mixture weights, and (x, y, t) = mean + sd * (truncated normals);
-// otherwise (x, y, t) come from the prior on the region.  Either way
-// log(b / p_R) at the proposal, summed over (station, window) pairs across
-// the lanes, goes with it.
+// Learned births of one sweep, one wave per run of mpw <= 64 consecutive
+// moves of a (slot, region): each birth move's proposal depends only on its
+// draws and the sweep's partition, so it is derived here, off the sweep's
+// dependent chain of moves.  The wave finds the region's stations and total
+// anchor weight W_R; then lane l takes move l of its run.  With probability pl
+// (regions holding a station) the anchor is picked by u_anchor W_R against
+// the running weight sums (stations ascending, then windows), the component
+// by u_comp against the cumulative mixture weights, and (x, y, t) = mean +
+// sd * (truncated normals); otherwise (x, y, t) come from the prior on the
+// region.  Either way log(b / p_R) at the proposal is then summed over
+// (station, window) pairs across the lanes, one birth after another.
 __global__ void __launch_bounds__(64)
 k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ items, int k,
-                 int par, int *__restrict__ err)
+                 int mpw, int par, int *__restrict__ err)
 {
     __shared__ int s_sta[kMaxRegSta];
     __shared__ int s_ns;
     __shared__ double s_W;
-    const unsigned item = items[blockIdx.x / k];
-    const int j = (int)(blockIdx.x % k);
+    const int nrun = (k + mpw - 1) / mpw;
+    const unsigned item = items[blockIdx.x / nrun];
+    const int jbeg = (int)(blockIdx.x % nrun) * mpw, jend = min(k, jbeg + mpw);
     const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu), lane = threadIdx.x;
     const Learned &L = slots[slot].L;
     if (L.tab == nullptr) return;
-    const long long q = (long long)r * k + j;
-    const double *d = slots[slot].draws + q * 8;
-    double *lb = L.birth + q * 4;
-    if (!(d[0] < slots[slot].g.c1)) {  // not a birth
-        if (lane < 4) lb[lane] = 0.0;
-        return;
-    }
     const Geo &g = slots[slot].g;
     const double *offs = slots[slot].ev[par].off;
     const int i = r % g.nrx, kk = r / g.nrx;
@@ -2034,61 +2029,79 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
     const int ns = s_ns;
     const double W = s_W, pl = ns > 0 ? L.pl : 0.0;
     const double area = (x1 - x0) * (y1 - y0);
-    const double *e = L.raw + q * 8;  // draws 8..15
-    double x, y, t;
-    if (pl > 0.0 && e[0] < pl) {
-        // lane 0 walks the running sums; the choice is broadcast
-        double px = 0.0, py = 0.0, pt = 0.0;
-        if (lane == 0) {
-            const double target = e[1] * W;
-            double acc = 0.0, rem = 0.0;
-            int pick = -1;
-            for (int s = 0; s < ns; ++s) {
-                const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
-                if (target < nxt) {
-                    pick = s_sta[s];
-                    rem = target - acc;
-                    break;
+    const double c1 = g.c1;
+    {
+        const int j = jbeg + lane;
+        const long long q = (long long)r * k + j;
+        double x = 0.0, y = 0.0, t = 0.0;
+        bool birth = false;
+        if (j < jend) {
+            const double *d = slots[slot].draws + q * 8;
+            birth = d[0] < c1;
+            if (!birth) {
+                double *lb = L.birth + q * 4;
+                lb[0] = 0.0; lb[1] = 0.0; lb[2] = 0.0; lb[3] = 0.0;
+            } else {
+                const double *e = L.raw + q * 8;  // draws 8..15
+                if (pl > 0.0 && e[0] < pl) {
+                    // this lane walks the running sums
+                    const double target = e[1] * W;
+                    double acc = 0.0, rem = 0.0;
+                    int pick = -1;
+                    for (int s = 0; s < ns; ++s) {
+                        const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
+                        if (target < nxt) {
+                            pick = s_sta[s];
+                            rem = target - acc;
+                            break;
+                        }
+                        acc = nxt;
+                    }
+                    if (pick < 0) {
+                        pick = s_sta[ns - 1];
+                        rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
+                    }
+                    // smallest window with rem < cum (the last one if none)
+                    const double *cum = L.cum + (long long)pick * L.ntau;
+                    int lo = 0, hi = L.ntau - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (rem < cum[mid]) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
+                    int c = 7;
+                    for (int u = 0; u < 8; ++u)
+                        if (e[2] < T[8 * u + 7]) { c = u; break; }
+                    x = T[8 * c + 0] + T[8 * c + 3] * e[3];
+                    y = T[8 * c + 1] + T[8 * c + 4] * e[4];
+                    t = T[8 * c + 2] + T[8 * c + 5] * e[5];
+                } else {
+                    x = x0 + d[1] * (x1 - x0);
+                    y = y0 + d[2] * (y1 - y0);
+                    t = d[3] * (double)g.N;
                 }
-                acc = nxt;
             }
-            if (pick < 0) {
-                pick = s_sta[ns - 1];
-                rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
-            }
-            // smallest window with rem < cum (the last one if none)
-            const double *cum = L.cum + (long long)pick * L.ntau;
-            int lo = 0, hi = L.ntau - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (rem < cum[mid]) hi = mid;
-                else lo = mid + 1;
-            }
-            const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
-            int c = 7;
-            for (int u = 0; u < 8; ++u)
-                if (e[2] < T[8 * u + 7]) { c = u; break; }
-            px = T[8 * c + 0] + T[8 * c + 3] * e[3];
-            py = T[8 * c + 1] + T[8 * c + 4] * e[4];
-            pt = T[8 * c + 2] + T[8 * c + 5] * e[5];
         }
-        x = lane_f64(px, 0);
-        y = lane_f64(py, 0);
-        t = lane_f64(pt, 0);
-    } else {
-        x = x0 + d[1] * (x1 - x0);
-        y = y0 + d[2] * (y1 - y0);
-        t = d[3] * (double)g.N;
-    }
-    double lr = 0.0;
-    if (pl > 0.0) {
-        int ilo, ihi;
-        learned_windows(L, t, &ilo, &ihi);
-        const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, x, y, t, lane, 64));
-        lr = learned_log_ratio(pl, S, W, area, g.N);
-    }
-    if (lane == 0) {
-        lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
+        // each birth's density, (station, window) pairs over the lanes
+        unsigned long long todo = __ballot(birth);
+        while (todo) {
+            const int bl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(todo));
+            todo &= todo - 1;
+            const double bx = lane_f64(x, bl), by = lane_f64(y, bl), bt = lane_f64(t, bl);
+            double lr = 0.0;
+            if (pl > 0.0) {
+                int ilo, ihi;
+                learned_windows(L, bt, &ilo, &ihi);
+                const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, bx, by, bt, lane,
+                                                       64));
+                lr = learned_log_ratio(pl, S, W, area, g.N);
+            }
+            if (lane == bl) {
+                double *lb = L.birth + q * 4;
+                lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
+            }
+        }
     }
 }
 
@@ -2870,6 +2883,8 @@ hipError_t launch_refresh_slots(const Slot *slots, int nslots, int max_blocks, i
     return hipGetLastError();
 }
 
+constexpr long long kBirthWaves = 8192;
+
 hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int nall, int k,
                               int par, const long long *sweep_ptr, const double *feed,
                               long long feed_first, int width, bool learned, int *err,
@@ -2881,7 +2896,11 @@ hipError_t launch_sweep_draws(const Slot *slots, const unsigned *items_all, int 
                                                                   width);
     hipError_t e = hipGetLastError();
     if (e || !learned) return e;
-    k_learned_births<<<(unsigned)nmoves, 64, 0, s>>>(slots, items_all, k, par, err);
+    // runs of up to 64 moves per wave, shorter while that leaves fewer than
+    // kBirthWaves waves
+    const int mpw = (int)std::max(1LL, std::min(64LL, std::min((long long)k, nmoves / kBirthWaves)));
+    const long long nrun = (k + mpw - 1) / mpw;
+    k_learned_births<<<(unsigned)(nall * nrun), 64, 0, s>>>(slots, items_all, k, mpw, par, err);
     return hipGetLastError();
 }
 

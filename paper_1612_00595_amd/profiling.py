@@ -27,7 +27,7 @@ def _files(d: str, suffix: str) -> list[str]:
     return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
 
-def trace(d: str, pattern: str, last: int) -> dict:
+def trace(d: str, pattern: str, last: int, top: int = 12) -> dict:
     rows = []
     for f in _files(d, "kernel_trace.csv"):
         with open(f, newline="") as fh:
@@ -37,7 +37,7 @@ def trace(d: str, pattern: str, last: int) -> dict:
     by = collections.defaultdict(list)
     for a, b, n in rows:
         by[n].append(b - a)
-    top = sorted(by.items(), key=lambda kv: -sum(kv[1]))[:12]
+    top = sorted(by.items(), key=lambda kv: -sum(kv[1]))[:top]
     sel = [b - a for a, b, n in rows if pattern in n][-last:]
     return {
         "pattern": pattern,
@@ -77,8 +77,9 @@ def main(argv=None):
     ap.add_argument("dir")
     ap.add_argument("--kernel", required=True, help="substring of the kernel name")
     ap.add_argument("--last", type=int, default=1 << 30)
+    ap.add_argument("--top", type=int, default=12, help="kernels listed by total time")
     a = ap.parse_args(argv)
-    res = trace(a.dir, a.kernel, a.last) if a.mode == "trace" else counters(a.dir, a.kernel,
+    res = trace(a.dir, a.kernel, a.last, a.top) if a.mode == "trace" else counters(a.dir, a.kernel,
                                                                             a.last)
     json.dump(res, sys.stdout, indent=1)
     print()
