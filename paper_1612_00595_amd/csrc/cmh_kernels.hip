@@ -1714,12 +1714,15 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
 // proposal and footprint, evaluates the log-likelihood change over the
 // footprint and decides, all from the region's state before move j.  That is
 // the state the sequential chain hands to move j + w whenever moves j ..
-// j + w - 1 are all rejected.  The first accepted move of the round (in move
-// order) is committed by its wave; the moves after it are dropped and built
-// again from the new state in the next round.  Without an acceptance all D
-// moves stand.  The chain of states is therefore exactly the sequential one
-// (Algorithm 4's inner loop), while a round costs about one move's latency
-// and consumes sum_{w < D} (1 - a)^w moves at acceptance rate a.
+// j + w - 1 are all rejected, and also whenever the accepted ones among them
+// leave the event count, move j + w's event and the variance on its
+// footprint unchanged.  The moves of a round therefore stand in move order
+// up to the first one that conflicts with an earlier standing acceptance, or
+// up to and including an accepted birth or death; the accepted moves among
+// them are committed (their footprints are disjoint), the rest is dropped
+// and built again from the new state in the next round.  The chain of
+// states is exactly the sequential one (Algorithm 4's inner loop), while a
+// round costs about one move's latency.
 // Plain and mean-template likelihoods, grid and line models; latent arrivals
 // and the naive schedule keep their own forms.
 template <typename TraceT, int D, bool OWN = false>
@@ -1739,10 +1742,12 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
     __shared__ double s_ex[kMaxCap], s_ey[kMaxCap], s_et[kMaxCap], s_em[kMaxCap];
     __shared__ unsigned long long s_id[kMaxCap];
     __shared__ double s_lsx[8];  // line model: station positions
-    __shared__ Seg s_seg[D][1][kMaxSeg];
-    __shared__ SegIndex s_six[D][1];
-    __shared__ MoveHdr s_hdr[D][1];
-    __shared__ double s_prop[D][1][5];
+    // per wave and round parity: a round's tables stay readable until every
+    // wave has passed the next round's first barrier
+    __shared__ Seg s_seg[D][2][kMaxSeg];
+    __shared__ SegIndex s_six[D][2];
+    __shared__ MoveHdr s_hdr[D][2];
+    __shared__ double s_prop[D][2][5];
     __shared__ int s_acc[2][D];  // per round parity: wave w's move accepted
     __shared__ int s_n;
     __shared__ unsigned long long s_cnt[D][kStats];
@@ -1837,20 +1842,21 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         }
         const int jm = j + wv;  // this wave's move
         const int db = (jm >> 6) & 1, dj = jm & 63;
+        const int pb = round & 1;
         MoveHdr h = {};
         double delta = 0.0, la = 0.0;
         bool accept = false, nan = false;
         if (wv < m) {
-            scout_move<false>(g, lane, 0, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[db][dj],
+            scout_move<false>(g, lane, pb, i, kk, offx, offy, x0, x1, y0, y1, n, s_draw[db][dj],
                               s_ex, s_ey, s_et, s_em, s_seg[wv], s_six[wv], s_lsx, s_hdr[wv],
                               s_prop[wv], kMaxFootprint, L, s_lb[db][dj], s_lsta, rl, nullptr,
                               nullptr, nullptr, own, tag);
             __builtin_amdgcn_wave_barrier();
-            h = s_hdr[wv][0];
+            h = s_hdr[wv][pb];
             const double lnu = s_draw[db][dj][7];
             if (h.valid && !g.prior_only)
-                delta = wave_sum(wave_delta_part<TraceT, true>(g, trace, E, s_seg[wv][0],
-                                                               s_six[wv][0], h.nseg, h.S, s_T,
+                delta = wave_sum(wave_delta_part<TraceT, true>(g, trace, E, s_seg[wv][pb],
+                                                               s_six[wv][pb], h.nseg, h.S, s_T,
                                                                lane));
             if (h.type == 0)
                 la = delta + log_lamR + log_pd - s_log[h.n + 1] - log_pb - h.lr;
@@ -1863,13 +1869,61 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             accept = h.valid && lnu < la;
             nan = !(delta == delta) || delta - delta != 0.0;  // NaN or Inf
             if (nan) accept = false;
-            if (lane == 0) s_acc[round & 1][wv] = accept ? 1 : 0;
+            if (lane == 0) s_acc[pb][wv] = accept ? 1 : 0;
         }
         __syncthreads();
-        int first = m;  // the first accepted move of the round, m if none
-        for (int w = m - 1; w >= 0; --w)
-            if (s_acc[round & 1][w]) first = w;
-        const int used = first < m ? first + 1 : m;
+        // Which moves of the round stand.  Move w was built and decided from
+        // the state before move j; it is exactly the move the sequential chain
+        // makes from the state after moves j .. j + w - 1 whenever none of the
+        // accepted ones among them changed the event count (a birth or death),
+        // the event w acts on, or the variance on w's footprint.  The moves
+        // stand in order up to the first one in conflict with an earlier
+        // standing acceptance (same event, or runs at one station with
+        // overlapping samples), or up to and including an accepted birth or
+        // death.  Every wave finds them by itself from the round's tables.
+        int l_acc = 0, l_type = 0, l_idx = -1, l_nseg = 0;
+        if (lane < m) {
+            l_acc = s_acc[pb][lane];
+            const MoveHdr &hl = s_hdr[lane][pb];
+            l_type = hl.type;
+            l_idx = (int)s_prop[lane][pb][4];
+            l_nseg = hl.valid ? hl.nseg : 0;
+        }
+        const unsigned long long acc_mask = __ballot(l_acc != 0);
+        int used = m;
+        unsigned stand = 0u;  // accepted moves that stand
+        for (int w = 0; w < m; ++w) {
+            if (stand) {
+                const int tw = __builtin_amdgcn_readlane(l_type, w);
+                const int iw = __builtin_amdgcn_readlane(l_idx, w);
+                const int nw = __builtin_amdgcn_readlane(l_nseg, w);
+                bool c = false;
+                for (int v = 0; v < w && !c; ++v) {
+                    if (!((stand >> v) & 1u)) continue;
+                    const int tv = __builtin_amdgcn_readlane(l_type, v);
+                    const int iv = __builtin_amdgcn_readlane(l_idx, v);
+                    const int nv = __builtin_amdgcn_readlane(l_nseg, v);
+                    c = tw >= 1 && tv >= 1 && iw == iv;
+                    bool ov = false;
+                    for (int p = lane; !c && p < nw * nv; p += 64) {
+                        const Seg &sa = s_seg[w][pb][p / nv], &sb = s_seg[v][pb][p % nv];
+                        ov = ov || (sa.j == sb.j && sa.lo < sb.lo + sb.len && sb.lo < sa.lo + sa.len);
+                    }
+                    c = c || __ballot(ov) != 0ull;
+                }
+                if (c) {
+                    used = w;
+                    break;
+                }
+            }
+            if ((acc_mask >> w) & 1ull) {
+                stand |= 1u << w;
+                if (__builtin_amdgcn_readlane(l_type, w) <= 1) {
+                    used = w + 1;
+                    break;
+                }
+            }
+        }
         if (wv < used && lane == 0) {  // this wave's move is consumed
             flags |= h.flags | (nan ? kFlagNan : 0);
             cnt[stat_base(h.type)]++;
@@ -1885,20 +1939,26 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                 lg[3] = h.valid ? la : 0.0;
             }
         }
-        if (first < m) {
-            if (wv == first) {
+        if (stand) {
+            if ((stand >> wv) & 1u) {  // this wave's accepted move stands
                 if (!g.prior_only)
-                    wave_write<true>(g, E, s_seg[wv][0], s_six[wv][0], h.nseg, h.S, s_T, lane);
+                    wave_write<true>(g, E, s_seg[wv][pb], s_six[wv][pb], h.nseg, h.S, s_T, lane);
                 if (lane == 0) {
                     cnt[stat_base(h.type) + 2]++;
                     cnt[16] += (unsigned long long)h.S;
-                    const double *pr = s_prop[wv][0];
-                    if (h.type == 0) {
+                }
+            }
+            if (tid == 0) {  // the event table, in move order
+                for (int w = 0; w < used; ++w) {
+                    if (!((stand >> w) & 1u)) continue;
+                    const int type = s_hdr[w][pb].type;
+                    const double *pr = s_prop[w][pb];
+                    if (type == 0) {
                         s_ex[n] = pr[0]; s_ey[n] = pr[1]; s_et[n] = pr[2]; s_em[n] = pr[3];
                         s_id[n] = ((unsigned long long)(uint32_t)sweep << 32) |
-                                  ((unsigned long long)r << 12) | (unsigned long long)jm;
+                                  ((unsigned long long)r << 12) | (unsigned long long)(j + w);
                         ++n;
-                    } else if (h.type == 1) {
+                    } else if (type == 1) {
                         const int idx = (int)pr[4];
                         for (int q = idx; q + 1 < n; ++q) {
                             s_ex[q] = s_ex[q + 1]; s_ey[q] = s_ey[q + 1];
@@ -1910,8 +1970,8 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
                         const int idx = (int)pr[4];
                         s_ex[idx] = pr[0]; s_ey[idx] = pr[1]; s_et[idx] = pr[2]; s_em[idx] = pr[3];
                     }
-                    s_n = n;
                 }
+                s_n = n;
             }
             __syncthreads();  // the new events and variance are visible
             n = s_n;
