@@ -2127,7 +2127,6 @@ size_t carve_mdn_work(int M, char *base, cmh::MdnBuffers *B, float **grad)
     for (int l = 0; l < 3; ++l) b.A[l] = c.take<__bf16>(mh);
     b.O = c.take<float>(mo);
     b.dO = c.take<__bf16>(mo);
-    b.dA = c.take<float>(mh);
     b.dH[0] = c.take<__bf16>(mh);
     b.dH[1] = c.take<__bf16>(mh);
     b.loss = c.take<float>((size_t)M);

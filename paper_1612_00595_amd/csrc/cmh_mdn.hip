@@ -3,11 +3,10 @@
 // its training pairs and its input features.
 //
 //   k_gemm          C = op(A) op(B), BF16 operands on 16x16x32 MFMA tiles with
-//                   FP32 accumulation, fused bias / GELU epilogues
+//                   FP32 accumulation, fused bias / GELU / GELU-backward epilogues
 //   k_mdn_loss      mixture negative log-likelihood and its gradient
-//   k_gelu_back     dH = dA * GELU'(H), rounded to BF16
 //   k_bias_grad     column sums
-//   k_adam          Adam on FP32 master weights, BF16 copies refreshed
+//   k_adam_all      Adam on FP32 master weights, BF16 copies refreshed
 //   k_sim_pairs     simulator-generated (window features, event) pairs
 //   k_anchor_feat   window features and weights of an instance's anchors
 //   k_mdn_init      Glorot-uniform initial weights from Philox
@@ -45,8 +44,10 @@ __device__ inline float gelu_grad_f(float z)
 // contiguous dimension, so the contiguous extents (M for TA, K otherwise,
 // and N for !TB) and the leading dimensions must be multiples of 8.
 // EPI 0: C (fp32).  EPI 1: Z = C + bias (fp32) and GELU(Z) as BF16 into Cb.
-// EPI 2: C + bias (fp32).  Split K: workgroup z sums k in [z kper, (z + 1)
-// kper) and writes its partial product to C + z M ldc (EPI 0 only).
+// EPI 2: C + bias (fp32).  EPI 3: the backward through GELU, BF16 C * GELU'(Z)
+// into Cb, Z (fp32, row pitch ldc) passed as `bias`; C is not written.
+// Split K: workgroup z sums k in [z kper, (z + 1) kper) and writes its
+// partial product to C + z M ldc (EPI 0 only).
 template <bool TA, bool TB, int EPI, int WM, int WN>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
@@ -161,19 +162,14 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
                 const int j = j0 + wj + 16 * b + (lane & 15);
                 if (i >= M || j >= N) continue;
                 float z = acc[a][b][v];
+                if (EPI == 3) {  // dH = C * GELU'(Z), Z read through `bias` with row pitch ldc
+                    Cb[(long)i * ldcb + j] = (__bf16)(z * gelu_grad_f(bias[(long)i * ldc + j]));
+                    continue;
+                }
                 if (EPI != 0) z += bias[j];
                 C[(long)i * ldc + j] = z;
                 if (EPI == 1) Cb[(long)i * ldcb + j] = (__bf16)gelu_f(z);
             }
-}
-
-// dH = dA * GELU'(Z), BF16.
-__global__ void k_gelu_back(long n, const float *__restrict__ dA, const float *__restrict__ Z,
-                            __bf16 *__restrict__ dH)
-{
-    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
-         q += (long)gridDim.x * blockDim.x)
-        dH[q] = (__bf16)(dA[q] * gelu_grad_f(Z[q]));
 }
 
 // Column sums of a BF16 matrix D[M][N] over rows [z mper, (z + 1) mper)
@@ -189,6 +185,7 @@ k_col_partial(int M, int N, const __bf16 *__restrict__ D, int ldd, int mper,
     const int m0 = blockIdx.y * mper, m1 = min(M, m0 + mper);
     float s = 0.f;
     if (j < N)
+#pragma unroll 8
         for (int m = m0 + ph; m < m1; m += 4) s += (float)D[(long)m * ldd + j];
     s_p[ph][c] = s;
     __syncthreads();
@@ -202,6 +199,7 @@ __global__ void k_sum_splits(long n, int nz, const float *__restrict__ part, flo
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
          q += (long)gridDim.x * blockDim.x) {
         float s = 0.f;
+#pragma unroll 8
         for (int z = 0; z < nz; ++z) s += part[(long)z * n + q];
         out[q] = s;
     }
@@ -259,11 +257,18 @@ __global__ void k_mdn_loss(int M, const float *__restrict__ O, int ldo,
     for (int c = 7 * kMdnK; c < lddo; ++c) g[c] = (__bf16)0.0f;
 }
 
-// Adam (Kingma & Ba) with bias correction on FP32 master weights; the BF16
-// copy of a weight matrix is refreshed in the same pass (wb may be null).
-__global__ void k_adam(long n, float *__restrict__ w, float *__restrict__ mo, float *__restrict__ ve,
-                       const float *__restrict__ g, __bf16 *__restrict__ wb, float lr, float b1,
-                       float b2, float eps, float c1, float c2)
+// Adam (Kingma & Ba) with bias correction on FP32 master weights.
+// Adam over the whole FP32 parameter blob (every layer's weights and bias,
+// moments mo and ve laid out alike) in one pass; a weight's BF16 copy is
+// refreshed at its place in hcopy.
+struct AdamCopies {
+    long w[4], nw[4], wh[4];  // layer weights: blob offset, count, offset in hcopy
+};
+
+__global__ void k_adam_all(long n, float *__restrict__ w, float *__restrict__ mo,
+                           float *__restrict__ ve, const float *__restrict__ g,
+                           __bf16 *__restrict__ hcopy, AdamCopies cp, float lr, float b1, float b2,
+                           float eps, float c1, float c2)
 {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
          q += (long)gridDim.x * blockDim.x) {
@@ -274,7 +279,9 @@ __global__ void k_adam(long n, float *__restrict__ w, float *__restrict__ mo, fl
         ve[q] = v;
         const float wn = w[q] - lr * (m / c1) / (sqrtf(v / c2) + eps);
         w[q] = wn;
-        if (wb) wb[q] = (__bf16)wn;
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+            if (q >= cp.w[l] && q < cp.w[l] + cp.nw[l]) hcopy[cp.wh[l] + (q - cp.w[l])] = (__bf16)wn;
     }
 }
 
@@ -342,6 +349,7 @@ __global__ void __launch_bounds__(64)
 k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__restrict__ Zt)
 {
     __shared__ double s_ev[kMdnBg + 1][4];
+    __shared__ double s_arr[kMdnBg + 1][9][3];
     __shared__ double s_q[9][kMdnWin + 4];
     const long p = first + blockIdx.x;
     const int lane = threadIdx.x;
@@ -367,31 +375,47 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
         s_ev[lane][3] = g.mmin - log(um) / g.mrate;
     }
     __syncthreads();
-    const int nsamp = kMdnWin + 3;
-    for (int e = lane; e < 9 * nsamp; e += 64) {
-        const int b = e / nsamp, n = e % nsamp;
+    // per (event, station): reach, arrival, first sample and amplitude, the
+    // same for every sample of the station
+    if (lane < 9 * (kMdnBg + 1)) {
+        const int b = lane % 9, q = lane / 9;
+        const int dx = b % 3 - 1, dy = b / 3 - 1;
+        const double sx = (double)dx * g.ds, sy = (double)dy * g.ds;
+        const double ddx = s_ev[q][0] - sx, ddy = s_ev[q][1] - sy;
+        const double d = sqrt(ddx * ddx + ddy * ddy);
+        const double a = s_ev[q][2] + d / g.vel;
+        s_arr[q][b][0] = d < g.rc ? a : NAN;   // NaN: out of reach
+        s_arr[q][b][1] = ceil(a);
+        s_arr[q][b][2] = s_ev[q][3] * exp(-d / g.atten);
+    }
+    __syncthreads();
+    // noise of samples 2h and 2h + 1 of a station from one Box-Muller pair
+    const int nsamp = kMdnWin + 3, npair = (nsamp + 1) / 2;
+    for (int e = lane; e < 9 * npair; e += 64) {
+        const int b = e / npair, hn = e % npair;
         const int dx = b % 3 - 1, dy = b / 3 - 1;
         if ((ex != 0 && dx == ex) || (ey != 0 && dy == ey)) continue;
-        const double sx = (double)dx * g.ds, sy = (double)dy * g.ds;
-        double E = 0.0;
-        for (int q = 0; q <= kMdnBg; ++q) {
-            const double ddx = s_ev[q][0] - sx, ddy = s_ev[q][1] - sy;
-            const double d = sqrt(ddx * ddx + ddy * ddy);
-            if (!(d < g.rc)) continue;
-            const double a = s_ev[q][2] + d / g.vel;
-            const double n0 = ceil(a);
-            if ((double)n < n0 || (double)n >= n0 + g.ts) continue;
-            const double amp = s_ev[q][3] * exp(-d / g.atten);
-            const double env = exp(-((double)n - a) / g.decay);
-            E += (amp * env) * (amp * env);
-        }
-        uint32_t c[4] = {(uint32_t)p, (uint32_t)(p >> 32), (uint32_t)(1 + b), (uint32_t)(n >> 1)};
+        uint32_t c[4] = {(uint32_t)p, (uint32_t)(p >> 32), (uint32_t)(1 + b), (uint32_t)hn};
         philox10(c, seed, 0x80000003u);
         const double u1 = unit_open(c[0], c[1]), u2 = unit_open(c[2], c[3]);
         const double rad = sqrt(-2.0 * log(u1));
-        const double zz = (n & 1) ? rad * sin(2.0 * M_PI * u2) : rad * cos(2.0 * M_PI * u2);
-        const double sv = sqrt(g.sigma2 + E) * zz;
-        s_q[b][n] = sv * sv;
+        for (int o = 0; o < 2; ++o) {
+            const int n = 2 * hn + o;
+            if (n >= nsamp) break;
+            double E = 0.0;
+            for (int q = 0; q <= kMdnBg; ++q) {
+                const double a = s_arr[q][b][0];
+                if (!(a == a)) continue;
+                const double n0 = s_arr[q][b][1];
+                if ((double)n < n0 || (double)n >= n0 + g.ts) continue;
+                const double amp = s_arr[q][b][2];
+                const double env = exp(-((double)n - a) / g.decay);
+                E += (amp * env) * (amp * env);
+            }
+            const double zz = o ? rad * sin(2.0 * M_PI * u2) : rad * cos(2.0 * M_PI * u2);
+            const double sv = sqrt(g.sigma2 + E) * zz;
+            s_q[b][n] = sv * sv;
+        }
     }
     __syncthreads();
     const double ls2 = log(g.sigma2);
@@ -823,12 +847,9 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     int nout = kMdnOutPad;
     for (int l = 2; l >= 0; --l) {
         // dA_l = dOut W_{l+1}; dH_l = dA_l * GELU'(Z_l)
-        e = gemm<false, false, 0>(M, kMdnHid, nout, dnext, nout, hcopy + L.Wh[l + 1], kMdnHid,
-                                  B.dA, kMdnHid, nullptr, nullptr, 0, s);
+        e = gemm<false, false, 3>(M, kMdnHid, nout, dnext, nout, hcopy + L.Wh[l + 1], kMdnHid,
+                                  nullptr, kMdnHid, B.Z[l], B.dH[l & 1], kMdnHid, s);
         if (e) return e;
-        const long n = (long)M * kMdnHid;
-        k_gelu_back<<<grid_for(n), 256, 0, s>>>(n, B.dA, B.Z[l], B.dH[l & 1]);
-        if ((e = hipGetLastError())) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
         e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l], B.part, s);
@@ -846,18 +867,15 @@ hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, f
     const MdnLayout L = mdn_layout();
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    float *mo = params + L.np, *ve = params + 2 * L.np;
+    AdamCopies cp;
     for (int l = 0; l < 4; ++l) {
-        const long nw = (long)L.fin[l] * L.fout[l];
-        k_adam<<<grid_for(nw), 256, 0, s>>>(nw, params + L.W[l], mo + L.W[l], ve + L.W[l],
-                                           grad + L.W[l], hcopy + L.Wh[l], lr, b1, b2, eps, c1, c2);
-        hipError_t e = hipGetLastError();
-        if (e) return e;
-        k_adam<<<1, 256, 0, s>>>(L.fout[l], params + L.b[l], mo + L.b[l], ve + L.b[l],
-                                 grad + L.b[l], nullptr, lr, b1, b2, eps, c1, c2);
-        if ((e = hipGetLastError())) return e;
+        cp.w[l] = L.W[l];
+        cp.nw[l] = (long)L.fin[l] * L.fout[l];
+        cp.wh[l] = L.Wh[l];
     }
-    return hipSuccess;
+    k_adam_all<<<grid_for(L.np), 256, 0, s>>>(L.np, params, params + L.np, params + 2 * L.np, grad,
+                                              hcopy, cp, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
 }
 
 hipError_t mdn_pairs(const Geo &g, uint32_t seed, long first, int count, __bf16 *X, float *Zt,
