@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-parallel", action="store_true",
                     help="skip the oracle on all host threads (context for the CPU baseline)")
     ap.add_argument("--traffic", default=os.path.join(
-                        ROOT, "profiles", "k_sweep_color-s64x64-n144000-dyn64x64-f32.traffic.json"),
+                        ROOT, "profiles", "k_sweep_spec-s64x64-n144000-dyn64x64-f32.traffic.json"),
                     help="JSON with rocprofv3 FETCH_SIZE/WRITE_SIZE bytes per sweep-kernel launch; "
                          "used only while the kernel source hash it records is current")
     ap.add_argument("--no-batched", action="store_true",

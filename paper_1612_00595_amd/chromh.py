@@ -578,11 +578,18 @@ class MDN:
                                        _stream()))
 
 
-def mdn_pairs(model: ModelSpec, seed: int, first: int, count: int, device="cuda"):
-    """Training pairs from the forward simulator: (bf16 [count, 576], f32 [count, 3])."""
+def mdn_pairs(model: ModelSpec, seed: int, first: int, count: int, device="cuda", out=None):
+    """Training pairs from the forward simulator: (bf16 [count, 576], f32 [count, 3]),
+    written into out = (X, Z) when given."""
     import torch
-    X = torch.empty((count, 576), dtype=torch.bfloat16, device=device)
-    Z = torch.empty((count, 3), dtype=torch.float32, device=device)
+    if out is None:
+        X = torch.empty((count, 576), dtype=torch.bfloat16, device=device)
+        Z = torch.empty((count, 3), dtype=torch.float32, device=device)
+    else:
+        X, Z = out
+        if X.shape != (count, 576) or Z.shape != (count, 3) or X.dtype != torch.bfloat16 \
+                or Z.dtype != torch.float32 or not (X.is_contiguous() and Z.is_contiguous()):
+            raise ValueError("out must be contiguous bf16 [count, 576] and f32 [count, 3]")
     m = model_struct(model)
     check(lib().cmh_mdn_pairs(C.byref(m), seed, first, count, _ptr(X), _ptr(Z), _stream()))
     return X, Z

@@ -36,10 +36,13 @@ def train(model: ModelSpec, pairs: int = 10_000_000, batch: int = 8192, lr: floa
     steps = max(1, pairs // batch)
     losses = []
     loss_buf = torch.empty(batch, dtype=torch.float32, device=device)
+    pairs_buf = (torch.empty((batch, 576), dtype=torch.bfloat16, device=device),
+                 torch.empty((batch, 3), dtype=torch.float32, device=device))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(1, steps + 1):
-        X, Z = chromh.mdn_pairs(model, seed, (step - 1) * batch, batch, device)
+        # the stream orders each step's pairs after the previous step's use of them
+        X, Z = chromh.mdn_pairs(model, seed, (step - 1) * batch, batch, device, out=pairs_buf)
         net.train_step(X, Z, step, lr, loss=loss_buf)
         if log_every and (step % log_every == 0 or step == steps):
             losses.append((step, float(loss_buf.mean())))
