@@ -166,6 +166,59 @@ def test_replay_parity_full_size_large():
         torch.cuda.empty_cache()
 
 
+def test_replay_parity_full_size_at_steady_state():
+    """The 64x64-station workload at the posterior's event count: a state
+    from 300 Philox sweeps is written into fresh samplers of every form and
+    into the oracle, then both replay two fed sweeps.  Most accepted moves
+    there are location, onset and magnitude changes of distinct events, so
+    the speculative forms commit several moves per round; every form must
+    still give the oracle's chain."""
+    w = W.LARGE
+    m, sp, truth, s = instance(w)
+    trace = torch.from_numpy(s).to(DEV)
+    first, nsw = 300, 2
+    say("burn-in to sweep", first)
+    base = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3,
+                                   block=chromh.SPEC4)
+    base.run_sweeps(0, first)
+    ev = base.read_events(0)
+    base.close()
+    say("state events", len(ev))
+    assert len(ev) > 15000
+    feed = W.feed_draws(w.sampler, nsw, seed=41)
+    R, k = w.sampler.nreg, w.sampler.k
+    ref = O.Chain(m, sp, s, seed=3)
+    assert ref.set_events(O.as_events(ev["x"], ev["y"], ev["t"], ev["m"], ev["id"])) == 0
+    rlog = np.full((nsw, R, k, 4), -1.0)
+    for q in range(nsw):
+        assert ref.sweep(first + q, feed=np.ascontiguousarray(feed[q]), log=rlog[q]) == 0
+    rev = ref.events()
+    fd = torch.from_numpy(feed).to(DEV)
+    for block in (64, 256, chromh.SPEC2, chromh.SPEC4, chromh.SPEC8):
+        say("gpu form", block)
+        gpu = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=1, seed=3, block=block)
+        gpu.write_events(0, ev)
+        gpu.set_feed(fd, first)
+        glog = torch.full((nsw, R, k, 4), -1.0, dtype=torch.float64, device=DEV)
+        gpu.set_log(glog, first)
+        gpu.run_sweeps(first, nsw)
+        acc = LogCheck()
+        exact = True
+        for q in range(nsw):
+            if not compare_logs(glog[q].cpu().numpy(), rlog[q], feed[q], acc,
+                                f"form {block} sweep {first + q}"):
+                exact = False  # a decision inside the tie band: the chains may part here
+                say("decision tie in sweep", first + q)
+                break
+        if exact:
+            compare_events(gpu.read_events(0), rev, f"form {block}")
+        assert acc.evaluated > 30000
+        say("evaluated", acc.evaluated, "ties", acc.ties, "max rel", acc.max_rel)
+        gpu.close()
+        del gpu, glog
+        torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------ state and replays
 
 def test_refresh_matches_oracle():
