@@ -555,6 +555,21 @@ int32_t cmh_mdn_train_step(void *params_dev, const void *x_dev, const float *z_d
 int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair, int32_t count,
                       void *x_dev, float *z_dev, void *hip_stream);
 
+/* Training (§3's model as the simulator of the pairs; the network and loss
+ * of cmh_mdn_gradients): `steps` Adam steps in one call, step s (0-based)
+ * drawing rows pairs first_pair + s rows .. first_pair + (s + 1) rows - 1
+ * into x_dev[rows][576] / z_dev[rows][3] (as cmh_mdn_pairs) and taking one
+ * step of cmh_mdn_train_step at Adam step step0 + s.  Everything is enqueued
+ * on hip_stream; the caller's buffers: x_dev (16-byte aligned), z_dev, the
+ * work buffer of cmh_mdn_work_bytes(rows), and loss_dev[rows] (optional)
+ * which receives the last step's per-pair losses.  Errors: CMH_EINVAL for a
+ * line or mean-template model, rows outside 1..2^20, steps < 1, step0 < 1,
+ * negative first_pair, NULL or misaligned buffers, a short work buffer. */
+int32_t cmh_mdn_train(void *params_dev, const cmh_model *model, uint32_t seed, int64_t first_pair,
+                      int32_t steps, int32_t rows, int32_t step0, float lr, void *x_dev,
+                      float *z_dev, float *loss_dev, void *work_dev, size_t work_bytes,
+                      void *hip_stream);
+
 /* Anchors of an instance: every station c (row-major) times window starts
  * tau = 32 i (tau + 67 <= n_samples); anchor index = c * n_tau + i.
  * CMH_EINVAL below 67 samples. */

@@ -62,7 +62,8 @@ EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_
            "cmh_move_draws", "cmh_move_draws_arrivals", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_infer",
-           "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_pairs", "cmh_anchor_count",
+           "cmh_mdn_gradients", "cmh_mdn_train_step", "cmh_mdn_train", "cmh_mdn_pairs",
+           "cmh_anchor_count",
            "cmh_anchor_features", "cmh_mixture_table", "cmh_learned_bytes",
            "cmh_set_learned", "cmh_set_record", "cmh_batch_bytes", "cmh_batch_init",
            "cmh_batch_learned_bytes", "cmh_batch_set_learned", "cmh_checkpoint_bytes", "cmh_save",
@@ -130,6 +131,8 @@ def lib():
         "cmh_mdn_gradients": ([P, P, P, I32, P, P, P, C.c_size_t, P], I32),
         "cmh_mdn_train_step": ([P, P, P, I32, I32, C.c_float, P, P, C.c_size_t, P], I32),
         "cmh_mdn_pairs": ([P, U32, I64, I32, P, P, P], I32),
+        "cmh_mdn_train": ([P, P, U32, I64, I32, I32, I32, C.c_float, P, P, P, P, C.c_size_t, P],
+                          I32),
         "cmh_anchor_count": ([P, P, P], I32),
         "cmh_anchor_features": ([P, P, I32, I64, I32, P, P, P], I32),
         "cmh_mixture_table": ([P, P, I64, I32, P, P], I32),
@@ -576,6 +579,23 @@ class MDN:
         check(lib().cmh_mdn_train_step(_ptr(self.params), _ptr(X), _ptr(Z), rows, step, lr,
                                        None if loss is None else _ptr(loss), _ptr(w), w.numel(),
                                        _stream()))
+
+    def train(self, model: ModelSpec, seed: int, first_pair: int, steps: int, rows: int,
+              step0: int, lr: float, pairs, loss=None):
+        """steps Adam steps on fresh simulator pairs in one library call (see
+        cmh_mdn_train); pairs = (X bf16 [rows, 576], Z f32 [rows, 3]) buffers."""
+        import torch
+        X, Z = pairs
+        if X.shape != (rows, 576) or Z.shape != (rows, 3) or X.dtype != torch.bfloat16 \
+                or Z.dtype != torch.float32 or not (X.is_contiguous() and Z.is_contiguous()):
+            raise ValueError("pairs must be contiguous bf16 [rows, 576] and f32 [rows, 3]")
+        if loss is not None and (loss.numel() < rows or loss.dtype != torch.float32):
+            raise ValueError("loss must be f32 with at least rows elements")
+        w = self.work(rows)
+        m = model_struct(model)
+        check(lib().cmh_mdn_train(_ptr(self.params), C.byref(m), seed, first_pair, steps, rows,
+                                  step0, lr, _ptr(X), _ptr(Z), None if loss is None else _ptr(loss),
+                                  _ptr(w), w.numel(), _stream()))
 
 
 def mdn_pairs(model: ModelSpec, seed: int, first: int, count: int, device="cuda", out=None):

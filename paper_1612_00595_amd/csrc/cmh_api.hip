@@ -2299,6 +2299,41 @@ int32_t cmh_mdn_pairs(const cmh_model *model, uint32_t seed, int64_t first_pair,
     return CMH_OK;
 }
 
+int32_t cmh_mdn_train(void *params_dev, const cmh_model *model, uint32_t seed, int64_t first_pair,
+                      int32_t steps, int32_t rows, int32_t step0, float lr, void *x_dev,
+                      float *z_dev, float *loss_dev, void *work_dev, size_t work_bytes,
+                      void *hip_stream)
+{
+    int32_t rc = check_model(model);
+    if (rc) return rc;
+    if (model->line || model->template_mean)
+        return fail(CMH_EINVAL, "training pairs need the grid model's variance signals");
+    if ((rc = check_rows(rows))) return rc;
+    if (steps < 1 || step0 < 1 || first_pair < 0)
+        return fail(CMH_EINVAL, "steps and step0 count from 1, first_pair from 0");
+    if (!params_dev || !x_dev || !z_dev || !work_dev) return fail(CMH_EINVAL, "NULL argument");
+    if ((rc = check_aligned(x_dev, "x_dev")) || (rc = check_aligned(work_dev, "work_dev")))
+        return rc;
+    if (work_bytes < carve_mdn_work(rows, nullptr, nullptr, nullptr))
+        return fail(CMH_EINVAL, "work buffer too small");
+    Geo g;
+    model_geo(model, &g);
+    cmh::MdnBuffers B;
+    float *grad = nullptr;
+    carve_mdn_work(rows, (char *)work_dev, &B, &grad);
+    const MdnBlob b = mdn_blob(params_dev);
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int32_t q = 0; q < steps; ++q) {
+        if (loss_dev && q == steps - 1) B.loss = loss_dev;
+        HIPCHK(cmh::mdn_pairs(g, seed, first_pair + (int64_t)q * rows, rows, (__bf16 *)x_dev,
+                              z_dev, s));
+        HIPCHK(cmh::mdn_backward(b.params, b.hcopy, (const __bf16 *)x_dev, z_dev, rows, B, grad,
+                                 s));
+        HIPCHK(cmh::mdn_adam(b.params, b.hcopy, grad, step0 + q, lr, s));
+    }
+    return CMH_OK;
+}
+
 int32_t cmh_anchor_count(const cmh_model *model, int32_t *n_anchors, int32_t *n_tau)
 {
     int32_t rc = check_model(model);

@@ -40,12 +40,16 @@ def train(model: ModelSpec, pairs: int = 10_000_000, batch: int = 8192, lr: floa
                  torch.empty((batch, 3), dtype=torch.float32, device=device))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for step in range(1, steps + 1):
-        # the stream orders each step's pairs after the previous step's use of them
-        X, Z = chromh.mdn_pairs(model, seed, (step - 1) * batch, batch, device, out=pairs_buf)
-        net.train_step(X, Z, step, lr, loss=loss_buf)
-        if log_every and (step % log_every == 0 or step == steps):
-            losses.append((step, float(loss_buf.mean())))
+    chunk = log_every if log_every else steps
+    step = 1
+    while step <= steps:
+        # pairs and steps step .. step + n - 1 in one library call; the stream
+        # orders each step's pairs after the previous step's use of the buffers
+        n = min(chunk, steps - step + 1)
+        net.train(model, seed, (step - 1) * batch, n, batch, step, lr, pairs_buf, loss=loss_buf)
+        step += n
+        if log_every:
+            losses.append((step - 1, float(loss_buf.mean())))
     torch.cuda.synchronize()
     seconds = time.perf_counter() - t0
     Xh, Zh = chromh.mdn_pairs(model, seed, 1 << 40, held_out, device)

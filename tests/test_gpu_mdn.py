@@ -8,8 +8,9 @@ re-rounding of hidden activations and backpropagated gradients whose FP32
 values land on the other side of a rounding boundary (one BF16 ulp, 2^-8
 relative, for a small fraction of entries).  Over 256-long dot products
 those flips average out to about 2^-8 / sqrt(256) of the output scale, so
-head outputs agree to 1e-2 of their RMS, and gradients (which pass such
-flips through three layers) to 3e-2 of each tensor's norm.
+head outputs agree to 1e-2 of their RMS; gradients are bounded element by
+element by the BF16 flip bound taken from the oracle's absolute-value
+products.
 """
 import numpy as np
 import pytest
@@ -217,6 +218,31 @@ def test_mdn_adam_step_matches_oracle(torch_dev):
         assert np.allclose(after[name][clear], want[clear], rtol=0, atol=2e-3 * lr), name
         assert np.all(np.abs(after[name] - P[name]) <= lr * (1 + 1e-5) + 1e-7), name
     assert checked > 200
+
+
+def test_mdn_training_loop_equals_single_steps(torch_dev):
+    """cmh_mdn_train (pairs and Adam steps enqueued by the library) gives the
+    parameters and last losses of the same steps taken one call at a time."""
+    from paper_1612_00595_amd import chromh
+    torch = torch_dev
+    rows, steps, lr, seed = 1024, 6, 1e-3, 9
+    say("[mdn] training loop against single steps")
+    a, b = chromh.MDN(seed=4), chromh.MDN(seed=4)
+    la = torch.empty(rows, dtype=torch.float32, device="cuda")
+    for q in range(steps):
+        X, Z = chromh.mdn_pairs(W.SMALL.model, seed, 17 + q * rows, rows)
+        a.train_step(X, Z, 3 + q, lr, loss=la)
+    buf = (torch.empty((rows, 576), dtype=torch.bfloat16, device="cuda"),
+           torch.empty((rows, 3), dtype=torch.float32, device="cuda"))
+    lb = torch.empty(rows, dtype=torch.float32, device="cuda")
+    b.train(W.SMALL.model, seed, 17, steps, rows, 3, lr, buf, loss=lb)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert torch.equal(la, lb)
+    with pytest.raises(chromh.CmhError):
+        b.train(W.PAPER1D.model, seed, 0, 1, rows, 1, lr, buf)   # no training pairs on the line
+    with pytest.raises(chromh.CmhError):
+        b.train(W.SMALL.model, seed, 0, 0, rows, 1, lr, buf)     # no steps
 
 
 def test_mdn_pairs_match_oracle(torch_dev):
