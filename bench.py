@@ -186,17 +186,20 @@ def small_full(dev):
 MDN_FWD_FLOP = 2 * (576 * 256 + 2 * 256 * 256 + 256 * 64)
 MDN_TRAIN_FLOP = 3 * MDN_FWD_FLOP
 BF16_PEAK_TFLOPS = 2500.0
-ESS_CHAINS = 8
 F1_EVERY = 50
+
+
+LEARNED_MAX_EVENTS = 96   # recorded events per chain and sweep (the worlds hold ~20)
 
 
 def learned_study(args, dev):
     """The learned birth proposal against the plain sampler on 5x5-station,
     1000-sample worlds (seeds 100, 101, ...): the network trained on fresh
-    simulator pairs, then per world the same chains with and without
-    learned births, sweeps timed with device-side recording of every
-    state, F1 of the final states and event-location ESS after a quarter of
-    burn-in."""
+    simulator pairs, then every (world, chain) of a mode as one instance of a
+    single batch (one launch per colour for all of them), with and without
+    learned births (each world's own anchor table), every state recorded on
+    the device; F1 of the final states, F1 against sweeps, and event-location
+    ESS after a quarter of burn-in."""
     import numpy as np
     import torch
 
@@ -205,74 +208,85 @@ def learned_study(args, dev):
     log(f"[bench] training the proposal network on {args.learned_pairs} simulator pairs")
     tr = learned.train(w.model, pairs=args.learned_pairs, batch=8192, lr=1e-3, seed=0)
     train_tflops = tr.pairs * MDN_TRAIN_FLOP / tr.seconds / 1e12
-    out = {"workload": w.name + " worlds", "worlds": args.learned_worlds,
-           "chains": args.learned_chains, "sweeps": args.learned_sweeps,
+    nw, nc = args.learned_worlds, args.learned_chains
+    out = {"workload": w.name + " worlds", "worlds": nw, "chains": nc,
+           "sweeps": args.learned_sweeps, "batch_instances": nw * nc,
            "train": {"pairs": tr.pairs, "batch": 8192, "seconds": tr.seconds,
                      "held_out_nll": tr.held_out, "achieved_TFLOPs": train_tflops,
                      "mfma_frac": train_tflops / BF16_PEAK_TFLOPS}}
-    per = {"plain": [], "learned": []}
+    truths, traces, tables = [], [], []
     infer_s = 0.0
-    for wi in range(args.learned_worlds):
+    for wi in range(nw):
         seed = 100 + wi
         tr_ev = W.truth_events(w.model, seed)
+        truths.append(tr_ev)
         truth = chromh.as_events(tr_ev["x"], tr_ev["y"], tr_ev["t"], tr_ev["m"])
-        trace = chromh.simulate(w.model, truth, 1000 + seed, w.trace_dtype, dev)
+        traces.append(chromh.simulate(w.model, truth, 1000 + seed, w.trace_dtype, dev))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        T, wt, ntau = learned.anchor_table(tr.net, w.model, trace)
+        tables.append(learned.anchor_table(tr.net, w.model, traces[-1]))
         torch.cuda.synchronize()
         infer_s += time.perf_counter() - t0
-        for mode in ("plain", "learned"):
-            smp = chromh.ChromaticSampler(w.model, w.sampler, trace, chains=args.learned_chains,
-                                          seed=seed)
-            if mode == "learned":
-                smp.set_learned(T, wt, ntau, 0.5)
-            rec = smp.set_record(0, args.learned_sweeps + 1, 256)
-            smp.run_sweeps(0, 1)            # graphs built outside the timed region
-            torch.cuda.synchronize()
-            c0 = sum(smp.read_counters(c) for c in range(args.learned_chains))
-            t0 = time.perf_counter()
-            smp.run_sweeps(1, args.learned_sweeps)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            st = sum(smp.read_counters(c) for c in range(args.learned_chains)) - c0
-            f1, ess = [], []
-            curve = np.zeros(len(range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY)))
-            for c in range(args.learned_chains):
-                states = chromh.ChromaticSampler.recorded_states(rec[1:], c)
-                f1.append(M.match(tr_ev, states[-1]).f1)
-                curve += [M.match(tr_ev, states[q]).f1
-                          for q in range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY)]
-                if c < ESS_CHAINS:          # ESS per chain from a subset of the chains
-                    e, k = M.location_ess(states, tr_ev)
-                    ess.append(e if k else np.nan)
-            tab = st[:15].reshape(5, 3).astype(float)
-            per[mode].append(dict(seconds=el, f1=f1, ess=ess, curve=curve / args.learned_chains,
-                                  proposals=float(tab[:, 0].sum()),
-                                  acc=(tab[:, 2] / np.maximum(tab[:, 0], 1)).tolist()))
-            smp.close()
-        del trace, T, wt
+    q_of = [(wi, c) for wi in range(nw) for c in range(nc)]
+    per = {}
+    checkpoints = list(range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY))
     for mode in ("plain", "learned"):
-        rs = per[mode]
+        b = chromh.Batch([w.model] * len(q_of), [w.sampler] * len(q_of),
+                         [traces[wi] for wi, c in q_of],
+                         [(100 + wi) * 1000 + c for wi, c in q_of])
+        if mode == "learned":
+            for q, (wi, c) in enumerate(q_of):
+                T, wt, ntau = tables[wi]
+                b.set_learned_instance(q, T, wt, ntau, 0.5)
+        rec = b.set_record(0, args.learned_sweeps + 1, LEARNED_MAX_EVENTS)
+        b.run_sweeps(0, 1)            # graphs built outside the timed region
+        torch.cuda.synchronize()
+        c0 = [b.read_counters(q) for q in range(len(q_of))]
+        t0 = time.perf_counter()
+        b.run_sweeps(1, args.learned_sweeps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = sum(b.read_counters(q) - c0[q] for q in range(len(q_of)))
+        recc = rec[1:].cpu().numpy()
+        b.set_record(0, 0, 0)
+        block = b.block
+        b.close()
+        del rec
+        f1 = np.zeros((nw, nc))
+        ess = np.full((nw, nc), np.nan)
+        curve = np.zeros((nw, len(checkpoints)))
+        for q, (wi, c) in enumerate(q_of):
+            states = chromh.ChromaticSampler.recorded_states(recc, q)
+            f1[wi, c] = M.match(truths[wi], states[-1]).f1
+            curve[wi] += [M.match(truths[wi], states[k]).f1 for k in checkpoints]
+            e, k = M.location_ess(states, truths[wi])
+            if k:
+                ess[wi, c] = e
+        del recc
+        tab = st[:15].reshape(5, 3).astype(float)
+        per[mode] = dict(seconds=el, f1=f1, ess=ess, curve=curve / nc, block=block,
+                         proposals=float(tab[:, 0].sum()),
+                         acc=(tab[:, 2] / np.maximum(tab[:, 0], 1)).tolist())
+        torch.cuda.empty_cache()
+    for mode in ("plain", "learned"):
+        r = per[mode]
         # worlds are the independent units: the interval is over world means
-        mean, lo, hi = M.bootstrap_ci(np.array([np.mean(r["f1"]) for r in rs]))
-        # ESS/s per GPU: mean ESS per chain times the chains that run together
-        ess_s = [np.nanmean(r["ess"]) * args.learned_chains / r["seconds"] for r in rs]
+        mean, lo, hi = M.bootstrap_ci(r["f1"].mean(axis=1))
+        ess_chain = float(np.nanmean(r["ess"]))
         out[mode] = {"f1": mean, "f1_ci95": [lo, hi],
-                     "ess_per_s": float(np.mean(ess_s)),
-                     "ess_per_sweep_chain": float(np.nanmean([np.nanmean(r["ess"]) for r in rs]))
-                     / args.learned_sweeps,
-                     "proposals_per_s": float(np.mean([r["proposals"] / r["seconds"] for r in rs])),
-                     "ms_per_sweep": float(np.mean([r["seconds"] for r in rs]))
-                     * 1e3 / args.learned_sweeps,
-                     "acceptance_birth_death_loc_time_mag": np.mean([r["acc"] for r in rs],
-                                                                    axis=0).round(4).tolist()}
+                     # ESS/s per GPU: mean ESS per chain times the chains that run together
+                     "ess_per_s": ess_chain * len(q_of) / r["seconds"],
+                     "ess_per_sweep_chain": ess_chain / args.learned_sweeps,
+                     "proposals_per_s": r["proposals"] / r["seconds"],
+                     "ms_per_sweep": r["seconds"] * 1e3 / args.learned_sweeps,
+                     "block": r["block"],
+                     "acceptance_birth_death_loc_time_mag": np.round(r["acc"], 4).tolist()}
     pl, le = out["plain"], out["learned"]
     out["ess_per_s_ratio"] = le["ess_per_s"] / pl["ess_per_s"]
     # F1 against wall time (mean over worlds and chains, every F1_EVERY
     # sweeps): when the learned chains first reach the plain chains' final F1
-    cp = np.mean([r["curve"] for r in per["plain"]], axis=0)
-    cl = np.mean([r["curve"] for r in per["learned"]], axis=0)
+    cp = per["plain"]["curve"].mean(axis=0)
+    cl = per["learned"]["curve"].mean(axis=0)
     sw = np.arange(F1_EVERY, args.learned_sweeps + 1, F1_EVERY)
     hit = np.nonzero(cl >= cp[-1])[0]
     out["f1_curve"] = {"sweeps": sw.tolist(), "plain": cp.round(4).tolist(),
@@ -286,11 +300,12 @@ def learned_study(args, dev):
                            (le["f1_ci95"][0] <= pl["f1_ci95"][1]
                             and pl["f1_ci95"][0] <= le["f1_ci95"][1]))
     na = w.model.nsta * ((w.model.N - 67) // 32 + 1)
-    out["inference"] = {"anchors_per_world": na,
-                        "seconds_per_world": infer_s / args.learned_worlds}
-    log(f"[bench] learned study: F1 plain {pl['f1']:.3f} learned {le['f1']:.3f}; ESS/s plain "
-        f"{pl['ess_per_s']:.4g} learned {le['ess_per_s']:.4g}; training {tr.seconds:.2f} s "
-        f"({train_tflops:.1f} TFLOP/s)")
+    out["inference"] = {"anchors_per_world": na, "seconds_per_world": infer_s / nw}
+    log(f"[bench] learned study ({len(q_of)} chains in one batch): F1 plain {pl['f1']:.3f} "
+        f"learned {le['f1']:.3f}; ESS/s plain {pl['ess_per_s']:.4g} learned "
+        f"{le['ess_per_s']:.4g}; {pl['ms_per_sweep']:.3f} / {le['ms_per_sweep']:.3f} ms per "
+        f"sweep; training {tr.seconds:.2f} s ({train_tflops:.1f} TFLOP/s)")
+    del traces, tables
     return out, tr.net
 
 
