@@ -302,29 +302,26 @@ __device__ inline void learned_windows(const Learned &L, double t, int *ilo, int
 }
 
 // Part of sum over anchors a of the stations sta[0..ns) and windows
-// [ilo, ihi] of w_a sum_k pi_k TN_k(x, y, t): (station, window) pairs
-// first, first + stride, ...  TN_k is the component's Gaussian truncated at
-// 4 sd per axis and renormalised.
+// [ilo, ihi] of w_a sum_k pi_k TN_k(x, y, t): (station, window, component)
+// triples first, first + stride, ...  TN_k is the component's Gaussian
+// truncated at 4 sd per axis and renormalised.
 __device__ inline double learned_part(const Learned &L, const int *sta, int ns, int ilo, int ihi,
                                       double x, double y, double t, int first, int stride)
 {
     const int nw = ihi - ilo + 1;
     double S = 0.0;
     if (nw <= 0) return S;
-    for (int p = first; p < ns * nw; p += stride) {
-        const int q = p / nw;
-        const long long a = (long long)sta[q] * L.ntau + ilo + (p - q * nw);
-        const double *T = L.tab + a * 64;
-        const double *nr = L.norm + a * 8;
-        double qa = 0.0;
-        for (int k = 0; k < 8; ++k) {
-            const double ux = (x - T[8 * k + 0]) / T[8 * k + 3];
-            const double uy = (y - T[8 * k + 1]) / T[8 * k + 4];
-            const double ut = (t - T[8 * k + 2]) / T[8 * k + 5];
-            if (fabs(ux) <= 4.0 && fabs(uy) <= 4.0 && fabs(ut) <= 4.0)
-                qa += exp(nr[k] - 0.5 * (ux * ux + uy * uy + ut * ut));
-        }
-        S += L.w[a] * qa;
+    const int per = nw * 8;
+    for (int p = first; p < ns * per; p += stride) {
+        const int q = p / per, r = p - q * per;
+        const int k = r & 7;
+        const long long a = (long long)sta[q] * L.ntau + ilo + (r >> 3);
+        const double *T = L.tab + a * 64 + 8 * k;
+        const double ux = (x - T[0]) / T[3];
+        const double uy = (y - T[1]) / T[4];
+        const double ut = (t - T[2]) / T[5];
+        if (fabs(ux) <= 4.0 && fabs(uy) <= 4.0 && fabs(ut) <= 4.0)
+            S += L.w[a] * exp(L.norm[a * 8 + k] - 0.5 * (ux * ux + uy * uy + ut * ut));
     }
     return S;
 }
