@@ -288,7 +288,7 @@ def learned_study(args, dev):
     cp = per["plain"]["curve"].mean(axis=0)
     cl = per["learned"]["curve"].mean(axis=0)
     sw = np.arange(F1_EVERY, args.learned_sweeps + 1, F1_EVERY)
-    hit = np.nonzero(cl >= cp[-1])[0]
+    hit = np.nonzero(cl >= cp[-1])[0] if len(cp) else []
     out["f1_curve"] = {"sweeps": sw.tolist(), "plain": cp.round(4).tolist(),
                        "learned": cl.round(4).tolist()}
     if len(hit):
