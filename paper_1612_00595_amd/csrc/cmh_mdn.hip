@@ -38,9 +38,10 @@ __device__ inline float gelu_grad_f(float z)
 // : A[m*lda + k]; op(B)[k][n] = TB ? B[n*ldb + k] : B[k*ldb + n].  A
 // workgroup of four waves (2 x 2) computes a (2 WM) x (2 WN) tile, each wave
 // WM x WN as (WM/16) x (WN/16) MFMA 16x16x32 BF16 tiles with FP32
-// accumulators.  k-steps of 32 go through double-buffered LDS: the next
-// step's global loads are in flight while the current step's MFMAs run, one
-// barrier per step.  Loads are 16 bytes per lane along the operand's
+// accumulators.  k-steps of KS (whole MFMA k-slices of 32, taken in
+// ascending order) go through double-buffered LDS: the next step's global
+// loads are in flight while the current step's MFMAs run, one barrier per
+// step; longer steps keep more loads in flight per barrier.  Loads are 16 bytes per lane along the operand's
 // contiguous dimension, so the contiguous extents (M for TA, K otherwise,
 // and N for !TB) and the leading dimensions must be multiples of 8.
 // EPI 0: C (fp32).  EPI 1: Z = C + bias (fp32) and GELU(Z) as BF16 into Cb.
@@ -48,17 +49,20 @@ __device__ inline float gelu_grad_f(float z)
 // into Cb, Z (fp32, row pitch ldc) passed as `bias`; C is not written.
 // Split K: workgroup z sums k in [z kper, (z + 1) kper) and writes its
 // partial product to C + z M ldc (EPI 0 only).
-template <bool TA, bool TB, int EPI, int WM, int WN>
+template <bool TA, bool TB, int EPI, int WM, int WN, int KS = 32>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
        int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
        __bf16 *__restrict__ Cb, int ldcb, int kper)
 {
+    static_assert(KS % 32 == 0, "k-steps of whole MFMA k-slices");
     constexpr int TMR = 2 * WM, TNC = 2 * WN;       // workgroup tile
-    constexpr int NVA = WM / 32, NVB = WN / 32;     // 16-byte loads per lane per step
+    constexpr int NVA = TMR * KS / 2048;            // 16-byte loads per thread per step (A)
+    constexpr int NVB = TNC * KS / 2048;            //                                  (B)
     constexpr int FA = WM / 16, FB = WN / 16;       // MFMA tiles per wave
-    __shared__ __attribute__((aligned(16))) __bf16 sA[2][TMR][40];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[2][TNC][40];
+    constexpr int P = KS + 8;                       // LDS row pitch (bank spread)
+    __shared__ __attribute__((aligned(16))) __bf16 sA[2][TMR][P];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[2][TNC][P];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i0 = blockIdx.y * TMR, j0 = blockIdx.x * TNC;
     const int wi = (wave >> 1) * WM, wj = (wave & 1) * WN;
@@ -83,7 +87,7 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
                 const int gk = k0 + kq, gi = i0 + m8;
                 if (gk < kend && gi < M) ra[u] = *(const bf16x8 *)&A[(long)gk * lda + gi];
             } else {   // A[m][k]: 8 k's of one row
-                const int r = v >> 2, k8 = 8 * (v & 3);
+                const int r = v / (KS / 8), k8 = 8 * (v % (KS / 8));
                 const int gi = i0 + r, gk = k0 + k8;
                 if (gi < M && gk < kend) ra[u] = *(const bf16x8 *)&A[(long)gi * lda + gk];
             }
@@ -93,7 +97,7 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
             const int v = tid + 256 * u;
             rb[u] = (bf16x8){zero, zero, zero, zero, zero, zero, zero, zero};
             if (TB) {  // B[n][k]: 8 k's of one row
-                const int r = v >> 2, k8 = 8 * (v & 3);
+                const int r = v / (KS / 8), k8 = 8 * (v % (KS / 8));
                 const int gj = j0 + r, gk = k0 + k8;
                 if (gj < N && gk < kend) rb[u] = *(const bf16x8 *)&B[(long)gj * ldb + gk];
             } else {   // B[k][n]: 8 n's at one k
@@ -112,14 +116,14 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
 #pragma unroll
                 for (int q = 0; q < 8; ++q) sA[buf][m8 + q][kq] = ra[u][q];
             } else {
-                *(bf16x8 *)&sA[buf][v >> 2][8 * (v & 3)] = ra[u];
+                *(bf16x8 *)&sA[buf][v / (KS / 8)][8 * (v % (KS / 8))] = ra[u];
             }
         }
 #pragma unroll
         for (int u = 0; u < NVB; ++u) {
             const int v = tid + 256 * u;
             if (TB) {
-                *(bf16x8 *)&sB[buf][v >> 2][8 * (v & 3)] = rb[u];
+                *(bf16x8 *)&sB[buf][v / (KS / 8)][8 * (v % (KS / 8))] = rb[u];
             } else {
                 const int kq = v / (TNC / 8), n8 = 8 * (v % (TNC / 8));
 #pragma unroll
@@ -134,20 +138,29 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
         store(0);
     }
     __syncthreads();
-    for (int k0 = kbeg; k0 < kend; k0 += 32) {
-        const bool more = k0 + 32 < kend;
-        if (more) load(k0 + 32);           // in flight during the MFMAs below
-        const int kk = 8 * (lane >> 4);
-        bf16x8 fa[FA], fb[FB];
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+        const bool more = k0 + KS < kend;
+        if (more) load(k0 + KS);           // in flight during the MFMAs below
+        // k-slices of 32 in ascending order: the accumulation order of one
+        // slice per step
 #pragma unroll
-        for (int a = 0; a < FA; ++a) fa[a] = *(const bf16x8 *)&sA[cur][wi + 16 * a + (lane & 15)][kk];
+        for (int ks = 0; ks < KS / 32; ++ks) {
+            if (k0 + 32 * ks >= kend) break;  // the same in every lane
+            const int kk = 32 * ks + 8 * (lane >> 4);
+            bf16x8 fa[FA], fb[FB];
 #pragma unroll
-        for (int b = 0; b < FB; ++b) fb[b] = *(const bf16x8 *)&sB[cur][wj + 16 * b + (lane & 15)][kk];
-#pragma unroll
-        for (int a = 0; a < FA; ++a)
+            for (int a = 0; a < FA; ++a)
+                fa[a] = *(const bf16x8 *)&sA[cur][wi + 16 * a + (lane & 15)][kk];
 #pragma unroll
             for (int b = 0; b < FB; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                fb[b] = *(const bf16x8 *)&sB[cur][wj + 16 * b + (lane & 15)][kk];
+#pragma unroll
+            for (int a = 0; a < FA; ++a)
+#pragma unroll
+                for (int b = 0; b < FB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b],
+                                                                         0, 0, 0);
+        }
         if (more) store(cur ^ 1);
         __syncthreads();
         cur ^= 1;
@@ -547,12 +560,12 @@ static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf
     const long big = (long)((M + 127) / 128) * ((N + 127) / 128);
     if (N >= 128 && big >= kMdnBigTiles) {
         const dim3 grid((N + 127) / 128, (M + 127) / 128, 1);
-        k_gemm<TA, TB, EPI, 64, 64><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
-                                                          Cb, ldcb, K);
+        k_gemm<TA, TB, EPI, 64, 64, 32><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                              bias, Cb, ldcb, K);
     } else {
         const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
-        k_gemm<TA, TB, EPI, 32, 32><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, bias,
-                                                          Cb, ldcb, K);
+        k_gemm<TA, TB, EPI, 32, 32, 128><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                               bias, Cb, ldcb, K);
     }
     return hipGetLastError();
 }
@@ -579,7 +592,7 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
     int per = 0;
     const int nz = mdn_splits(Mb, &per);
     const dim3 grid((N + 63) / 64, (Mo + 63) / 64, nz);
-    k_gemm<true, false, 0, 32, 32><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb,
+    k_gemm<true, false, 0, 32, 32, 128><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb,
                                                         nz > 1 ? part : C, N, nullptr, nullptr, 0,
                                                         per);
     hipError_t e = hipGetLastError();
