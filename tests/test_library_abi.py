@@ -73,6 +73,19 @@ def test_host_validation_errors():
     assert L.cmh_init_state(C.byref(m), C.byref(s), None, 0, 1, 0, None, 0, None,
                             C.byref(h)) == -1
     assert L.cmh_destroy(None) == 0
+    # the training loop: refused before any device work for a model without
+    # training pairs, zero steps, Adam steps from 0, or missing buffers
+    lm = chromh.model_struct(W.PAPER1D.model)
+    args = (None, 0, 0, 8, 1024, 1, C.c_float(1e-3), None, None, None, None, 0, None)
+    assert L.cmh_mdn_train(None, C.byref(lm), *args[1:]) == -1
+    assert b"grid model" in L.cmh_last_error()
+    assert L.cmh_mdn_train(None, C.byref(m), 0, 0, 0, 1024, 1, C.c_float(1e-3), None, None, None,
+                           None, 0, None) == -1
+    assert L.cmh_mdn_train(None, C.byref(m), 0, 0, 4, 1024, 0, C.c_float(1e-3), None, None, None,
+                           None, 0, None) == -1
+    assert L.cmh_mdn_train(None, C.byref(m), 0, 0, 4, 1024, 1, C.c_float(1e-3), None, None, None,
+                           None, 0, None) == -1
+    assert b"NULL" in L.cmh_last_error()
 
 
 @pytest.mark.parametrize("side,grid,dynamic", [(5, 4, 0), (5, 5, 1), (12, 12, 1), (8, 3, 0),
