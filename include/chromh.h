@@ -135,9 +135,12 @@ typedef struct {
                                    workgroup (for many regions per colour), or
                                    CMH_BLOCK_SPEC + 128 / 256 / 512: 2, 4 or 8 waves per
                                    region, each taking one of the region's next moves from
-                                   the same state, the first accepted one committed (the
-                                   chain is the sequential one; not with latent arrivals
-                                   or the naive schedule), or CMH_BLOCK_PERSIST: the
+                                   the same state; the moves stand in order up to the
+                                   first that conflicts with an earlier standing
+                                   acceptance (same event, overlapping samples) or up to
+                                   an accepted birth or death (the chain is the
+                                   sequential one; not with latent arrivals or the naive
+                                   schedule), or CMH_BLOCK_PERSIST: the
                                    one-wave-per-region form as one persistent launch per
                                    sweep over every colour, each chain's (instance's)
                                    colours ordered by its own colour counter, different
