@@ -358,28 +358,31 @@ template <int Q>
 __device__ inline void locate_runs(const SegIndex &six, int nseg, int S, int f0, int stride,
                                    int *run, int *gidx)
 {
-    int base[Q];
+    // runs start at non-decreasing flat positions (fs[0] = 0), so the run of
+    // position f is the number of runs starting at or before f, minus one
+    int cnt[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) { run[q] = 0; base[q] = 0; }
+    for (int q = 0; q < Q; ++q) cnt[q] = 0;
     for (int t0 = 0; t0 < nseg; t0 += 4) {
         const int4 a = *(const int4 *)&six.fs[t0];
-        const int4 b = *(const int4 *)&six.gb[t0];
-        const int fa[4] = {a.x, a.y, a.z, a.w}, ba[4] = {b.x, b.y, b.z, b.w};
+        const int fa[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int f = f0 + q * stride;
+        for (int u = 0; u < 4; ++u) {
+            const bool in = t0 + u < nseg;  // the same in every lane
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool take = t0 + u < nseg && fa[u] <= f;
-                run[q] = take ? t0 + u : run[q];
-                base[q] = take ? ba[u] : base[q];
-            }
+            for (int q = 0; q < Q; ++q) cnt[q] += (in && fa[u] <= f0 + q * stride) ? 1 : 0;
         }
+    }
+    int gb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {  // every table read issued before any is used
+        run[q] = cnt[q] > 0 ? cnt[q] - 1 : 0;
+        gb[q] = six.gb[run[q]];
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int f = f0 + q * stride;
-        gidx[q] = f < S ? base[q] + f : -1;
+        gidx[q] = f < S ? gb[q] + f : -1;
     }
 }
 
