@@ -2130,11 +2130,8 @@ size_t carve_mdn_work(int M, char *base, cmh::MdnBuffers *B, float **grad)
     b.dH[0] = c.take<__bf16>(mh);
     b.dH[1] = c.take<__bf16>(mh);
     b.loss = c.take<float>((size_t)M);
-    // split partials: weight gradients (at most kMdnMaxSplits x 256 x 576) or
-    // bias gradients (one row of 256 per kMdnColRows batch rows)
-    b.part = c.take<float>(std::max((size_t)cmh::kMdnMaxSplits * cmh::kMdnHid * cmh::kMdnIn,
-                                    (size_t)((M + cmh::kMdnColRows - 1) / cmh::kMdnColRows) *
-                                        cmh::kMdnHid));
+    // split partials of every weight and bias gradient, side by side
+    b.part = c.take<float>(cmh::mdn_part_floats(M));
     float *gr = c.take<float>((size_t)L.np);
     if (B) *B = b;
     if (grad) *grad = gr;

@@ -206,15 +206,29 @@ k_col_partial(int M, int N, const __bf16 *__restrict__ D, int ldd, int mper,
         part[(long)blockIdx.y * N + j] = ((s_p[0][c] + s_p[1][c]) + s_p[2][c]) + s_p[3][c];
 }
 
-// out[q] = sum over z of part[z][q] (z ascending).
-__global__ void k_sum_splits(long n, int nz, const float *__restrict__ part, float *__restrict__ out)
+// Several fixed-order split sums in one launch: element q of job j is
+// out[j][q] = sum over z (ascending) of part[j][z n_j + q].
+struct SumJobs {
+    const float *part[8];
+    float *out[8];
+    long n[8], start[9];
+    int nz[8];
+    int njobs;
+};
+
+__global__ void k_sum_jobs(SumJobs J)
 {
-    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
-         q += (long)gridDim.x * blockDim.x) {
-        float s = 0.f;
+    const long total = J.start[J.njobs];
+    for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < total;
+         g += (long)gridDim.x * blockDim.x) {
+        int j = 0;
+        while (j + 1 < J.njobs && g >= J.start[j + 1]) ++j;
+        const long q = g - J.start[j], n = J.n[j];
+        const float *part = J.part[j];
+        float acc = 0.f;
 #pragma unroll 8
-        for (int z = 0; z < nz; ++z) s += part[(long)z * n + q];
-        out[q] = s;
+        for (int z = 0; z < J.nz[j]; ++z) acc += part[(long)z * n + q];
+        J.out[j][q] = acc;
     }
 }
 
@@ -585,9 +599,10 @@ int mdn_splits(int M, int *per)
 }
 
 // Weight gradient C[Mo][N] = sum over the batch of op(A)^T B, split over the
-// batch into partial products (part) and summed in a fixed order.
+// batch into partial products (part) whose fixed-order sum is left to the
+// job list J (summed by one launch for every gradient of a backward pass).
 static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, const __bf16 *B,
-                              int ldb, float *C, float *part, hipStream_t s)
+                              int ldb, float *C, float *part, SumJobs &J, hipStream_t s)
 {
     int per = 0;
     const int nz = mdn_splits(Mb, &per);
@@ -597,23 +612,40 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
                                                         per);
     hipError_t e = hipGetLastError();
     if (e || nz == 1) return e;
-    const long n = (long)Mo * N;
-    k_sum_splits<<<grid_for(n), 256, 0, s>>>(n, nz, part, C);
-    return hipGetLastError();
+    const int j = J.njobs++;
+    J.part[j] = part; J.out[j] = C; J.n[j] = (long)Mo * N; J.nz[j] = nz;
+    J.start[j + 1] = J.start[j] + J.n[j];
+    return hipSuccess;
 }
 
 // Bias gradient db[N] = column sums of D[Mb][N]: partial sums over chunks of
-// kMdnColRows rows (many workgroups), then summed in a fixed order.
+// kMdnColRows rows (many workgroups), their fixed-order sum left to J.
 static hipError_t bias_grad(int Mb, int N, const __bf16 *D, int ldd, float *db, float *part,
-                            hipStream_t s)
+                            SumJobs &J, hipStream_t s)
 {
     const int per = kMdnColRows;
     const int nz = (Mb + per - 1) / per;
     k_col_partial<<<dim3((N + 63) / 64, nz), 256, 0, s>>>(Mb, N, D, ldd, per, part);
     hipError_t e = hipGetLastError();
     if (e) return e;
-    k_sum_splits<<<grid_for(N), 256, 0, s>>>(N, nz, part, db);
-    return hipGetLastError();
+    const int j = J.njobs++;
+    J.part[j] = part; J.out[j] = db; J.n[j] = N; J.nz[j] = nz;
+    J.start[j + 1] = J.start[j] + J.n[j];
+    return hipSuccess;
+}
+
+// Partial-sum floats one backward pass over M rows needs: every layer's
+// weight-gradient splits and bias-gradient chunks side by side.
+size_t mdn_part_floats(int M)
+{
+    int per = 0;
+    const size_t nz = (size_t)mdn_splits(M, &per);
+    const size_t nzb = (size_t)((M + kMdnColRows - 1) / kMdnColRows);
+    const size_t fin[4] = {kMdnIn, kMdnHid, kMdnHid, kMdnHid};
+    const size_t fout[4] = {kMdnHid, kMdnHid, kMdnHid, kMdnOutPad};
+    size_t n = 0;
+    for (int l = 0; l < 4; ++l) n += nz * fin[l] * fout[l] + nzb * fout[l];
+    return n;
 }
 
 MdnLayout mdn_layout()
@@ -851,11 +883,19 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     if (e) return e;
     k_mdn_loss<<<(M + 127) / 128, 128, 0, s>>>(M, B.O, kMdnOutPad, Zt, B.loss, B.dO, kMdnOutPad);
     if ((e = hipGetLastError())) return e;
+    // Every gradient's partials get a region of B.part of their own, so that
+    // one launch at the end sums them all (each in a fixed order).
+    SumJobs J{};
+    int per = 0;
+    const long nz = mdn_splits(M, &per), nzb = (M + kMdnColRows - 1) / kMdnColRows;
+    float *part = B.part;
     // head: dW4 = dO^T A3, db4 = sum dO, dA3 = dO W4
     e = weight_grad(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid, grad + L.W[3],
-                    B.part, s);
+                    part, J, s);
     if (e) return e;
-    if ((e = bias_grad(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3], B.part, s))) return e;
+    part += nz * kMdnOutPad * kMdnHid;
+    if ((e = bias_grad(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3], part, J, s))) return e;
+    part += nzb * kMdnOutPad;
     const __bf16 *dnext = B.dO;
     int nout = kMdnOutPad;
     for (int l = 2; l >= 0; --l) {
@@ -865,13 +905,19 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
         if (e) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
-        e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l], B.part, s);
+        e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l], part, J,
+                        s);
         if (e) return e;
-        if ((e = bias_grad(M, kMdnHid, B.dH[l & 1], kMdnHid, grad + L.b[l], B.part, s))) return e;
+        part += nz * kMdnHid * kin;
+        if ((e = bias_grad(M, kMdnHid, B.dH[l & 1], kMdnHid, grad + L.b[l], part, J, s)))
+            return e;
+        part += nzb * kMdnHid;
         dnext = B.dH[l & 1];
         nout = kMdnHid;
     }
-    return hipSuccess;
+    if (J.njobs == 0) return hipSuccess;
+    k_sum_jobs<<<grid_for(J.start[J.njobs]), 256, 0, s>>>(J);
+    return hipGetLastError();
 }
 
 hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, float lr,

@@ -54,9 +54,10 @@ struct MdnBuffers {
     __bf16 *dO;       // d loss / d head output, M x 64
     __bf16 *dH[2];    // M x 256
     float *loss;      // M
-    float *part;      // split partial sums: kMdnMaxSplits x 256 x 576
+    float *part;      // split partial sums of every gradient: mdn_part_floats(M)
 };
 int mdn_splits(int M, int *per);
+size_t mdn_part_floats(int M);
 
 hipError_t mdn_init(float *params, __bf16 *hcopy, uint32_t seed, hipStream_t s);
 hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s);
