@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--learned-worlds", type=int, default=50)
     ap.add_argument("--learned-sweeps", type=int, default=1000)
     ap.add_argument("--learned-chains", type=int, default=8)
+    ap.add_argument("--learned-block", type=int, default=0,
+                    help="sweep kernel form of the learned study's batches (0: by trial)")
     ap.add_argument("--learned-pairs", type=int, default=10_000_000)
     ap.add_argument("--no-template", action="store_true",
                     help="skip the mean-template likelihood on the main workload's shape")
@@ -191,6 +193,28 @@ F1_EVERY = 50
 
 LEARNED_MAX_EVENTS = 96   # recorded events per chain and sweep (the worlds hold ~20)
 
+# sweep kernel forms a batch is tried with: wave form, latency forms, and the
+# speculative form with two, four and eight waves per region
+TRIAL_FORMS = (64, 128, 256, 1024 + 128, 1024 + 256, 1024 + 512)
+
+
+def pick_form(make, forms, sweeps: int = 3):
+    """Kernel form of a batch by a short trial: make(form) builds the batch,
+    which runs one sweep (graphs built) and then `sweeps` timed ones; the
+    fastest form and every form's time (ms per sweep) are returned."""
+    import torch
+    trial = {}
+    for f in forms:
+        b = make(f)
+        b.run_sweeps(0, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run_sweeps(1, sweeps)
+        torch.cuda.synchronize()
+        trial[f] = (time.perf_counter() - t0) * 1e3 / sweeps
+        b.close()
+    return min(trial, key=trial.get), trial
+
 
 def learned_study(args, dev):
     """The learned birth proposal against the plain sampler on 5x5-station,
@@ -231,13 +255,19 @@ def learned_study(args, dev):
     per = {}
     checkpoints = list(range(F1_EVERY - 1, args.learned_sweeps, F1_EVERY))
     for mode in ("plain", "learned"):
-        b = chromh.Batch([w.model] * len(q_of), [w.sampler] * len(q_of),
-                         [traces[wi] for wi, c in q_of],
-                         [(100 + wi) * 1000 + c for wi, c in q_of])
-        if mode == "learned":
-            for q, (wi, c) in enumerate(q_of):
-                T, wt, ntau = tables[wi]
-                b.set_learned_instance(q, T, wt, ntau, 0.5)
+        def make(form):
+            b = chromh.Batch([w.model] * len(q_of), [w.sampler] * len(q_of),
+                             [traces[wi] for wi, c in q_of],
+                             [(100 + wi) * 1000 + c for wi, c in q_of], block=form)
+            if mode == "learned":
+                for q, (wi, c) in enumerate(q_of):
+                    T, wt, ntau = tables[wi]
+                    b.set_learned_instance(q, T, wt, ntau, 0.5)
+            return b
+        # each mode runs in the form that is fastest for it
+        form, trial = (args.learned_block, None) if args.learned_block else \
+            pick_form(make, TRIAL_FORMS)
+        b = make(form)
         rec = b.set_record(0, args.learned_sweeps + 1, LEARNED_MAX_EVENTS)
         b.run_sweeps(0, 1)            # graphs built outside the timed region
         torch.cuda.synchronize()
@@ -264,7 +294,7 @@ def learned_study(args, dev):
                 ess[wi, c] = e
         del recc
         tab = st[:15].reshape(5, 3).astype(float)
-        per[mode] = dict(seconds=el, f1=f1, ess=ess, curve=curve / nc, block=block,
+        per[mode] = dict(seconds=el, f1=f1, ess=ess, curve=curve / nc, block=block, trial=trial,
                          proposals=float(tab[:, 0].sum()),
                          acc=(tab[:, 2] / np.maximum(tab[:, 0], 1)).tolist())
         torch.cuda.empty_cache()
@@ -280,6 +310,7 @@ def learned_study(args, dev):
                      "proposals_per_s": r["proposals"] / r["seconds"],
                      "ms_per_sweep": r["seconds"] * 1e3 / args.learned_sweeps,
                      "block": r["block"],
+                     "form_trial_ms_per_sweep": r["trial"],
                      "acceptance_birth_death_loc_time_mag": np.round(r["acc"], 4).tolist()}
     pl, le = out["plain"], out["learned"]
     out["ess_per_s_ratio"] = le["ess_per_s"] / pl["ess_per_s"]
@@ -360,20 +391,8 @@ def paper_world_study(args, dev, latent: bool = False):
                             [7919 * (q // nr) + q % nr for q in range(n)], block=block)
 
     for name, sp in scheds.items():
-        # kernel form by a short trial (few work items per colour favour the
-        # latency form, many the wave form)
-        trial = {}
-        forms = (64,) if sp.schedule == 1 else (64, 256) if latent else (64, 128, 256)
-        for block in forms:
-            b = batch(sp, block)
-            b.run_sweeps(0, 1)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            b.run_sweeps(1, 3)
-            torch.cuda.synchronize()
-            trial[block] = time.perf_counter() - t0
-            b.close()
-        block = min(trial, key=trial.get)
+        forms = (64,) if sp.schedule == 1 else (64, 256) if latent else TRIAL_FORMS
+        block, _ = pick_form(lambda f: batch(sp, f), forms)
         b = batch(sp, block)
         rec = b.set_record(0, S + 1, 64)
         b.run_sweeps(0, 1)                 # graphs built outside the timed region
