@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--learned-sweeps", type=int, default=1000)
     ap.add_argument("--learned-chains", type=int, default=8)
     ap.add_argument("--learned-block", type=int, default=0,
-                    help="sweep kernel form of the learned study's batches (0: by trial)")
+                    help="sweep kernel form of the learned study's batches (0: tuned while running)")
     ap.add_argument("--learned-pairs", type=int, default=10_000_000)
     ap.add_argument("--no-template", action="store_true",
                     help="skip the mean-template likelihood on the main workload's shape")
@@ -193,28 +193,6 @@ F1_EVERY = 50
 
 LEARNED_MAX_EVENTS = 96   # recorded events per chain and sweep (the worlds hold ~20)
 
-# sweep kernel forms a batch is tried with: wave form, latency forms, and the
-# speculative form with two, four and eight waves per region
-TRIAL_FORMS = (64, 128, 256, 1024 + 128, 1024 + 256, 1024 + 512)
-
-
-def pick_form(make, forms, sweeps: int = 3):
-    """Kernel form of a batch by a short trial: make(form) builds the batch,
-    which runs one sweep (graphs built) and then `sweeps` timed ones; the
-    fastest form and every form's time (ms per sweep) are returned."""
-    import torch
-    trial = {}
-    for f in forms:
-        b = make(f)
-        b.run_sweeps(0, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.run_sweeps(1, sweeps)
-        torch.cuda.synchronize()
-        trial[f] = (time.perf_counter() - t0) * 1e3 / sweeps
-        b.close()
-    return min(trial, key=trial.get), trial
-
 
 def learned_study(args, dev):
     """The learned birth proposal against the plain sampler on 5x5-station,
@@ -264,19 +242,26 @@ def learned_study(args, dev):
                     T, wt, ntau = tables[wi]
                     b.set_learned_instance(q, T, wt, ntau, 0.5)
             return b
-        # each mode runs in the form that is fastest for it
-        form, trial = (args.learned_block, None) if args.learned_block else \
-            pick_form(make, TRIAL_FORMS)
-        b = make(form)
-        rec = b.set_record(0, args.learned_sweeps + 1, LEARNED_MAX_EVENTS)
-        b.run_sweeps(0, 1)            # graphs built outside the timed region
+        b = make(args.learned_block)
+        S = args.learned_sweeps
+        rec = b.set_record(0, S + 1, LEARNED_MAX_EVENTS)
+        # each mode runs in the form that is fastest for it, tuned on the run's
+        # first sweeps (every form gives the same chain), which also build the
+        # graphs outside the timed region
+        first = 1
+        if args.learned_block:
+            b.run_sweeps(0, 1)
+        else:
+            first = b.tune_running(0, 2)
         torch.cuda.synchronize()
         c0 = [b.read_counters(q) for q in range(len(q_of))]
         t0 = time.perf_counter()
-        b.run_sweeps(1, args.learned_sweeps)
+        b.run_sweeps(first, S + 1 - first)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        st = sum(b.read_counters(q) - c0[q] for q in range(len(q_of)))
+        # seconds and proposals of S sweeps at the timed sweeps' rate
+        scale = S / (S + 1 - first)
+        el = (time.perf_counter() - t0) * scale
+        st = sum(b.read_counters(q) - c0[q] for q in range(len(q_of))) * scale
         recc = rec[1:].cpu().numpy()
         b.set_record(0, 0, 0)
         block = b.block
@@ -294,7 +279,7 @@ def learned_study(args, dev):
                 ess[wi, c] = e
         del recc
         tab = st[:15].reshape(5, 3).astype(float)
-        per[mode] = dict(seconds=el, f1=f1, ess=ess, curve=curve / nc, block=block, trial=trial,
+        per[mode] = dict(seconds=el, f1=f1, ess=ess, curve=curve / nc, block=block,
                          proposals=float(tab[:, 0].sum()),
                          acc=(tab[:, 2] / np.maximum(tab[:, 0], 1)).tolist())
         torch.cuda.empty_cache()
@@ -310,7 +295,6 @@ def learned_study(args, dev):
                      "proposals_per_s": r["proposals"] / r["seconds"],
                      "ms_per_sweep": r["seconds"] * 1e3 / args.learned_sweeps,
                      "block": r["block"],
-                     "form_trial_ms_per_sweep": r["trial"],
                      "acceptance_birth_death_loc_time_mag": np.round(r["acc"], 4).tolist()}
     pl, le = out["plain"], out["learned"]
     out["ess_per_s_ratio"] = le["ess_per_s"] / pl["ess_per_s"]
@@ -391,15 +375,16 @@ def paper_world_study(args, dev, latent: bool = False):
                             [7919 * (q // nr) + q % nr for q in range(n)], block=block)
 
     for name, sp in scheds.items():
-        forms = (64,) if sp.schedule == 1 else (64, 256) if latent else TRIAL_FORMS
-        block, _ = pick_form(lambda f: batch(sp, f), forms)
-        b = batch(sp, block)
+        b = batch(sp, 0)
         rec = b.set_record(0, S + 1, 64)
-        b.run_sweeps(0, 1)                 # graphs built outside the timed region
+        # the kernel form, tuned on the run's first sweeps (every form gives
+        # the same chain), which also build the graphs outside the timed region
+        first = b.tune_running(0, 2)
+        block = b.block
         torch.cuda.synchronize()
         c0 = sum(b.read_counters(q) for q in range(n))
         t0 = time.perf_counter()
-        b.run_sweeps(1, S)
+        b.run_sweeps(first, S + 1 - first)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         d = sum(b.read_counters(q) for q in range(n)) - c0
@@ -416,7 +401,7 @@ def paper_world_study(args, dev, latent: bool = False):
                 P[q, a], Rc[q, a], F[q, a], E[q, a] = r.precision, r.recall, r.f1, \
                     r.location_error
         b.close()
-        ms = el * 1e3 / S
+        ms = el * 1e3 / (S + 1 - first)
 
         def final(v):
             per_world = np.nanmean(v[:, -1].reshape(nw, nr), axis=1)

@@ -335,6 +335,17 @@ int32_t cmh_get_block(cmh_state *st, int32_t *block);
  * Synchronises. */
 int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream);
 
+/* Tuning while sampling, for single chains and batches alike: each
+ * sweep-kernel form in turn runs one sweep (which builds its graphs) and then
+ * n_trial timed sweeps of the chains themselves, starting at first_sweep;
+ * the fastest form is kept.  Every form takes the chains through the same
+ * states, so these are ordinary sweeps of the run (recorded, logged and fed
+ * like any other) and nothing is restored; *next_sweep receives the index
+ * of the first sweep not yet run.  Nothing is cached.  Synchronises; on an
+ * error the form in use before the call is kept. */
+int32_t cmh_tune_running(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream,
+                         int64_t *next_sweep);
+
 /* Log-posterior of every chain (instance, in a batch) as its current
  * events stand (Section 3's joint density of events and signals, as a set
  * density, up to the constant of the signal model): out_host[3 c] = the

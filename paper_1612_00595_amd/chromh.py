@@ -58,7 +58,7 @@ class CmhError(RuntimeError):
 EXPORTS = ["cmh_last_error", "cmh_partition_and_color", "cmh_state_bytes", "cmh_init_state",
            "cmh_sweep_color", "cmh_run_sweeps", "cmh_read_events", "cmh_write_events",
            "cmh_set_feed", "cmh_set_log", "cmh_refresh", "cmh_read_variance", "cmh_read_stats",
-           "cmh_get_block", "cmh_autotune", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
+           "cmh_get_block", "cmh_autotune", "cmh_tune_running", "cmh_time_phases", "cmh_destroy", "cmh_simulate_bytes", "cmh_simulate",
            "cmh_move_draws", "cmh_move_draws_arrivals", "cmh_mdn_sizes", "cmh_mdn_param_bytes", "cmh_mdn_init",
            "cmh_mdn_set_params", "cmh_mdn_get_params", "cmh_mdn_work_bytes", "cmh_mdn_forward",
            "cmh_mdn_infer",
@@ -99,6 +99,7 @@ def lib():
         "cmh_read_stats": ([P, I32, P], I32),
         "cmh_get_block": ([P, P], I32),
         "cmh_autotune": ([P, I64, I32, P], I32),
+        "cmh_tune_running": ([P, I64, I32, P, P], I32),
         "cmh_time_phases": ([P, I64, I64, P, P], I32),
         "cmh_set_stamps": ([P, P, I64, I64], I32),
         "cmh_simulate_noalloc": ([P, P, I64, U32, P, I32, P], I32),
@@ -298,6 +299,13 @@ class ChromaticSampler:
     def autotune(self, first: int, n_trial: int = 3, stream=None) -> int:
         check(lib().cmh_autotune(self._h, first, n_trial, _stream(stream)))
         return self.block
+
+    def tune_running(self, first: int, n_trial: int = 3, stream=None) -> int:
+        """Tunes the kernel form on sweeps of the run itself (first, first +
+        1, ...; every form gives the same chain); returns the next sweep."""
+        nxt = C.c_int64()
+        check(lib().cmh_tune_running(self._h, first, n_trial, _stream(stream), C.byref(nxt)))
+        return nxt.value
 
     @property
     def block(self) -> int:

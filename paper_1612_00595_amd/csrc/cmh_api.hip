@@ -1399,6 +1399,20 @@ int32_t cmh_get_block(cmh_state *st, int32_t *block)
     return CMH_OK;
 }
 
+// Sweep-kernel forms worth trying for a state's geometry.
+static std::vector<int> tune_forms(const cmh::Geo &g)
+{
+    if (g.naive) return {64};
+    // latent arrivals have the wave form and the 256-thread latency form
+    std::vector<int> f = g.latent ? std::vector<int>{64, 256}
+                                  : std::vector<int>{64, 128, 256, 512, cmh::kSpecBase + 128,
+                                                     cmh::kSpecBase + 256, cmh::kSpecBase + 512};
+    // the persistent form: dynamic partitions without latent arrivals (its
+    // kernel has no arrival moves)
+    if (g.dynamic && !g.latent) f.push_back(cmh::kPersist);
+    return f;
+}
+
 int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream)
 {
     int32_t rc = check_state(st);
@@ -1439,13 +1453,7 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    // latent arrivals have the wave form and the 256-thread latency form
-    const std::vector<int> cands =
-        g.latent ? std::vector<int>{64, 256}
-                 : std::vector<int>{64, 128, 256, 512, cmh::kSpecBase + 128,
-                                    cmh::kSpecBase + 256, cmh::kSpecBase + 512};
-    std::vector<int> forms = cands;
-    if (g.dynamic) forms.push_back(cmh::kPersist);
+    const std::vector<int> forms = tune_forms(g);
     int best = st->block;
     float best_ms = 1e30f;
     for (int b : forms) {
@@ -1480,6 +1488,57 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
         g_tune_cache[key] = best;
     }
     return sync_and_check(st);
+}
+
+int32_t cmh_tune_running(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream,
+                         int64_t *next_sweep)
+{
+    int32_t rc = check_state(st);
+    if (rc) return rc;
+    if (!next_sweep) return fail(CMH_EINVAL, "next_sweep is NULL");
+    if (n_trial < 1) return fail(CMH_EINVAL, "n_trial must be positive");
+    const std::vector<int> forms = tune_forms(st->g);
+    const int64_t per = 1 + (int64_t)n_trial;
+    if (first_sweep < 0 || first_sweep + per * (int64_t)forms.size() > (1LL << 32))
+        return fail(CMH_EINVAL, "sweep range out of bounds");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int saved = st->block;
+    int best = saved;
+    float best_ms = 1e30f;
+    int64_t sw = first_sweep;
+    for (int b : forms) {
+        st->block = b;
+        // one sweep that builds the form's graphs, then the timed ones; every
+        // form takes the chain through the same states
+        rc = cmh_run_sweeps(st, sw, 1, hip_stream);
+        if (!rc) {
+            (void)hipEventRecord(e0, s);
+            rc = cmh_run_sweeps(st, sw + 1, n_trial, hip_stream);
+            (void)hipEventRecord(e1, s);
+        }
+        if (!rc) rc = sync_and_check(st);
+        float ms = 0.f;
+        if (!rc) (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rc) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            st->block = saved;
+            return rc;
+        }
+        sw += per;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st->block = best;
+    *next_sweep = sw;
+    return CMH_OK;
 }
 
 int32_t cmh_time_phases(cmh_state *st, int64_t first_sweep, int64_t n_sweeps, void *hip_stream,

@@ -60,6 +60,61 @@ def test_batch_instances_match_single_runs(block):
     b.close()
 
 
+def test_tuning_while_running_keeps_the_chain():
+    """cmh_tune_running runs each kernel form on sweeps of the batch itself:
+    the batch's instances end exactly where a batch run in one fixed form
+    ends after the same sweeps, before and after two more sweeps in the
+    chosen form."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1612_00595_amd import chromh
+    specs, samplers = _instances()
+    seeds = [21, 22, 23, 24]
+    traces = []
+    for q, m in enumerate(specs):
+        tr = W.truth_events(m, 60 + q)
+        truth = chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"])
+        traces.append(chromh.simulate(m, truth, 700 + q, "f32", "cuda"))
+    say("tuning a batch of", len(specs), "instances while it runs")
+    a = chromh.Batch(specs, samplers, traces, seeds)
+    nxt = a.tune_running(0, 1)
+    # seven forms and the persistent one (dynamic partitions), 1 + 1 sweeps each
+    assert nxt == 16
+    assert a.block in (64, 128, 256, 512, 1024 + 128, 1024 + 256, 1024 + 512, 2048 + 64)
+    ref = chromh.Batch(specs, samplers, traces, seeds, block=256)
+    ref.run_sweeps(0, nxt)
+    torch.cuda.synchronize()
+    for q in range(len(specs)):
+        compare_events(a.read_events(q), ref.read_events(q), f"instance {q} after tuning")
+        assert np.array_equal(a.read_counters(q), ref.read_counters(q))
+    a.run_sweeps(nxt, 2)
+    ref.run_sweeps(nxt, 2)
+    torch.cuda.synchronize()
+    for q in range(len(specs)):
+        compare_events(a.read_events(q), ref.read_events(q), f"instance {q} after two more")
+    a.close()
+    ref.close()
+    # latent arrivals on dynamic partitions: the wave and 256-thread forms
+    # only (the persistent kernel has no arrival moves)
+    import dataclasses
+    m = W.PAPER1D_LATENT_MODEL
+    sp = dataclasses.replace(W.PAPER1D_LATENT_SAMPLER, dynamic=1)
+    tr = W.truth_events(m, 5)
+    trace = chromh.simulate(m, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"], da=tr["da"]),
+                            75, "f64", "cuda")
+    say("tuning a latent-arrival chain while it runs")
+    one = chromh.ChromaticSampler(m, sp, trace, chains=2, seed=9)
+    nxt = one.tune_running(0, 1)
+    assert nxt == 4 and one.block in (64, 256)
+    ref = chromh.ChromaticSampler(m, sp, trace, chains=2, seed=9, block=256)
+    ref.run_sweeps(0, nxt)
+    torch.cuda.synchronize()
+    for c in range(2):
+        compare_events(one.read_events(c), ref.read_events(c), f"latent chain {c}")
+    one.close()
+    ref.close()
+
+
 def test_batch_rejects_mixed_settings():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

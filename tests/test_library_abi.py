@@ -73,6 +73,8 @@ def test_host_validation_errors():
     assert L.cmh_init_state(C.byref(m), C.byref(s), None, 0, 1, 0, None, 0, None,
                             C.byref(h)) == -1
     assert L.cmh_destroy(None) == 0
+    nxt = C.c_int64()
+    assert L.cmh_tune_running(None, 0, 1, None, C.byref(nxt)) == -1
     # the training loop: refused before any device work for a model without
     # training pairs, zero steps, Adam steps from 0, or missing buffers
     lm = chromh.model_struct(W.PAPER1D.model)
