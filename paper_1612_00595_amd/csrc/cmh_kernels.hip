@@ -2060,12 +2060,12 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
 {
     __shared__ int s_sta[kMaxRegSta];
     __shared__ int s_ns;
-    __shared__ double s_W;
     const int nrun = (k + mpw - 1) / mpw;
     const unsigned item = items[blockIdx.x / nrun];
     const int jbeg = (int)(blockIdx.x % nrun) * mpw, jend = min(k, jbeg + mpw);
     const int slot = (int)(item >> 16), r = (int)(item & 0xFFFFu), lane = threadIdx.x;
-    const Learned &L = slots[slot].L;
+    // the table's pointers in registers (no reload after the stores below)
+    const Learned L = slots[slot].L;
     if (L.tab == nullptr) return;
     const Geo &g = slots[slot].g;
     const double *offs = slots[slot].ev[par].off;
@@ -2074,93 +2074,114 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
     double x0, x1, y0, y1;
     region_span(offx, g.wx, g.Lx, i, &x0, &x1);
     region_span(offy, g.wy, g.Ly, kk, &y0, &y1);
+    const double area = (x1 - x0) * (y1 - y0);
+    const double c1 = g.c1, N = (double)g.N;
+    const int ntau = L.ntau;
+    // this lane's move and its draws, loaded before the region's stations
+    const int j = jbeg + lane;
+    const long long q = (long long)r * k + j;
+    double d[4] = {1.0, 0.0, 0.0, 0.0}, e[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (j < jend) {
+        for (int u = 0; u < 4; ++u) d[u] = slots[slot].draws[q * 8 + u];
+        for (int u = 0; u < 6; ++u) e[u] = L.raw[q * 8 + u];  // draws 8..13
+    }
+    const bool birth = j < jend && d[0] < c1;
     if (lane == 0) {
         int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_sta, kMaxRegSta);
         if (ns > kMaxRegSta) {
             atomicOr(err, kFlagSta);
             ns = 0;
         }
-        double W = 0.0;
-        for (int s = 0; s < ns; ++s) W = W + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
         s_ns = ns;
-        s_W = W;
     }
     __syncthreads();
     const int ns = s_ns;
-    const double W = s_W, pl = ns > 0 ? L.pl : 0.0;
-    const double area = (x1 - x0) * (y1 - y0);
-    const double c1 = g.c1;
-    {
-        const int j = jbeg + lane;
-        const long long q = (long long)r * k + j;
-        double x = 0.0, y = 0.0, t = 0.0;
-        bool birth = false;
-        if (j < jend) {
-            const double *d = slots[slot].draws + q * 8;
-            birth = d[0] < c1;
-            if (!birth) {
-                double *lb = L.birth + q * 4;
-                lb[0] = 0.0; lb[1] = 0.0; lb[2] = 0.0; lb[3] = 0.0;
-            } else {
-                const double *e = L.raw + q * 8;  // draws 8..15
-                if (pl > 0.0 && e[0] < pl) {
-                    // this lane walks the running sums
-                    const double target = e[1] * W;
-                    double acc = 0.0, rem = 0.0;
-                    int pick = -1;
-                    for (int s = 0; s < ns; ++s) {
-                        const double nxt = acc + L.cum[(long long)s_sta[s] * L.ntau + L.ntau - 1];
-                        if (target < nxt) {
-                            pick = s_sta[s];
-                            rem = target - acc;
-                            break;
-                        }
-                        acc = nxt;
-                    }
-                    if (pick < 0) {
-                        pick = s_sta[ns - 1];
-                        rem = L.cum[(long long)pick * L.ntau + L.ntau - 1];
-                    }
-                    // smallest window with rem < cum (the last one if none)
-                    const double *cum = L.cum + (long long)pick * L.ntau;
-                    int lo = 0, hi = L.ntau - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (rem < cum[mid]) hi = mid;
-                        else lo = mid + 1;
-                    }
-                    const double *T = L.tab + ((long long)pick * L.ntau + lo) * 64;
-                    int c = 7;
-                    for (int u = 0; u < 8; ++u)
-                        if (e[2] < T[8 * u + 7]) { c = u; break; }
-                    x = T[8 * c + 0] + T[8 * c + 3] * e[3];
-                    y = T[8 * c + 1] + T[8 * c + 4] * e[4];
-                    t = T[8 * c + 2] + T[8 * c + 5] * e[5];
-                } else {
-                    x = x0 + d[1] * (x1 - x0);
-                    y = y0 + d[2] * (y1 - y0);
-                    t = d[3] * (double)g.N;
-                }
-            }
+    const double pl = ns > 0 ? L.pl : 0.0;
+    // the stations' total anchor weights, loaded together (lane s, station
+    // s), then one running total in station order: W and the walk below
+    // add the same terms in the same order
+    const double tot = lane < ns ? L.cum[(long long)s_sta[lane] * ntau + ntau - 1] : 0.0;
+    double W = 0.0;
+    for (int s = 0; s < ns; ++s) W = W + lane_f64(tot, s);
+    const bool from_net = birth && pl > 0.0 && e[0] < pl;
+    // anchor: the first station whose running total exceeds u_anchor W
+    // (the last one if none), then the remainder within its windows
+    const double target = e[1] * W;
+    int pick = -1;
+    double rem = 0.0, acc = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        const double ts = lane_f64(tot, s);
+        const double nxt = acc + ts;
+        if (pick < 0 && target < nxt) {
+            pick = s;
+            rem = target - acc;
         }
-        // each birth's density, (station, window) pairs over the lanes
-        unsigned long long todo = __ballot(birth);
-        while (todo) {
-            const int bl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(todo));
-            todo &= todo - 1;
-            const double bx = lane_f64(x, bl), by = lane_f64(y, bl), bt = lane_f64(t, bl);
-            double lr = 0.0;
-            if (pl > 0.0) {
-                int ilo, ihi;
-                learned_windows(L, bt, &ilo, &ihi);
-                const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, bx, by, bt, lane,
-                                                       64));
-                lr = learned_log_ratio(pl, S, W, area, g.N);
+        if (s == ns - 1 && pick < 0) {
+            pick = s;
+            rem = ts;
+        }
+        acc = nxt;
+    }
+    double x = 0.0, y = 0.0, t = 0.0;
+    if (from_net) {
+        const int sta = s_sta[pick];
+        // smallest window w < ntau - 1 with rem < cum[w], else ntau - 1: an
+        // eight-way search whose seven probes per level load together
+        const double *cum = L.cum + (long long)sta * ntau;
+        int lo = 0, hi = ntau - 1;
+        while (lo < hi) {
+            const int dd = hi - lo;
+            double c[7];
+#pragma unroll
+            for (int u = 0; u < 7; ++u) c[u] = cum[lo + (u + 1) * dd / 8];
+            int nlo = lo, nhi = hi;
+#pragma unroll
+            for (int u = 0; u < 7; ++u) {
+                const int pu = lo + (u + 1) * dd / 8;
+                if (rem < c[u]) nhi = min(nhi, pu);
+                else nlo = max(nlo, pu + 1);
             }
-            if (lane == bl) {
-                double *lb = L.birth + q * 4;
-                lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
-            }
+            lo = nlo;
+            hi = nhi;
+        }
+        // component: the first with u_comp below its cumulative weight (the
+        // last if none)
+        const double *T = L.tab + ((long long)sta * ntau + lo) * 64;
+        double cw[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cw[u] = T[8 * u + 7];
+        int c = 7;
+#pragma unroll
+        for (int u = 6; u >= 0; --u)
+            if (e[2] < cw[u]) c = u;
+        x = T[8 * c + 0] + T[8 * c + 3] * e[3];
+        y = T[8 * c + 1] + T[8 * c + 4] * e[4];
+        t = T[8 * c + 2] + T[8 * c + 5] * e[5];
+    } else if (birth) {
+        x = x0 + d[1] * (x1 - x0);
+        y = y0 + d[2] * (y1 - y0);
+        t = d[3] * N;
+    }
+    if (j < jend && !birth) {
+        double *lb = L.birth + q * 4;
+        lb[0] = 0.0; lb[1] = 0.0; lb[2] = 0.0; lb[3] = 0.0;
+    }
+    // each birth's density, (station, window) pairs over the lanes
+    unsigned long long todo = __ballot(birth);
+    while (todo) {
+        const int bl = __builtin_amdgcn_readfirstlane(__builtin_ctzll(todo));
+        todo &= todo - 1;
+        const double bx = lane_f64(x, bl), by = lane_f64(y, bl), bt = lane_f64(t, bl);
+        double lr = 0.0;
+        if (pl > 0.0) {
+            int ilo, ihi;
+            learned_windows(L, bt, &ilo, &ihi);
+            const double S = wave_sum(learned_part(L, s_sta, ns, ilo, ihi, bx, by, bt, lane, 64));
+            lr = learned_log_ratio(pl, S, W, area, g.N);
+        }
+        if (lane == bl) {
+            double *lb = L.birth + q * 4;
+            lb[0] = x; lb[1] = y; lb[2] = t; lb[3] = lr;
         }
     }
 }
