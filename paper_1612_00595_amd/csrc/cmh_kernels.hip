@@ -269,25 +269,38 @@ struct JointScratch {
 
 // Stations whose position falls in region (i, kk) of a partition with
 // offsets (offx, offy), in ascending index; returns their number (only the
-// first `cap` are stored).  Candidates are the cells around the region's
-// span; membership is decided by the region binning itself.
-__device__ inline int region_stations(const Geo &g, double offx, double offy, int i, int kk,
-                                      double x0, double x1, double y0, double y1, int *sta,
-                                      int cap)
+// first `cap` are stored in sta).  Candidates are the cells around the
+// region's span, one per lane of the calling wave (every lane must take
+// part), membership decided by the region binning itself, compacted in
+// order by a ballot.  Every lane returns the count.
+__device__ inline int region_stations_wave(const Geo &g, double offx, double offy, int i, int kk,
+                                           double x0, double x1, double y0, double y1, int *sta,
+                                           int cap, int lane)
 {
     const int ix0 = max((int)floor(x0 / g.ds - 0.5) - 1, 0);
     const int ix1 = min((int)ceil(x1 / g.ds - 0.5) + 1, g.nsx - 1);
     const int iy0 = max((int)floor(y0 / g.ds - 0.5) - 1, 0);
     const int iy1 = min((int)ceil(y1 / g.ds - 0.5) + 1, g.nsy - 1);
+    const int nx = ix1 - ix0 + 1, ny = iy1 - iy0 + 1;
     int cnt = 0;
-    for (int iy = iy0; iy <= iy1; ++iy) {
-        if (region_axis(station_pos(iy, g.ds), offy, g.wy, g.gy) != kk) continue;
-        for (int ix = ix0; ix <= ix1; ++ix) {
-            if (region_axis(station_pos(ix, g.ds), offx, g.wx, g.gx) != i) continue;
-            if (cnt < cap) sta[cnt] = iy * g.nsx + ix;
-            ++cnt;
+    if (nx <= 0 || ny <= 0) return 0;
+    for (int c0 = 0; c0 < nx * ny; c0 += 64) {
+        const int c = c0 + lane;
+        bool in = false;
+        int id = 0;
+        if (c < nx * ny) {
+            const int iy = iy0 + c / nx, ix = ix0 + c % nx;
+            in = region_axis(station_pos(iy, g.ds), offy, g.wy, g.gy) == kk &&
+                 region_axis(station_pos(ix, g.ds), offx, g.wx, g.gx) == i;
+            id = iy * g.nsx + ix;
         }
+        const unsigned long long m = __ballot(in);
+        const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (in && cnt + below < cap) sta[cnt + below] = id;
+        cnt += __popcll(m);
     }
+    __builtin_amdgcn_wave_barrier();
     return cnt;
 }
 
@@ -436,6 +449,33 @@ struct RegionLearned {
     double W, pl;    // their total anchor weight; mixing probability (0: plain)
     double area;
 };
+
+// A region's learned-birth constants, computed by one whole wave (every lane
+// takes part and gets the same value): its stations into sta, and W, the
+// running total of their anchors' weights in station order (loads one per
+// lane, additions in order).  *over: more than kMaxRegSta stations (the
+// region is then taken as plain).
+__device__ inline RegionLearned region_learned_wave(const Geo &g, const Learned &L, double offx,
+                                                    double offy, int i, int kk, double x0,
+                                                    double x1, double y0, double y1, double area,
+                                                    int *sta, int lane, bool *over)
+{
+    RegionLearned rl;
+    rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
+    *over = false;
+    if (L.tab == nullptr) return rl;
+    const int ns = region_stations_wave(g, offx, offy, i, kk, x0, x1, y0, y1, sta, kMaxRegSta,
+                                        lane);
+    if (ns > kMaxRegSta) {
+        *over = true;
+    } else if (ns > 0) {
+        const double tot = lane < ns ? L.cum[(long long)sta[lane] * L.ntau + L.ntau - 1] : 0.0;
+        double W = 0.0;
+        for (int q = 0; q < ns; ++q) W = W + lane_f64(tot, q);
+        rl.ns = ns; rl.W = W; rl.pl = L.pl;
+    }
+    return rl;
+}
 
 // x lies in region index `want` of one axis.  Points further than 1e-9 w
 // from both edges of the region's interval are decided by comparison (the
@@ -994,22 +1034,14 @@ k_sweep_color(const Slot *__restrict__ slots, const unsigned *__restrict__ items
                 s_lb[c][q >> 2][q & 3] = lsrc[64LL * 4 * c + q];
     }
     int flags = 0;
-    if (tid == 0) {
-        RegionLearned rl;
-        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
-        if (L.tab != nullptr) {
-            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta,
-                                           kMaxRegSta);
-            if (ns > kMaxRegSta) {
-                flags |= kFlagSta;
-            } else if (ns > 0) {
-                double W = 0.0;
-                for (int q = 0; q < ns; ++q)
-                    W = W + L.cum[(long long)s_lsta[q] * L.ntau + L.ntau - 1];
-                rl.ns = ns; rl.W = W; rl.pl = L.pl;
-            }
+    if (tid < 64) {  // the first wave
+        bool over = false;
+        const RegionLearned rl = region_learned_wave(g, L, offx, offy, i, kk, x0, x1, y0, y1,
+                                                     area, s_lsta, tid, &over);
+        if (tid == 0) {
+            if (over) flags |= kFlagSta;
+            s_rl = rl;
         }
-        s_rl = rl;
     }
 
     const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
@@ -1518,22 +1550,14 @@ k_sweep_wave(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
             }
             Ew = pe;
         }
-        if (lane == 0) {
-            RegionLearned rl;
-            rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
-            if (L.tab != nullptr) {
-                const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta[wv],
-                                               kMaxRegSta);
-                if (ns > kMaxRegSta) {
-                    flags |= kFlagSta;
-                } else if (ns > 0) {
-                    double W = 0.0;
-                    for (int q = 0; q < ns; ++q)
-                        W = W + L.cum[(long long)s_lsta[wv][q] * L.ntau + L.ntau - 1];
-                    rl.ns = ns; rl.W = W; rl.pl = L.pl;
-                }
+        {
+            bool over = false;
+            const RegionLearned rl = region_learned_wave(g, L, offx, offy, i, kk, x0, x1, y0, y1,
+                                                         area, s_lsta[wv], lane, &over);
+            if (lane == 0) {
+                if (over) flags |= kFlagSta;
+                s_rl[wv] = rl;
             }
-            s_rl[wv] = rl;
         }
         __builtin_amdgcn_wave_barrier();
         const RegionLearned rl = s_rl[wv];
@@ -1801,22 +1825,14 @@ k_sweep_spec(const Slot *__restrict__ slots, const unsigned *__restrict__ items,
         loaded += m;
     }
     int flags = 0;
-    if (tid == 0) {
-        RegionLearned rl;
-        rl.ns = 0; rl.W = 0.0; rl.pl = 0.0; rl.area = area;
-        if (L.tab != nullptr) {
-            const int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_lsta,
-                                           kMaxRegSta);
-            if (ns > kMaxRegSta) {
-                flags |= kFlagSta;
-            } else if (ns > 0) {
-                double W = 0.0;
-                for (int q = 0; q < ns; ++q)
-                    W = W + L.cum[(long long)s_lsta[q] * L.ntau + L.ntau - 1];
-                rl.ns = ns; rl.W = W; rl.pl = L.pl;
-            }
+    if (tid < 64) {  // the first wave
+        bool over = false;
+        const RegionLearned rl = region_learned_wave(g, L, offx, offy, i, kk, x0, x1, y0, y1,
+                                                     area, s_lsta, tid, &over);
+        if (tid == 0) {
+            if (over) flags |= kFlagSta;
+            s_rl = rl;
         }
-        s_rl = rl;
     }
     const bool use_log = logp != nullptr && slot == 0 && sweep >= log_first &&
                          sweep < log_first + log_n;
@@ -2059,7 +2075,6 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
                  int mpw, int par, int *__restrict__ err)
 {
     __shared__ int s_sta[kMaxRegSta];
-    __shared__ int s_ns;
     const int nrun = (k + mpw - 1) / mpw;
     const unsigned item = items[blockIdx.x / nrun];
     const int jbeg = (int)(blockIdx.x % nrun) * mpw, jend = min(k, jbeg + mpw);
@@ -2086,16 +2101,11 @@ k_learned_births(const Slot *__restrict__ slots, const unsigned *__restrict__ it
         for (int u = 0; u < 6; ++u) e[u] = L.raw[q * 8 + u];  // draws 8..13
     }
     const bool birth = j < jend && d[0] < c1;
-    if (lane == 0) {
-        int ns = region_stations(g, offx, offy, i, kk, x0, x1, y0, y1, s_sta, kMaxRegSta);
-        if (ns > kMaxRegSta) {
-            atomicOr(err, kFlagSta);
-            ns = 0;
-        }
-        s_ns = ns;
+    int ns = region_stations_wave(g, offx, offy, i, kk, x0, x1, y0, y1, s_sta, kMaxRegSta, lane);
+    if (ns > kMaxRegSta) {
+        if (lane == 0) atomicOr(err, kFlagSta);
+        ns = 0;
     }
-    __syncthreads();
-    const int ns = s_ns;
     const double pl = ns > 0 ? L.pl : 0.0;
     // the stations' total anchor weights, loaded together (lane s, station
     // s), then one running total in station order: W and the walk below
