@@ -341,8 +341,9 @@ int32_t cmh_autotune(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *
  * the fastest form is kept.  Every form takes the chains through the same
  * states, so these are ordinary sweeps of the run (recorded, logged and fed
  * like any other) and nothing is restored; *next_sweep receives the index
- * of the first sweep not yet run.  Nothing is cached.  Synchronises; on an
- * error the form in use before the call is kept. */
+ * of the first sweep not yet run.  Nothing is cached.  Synchronises.  On an
+ * error the form in use before the call is kept, and the chains may have
+ * run part of the trial sweeps. */
 int32_t cmh_tune_running(cmh_state *st, int64_t first_sweep, int32_t n_trial, void *hip_stream,
                          int64_t *next_sweep);
 
