@@ -23,6 +23,7 @@
 namespace cmh {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline double gelu_d(double z) { return 0.5 * z * (1.0 + erf(z * M_SQRT1_2)); }
@@ -76,13 +77,23 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
     const int kend = min(K, kbeg + kper);
     C += (long)blockIdx.z * M * ldc;
 
+    // An operand stored k-strided (A for TA, B for !TB) is loaded as blocks of
+    // 4 k-rows x 8 contiguous entries per thread (when the step holds exactly
+    // one such block per thread per four vectors) and transposed in registers,
+    // so that LDS takes 8-byte rows of 4 k's instead of 2-byte scalars.
+    constexpr bool BLKA = TA && NVA % 4 == 0, BLKB = !TB && NVB % 4 == 0;
     bf16x8 ra[NVA], rb[NVB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < NVA; ++u) {
             const int v = tid + 256 * u;
             ra[u] = (bf16x8){zero, zero, zero, zero, zero, zero, zero, zero};
-            if (TA) {  // A[k][m]: 8 m's at one k
+            if (BLKA) {  // block u / 4 of this thread, k-row u % 4
+                const int blk = tid + 256 * (u / 4);
+                const int k4 = 4 * (blk / (TMR / 8)), m8 = 8 * (blk % (TMR / 8));
+                const int gk = k0 + k4 + u % 4, gi = i0 + m8;
+                if (gk < kend && gi < M) ra[u] = *(const bf16x8 *)&A[(long)gk * lda + gi];
+            } else if (TA) {  // A[k][m]: 8 m's at one k
                 const int kq = v / (TMR / 8), m8 = 8 * (v % (TMR / 8));
                 const int gk = k0 + kq, gi = i0 + m8;
                 if (gk < kend && gi < M) ra[u] = *(const bf16x8 *)&A[(long)gk * lda + gi];
@@ -100,6 +111,11 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
                 const int r = v / (KS / 8), k8 = 8 * (v % (KS / 8));
                 const int gj = j0 + r, gk = k0 + k8;
                 if (gj < N && gk < kend) rb[u] = *(const bf16x8 *)&B[(long)gj * ldb + gk];
+            } else if (BLKB) {
+                const int blk = tid + 256 * (u / 4);
+                const int k4 = 4 * (blk / (TNC / 8)), n8 = 8 * (blk % (TNC / 8));
+                const int gk = k0 + k4 + u % 4, gj = j0 + n8;
+                if (gk < kend && gj < N) rb[u] = *(const bf16x8 *)&B[(long)gk * ldb + gj];
             } else {   // B[k][n]: 8 n's at one k
                 const int kq = v / (TNC / 8), n8 = 8 * (v % (TNC / 8));
                 const int gk = k0 + kq, gj = j0 + n8;
@@ -107,11 +123,26 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
             }
         }
     };
+    // rows q of a 4 x 8 block (r[0..3]: k-rows) as 4 k-values each, into
+    // dst[q][0..3] (8-byte stores)
+    auto store_blk = [&](const bf16x8 *r, __bf16 (*dst)[P], int k4) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bf16x4 col = (bf16x4){r[0][q], r[1][q], r[2][q], r[3][q]};
+            *(bf16x4 *)&dst[q][k4] = col;
+        }
+    };
     auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < NVA; ++u) {
             const int v = tid + 256 * u;
-            if (TA) {
+            if (BLKA) {
+                if (u % 4 == 0) {
+                    const int blk = tid + 256 * (u / 4);
+                    const int k4 = 4 * (blk / (TMR / 8)), m8 = 8 * (blk % (TMR / 8));
+                    store_blk(&ra[u], &sA[buf][m8], k4);
+                }
+            } else if (TA) {
                 const int kq = v / (TMR / 8), m8 = 8 * (v % (TMR / 8));
 #pragma unroll
                 for (int q = 0; q < 8; ++q) sA[buf][m8 + q][kq] = ra[u][q];
@@ -124,6 +155,12 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
             const int v = tid + 256 * u;
             if (TB) {
                 *(bf16x8 *)&sB[buf][v / (KS / 8)][8 * (v % (KS / 8))] = rb[u];
+            } else if (BLKB) {
+                if (u % 4 == 0) {
+                    const int blk = tid + 256 * (u / 4);
+                    const int k4 = 4 * (blk / (TNC / 8)), n8 = 8 * (blk % (TNC / 8));
+                    store_blk(&rb[u], &sB[buf][n8], k4);
+                }
             } else {
                 const int kq = v / (TNC / 8), n8 = 8 * (v % (TNC / 8));
 #pragma unroll

@@ -191,3 +191,26 @@ def test_learned_births_in_a_batch_match_single_runs(block):
     # back to plain births for instance 0: it then matches a plain single run
     b.set_learned_instance(0, None, None, 0)
     b.close()
+
+
+@pytest.mark.parametrize("block", [64, 256, 1024 + 256])
+def test_region_with_too_many_stations_is_reported(block):
+    """A region holding more than 16 stations cannot take learned births:
+    the learned-birth kernel and every sweep form report it and the run ends
+    in CMH_ESTATE (10 x 10 stations in 2 x 2 regions: about 25 per region)."""
+    import dataclasses
+    from paper_1612_00595_amd import chromh
+    m = W.ModelSpec(nsx=10, nsy=10, N=1000, lam=10.0)
+    sp = dataclasses.replace(W.SMALL.sampler, gx=2, gy=2)
+    tr = W.truth_events(m, 3)
+    trace = chromh.simulate(m, chromh.as_events(tr["x"], tr["y"], tr["t"], tr["m"]), 30,
+                            "f64", DEV)
+    T, wts, ntau = W.random_mixture_table(m, 4)
+    say("learned births with 25 stations per region, form", block)
+    gpu = chromh.ChromaticSampler(m, sp, trace, chains=1, seed=5, block=block)
+    gpu.set_learned(torch.from_numpy(T).to(DEV), torch.from_numpy(wts).to(DEV), ntau, 0.5)
+    with pytest.raises(chromh.CmhError, match="more stations"):
+        gpu.run_sweeps(0, 1)
+        torch.cuda.synchronize()
+        gpu.read_events(0)
+    gpu.close()
