@@ -270,55 +270,63 @@ __global__ void k_sum_jobs(SumJobs J)
 }
 
 // Mixture negative log-likelihood of the targets and its gradient w.r.t. the
-// head outputs, per sample (one thread each).  Head layout, component k:
-// [7k] logit, [7k+1..3] means, [7k+4..6] log standard deviations, clamped to
-// [slo_d, shi_d].  Gradients are divided by M (mean loss).
-__global__ void k_mdn_loss(int M, const float *__restrict__ O, int ldo,
-                           const float *__restrict__ Zt, float *__restrict__ loss,
-                           __bf16 *__restrict__ dO, int lddo)
+// head outputs, per sample: eight lanes per sample, lane k taking component
+// k, the sums and maxima over a sample's components by butterflies within
+// its eight lanes.  Head layout, component k: [7k] logit, [7k+1..3] means,
+// [7k+4..6] log standard deviations, clamped to [slo_d, shi_d].  Gradients
+// are divided by M (mean loss).
+__device__ inline float group8_max(float v)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const float *o = O + (long)m * ldo;
-    const float z[3] = {Zt[3 * m], Zt[3 * m + 1], Zt[3 * m + 2]};
+    for (int off = 1; off < 8; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ inline float group8_sum(float v)
+{
+    for (int off = 1; off < 8; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256)
+k_mdn_loss(int M, const float *__restrict__ O, int ldo, const float *__restrict__ Zt,
+           float *__restrict__ loss, __bf16 *__restrict__ dO, int lddo)
+{
+    static_assert(kMdnK == 8, "one lane per component, eight per sample");
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = (int)(t >> 3), k = (int)(t & 7);
+    const bool live = m < M;
+    const int mm = live ? m : M - 1;  // every lane takes part in the butterflies
+    const float *o = O + (long)mm * ldo + 7 * k;
+    float ov[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) ov[c] = o[c];
+    const float z[3] = {Zt[3 * (long)mm], Zt[3 * (long)mm + 1], Zt[3 * (long)mm + 2]};
     const float slo[3] = {kMdnSloXY, kMdnSloXY, kMdnSloT}, shi[3] = {kMdnShiXY, kMdnShiXY, kMdnShiT};
-    float lmax = -1e30f;
-    for (int k = 0; k < kMdnK; ++k) lmax = fmaxf(lmax, o[7 * k]);
-    float lse = 0.f;
-    for (int k = 0; k < kMdnK; ++k) lse += expf(o[7 * k] - lmax);
-    lse = lmax + logf(lse);
-    float ell[kMdnK], best = -1e30f;
-    for (int k = 0; k < kMdnK; ++k) {
-        float l = o[7 * k] - lse;
-        for (int d = 0; d < 3; ++d) {
-            const float s = fminf(fmaxf(o[7 * k + 4 + d], slo[d]), shi[d]);
-            const float u = (z[d] - o[7 * k + 1 + d]) * expf(-s);
-            l += -0.5f * u * u - s - 0.9189385332046727f;
-        }
-        ell[k] = l;
-        best = fmaxf(best, l);
+    const float lmax = group8_max(ov[0]);
+    const float lse = lmax + logf(group8_sum(expf(ov[0] - lmax)));
+    float l = ov[0] - lse, u[3], is[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float sd = fminf(fmaxf(ov[4 + d], slo[d]), shi[d]);
+        is[d] = expf(-sd);
+        u[d] = (z[d] - ov[1 + d]) * is[d];
+        l += -0.5f * u[d] * u[d] - sd - 0.9189385332046727f;
     }
-    float tot = 0.f;
-    for (int k = 0; k < kMdnK; ++k) tot += expf(ell[k] - best);
-    const float logp = best + logf(tot);
-    loss[m] = -logp;
+    const float best = group8_max(l);
+    const float logp = best + logf(group8_sum(expf(l - best)));
+    if (!live) return;
+    if (k == 0) loss[m] = -logp;
     const float inv = 1.0f / (float)M;
     __bf16 *g = dO + (long)m * lddo;
-    for (int k = 0; k < kMdnK; ++k) {
-        const float gam = expf(ell[k] - logp);
-        const float pik = expf(o[7 * k] - lse);
-        g[7 * k] = (__bf16)((pik - gam) * inv);
-        for (int d = 0; d < 3; ++d) {
-            const float sr = o[7 * k + 4 + d];
-            const float s = fminf(fmaxf(sr, slo[d]), shi[d]);
-            const float is = expf(-s);
-            const float u = (z[d] - o[7 * k + 1 + d]) * is;
-            g[7 * k + 1 + d] = (__bf16)(-gam * u * is * inv);
-            const bool free = sr > slo[d] && sr < shi[d];
-            g[7 * k + 4 + d] = (__bf16)(free ? -gam * (u * u - 1.0f) * inv : 0.0f);
-        }
+    const float gam = expf(l - logp);
+    const float pik = expf(ov[0] - lse);
+    g[7 * k] = (__bf16)((pik - gam) * inv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        g[7 * k + 1 + d] = (__bf16)(-gam * u[d] * is[d] * inv);
+        const bool free = ov[4 + d] > slo[d] && ov[4 + d] < shi[d];
+        g[7 * k + 4 + d] = (__bf16)(free ? -gam * (u[d] * u[d] - 1.0f) * inv : 0.0f);
     }
-    for (int c = 7 * kMdnK; c < lddo; ++c) g[c] = (__bf16)0.0f;
+    for (int c = 7 * kMdnK + k; c < lddo; c += 8) g[c] = (__bf16)0.0f;
 }
 
 // Adam (Kingma & Ba) with bias correction on FP32 master weights.
@@ -918,7 +926,8 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     const MdnLayout L = mdn_layout();
     hipError_t e = mdn_forward(params, hcopy, X, M, B, s);
     if (e) return e;
-    k_mdn_loss<<<(M + 127) / 128, 128, 0, s>>>(M, B.O, kMdnOutPad, Zt, B.loss, B.dO, kMdnOutPad);
+    k_mdn_loss<<<(unsigned)(((long)M * 8 + 255) / 256), 256, 0, s>>>(M, B.O, kMdnOutPad, Zt, B.loss,
+                                                                    B.dO, kMdnOutPad);
     if ((e = hipGetLastError())) return e;
     // Every gradient's partials get a region of B.part of their own, so that
     // one launch at the end sums them all (each in a fixed order).
