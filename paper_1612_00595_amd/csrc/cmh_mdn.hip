@@ -3,9 +3,10 @@
 // its training pairs and its input features.
 //
 //   k_gemm          C = op(A) op(B), BF16 operands on 16x16x32 MFMA tiles with
-//                   FP32 accumulation, fused bias / GELU / GELU-backward epilogues
+//                   FP32 accumulation, fused bias / GELU / GELU-backward epilogues,
+//                   the bias gradient's column sums in the weight-gradient product
 //   k_mdn_loss      mixture negative log-likelihood and its gradient
-//   k_bias_grad     column sums
+//   k_sum_jobs      the fixed-order sums of every gradient's split partials
 //   k_adam_all      Adam on FP32 master weights, BF16 copies refreshed
 //   k_sim_pairs     simulator-generated (window features, event) pairs
 //   k_anchor_feat   window features and weights of an instance's anchors
@@ -49,12 +50,16 @@ __device__ inline float gelu_grad_f(float z)
 // EPI 2: C + bias (fp32).  EPI 3: the backward through GELU, BF16 C * GELU'(Z)
 // into Cb, Z (fp32, row pitch ldc) passed as `bias`; C is not written.
 // Split K: workgroup z sums k in [z kper, (z + 1) kper) and writes its
-// partial product to C + z M ldc (EPI 0 only).
+// partial product to C + z M ldc (EPI 0 only).  With TA, EPI 0 and colsum
+// given (64-row tiles), the first column of workgroups also sums A over its
+// k range for each of its M rows into colsum[z M + i] (the bias gradient of
+// a weight-gradient product): thread t adds a quarter of row t / 4 of each
+// step's tile in order, then the four quarters by a butterfly.
 template <bool TA, bool TB, int EPI, int WM, int WN, int KS = 32>
 __global__ void __launch_bounds__(256)
 k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ B,
        int ldb, float *__restrict__ C, int ldc, const float *__restrict__ bias,
-       __bf16 *__restrict__ Cb, int ldcb, int kper)
+       __bf16 *__restrict__ Cb, int ldcb, int kper, float *__restrict__ colsum)
 {
     static_assert(KS % 32 == 0, "k-steps of whole MFMA k-slices");
     constexpr int TMR = 2 * WM, TNC = 2 * WN;       // workgroup tile
@@ -76,6 +81,9 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
     const int kbeg = blockIdx.z * kper;
     const int kend = min(K, kbeg + kper);
     C += (long)blockIdx.z * M * ldc;
+    constexpr bool CS = TA && EPI == 0 && TMR * 4 == 256;  // one thread per row quarter
+    const bool do_cs = CS && colsum != nullptr && blockIdx.x == 0;
+    float cs = 0.f;
 
     // An operand stored k-strided (A for TA, B for !TB) is loaded as blocks of
     // 4 k-rows x 8 contiguous entries per thread (when the step holds exactly
@@ -198,9 +206,28 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b],
                                                                          0, 0, 0);
         }
+        if constexpr (CS) {
+            if (do_cs) {  // the same in every thread of the workgroup
+                const int r = tid >> 2, q4 = tid & 3;
+#pragma unroll
+                for (int c = 0; c < KS / 32; ++c) {
+                    const bf16x8 v = *(const bf16x8 *)&sA[cur][r][q4 * (KS / 4) + 8 * c];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) cs += (float)v[e];
+                }
+            }
+        }
         if (more) store(cur ^ 1);
         __syncthreads();
         cur ^= 1;
+    }
+    if constexpr (CS) {
+        if (do_cs) {
+            cs += __shfl_xor(cs, 1, 64);
+            cs += __shfl_xor(cs, 2, 64);
+            const int r = tid >> 2;
+            if ((tid & 3) == 0 && i0 + r < M) colsum[(long)blockIdx.z * M + i0 + r] = cs;
+        }
     }
 #pragma unroll
     for (int a = 0; a < FA; ++a)
@@ -220,27 +247,6 @@ k_gemm(int M, int N, int K, const __bf16 *__restrict__ A, int lda, const __bf16 
                 C[(long)i * ldc + j] = z;
                 if (EPI == 1) Cb[(long)i * ldcb + j] = (__bf16)gelu_f(z);
             }
-}
-
-// Column sums of a BF16 matrix D[M][N] over rows [z mper, (z + 1) mper)
-// into part[z][N]: 64 columns per workgroup, four row phases per column
-// summed in a fixed order.
-__global__ void __launch_bounds__(256)
-k_col_partial(int M, int N, const __bf16 *__restrict__ D, int ldd, int mper,
-              float *__restrict__ part)
-{
-    __shared__ float s_p[4][64];
-    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + c;
-    const int m0 = blockIdx.y * mper, m1 = min(M, m0 + mper);
-    float s = 0.f;
-    if (j < N)
-#pragma unroll 8
-        for (int m = m0 + ph; m < m1; m += 4) s += (float)D[(long)m * ldd + j];
-    s_p[ph][c] = s;
-    __syncthreads();
-    if (ph == 0 && j < N)
-        part[(long)blockIdx.y * N + j] = ((s_p[0][c] + s_p[1][c]) + s_p[2][c]) + s_p[3][c];
 }
 
 // Several fixed-order split sums in one launch: element q of job j is
@@ -620,11 +626,11 @@ static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf
     if (N >= 128 && big >= kMdnBigTiles) {
         const dim3 grid((N + 127) / 128, (M + 127) / 128, 1);
         k_gemm<TA, TB, EPI, 64, 64, 32><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
-                                                              bias, Cb, ldcb, K);
+                                                              bias, Cb, ldcb, K, nullptr);
     } else {
         const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
         k_gemm<TA, TB, EPI, 32, 32, 128><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
-                                                               bias, Cb, ldcb, K);
+                                                               bias, Cb, ldcb, K, nullptr);
     }
     return hipGetLastError();
 }
@@ -643,53 +649,42 @@ int mdn_splits(int M, int *per)
     return (M + p - 1) / p;
 }
 
-// Weight gradient C[Mo][N] = sum over the batch of op(A)^T B, split over the
-// batch into partial products (part) whose fixed-order sum is left to the
-// job list J (summed by one launch for every gradient of a backward pass).
+// Weight gradient C[Mo][N] = sum over the batch of op(A)^T B and bias
+// gradient db[Mo] = column sums of A[Mb][Mo], split over the batch into
+// partial products (part) and partial sums (bpart) whose fixed-order sums
+// are left to the job list J (summed by one launch for every gradient of a
+// backward pass).
 static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, const __bf16 *B,
-                              int ldb, float *C, float *part, SumJobs &J, hipStream_t s)
+                              int ldb, float *C, float *db, float *part, float *bpart,
+                              SumJobs &J, hipStream_t s)
 {
     int per = 0;
     const int nz = mdn_splits(Mb, &per);
     const dim3 grid((N + 63) / 64, (Mo + 63) / 64, nz);
     k_gemm<true, false, 0, 32, 32, 128><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb,
                                                         nz > 1 ? part : C, N, nullptr, nullptr, 0,
-                                                        per);
+                                                        per, nz > 1 ? bpart : db);
     hipError_t e = hipGetLastError();
     if (e || nz == 1) return e;
-    const int j = J.njobs++;
+    int j = J.njobs++;
     J.part[j] = part; J.out[j] = C; J.n[j] = (long)Mo * N; J.nz[j] = nz;
     J.start[j + 1] = J.start[j] + J.n[j];
-    return hipSuccess;
-}
-
-// Bias gradient db[N] = column sums of D[Mb][N]: partial sums over chunks of
-// kMdnColRows rows (many workgroups), their fixed-order sum left to J.
-static hipError_t bias_grad(int Mb, int N, const __bf16 *D, int ldd, float *db, float *part,
-                            SumJobs &J, hipStream_t s)
-{
-    const int per = kMdnColRows;
-    const int nz = (Mb + per - 1) / per;
-    k_col_partial<<<dim3((N + 63) / 64, nz), 256, 0, s>>>(Mb, N, D, ldd, per, part);
-    hipError_t e = hipGetLastError();
-    if (e) return e;
-    const int j = J.njobs++;
-    J.part[j] = part; J.out[j] = db; J.n[j] = N; J.nz[j] = nz;
+    j = J.njobs++;
+    J.part[j] = bpart; J.out[j] = db; J.n[j] = Mo; J.nz[j] = nz;
     J.start[j + 1] = J.start[j] + J.n[j];
     return hipSuccess;
 }
 
 // Partial-sum floats one backward pass over M rows needs: every layer's
-// weight-gradient splits and bias-gradient chunks side by side.
+// weight- and bias-gradient splits side by side.
 size_t mdn_part_floats(int M)
 {
     int per = 0;
     const size_t nz = (size_t)mdn_splits(M, &per);
-    const size_t nzb = (size_t)((M + kMdnColRows - 1) / kMdnColRows);
     const size_t fin[4] = {kMdnIn, kMdnHid, kMdnHid, kMdnHid};
     const size_t fout[4] = {kMdnHid, kMdnHid, kMdnHid, kMdnOutPad};
     size_t n = 0;
-    for (int l = 0; l < 4; ++l) n += nz * fin[l] * fout[l] + nzb * fout[l];
+    for (int l = 0; l < 4; ++l) n += nz * fin[l] * fout[l] + nz * fout[l];
     return n;
 }
 
@@ -933,15 +928,13 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     // one launch at the end sums them all (each in a fixed order).
     SumJobs J{};
     int per = 0;
-    const long nz = mdn_splits(M, &per), nzb = (M + kMdnColRows - 1) / kMdnColRows;
+    const long nz = mdn_splits(M, &per);
     float *part = B.part;
     // head: dW4 = dO^T A3, db4 = sum dO, dA3 = dO W4
     e = weight_grad(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid, grad + L.W[3],
-                    part, J, s);
+                    grad + L.b[3], part, part + nz * kMdnOutPad * kMdnHid, J, s);
     if (e) return e;
-    part += nz * kMdnOutPad * kMdnHid;
-    if ((e = bias_grad(M, kMdnOutPad, B.dO, kMdnOutPad, grad + L.b[3], part, J, s))) return e;
-    part += nzb * kMdnOutPad;
+    part += nz * kMdnOutPad * kMdnHid + nz * kMdnOutPad;
     const __bf16 *dnext = B.dO;
     int nout = kMdnOutPad;
     for (int l = 2; l >= 0; --l) {
@@ -951,13 +944,10 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
         if (e) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
-        e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l], part, J,
-                        s);
+        e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l],
+                        grad + L.b[l], part, part + nz * kMdnHid * kin, J, s);
         if (e) return e;
-        part += nz * kMdnHid * kin;
-        if ((e = bias_grad(M, kMdnHid, B.dH[l & 1], kMdnHid, grad + L.b[l], part, J, s)))
-            return e;
-        part += nzb * kMdnHid;
+        part += nz * kMdnHid * kin + nz * kMdnHid;
         dnext = B.dH[l & 1];
         nout = kMdnHid;
     }

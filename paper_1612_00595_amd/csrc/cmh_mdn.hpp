@@ -17,7 +17,6 @@ constexpr int kMdnBg = 3;               // background events per training pair
 constexpr int kMdnTScale = 32;          // window step and time unit, samples
 constexpr int kMdnSplitRows = 512;      // batch rows per split of a gradient reduction
 constexpr int kMdnMaxSplits = 32;       // splits at most
-constexpr int kMdnColRows = 256;        // batch rows per partial of a bias gradient
 constexpr long kMdnBigTiles = 1024;     // 128 x 128 GEMM tiles from this many workgroups on
 // clamps of the log standard deviations (x, y in units of ds; t in units of
 // 32 samples): sigma_xy in [0.025, 1.5] ds, sigma_t in [0.5, 32] samples
