@@ -617,7 +617,9 @@ __global__ void k_mixture_table(Geo g, int ntau, long first, int rows, const flo
 // ------------------------------------------------------------- launchers
 // Tile choice: 128 x 128 workgroup tiles once they still give at least
 // kMdnBigTiles workgroups (large row counts: inference over anchors), else
-// 64 x 64 (the training batch), so that the grid fills the device.
+// (the training batch) 32 x 64 with k-steps of 64, twice the workgroups of
+// 64 x 64 tiles and five resident per CU, or 64 x 64 with steps of 128 where
+// an operand is stored k-strided, so that the grid fills the device.
 template <bool TA, bool TB, int EPI>
 static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
                        float *C, int ldc, const float *bias, __bf16 *Cb, int ldcb, hipStream_t s)
@@ -627,10 +629,15 @@ static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf
         const dim3 grid((N + 127) / 128, (M + 127) / 128, 1);
         k_gemm<TA, TB, EPI, 64, 64, 32><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
                                                               bias, Cb, ldcb, K, nullptr);
-    } else {
+    } else if (TA || !TB) {  // a k-strided operand: 64 x 64 tiles, whose steps of 128 hold
+                             // whole 4 x 8 blocks per thread for the register transposes
         const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
         k_gemm<TA, TB, EPI, 32, 32, 128><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
                                                                bias, Cb, ldcb, K, nullptr);
+    } else {
+        const dim3 grid((N + 63) / 64, (M + 31) / 32, 1);
+        k_gemm<TA, TB, EPI, 16, 32, 64><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc,
+                                                              bias, Cb, ldcb, K, nullptr);
     }
     return hipGetLastError();
 }
