@@ -140,10 +140,12 @@ def test_mdn_fused_inference_matches_oracle_and_forward(torch_dev, rows):
 GRAD_ULPS = 4.0
 
 
-def test_mdn_gradients_match_oracle(torch_dev):
+@pytest.mark.parametrize("rows", [200, 2080])
+def test_mdn_gradients_match_oracle(torch_dev, rows):
+    """200 rows: one split of the batch reduction; 2 080 rows: five splits,
+    their partial products and column sums summed by the job launch."""
     from paper_1612_00595_amd import chromh
     torch = torch_dev
-    rows = 200
     say(f"[mdn] gradients rows={rows}")
     flat, P = random_params(3)
     X, Z = oracle_pairs(12, 500, rows)
