@@ -422,13 +422,14 @@ __device__ inline void edge_class(double u, int *ex, int *ey)
 // 0x80000003); counter (pair, 0, 0, c) for the events (c = 0 target x, y;
 // c = 1 target t, magnitude; c = 2 + b background event b x, y; c = 2 +
 // kMdnBg + b its t, magnitude; c = 8 the edge class); counter (pair, 1 +
-// station, n / 2, 0) for the noise.
+// station, n / 2, 0) for the noise.  Events, arrivals and envelope sums in
+// binary64; the noise and the features in binary32 (they end as BF16).
 __global__ void __launch_bounds__(64)
 k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__restrict__ Zt)
 {
     __shared__ double s_ev[kMdnBg + 1][4];
     __shared__ double s_arr[kMdnBg + 1][9][3];
-    __shared__ double s_q[9][kMdnWin + 4];
+    __shared__ float s_q[9][kMdnWin + 4];
     const long p = first + blockIdx.x;
     const int lane = threadIdx.x;
     uint32_t cm[4] = {(uint32_t)p, (uint32_t)(p >> 32), 0u, 8u};
@@ -467,7 +468,9 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
         s_arr[q][b][2] = s_ev[q][3] * exp(-d / g.atten);
     }
     __syncthreads();
-    // noise of samples 2h and 2h + 1 of a station from one Box-Muller pair
+    // noise of samples 2h and 2h + 1 of a station from one Box-Muller pair;
+    // from here on binary32 (the features are rounded to BF16), the envelope
+    // sums E in binary64
     const int nsamp = kMdnWin + 3, npair = (nsamp + 1) / 2;
     for (int e = lane; e < 9 * npair; e += 64) {
         const int b = e / npair, hn = e % npair;
@@ -476,7 +479,9 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
         uint32_t c[4] = {(uint32_t)p, (uint32_t)(p >> 32), (uint32_t)(1 + b), (uint32_t)hn};
         philox10(c, seed, 0x80000003u);
         const double u1 = unit_open(c[0], c[1]), u2 = unit_open(c[2], c[3]);
-        const double rad = sqrt(-2.0 * log(u1));
+        const float rad = sqrtf(-2.0f * logf((float)u1));
+        float sn, cs;
+        sincosf((float)(2.0 * M_PI * u2), &sn, &cs);
         for (int o = 0; o < 2; ++o) {
             const int n = 2 * hn + o;
             if (n >= nsamp) break;
@@ -490,13 +495,13 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
                 const double env = exp(-((double)n - a) / g.decay);
                 E += (amp * env) * (amp * env);
             }
-            const double zz = o ? rad * sin(2.0 * M_PI * u2) : rad * cos(2.0 * M_PI * u2);
-            const double sv = sqrt(g.sigma2 + E) * zz;
+            const float zz = rad * (o ? sn : cs);
+            const float sv = sqrtf((float)(g.sigma2 + E)) * zz;
             s_q[b][n] = sv * sv;
         }
     }
     __syncthreads();
-    const double ls2 = log(g.sigma2);
+    const float is2 = (float)(1.0 / g.sigma2);
     __bf16 *xo = X + (long)blockIdx.x * kMdnIn;
     for (int e = lane; e < kMdnIn; e += 64) {
         const int b = e / kMdnWin, n = e % kMdnWin;
@@ -505,8 +510,9 @@ k_sim_pairs(Geo g, uint32_t seed, long first, __bf16 *__restrict__ X, float *__r
             xo[e] = (__bf16)0.0f;
             continue;
         }
-        const double m4 = (s_q[b][n] + s_q[b][n + 1] + s_q[b][n + 2] + s_q[b][n + 3]) * 0.25;
-        xo[e] = feat_bf16(log(g.sigma2 + m4) - ls2);
+        // log(sigma^2 + m4) - log(sigma^2) as log1p(m4 / sigma^2): no cancellation
+        const float m4 = (s_q[b][n] + s_q[b][n + 1] + s_q[b][n + 2] + s_q[b][n + 3]) * 0.25f;
+        xo[e] = (__bf16)log1pf(m4 * is2);
     }
     if (lane == 0) {
         Zt[3 * (long)blockIdx.x + 0] = (float)(s_ev[0][0] / g.ds);
