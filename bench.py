@@ -192,6 +192,7 @@ F1_EVERY = 50
 
 
 LEARNED_MAX_EVENTS = 96   # recorded events per chain and sweep (the worlds hold ~20)
+TUNE_MIN_SWEEPS = 50      # runs at least this long tune their kernel form on their first sweeps
 
 
 def learned_study(args, dev):
@@ -249,7 +250,7 @@ def learned_study(args, dev):
         # first sweeps (every form gives the same chain), which also build the
         # graphs outside the timed region
         first = 1
-        if args.learned_block:
+        if args.learned_block or S < TUNE_MIN_SWEEPS:
             b.run_sweeps(0, 1)
         else:
             first = b.tune_running(0, 2)
@@ -379,7 +380,11 @@ def paper_world_study(args, dev, latent: bool = False):
         rec = b.set_record(0, S + 1, 64)
         # the kernel form, tuned on the run's first sweeps (every form gives
         # the same chain), which also build the graphs outside the timed region
-        first = b.tune_running(0, 2)
+        if S >= TUNE_MIN_SWEEPS:
+            first = b.tune_running(0, 2)
+        else:
+            b.run_sweeps(0, 1)
+            first = 1
         block = b.block
         torch.cuda.synchronize()
         c0 = sum(b.read_counters(q) for q in range(n))
