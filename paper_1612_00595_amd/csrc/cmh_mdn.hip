@@ -650,12 +650,18 @@ static hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf
 
 static unsigned grid_for(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
 
-// Row splits of a batch reduction: chunks of at least kMdnSplitRows rows (a
-// multiple of 32), at most kMdnMaxSplits of them.
-int mdn_splits(int M, int *per)
+// Row splits of a weight-gradient product C[Mo][N] over a batch of M rows:
+// as many as keep the product's 64 x 64 tiles times the splits within
+// kMdnWgradSlots workgroups (one round of two per CU), at most
+// kMdnMaxSplits, with chunks of at least kMdnSplitRows rows (a multiple of
+// 32).  The same for every call with the same shape.
+int mdn_splits(int M, int Mo, int N, int *per)
 {
-    int z = (M + kMdnSplitRows - 1) / kMdnSplitRows;
-    z = std::max(1, std::min(z, kMdnMaxSplits));
+    const int tiles = ((Mo + 63) / 64) * ((N + 63) / 64);
+    int z = std::max(1, kMdnWgradSlots / tiles);
+    z = std::min(z, kMdnMaxSplits);
+    z = std::min(z, (M + kMdnSplitRows - 1) / kMdnSplitRows);
+    z = std::max(z, 1);
     int p = (M + z - 1) / z;
     p = (p + 31) / 32 * 32;
     *per = p;
@@ -672,7 +678,7 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
                               SumJobs &J, hipStream_t s)
 {
     int per = 0;
-    const int nz = mdn_splits(Mb, &per);
+    const int nz = mdn_splits(Mb, Mo, N, &per);
     const dim3 grid((N + 63) / 64, (Mo + 63) / 64, nz);
     k_gemm<true, false, 0, 32, 32, 128><<<grid, 256, 0, s>>>(Mo, N, Mb, A, lda, B, ldb,
                                                         nz > 1 ? part : C, N, nullptr, nullptr, 0,
@@ -692,12 +698,14 @@ static hipError_t weight_grad(int Mo, int N, int Mb, const __bf16 *A, int lda, c
 // weight- and bias-gradient splits side by side.
 size_t mdn_part_floats(int M)
 {
-    int per = 0;
-    const size_t nz = (size_t)mdn_splits(M, &per);
-    const size_t fin[4] = {kMdnIn, kMdnHid, kMdnHid, kMdnHid};
-    const size_t fout[4] = {kMdnHid, kMdnHid, kMdnHid, kMdnOutPad};
+    const int fin[4] = {kMdnIn, kMdnHid, kMdnHid, kMdnHid};
+    const int fout[4] = {kMdnHid, kMdnHid, kMdnHid, kMdnOutPad};
     size_t n = 0;
-    for (int l = 0; l < 4; ++l) n += nz * fin[l] * fout[l] + nz * fout[l];
+    for (int l = 0; l < 4; ++l) {
+        int per = 0;
+        const size_t nz = (size_t)mdn_splits(M, fout[l], fin[l], &per);
+        n += nz * fin[l] * fout[l] + nz * fout[l];
+    }
     return n;
 }
 
@@ -941,7 +949,7 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     // one launch at the end sums them all (each in a fixed order).
     SumJobs J{};
     int per = 0;
-    const long nz = mdn_splits(M, &per);
+    long nz = mdn_splits(M, kMdnOutPad, kMdnHid, &per);
     float *part = B.part;
     // head: dW4 = dO^T A3, db4 = sum dO, dA3 = dO W4
     e = weight_grad(kMdnOutPad, kMdnHid, M, B.dO, kMdnOutPad, B.A[2], kMdnHid, grad + L.W[3],
@@ -957,6 +965,7 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
         if (e) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
+        nz = mdn_splits(M, kMdnHid, kin, &per);
         e = weight_grad(kMdnHid, kin, M, B.dH[l & 1], kMdnHid, in, kin, grad + L.W[l],
                         grad + L.b[l], part, part + nz * kMdnHid * kin, J, s);
         if (e) return e;

@@ -15,8 +15,9 @@ constexpr int kMdnK = 8;                // mixture components
 constexpr int kMdnOutPad = 64;          // 8 x 7 outputs padded to 64
 constexpr int kMdnBg = 3;               // background events per training pair
 constexpr int kMdnTScale = 32;          // window step and time unit, samples
-constexpr int kMdnSplitRows = 512;      // batch rows per split of a gradient reduction
+constexpr int kMdnSplitRows = 256;      // batch rows per split of a gradient reduction, at least
 constexpr int kMdnMaxSplits = 32;       // splits at most
+constexpr int kMdnWgradSlots = 512;     // weight-gradient workgroups per product, at most
 constexpr long kMdnBigTiles = 1024;     // 128 x 128 GEMM tiles from this many workgroups on
 // clamps of the log standard deviations (x, y in units of ds; t in units of
 // 32 samples): sigma_xy in [0.025, 1.5] ds, sigma_t in [0.5, 32] samples
@@ -55,7 +56,7 @@ struct MdnBuffers {
     float *loss;      // M
     float *part;      // split partial sums of every gradient: mdn_part_floats(M)
 };
-int mdn_splits(int M, int *per);
+int mdn_splits(int M, int Mo, int N, int *per);
 size_t mdn_part_floats(int M);
 
 hipError_t mdn_init(float *params, __bf16 *hcopy, uint32_t seed, hipStream_t s);
