@@ -503,7 +503,8 @@ int32_t cmh_move_draws_arrivals(uint32_t seed, uint32_t chain, uint32_t sweep, u
  * Parameter blob (caller-owned device memory, cmh_mdn_param_bytes): FP32
  * master weights and biases of the four layers (weights [out][in]) in order
  * W1 b1 W2 b2 W3 b3 W4 b4 (n_params floats), the Adam moments, then BF16
- * copies of the weights.  Work buffers hold a row batch's activations.
+ * copies of the weights and transposed BF16 copies of W2, W3 and W4 (for
+ * the backward pass).  Work buffers hold a row batch's activations.
  * ---------------------------------------------------------------------- */
 #define CMH_MDN_IN 576
 #define CMH_MDN_OUT 64

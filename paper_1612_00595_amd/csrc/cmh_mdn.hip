@@ -341,6 +341,8 @@ k_mdn_loss(int M, const float *__restrict__ O, int ldo, const float *__restrict_
 // refreshed at its place in hcopy.
 struct AdamCopies {
     long w[4], nw[4], wh[4];  // layer weights: blob offset, count, offset in hcopy
+    long wt[4];               // offset of the transposed copy in hcopy (-1: none)
+    int fin[4], fout[4];
 };
 
 __global__ void k_adam_all(long n, float *__restrict__ w, float *__restrict__ mo,
@@ -359,7 +361,12 @@ __global__ void k_adam_all(long n, float *__restrict__ w, float *__restrict__ mo
         w[q] = wn;
 #pragma unroll
         for (int l = 0; l < 4; ++l)
-            if (q >= cp.w[l] && q < cp.w[l] + cp.nw[l]) hcopy[cp.wh[l] + (q - cp.w[l])] = (__bf16)wn;
+            if (q >= cp.w[l] && q < cp.w[l] + cp.nw[l]) {
+                const long r = q - cp.w[l];  // output row r / fin, input r % fin
+                hcopy[cp.wh[l] + r] = (__bf16)wn;
+                if (cp.wt[l] >= 0)
+                    hcopy[cp.wt[l] + (r % cp.fin[l]) * cp.fout[l] + r / cp.fin[l]] = (__bf16)wn;
+            }
     }
 }
 
@@ -368,6 +375,15 @@ __global__ void k_to_bf16(long n, const float *__restrict__ w, __bf16 *__restric
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
          q += (long)gridDim.x * blockDim.x)
         wb[q] = (__bf16)w[q];
+}
+
+// w[fout][fin] as BF16, transposed: wt[i][o] = w[o][i].
+__global__ void k_to_bf16_t(long n, int fin, int fout, const float *__restrict__ w,
+                            __bf16 *__restrict__ wt)
+{
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n;
+         q += (long)gridDim.x * blockDim.x)
+        wt[(q % fin) * fout + q / fin] = (__bf16)w[q];
 }
 
 // Glorot-uniform weights U(-a, a), a = sqrt(6 / (fan_in + fan_out)), from
@@ -727,6 +743,13 @@ MdnLayout mdn_layout()
         L.Wh[l] = h;
         h += (long)L.fin[l] * L.fout[l];
     }
+    // transposed copies for the backward pass's dA = dOut W products, after
+    // the copies the inference kernel reads
+    L.WhT[0] = -1;
+    for (int l = 1; l < 4; ++l) {
+        L.WhT[l] = h;
+        h += (long)L.fin[l] * L.fout[l];
+    }
     L.nh = h;
     return L;
 }
@@ -757,6 +780,10 @@ hipError_t mdn_refresh_copies(const float *params, __bf16 *hcopy, hipStream_t s)
         k_to_bf16<<<grid_for(n), 256, 0, s>>>(n, params + L.W[l], hcopy + L.Wh[l]);
         hipError_t e = hipGetLastError();
         if (e) return e;
+        if (L.WhT[l] < 0) continue;
+        k_to_bf16_t<<<grid_for(n), 256, 0, s>>>(n, L.fin[l], L.fout[l], params + L.W[l],
+                                                hcopy + L.WhT[l]);
+        if ((e = hipGetLastError())) return e;
     }
     return hipSuccess;
 }
@@ -959,9 +986,10 @@ hipError_t mdn_backward(const float *params, const __bf16 *hcopy, const __bf16 *
     const __bf16 *dnext = B.dO;
     int nout = kMdnOutPad;
     for (int l = 2; l >= 0; --l) {
-        // dA_l = dOut W_{l+1}; dH_l = dA_l * GELU'(Z_l)
-        e = gemm<false, false, 3>(M, kMdnHid, nout, dnext, nout, hcopy + L.Wh[l + 1], kMdnHid,
-                                  nullptr, kMdnHid, B.Z[l], B.dH[l & 1], kMdnHid, s);
+        // dA_l = dOut W_{l+1} (W_{l+1}'s transposed copy as the k-contiguous
+        // operand); dH_l = dA_l * GELU'(Z_l)
+        e = gemm<false, true, 3>(M, kMdnHid, nout, dnext, nout, hcopy + L.WhT[l + 1], nout,
+                                 nullptr, kMdnHid, B.Z[l], B.dH[l & 1], kMdnHid, s);
         if (e) return e;
         const __bf16 *in = l == 0 ? X : B.A[l - 1];
         const int kin = l == 0 ? kMdnIn : kMdnHid;
@@ -989,6 +1017,9 @@ hipError_t mdn_adam(float *params, __bf16 *hcopy, const float *grad, int step, f
         cp.w[l] = L.W[l];
         cp.nw[l] = (long)L.fin[l] * L.fout[l];
         cp.wh[l] = L.Wh[l];
+        cp.wt[l] = L.WhT[l];
+        cp.fin[l] = L.fin[l];
+        cp.fout[l] = L.fout[l];
     }
     k_adam_all<<<grid_for(L.np), 256, 0, s>>>(L.np, params, params + L.np, params + 2 * L.np, grad,
                                               hcopy, cp, lr, b1, b2, eps, c1, c2);

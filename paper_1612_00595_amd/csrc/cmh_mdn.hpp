@@ -38,6 +38,7 @@ constexpr double kMdnMuXY = 2.0, kMdnMuTLo = -1.0, kMdnMuTHi = 3.0;
 // four weight matrices live in a separate array (offsets Wh[l], nh values).
 struct MdnLayout {
     long W[4], b[4], Wh[4];
+    long WhT[4];      // BF16 copies of layers 1..3 transposed, [fin][fout] (-1: none)
     int fin[4], fout[4];
     long np, nh;
 };
